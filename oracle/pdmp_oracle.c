@@ -1,0 +1,919 @@
+/*
+ * pdmp_oracle.c -- plain FP64 CPU oracle for the PDMP morph path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code, header,
+ * table or constant with the HIP library; the product path never calls it.
+ *
+ * What it computes (Lai, Zhi, Hermans, Ramos, "Parallelised Diffeomorphic
+ * Sampling-based Motion Planning"):
+ *   - occupancy c(x) = sigma(s(x)), s(x) = sum_j w_j phi_j(x) + beta, with Gaussian
+ *     RBF features phi_j(x) = exp(-|x-h_j|^2/(2 l^2)) on hinge points (the
+ *     Hilbert-map form of the continuous occupancy of Sec. 3.1), its gradient and
+ *     Hessian, written out from the definition;
+ *   - the occupancy fit by binary cross-entropy with gradient descent or Adam
+ *     (Sec. 3.1), full batch;
+ *   - the morph: explicit Euler steps along the negative cost gradient, i.e. the
+ *     integral curve of Eq. (1) solved by Euler's method (Sec. 3.2);
+ *   - standard Denavit-Hartenberg forward kinematics of body points and the
+ *     pull-back of the task-space gradient into joint space (Sec. 3.2, Eq. 3,
+ *     read with the Jacobian transposed and each body point's own gradient);
+ *   - collision labels of points and configurations (the "feasible" count of
+ *     Table 1), decided in FP64;
+ *   - Philox4x32-10 (Salmon et al., SC 2011) for the prior samples that the
+ *     method draws in batches (Sec. 3.3);
+ *   - the residual MLP of the amortised morph (forward, MSE backward, Adam).
+ *
+ * Every loop runs in the order the definition states: sums over hinges j = 0..M-1
+ * and over points i = 0..n-1 in index order.  Build with -ffp-contract=off and no
+ * fast-math.  OpenMP is used over independent samples only.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAX_DIM 3
+#define ORC_MAX_DOF 8
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011, Sec. 4 and Table 2).  */
+/* ------------------------------------------------------------------------- */
+
+static uint32_t mul_hi_lo(uint32_t a, uint32_t b, uint32_t *lo) {
+    uint64_t p = (uint64_t)a * (uint64_t)b;
+    *lo = (uint32_t)p;
+    return (uint32_t)(p >> 32);
+}
+
+/* Ten rounds; the key is bumped by the Weyl constants before every round after
+ * the first.  Each round: two 32x32->64 multiplies of counter words 0 and 2, and
+ * the high halves XOR-ed with the other counter words and the key. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint32_t lo0, lo1;
+        uint32_t hi0 = mul_hi_lo(0xD2511F53u, c0, &lo0);
+        uint32_t hi1 = mul_hi_lo(0xCD9E8D57u, c2, &lo1);
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Prior samples x ~ U[lo, hi)^dim.  Sample i, coordinate k takes word k%4 of
+ * Philox(counter = {i_lo, i_hi, k/4, stream}, key = {seed_lo, seed_hi});
+ * u = (word >> 8) * 2^-24 in [0,1); x = lo + (hi - lo) * u in FP64, rounded
+ * once to FP32. */
+void orc_uniform_samples(uint64_t seed, uint32_t stream, const float *lo, const float *hi,
+                         int dim, int64_t n, float *out) {
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k < dim; ++k) {
+            uint32_t ctr[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), (uint32_t)(k / 4), stream};
+            uint32_t r[4];
+            orc_philox4x32_10(ctr, key, r);
+            double u = (double)(r[k % 4] >> 8) * (1.0 / 16777216.0);
+            double span = (double)hi[k] - (double)lo[k];
+            double t = span * u;
+            double x = (double)lo[k] + t;
+            out[(int64_t)k * n + i] = (float)x;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Collision labels (closed obstacles, FP64).                                */
+/* ------------------------------------------------------------------------- */
+
+/* Point (x, y) is inside disc k iff dx*dx + dy*dy <= r*r, dx = x - cx. */
+void orc_label_discs(const double *cx, const double *cy, const double *r, int K,
+                     const double *x, int64_t n, uint8_t *out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        int in = 0;
+        for (int k = 0; k < K; ++k) {
+            double dx = x[i] - cx[k];
+            double dy = x[n + i] - cy[k];
+            double a = dx * dx;
+            double b = dy * dy;
+            double d2 = a + b;
+            double rr = r[k] * r[k];
+            if (d2 <= rr) in = 1;
+        }
+        out[i] = (uint8_t)in;
+    }
+}
+
+/* Point is inside axis-aligned box k iff |x_a - c_a| <= e_a for a = 0, 1, 2. */
+static int in_any_box(const double p[3], const double *c, const double *e, int K) {
+    for (int k = 0; k < K; ++k) {
+        int in = 1;
+        for (int a = 0; a < 3; ++a)
+            if (!(fabs(p[a] - c[a * K + k]) <= e[a * K + k])) in = 0;
+        if (in) return 1;
+    }
+    return 0;
+}
+
+void orc_label_boxes(const double *c, const double *e, int K, const double *x, int64_t n,
+                     uint8_t *out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double p[3] = {x[i], x[n + i], x[2 * n + i]};
+        out[i] = (uint8_t)in_any_box(p, c, e, K);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* RBF occupancy: value, gradient, Hessian at one point.                     */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double s;               /* logit */
+    double gs[ORC_MAX_DIM];  /* grad s */
+    double Hs[ORC_MAX_DIM * ORC_MAX_DIM];
+    double sabs;            /* |beta| + sum |w_j| phi_j */
+    double graw;            /* l^-2 sum |w_j| phi_j |x - h_j| */
+} rbf_val;
+
+static void rbf_point(int dim, int M, const double *h, const double *w, double beta,
+                      double ell, const double *x, int want_hess, rbf_val *v) {
+    double il2 = 1.0 / (ell * ell);
+    double i2l2 = 0.5 * il2;
+    memset(v, 0, sizeof(*v));
+    v->s = beta;
+    v->sabs = fabs(beta);
+    for (int j = 0; j < M; ++j) {
+        double diff[ORC_MAX_DIM];
+        double r2 = 0.0;
+        for (int k = 0; k < dim; ++k) {
+            diff[k] = x[k] - h[(int64_t)k * M + j];
+            r2 += diff[k] * diff[k];
+        }
+        double phi = exp(-r2 * i2l2);
+        double wp = w[j] * phi;
+        v->s += wp;
+        v->sabs += fabs(w[j]) * phi;
+        v->graw += fabs(w[j]) * phi * sqrt(r2) * il2;
+        for (int k = 0; k < dim; ++k) v->gs[k] += -il2 * wp * diff[k];
+        if (want_hess)
+            for (int a = 0; a < dim; ++a)
+                for (int b = 0; b < dim; ++b)
+                    v->Hs[a * dim + b] += wp * (diff[a] * diff[b] * il2 * il2 - (a == b ? il2 : 0.0));
+    }
+}
+
+static double sigmoid(double s) { return 1.0 / (1.0 + exp(-s)); }
+
+/* c, grad c, Hessian of c and the gradient error scale G_abs from the logit. */
+typedef struct {
+    double c, dc;                       /* sigma(s), sigma'(s) */
+    double g[ORC_MAX_DIM];              /* grad c */
+    double H[ORC_MAX_DIM * ORC_MAX_DIM]; /* Hessian of c */
+    double gabs;
+} occ_val;
+
+static void occ_point(int dim, int M, const double *h, const double *w, double beta, double ell,
+                      const double *x, int want_hess, occ_val *o, rbf_val *rv) {
+    rbf_val v;
+    rbf_point(dim, M, h, w, beta, ell, x, want_hess, &v);
+    double c = sigmoid(v.s);
+    double d1 = c * (1.0 - c);
+    double d2 = d1 * (1.0 - 2.0 * c);
+    o->c = c;
+    o->dc = d1;
+    double gn = 0.0;
+    for (int k = 0; k < dim; ++k) {
+        o->g[k] = d1 * v.gs[k];
+        gn += v.gs[k] * v.gs[k];
+    }
+    o->gabs = d1 * v.graw + fabs(d2) * sqrt(gn) * v.sabs;
+    if (want_hess)
+        for (int a = 0; a < dim; ++a)
+            for (int b = 0; b < dim; ++b)
+                o->H[a * dim + b] = d1 * v.Hs[a * dim + b] + d2 * v.gs[a] * v.gs[b];
+    if (rv) *rv = v;
+}
+
+/* Logit s, occupancy c and the logit error scale S_abs at n points. */
+void orc_occ_eval(int dim, int M, const double *h, const double *w, double beta, double ell,
+                  const double *x, int64_t n, double *s, double *c, double *sabs) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double xi[ORC_MAX_DIM];
+        for (int k = 0; k < dim; ++k) xi[k] = x[(int64_t)k * n + i];
+        rbf_val v;
+        rbf_point(dim, M, h, w, beta, ell, xi, 0, &v);
+        if (s) s[i] = v.s;
+        if (c) c[i] = sigmoid(v.s);
+        if (sabs) sabs[i] = v.sabs;
+    }
+}
+
+/* grad c = sigma'(s) grad s, also grad s and the error scale G_abs. */
+void orc_occ_grad(int dim, int M, const double *h, const double *w, double beta, double ell,
+                  const double *x, int64_t n, double *c, double *gc, double *gs, double *gabs) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double xi[ORC_MAX_DIM];
+        for (int k = 0; k < dim; ++k) xi[k] = x[(int64_t)k * n + i];
+        occ_val o;
+        rbf_val v;
+        occ_point(dim, M, h, w, beta, ell, xi, 0, &o, &v);
+        if (c) c[i] = o.c;
+        for (int k = 0; k < dim; ++k) {
+            if (gc) gc[(int64_t)k * n + i] = o.g[k];
+            if (gs) gs[(int64_t)k * n + i] = v.gs[k];
+        }
+        if (gabs) gabs[i] = o.gabs;
+    }
+}
+
+/* Hessian of c (row-major dim x dim per point, [dim*dim][n]) and of s. */
+void orc_occ_hess(int dim, int M, const double *h, const double *w, double beta, double ell,
+                  const double *x, int64_t n, double *Hc, double *Hs) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double xi[ORC_MAX_DIM];
+        for (int k = 0; k < dim; ++k) xi[k] = x[(int64_t)k * n + i];
+        occ_val o;
+        rbf_val v;
+        occ_point(dim, M, h, w, beta, ell, xi, 1, &o, &v);
+        for (int a = 0; a < dim * dim; ++a) {
+            if (Hc) Hc[(int64_t)a * n + i] = o.H[a];
+            if (Hs) Hs[(int64_t)a * n + i] = v.Hs[a];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Symmetric eigenvalues by cyclic Jacobi rotations (Golub & Van Loan 8.5).  */
+/* ------------------------------------------------------------------------- */
+
+static void sym_eigvals(int n, double *A /* n*n, destroyed */, double *ev) {
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += A[p * n + q] * A[p * n + q];
+        if (off < 1e-300) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double apq = A[p * n + q];
+                if (apq == 0.0) continue;
+                double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < n; ++k) { /* columns p, q */
+                    double akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = cs * akp - sn * akq;
+                    A[k * n + q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < n; ++k) { /* rows p, q */
+                    double apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = cs * apk - sn * aqk;
+                    A[q * n + k] = sn * apk + cs * aqk;
+                }
+            }
+    }
+    for (int k = 0; k < n; ++k) ev[k] = A[k * n + k];
+}
+
+/* Spectral norm, determinant of the symmetric step Jacobian I - eta*H. */
+static void step_jac_stats(int n, const double *H, double eta, double *norm2, double *det,
+                           double *hnorm) {
+    double A[ORC_MAX_DOF * ORC_MAX_DOF], B[ORC_MAX_DOF * ORC_MAX_DOF], ev[ORC_MAX_DOF];
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            A[a * n + b] = (a == b ? 1.0 : 0.0) - eta * 0.5 * (H[a * n + b] + H[b * n + a]);
+            B[a * n + b] = 0.5 * (H[a * n + b] + H[b * n + a]);
+        }
+    sym_eigvals(n, A, ev);
+    double nm = 0.0, d = 1.0;
+    for (int k = 0; k < n; ++k) {
+        if (fabs(ev[k]) > nm) nm = fabs(ev[k]);
+        d *= ev[k];
+    }
+    *norm2 = nm;
+    *det = d;
+    sym_eigvals(n, B, ev);
+    double hn = 0.0;
+    for (int k = 0; k < n; ++k)
+        if (fabs(ev[k]) > hn) hn = fabs(ev[k]);
+    *hnorm = hn;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Plain workspace morph: x_{k+1} = x_k - eta * grad c(x_k), k = 0..T-1.      */
+/* ------------------------------------------------------------------------- */
+
+/* Optional diagnostics per sample (any pointer may be NULL):
+ *   amp:     product over steps of |I - eta Hc(x_k)|_2 (FP64 error amplification),
+ *   min_det: smallest det(I - eta Hc(x_k)) along the path,
+ *   max_eh:  largest eta*|Hc(x_k)|_2 along the path,
+ *   traj:    all states, [T+1][dim][n]. */
+void orc_morph_ws(int dim, int M, const double *h, const double *w, double beta, double ell,
+                  const double *xin, int64_t n, int T, double eta, double *xout, double *amp,
+                  double *min_det, double *max_eh, double *traj) {
+    int diag = (amp || min_det || max_eh);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double x[ORC_MAX_DIM];
+        for (int k = 0; k < dim; ++k) x[k] = xin[(int64_t)k * n + i];
+        double A = 1.0, mdet = INFINITY, meh = 0.0;
+        if (traj)
+            for (int k = 0; k < dim; ++k) traj[(int64_t)k * n + i] = x[k];
+        for (int t = 0; t < T; ++t) {
+            occ_val o;
+            occ_point(dim, M, h, w, beta, ell, x, diag, &o, NULL);
+            if (diag) {
+                double nm, det, hn;
+                step_jac_stats(dim, o.H, eta, &nm, &det, &hn);
+                A *= nm;
+                if (det < mdet) mdet = det;
+                if (eta * hn > meh) meh = eta * hn;
+            }
+            for (int k = 0; k < dim; ++k) x[k] = x[k] - eta * o.g[k];
+            if (traj)
+                for (int k = 0; k < dim; ++k)
+                    traj[((int64_t)(t + 1) * dim + k) * n + i] = x[k];
+        }
+        for (int k = 0; k < dim; ++k) xout[(int64_t)k * n + i] = x[k];
+        if (amp) amp[i] = A;
+        if (min_det) min_det[i] = mdet;
+        if (max_eh) max_eh[i] = meh;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Occupancy fit: mean BCE on logits + (l2/2)|w|^2, beta unregularised.       */
+/* ------------------------------------------------------------------------- */
+
+/* Binary cross-entropy of sigma(s) against y in the overflow-free form
+ * max(s,0) - y*s + log(1 + exp(-|s|)). */
+static double bce_logit(double s, double y) {
+    return (s > 0 ? s : 0.0) - y * s + log1p(exp(-fabs(s)));
+}
+
+/* Loss and gradient at wb = [w_0..w_{M-1}, beta]:
+ *   grad_j = (1/n) sum_i r_i phi_ij + l2 w_j,  grad_M = (1/n) sum_i r_i,
+ *   r_i = sigma(s_i) - y_i.
+ * gscale (nullable) gets (1/n) sum_i |r_i| phi_ij + l2 |w_j| (and (1/n) sum |r_i|). */
+double orc_fit_loss_grad(int dim, int M, const double *h, double ell, const double *wb,
+                         const double *pts, const uint8_t *y, int64_t n, double l2,
+                         double *grad, double *gscale) {
+    double *r = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *li = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double i2l2 = 0.5 / (ell * ell);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double xi[ORC_MAX_DIM];
+        for (int k = 0; k < dim; ++k) xi[k] = pts[(int64_t)k * n + i];
+        rbf_val v;
+        rbf_point(dim, M, h, wb, wb[M], ell, xi, 0, &v);
+        r[i] = sigmoid(v.s) - (double)y[i];
+        li[i] = bce_logit(v.s, (double)y[i]);
+    }
+    double loss = 0.0;
+    for (int64_t i = 0; i < n; ++i) loss += li[i];
+    loss /= (double)n;
+    double reg = 0.0;
+    for (int j = 0; j < M; ++j) reg += wb[j] * wb[j];
+    loss += 0.5 * l2 * reg;
+    if (grad) {
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < M; ++j) {
+            double acc = 0.0, aabs = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                double r2 = 0.0;
+                for (int k = 0; k < dim; ++k) {
+                    double d = pts[(int64_t)k * n + i] - h[(int64_t)k * M + j];
+                    r2 += d * d;
+                }
+                double phi = exp(-r2 * i2l2);
+                acc += r[i] * phi;
+                aabs += fabs(r[i]) * phi;
+            }
+            grad[j] = acc / (double)n + l2 * wb[j];
+            if (gscale) gscale[j] = aabs / (double)n + l2 * fabs(wb[j]);
+        }
+        double acc = 0.0, aabs = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            acc += r[i];
+            aabs += fabs(r[i]);
+        }
+        grad[M] = acc / (double)n;
+        if (gscale) gscale[M] = aabs / (double)n;
+    }
+    free(r);
+    free(li);
+    return loss;
+}
+
+/* Adam (Kingma & Ba 2015, Algorithm 1), step t >= 1, on a flat parameter array. */
+void orc_adam_step(double *p, const double *g, double *m, double *v, int64_t n, int t,
+                   double lr, double b1, double b2, double eps) {
+    double bc1 = 1.0 - pow(b1, (double)t);
+    double bc2 = 1.0 - pow(b2, (double)t);
+    for (int64_t k = 0; k < n; ++k) {
+        m[k] = b1 * m[k] + (1.0 - b1) * g[k];
+        v[k] = b2 * v[k] + (1.0 - b2) * g[k] * g[k];
+        double mh = m[k] / bc1;
+        double vh = v[k] / bc2;
+        p[k] = p[k] - lr * mh / (sqrt(vh) + eps);
+    }
+}
+
+/* Full-batch fit, `steps` iterations from the given wb (in/out, [M+1]).
+ * optimizer 0: gradient descent, w <- w - lr * grad_w, beta <- beta - lr_bias * grad_beta;
+ * optimizer 1: Adam with step lr on every parameter and state m, v ([M+1], in/out),
+ *              whose step counter continues from t0.
+ * loss[t] (nullable) is the loss at the start of step t. */
+void orc_fit(int dim, int M, const double *h, double ell, const double *pts, const uint8_t *y,
+             int64_t n, int optimizer, int steps, double lr, double lr_bias, double l2,
+             double b1, double b2, double eps, double *wb, double *m, double *v, int t0,
+             double *loss) {
+    double *g = (double *)malloc(sizeof(double) * (size_t)(M + 1));
+    for (int t = 0; t < steps; ++t) {
+        double L = orc_fit_loss_grad(dim, M, h, ell, wb, pts, y, n, l2, g, NULL);
+        if (loss) loss[t] = L;
+        if (optimizer == 0) {
+            for (int j = 0; j < M; ++j) wb[j] = wb[j] - lr * g[j];
+            wb[M] = wb[M] - lr_bias * g[M];
+        } else {
+            orc_adam_step(wb, g, m, v, M + 1, t0 + t + 1, lr, b1, b2, eps);
+        }
+    }
+    free(g);
+}
+
+/* Backward of the logit s(x; w, beta) for an upstream dL/ds = gs:
+ *   grad_w_j = sum_i gs_i phi_ij, grad_beta = sum_i gs_i,
+ *   grad_x_i = gs_i * grad s(x_i). */
+void orc_logit_bwd(int dim, int M, const double *h, const double *w, double ell,
+                   const double *x, int64_t n, const double *gsv, double *grad_w,
+                   double *grad_x) {
+    double i2l2 = 0.5 / (ell * ell);
+    if (grad_w) {
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < M; ++j) {
+            double acc = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                double r2 = 0.0;
+                for (int k = 0; k < dim; ++k) {
+                    double d = x[(int64_t)k * n + i] - h[(int64_t)k * M + j];
+                    r2 += d * d;
+                }
+                acc += gsv[i] * exp(-r2 * i2l2);
+            }
+            grad_w[j] = acc;
+        }
+        double acc = 0.0;
+        for (int64_t i = 0; i < n; ++i) acc += gsv[i];
+        grad_w[M] = acc;
+    }
+    if (grad_x) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double xi[ORC_MAX_DIM];
+            for (int k = 0; k < dim; ++k) xi[k] = x[(int64_t)k * n + i];
+            rbf_val v;
+            rbf_point(dim, M, h, w, 0.0, ell, xi, 0, &v);
+            for (int k = 0; k < dim; ++k) grad_x[(int64_t)k * n + i] = gsv[i] * v.gs[k];
+        }
+    }
+}
+
+/* Mean BCE on logits and its gradient g_i = (sigma(s_i) - y_i)/n. */
+double orc_bce_logits(const double *s, const uint8_t *y, int64_t n, double *g) {
+    double loss = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        loss += bce_logit(s[i], (double)y[i]);
+        if (g) g[i] = (sigmoid(s[i]) - (double)y[i]) / (double)n;
+    }
+    return loss / (double)n;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Arm: standard DH chain, body points, cost gradient in joint space.        */
+/* ------------------------------------------------------------------------- */
+
+/* dh = [a(ndof), d(ndof), alpha(ndof), theta0(ndof)].
+ * A_i = Rz(theta0_i + q_i) * Tz(d_i) * Tx(a_i) * Rx(alpha_i); T_0 = I; T_i = T_{i-1} A_i.
+ * o[i], z[i] (i = 0..ndof) are the origin and z axis of T_i. */
+static void dh_chain(int ndof, const double *dh, const double *q, double o[][3], double z[][3]) {
+    double T[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+    for (int a = 0; a < 3; ++a) {
+        o[0][a] = T[a][3];
+        z[0][a] = T[a][2];
+    }
+    for (int i = 0; i < ndof; ++i) {
+        double a = dh[i], d = dh[ndof + i], al = dh[2 * ndof + i];
+        double th = dh[3 * ndof + i] + q[i];
+        double ct = cos(th), st = sin(th), ca = cos(al), sa = sin(al);
+        double A[4][4] = {{ct, -st * ca, st * sa, a * ct},
+                          {st, ct * ca, -ct * sa, a * st},
+                          {0.0, sa, ca, d},
+                          {0.0, 0.0, 0.0, 1.0}};
+        double N[4][4];
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) {
+                double acc = 0.0;
+                for (int k = 0; k < 4; ++k) acc += T[r][k] * A[k][c];
+                N[r][c] = acc;
+            }
+        memcpy(T, N, sizeof(T));
+        for (int r = 0; r < 3; ++r) {
+            o[i + 1][r] = T[r][3];
+            z[i + 1][r] = T[r][2];
+        }
+    }
+}
+
+/* Body point k (0-based) of link i (1-based): o_{i-1} + ((k+1)/ppl)(o_i - o_{i-1}). */
+static void body_point(double o[][3], int i, int k, int ppl, double p[3]) {
+    double f = (double)(k + 1) / (double)ppl;
+    for (int a = 0; a < 3; ++a) p[a] = o[i - 1][a] + f * (o[i][a] - o[i - 1][a]);
+}
+
+/* pts: [3][ndof*ppl][n], body point index p = (i-1)*ppl + k. */
+void orc_fk_points(int ndof, int ppl, const double *dh, const double *q, int64_t n, double *pts) {
+    int nb = ndof * ppl;
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < n; ++s) {
+        double qs[ORC_MAX_DOF], o[ORC_MAX_DOF + 1][3], z[ORC_MAX_DOF + 1][3];
+        for (int j = 0; j < ndof; ++j) qs[j] = q[(int64_t)j * n + s];
+        dh_chain(ndof, dh, qs, o, z);
+        for (int i = 1; i <= ndof; ++i)
+            for (int k = 0; k < ppl; ++k) {
+                double p[3];
+                body_point(o, i, k, ppl, p);
+                for (int a = 0; a < 3; ++a) pts[((int64_t)a * nb + (i - 1) * ppl + k) * n + s] = p[a];
+            }
+    }
+}
+
+/* Positional Jacobian of body point p on link i, [3][ndof] row-major:
+ * column j (0-based joint, rotating about z_j through o_j) is z_j x (p - o_j) for
+ * j < i, zero otherwise. */
+void orc_fk_jacobian(int ndof, int ppl, const double *dh, const double *q /*[ndof]*/, int body,
+                     double *J) {
+    double o[ORC_MAX_DOF + 1][3], z[ORC_MAX_DOF + 1][3], p[3];
+    dh_chain(ndof, dh, q, o, z);
+    int i = body / ppl + 1, k = body % ppl;
+    body_point(o, i, k, ppl, p);
+    for (int j = 0; j < ndof; ++j) {
+        double col[3] = {0, 0, 0};
+        if (j < i) {
+            double r[3] = {p[0] - o[j][0], p[1] - o[j][1], p[2] - o[j][2]};
+            col[0] = z[j][1] * r[2] - z[j][2] * r[1];
+            col[1] = z[j][2] * r[0] - z[j][0] * r[2];
+            col[2] = z[j][0] * r[1] - z[j][1] * r[0];
+        }
+        for (int a = 0; a < 3; ++a) J[a * ndof + j] = col[a];
+    }
+}
+
+static void cross3(const double a[3], const double b[3], double c[3]) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Cost c(q) = sum_p c(psi_p(q)) and its joint gradient at one configuration.
+ * form 0: sum_p J_p^T grad_x c(p) with J_p column by column (brute force);
+ * form 1: per-link sums G_i = sum g_p, Mo_i = sum p x g_p, suffix-summed over
+ *         links, dc/dq_j = z_j . (SM_j - o_j x SG_j). */
+static double arm_cost_grad1(int ndof, int ppl, const double *dh, int M, const double *h,
+                             const double *w, double beta, double ell, const double *qs,
+                             int form, double *gq) {
+    double o[ORC_MAX_DOF + 1][3], z[ORC_MAX_DOF + 1][3];
+    dh_chain(ndof, dh, qs, o, z);
+    double cost = 0.0;
+    double G[ORC_MAX_DOF + 1][3], Mo[ORC_MAX_DOF + 1][3];
+    memset(G, 0, sizeof(G));
+    memset(Mo, 0, sizeof(Mo));
+    for (int j = 0; j < ndof; ++j) gq[j] = 0.0;
+    for (int i = 1; i <= ndof; ++i)
+        for (int k = 0; k < ppl; ++k) {
+            double p[3];
+            body_point(o, i, k, ppl, p);
+            occ_val ov;
+            occ_point(3, M, h, w, beta, ell, p, 0, &ov, NULL);
+            cost += ov.c;
+            if (form == 0) {
+                for (int j = 0; j < i; ++j) {
+                    double r[3] = {p[0] - o[j][0], p[1] - o[j][1], p[2] - o[j][2]}, col[3];
+                    cross3(z[j], r, col);
+                    gq[j] += col[0] * ov.g[0] + col[1] * ov.g[1] + col[2] * ov.g[2];
+                }
+            } else {
+                double pg[3];
+                cross3(p, ov.g, pg);
+                for (int a = 0; a < 3; ++a) {
+                    G[i][a] += ov.g[a];
+                    Mo[i][a] += pg[a];
+                }
+            }
+        }
+    if (form == 1) {
+        double SG[3] = {0, 0, 0}, SM[3] = {0, 0, 0};
+        for (int i = ndof; i >= 1; --i) {
+            for (int a = 0; a < 3; ++a) {
+                SG[a] += G[i][a];
+                SM[a] += Mo[i][a];
+            }
+            /* joint i-1 (0-based) rotates links i..ndof about z_{i-1} through o_{i-1} */
+            double oxg[3];
+            cross3(o[i - 1], SG, oxg);
+            double v[3] = {SM[0] - oxg[0], SM[1] - oxg[1], SM[2] - oxg[2]};
+            gq[i - 1] = z[i - 1][0] * v[0] + z[i - 1][1] * v[1] + z[i - 1][2] * v[2];
+        }
+    }
+    return cost;
+}
+
+void orc_arm_cost_grad(int ndof, int ppl, const double *dh, int M, const double *h,
+                       const double *w, double beta, double ell, const double *q, int64_t n,
+                       int form, double *cost, double *grad) {
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < n; ++s) {
+        double qs[ORC_MAX_DOF], gq[ORC_MAX_DOF];
+        for (int j = 0; j < ndof; ++j) qs[j] = q[(int64_t)j * n + s];
+        double c = arm_cost_grad1(ndof, ppl, dh, M, h, w, beta, ell, qs, form, gq);
+        if (cost) cost[s] = c;
+        if (grad)
+            for (int j = 0; j < ndof; ++j) grad[(int64_t)j * n + s] = gq[j];
+    }
+}
+
+/* Joint-space morph q_{k+1} = q_k - eta * grad_q c(q_k) (brute-force pull-back).
+ * amp (nullable): product of |I - eta H_q|_2 with H_q the central-difference
+ * Jacobian (step fd_h) of the analytic gradient, symmetrised.  min_det likewise. */
+void orc_morph_arm(int ndof, int ppl, const double *dh, int M, const double *h, const double *w,
+                   double beta, double ell, const double *qin, int64_t n, int T, double eta,
+                   double *qout, double *amp, double *min_det, double fd_h) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < n; ++s) {
+        double qs[ORC_MAX_DOF], gq[ORC_MAX_DOF];
+        double A = 1.0, mdet = INFINITY;
+        for (int j = 0; j < ndof; ++j) qs[j] = qin[(int64_t)j * n + s];
+        for (int t = 0; t < T; ++t) {
+            if (amp || min_det) {
+                double H[ORC_MAX_DOF * ORC_MAX_DOF];
+                for (int b = 0; b < ndof; ++b) {
+                    double qp[ORC_MAX_DOF], qm[ORC_MAX_DOF], gp[ORC_MAX_DOF], gm[ORC_MAX_DOF];
+                    memcpy(qp, qs, sizeof(qp));
+                    memcpy(qm, qs, sizeof(qm));
+                    qp[b] += fd_h;
+                    qm[b] -= fd_h;
+                    arm_cost_grad1(ndof, ppl, dh, M, h, w, beta, ell, qp, 0, gp);
+                    arm_cost_grad1(ndof, ppl, dh, M, h, w, beta, ell, qm, 0, gm);
+                    for (int a = 0; a < ndof; ++a) H[a * ndof + b] = (gp[a] - gm[a]) / (2.0 * fd_h);
+                }
+                double nm, det, hn;
+                step_jac_stats(ndof, H, eta, &nm, &det, &hn);
+                A *= nm;
+                if (det < mdet) mdet = det;
+            }
+            arm_cost_grad1(ndof, ppl, dh, M, h, w, beta, ell, qs, 0, gq);
+            for (int j = 0; j < ndof; ++j) qs[j] = qs[j] - eta * gq[j];
+        }
+        for (int j = 0; j < ndof; ++j) qout[(int64_t)j * n + s] = qs[j];
+        if (amp) amp[s] = A;
+        if (min_det) min_det[s] = mdet;
+    }
+}
+
+/* A configuration collides iff any of its body points lies in any box. */
+void orc_label_configs(int ndof, int ppl, const double *dh, const double *c, const double *e,
+                       int K, const double *q, int64_t n, uint8_t *out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < n; ++s) {
+        double qs[ORC_MAX_DOF], o[ORC_MAX_DOF + 1][3], z[ORC_MAX_DOF + 1][3];
+        for (int j = 0; j < ndof; ++j) qs[j] = q[(int64_t)j * n + s];
+        dh_chain(ndof, dh, qs, o, z);
+        int hit = 0;
+        for (int i = 1; i <= ndof && !hit; ++i)
+            for (int k = 0; k < ppl && !hit; ++k) {
+                double p[3];
+                body_point(o, i, k, ppl, p);
+                hit = in_any_box(p, c, e, K);
+            }
+        out[s] = (uint8_t)hit;
+    }
+}
+
+/* Label margin of each configuration: min over body points p and boxes b of
+ * |max_a (|p_a - c_a| - e_a)|.  The inside test of p in b flips only when that
+ * maximum changes sign, and moving p by delta changes it by at most delta, so a
+ * configuration whose margin exceeds delta keeps its label under any perturbation
+ * of its body points smaller than delta. */
+void orc_config_label_margin(int ndof, int ppl, const double *dh, const double *c,
+                             const double *e, int K, const double *q, int64_t n, double *margin) {
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < n; ++s) {
+        double qs[ORC_MAX_DOF], o[ORC_MAX_DOF + 1][3], z[ORC_MAX_DOF + 1][3];
+        for (int j = 0; j < ndof; ++j) qs[j] = q[(int64_t)j * n + s];
+        dh_chain(ndof, dh, qs, o, z);
+        double mg = INFINITY;
+        for (int i = 1; i <= ndof; ++i)
+            for (int k = 0; k < ppl; ++k) {
+                double p[3];
+                body_point(o, i, k, ppl, p);
+                for (int b = 0; b < K; ++b) {
+                    /* signed distance proxy: max_a (|p_a - c_a| - e_a) is <= 0 inside */
+                    double dmax = -INFINITY;
+                    for (int a = 0; a < 3; ++a) {
+                        double d = fabs(p[a] - c[a * K + b]) - e[a * K + b];
+                        if (d > dmax) dmax = d;
+                    }
+                    if (fabs(dmax) < mg) mg = fabs(dmax);
+                }
+            }
+        margin[s] = mg;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Residual MLP q_hat = q + f(q), f = W_L SiLU(... SiLU(W_1 q + b_1) ...) + b_L  */
+/* ------------------------------------------------------------------------- */
+
+/* Parameters are one flat array: for each layer l = 1..L, W_l [out][in] row-major
+ * followed by b_l [out].  widths has L+1 entries. */
+static int64_t mlp_nparams(int L, const int *widths) {
+    int64_t np = 0;
+    for (int l = 0; l < L; ++l) np += (int64_t)widths[l + 1] * widths[l] + widths[l + 1];
+    return np;
+}
+
+int64_t orc_mlp_nparams(int L, const int *widths) { return mlp_nparams(L, widths); }
+
+static double silu(double z) { return z / (1.0 + exp(-z)); }
+static double silu_d(double z) {
+    double sg = 1.0 / (1.0 + exp(-z));
+    return sg * (1.0 + z * (1.0 - sg));
+}
+
+#define ORC_MLP_MAXW 1024
+#define ORC_MLP_MAXL 8
+
+/* Forward for one sample; stores pre-activations z[l] and activations a[l]
+ * (a[0] = input) when the buffers are given. */
+static void mlp_fwd1(int L, const int *widths, const double *P, const double *in, double *out,
+                     double *zbuf, double *abuf) {
+    double a[ORC_MLP_MAXW], nx[ORC_MLP_MAXW];
+    int w0 = widths[0];
+    for (int k = 0; k < w0; ++k) a[k] = in[k];
+    if (abuf) memcpy(abuf, a, sizeof(double) * (size_t)w0);
+    const double *p = P;
+    int64_t zoff = 0, aoff = w0;
+    for (int l = 0; l < L; ++l) {
+        int fi = widths[l], fo = widths[l + 1];
+        const double *W = p, *b = p + (int64_t)fo * fi;
+        for (int o = 0; o < fo; ++o) {
+            double acc = 0.0;
+            for (int k = 0; k < fi; ++k) acc += W[(int64_t)o * fi + k] * a[k];
+            acc += b[o];
+            nx[o] = acc;
+        }
+        if (zbuf) memcpy(zbuf + zoff, nx, sizeof(double) * (size_t)fo);
+        zoff += fo;
+        if (l < L - 1)
+            for (int o = 0; o < fo; ++o) nx[o] = silu(nx[o]);
+        memcpy(a, nx, sizeof(double) * (size_t)fo);
+        if (abuf && l < L - 1) memcpy(abuf + aoff, a, sizeof(double) * (size_t)fo);
+        if (l < L - 1) aoff += fo;
+        p += (int64_t)fo * fi + fo;
+    }
+    for (int k = 0; k < widths[L]; ++k) out[k] = a[k];
+}
+
+/* q_hat = q + f(q) for [w0][B] inputs (SoA), residual requires widths[0]==widths[L]. */
+void orc_mlp_forward(int L, const int *widths, const double *P, const double *q, int64_t B,
+                     int residual, double *out) {
+    int w0 = widths[0], wl = widths[L];
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < B; ++s) {
+        double in[ORC_MLP_MAXW], f[ORC_MLP_MAXW];
+        for (int k = 0; k < w0; ++k) in[k] = q[(int64_t)k * B + s];
+        mlp_fwd1(L, widths, P, in, f, NULL, NULL);
+        for (int k = 0; k < wl; ++k) out[(int64_t)k * B + s] = (residual ? in[k] : 0.0) + f[k];
+    }
+}
+
+/* MSE loss (1/(wL*B)) sum |q_hat - target|^2 of the residual network and its
+ * gradient with respect to every parameter (same flat layout as P). */
+double orc_mlp_loss_grad(int L, const int *widths, const double *P, const double *q,
+                         const double *target, int64_t B, double *grad) {
+    int w0 = widths[0], wl = widths[L];
+    int64_t np = mlp_nparams(L, widths);
+    int64_t zlen = 0, alen = w0;
+    for (int l = 0; l < L; ++l) {
+        zlen += widths[l + 1];
+        if (l < L - 1) alen += widths[l + 1];
+    }
+    memset(grad, 0, sizeof(double) * (size_t)np);
+    double loss = 0.0;
+    double scale = 1.0 / ((double)wl * (double)B);
+    double *z = (double *)malloc(sizeof(double) * (size_t)zlen);
+    double *a = (double *)malloc(sizeof(double) * (size_t)alen);
+    for (int64_t s = 0; s < B; ++s) {
+        double in[ORC_MLP_MAXW], f[ORC_MLP_MAXW], d[ORC_MLP_MAXW], dn[ORC_MLP_MAXW];
+        for (int k = 0; k < w0; ++k) in[k] = q[(int64_t)k * B + s];
+        mlp_fwd1(L, widths, P, in, f, z, a);
+        for (int k = 0; k < wl; ++k) {
+            double e = in[k] + f[k] - target[(int64_t)k * B + s];
+            loss += e * e;
+            d[k] = 2.0 * scale * e; /* dL/df = dL/dq_hat */
+        }
+        /* walk layers backwards; d holds dL/dz_l of the current layer */
+        int64_t poff = np, zoff = zlen, aoff = alen;
+        for (int l = L - 1; l >= 0; --l) {
+            int fi = widths[l], fo = widths[l + 1];
+            poff -= (int64_t)fo * fi + fo;
+            zoff -= fo;
+            aoff -= fi;
+            const double *W = P + poff;
+            double *gW = grad + poff, *gb = grad + poff + (int64_t)fo * fi;
+            const double *ain = a + aoff; /* input activation of layer l */
+            for (int o = 0; o < fo; ++o) {
+                for (int k = 0; k < fi; ++k) gW[(int64_t)o * fi + k] += d[o] * ain[k];
+                gb[o] += d[o];
+            }
+            if (l > 0) {
+                const double *zin = z + zoff - fi; /* pre-activation feeding ain */
+                for (int k = 0; k < fi; ++k) {
+                    double acc = 0.0;
+                    for (int o = 0; o < fo; ++o) acc += W[(int64_t)o * fi + k] * d[o];
+                    dn[k] = acc * silu_d(zin[k]);
+                }
+                memcpy(d, dn, sizeof(double) * (size_t)fi);
+            }
+        }
+    }
+    free(z);
+    free(a);
+    return loss * scale;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Amortised morph: q_hat = q + f(q); a configuration whose largest body-point */
+/* occupancy at q_hat exceeds `thresh` takes the plain morph from q instead.  */
+/* ------------------------------------------------------------------------- */
+
+void orc_amortised_morph(int L, const int *widths, const double *P, int ndof, int ppl,
+                         const double *dh, int M, const double *h, const double *w, double beta,
+                         double ell, const double *q, int64_t n, int T, double eta,
+                         double thresh, double *qout, uint8_t *flag, double *maxc) {
+    double *qh = (double *)malloc(sizeof(double) * (size_t)ndof * (size_t)(n > 0 ? n : 1));
+    orc_mlp_forward(L, widths, P, q, n, 1, qh);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < n; ++s) {
+        double qs[ORC_MAX_DOF], o[ORC_MAX_DOF + 1][3], z[ORC_MAX_DOF + 1][3];
+        for (int j = 0; j < ndof; ++j) qs[j] = qh[(int64_t)j * n + s];
+        dh_chain(ndof, dh, qs, o, z);
+        double mc = -INFINITY;
+        for (int i = 1; i <= ndof; ++i)
+            for (int k = 0; k < ppl; ++k) {
+                double p[3];
+                body_point(o, i, k, ppl, p);
+                occ_val ov;
+                occ_point(3, M, h, w, beta, ell, p, 0, &ov, NULL);
+                if (ov.c > mc) mc = ov.c;
+            }
+        int fb = mc > thresh;
+        if (maxc) maxc[s] = mc;
+        if (flag) flag[s] = (uint8_t)fb;
+        if (fb) {
+            double gq[ORC_MAX_DOF];
+            for (int j = 0; j < ndof; ++j) qs[j] = q[(int64_t)j * n + s];
+            for (int t = 0; t < T; ++t) {
+                arm_cost_grad1(ndof, ppl, dh, M, h, w, beta, ell, qs, 0, gq);
+                for (int j = 0; j < ndof; ++j) qs[j] = qs[j] - eta * gq[j];
+            }
+        }
+        for (int j = 0; j < ndof; ++j) qout[(int64_t)j * n + s] = qs[j];
+    }
+    free(qh);
+}

@@ -1,0 +1,143 @@
+"""Pins for the oracle's arm path (Sec. 3.2: body points, FK Jacobians, Eq. 3).
+
+- q = 0 with d = 0 puts every joint origin on the base x axis (closed form);
+- alpha = 0, d = 0 reduces standard DH to the textbook planar arm;
+- the positional Jacobian against central differences of the body points;
+- the suffix-sum pull-back against the column-by-column sum of J^T grad c;
+- the joint gradient against finite differences of the summed occupancy;
+- the joint-space morph: identities and positive step determinants for small eta;
+- configuration labels against point labels of the oracle's own body points.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2108_11775_amd import configs as K, inputs as I
+
+
+def _arm(seed=0, ndof=7, ppl=8, planar=False):
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.1, 0.4, ndof)
+    alpha = np.zeros(ndof) if planar else np.array(K.C3.alpha[:ndof])
+    return O.Arm(a, np.zeros(ndof), alpha, np.zeros(ndof), ppl)
+
+
+def _occ3(seed=1, M=64, ell=0.3, scale=2.0):
+    rng = np.random.default_rng(seed)
+    h = rng.uniform(-1.2, 1.2, (3, M))
+    return O.Occupancy(h, rng.normal(0, scale, M), -0.5, ell)
+
+
+def test_zero_configuration_closed_form():
+    arm = _arm()
+    pts = O.fk_points(arm, np.zeros((7, 1)))[:, :, 0]
+    ends = np.concatenate([[0.0], np.cumsum(arm.a)])
+    for i in range(7):
+        for k in range(8):
+            x = ends[i] + (k + 1) / 8 * (ends[i + 1] - ends[i])
+            np.testing.assert_allclose(pts[:, i * 8 + k], [x, 0, 0], atol=1e-15)
+
+
+def test_planar_reduction():
+    arm = _arm(seed=2, planar=True)
+    q = np.random.default_rng(3).uniform(-math.pi, math.pi, (7, 20))
+    pts = O.fk_points(arm, q)
+    for s in range(20):
+        ang = np.cumsum(q[:, s])
+        ox = np.concatenate([[0.0], np.cumsum(arm.a * np.cos(ang))])
+        oy = np.concatenate([[0.0], np.cumsum(arm.a * np.sin(ang))])
+        for i in range(7):
+            f = (np.arange(8) + 1) / 8
+            np.testing.assert_allclose(pts[0, i * 8:(i + 1) * 8, s], ox[i] + f * (ox[i + 1] - ox[i]),
+                                       atol=1e-14)
+            np.testing.assert_allclose(pts[1, i * 8:(i + 1) * 8, s], oy[i] + f * (oy[i + 1] - oy[i]),
+                                       atol=1e-14)
+            np.testing.assert_allclose(pts[2, i * 8:(i + 1) * 8, s], 0.0, atol=1e-15)
+
+
+def test_jacobian_matches_central_differences():
+    arm = _arm(seed=4)
+    q = np.random.default_rng(5).uniform(-math.pi, math.pi, 7)
+    for body in (0, 9, 27, 55):
+        J = O.fk_jacobian(arm, q, body)
+        fd = np.zeros((3, 7))
+        for j in range(7):
+            def P(d):
+                qq = q.copy()
+                qq[j] += d
+                return O.fk_points(arm, qq[:, None])[:, body, 0]
+            f1 = (P(2e-4) - P(-2e-4)) / 4e-4
+            f2 = (P(1e-4) - P(-1e-4)) / 2e-4
+            fd[:, j] = (4 * f2 - f1) / 3
+        np.testing.assert_allclose(J, fd, atol=1e-10)
+        # joints beyond the point's link do not move it
+        assert np.all(J[:, body // 8 + 1:] == 0)
+
+
+def test_pullback_forms_agree_and_match_explicit_sum():
+    arm = _arm(seed=6)
+    occ = _occ3()
+    q = np.random.default_rng(7).uniform(-math.pi, math.pi, (7, 16))
+    c0, g0 = O.arm_cost_grad(arm, occ, q, form=0)
+    c1, g1 = O.arm_cost_grad(arm, occ, q, form=1)
+    np.testing.assert_allclose(g1, g0, rtol=0, atol=1e-12 * max(1.0, np.abs(g0).max()))
+    assert np.array_equal(c0, c1)
+    # explicit sum_p J_p^T grad c(p) with the Jacobian routine
+    pts = O.fk_points(arm, q)
+    for s in (0, 5, 15):
+        _, gc, _, _ = O.occ_grad(occ, pts[:, :, s])
+        ref = np.zeros(7)
+        for p in range(56):
+            ref += O.fk_jacobian(arm, q[:, s], p).T @ gc[:, p]
+        np.testing.assert_allclose(g0[:, s], ref, atol=1e-12 * max(1.0, np.abs(ref).max()))
+        cc = O.occ_eval(occ, pts[:, :, s])[1]
+        assert c0[s] == pytest.approx(cc.sum(), rel=1e-14)
+
+
+def test_joint_gradient_matches_finite_differences():
+    arm = _arm(seed=8)
+    occ = _occ3(seed=9)
+    q = np.random.default_rng(10).uniform(-math.pi, math.pi, (7, 6))
+    _, g = O.arm_cost_grad(arm, occ, q)
+    for j in range(7):
+        def C(d):
+            qq = q.copy()
+            qq[j] += d
+            return O.arm_cost_grad(arm, occ, qq)[0]
+        f1 = (C(2e-4) - C(-2e-4)) / 4e-4
+        f2 = (C(1e-4) - C(-1e-4)) / 2e-4
+        np.testing.assert_allclose(g[j], (4 * f2 - f1) / 3, atol=1e-8 * max(1, np.abs(g).max()))
+
+
+def test_arm_morph_identities_and_steps():
+    arm = _arm(seed=11)
+    occ = _occ3(seed=12)
+    q = np.random.default_rng(13).uniform(-math.pi, math.pi, (7, 8))
+    assert np.array_equal(O.morph_arm(arm, occ, q, 10, 0.0), q)
+    assert np.array_equal(O.morph_arm(arm, occ, q, 0, 0.01), q)
+    # T steps = T single steps
+    a = O.morph_arm(arm, occ, q, 3, 0.01)
+    b = q
+    for _ in range(3):
+        b = b - 0.01 * O.arm_cost_grad(arm, occ, b)[1]
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-14)
+    _, amp, mdet = O.morph_arm(arm, occ, q, 5, 1e-3, diag=True)
+    assert np.all(mdet > 0) and np.all(np.isfinite(amp))
+
+
+def test_config_labels_match_point_labels_of_body_points():
+    c3 = K.C3
+    a, d, al, th = I.dh_params(c3.cfg_id, c3.n_dof, c3.link_min, c3.link_max, c3.alpha)
+    arm = O.Arm(a, d, al, th, c3.pts_per_link)
+    bc, be = I.boxes(c3.cfg_id, c3.n_boxes, c3.box_lo, c3.box_hi, c3.half_min, c3.half_max)
+    q = I.uniform_points(c3.cfg_id, K.STREAM_EVAL, 7, 2000, c3.q_lo, c3.q_hi)
+    lab = O.label_configs(arm, bc, be, q)
+    pts = O.fk_points(arm, q)
+    per_pt = np.stack([O.label_boxes(bc, be, pts[:, p, :]) for p in range(56)])
+    assert np.array_equal(lab, per_pt.max(axis=0))
+    free = 1 - lab.mean()
+    assert 0.10 <= free <= 0.60  # within the span of Table 1's prior feasibility
+    margin = O.config_label_margin(arm, bc, be, q)
+    assert np.all(margin >= 0)

@@ -1,0 +1,83 @@
+"""Pins for the oracle's residual MLP and amortised morph.
+
+The forward is pinned by a hand-evaluated one-unit network and by torch's FP64
+linear/SiLU layers; the MSE gradient by torch autograd in FP64 (a different
+differentiation route); the amortised morph by its fallback rule: with a zero
+network, flagged samples take exactly the plain morph and the rest stay put.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2108_11775_amd import configs as K, inputs as I
+
+
+def test_one_unit_network_by_hand():
+    widths = (1, 1, 1)
+    P = O.mlp_pack([(np.array([[2.0]]), np.array([0.0])), (np.array([[3.0]]), np.array([0.5]))])
+    out = O.mlp_forward(widths, P, np.array([[1.0]]))
+    silu2 = 2.0 / (1.0 + math.exp(-2.0))
+    assert out[0, 0] == pytest.approx(1.0 + 3.0 * silu2 + 0.5, rel=1e-15)
+
+
+def _torch_mlp(layers, q):
+    x = torch.tensor(q.T, dtype=torch.float64)
+    h = x
+    for li, (W, b) in enumerate(layers):
+        h = torch.nn.functional.linear(h, W, b)
+        if li < len(layers) - 1:
+            h = torch.nn.functional.silu(h)
+    return x + h
+
+
+def test_forward_and_gradient_match_torch():
+    widths = (7, 32, 32, 32, 7)
+    layers = I.mlp_init(5, widths, zero_last=False)
+    P = O.mlp_pack(layers)
+    rng = np.random.default_rng(0)
+    q = rng.uniform(-math.pi, math.pi, (7, 40))
+    tgt = rng.normal(size=(7, 40))
+    out = O.mlp_forward(widths, P, q)
+    tl = [(torch.tensor(W, dtype=torch.float64, requires_grad=True),
+           torch.tensor(b, dtype=torch.float64, requires_grad=True)) for W, b in layers]
+    ref = _torch_mlp(tl, q)
+    np.testing.assert_allclose(out, ref.detach().numpy().T, rtol=1e-13, atol=1e-14)
+    L, g = O.mlp_loss_grad(widths, P, q, tgt)
+    loss = ((ref - torch.tensor(tgt.T)) ** 2).mean()
+    loss.backward()
+    assert L == pytest.approx(loss.item(), rel=1e-13)
+    gref = np.concatenate([np.concatenate([W.grad.numpy().reshape(-1), b.grad.numpy()])
+                           for W, b in tl])
+    np.testing.assert_allclose(g, gref, rtol=1e-11, atol=1e-15)
+
+
+def test_zero_last_layer_is_identity():
+    widths = K.C5.widths
+    P = O.mlp_pack(I.mlp_init(5, widths))
+    q = np.random.default_rng(1).uniform(-3, 3, (7, 10))
+    assert np.array_equal(O.mlp_forward(widths, P, q), q)
+
+
+def test_amortised_zero_network_falls_back_to_plain_morph():
+    rng = np.random.default_rng(2)
+    arm = O.Arm(rng.uniform(0.1, 0.4, 7), np.zeros(7), np.array(K.C3.alpha), np.zeros(7), 8)
+    h = rng.uniform(-1.2, 1.2, (3, 48))
+    occ = O.Occupancy(h, rng.normal(0, 3.0, 48), -0.5, 0.3)
+    widths = (7, 16, 16, 7)
+    P = O.mlp_pack(I.mlp_init(5, widths))
+    q = rng.uniform(-math.pi, math.pi, (7, 24))
+    out, flag, maxc = O.amortised_morph(widths, P, arm, occ, q, 5, 0.01, 0.5)
+    plain = O.morph_arm(arm, occ, q, 5, 0.01)
+    pts = O.fk_points(arm, q)
+    for s in range(24):
+        cmax = O.occ_eval(occ, pts[:, :, s])[1].max()
+        assert maxc[s] == pytest.approx(cmax, rel=1e-14)
+        assert flag[s] == (cmax > 0.5)
+        if flag[s]:
+            np.testing.assert_array_equal(out[:, s], plain[:, s])
+        else:
+            np.testing.assert_array_equal(out[:, s], q[:, s])
+    assert 0 < flag.sum() < 24
