@@ -1,0 +1,158 @@
+/*
+ * pdmp.h -- C ABI of the MI355X (gfx950) library for the batched diffeomorphic
+ * morph of planner samples (Lai, Zhi, Hermans, Ramos, "Parallelised
+ * Diffeomorphic Sampling-based Motion Planning").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns a pdmp_status.  Arguments are validated on the host
+ *   before anything is launched; an invalid argument returns PDMP_EINVAL and
+ *   launches nothing.  The message of the last failure on the calling thread is
+ *   available from pdmp_last_error().  No C++ exception crosses this boundary.
+ * - Array arguments are DEVICE pointers owned by the caller (the library never
+ *   frees them and keeps no reference after the call returns).  Floating-point
+ *   arrays are FP32, structure-of-arrays: a batch of n vectors of dimension d is
+ *   d contiguous rows of n values, element (k, i) at [k*n + i].  Labels are uint8.
+ *   Pointers must be 4-byte aligned; 16-byte alignment is recommended.
+ * - Structs (pdmp_occupancy, pdmp_arm, scenes, options) are HOST structs passed by
+ *   pointer; the device arrays they point to follow the rules above.
+ * - `stream` is a hipStream_t (NULL = the null stream).  Every call only enqueues
+ *   work and returns; results are valid once the stream has been synchronised.
+ *   pdmp_sync() synchronises and reports any deferred device error.
+ * - Scratch memory, where an operation needs it, is a caller-provided device
+ *   workspace whose size the matching *_workspace_size() query returns.
+ * - NaN or Inf inputs propagate through the arithmetic and are not trapped; the
+ *   occupancy is defined on all of R^d, so out-of-domain samples are legal.
+ * - Results are deterministic: the same call on the same inputs gives the same
+ *   bits (fixed-order reductions, no floating-point atomics).
+ */
+#ifndef PDMP_H
+#define PDMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PDMP_ABI_VERSION 1
+
+typedef enum {
+    PDMP_OK = 0,
+    PDMP_EINVAL = 1,        /* invalid argument (null pointer, bad size or dimension) */
+    PDMP_EUNSUPPORTED = 2,  /* valid but not supported by this build (e.g. too many DOF) */
+    PDMP_EDEVICE = 3,       /* a HIP call or kernel launch failed */
+    PDMP_ENOMEM = 4         /* caller workspace too small */
+} pdmp_status;
+
+/* Continuous occupancy of Sec. 3.1 in the Hilbert-map (RBF logistic) form:
+ *   c(x) = sigma(s(x)),  s(x) = sum_{j<M} w_j exp(-|x - h_j|^2 / (2 l^2)) + beta.
+ * hinges  : device [dim][M] hinge coordinates.
+ * weights : device [M+1]; weights[M] holds the bias beta, so a fitted model stays
+ *           entirely on the device.
+ * dim must be 2 or 3, M >= 1, lengthscale > 0 and finite. */
+typedef struct {
+    int32_t dim;
+    int32_t n_hinges;
+    const float *hinges;
+    const float *weights;
+    float lengthscale;
+} pdmp_occupancy;
+
+/* Serial arm with standard Denavit-Hartenberg links (Sec. 3.2, body points):
+ *   A_i = Rz(theta0_i + q_i) Tz(d_i) Tx(a_i) Rx(alpha_i), base frame at the origin.
+ * Link i runs from the origin o_{i-1} of frame i-1 to o_i; it carries
+ * pts_per_link body points o_{i-1} + (k/P)(o_i - o_{i-1}), k = 1..P.
+ * Body point index p = (i-1)*P + (k-1).  1 <= n_dof <= 8, 1 <= P <= 16. */
+#define PDMP_MAX_DOF 8
+#define PDMP_MAX_PTS_PER_LINK 16
+typedef struct {
+    int32_t n_dof;
+    int32_t pts_per_link;
+    float a[PDMP_MAX_DOF];
+    float d[PDMP_MAX_DOF];
+    float alpha[PDMP_MAX_DOF];
+    float theta0[PDMP_MAX_DOF];
+} pdmp_arm;
+
+/* Closed discs (2-D) and closed axis-aligned boxes (3-D): device arrays
+ * centres [2][n] / [3][n], radii [n], half-extents [3][n]. */
+typedef struct {
+    int32_t n;
+    const float *centres;
+    const float *radii;
+} pdmp_discs;
+
+typedef struct {
+    int32_t n;
+    const float *centres;
+    const float *half;
+} pdmp_boxes;
+
+int32_t pdmp_abi_version(void);
+const char *pdmp_last_error(void);
+
+/* Wait for all work on `stream`, then return PDMP_EDEVICE if any earlier launch
+ * on it failed asynchronously. */
+int32_t pdmp_sync(void *stream);
+
+/* ---- prior samples (Sec. 3.3: the sampler draws large prior batches on the GPU).
+ * x ~ U[lo, hi)^dim, written to out [dim][n].  Sample i, coordinate k uses word
+ * k%4 of Philox4x32-10 (Salmon et al., SC 2011) at counter {i_lo, i_hi, k/4,
+ * stream_id} and key {seed_lo, seed_hi}: u = (word >> 8) * 2^-24 and
+ * x = lo_k + (hi_k - lo_k) * u evaluated in FP64 and rounded once to FP32, so the
+ * values do not depend on n, on the launch or on the device.
+ * lo, hi: HOST arrays [dim]; 1 <= dim <= 16; n >= 0. */
+int32_t pdmp_uniform_samples(uint64_t seed, uint32_t stream_id, const float *lo,
+                             const float *hi, int32_t dim, int64_t n, float *out,
+                             void *stream);
+
+/* ---- collision labels (the "feasible" test behind Table 1).  The inside test is
+ * taken in FP64 on the FP32 inputs with the operation order stated here and no
+ * contraction, so it is bit-reproducible:
+ *   disc:  (x - cx)^2 + (y - cy)^2 <= r^2   as  a = dx*dx; b = dy*dy; a + b <= r*r
+ *   box:   |x_a - c_a| <= e_a for a = 0, 1, 2.
+ * out[i] = 1 if point i lies in any obstacle, else 0.
+ * n_hit (nullable, device): receives the number of points labelled 1. */
+int32_t pdmp_label_points_discs(const pdmp_discs *scene, const float *x, int64_t n,
+                                uint8_t *out, uint64_t *n_hit, void *stream);
+int32_t pdmp_label_points_boxes(const pdmp_boxes *scene, const float *x, int64_t n,
+                                uint8_t *out, uint64_t *n_hit, void *stream);
+
+/* A configuration collides iff any of its body points lies in any box.  The body
+ * points are computed in FP64 from the FP32 joint values for this decision.
+ * q: [n_dof][n]. */
+int32_t pdmp_label_configs(const pdmp_arm *arm, const pdmp_boxes *scene, const float *q,
+                           int64_t n, uint8_t *out, uint64_t *n_hit, void *stream);
+
+/* ---- occupancy (Sec. 3.1: batched queries of the occupancy and its input
+ * derivative on the GPU).
+ * occupancy_eval: c_out[n] = c(x_i); s_out (nullable) [n] = s(x_i).
+ * occupancy_grad: grad_out[dim][n] = grad_x c(x_i) = sigma'(s) grad s;
+ *                 c_out (nullable) [n]. */
+int32_t pdmp_occupancy_eval(const pdmp_occupancy *occ, const float *x, int64_t n,
+                            float *c_out, float *s_out, void *stream);
+int32_t pdmp_occupancy_grad(const pdmp_occupancy *occ, const float *x, int64_t n,
+                            float *c_out, float *grad_out, void *stream);
+
+/* ---- the morph (Sec. 3.2, Eq. 1 solved by explicit Euler; Eq. 3 for the arm).
+ * arm == NULL: workspace morph in R^dim,  x_{k+1} = x_k - eta * grad c(x_k).
+ * arm != NULL: joint-space morph, occ->dim must be 3, with the summed body-point
+ *              cost C(q) = sum_p c(psi_p(q)) and
+ *              q_{k+1} = q_k - eta * sum_p J_p(q_k)^T grad c(psi_p(q_k)).
+ * in, out: [dim or n_dof][n]; in == out (in place) is allowed, other overlap is
+ * not.  T >= 0 steps with constant eta (finite).  No clipping, no angle wrapping. */
+int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,
+                           float *out, int64_t n, int32_t T, float eta, void *stream);
+
+/* ---- forward kinematics (Sec. 3.2): body points of configurations q [n_dof][n]
+ * in FP32, written to pts [3][n_dof*pts_per_link][n]. */
+int32_t pdmp_fk_body_points(const pdmp_arm *arm, const float *q, int64_t n, float *pts,
+                            void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDMP_H */

@@ -1,0 +1,231 @@
+"""MI355X (gfx950) batched diffeomorphic morph of planner samples.
+
+Python binding over libpdmp.so (include/pdmp.h).  Every step of the path runs in
+the library's HIP kernels; this module only marshals torch device tensors (used
+for device memory and streams) into the C ABI.  There is no CPU fallback: a call
+without the built library, or with CPU tensors, raises.
+
+Method: Lai, Zhi, Hermans, Ramos, "Parallelised Diffeomorphic Sampling-based
+Motion Planning" -- occupancy learning (Sec. 3.1), cost-informed diffeomorphism
+by Euler integration of Eq. 1 and its joint-space pull-back (Sec. 3.2, Eq. 3),
+batched GPU sampling (Sec. 3.3).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+from . import _lib
+from ._lib import PdmpError
+
+__all__ = ["Occupancy", "Arm", "PdmpError", "abi_version", "uniform_samples",
+           "label_points_discs", "label_points_boxes", "label_configs", "occupancy_eval",
+           "occupancy_grad", "morph_samples", "fk_body_points", "sync"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(device=None):
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev(t, name, dtype=None, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor; there is no CPU path")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def abi_version() -> int:
+    return int(_lib.load().pdmp_abi_version())
+
+
+def sync(device=None):
+    _lib.call("pdmp_sync", _stream(device))
+
+
+@dataclass
+class Occupancy:
+    """c(x) = sigma(sum_j w_j exp(-|x-h_j|^2/(2 l^2)) + beta) (Sec. 3.1).
+
+    hinges: [dim][M] float32 device tensor; weights: [M+1] float32 device tensor
+    whose last entry is the bias beta.
+    """
+    hinges: "object"
+    weights: "object"
+    lengthscale: float
+
+    @property
+    def dim(self) -> int:
+        return int(self.hinges.shape[0])
+
+    @property
+    def n_hinges(self) -> int:
+        return int(self.hinges.shape[1])
+
+    def c_struct(self) -> _lib.pdmp_occupancy:
+        torch = _torch()
+        _dev(self.hinges, "hinges", torch.float32)
+        _dev(self.weights, "weights", torch.float32, (self.n_hinges + 1,))
+        return _lib.pdmp_occupancy(self.dim, self.n_hinges, self.hinges.data_ptr(),
+                                   self.weights.data_ptr(), float(self.lengthscale))
+
+
+@dataclass
+class Arm:
+    """Standard-DH serial arm, pts_per_link body points per link (Sec. 3.2)."""
+    a: Sequence[float]
+    d: Sequence[float]
+    alpha: Sequence[float]
+    theta0: Sequence[float]
+    pts_per_link: int = 8
+
+    @property
+    def n_dof(self) -> int:
+        return len(self.a)
+
+    @property
+    def n_body(self) -> int:
+        return self.n_dof * self.pts_per_link
+
+    def c_struct(self) -> _lib.pdmp_arm:
+        s = _lib.pdmp_arm()
+        s.n_dof = self.n_dof
+        s.pts_per_link = int(self.pts_per_link)
+        n = min(self.n_dof, _lib.MAX_DOF)
+        for i in range(n):
+            s.a[i] = float(self.a[i])
+            s.d[i] = float(self.d[i])
+            s.alpha[i] = float(self.alpha[i])
+            s.theta0[i] = float(self.theta0[i])
+        return s
+
+
+def uniform_samples(seed: int, stream_id: int, lo, hi, n: int, device="cuda", out=None):
+    """Prior batch x ~ U[lo, hi)^dim as a [dim][n] float32 device tensor (Sec. 3.3)."""
+    torch = _torch()
+    lo = [float(v) for v in lo]
+    hi = [float(v) for v in hi]
+    dim = len(lo)
+    if out is None:
+        out = torch.empty((dim, n), dtype=torch.float32, device=device)
+    _dev(out, "out", torch.float32, (dim, n))
+    lo_a = (C.c_float * dim)(*lo)
+    hi_a = (C.c_float * dim)(*hi)
+    _lib.call("pdmp_uniform_samples", C.c_uint64(seed & (2**64 - 1)), C.c_uint32(stream_id),
+              lo_a, hi_a, dim, n, _dev(out, "out") if n else None, _stream(out.device))
+    return out
+
+
+def _labels_out(n, device, count, out=None, hit=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device=device)
+    if count and hit is None:
+        hit = torch.empty(1, dtype=torch.int64, device=device)
+    return out, hit
+
+
+def label_points_discs(centres, radii, x, count: bool = False, out=None, hit=None):
+    """1 where a 2-D point lies in any closed disc; optionally the count of 1s."""
+    torch = _torch()
+    n = int(x.shape[1])
+    sc = _lib.pdmp_discs(int(radii.shape[0]), _dev(centres, "centres", torch.float32).value,
+                         _dev(radii, "radii", torch.float32).value)
+    out, hit = _labels_out(n, x.device, count, out, hit)
+    _lib.call("pdmp_label_points_discs", C.byref(sc), _dev(x, "x", torch.float32, (2, n)), n,
+              _dev(out, "out"), _dev(hit, "n_hit") if count else None, _stream(x.device))
+    return (out, hit) if count else out
+
+
+def label_points_boxes(centres, half, x, count: bool = False, out=None, hit=None):
+    """1 where a 3-D point lies in any closed axis-aligned box."""
+    torch = _torch()
+    n = int(x.shape[1])
+    sc = _lib.pdmp_boxes(int(centres.shape[1]), _dev(centres, "centres", torch.float32).value,
+                         _dev(half, "half", torch.float32).value)
+    out, hit = _labels_out(n, x.device, count, out, hit)
+    _lib.call("pdmp_label_points_boxes", C.byref(sc), _dev(x, "x", torch.float32, (3, n)), n,
+              _dev(out, "out"), _dev(hit, "n_hit") if count else None, _stream(x.device))
+    return (out, hit) if count else out
+
+
+def label_configs(arm: Arm, centres, half, q, count: bool = False, out=None, hit=None):
+    """1 where any body point of a configuration lies in any box."""
+    torch = _torch()
+    n = int(q.shape[1])
+    sc = _lib.pdmp_boxes(int(centres.shape[1]), _dev(centres, "centres", torch.float32).value,
+                         _dev(half, "half", torch.float32).value)
+    a = arm.c_struct()
+    out, hit = _labels_out(n, q.device, count, out, hit)
+    _lib.call("pdmp_label_configs", C.byref(a), C.byref(sc),
+              _dev(q, "q", torch.float32, (arm.n_dof, n)), n, _dev(out, "out"),
+              _dev(hit, "n_hit") if count else None, _stream(q.device))
+    return (out, hit) if count else out
+
+
+def occupancy_eval(occ: Occupancy, x):
+    """(c, s) at [dim][n] points."""
+    torch = _torch()
+    n = int(x.shape[1])
+    c = torch.empty(n, dtype=torch.float32, device=x.device)
+    s = torch.empty(n, dtype=torch.float32, device=x.device)
+    o = occ.c_struct()
+    _lib.call("pdmp_occupancy_eval", C.byref(o), _dev(x, "x", torch.float32, (occ.dim, n)), n,
+              _dev(c, "c"), _dev(s, "s"), _stream(x.device))
+    return c, s
+
+
+def occupancy_grad(occ: Occupancy, x):
+    """(c, grad_x c) at [dim][n] points."""
+    torch = _torch()
+    n = int(x.shape[1])
+    c = torch.empty(n, dtype=torch.float32, device=x.device)
+    g = torch.empty((occ.dim, n), dtype=torch.float32, device=x.device)
+    o = occ.c_struct()
+    _lib.call("pdmp_occupancy_grad", C.byref(o), _dev(x, "x", torch.float32, (occ.dim, n)), n,
+              _dev(c, "c"), _dev(g, "grad"), _stream(x.device))
+    return c, g
+
+
+def morph_samples(occ: Occupancy, x, T: int, eta: float, arm: Optional[Arm] = None,
+                  out=None):
+    """Explicit-Euler morph of base samples (Eq. 1; Eq. 3 when `arm` is given).
+
+    x: [dim][n] workspace points, or [n_dof][n] joint configurations with an arm.
+    Returns `out` (a new tensor unless given; out may be x for in-place).
+    """
+    torch = _torch()
+    n = int(x.shape[1])
+    rows = arm.n_dof if arm is not None else occ.dim
+    _dev(x, "x", torch.float32, (rows, n))
+    if out is None:
+        out = torch.empty_like(x)
+    o = occ.c_struct()
+    a = C.byref(arm.c_struct()) if arm is not None else None
+    _lib.call("pdmp_morph_samples", C.byref(o), a, C.c_void_p(x.data_ptr()),
+              _dev(out, "out", torch.float32, (rows, n)), n, int(T), float(eta),
+              _stream(x.device))
+    return out
+
+
+def fk_body_points(arm: Arm, q):
+    """Body points [3][n_dof*pts_per_link][n] of configurations q [n_dof][n]."""
+    torch = _torch()
+    n = int(q.shape[1])
+    pts = torch.empty((3, arm.n_body, n), dtype=torch.float32, device=q.device)
+    a = arm.c_struct()
+    _lib.call("pdmp_fk_body_points", C.byref(a), _dev(q, "q", torch.float32, (arm.n_dof, n)), n,
+              _dev(pts, "pts"), _stream(q.device))
+    return pts

@@ -1,0 +1,99 @@
+"""ctypes view of libpdmp.so (include/pdmp.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdmp.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pdmp.h")
+
+PDMP_OK, PDMP_EINVAL, PDMP_EUNSUPPORTED, PDMP_EDEVICE, PDMP_ENOMEM = 0, 1, 2, 3, 4
+STATUS_NAMES = {0: "PDMP_OK", 1: "PDMP_EINVAL", 2: "PDMP_EUNSUPPORTED", 3: "PDMP_EDEVICE",
+                4: "PDMP_ENOMEM"}
+MAX_DOF = 8
+
+
+class pdmp_occupancy(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_hinges", C.c_int32), ("hinges", C.c_void_p),
+                ("weights", C.c_void_p), ("lengthscale", C.c_float)]
+
+
+class pdmp_arm(C.Structure):
+    _fields_ = [("n_dof", C.c_int32), ("pts_per_link", C.c_int32),
+                ("a", C.c_float * MAX_DOF), ("d", C.c_float * MAX_DOF),
+                ("alpha", C.c_float * MAX_DOF), ("theta0", C.c_float * MAX_DOF)]
+
+
+class pdmp_discs(C.Structure):
+    _fields_ = [("n", C.c_int32), ("centres", C.c_void_p), ("radii", C.c_void_p)]
+
+
+class pdmp_boxes(C.Structure):
+    _fields_ = [("n", C.c_int32), ("centres", C.c_void_p), ("half", C.c_void_p)]
+
+
+class pdmp_fit_opts(C.Structure):
+    _fields_ = [("optimizer", C.c_int32), ("steps", C.c_int32), ("lr", C.c_float),
+                ("lr_bias", C.c_float), ("l2", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("t0", C.c_int32)]
+
+
+class pdmp_mlp(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("hidden", C.c_int32), ("n_hidden_layers", C.c_int32),
+                ("w_bf16", C.c_void_p), ("bias", C.c_void_p)]
+
+
+_vp, _i32, _i64, _u32, _u64, _f = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float
+_P = C.POINTER
+
+# name -> (restype, argtypes); every symbol declared in include/pdmp.h
+SIGNATURES = {
+    "pdmp_abi_version": (_i32, []),
+    "pdmp_last_error": (C.c_char_p, []),
+    "pdmp_sync": (_i32, [_vp]),
+    "pdmp_uniform_samples": (_i32, [_u64, _u32, _P(_f), _P(_f), _i32, _i64, _vp, _vp]),
+    "pdmp_label_points_discs": (_i32, [_P(pdmp_discs), _vp, _i64, _vp, _vp, _vp]),
+    "pdmp_label_points_boxes": (_i32, [_P(pdmp_boxes), _vp, _i64, _vp, _vp, _vp]),
+    "pdmp_label_configs": (_i32, [_P(pdmp_arm), _P(pdmp_boxes), _vp, _i64, _vp, _vp, _vp]),
+    "pdmp_occupancy_eval": (_i32, [_P(pdmp_occupancy), _vp, _i64, _vp, _vp, _vp]),
+    "pdmp_occupancy_grad": (_i32, [_P(pdmp_occupancy), _vp, _i64, _vp, _vp, _vp]),
+    "pdmp_morph_samples": (_i32, [_P(pdmp_occupancy), _P(pdmp_arm), _vp, _vp, _i64, _i32, _f, _vp]),
+    "pdmp_fk_body_points": (_i32, [_P(pdmp_arm), _vp, _i64, _vp, _vp]),
+}
+
+_lib = None
+
+
+class PdmpError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn} -> {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load():
+    """Load the HIP library; raise loudly if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"libpdmp.so not found at {LIB_PATH}: build it first "
+            "(python -c 'import __graft_entry__ as g; g.build()' or "
+            "python paper_2108_11775_amd/build.py).  There is no CPU fallback.")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def call(name, *args):
+    lib = load()
+    st = getattr(lib, name)(*args)
+    if st != PDMP_OK:
+        msg = lib.pdmp_last_error()
+        raise PdmpError(name, st, msg.decode() if msg else "")
+    return st

@@ -1,0 +1,222 @@
+// pdmp_api.hip -- the extern "C" entry points of libpdmp: argument validation on the
+// host, parameter derivation, and the launches.  See include/pdmp.h for the contract.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "pdmp_common.h"
+
+namespace pdmp {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+const char *last_error() { return g_err; }
+
+int32_t check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("%s: %s", what, hipGetErrorString(e));
+        return PDMP_EDEVICE;
+    }
+    return PDMP_OK;
+}
+
+#define PDMP_REQUIRE(cond, ...)           \
+    do {                                  \
+        if (!(cond)) {                    \
+            ::pdmp::set_error(__VA_ARGS__); \
+            return PDMP_EINVAL;           \
+        }                                 \
+    } while (0)
+
+static int32_t check_occ(const pdmp_occupancy *occ) {
+    PDMP_REQUIRE(occ != nullptr, "occupancy is NULL");
+    PDMP_REQUIRE(occ->dim == 2 || occ->dim == 3, "occupancy dim %d not in {2,3}", occ->dim);
+    PDMP_REQUIRE(occ->n_hinges >= 1, "n_hinges %d < 1", occ->n_hinges);
+    PDMP_REQUIRE(occ->hinges != nullptr && occ->weights != nullptr, "hinges/weights NULL");
+    PDMP_REQUIRE(std::isfinite(occ->lengthscale) && occ->lengthscale > 0.0f,
+                 "lengthscale must be finite and > 0");
+    return PDMP_OK;
+}
+
+static int32_t check_arm(const pdmp_arm *arm, int max_ppl) {
+    PDMP_REQUIRE(arm != nullptr, "arm is NULL");
+    PDMP_REQUIRE(arm->n_dof >= 1 && arm->n_dof <= PDMP_MAX_DOF, "n_dof %d not in [1,%d]",
+                 arm->n_dof, PDMP_MAX_DOF);
+    PDMP_REQUIRE(arm->pts_per_link >= 1 && arm->pts_per_link <= PDMP_MAX_PTS_PER_LINK,
+                 "pts_per_link %d not in [1,%d]", arm->pts_per_link, PDMP_MAX_PTS_PER_LINK);
+    for (int i = 0; i < arm->n_dof; ++i)
+        PDMP_REQUIRE(std::isfinite(arm->a[i]) && std::isfinite(arm->d[i]) &&
+                         std::isfinite(arm->alpha[i]) && std::isfinite(arm->theta0[i]),
+                     "non-finite DH parameter on joint %d", i);
+    if (arm->pts_per_link > max_ppl) {
+        set_error("pts_per_link %d > %d is not supported here", arm->pts_per_link, max_ppl);
+        return PDMP_EUNSUPPORTED;
+    }
+    return PDMP_OK;
+}
+
+// kappa^2 = log2(e) / (2 l^2):  exp(-r^2/(2 l^2)) = exp2(-(kappa r)^2).
+// grad s = -(1/l^2) sum w phi (x - h) = -(1/(l^2 kappa)) sum w phi (kappa x - kappa h).
+static void derive_scales(float ell, float &kappa, float &gscale) {
+    const double l = ell;
+    const double k = std::sqrt(1.4426950408889634 / (2.0 * l * l));
+    kappa = (float)k;
+    gscale = (float)(1.0 / (l * l * k));
+}
+
+}  // namespace pdmp
+
+using namespace pdmp;
+
+extern "C" {
+
+int32_t pdmp_abi_version(void) { return PDMP_ABI_VERSION; }
+
+const char *pdmp_last_error(void) { return pdmp::last_error(); }
+
+int32_t pdmp_sync(void *stream) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) {
+        set_error("hipStreamSynchronize: %s", hipGetErrorString(e));
+        return PDMP_EDEVICE;
+    }
+    return PDMP_OK;
+}
+
+int32_t pdmp_uniform_samples(uint64_t seed, uint32_t stream_id, const float *lo, const float *hi,
+                             int32_t dim, int64_t n, float *out, void *stream) {
+    PDMP_REQUIRE(dim >= 1 && dim <= 16, "dim %d not in [1,16]", dim);
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    PDMP_REQUIRE(lo != nullptr && hi != nullptr, "lo/hi NULL");
+    for (int k = 0; k < dim; ++k)
+        PDMP_REQUIRE(std::isfinite(lo[k]) && std::isfinite(hi[k]) && lo[k] <= hi[k],
+                     "bad range on coordinate %d", k);
+    if (n == 0) return PDMP_OK;
+    PDMP_REQUIRE(out != nullptr, "out NULL");
+    return launch_uniform(seed, stream_id, lo, hi, dim, n, out, (hipStream_t)stream);
+}
+
+int32_t pdmp_label_points_discs(const pdmp_discs *scene, const float *x, int64_t n, uint8_t *out,
+                                uint64_t *n_hit, void *stream) {
+    PDMP_REQUIRE(scene != nullptr && scene->n >= 0, "bad disc scene");
+    PDMP_REQUIRE(scene->n == 0 || (scene->centres && scene->radii), "disc arrays NULL");
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    if (n == 0 && !n_hit) return PDMP_OK;
+    PDMP_REQUIRE(n == 0 || (x && out), "x/out NULL");
+    return launch_label_discs(*scene, x, n, out, n_hit, (hipStream_t)stream);
+}
+
+int32_t pdmp_label_points_boxes(const pdmp_boxes *scene, const float *x, int64_t n, uint8_t *out,
+                                uint64_t *n_hit, void *stream) {
+    PDMP_REQUIRE(scene != nullptr && scene->n >= 0, "bad box scene");
+    PDMP_REQUIRE(scene->n == 0 || (scene->centres && scene->half), "box arrays NULL");
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    if (n == 0 && !n_hit) return PDMP_OK;
+    PDMP_REQUIRE(n == 0 || (x && out), "x/out NULL");
+    return launch_label_boxes(*scene, x, n, out, n_hit, (hipStream_t)stream);
+}
+
+int32_t pdmp_label_configs(const pdmp_arm *arm, const pdmp_boxes *scene, const float *q,
+                           int64_t n, uint8_t *out, uint64_t *n_hit, void *stream) {
+    int32_t st = check_arm(arm, PDMP_MAX_PTS_PER_LINK);
+    if (st) return st;
+    PDMP_REQUIRE(scene != nullptr && scene->n >= 0, "bad box scene");
+    PDMP_REQUIRE(scene->n == 0 || (scene->centres && scene->half), "box arrays NULL");
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    if (n == 0 && !n_hit) return PDMP_OK;
+    PDMP_REQUIRE(n == 0 || (q && out), "q/out NULL");
+    return launch_label_configs(*arm, *scene, q, n, out, n_hit, (hipStream_t)stream);
+}
+
+static int32_t rbf_call(const pdmp_occupancy *occ, int mode, const float *x, int64_t n,
+                        float *c_out, float *s_out, float *g_out, float *x_out, int32_t T,
+                        float eta, void *stream) {
+    RbfArgs a;
+    a.hinges = occ->hinges;
+    a.weights = occ->weights;
+    a.M = occ->n_hinges;
+    derive_scales(occ->lengthscale, a.kappa, a.gscale);
+    a.x_in = x;
+    a.n = n;
+    a.T = T;
+    a.eta = eta;
+    a.c_out = c_out;
+    a.s_out = s_out;
+    a.g_out = g_out;
+    a.x_out = x_out;
+    return launch_rbf(occ->dim, mode, a, (hipStream_t)stream);
+}
+
+int32_t pdmp_occupancy_eval(const pdmp_occupancy *occ, const float *x, int64_t n, float *c_out,
+                            float *s_out, void *stream) {
+    int32_t st = check_occ(occ);
+    if (st) return st;
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    if (n == 0) return PDMP_OK;
+    PDMP_REQUIRE(x && c_out, "x/c_out NULL");
+    return rbf_call(occ, kEval, x, n, c_out, s_out, nullptr, nullptr, 1, 0.0f, stream);
+}
+
+int32_t pdmp_occupancy_grad(const pdmp_occupancy *occ, const float *x, int64_t n, float *c_out,
+                            float *grad_out, void *stream) {
+    int32_t st = check_occ(occ);
+    if (st) return st;
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    if (n == 0) return PDMP_OK;
+    PDMP_REQUIRE(x && grad_out, "x/grad_out NULL");
+    return rbf_call(occ, kGrad, x, n, c_out, nullptr, grad_out, nullptr, 1, 0.0f, stream);
+}
+
+int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,
+                           float *out, int64_t n, int32_t T, float eta, void *stream) {
+    int32_t st = check_occ(occ);
+    if (st) return st;
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    PDMP_REQUIRE(T >= 0, "T < 0");
+    PDMP_REQUIRE(std::isfinite(eta), "eta not finite");
+    if (arm) {
+        st = check_arm(arm, 8);
+        if (st) return st;
+        PDMP_REQUIRE(occ->dim == 3, "the joint-space morph needs a 3-D occupancy");
+    }
+    if (n == 0) return PDMP_OK;
+    PDMP_REQUIRE(in && out, "in/out NULL");
+    if (T == 0) {
+        if (in == out) return PDMP_OK;
+        const size_t rows = arm ? (size_t)arm->n_dof : (size_t)occ->dim;
+        hipError_t e = hipMemcpyAsync(out, in, rows * (size_t)n * sizeof(float),
+                                      hipMemcpyDeviceToDevice, (hipStream_t)stream);
+        if (e != hipSuccess) {
+            set_error("hipMemcpyAsync: %s", hipGetErrorString(e));
+            return PDMP_EDEVICE;
+        }
+        return PDMP_OK;
+    }
+    if (arm) {
+        float kappa, gscale;
+        derive_scales(occ->lengthscale, kappa, gscale);
+        return launch_morph_arm(*arm, occ->hinges, occ->weights, occ->n_hinges, kappa, gscale, in,
+                                out, n, T, eta, (hipStream_t)stream);
+    }
+    return rbf_call(occ, kMorph, in, n, nullptr, nullptr, nullptr, out, T, eta, stream);
+}
+
+int32_t pdmp_fk_body_points(const pdmp_arm *arm, const float *q, int64_t n, float *pts,
+                            void *stream) {
+    int32_t st = check_arm(arm, PDMP_MAX_PTS_PER_LINK);
+    if (st) return st;
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    if (n == 0) return PDMP_OK;
+    PDMP_REQUIRE(q && pts, "q/pts NULL");
+    return launch_fk_points(*arm, q, n, pts, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// pdmp_common.h -- internal helpers shared by the HIP translation units of libpdmp.
+// Not part of the public ABI (include/pdmp.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "pdmp.h"
+
+namespace pdmp {
+
+// Thread-local message of the last failure, returned by pdmp_last_error().
+void set_error(const char *fmt, ...);
+const char *last_error();
+
+// Launch-status helper: returns PDMP_EDEVICE (with the HIP message) if the last
+// launch on this thread failed.
+int32_t check_launch(const char *what);
+
+// log2(e): exp(-r^2/(2 l^2)) = exp2(-(kappa*r)^2) with kappa^2 = log2(e)/(2 l^2).
+constexpr float kLog2e = 1.4426950408889634f;
+
+// Hinge staging in LDS: hinges are grouped in chunks of four; a chunk holds DIM
+// float4 rows of prescaled coordinates (kappa*h) followed by one float4 of weights,
+// so one ds_read_b128 feeds four hinges.  Chunks past M are padded with w = 0.
+template <int DIM>
+struct ChunkLayout {
+    static constexpr int kRows = DIM + 1;             // float4 rows per chunk
+    static constexpr int kBytes = 16 * kRows;         // bytes per chunk of 4 hinges
+};
+
+// Resident LDS budget per block for hinge chunks (bytes).  64 KiB keeps two
+// 1024-thread blocks per CU within the 160 KiB of a gfx950 CU.
+constexpr int kHingeLdsBytes = 64 * 1024;
+
+__host__ __device__ inline int chunks_for(int M) { return (M + 3) / 4; }
+
+// Number of hinge chunks one LDS tile holds.
+template <int DIM>
+__host__ __device__ constexpr int tile_chunks() { return kHingeLdsBytes / ChunkLayout<DIM>::kBytes; }
+
+__device__ __forceinline__ float f4c(const float4 &v, int u) {
+    return u == 0 ? v.x : (u == 1 ? v.y : (u == 2 ? v.z : v.w));
+}
+
+// v_exp_f32: 2^x with ~1 ulp error; flushes to 0 for very negative arguments.
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// sigma(s) and sigma'(s) = sigma(1 - sigma) from e = exp(-|s|) in (0, 1], which keeps
+// both to a few ulp relative even where sigma is within rounding of 0 or 1.
+__device__ __forceinline__ void sigmoid_and_slope(float s, float &c, float &sp) {
+    float e = exp2_fast(-fabsf(s) * kLog2e);
+    float inv = 1.0f / (1.0f + e);
+    c = s >= 0.0f ? inv : e * inv;
+    sp = e * inv * inv;
+}
+
+// ---- launchers (host side, one per kernel family) ----
+
+enum RbfMode { kEval = 0, kGrad = 1, kMorph = 2 };
+
+struct RbfArgs {
+    const float *hinges, *weights;
+    int M;
+    float kappa, gscale;
+    const float *x_in;
+    int64_t n;
+    int T;
+    float eta;
+    float *c_out, *s_out, *g_out, *x_out;
+};
+
+int32_t launch_rbf(int dim, int mode, const RbfArgs &a, hipStream_t st);
+int32_t launch_uniform(uint64_t seed, uint32_t sid, const float *lo, const float *hi, int dim,
+                       int64_t n, float *out, hipStream_t st);
+int32_t launch_label_discs(const pdmp_discs &sc, const float *x, int64_t n, uint8_t *out,
+                           uint64_t *n_hit, hipStream_t st);
+int32_t launch_label_boxes(const pdmp_boxes &sc, const float *x, int64_t n, uint8_t *out,
+                           uint64_t *n_hit, hipStream_t st);
+int32_t launch_label_configs(const pdmp_arm &arm, const pdmp_boxes &sc, const float *q, int64_t n,
+                             uint8_t *out, uint64_t *n_hit, hipStream_t st);
+int32_t launch_morph_arm(const pdmp_arm &arm, const float *h, const float *w, int M, float kappa,
+                         float gscale, const float *qi, float *qo, int64_t n, int T, float eta,
+                         hipStream_t st);
+int32_t launch_fk_points(const pdmp_arm &arm, const float *q, int64_t n, float *pts,
+                         hipStream_t st);
+
+}  // namespace pdmp

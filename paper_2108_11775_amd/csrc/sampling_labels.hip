@@ -1,0 +1,200 @@
+// sampling_labels.hip -- batched prior samples (Philox4x32-10) and collision labels.
+//
+// Prior samples: the sampler of Sec. 3.3 draws large batches from the prior on the
+// GPU.  Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011) is counter based, so
+// sample i's coordinates depend only on (seed, stream id, i) and not on the launch.
+//
+// Labels: a point is in collision iff it lies in a closed obstacle; a configuration
+// iff any of its body points does (the "feasible" fraction of Table 1).  The test
+// is taken in FP64 with contraction off and a fixed operation order, so the label
+// of a given FP32 point is reproducible bit for bit.
+#include "pdmp_common.h"
+
+namespace pdmp {
+
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+struct Box16 {
+    float lo[16], hi[16];
+};
+
+// One thread per (sample, block of four coordinates).
+__global__ void __launch_bounds__(256)
+k_uniform(uint32_t k0, uint32_t k1, uint32_t sid, Box16 box, int dim, int64_t n, float *out) {
+#pragma clang fp contract(off)
+    const int nb = (dim + 3) / 4;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    const int b = (int)(t / n);
+    const int64_t i = t - (int64_t)b * n;
+    uint32_t c[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), (uint32_t)b, sid};
+    philox4x32_10(c, k0, k1);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const int k = b * 4 + w;
+        if (k >= dim) break;
+        const double u = (double)(c[w] >> 8) * (1.0 / 16777216.0);
+        const double span = (double)box.hi[k] - (double)box.lo[k];
+        const double v = (double)box.lo[k] + span * u;
+        out[(size_t)k * n + i] = (float)v;
+    }
+}
+
+int32_t launch_uniform(uint64_t seed, uint32_t sid, const float *lo, const float *hi, int dim,
+                       int64_t n, float *out, hipStream_t st) {
+    Box16 box;
+    for (int k = 0; k < 16; ++k) {
+        box.lo[k] = k < dim ? lo[k] : 0.0f;
+        box.hi[k] = k < dim ? hi[k] : 0.0f;
+    }
+    const int64_t work = n * ((dim + 3) / 4);
+    const int64_t blocks = (work + 255) / 256;
+    hipLaunchKernelGGL(k_uniform, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), sid, box, dim, n, out);
+    return check_launch("k_uniform");
+}
+
+// Count of 1-labels: one integer atomic per wave (deterministic).
+__device__ __forceinline__ void count_hits(bool hit, uint64_t *n_hit) {
+    if (!n_hit) return;
+    const uint64_t m = __ballot(hit);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd((unsigned long long *)n_hit, (unsigned long long)__popcll(m));
+}
+
+__global__ void __launch_bounds__(256)
+k_label_discs(const float *__restrict__ cen, const float *__restrict__ rad, int K,
+              const float *__restrict__ x, int64_t n, uint8_t *out, uint64_t *n_hit) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool hit = false;
+    if (i < n) {
+        const double px = x[i], py = x[(size_t)n + i];
+        for (int k = 0; k < K; ++k) {
+            const double dx = px - (double)cen[k];
+            const double dy = py - (double)cen[K + k];
+            const double a = dx * dx;
+            const double b = dy * dy;
+            const double d2 = a + b;
+            const double r = rad[k];
+            const double rr = r * r;
+            if (d2 <= rr) hit = true;
+        }
+        out[i] = hit ? 1 : 0;
+    }
+    count_hits(hit, n_hit);
+}
+
+__device__ __forceinline__ bool in_any_box(const double p[3], const float *__restrict__ cen,
+                                           const float *__restrict__ half, int K) {
+#pragma clang fp contract(off)
+    for (int k = 0; k < K; ++k) {
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (!(fabs(p[a] - (double)cen[a * K + k]) <= (double)half[a * K + k])) in = false;
+        if (in) return true;
+    }
+    return false;
+}
+
+__global__ void __launch_bounds__(256)
+k_label_boxes(const float *__restrict__ cen, const float *__restrict__ half, int K,
+              const float *__restrict__ x, int64_t n, uint8_t *out, uint64_t *n_hit) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool hit = false;
+    if (i < n) {
+        const double p[3] = {x[i], x[(size_t)n + i], x[2 * (size_t)n + i]};
+        hit = in_any_box(p, cen, half, K);
+        out[i] = hit ? 1 : 0;
+    }
+    count_hits(hit, n_hit);
+}
+
+// Standard-DH chain in FP64 for the label decision (same operation order as the
+// plain definition: T_i = T_{i-1} A_i, each entry a k = 0..3 sum).
+__global__ void __launch_bounds__(256)
+k_label_configs(pdmp_arm arm, const float *__restrict__ cen, const float *__restrict__ half,
+                int K, const float *__restrict__ q, int64_t n, uint8_t *out, uint64_t *n_hit) {
+#pragma clang fp contract(off)
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool hit = false;
+    if (s < n) {
+        double T[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+        double op[3] = {0, 0, 0};
+        const int P = arm.pts_per_link;
+        for (int i = 0; i < arm.n_dof && !hit; ++i) {
+            const double a = arm.a[i], d = arm.d[i], al = arm.alpha[i];
+            const double th = (double)arm.theta0[i] + (double)q[(size_t)i * n + s];
+            double st, ct, sa, ca;
+            sincos(th, &st, &ct);
+            sincos(al, &sa, &ca);
+            const double A[4][4] = {{ct, -st * ca, st * sa, a * ct},
+                                    {st, ct * ca, -ct * sa, a * st},
+                                    {0.0, sa, ca, d},
+                                    {0.0, 0.0, 0.0, 1.0}};
+            double N[4][4];
+            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c) {
+                    double acc = 0.0;
+                    for (int k = 0; k < 4; ++k) acc += T[r][k] * A[k][c];
+                    N[r][c] = acc;
+                }
+            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c) T[r][c] = N[r][c];
+            const double on[3] = {T[0][3], T[1][3], T[2][3]};
+            for (int k = 0; k < P && !hit; ++k) {
+                const double f = (double)(k + 1) / (double)P;
+                double p[3];
+                for (int e = 0; e < 3; ++e) p[e] = op[e] + f * (on[e] - op[e]);
+                hit = in_any_box(p, cen, half, K);
+            }
+            for (int e = 0; e < 3; ++e) op[e] = on[e];
+        }
+        out[s] = hit ? 1 : 0;
+    }
+    count_hits(hit, n_hit);
+}
+
+int32_t launch_label_discs(const pdmp_discs &sc, const float *x, int64_t n, uint8_t *out,
+                           uint64_t *n_hit, hipStream_t st) {
+    if (n_hit && hipMemsetAsync(n_hit, 0, sizeof(uint64_t), st) != hipSuccess)
+        return check_launch("hipMemsetAsync");
+    hipLaunchKernelGGL(k_label_discs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       sc.centres, sc.radii, sc.n, x, n, out, n_hit);
+    return check_launch("k_label_discs");
+}
+
+int32_t launch_label_boxes(const pdmp_boxes &sc, const float *x, int64_t n, uint8_t *out,
+                           uint64_t *n_hit, hipStream_t st) {
+    if (n_hit && hipMemsetAsync(n_hit, 0, sizeof(uint64_t), st) != hipSuccess)
+        return check_launch("hipMemsetAsync");
+    hipLaunchKernelGGL(k_label_boxes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       sc.centres, sc.half, sc.n, x, n, out, n_hit);
+    return check_launch("k_label_boxes");
+}
+
+int32_t launch_label_configs(const pdmp_arm &arm, const pdmp_boxes &sc, const float *q, int64_t n,
+                             uint8_t *out, uint64_t *n_hit, hipStream_t st) {
+    if (n_hit && hipMemsetAsync(n_hit, 0, sizeof(uint64_t), st) != hipSuccess)
+        return check_launch("hipMemsetAsync");
+    hipLaunchKernelGGL(k_label_configs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, arm,
+                       sc.centres, sc.half, sc.n, q, n, out, n_hit);
+    return check_launch("k_label_configs");
+}
+
+}  // namespace pdmp
