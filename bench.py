@@ -24,17 +24,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X published peaks and the chip's unit counts (256 CUs, 2.4 GHz).
-PEAK_FP32_VALU = 157.3e12          # FLOP/s, dense FP32 vector
-# v_exp_f32 issues at half rate (8 cycles per wave64 on a 16-lane SIMD): 4 SIMDs x
-# 16 lanes x 1/2 per clock per CU.
+PEAK_FP32_VALU = 157.3e12          # FLOP/s, dense FP32 vector (packed issue)
+# v_exp_f32 runs at half rate (8 cycles per wave64 on a 16-lane SIMD): 4 SIMDs x
+# 16 lanes x 1/2 per clock per CU.  Measured on the part, it overlaps with
+# independent VALU work, so the pair bound is max(flop time, exp time).
 PEAK_EXP = 256 * 4 * 16 * 0.5 * 2.4e9
 FLOPS_PER_PAIR = {2: 12, 3: 17}    # 5*dim + 2 algorithmic FP32 flops per sample-hinge pair
 
 
 def alu_peak_tflops(dim):
-    """Additive issue bound for one pair = f flops + 1 exp, expressed as FP32 TFLOP/s."""
+    """Bound for one pair = f flops + 1 exp (max model), as FP32 TFLOP/s."""
     f = FLOPS_PER_PAIR[dim]
-    t_pair = f / PEAK_FP32_VALU + 1.0 / PEAK_EXP
+    t_pair = max(f / PEAK_FP32_VALU, 1.0 / PEAK_EXP)
     return f / t_pair / 1e12
 
 
@@ -44,7 +45,7 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample", type=int, default=4096,
+    p.add_argument("--cpu-sample", type=int, default=1 << 17,
                    help="samples of the batch the oracle morphs for the CPU baseline")
     return p.parse_args()
 

@@ -151,6 +151,62 @@ int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const
 int32_t pdmp_fk_body_points(const pdmp_arm *arm, const float *q, int64_t n, float *pts,
                             void *stream);
 
+/* ---- occupancy fit (Sec. 3.1: binary cross-entropy minimised by gradient-descent
+ * optimisers), full batch over n labelled points:
+ *   L(w, beta) = (1/n) sum_i BCE(sigma(s(x_i)), y_i) + (l2/2) sum_j w_j^2   (beta free)
+ *   grad_w = (1/n) Phi^T r + l2 w,  grad_beta = (1/n) sum_i r_i,  r_i = sigma(s_i) - y_i.
+ * optimizer 0 (gradient descent): w -= lr grad_w, beta -= lr_bias grad_beta.
+ * optimizer 1 (Adam, Kingma & Ba 2015, Alg. 1, bias-corrected, eps added to
+ *   sqrt(v_hat)): step lr on every parameter; adam_m, adam_v are device [M+1] state,
+ *   in/out; the step counter continues from t0 (first step uses t0 + 1). */
+typedef struct {
+    int32_t optimizer;
+    int32_t steps;
+    float lr;
+    float lr_bias;
+    float l2;
+    float beta1, beta2, eps;
+    int32_t t0;
+    float *adam_m;
+    float *adam_v;
+} pdmp_fit_opts;
+
+/* Workspace bytes for pdmp_fit_occupancy / pdmp_occupancy_bwd / pdmp_bce_logits. */
+size_t pdmp_fit_workspace_size(int32_t dim, int32_t n_hinges, int64_t n);
+size_t pdmp_bwd_workspace_size(int32_t dim, int32_t n_hinges, int64_t n);
+size_t pdmp_bce_workspace_size(int64_t n);
+
+/* Fit the occupancy.  Hinges, dim and lengthscale come from `occ` (occ->weights is
+ * not read); `weights` is the device [M+1] model (w, then beta), read as the
+ * starting point and overwritten with the result.  pts: [dim][n] device; labels:
+ * [n] device uint8 (nonzero = occupied).  loss_out (nullable): device [steps], the
+ * loss at the start of each step.  Deterministic. */
+int32_t pdmp_fit_occupancy(const pdmp_occupancy *occ, float *weights, const float *pts,
+                           const uint8_t *labels, int64_t n, const pdmp_fit_opts *opts,
+                           float *loss_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Hand-written backward of the occupancy at n points x [dim][n].
+ * s_fwd == NULL: g is dL/ds (the logit);  s_fwd != NULL: g is dL/dc and s_fwd the
+ * forward logits, so the chain through sigma'(s) is applied.  Outputs (each
+ * nullable): grad_w [M+1] = (sum_i g_i ds_i/dw_j, sum_i g_i ds_i/dbeta) (chained),
+ * grad_x [dim][n] = g_i ds_i/dx_i (chained). */
+int32_t pdmp_occupancy_bwd(const pdmp_occupancy *occ, const float *x, int64_t n, const float *g,
+                           const float *s_fwd, float *grad_w, float *grad_x, void *ws,
+                           size_t ws_bytes, void *stream);
+
+/* Mean binary cross-entropy of sigma(s) against labels y (nonzero = 1), in the
+ * overflow-free form max(s,0) - y s + log(1 + exp(-|s|)).  loss (nullable): device
+ * [1]; g_s (nullable): device [n], dL/ds_i = (sigma(s_i) - y_i)/n. */
+int32_t pdmp_bce_logits(const float *s, const uint8_t *y, int64_t n, float *loss, float *g_s,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* One Adam update (Kingma & Ba 2015, Alg. 1) of n device parameters p with gradient
+ * g and state m, v (all FP32, in place), at step t >= 1.  The first n_decay entries
+ * get l2 * p added to their gradient (L2 regularisation). */
+int32_t pdmp_adam_step(float *p, const float *g, float *m, float *v, int64_t n, int64_t n_decay,
+                       int32_t t, float lr, float beta1, float beta2, float eps, float l2,
+                       void *stream);
+
 #ifdef __cplusplus
 }
 #endif

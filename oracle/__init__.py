@@ -50,7 +50,9 @@ def _load():
         "orc_occ_eval": (None, [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_double, _dp, _i64,
                                 _dp, _dp, _dp]),
         "orc_occ_grad": (None, [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_double, _dp, _i64,
-                                _dp, _dp, _dp, _dp]),
+                                _dp, _dp, _dp, _dp, _dp]),
+        "orc_logit_bwd_w_subset": (None, [C.c_int, C.c_int, _dp, C.c_double, _dp, _i64, _dp, _ip,
+                                          C.c_int, _dp, _dp]),
         "orc_occ_hess": (None, [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_double, _dp, _i64,
                                 _dp, _dp]),
         "orc_morph_ws": (None, [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_double, _dp, _i64,
@@ -186,13 +188,13 @@ def occ_eval(occ: Occupancy, x):
     return s, c, sa
 
 
-def occ_grad(occ: Occupancy, x):
-    """(c, grad c, grad s, G_abs) at [dim][n] points."""
+def occ_grad(occ: Occupancy, x, with_raw: bool = False):
+    """(c, grad c, grad s, G_abs[, l^-2 sum |w| phi |x-h|]) at [dim][n] points."""
     x = _d(x)
     dim, n = x.shape
-    c, gc, gs, ga = _zeros(n), _zeros(dim, n), _zeros(dim, n), _zeros(n)
-    _load().orc_occ_grad(*occ.args(), _P(x), n, _P(c), _P(gc), _P(gs), _P(ga))
-    return c, gc, gs, ga
+    c, gc, gs, ga, gr = _zeros(n), _zeros(dim, n), _zeros(dim, n), _zeros(n), _zeros(n)
+    _load().orc_occ_grad(*occ.args(), _P(x), n, _P(c), _P(gc), _P(gs), _P(ga), _P(gr))
+    return (c, gc, gs, ga, gr) if with_raw else (c, gc, gs, ga)
 
 
 def occ_hess(occ: Occupancy, x):
@@ -277,6 +279,17 @@ def logit_bwd(hinges, w, ell, x, g_s, want_w=True, want_x=True):
     gx = _zeros(dim, n) if want_x else None
     _load().orc_logit_bwd(dim, M, _P(h), _P(w), float(ell), _P(x), n, _P(g), _P(gw), _P(gx))
     return gw, gx
+
+
+def logit_bwd_w_subset(hinges, ell, x, g_s, js):
+    """(sum_i g_i phi_ij, sum_i |g_i| phi_ij) for the hinges listed in js only."""
+    h, x, g = _d(hinges), _d(x), _d(g_s)
+    js = np.ascontiguousarray(np.asarray(js, dtype=np.intc))
+    dim, M = h.shape
+    out, ab = _zeros(js.size), _zeros(js.size)
+    _load().orc_logit_bwd_w_subset(dim, M, _P(h), float(ell), _P(x), x.shape[1], _P(g),
+                                   _P(js, _ip), js.size, _P(out), _P(ab))
+    return out, ab
 
 
 def bce_logits(s, y):

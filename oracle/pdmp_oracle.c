@@ -231,9 +231,11 @@ void orc_occ_eval(int dim, int M, const double *h, const double *w, double beta,
     }
 }
 
-/* grad c = sigma'(s) grad s, also grad s and the error scale G_abs. */
+/* grad c = sigma'(s) grad s, also grad s, the error scale G_abs and (graw) the
+ * logit-gradient scale l^-2 sum_j |w_j| phi_j |x - h_j|. */
 void orc_occ_grad(int dim, int M, const double *h, const double *w, double beta, double ell,
-                  const double *x, int64_t n, double *c, double *gc, double *gs, double *gabs) {
+                  const double *x, int64_t n, double *c, double *gc, double *gs, double *gabs,
+                  double *graw) {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double xi[ORC_MAX_DIM];
@@ -247,6 +249,7 @@ void orc_occ_grad(int dim, int M, const double *h, const double *w, double beta,
             if (gs) gs[(int64_t)k * n + i] = v.gs[k];
         }
         if (gabs) gabs[i] = o.gabs;
+        if (graw) graw[i] = v.graw;
     }
 }
 
@@ -501,6 +504,32 @@ void orc_logit_bwd(int dim, int M, const double *h, const double *w, double ell,
             rbf_point(dim, M, h, w, 0.0, ell, xi, 0, &v);
             for (int k = 0; k < dim; ++k) grad_x[(int64_t)k * n + i] = gsv[i] * v.gs[k];
         }
+    }
+}
+
+/* grad_w_j = sum_i gs_i phi_ij for the listed hinges js[0..nj) only (and, in
+ * abs_out, sum_i |gs_i| phi_ij): the same sum as orc_logit_bwd, evaluated for a
+ * subset so that large point sets stay cheap. */
+void orc_logit_bwd_w_subset(int dim, int M, const double *h, double ell, const double *x,
+                            int64_t n, const double *gsv, const int *js, int nj, double *out,
+                            double *abs_out) {
+    double i2l2 = 0.5 / (ell * ell);
+#pragma omp parallel for schedule(static)
+    for (int q = 0; q < nj; ++q) {
+        int j = js[q];
+        double acc = 0.0, aabs = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double r2 = 0.0;
+            for (int k = 0; k < dim; ++k) {
+                double d = x[(int64_t)k * n + i] - h[(int64_t)k * M + j];
+                r2 += d * d;
+            }
+            double phi = exp(-r2 * i2l2);
+            acc += gsv[i] * phi;
+            aabs += fabs(gsv[i]) * phi;
+        }
+        out[q] = acc;
+        if (abs_out) abs_out[q] = aabs;
     }
 }
 

@@ -21,7 +21,8 @@ from ._lib import PdmpError
 
 __all__ = ["Occupancy", "Arm", "PdmpError", "abi_version", "uniform_samples",
            "label_points_discs", "label_points_boxes", "label_configs", "occupancy_eval",
-           "occupancy_grad", "morph_samples", "fk_body_points", "sync"]
+           "occupancy_grad", "morph_samples", "fk_body_points", "sync", "occupancy_bwd",
+           "bce_logits", "adam_step", "fit_occupancy"]
 
 
 def _torch():
@@ -229,3 +230,90 @@ def fk_body_points(arm: Arm, q):
     _lib.call("pdmp_fk_body_points", C.byref(a), _dev(q, "q", torch.float32, (arm.n_dof, n)), n,
               _dev(pts, "pts"), _stream(q.device))
     return pts
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def occupancy_bwd(occ: Occupancy, x, g, s_fwd=None, want_w: bool = True, want_x: bool = True):
+    """Hand-written backward of the occupancy at points x [dim][n].
+
+    g is dL/ds (s_fwd None) or dL/dc (s_fwd = forward logits).  Returns
+    (grad_w [M+1] or None, grad_x [dim][n] or None).
+    """
+    torch = _torch()
+    lib = _lib.load()
+    n = int(x.shape[1])
+    gw = torch.empty(occ.n_hinges + 1, dtype=torch.float32, device=x.device) if want_w else None
+    gx = torch.empty((occ.dim, n), dtype=torch.float32, device=x.device) if want_x else None
+    wsb = lib.pdmp_bwd_workspace_size(occ.dim, occ.n_hinges, n)
+    ws = _workspace(wsb, x.device)
+    o = occ.c_struct()
+    _lib.call("pdmp_occupancy_bwd", C.byref(o), _dev(x, "x", torch.float32, (occ.dim, n)), n,
+              _dev(g, "g", torch.float32, (n,)),
+              _dev(s_fwd, "s_fwd", torch.float32, (n,)) if s_fwd is not None else None,
+              _dev(gw, "grad_w") if want_w else None, _dev(gx, "grad_x") if want_x else None,
+              _dev(ws, "ws"), ws.numel(), _stream(x.device))
+    return gw, gx
+
+
+def bce_logits(s, y):
+    """(mean BCE loss [1], dL/ds [n]) of logits s against uint8 labels y."""
+    torch = _torch()
+    lib = _lib.load()
+    n = int(s.shape[0])
+    loss = torch.empty(1, dtype=torch.float32, device=s.device)
+    g = torch.empty(n, dtype=torch.float32, device=s.device)
+    ws = _workspace(lib.pdmp_bce_workspace_size(n), s.device)
+    _lib.call("pdmp_bce_logits", _dev(s, "s", torch.float32), _dev(y, "y", torch.uint8, (n,)), n,
+              _dev(loss, "loss"), _dev(g, "g"), _dev(ws, "ws"), ws.numel(), _stream(s.device))
+    return loss, g
+
+
+def adam_step(p, g, m, v, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, l2=0.0,
+              n_decay=None):
+    """One in-place Adam update of flat FP32 device tensors (Kingma & Ba 2015, Alg. 1)."""
+    torch = _torch()
+    n = int(p.numel())
+    nd = n if n_decay is None else int(n_decay)
+    _lib.call("pdmp_adam_step", _dev(p, "p", torch.float32), _dev(g, "g", torch.float32, p.shape),
+              _dev(m, "m", torch.float32, p.shape), _dev(v, "v", torch.float32, p.shape), n, nd,
+              int(t), float(lr), float(beta1), float(beta2), float(eps), float(l2),
+              _stream(p.device))
+
+
+def fit_occupancy(hinges, lengthscale: float, weights, pts, labels, steps: int, lr: float,
+                  l2: float, optimizer: str = "gd", lr_bias=None, beta1=0.9, beta2=0.999,
+                  eps=1e-8, adam_m=None, adam_v=None, t0: int = 0, record_loss: bool = True):
+    """Full-batch occupancy fit on the GPU (Sec. 3.1); updates `weights` in place.
+
+    Returns the per-step loss tensor [steps] (device) or None.
+    """
+    torch = _torch()
+    lib = _lib.load()
+    dim, M = int(hinges.shape[0]), int(hinges.shape[1])
+    n = int(pts.shape[1])
+    occ = Occupancy(hinges, weights, lengthscale)
+    o = occ.c_struct()
+    opt = _lib.pdmp_fit_opts()
+    opt.optimizer = 0 if optimizer == "gd" else 1
+    opt.steps = int(steps)
+    opt.lr = float(lr)
+    opt.lr_bias = float(lr if lr_bias is None else lr_bias)
+    opt.l2 = float(l2)
+    opt.beta1, opt.beta2, opt.eps = float(beta1), float(beta2), float(eps)
+    opt.t0 = int(t0)
+    if opt.optimizer == 1:
+        if adam_m is None or adam_v is None:
+            raise ValueError("Adam needs adam_m and adam_v state tensors [M+1]")
+        opt.adam_m = _dev(adam_m, "adam_m", torch.float32, (M + 1,)).value
+        opt.adam_v = _dev(adam_v, "adam_v", torch.float32, (M + 1,)).value
+    loss = torch.empty(max(steps, 1), dtype=torch.float32, device=pts.device) if record_loss else None
+    ws = _workspace(lib.pdmp_fit_workspace_size(dim, M, n), pts.device)
+    _lib.call("pdmp_fit_occupancy", C.byref(o), _dev(weights, "weights", torch.float32, (M + 1,)),
+              _dev(pts, "pts", torch.float32, (dim, n)), _dev(labels, "labels", torch.uint8, (n,)),
+              n, C.byref(opt), _dev(loss, "loss") if record_loss else None, _dev(ws, "ws"),
+              ws.numel(), _stream(pts.device))
+    return loss[:steps] if record_loss else None

@@ -36,12 +36,8 @@ class pdmp_boxes(C.Structure):
 class pdmp_fit_opts(C.Structure):
     _fields_ = [("optimizer", C.c_int32), ("steps", C.c_int32), ("lr", C.c_float),
                 ("lr_bias", C.c_float), ("l2", C.c_float), ("beta1", C.c_float),
-                ("beta2", C.c_float), ("eps", C.c_float), ("t0", C.c_int32)]
-
-
-class pdmp_mlp(C.Structure):
-    _fields_ = [("n_in", C.c_int32), ("hidden", C.c_int32), ("n_hidden_layers", C.c_int32),
-                ("w_bf16", C.c_void_p), ("bias", C.c_void_p)]
+                ("beta2", C.c_float), ("eps", C.c_float), ("t0", C.c_int32),
+                ("adam_m", C.c_void_p), ("adam_v", C.c_void_p)]
 
 
 _vp, _i32, _i64, _u32, _u64, _f = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float
@@ -60,6 +56,15 @@ SIGNATURES = {
     "pdmp_occupancy_grad": (_i32, [_P(pdmp_occupancy), _vp, _i64, _vp, _vp, _vp]),
     "pdmp_morph_samples": (_i32, [_P(pdmp_occupancy), _P(pdmp_arm), _vp, _vp, _i64, _i32, _f, _vp]),
     "pdmp_fk_body_points": (_i32, [_P(pdmp_arm), _vp, _i64, _vp, _vp]),
+    "pdmp_fit_workspace_size": (C.c_size_t, [_i32, _i32, _i64]),
+    "pdmp_bwd_workspace_size": (C.c_size_t, [_i32, _i32, _i64]),
+    "pdmp_bce_workspace_size": (C.c_size_t, [_i64]),
+    "pdmp_fit_occupancy": (_i32, [_P(pdmp_occupancy), _vp, _vp, _vp, _i64, _P(pdmp_fit_opts), _vp,
+                                  _vp, C.c_size_t, _vp]),
+    "pdmp_occupancy_bwd": (_i32, [_P(pdmp_occupancy), _vp, _i64, _vp, _vp, _vp, _vp, _vp,
+                                  C.c_size_t, _vp]),
+    "pdmp_bce_logits": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t, _vp]),
+    "pdmp_adam_step": (_i32, [_vp, _vp, _vp, _vp, _i64, _i64, _i32, _f, _f, _f, _f, _f, _vp]),
 }
 
 _lib = None

@@ -78,20 +78,27 @@ __device__ __forceinline__ float group_sum(float v) {
     return v;
 }
 
-// MODE kEval : c_out[n], s_out[n] (nullable)
-// MODE kGrad : c_out[n] (nullable), g_out[DIM][n]
-// MODE kMorph: x_out[DIM][n] after T steps (x_out may equal x_in)
+// MODE kEval   : c_out[n] (nullable), s_out[n] (nullable).  With gridDim.y > 1 the
+//                hinge chunks are split into ranges of `cps` chunks, block row y sums
+//                range y only and writes s_out[y*n + i] (partial sums, no bias).
+// MODE kGrad   : c_out[n] (nullable), g_out[DIM][n] = sigma'(s) grad s
+// MODE kGradBwd: g_out[DIM][n] = g_in[i] * (chain ? sigma'(s) : 1) * grad s
+// MODE kMorph  : x_out[DIM][n] after T steps (x_out may equal x_in)
+// The bias is *bias_ptr (nullable: no bias).
 template <int DIM, int SPL, int G, int BLOCK, int MODE>
 __global__ void __launch_bounds__(BLOCK)
-k_rbf(const float *__restrict__ hinges, const float *__restrict__ weights, int M, float kappa,
-      float gscale, const float *x_in, int64_t n, int T, float eta, float *c_out, float *s_out,
-      float *g_out, float *x_out) {
+k_rbf(const float *__restrict__ hinges, const float *__restrict__ weights, int M,
+      const float *__restrict__ bias_ptr, float kappa, float gscale, const float *x_in, int64_t n,
+      int T, float eta, float *c_out, float *s_out, float *g_out, float *x_out,
+      const float *__restrict__ g_in, int chain, int cps) {
     static_assert(G == 1 || SPL == 1, "lane groups carry one sample");
     constexpr int R = DIM + 1;
     constexpr int TILE = tile_chunks<DIM>();
     extern __shared__ float4 lds[];
 
-    const int nchunks = chunks_for(M);
+    const int nchunks_all = chunks_for(M);
+    const int cbeg = (int)blockIdx.y * cps;                  // this block row's hinge chunks
+    const int nchunks = min(cps, nchunks_all - cbeg);
     const int ntiles = (nchunks + TILE - 1) / TILE;
     const int lg = threadIdx.x % G;
     constexpr int GPB = BLOCK / G;  // sample groups per block
@@ -106,10 +113,10 @@ k_rbf(const float *__restrict__ hinges, const float *__restrict__ weights, int M
 #pragma unroll
         for (int k = 0; k < DIM; ++k) x[s][k] = x_in[(size_t)k * n + i];
     }
-    const float beta = weights[M];
+    const float beta = bias_ptr ? *bias_ptr : 0.0f;
 
     if (ntiles == 1) {
-        stage_chunks<DIM>(lds, hinges, weights, M, kappa, 0, nchunks);
+        stage_chunks<DIM>(lds, hinges, weights, M, kappa, cbeg, nchunks);
         __syncthreads();
     }
 
@@ -131,7 +138,7 @@ k_rbf(const float *__restrict__ hinges, const float *__restrict__ weights, int M
             const int nc = min(TILE, nchunks - c0);
             if (ntiles > 1) {
                 __syncthreads();
-                stage_chunks<DIM>(lds, hinges, weights, M, kappa, c0, nc);
+                stage_chunks<DIM>(lds, hinges, weights, M, kappa, cbeg + c0, nc);
                 __syncthreads();
             }
             for (int c = lg; c < nc; c += G) chunk_accumulate<DIM, SPL>(lds + (size_t)c * R, xs, as, ag);
@@ -162,17 +169,27 @@ k_rbf(const float *__restrict__ hinges, const float *__restrict__ weights, int M
         if (MODE == kMorph) {
 #pragma unroll
             for (int k = 0; k < DIM; ++k) x_out[(size_t)k * n + i] = x[s][k];
+        } else if (MODE == kEval) {
+            const float sv = as[s] + beta;
+            if (c_out) {
+                float c, sp;
+                sigmoid_and_slope(sv, c, sp);
+                c_out[i] = c;
+            }
+            if (s_out) s_out[(size_t)blockIdx.y * n + i] = sv;
         } else {
             const float sv = as[s] + beta;
             float c, sp;
             sigmoid_and_slope(sv, c, sp);
-            if (c_out) c_out[i] = c;
-            if (MODE == kEval) {
-                if (s_out) s_out[i] = sv;
+            float f;
+            if (MODE == kGrad) {
+                if (c_out) c_out[i] = c;
+                f = -sp * gscale;
             } else {
-#pragma unroll
-                for (int k = 0; k < DIM; ++k) g_out[(size_t)k * n + i] = -sp * gscale * ag[s][k];
+                f = -g_in[i] * (chain ? sp : 1.0f) * gscale;
             }
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) g_out[(size_t)k * n + i] = f * ag[s][k];
         }
     }
 }
@@ -183,7 +200,9 @@ template <int DIM, int SPL, int G, int BLOCK, int MODE>
 static int32_t launch_rbf_v(const RbfArgs &a, hipStream_t st) {
     constexpr int TILE = tile_chunks<DIM>();
     const int nchunks = chunks_for(a.M);
-    const int used = nchunks < TILE ? nchunks : TILE;
+    const int splits = a.splits > 1 ? a.splits : 1;
+    const int cps = (nchunks + splits - 1) / splits;
+    const int used = cps < TILE ? cps : TILE;
     const size_t lds = (size_t)used * ChunkLayout<DIM>::kBytes;
     const int64_t per_block = (int64_t)(BLOCK / G) * SPL;
     const int64_t blocks = (a.n + per_block - 1) / per_block;
@@ -191,9 +210,10 @@ static int32_t launch_rbf_v(const RbfArgs &a, hipStream_t st) {
         set_error("batch too large (%lld samples)", (long long)a.n);
         return PDMP_EUNSUPPORTED;
     }
-    hipLaunchKernelGGL((k_rbf<DIM, SPL, G, BLOCK, MODE>), dim3((unsigned)blocks), dim3(BLOCK), lds,
-                       st, a.hinges, a.weights, a.M, a.kappa, a.gscale, a.x_in, a.n, a.T, a.eta,
-                       a.c_out, a.s_out, a.g_out, a.x_out);
+    hipLaunchKernelGGL((k_rbf<DIM, SPL, G, BLOCK, MODE>), dim3((unsigned)blocks, (unsigned)splits),
+                       dim3(BLOCK), lds, st, a.hinges, a.weights, a.M, a.bias, a.kappa, a.gscale,
+                       a.x_in, a.n, a.T, a.eta, a.c_out, a.s_out, a.g_out, a.x_out, a.g_in,
+                       a.chain, cps);
     return check_launch("k_rbf");
 }
 
@@ -201,21 +221,25 @@ static int32_t launch_rbf_v(const RbfArgs &a, hipStream_t st) {
 // 1024 SIMDs with a few waves each.
 template <int DIM, int MODE>
 static int32_t launch_rbf_dim(const RbfArgs &a, hipStream_t st) {
+    if (MODE == kEval && a.splits > 1) return launch_rbf_v<DIM, 1, 1, 256, MODE>(a, st);
     if (a.n >= (1 << 19)) return launch_rbf_v<DIM, 2, 1, 1024, MODE>(a, st);
     if (a.n >= (1 << 17)) return launch_rbf_v<DIM, 1, 1, 256, MODE>(a, st);
     if (a.n >= (1 << 15)) return launch_rbf_v<DIM, 1, 4, 256, MODE>(a, st);
     return launch_rbf_v<DIM, 1, 16, 256, MODE>(a, st);
 }
 
-int32_t launch_rbf(int dim, int mode, const RbfArgs &a, hipStream_t st) {
-    if (dim == 2) {
-        if (mode == kEval) return launch_rbf_dim<2, kEval>(a, st);
-        if (mode == kGrad) return launch_rbf_dim<2, kGrad>(a, st);
-        return launch_rbf_dim<2, kMorph>(a, st);
+template <int DIM>
+static int32_t launch_rbf_mode(int mode, const RbfArgs &a, hipStream_t st) {
+    switch (mode) {
+        case kEval: return launch_rbf_dim<DIM, kEval>(a, st);
+        case kGrad: return launch_rbf_dim<DIM, kGrad>(a, st);
+        case kGradBwd: return launch_rbf_dim<DIM, kGradBwd>(a, st);
+        default: return launch_rbf_dim<DIM, kMorph>(a, st);
     }
-    if (mode == kEval) return launch_rbf_dim<3, kEval>(a, st);
-    if (mode == kGrad) return launch_rbf_dim<3, kGrad>(a, st);
-    return launch_rbf_dim<3, kMorph>(a, st);
+}
+
+int32_t launch_rbf(int dim, int mode, const RbfArgs &a, hipStream_t st) {
+    return dim == 2 ? launch_rbf_mode<2>(mode, a, st) : launch_rbf_mode<3>(mode, a, st);
 }
 
 }  // namespace pdmp

@@ -63,15 +63,6 @@ static int32_t check_arm(const pdmp_arm *arm, int max_ppl) {
     return PDMP_OK;
 }
 
-// kappa^2 = log2(e) / (2 l^2):  exp(-r^2/(2 l^2)) = exp2(-(kappa r)^2).
-// grad s = -(1/l^2) sum w phi (x - h) = -(1/(l^2 kappa)) sum w phi (kappa x - kappa h).
-static void derive_scales(float ell, float &kappa, float &gscale) {
-    const double l = ell;
-    const double k = std::sqrt(1.4426950408889634 / (2.0 * l * l));
-    kappa = (float)k;
-    gscale = (float)(1.0 / (l * l * k));
-}
-
 }  // namespace pdmp
 
 using namespace pdmp;
@@ -143,6 +134,7 @@ static int32_t rbf_call(const pdmp_occupancy *occ, int mode, const float *x, int
     a.hinges = occ->hinges;
     a.weights = occ->weights;
     a.M = occ->n_hinges;
+    a.bias = occ->weights + occ->n_hinges;
     derive_scales(occ->lengthscale, a.kappa, a.gscale);
     a.x_in = x;
     a.n = n;
@@ -217,6 +209,95 @@ int32_t pdmp_fk_body_points(const pdmp_arm *arm, const float *q, int64_t n, floa
     if (n == 0) return PDMP_OK;
     PDMP_REQUIRE(q && pts, "q/pts NULL");
     return launch_fk_points(*arm, q, n, pts, (hipStream_t)stream);
+}
+
+size_t pdmp_fit_workspace_size(int32_t dim, int32_t n_hinges, int64_t n) {
+    if ((dim != 2 && dim != 3) || n_hinges < 1 || n < 1) return 0;
+    return fit_ws_bytes(dim, n_hinges, n);
+}
+
+size_t pdmp_bwd_workspace_size(int32_t dim, int32_t n_hinges, int64_t n) {
+    if ((dim != 2 && dim != 3) || n_hinges < 1 || n < 1) return 0;
+    return bwd_ws_bytes(dim, n_hinges, n);
+}
+
+size_t pdmp_bce_workspace_size(int64_t n) { return n < 1 ? 0 : bce_ws_bytes(n); }
+
+int32_t pdmp_fit_occupancy(const pdmp_occupancy *occ, float *weights, const float *pts,
+                           const uint8_t *labels, int64_t n, const pdmp_fit_opts *opts,
+                           float *loss_out, void *ws, size_t ws_bytes, void *stream) {
+    PDMP_REQUIRE(occ != nullptr, "occupancy is NULL");
+    PDMP_REQUIRE(occ->dim == 2 || occ->dim == 3, "occupancy dim %d not in {2,3}", occ->dim);
+    PDMP_REQUIRE(occ->n_hinges >= 1 && occ->hinges, "bad hinges");
+    PDMP_REQUIRE(std::isfinite(occ->lengthscale) && occ->lengthscale > 0.0f, "bad lengthscale");
+    PDMP_REQUIRE(weights && pts && labels && opts, "NULL argument");
+    PDMP_REQUIRE(n >= 1, "n < 1");
+    PDMP_REQUIRE(opts->optimizer == 0 || opts->optimizer == 1, "optimizer %d", opts->optimizer);
+    PDMP_REQUIRE(opts->steps >= 0, "steps < 0");
+    PDMP_REQUIRE(std::isfinite(opts->lr) && std::isfinite(opts->l2) && opts->l2 >= 0.0f,
+                 "bad lr/l2");
+    if (opts->optimizer == 1) {
+        PDMP_REQUIRE(opts->adam_m && opts->adam_v, "Adam needs adam_m and adam_v");
+        PDMP_REQUIRE(opts->beta1 >= 0 && opts->beta1 < 1 && opts->beta2 >= 0 && opts->beta2 < 1 &&
+                         opts->eps > 0 && opts->t0 >= 0,
+                     "bad Adam hyperparameters");
+    } else {
+        PDMP_REQUIRE(std::isfinite(opts->lr_bias), "bad lr_bias");
+    }
+    const size_t need = fit_ws_bytes(occ->dim, occ->n_hinges, n);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+        return PDMP_ENOMEM;
+    }
+    return launch_fit(occ->dim, occ->hinges, occ->n_hinges, occ->lengthscale, weights, pts,
+                      labels, n, *opts, loss_out, ws, (hipStream_t)stream);
+}
+
+int32_t pdmp_occupancy_bwd(const pdmp_occupancy *occ, const float *x, int64_t n, const float *g,
+                           const float *s_fwd, float *grad_w, float *grad_x, void *ws,
+                           size_t ws_bytes, void *stream) {
+    int32_t st = check_occ(occ);
+    if (st) return st;
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    if (n == 0) {
+        PDMP_REQUIRE(grad_w == nullptr, "grad_w of an empty batch: use n >= 1");
+        return PDMP_OK;
+    }
+    PDMP_REQUIRE(x && g, "x/g NULL");
+    if (!grad_w && !grad_x) return PDMP_OK;
+    const size_t need = bwd_ws_bytes(occ->dim, occ->n_hinges, n);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+        return PDMP_ENOMEM;
+    }
+    return launch_logit_bwd(occ->dim, occ->hinges, occ->weights, occ->n_hinges, occ->lengthscale,
+                            x, n, g, s_fwd, grad_w, grad_x, 1.0f, nullptr, 0.0f, ws,
+                            (hipStream_t)stream);
+}
+
+int32_t pdmp_bce_logits(const float *s, const uint8_t *y, int64_t n, float *loss, float *g_s,
+                        void *ws, size_t ws_bytes, void *stream) {
+    PDMP_REQUIRE(n >= 1, "n < 1");
+    PDMP_REQUIRE(s && y, "s/y NULL");
+    const size_t need = bce_ws_bytes(n);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+        return PDMP_ENOMEM;
+    }
+    return launch_bce(s, y, n, loss, g_s, (double *)ws, (hipStream_t)stream);
+}
+
+int32_t pdmp_adam_step(float *p, const float *g, float *m, float *v, int64_t n, int64_t n_decay,
+                       int32_t t, float lr, float beta1, float beta2, float eps, float l2,
+                       void *stream) {
+    PDMP_REQUIRE(n >= 0 && n_decay >= 0 && n_decay <= n, "bad sizes");
+    PDMP_REQUIRE(t >= 1, "t < 1");
+    PDMP_REQUIRE(beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0 &&
+                     std::isfinite(lr) && std::isfinite(l2),
+                 "bad hyperparameters");
+    if (n == 0) return PDMP_OK;
+    PDMP_REQUIRE(p && g && m && v, "NULL argument");
+    return launch_adam(p, g, m, v, n, n_decay, t, lr, beta1, beta2, eps, l2, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -58,19 +59,35 @@ __device__ __forceinline__ void sigmoid_and_slope(float s, float &c, float &sp) 
     sp = e * inv * inv;
 }
 
+// kappa^2 = log2(e) / (2 l^2):  exp(-r^2/(2 l^2)) = exp2(-(kappa r)^2).
+// grad s = -(1/l^2) sum w phi (x - h) = -(1/(l^2 kappa)) sum w phi (kappa x - kappa h).
+inline void derive_scales(float ell, float &kappa, float &gscale) {
+    const double l = ell;
+    const double k = std::sqrt(1.4426950408889634 / (2.0 * l * l));
+    kappa = (float)k;
+    gscale = (float)(1.0 / (l * l * k));
+}
+
 // ---- launchers (host side, one per kernel family) ----
 
-enum RbfMode { kEval = 0, kGrad = 1, kMorph = 2 };
+enum RbfMode { kEval = 0, kGrad = 1, kMorph = 2, kGradBwd = 3 };
 
+// One RBF-sum launch: for every "sample" x_i (n of them) sum over the weighted
+// "hinge" set (M of them).  The roles are symmetric: with hinges = data points,
+// weights = upstream gradients and x_in = hinge positions, kEval computes Phi^T g.
 struct RbfArgs {
-    const float *hinges, *weights;
-    int M;
-    float kappa, gscale;
-    const float *x_in;
-    int64_t n;
-    int T;
-    float eta;
-    float *c_out, *s_out, *g_out, *x_out;
+    const float *hinges = nullptr, *weights = nullptr;
+    int M = 0;
+    const float *bias = nullptr;  // nullable
+    float kappa = 0, gscale = 0;
+    const float *x_in = nullptr;
+    int64_t n = 0;
+    int T = 1;
+    float eta = 0;
+    float *c_out = nullptr, *s_out = nullptr, *g_out = nullptr, *x_out = nullptr;
+    const float *g_in = nullptr;  // kGradBwd upstream gradient
+    int chain = 0;                // kGradBwd: multiply by sigma'(s)
+    int splits = 1;               // kEval: hinge-range splits (partial sums)
 };
 
 int32_t launch_rbf(int dim, int mode, const RbfArgs &a, hipStream_t st);
@@ -87,5 +104,19 @@ int32_t launch_morph_arm(const pdmp_arm &arm, const float *h, const float *w, in
                          hipStream_t st);
 int32_t launch_fk_points(const pdmp_arm &arm, const float *q, int64_t n, float *pts,
                          hipStream_t st);
+size_t bwd_ws_bytes(int dim, int M, int64_t n);
+size_t bce_ws_bytes(int64_t n);
+size_t fit_ws_bytes(int dim, int M, int64_t n);
+int32_t launch_logit_bwd(int dim, const float *hinges, const float *weights, int M, float ell,
+                         const float *x, int64_t n, const float *g, const float *s_fwd,
+                         float *grad_w, float *grad_x, float grad_scale, const float *decay_w,
+                         float l2, void *ws, hipStream_t st);
+int32_t launch_bce(const float *s, const uint8_t *y, int64_t n, float *loss, float *g_out,
+                   double *parts, hipStream_t st);
+int32_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, int64_t n_decay,
+                    int t, float lr, float b1, float b2, float eps, float l2, hipStream_t st);
+int32_t launch_fit(int dim, const float *hinges, int M, float ell, float *wb, const float *pts,
+                   const uint8_t *y, int64_t n, const pdmp_fit_opts &o, float *loss_out, void *ws,
+                   hipStream_t st);
 
 }  // namespace pdmp

@@ -69,6 +69,10 @@ int32_t launch_uniform(uint64_t seed, uint32_t sid, const float *lo, const float
     return check_launch("k_uniform");
 }
 
+__global__ void k_zero_u64(uint64_t *p) {
+    if (threadIdx.x == 0) *p = 0;
+}
+
 // Count of 1-labels: one integer atomic per wave (deterministic).
 __device__ __forceinline__ void count_hits(bool hit, uint64_t *n_hit) {
     if (!n_hit) return;
@@ -172,8 +176,12 @@ k_label_configs(pdmp_arm arm, const float *__restrict__ cen, const float *__rest
 
 int32_t launch_label_discs(const pdmp_discs &sc, const float *x, int64_t n, uint8_t *out,
                            uint64_t *n_hit, hipStream_t st) {
-    if (n_hit && hipMemsetAsync(n_hit, 0, sizeof(uint64_t), st) != hipSuccess)
-        return check_launch("hipMemsetAsync");
+    if (n_hit) {
+        // a fill kernel rather than a memset node, so the call can be graph-captured
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, n_hit);
+        if (int32_t e = check_launch("k_zero_u64")) return e;
+    }
+    if (n == 0) return PDMP_OK;
     hipLaunchKernelGGL(k_label_discs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                        sc.centres, sc.radii, sc.n, x, n, out, n_hit);
     return check_launch("k_label_discs");
@@ -181,8 +189,12 @@ int32_t launch_label_discs(const pdmp_discs &sc, const float *x, int64_t n, uint
 
 int32_t launch_label_boxes(const pdmp_boxes &sc, const float *x, int64_t n, uint8_t *out,
                            uint64_t *n_hit, hipStream_t st) {
-    if (n_hit && hipMemsetAsync(n_hit, 0, sizeof(uint64_t), st) != hipSuccess)
-        return check_launch("hipMemsetAsync");
+    if (n_hit) {
+        // a fill kernel rather than a memset node, so the call can be graph-captured
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, n_hit);
+        if (int32_t e = check_launch("k_zero_u64")) return e;
+    }
+    if (n == 0) return PDMP_OK;
     hipLaunchKernelGGL(k_label_boxes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                        sc.centres, sc.half, sc.n, x, n, out, n_hit);
     return check_launch("k_label_boxes");
@@ -190,8 +202,12 @@ int32_t launch_label_boxes(const pdmp_boxes &sc, const float *x, int64_t n, uint
 
 int32_t launch_label_configs(const pdmp_arm &arm, const pdmp_boxes &sc, const float *q, int64_t n,
                              uint8_t *out, uint64_t *n_hit, hipStream_t st) {
-    if (n_hit && hipMemsetAsync(n_hit, 0, sizeof(uint64_t), st) != hipSuccess)
-        return check_launch("hipMemsetAsync");
+    if (n_hit) {
+        // a fill kernel rather than a memset node, so the call can be graph-captured
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, n_hit);
+        if (int32_t e = check_launch("k_zero_u64")) return e;
+    }
+    if (n == 0) return PDMP_OK;
     hipLaunchKernelGGL(k_label_configs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, arm,
                        sc.centres, sc.half, sc.n, q, n, out, n_hit);
     return check_launch("k_label_configs");
