@@ -207,6 +207,58 @@ int32_t pdmp_adam_step(float *p, const float *g, float *m, float *v, int64_t n, 
                        int32_t t, float lr, float beta1, float beta2, float eps, float l2,
                        void *stream);
 
+/* ---- amortised morph: residual MLP q_hat = q + f(q) with
+ * f = W_L SiLU(... SiLU(W_1 q + b_1) ...) + b_L, n_hidden hidden layers of width
+ * `hidden`, trained by MSE on (base, plain-morphed) pairs.  Products run on BF16
+ * MFMA with FP32 accumulation; biases, the residual add and the optimiser are FP32.
+ * params:      device FP32 master parameters, flat: for each layer W [out][in]
+ *              row-major, then b [out] (layers in order).
+ * params_bf16: device BF16 copy of params (same layout) from pdmp_mlp_pack; the
+ *              matrix products read the weights from here. */
+typedef struct {
+    int32_t n_in;       /* input = output width, 1..16 */
+    int32_t hidden;     /* 1..1024 */
+    int32_t n_hidden;   /* 1..6 */
+    const float *params;
+    const uint16_t *params_bf16;
+} pdmp_mlp;
+
+int64_t pdmp_mlp_num_params(const pdmp_mlp *mlp);
+/* Round params to BF16 (nearest even) into params_bf16 [num_params] (device). */
+int32_t pdmp_mlp_pack(const pdmp_mlp *mlp, uint16_t *params_bf16, void *stream);
+/* Bytes of saved activations for a training forward of B samples, and of the
+ * scratch workspace that forward/backward need. */
+size_t pdmp_mlp_acts_size(const pdmp_mlp *mlp, int64_t B);
+size_t pdmp_mlp_workspace_size(const pdmp_mlp *mlp, int64_t B);
+/* q_hat [n_in][B] = q + f(q) for q [n_in][B].  acts (nullable, device,
+ * pdmp_mlp_acts_size bytes): keep the activations for pdmp_mlp_backward. */
+int32_t pdmp_mlp_forward(const pdmp_mlp *mlp, const float *q, int64_t B, float *q_hat, void *acts,
+                         void *ws, size_t ws_bytes, void *stream);
+/* MSE loss (1/(n_in B)) sum |q_hat - target|^2 (loss, nullable, device [1]) and its
+ * gradient with respect to params (grad, device FP32 [num_params], overwritten),
+ * from the activations of the matching forward. */
+int32_t pdmp_mlp_backward(const pdmp_mlp *mlp, const float *q_hat, const float *target,
+                          int64_t B, void *acts, float *grad, float *loss, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* Largest body-point occupancy of each configuration, max_p c(psi_p(q)) (maxc,
+ * nullable, [n]) and flag = (max > thresh) (nullable, [n]).  FP32 kinematics. */
+int32_t pdmp_arm_max_occupancy(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *q,
+                               int64_t n, float thresh, float *maxc, uint8_t *flag,
+                               void *stream);
+
+/* Amortised morph of configurations q [n_dof][n] into out [n_dof][n]:
+ * q_hat = q + f(q); a configuration whose largest body-point occupancy at q_hat
+ * exceeds `thresh` is re-morphed by the plain T-step joint-space morph from its base
+ * q (the fallback), all others keep q_hat.  flag (nullable, [n]) marks the
+ * fallbacks, n_fallback (nullable, device) receives their count.  No host
+ * synchronisation inside; out must not alias q. */
+size_t pdmp_amortised_workspace_size(const pdmp_mlp *mlp, const pdmp_arm *arm, int64_t n);
+int32_t pdmp_amortised_morph(const pdmp_mlp *mlp, const pdmp_occupancy *occ, const pdmp_arm *arm,
+                             const float *q, float *out, int64_t n, int32_t T, float eta,
+                             float thresh, uint8_t *flag, uint32_t *n_fallback, void *ws,
+                             size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

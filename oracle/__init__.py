@@ -78,7 +78,7 @@ def _load():
         "orc_config_label_margin": (None, [C.c_int, C.c_int, _dp, _dp, _dp, C.c_int, _dp, _i64,
                                            _dp]),
         "orc_mlp_nparams": (C.c_int64, [C.c_int, _ip]),
-        "orc_mlp_forward": (None, [C.c_int, _ip, _dp, _dp, _i64, C.c_int, _dp]),
+        "orc_mlp_forward": (None, [C.c_int, _ip, _dp, _dp, _i64, C.c_int, _dp, _dp]),
         "orc_mlp_loss_grad": (C.c_double, [C.c_int, _ip, _dp, _dp, _dp, _i64, _dp]),
         "orc_amortised_morph": (None, [C.c_int, _ip, _dp, C.c_int, C.c_int, _dp, C.c_int, _dp,
                                        _dp, C.c_double, C.c_double, _dp, _i64, C.c_int,
@@ -413,14 +413,17 @@ def _widths(widths):
     return np.ascontiguousarray(np.asarray(widths, dtype=np.int32)).astype(np.intc)
 
 
-def mlp_forward(widths, P, q, residual: bool = True):
-    """q + f(q) (or f(q)) for [w0][B] inputs; f is the SiLU MLP."""
+def mlp_forward(widths, P, q, residual: bool = True, with_scale: bool = False):
+    """q + f(q) (or f(q)) for [w0][B] inputs; f is the SiLU MLP.  with_scale also
+    returns sum_k |W_L| |a_{L-1}| + |b_L| per output."""
     wd = _widths(widths)
     q = _d(q)
     B = q.shape[1]
     out = _zeros(int(wd[-1]), B)
-    _load().orc_mlp_forward(wd.size - 1, _P(wd, _ip), _P(_d(P)), _P(q), B, int(residual), _P(out))
-    return out
+    sc = _zeros(int(wd[-1]), B) if with_scale else None
+    _load().orc_mlp_forward(wd.size - 1, _P(wd, _ip), _P(_d(P)), _P(q), B, int(residual), _P(out),
+                            _P(sc))
+    return (out, sc) if with_scale else out
 
 
 def mlp_loss_grad(widths, P, q, target):

@@ -838,16 +838,38 @@ static void mlp_fwd1(int L, const int *widths, const double *P, const double *in
     for (int k = 0; k < widths[L]; ++k) out[k] = a[k];
 }
 
-/* q_hat = q + f(q) for [w0][B] inputs (SoA), residual requires widths[0]==widths[L]. */
+/* q_hat = q + f(q) for [w0][B] inputs (SoA), residual requires widths[0]==widths[L].
+ * fscale (nullable, [wL][B]): sum_k |W_L[o][k]| |a_{L-1,k}| + |b_L[o]|, the magnitude
+ * scale the rounding of the last layer's inputs and weights acts on. */
 void orc_mlp_forward(int L, const int *widths, const double *P, const double *q, int64_t B,
-                     int residual, double *out) {
+                     int residual, double *out, double *fscale) {
     int w0 = widths[0], wl = widths[L];
+    int64_t zlen = 0, alen = w0, plast = 0;
+    for (int l = 0; l < L; ++l) {
+        zlen += widths[l + 1];
+        if (l < L - 1) alen += widths[l + 1];
+        if (l < L - 1) plast += (int64_t)widths[l + 1] * widths[l] + widths[l + 1];
+    }
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < B; ++s) {
         double in[ORC_MLP_MAXW], f[ORC_MLP_MAXW];
+        double *z = (double *)malloc(sizeof(double) * (size_t)zlen);
+        double *a = (double *)malloc(sizeof(double) * (size_t)alen);
         for (int k = 0; k < w0; ++k) in[k] = q[(int64_t)k * B + s];
-        mlp_fwd1(L, widths, P, in, f, NULL, NULL);
+        mlp_fwd1(L, widths, P, in, f, z, a);
         for (int k = 0; k < wl; ++k) out[(int64_t)k * B + s] = (residual ? in[k] : 0.0) + f[k];
+        if (fscale) {
+            int fi = widths[L - 1];
+            const double *W = P + plast, *b = P + plast + (int64_t)wl * fi;
+            const double *alast = a + (alen - fi);
+            for (int o = 0; o < wl; ++o) {
+                double acc = fabs(b[o]);
+                for (int k = 0; k < fi; ++k) acc += fabs(W[(int64_t)o * fi + k]) * fabs(alast[k]);
+                fscale[(int64_t)o * B + s] = acc;
+            }
+        }
+        free(z);
+        free(a);
     }
 }
 
@@ -916,7 +938,7 @@ void orc_amortised_morph(int L, const int *widths, const double *P, int ndof, in
                          double ell, const double *q, int64_t n, int T, double eta,
                          double thresh, double *qout, uint8_t *flag, double *maxc) {
     double *qh = (double *)malloc(sizeof(double) * (size_t)ndof * (size_t)(n > 0 ? n : 1));
-    orc_mlp_forward(L, widths, P, q, n, 1, qh);
+    orc_mlp_forward(L, widths, P, q, n, 1, qh, NULL);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t s = 0; s < n; ++s) {
         double qs[ORC_MAX_DOF], o[ORC_MAX_DOF + 1][3], z[ORC_MAX_DOF + 1][3];

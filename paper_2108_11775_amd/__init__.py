@@ -22,7 +22,8 @@ from ._lib import PdmpError
 __all__ = ["Occupancy", "Arm", "PdmpError", "abi_version", "uniform_samples",
            "label_points_discs", "label_points_boxes", "label_configs", "occupancy_eval",
            "occupancy_grad", "morph_samples", "fk_body_points", "sync", "occupancy_bwd",
-           "bce_logits", "adam_step", "fit_occupancy"]
+           "bce_logits", "adam_step", "fit_occupancy", "Mlp", "arm_max_occupancy",
+           "amortised_morph"]
 
 
 def _torch():
@@ -317,3 +318,129 @@ def fit_occupancy(hinges, lengthscale: float, weights, pts, labels, steps: int, 
               n, C.byref(opt), _dev(loss, "loss") if record_loss else None, _dev(ws, "ws"),
               ws.numel(), _stream(pts.device))
     return loss[:steps] if record_loss else None
+
+
+class Mlp:
+    """Residual MLP q_hat = q + f(q) on BF16 MFMA (the amortised morph's network).
+
+    Holds FP32 master parameters (flat, per layer W [out][in] then b [out]) and
+    their BF16 copy; `widths` = (n_in, hidden, ..., hidden, n_in).
+    """
+
+    def __init__(self, widths, params=None, device="cuda"):
+        torch = _torch()
+        widths = tuple(int(w) for w in widths)
+        if len(widths) < 3 or widths[0] != widths[-1] or len(set(widths[1:-1])) != 1:
+            raise ValueError("widths must be (n, h, ..., h, n)")
+        self.widths = widths
+        self.n_in, self.hidden, self.n_hidden = widths[0], widths[1], len(widths) - 2
+        n = sum(widths[l + 1] * widths[l] + widths[l + 1] for l in range(len(widths) - 1))
+        self.params = (torch.zeros(n, dtype=torch.float32, device=device) if params is None
+                       else params.to(device=device, dtype=torch.float32).contiguous())
+        if self.params.numel() != n:
+            raise ValueError(f"expected {n} parameters, got {self.params.numel()}")
+        self.params_bf16 = torch.empty(n, dtype=torch.int16, device=device)
+        self.pack()
+
+    @classmethod
+    def from_layers(cls, layers, device="cuda"):
+        import numpy as np
+        torch = _torch()
+        widths = [layers[0][0].shape[1]] + [W.shape[0] for W, _ in layers]
+        flat = np.concatenate([np.concatenate([np.asarray(W, np.float32).reshape(-1),
+                                               np.asarray(b, np.float32).reshape(-1)])
+                               for W, b in layers])
+        return cls(widths, torch.from_numpy(flat), device)
+
+    @property
+    def num_params(self):
+        return int(self.params.numel())
+
+    def c_struct(self) -> _lib.pdmp_mlp:
+        return _lib.pdmp_mlp(self.n_in, self.hidden, self.n_hidden, self.params.data_ptr(),
+                             self.params_bf16.data_ptr())
+
+    def pack(self):
+        """Refresh the BF16 copy from the FP32 master parameters."""
+        m = self.c_struct()
+        _lib.call("pdmp_mlp_pack", C.byref(m), C.c_void_p(self.params_bf16.data_ptr()),
+                  _stream(self.params.device))
+
+    def forward(self, q, acts=None, out=None):
+        """q_hat = q + f(q) for q [n_in][B]; `acts` (from acts_buffer) keeps activations."""
+        torch = _torch()
+        lib = _lib.load()
+        B = int(q.shape[1])
+        m = self.c_struct()
+        if out is None:
+            out = torch.empty_like(q)
+        ws = None
+        if acts is None:
+            ws = _workspace(lib.pdmp_mlp_workspace_size(C.byref(m), B), q.device)
+        _lib.call("pdmp_mlp_forward", C.byref(m), _dev(q, "q", torch.float32, (self.n_in, B)), B,
+                  _dev(out, "q_hat", torch.float32, (self.n_in, B)),
+                  _dev(acts, "acts") if acts is not None else None,
+                  _dev(ws, "ws") if ws is not None else None, ws.numel() if ws is not None else 0,
+                  _stream(q.device))
+        return out
+
+    def acts_buffer(self, B, device="cuda"):
+        lib = _lib.load()
+        m = self.c_struct()
+        return _workspace(lib.pdmp_mlp_acts_size(C.byref(m), int(B)), device)
+
+    def backward(self, q_hat, target, acts, grad=None, loss=None, ws=None):
+        """MSE loss and its parameter gradient (FP32 flat) from saved activations."""
+        torch = _torch()
+        lib = _lib.load()
+        B = int(q_hat.shape[1])
+        m = self.c_struct()
+        if grad is None:
+            grad = torch.empty_like(self.params)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=q_hat.device)
+        if ws is None:
+            ws = _workspace(lib.pdmp_mlp_workspace_size(C.byref(m), B), q_hat.device)
+        _lib.call("pdmp_mlp_backward", C.byref(m), _dev(q_hat, "q_hat", torch.float32),
+                  _dev(target, "target", torch.float32, tuple(q_hat.shape)), B, _dev(acts, "acts"),
+                  _dev(grad, "grad", torch.float32, (self.num_params,)), _dev(loss, "loss"),
+                  _dev(ws, "ws"), ws.numel(), _stream(q_hat.device))
+        return loss, grad
+
+
+def arm_max_occupancy(occ: Occupancy, arm: Arm, q, thresh: float = 0.5):
+    """(max body-point occupancy [n], flag [n]) of configurations q [n_dof][n]."""
+    torch = _torch()
+    n = int(q.shape[1])
+    maxc = torch.empty(n, dtype=torch.float32, device=q.device)
+    flag = torch.empty(n, dtype=torch.uint8, device=q.device)
+    o, a = occ.c_struct(), arm.c_struct()
+    _lib.call("pdmp_arm_max_occupancy", C.byref(o), C.byref(a),
+              _dev(q, "q", torch.float32, (arm.n_dof, n)), n, float(thresh), _dev(maxc, "maxc"),
+              _dev(flag, "flag"), _stream(q.device))
+    return maxc, flag
+
+
+def amortised_morph(mlp: Mlp, occ: Occupancy, arm: Arm, q, T: int, eta: float,
+                    thresh: float = 0.5, out=None, flag=None, n_fallback=None, ws=None):
+    """Amortised morph: q + f(q), plain-morph fallback where max occupancy > thresh.
+
+    Returns (out [n_dof][n], flag [n] uint8, n_fallback [1] int32 device).
+    """
+    torch = _torch()
+    lib = _lib.load()
+    n = int(q.shape[1])
+    m, o, a = mlp.c_struct(), occ.c_struct(), arm.c_struct()
+    if out is None:
+        out = torch.empty_like(q)
+    if flag is None:
+        flag = torch.empty(n, dtype=torch.uint8, device=q.device)
+    if n_fallback is None:
+        n_fallback = torch.zeros(1, dtype=torch.int32, device=q.device)
+    if ws is None:
+        ws = _workspace(lib.pdmp_amortised_workspace_size(C.byref(m), C.byref(a), n), q.device)
+    _lib.call("pdmp_amortised_morph", C.byref(m), C.byref(o), C.byref(a),
+              _dev(q, "q", torch.float32, (arm.n_dof, n)), _dev(out, "out", torch.float32, (arm.n_dof, n)),
+              n, int(T), float(eta), float(thresh), _dev(flag, "flag", torch.uint8, (n,)),
+              _dev(n_fallback, "n_fallback"), _dev(ws, "ws"), ws.numel(), _stream(q.device))
+    return out, flag, n_fallback

@@ -40,6 +40,11 @@ class pdmp_fit_opts(C.Structure):
                 ("adam_m", C.c_void_p), ("adam_v", C.c_void_p)]
 
 
+class pdmp_mlp(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("hidden", C.c_int32), ("n_hidden", C.c_int32),
+                ("params", C.c_void_p), ("params_bf16", C.c_void_p)]
+
+
 _vp, _i32, _i64, _u32, _u64, _f = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float
 _P = C.POINTER
 
@@ -65,6 +70,18 @@ SIGNATURES = {
                                   C.c_size_t, _vp]),
     "pdmp_bce_logits": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t, _vp]),
     "pdmp_adam_step": (_i32, [_vp, _vp, _vp, _vp, _i64, _i64, _i32, _f, _f, _f, _f, _f, _vp]),
+    "pdmp_mlp_num_params": (_i64, [_P(pdmp_mlp)]),
+    "pdmp_mlp_pack": (_i32, [_P(pdmp_mlp), _vp, _vp]),
+    "pdmp_mlp_acts_size": (C.c_size_t, [_P(pdmp_mlp), _i64]),
+    "pdmp_mlp_workspace_size": (C.c_size_t, [_P(pdmp_mlp), _i64]),
+    "pdmp_mlp_forward": (_i32, [_P(pdmp_mlp), _vp, _i64, _vp, _vp, _vp, C.c_size_t, _vp]),
+    "pdmp_mlp_backward": (_i32, [_P(pdmp_mlp), _vp, _vp, _i64, _vp, _vp, _vp, _vp, C.c_size_t,
+                                 _vp]),
+    "pdmp_arm_max_occupancy": (_i32, [_P(pdmp_occupancy), _P(pdmp_arm), _vp, _i64, _f, _vp, _vp,
+                                      _vp]),
+    "pdmp_amortised_workspace_size": (C.c_size_t, [_P(pdmp_mlp), _P(pdmp_arm), _i64]),
+    "pdmp_amortised_morph": (_i32, [_P(pdmp_mlp), _P(pdmp_occupancy), _P(pdmp_arm), _vp, _vp, _i64,
+                                    _i32, _f, _f, _vp, _vp, _vp, C.c_size_t, _vp]),
 }
 
 _lib = None

@@ -1,0 +1,58 @@
+"""Learned amortised morph: training data from the plain morph and the MLP training
+loop.  Every arithmetic step runs in libpdmp's kernels (Philox prior batches, the
+joint-space morph, BF16-MFMA forward/backward, Adam, BF16 repacking); this module
+only sequences the calls.
+
+Training pairs are (q, morph_T(q)) for prior batches q ~ U[q_lo, q_hi)^n_dof drawn
+with Philox streams 0, 1, 2, ...; each batch is its own contiguous [n_dof][B]
+tensor, so epochs iterate over the batches without any gather or shuffle copy
+(the batches are independent uniform draws).
+"""
+from __future__ import annotations
+
+import time
+
+import torch
+
+from . import Arm, Mlp, Occupancy, adam_step, morph_samples, uniform_samples
+
+
+def make_pairs(occ: Occupancy, arm: Arm, n_batches: int, batch: int, T: int, eta: float,
+               seed: int, q_lo: float, q_hi: float, first_stream: int = 0, device="cuda"):
+    pairs = []
+    lo, hi = [q_lo] * arm.n_dof, [q_hi] * arm.n_dof
+    for b in range(n_batches):
+        q = uniform_samples(seed, first_stream + b, lo, hi, batch, device=device)
+        t = morph_samples(occ, q, T, eta, arm=arm)
+        pairs.append((q, t))
+    return pairs
+
+
+def train(mlp: Mlp, pairs, epochs: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
+          log=None):
+    """Adam on the MSE between q + f(q) and the plain-morph target.
+
+    Returns the per-step loss as a device tensor [epochs * len(pairs)].
+    """
+    dev = mlp.params.device
+    B = int(pairs[0][0].shape[1])
+    steps = epochs * len(pairs)
+    losses = torch.empty(steps, dtype=torch.float32, device=dev)
+    m = torch.zeros_like(mlp.params)
+    v = torch.zeros_like(mlp.params)
+    grad = torch.empty_like(mlp.params)
+    acts = mlp.acts_buffer(B, dev)
+    qhat = torch.empty_like(pairs[0][0])
+    t = 0
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        for q, tgt in pairs:
+            mlp.forward(q, acts=acts, out=qhat)
+            mlp.backward(qhat, tgt, acts, grad=grad, loss=losses[t:t + 1])
+            t += 1
+            adam_step(mlp.params, grad, m, v, t, lr, beta1, beta2, eps)
+            mlp.pack()
+        if log is not None:
+            log(f"epoch {ep + 1}/{epochs}: loss {losses[t - 1].item():.5f} "
+                f"({time.perf_counter() - t0:.1f} s)")
+    return losses

@@ -1,0 +1,451 @@
+// mlp.hip -- residual MLP of the amortised morph on BF16 MFMA with FP32 accumulation.
+//
+// q_hat = q + f(q),  f = W_L SiLU(... SiLU(W_1 q + b_1) ...) + b_L, trained by MSE
+// against plain-morph targets.  Weights and activations are BF16, products are
+// accumulated in FP32 (v_mfma_f32_32x32x16_bf16), biases, the residual and the
+// optimiser state are FP32.
+//
+// Every layer product is one tiled GEMM  C[m][n] = sum_k A(m, k) B(n, k)  with
+// general strides, so the same kernel serves
+//   forward      Z[b][o]  = sum_i H[b][i] W[o][i]        (+ bias, SiLU epilogue)
+//   data grad    dH[b][i] = sum_o dZ[b][o] W[o][i]        (x SiLU'(Z_prev) epilogue)
+//   weight grad  dW[o][i] = sum_b dZ[b][o] H[b][i]        (split over b, fixed-order sum)
+// Block tile 64 x 64, four waves each owning a 32 x 32 MFMA tile, K staged through
+// LDS 32 at a time with rows padded so the fragment reads are conflict-light
+// ds_read_b128.  Activations are sample-major [B][width].
+#include "pdmp_common.h"
+
+namespace pdmp {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16_t;
+
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+    // round to nearest even; NaN stays NaN
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+__device__ __forceinline__ float silu_f(float z) {
+    float c, sp;
+    sigmoid_and_slope(z, c, sp);
+    return z * c;
+}
+
+__device__ __forceinline__ float silu_grad_f(float z) {
+    float c, sp;
+    sigmoid_and_slope(z, c, sp);
+    return c + z * sp;  // sigma (1 + z (1 - sigma))
+}
+
+enum GemmEpi { kEpiF32 = 0, kEpiHidden = 1, kEpiOut = 2, kEpiDSilu = 3 };
+
+struct GemmArgs {
+    int M = 0, N = 0, K = 0;
+    const uint16_t *A = nullptr;
+    int64_t a_sm = 0, a_sk = 0;
+    const uint16_t *B = nullptr;
+    int64_t b_sn = 0, b_sk = 0;
+    int kps = 0;  // K per split (blockIdx.z)
+    // epilogues
+    float *c = nullptr;          // kEpiF32: c[z*M*N + m*N + n]
+    const float *bias = nullptr; // kEpiHidden/kEpiOut: bias[n]
+    float *zsave = nullptr;      // kEpiHidden: z[m*N + n] (nullable)
+    uint16_t *hout = nullptr;    // kEpiHidden: bf16 silu(z)[m*N + n]; kEpiDSilu: bf16 out
+    const float *qin = nullptr;  // kEpiOut: residual input [N][ldq] (SoA)
+    float *qout = nullptr;       // kEpiOut: q + f, [N][ldq]
+    int64_t ldq = 0;
+    const float *zprev = nullptr; // kEpiDSilu: z of the layer below, [m*N + n]
+};
+
+constexpr int kGT = 64;      // block tile (M and N)
+constexpr int kGK = 32;      // K per LDS stage
+constexpr int kGPad = 8;     // row padding (bf16) against bank conflicts
+constexpr int kGRow = kGK + kGPad;
+
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[kGT * kGRow];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kGT * kGRow];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int m0 = blockIdx.x * kGT, n0 = blockIdx.y * kGT;
+    const int kb = blockIdx.z * g.kps;
+    const int ke = min(g.K, kb + g.kps);
+
+    floatx16_t acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+
+    const int lrow = tid >> 2;        // 0..63: tile row this thread stages
+    const int lseg = (tid & 3) * 8;   // 8 consecutive k
+    for (int k0 = kb; k0 < ke; k0 += kGK) {
+        {
+            const int m = m0 + lrow;
+            uint16_t va[8], vb[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = k0 + lseg + j;
+                const bool okk = k < ke;
+                va[j] = (okk && m < g.M) ? g.A[(int64_t)m * g.a_sm + (int64_t)k * g.a_sk] : (uint16_t)0;
+                const int n = n0 + lrow;
+                vb[j] = (okk && n < g.N) ? g.B[(int64_t)n * g.b_sn + (int64_t)k * g.b_sk] : (uint16_t)0;
+            }
+            uint4 pa, pb;
+            pa.x = va[0] | ((uint32_t)va[1] << 16);
+            pa.y = va[2] | ((uint32_t)va[3] << 16);
+            pa.z = va[4] | ((uint32_t)va[5] << 16);
+            pa.w = va[6] | ((uint32_t)va[7] << 16);
+            pb.x = vb[0] | ((uint32_t)vb[1] << 16);
+            pb.y = vb[2] | ((uint32_t)vb[3] << 16);
+            pb.z = vb[4] | ((uint32_t)vb[5] << 16);
+            pb.w = vb[6] | ((uint32_t)vb[7] << 16);
+            *reinterpret_cast<uint4 *>(&As[lrow * kGRow + lseg]) = pa;
+            *reinterpret_cast<uint4 *>(&Bs[lrow * kGRow + lseg]) = pb;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kGK; kk += 16) {
+            const int ka = kk + 8 * (lane >> 5);
+            const uint4 ra = *reinterpret_cast<const uint4 *>(&As[(wm * 32 + (lane & 31)) * kGRow + ka]);
+            const uint4 rb = *reinterpret_cast<const uint4 *>(&Bs[(wn * 32 + (lane & 31)) * kGRow + ka]);
+            bf16x8_t fa, fb;
+            __builtin_memcpy(&fa, &ra, 16);
+            __builtin_memcpy(&fb, &rb, 16);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    const int n = n0 + wn * 32 + (lane & 31);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int m = m0 + wm * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (m >= g.M || n >= g.N) continue;
+        const float a = acc[v];
+        const int64_t mn = (int64_t)m * g.N + n;
+        if (EPI == kEpiF32) {
+            g.c[(int64_t)blockIdx.z * g.M * g.N + mn] = a;
+        } else if (EPI == kEpiHidden) {
+            const float z = a + g.bias[n];
+            if (g.zsave) g.zsave[mn] = z;
+            g.hout[mn] = f32_to_bf16(silu_f(z));
+        } else if (EPI == kEpiOut) {
+            const int64_t o = (int64_t)n * g.ldq + m;  // SoA [n_out][B], m = sample
+            g.qout[o] = g.qin[o] + (a + g.bias[n]);
+        } else {
+            g.hout[mn] = f32_to_bf16(a * silu_grad_f(g.zprev[mn]));
+        }
+    }
+}
+
+template <int EPI>
+static int32_t launch_gemm(const GemmArgs &g, int splits, hipStream_t st) {
+    dim3 grid((g.M + kGT - 1) / kGT, (g.N + kGT - 1) / kGT, splits);
+    hipLaunchKernelGGL(k_gemm<EPI>, grid, dim3(256), 0, st, g);
+    return check_launch("k_gemm");
+}
+
+// ---------------------------------------------------------- small kernels ---
+
+// q [n_in][B] FP32 (SoA) -> H0 [B][n_in] BF16
+__global__ void k_q_to_bf16(const float *__restrict__ q, int n_in, int64_t B, uint16_t *h0) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B * n_in) return;
+    const int64_t b = t / n_in;
+    const int i = (int)(t - b * n_in);
+    h0[t] = f32_to_bf16(q[(int64_t)i * B + b]);
+}
+
+__global__ void k_f32_to_bf16(const float *__restrict__ x, int64_t n, uint16_t *y) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = f32_to_bf16(x[t]);
+}
+
+// MSE: dF[b][k] = bf16(2 (q_hat - t) / (n_out B)), per-block sums of (q_hat - t)^2.
+__global__ void __launch_bounds__(256)
+k_mse(const float *__restrict__ qhat, const float *__restrict__ tgt, int n_out, int64_t B,
+      float scale, uint16_t *dF, double *parts) {
+    __shared__ double sh[256];
+    const int64_t total = B * n_out;
+    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * per;
+    const int64_t t1 = t0 + per < total ? t0 + per : total;
+    double acc = 0.0;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
+        // t enumerates [b][k] (sample-major) so dF is written contiguously
+        const int64_t b = t / n_out;
+        const int k = (int)(t - b * n_out);
+        const int64_t o = (int64_t)k * B + b;
+        const float e = qhat[o] - tgt[o];
+        acc += (double)e * (double)e;
+        dF[t] = f32_to_bf16(2.0f * scale * e);
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off >= 1; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) parts[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256)
+k_final_scaled(const double *__restrict__ parts, int np, double scale, float *out) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) acc += parts[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off >= 1; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = (float)(sh[0] * scale);
+}
+
+// out[j] = sum_{s < S} part[s * MN + j], fixed order
+__global__ void k_sum_splits(const float *__restrict__ part, int S, int64_t MN, float *out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= MN) return;
+    double acc = 0.0;
+    for (int s = 0; s < S; ++s) acc += part[(int64_t)s * MN + j];
+    out[j] = (float)acc;
+}
+
+// Column sums of a BF16 [B][N] matrix: partial over row range blockIdx.y, then
+// k_sum_splits.  part[y * N + col].
+__global__ void k_colsum_partial(const uint16_t *__restrict__ x, int64_t B, int N, int64_t rows_per,
+                                 float *part) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= N) return;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per;
+    const int64_t r1 = r0 + rows_per < B ? r0 + rows_per : B;
+    double acc = 0.0;
+    for (int64_t r = r0; r < r1; ++r) acc += bf16_to_f32(x[r * N + col]);
+    part[(int64_t)blockIdx.y * N + col] = (float)acc;
+}
+
+// ------------------------------------------------------------------ host ---
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct MlpLayout {
+    int L, n_in, H;
+    int in(int l) const { return l == 0 ? n_in : H; }
+    int out(int l) const { return l == L - 1 ? n_in : H; }
+    int64_t woff(int l) const {
+        int64_t o = 0;
+        for (int k = 0; k < l; ++k) o += (int64_t)out(k) * in(k) + out(k);
+        return o;
+    }
+    int64_t boff(int l) const { return woff(l) + (int64_t)out(l) * in(l); }
+    int64_t nparams() const { return woff(L); }
+};
+
+static MlpLayout layout_of(const pdmp_mlp &m) { return MlpLayout{m.n_hidden + 1, m.n_in, m.hidden}; }
+
+int64_t mlp_nparams(const pdmp_mlp &m) { return layout_of(m).nparams(); }
+
+// Activations kept by a training forward: H0 bf16 [B][n_in]; for l < L-1:
+// Z_l f32 [B][H] and H_l bf16 [B][H].
+size_t mlp_acts_bytes(const pdmp_mlp &m, int64_t B) {
+    const MlpLayout ly = layout_of(m);
+    size_t b = al256((size_t)B * ly.n_in * 2);
+    for (int l = 0; l < ly.L - 1; ++l) b += al256((size_t)B * ly.H * 4) + al256((size_t)B * ly.H * 2);
+    return b;
+}
+
+struct ActPtrs {
+    uint16_t *h0;
+    float *z[8];
+    uint16_t *h[8];
+};
+
+static ActPtrs act_ptrs(const MlpLayout &ly, void *acts, int64_t B) {
+    ActPtrs p{};
+    char *c = (char *)acts;
+    p.h0 = (uint16_t *)c;
+    c += al256((size_t)B * ly.n_in * 2);
+    for (int l = 0; l < ly.L - 1; ++l) {
+        p.z[l] = (float *)c;
+        c += al256((size_t)B * ly.H * 4);
+        p.h[l] = (uint16_t *)c;
+        c += al256((size_t)B * ly.H * 2);
+    }
+    return p;
+}
+
+// Inference-only forward keeps two BF16 activation buffers.
+size_t mlp_fwd_ws_bytes(const pdmp_mlp &m, int64_t B) {
+    const MlpLayout ly = layout_of(m);
+    return al256((size_t)B * ly.n_in * 2) + 2 * al256((size_t)B * ly.H * 2);
+}
+
+int32_t launch_mlp_forward(const pdmp_mlp &m, const float *q, int64_t B, float *qhat, void *acts,
+                           void *ws, hipStream_t st) {
+    const MlpLayout ly = layout_of(m);
+    uint16_t *h0, *hb[2];
+    float *zs[8] = {nullptr};
+    uint16_t *hs[8] = {nullptr};
+    if (acts) {
+        ActPtrs p = act_ptrs(ly, acts, B);
+        h0 = p.h0;
+        for (int l = 0; l < ly.L - 1; ++l) {
+            zs[l] = p.z[l];
+            hs[l] = p.h[l];
+        }
+    } else {
+        char *c = (char *)ws;
+        h0 = (uint16_t *)c;
+        c += al256((size_t)B * ly.n_in * 2);
+        hb[0] = (uint16_t *)c;
+        c += al256((size_t)B * ly.H * 2);
+        hb[1] = (uint16_t *)c;
+        for (int l = 0; l < ly.L - 1; ++l) hs[l] = hb[l & 1];
+    }
+    hipLaunchKernelGGL(k_q_to_bf16, dim3((unsigned)((B * ly.n_in + 255) / 256)), dim3(256), 0, st, q,
+                       ly.n_in, B, h0);
+    if (int32_t e = check_launch("k_q_to_bf16")) return e;
+    const uint16_t *hin = h0;
+    for (int l = 0; l < ly.L; ++l) {
+        GemmArgs g;
+        g.M = (int)B;
+        g.N = ly.out(l);
+        g.K = ly.in(l);
+        g.A = hin;
+        g.a_sm = ly.in(l);
+        g.a_sk = 1;
+        g.B = m.params_bf16 + ly.woff(l);
+        g.b_sn = ly.in(l);
+        g.b_sk = 1;
+        g.kps = g.K;
+        g.bias = m.params + ly.boff(l);
+        int32_t e;
+        if (l < ly.L - 1) {
+            g.zsave = zs[l];
+            g.hout = hs[l];
+            e = launch_gemm<kEpiHidden>(g, 1, st);
+            hin = hs[l];
+        } else {
+            g.qin = q;
+            g.qout = qhat;
+            g.ldq = B;
+            e = launch_gemm<kEpiOut>(g, 1, st);
+        }
+        if (e) return e;
+    }
+    return PDMP_OK;
+}
+
+static int wgrad_splits(int64_t B) {
+    int64_t s = B / 2048;
+    if (s < 1) s = 1;
+    if (s > 64) s = 64;
+    return (int)s;
+}
+
+size_t mlp_bwd_ws_bytes(const pdmp_mlp &m, int64_t B) {
+    const MlpLayout ly = layout_of(m);
+    const int S = wgrad_splits(B);
+    const int64_t rows_per = 2048;
+    const int64_t cs = (B + rows_per - 1) / rows_per;
+    const int wmax = ly.H > ly.n_in ? ly.H : ly.n_in;
+    return 2 * al256((size_t)B * wmax * 2) + al256((size_t)S * wmax * wmax * 4) +
+           al256((size_t)cs * wmax * 4) + al256(1024 * sizeof(double));
+}
+
+// Backward of the MSE loss through the whole network from saved activations.
+// grad: FP32 [nparams] in the flat layout; loss (nullable): device [1].
+int32_t launch_mlp_backward(const pdmp_mlp &m, const float *qhat, const float *target, int64_t B,
+                            void *acts, float *grad, float *loss, void *ws, hipStream_t st) {
+    const MlpLayout ly = layout_of(m);
+    ActPtrs ap = act_ptrs(ly, acts, B);
+    const int S = wgrad_splits(B);
+    const int64_t rows_per = 2048;
+    const int cs = (int)((B + rows_per - 1) / rows_per);
+    const int wmax = ly.H > ly.n_in ? ly.H : ly.n_in;
+    char *c = (char *)ws;
+    uint16_t *dz[2];
+    dz[0] = (uint16_t *)c;
+    c += al256((size_t)B * wmax * 2);
+    dz[1] = (uint16_t *)c;
+    c += al256((size_t)B * wmax * 2);
+    float *part = (float *)c;
+    c += al256((size_t)S * wmax * wmax * 4);
+    float *cpart = (float *)c;
+    c += al256((size_t)cs * wmax * 4);
+    double *rparts = (double *)c;
+
+    const int nb = 1024;
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, qhat, target, ly.n_in, B,
+                       (float)(1.0 / ((double)ly.n_in * (double)B)), dz[0], rparts);
+    if (loss)
+        hipLaunchKernelGGL(k_final_scaled, dim3(1), dim3(256), 0, st, rparts, nb,
+                           1.0 / ((double)ly.n_in * (double)B), loss);
+    if (int32_t e = check_launch("k_mse")) return e;
+
+    int cur = 0;
+    for (int l = ly.L - 1; l >= 0; --l) {
+        const int O = ly.out(l), I = ly.in(l);
+        const uint16_t *hin = l == 0 ? ap.h0 : ap.h[l - 1];
+        // dW_l[o][i] = sum_b dZ[b][o] H_{l-1}[b][i], split over b
+        GemmArgs gw;
+        gw.M = O;
+        gw.N = I;
+        gw.K = (int)B;
+        gw.A = dz[cur];
+        gw.a_sm = 1;
+        gw.a_sk = O;
+        gw.B = hin;
+        gw.b_sn = 1;
+        gw.b_sk = I;
+        gw.kps = (int)(((B + S - 1) / S + kGK - 1) / kGK * kGK);
+        const int splits = (int)((B + gw.kps - 1) / gw.kps);
+        gw.c = part;
+        if (int32_t e = launch_gemm<kEpiF32>(gw, splits, st)) return e;
+        hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)(((int64_t)O * I + 255) / 256)), dim3(256), 0,
+                           st, part, splits, (int64_t)O * I, grad + ly.woff(l));
+        // db_l[o] = sum_b dZ[b][o]
+        hipLaunchKernelGGL(k_colsum_partial, dim3((O + 255) / 256, cs), dim3(256), 0, st, dz[cur], B,
+                           O, rows_per, cpart);
+        hipLaunchKernelGGL(k_sum_splits, dim3((O + 255) / 256), dim3(256), 0, st, cpart, cs,
+                           (int64_t)O, grad + ly.boff(l));
+        if (int32_t e = check_launch("mlp wgrad")) return e;
+        if (l == 0) break;
+        // dZ_{l-1}[b][i] = (sum_o dZ[b][o] W_l[o][i]) * SiLU'(Z_{l-1}[b][i])
+        GemmArgs gd;
+        gd.M = (int)B;
+        gd.N = I;
+        gd.K = O;
+        gd.A = dz[cur];
+        gd.a_sm = O;
+        gd.a_sk = 1;
+        gd.B = m.params_bf16 + ly.woff(l);
+        gd.b_sn = 1;
+        gd.b_sk = I;
+        gd.kps = O;
+        gd.hout = dz[cur ^ 1];
+        gd.zprev = ap.z[l - 1];
+        if (int32_t e = launch_gemm<kEpiDSilu>(gd, 1, st)) return e;
+        cur ^= 1;
+    }
+    return PDMP_OK;
+}
+
+int32_t launch_f32_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_t st) {
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, y);
+    return check_launch("k_f32_to_bf16");
+}
+
+}  // namespace pdmp

@@ -196,7 +196,7 @@ int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const
         float kappa, gscale;
         derive_scales(occ->lengthscale, kappa, gscale);
         return launch_morph_arm(*arm, occ->hinges, occ->weights, occ->n_hinges, kappa, gscale, in,
-                                out, n, T, eta, (hipStream_t)stream);
+                                out, n, T, eta, nullptr, (hipStream_t)stream);
     }
     return rbf_call(occ, kMorph, in, n, nullptr, nullptr, nullptr, out, T, eta, stream);
 }
@@ -298,6 +298,149 @@ int32_t pdmp_adam_step(float *p, const float *g, float *m, float *v, int64_t n, 
     if (n == 0) return PDMP_OK;
     PDMP_REQUIRE(p && g && m && v, "NULL argument");
     return launch_adam(p, g, m, v, n, n_decay, t, lr, beta1, beta2, eps, l2, (hipStream_t)stream);
+}
+
+static int32_t check_mlp(const pdmp_mlp *m, bool need_params) {
+    PDMP_REQUIRE(m != nullptr, "mlp is NULL");
+    PDMP_REQUIRE(m->n_in >= 1 && m->n_in <= 16, "mlp n_in %d not in [1,16]", m->n_in);
+    PDMP_REQUIRE(m->hidden >= 1 && m->hidden <= 1024, "mlp hidden %d not in [1,1024]", m->hidden);
+    PDMP_REQUIRE(m->n_hidden >= 1 && m->n_hidden <= 6, "mlp n_hidden %d not in [1,6]", m->n_hidden);
+    if (need_params) PDMP_REQUIRE(m->params && m->params_bf16, "mlp params NULL");
+    return PDMP_OK;
+}
+
+int64_t pdmp_mlp_num_params(const pdmp_mlp *mlp) {
+    if (check_mlp(mlp, false)) return -1;
+    return mlp_nparams(*mlp);
+}
+
+int32_t pdmp_mlp_pack(const pdmp_mlp *mlp, uint16_t *params_bf16, void *stream) {
+    int32_t st = check_mlp(mlp, false);
+    if (st) return st;
+    PDMP_REQUIRE(mlp->params && params_bf16, "params/params_bf16 NULL");
+    return launch_f32_to_bf16(mlp->params, mlp_nparams(*mlp), params_bf16, (hipStream_t)stream);
+}
+
+size_t pdmp_mlp_acts_size(const pdmp_mlp *mlp, int64_t B) {
+    if (check_mlp(mlp, false) || B < 1) return 0;
+    return mlp_acts_bytes(*mlp, B);
+}
+
+size_t pdmp_mlp_workspace_size(const pdmp_mlp *mlp, int64_t B) {
+    if (check_mlp(mlp, false) || B < 1) return 0;
+    const size_t a = mlp_fwd_ws_bytes(*mlp, B), b = mlp_bwd_ws_bytes(*mlp, B);
+    return a > b ? a : b;
+}
+
+int32_t pdmp_mlp_forward(const pdmp_mlp *mlp, const float *q, int64_t B, float *q_hat, void *acts,
+                         void *ws, size_t ws_bytes, void *stream) {
+    int32_t st = check_mlp(mlp, true);
+    if (st) return st;
+    PDMP_REQUIRE(B >= 0, "B < 0");
+    if (B == 0) return PDMP_OK;
+    PDMP_REQUIRE(q && q_hat, "q/q_hat NULL");
+    PDMP_REQUIRE(B <= 0x7fffffff, "B too large");
+    if (!acts) {
+        const size_t need = mlp_fwd_ws_bytes(*mlp, B);
+        if (!ws || ws_bytes < need) {
+            set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+            return PDMP_ENOMEM;
+        }
+    }
+    return launch_mlp_forward(*mlp, q, B, q_hat, acts, ws, (hipStream_t)stream);
+}
+
+int32_t pdmp_mlp_backward(const pdmp_mlp *mlp, const float *q_hat, const float *target,
+                          int64_t B, void *acts, float *grad, float *loss, void *ws,
+                          size_t ws_bytes, void *stream) {
+    int32_t st = check_mlp(mlp, true);
+    if (st) return st;
+    PDMP_REQUIRE(B >= 1 && B <= 0x7fffffff, "B out of range");
+    PDMP_REQUIRE(q_hat && target && acts && grad, "NULL argument");
+    const size_t need = mlp_bwd_ws_bytes(*mlp, B);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+        return PDMP_ENOMEM;
+    }
+    return launch_mlp_backward(*mlp, q_hat, target, B, acts, grad, loss, ws, (hipStream_t)stream);
+}
+
+int32_t pdmp_arm_max_occupancy(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *q,
+                               int64_t n, float thresh, float *maxc, uint8_t *flag,
+                               void *stream) {
+    int32_t st = check_occ(occ);
+    if (st) return st;
+    st = check_arm(arm, 8);
+    if (st) return st;
+    PDMP_REQUIRE(occ->dim == 3, "the body-point check needs a 3-D occupancy");
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    if (n == 0) return PDMP_OK;
+    PDMP_REQUIRE(q != nullptr, "q NULL");
+    float kappa, gscale;
+    derive_scales(occ->lengthscale, kappa, gscale);
+    return launch_arm_max_occ(*arm, occ->hinges, occ->weights, occ->n_hinges, kappa, q, n, thresh,
+                              maxc, flag, (hipStream_t)stream);
+}
+
+static size_t al256h(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t pdmp_amortised_workspace_size(const pdmp_mlp *mlp, const pdmp_arm *arm, int64_t n) {
+    if (check_mlp(mlp, false) || !arm || n < 1) return 0;
+    const size_t nb = (size_t)((n + 255) / 256);
+    return mlp_fwd_ws_bytes(*mlp, n) + al256h((size_t)n) /* flags */ +
+           2 * al256h(nb * 4) + al256h(8) + al256h((size_t)n * 4) /* idx */ +
+           al256h((size_t)arm->n_dof * n * 4) /* compact batch */;
+}
+
+int32_t pdmp_amortised_morph(const pdmp_mlp *mlp, const pdmp_occupancy *occ, const pdmp_arm *arm,
+                             const float *q, float *out, int64_t n, int32_t T, float eta,
+                             float thresh, uint8_t *flag, uint32_t *n_fallback, void *ws,
+                             size_t ws_bytes, void *stream) {
+    int32_t st = check_mlp(mlp, true);
+    if (st) return st;
+    st = check_occ(occ);
+    if (st) return st;
+    st = check_arm(arm, 8);
+    if (st) return st;
+    PDMP_REQUIRE(occ->dim == 3, "the amortised arm morph needs a 3-D occupancy");
+    PDMP_REQUIRE(mlp->n_in == arm->n_dof, "mlp width %d != n_dof %d", mlp->n_in, arm->n_dof);
+    PDMP_REQUIRE(n >= 0 && n <= 0x7fffffff, "n out of range");
+    PDMP_REQUIRE(T >= 0 && std::isfinite(eta) && std::isfinite(thresh), "bad T/eta/thresh");
+    if (n == 0) return PDMP_OK;
+    PDMP_REQUIRE(q && out && q != out, "q/out NULL or aliased");
+    const size_t need = pdmp_amortised_workspace_size(mlp, arm, n);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+        return PDMP_ENOMEM;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = (size_t)((n + 255) / 256);
+    char *c = (char *)ws;
+    void *mws = c;
+    c += mlp_fwd_ws_bytes(*mlp, n);
+    uint8_t *fl = flag ? flag : (uint8_t *)c;
+    c += al256h((size_t)n);
+    uint32_t *counts = (uint32_t *)c;
+    c += al256h(nb * 4);
+    uint32_t *offs = (uint32_t *)c;
+    c += al256h(nb * 4);
+    uint32_t *total = n_fallback ? n_fallback : (uint32_t *)c;
+    c += al256h(8);
+    uint32_t *idx = (uint32_t *)c;
+    c += al256h((size_t)n * 4);
+    float *qc = (float *)c;
+
+    float kappa, gscale;
+    derive_scales(occ->lengthscale, kappa, gscale);
+    if ((st = launch_mlp_forward(*mlp, q, n, out, nullptr, mws, s))) return st;
+    if ((st = launch_arm_max_occ(*arm, occ->hinges, occ->weights, occ->n_hinges, kappa, out, n,
+                                 thresh, nullptr, fl, s)))
+        return st;
+    if ((st = launch_compact(*arm, fl, q, n, counts, offs, total, idx, qc, s))) return st;
+    if ((st = launch_morph_arm(*arm, occ->hinges, occ->weights, occ->n_hinges, kappa, gscale, qc, qc,
+                               n, T, eta, total, s)))
+        return st;
+    return launch_scatter(*arm, idx, total, qc, n, out, s);
 }
 
 }  // extern "C"

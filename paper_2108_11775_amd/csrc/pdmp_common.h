@@ -101,7 +101,24 @@ int32_t launch_label_configs(const pdmp_arm &arm, const pdmp_boxes &sc, const fl
                              uint8_t *out, uint64_t *n_hit, hipStream_t st);
 int32_t launch_morph_arm(const pdmp_arm &arm, const float *h, const float *w, int M, float kappa,
                          float gscale, const float *qi, float *qo, int64_t n, int T, float eta,
-                         hipStream_t st);
+                         const uint32_t *n_active, hipStream_t st);
+int32_t launch_arm_max_occ(const pdmp_arm &arm, const float *h, const float *w, int M, float kappa,
+                           const float *q, int64_t n, float thresh, float *maxc, uint8_t *flag,
+                           hipStream_t st);
+int32_t launch_compact(const pdmp_arm &arm, const uint8_t *flag, const float *q, int64_t n,
+                       uint32_t *counts, uint32_t *offs, uint32_t *total, uint32_t *idx, float *qc,
+                       hipStream_t st);
+int32_t launch_scatter(const pdmp_arm &arm, const uint32_t *idx, const uint32_t *total,
+                       const float *qc, int64_t n, float *out, hipStream_t st);
+int64_t mlp_nparams(const pdmp_mlp &m);
+size_t mlp_acts_bytes(const pdmp_mlp &m, int64_t B);
+size_t mlp_fwd_ws_bytes(const pdmp_mlp &m, int64_t B);
+size_t mlp_bwd_ws_bytes(const pdmp_mlp &m, int64_t B);
+int32_t launch_mlp_forward(const pdmp_mlp &m, const float *q, int64_t B, float *qhat, void *acts,
+                           void *ws, hipStream_t st);
+int32_t launch_mlp_backward(const pdmp_mlp &m, const float *qhat, const float *target, int64_t B,
+                            void *acts, float *grad, float *loss, void *ws, hipStream_t st);
+int32_t launch_f32_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_t st);
 int32_t launch_fk_points(const pdmp_arm &arm, const float *q, int64_t n, float *pts,
                          hipStream_t st);
 size_t bwd_ws_bytes(int dim, int M, int64_t n);

@@ -1,0 +1,170 @@
+"""GPU parity: BF16-MFMA residual MLP (forward, MSE gradient), the body-point
+occupancy check and the amortised morph with its plain-morph fallback.
+
+BF16 bar (FP32 accumulate against the FP64 oracle on the same BF16-valued weights
+and inputs): |f_gpu - f| <= 2e-2 * (|f| + F_abs), F_abs = sum_k |W_L| |h_{L-1}| + |b_L|;
+per-layer weight gradients within 2e-2 relative (Frobenius).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2108_11775_amd as P
+from paper_2108_11775_amd import configs as K, inputs as I
+
+from helpers import arm_scene, dev, gpu_occ, host, oracle_occ, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16(a):
+    """Round FP32 values to BF16 (nearest even) and return them as FP32."""
+    a = np.ascontiguousarray(np.asarray(a, np.float32))
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32)
+
+
+def _net(widths, seed=5, zero_last=False):
+    layers = I.mlp_init(seed, widths, zero_last=zero_last)
+    if not zero_last:  # give the last layer a realistic, non-zero scale
+        W, b = layers[-1]
+        layers[-1] = (W * 0.5, b * 0.5)
+    return layers
+
+
+@pytest.mark.parametrize("widths,B", [((7, 256, 256, 256, 7), 1000), ((7, 64, 64, 7), 4099),
+                                      ((3, 96, 96, 96, 3), 77)])
+def test_forward_bf16(widths, B):
+    require_gpu()
+    layers = _net(widths)
+    mlp = P.Mlp.from_layers(layers)
+    q = I.uniform_points(5, K.STREAM_EVAL, widths[0], B, -math.pi, math.pi)
+    got = host(mlp.forward(dev(q)))
+    # oracle on the BF16-valued weights and inputs (exact upcast); biases stay FP32
+    lb = [(_bf16(W), b) for W, b in layers]
+    f, fs = O.mlp_forward(widths, O.mlp_pack(lb), _bf16(q), residual=False, with_scale=True)
+    fg = got.astype(np.float64) - q.astype(np.float64)
+    err = np.abs(fg - f)
+    assert np.all(err <= 2e-2 * (np.abs(f) + fs)), np.max(err / (np.abs(f) + fs))
+
+
+def test_zero_last_layer_is_exact_identity():
+    require_gpu()
+    mlp = P.Mlp.from_layers(I.mlp_init(5, K.C5.widths))
+    q = dev(I.uniform_points(5, K.STREAM_EVAL, 7, 3000, -math.pi, math.pi))
+    assert np.array_equal(host(mlp.forward(q)), host(q))
+
+
+@pytest.mark.parametrize("widths,B", [((7, 256, 256, 256, 7), 2048), ((7, 64, 64, 7), 3001)])
+def test_mse_gradient_per_layer(widths, B):
+    require_gpu()
+    layers = _net(widths, seed=6)
+    mlp = P.Mlp.from_layers(layers)
+    q = I.uniform_points(6, K.STREAM_EVAL, widths[0], B, -math.pi, math.pi)
+    t = q + 0.3 * I.rng(6, 13).normal(size=q.shape).astype(np.float32)
+    acts = mlp.acts_buffer(B)
+    qh = mlp.forward(dev(q), acts=acts)
+    loss, grad = mlp.backward(qh, dev(t), acts)
+    grad = host(grad)
+    lb = [(_bf16(W), b) for W, b in layers]
+    Pb = O.mlp_pack(lb)
+    L, gref = O.mlp_loss_grad(widths, Pb, q, t)
+    assert abs(host(loss)[0] - L) <= 2e-2 * L
+    off = 0
+    for li in range(len(widths) - 1):
+        fi, fo = widths[li], widths[li + 1]
+        for n_el in (fi * fo, fo):  # W then b
+            a, b = grad[off:off + n_el], gref[off:off + n_el]
+            assert np.linalg.norm(a - b) <= 2e-2 * np.linalg.norm(b) + 1e-12, (li, n_el)
+            off += n_el
+
+
+def test_arm_max_occupancy_matches_oracle():
+    require_gpu()
+    sc = arm_scene()
+    a, d, al, th = sc["dh"]
+    arm_o, arm_g = O.Arm(a, d, al, th, 8), P.Arm(a, d, al, th, 8)
+    q = I.uniform_points(3, K.STREAM_EVAL, 7, 3000, -math.pi, math.pi)
+    maxc, flag = P.arm_max_occupancy(gpu_occ(sc["h"], sc["wb"], sc["ell"]), arm_g, dev(q), 0.5)
+    maxc, flag = host(maxc), host(flag)
+    oo = oracle_occ(sc["h"], sc["wb"], sc["ell"])
+    pts = O.fk_points(arm_o, q)
+    ref = np.array([O.occ_eval(oo, pts[:, :, s])[1].max() for s in range(q.shape[1])])
+    assert np.abs(maxc - ref).max() <= 1e-4
+    sure = np.abs(ref - 0.5) > 1e-4
+    assert np.array_equal(flag[sure], (ref[sure] > 0.5).astype(np.uint8))
+
+
+def test_amortised_zero_network_is_plain_morph_on_flagged():
+    require_gpu()
+    sc = arm_scene()
+    a, d, al, th = sc["dh"]
+    arm_g = P.Arm(a, d, al, th, 8)
+    occ = gpu_occ(sc["h"], sc["wb"], sc["ell"])
+    mlp = P.Mlp.from_layers(I.mlp_init(5, K.C5.widths))
+    q = dev(I.uniform_points(3, K.STREAM_EVAL, 7, 5000, -math.pi, math.pi))
+    out, flag, nf = P.amortised_morph(mlp, occ, arm_g, q, K.C3.T, K.C3.eta)
+    _, flag_ref = P.arm_max_occupancy(occ, arm_g, q, 0.5)
+    plain = host(P.morph_samples(occ, q, K.C3.T, K.C3.eta, arm=arm_g))
+    out, flag, qh = host(out), host(flag), host(q)
+    assert np.array_equal(flag, host(flag_ref))
+    assert int(host(nf)[0]) == int(flag.sum()) and 0 < flag.sum() < 5000
+    f = flag.astype(bool)
+    assert np.array_equal(out[:, f], plain[:, f])       # same kernel, same per-config arithmetic
+    assert np.array_equal(out[:, ~f], qh[:, ~f])        # q_hat = q exactly
+
+
+def test_amortised_matches_oracle():
+    require_gpu()
+    sc = arm_scene()
+    a, d, al, th = sc["dh"]
+    arm_o, arm_g = O.Arm(a, d, al, th, 8), P.Arm(a, d, al, th, 8)
+    widths = (7, 64, 64, 7)
+    layers = _net(widths, seed=8)
+    layers[-1] = (layers[-1][0] * 0.05, layers[-1][1] * 0.05)
+    mlp = P.Mlp.from_layers(layers)
+    n = 48
+    q = I.uniform_points(3, K.STREAM_EVAL, 7, n, -math.pi, math.pi)
+    out, flag, _ = P.amortised_morph(mlp, gpu_occ(sc["h"], sc["wb"], sc["ell"]), arm_g, dev(q),
+                                     K.C3.T, K.C3.eta)
+    out, flag = host(out), host(flag)
+    lb = [(_bf16(W), b) for W, b in layers]
+    ref, fref, maxc = O.amortised_morph(widths, O.mlp_pack(lb), arm_o,
+                                        oracle_occ(sc["h"], sc["wb"], sc["ell"]), q, K.C3.T,
+                                        K.C3.eta)
+    # the flag is decided in FP32 from a BF16 network: compare where the oracle's
+    # max occupancy is clear of the threshold
+    sure = np.abs(maxc - 0.5) > 2e-2
+    assert np.array_equal(flag[sure], fref[sure])
+    both = sure & (flag == 1)
+    if both.any():
+        _, amp, _ = O.morph_arm(arm_o, oracle_occ(sc["h"], sc["wb"], sc["ell"]), q[:, both],
+                                K.C3.T, K.C3.eta, diag=True)
+        err = np.abs(out[:, both] - ref[:, both]).max(axis=0)
+        assert np.all(err <= 1e-5 * np.maximum(1, amp) * np.maximum(1, np.abs(ref[:, both]).max(axis=0)))
+    keep = sure & (flag == 0)
+    assert np.all(np.abs(out[:, keep] - ref[:, keep]) <= 2e-2 * (np.abs(ref[:, keep] - q[:, keep]) + 0.05))
+
+
+def test_training_reduces_loss_and_fallbacks():
+    """The trained network beats the method without it: fewer fallbacks than the
+    zero network (q_hat = q) on held-out configurations."""
+    require_gpu()
+    from paper_2108_11775_amd import amortise
+    sc = arm_scene()
+    a, d, al, th = sc["dh"]
+    arm_g = P.Arm(a, d, al, th, 8)
+    occ = gpu_occ(sc["h"], sc["wb"], sc["ell"])
+    c3 = K.C3
+    pairs = amortise.make_pairs(occ, arm_g, 8, 8192, c3.T, c3.eta, I.philox_seed(5), c3.q_lo, c3.q_hi)
+    mlp = P.Mlp.from_layers(I.mlp_init(5, (7, 128, 128, 128, 7)))
+    losses = host(amortise.train(mlp, pairs, 6, 3e-3))
+    assert losses[-1] < 0.7 * losses[0]
+    q = P.uniform_samples(I.philox_seed(5), 999, [c3.q_lo] * 7, [c3.q_hi] * 7, 8192)
+    zero = P.Mlp.from_layers(I.mlp_init(5, (7, 128, 128, 128, 7)))
+    _, f_zero, _ = P.amortised_morph(zero, occ, arm_g, q, c3.T, c3.eta)
+    _, f_net, _ = P.amortised_morph(mlp, occ, arm_g, q, c3.T, c3.eta)
+    assert host(f_net).mean() < host(f_zero).mean()
