@@ -51,6 +51,13 @@ typedef enum {
  * hinges  : device [dim][M] hinge coordinates.
  * weights : device [M+1]; weights[M] holds the bias beta, so a fitted model stays
  *           entirely on the device.
+ * grid    : optional.  All zero: the hinges are arbitrary points.  Otherwise the
+ *           caller states that the hinges are the tensor grid of grid[0] x grid[1]
+ *           (x grid[2] in 3-D) points, x fastest: hinge j = i0 + g0 (i1 + g1 i2) has
+ *           coordinates (X0[i0], X1[i1], X2[i2]) read from the hinge array itself.
+ *           The library may then evaluate the same sums through the factorisation
+ *           phi_j = prod_k exp(-(x_k - X_k[i_k])^2 / (2 l^2)) (equal up to rounding).
+ *           Hinges that are not that grid give undefined results.
  * dim must be 2 or 3, M >= 1, lengthscale > 0 and finite. */
 typedef struct {
     int32_t dim;
@@ -58,6 +65,7 @@ typedef struct {
     const float *hinges;
     const float *weights;
     float lengthscale;
+    int32_t grid[3];
 } pdmp_occupancy;
 
 /* Serial arm with standard Denavit-Hartenberg links (Sec. 3.2, body points):

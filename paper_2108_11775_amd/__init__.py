@@ -67,6 +67,7 @@ class Occupancy:
     hinges: "object"
     weights: "object"
     lengthscale: float
+    grid: Optional[tuple] = None  # points per axis when the hinges are a tensor grid
 
     @property
     def dim(self) -> int:
@@ -80,8 +81,12 @@ class Occupancy:
         torch = _torch()
         _dev(self.hinges, "hinges", torch.float32)
         _dev(self.weights, "weights", torch.float32, (self.n_hinges + 1,))
+        g = (0, 0, 0)
+        if self.grid:
+            g = tuple(int(v) for v in self.grid) + (0,) * (3 - len(self.grid))
         return _lib.pdmp_occupancy(self.dim, self.n_hinges, self.hinges.data_ptr(),
-                                   self.weights.data_ptr(), float(self.lengthscale))
+                                   self.weights.data_ptr(), float(self.lengthscale),
+                                   (C.c_int32 * 3)(*g))
 
 
 @dataclass

@@ -16,7 +16,7 @@ MAX_DOF = 8
 
 class pdmp_occupancy(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_hinges", C.c_int32), ("hinges", C.c_void_p),
-                ("weights", C.c_void_p), ("lengthscale", C.c_float)]
+                ("weights", C.c_void_p), ("lengthscale", C.c_float), ("grid", C.c_int32 * 3)]
 
 
 class pdmp_arm(C.Structure):

@@ -43,8 +43,20 @@ static int32_t check_occ(const pdmp_occupancy *occ) {
     PDMP_REQUIRE(occ->hinges != nullptr && occ->weights != nullptr, "hinges/weights NULL");
     PDMP_REQUIRE(std::isfinite(occ->lengthscale) && occ->lengthscale > 0.0f,
                  "lengthscale must be finite and > 0");
+    if (occ->grid[0] || occ->grid[1] || occ->grid[2]) {
+        int64_t prod = 1;
+        for (int k = 0; k < occ->dim; ++k) {
+            PDMP_REQUIRE(occ->grid[k] >= 1, "grid[%d] = %d", k, occ->grid[k]);
+            prod *= occ->grid[k];
+        }
+        PDMP_REQUIRE(occ->dim == 3 || occ->grid[2] == 0, "grid[2] must be 0 in 2-D");
+        PDMP_REQUIRE(prod == occ->n_hinges, "grid product %lld != n_hinges %d", (long long)prod,
+                     occ->n_hinges);
+    }
     return PDMP_OK;
 }
+
+static bool has_grid(const pdmp_occupancy *occ) { return occ->grid[0] > 0; }
 
 static int32_t check_arm(const pdmp_arm *arm, int max_ppl) {
     PDMP_REQUIRE(arm != nullptr, "arm is NULL");
@@ -144,6 +156,10 @@ static int32_t rbf_call(const pdmp_occupancy *occ, int mode, const float *x, int
     a.s_out = s_out;
     a.g_out = g_out;
     a.x_out = x_out;
+    if (has_grid(occ) && occ->dim == 2) {
+        const int32_t st = launch_grid2d(mode, a, occ->grid[0], occ->grid[1], (hipStream_t)stream);
+        if (st != PDMP_EUNSUPPORTED) return st;  // grids beyond the MFMA path take the pair sum
+    }
     return launch_rbf(occ->dim, mode, a, (hipStream_t)stream);
 }
 

@@ -91,6 +91,7 @@ struct RbfArgs {
 };
 
 int32_t launch_rbf(int dim, int mode, const RbfArgs &a, hipStream_t st);
+int32_t launch_grid2d(int mode, const RbfArgs &a, int g0, int g1, hipStream_t st);
 int32_t launch_uniform(uint64_t seed, uint32_t sid, const float *lo, const float *hi, int dim,
                        int64_t n, float *out, hipStream_t st);
 int32_t launch_label_discs(const pdmp_discs &sc, const float *x, int64_t n, uint8_t *out,

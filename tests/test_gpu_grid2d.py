@@ -1,0 +1,88 @@
+"""GPU parity of the grid-factorised 2-D path (FP32 MFMA) against the oracle's
+pairwise definition, with the same condition-aware tolerances as the pairwise path."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2108_11775_amd as P
+from paper_2108_11775_amd import configs as K, inputs as I
+
+from helpers import dev, host, oracle_occ, require_gpu, ws_scene
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _grid_occ(h, wb, ell, g0, g1):
+    return P.Occupancy(dev(h), dev(wb), ell, grid=(g0, g1))
+
+
+@pytest.mark.parametrize("cfg", [K.C1, K.C2])
+@pytest.mark.parametrize("n", [1, 3001])
+def test_grid_eval_grad(cfg, n):
+    require_gpu()
+    sc = ws_scene(cfg)
+    go = _grid_occ(sc["h"], sc["wb"], sc["ell"], cfg.grid, cfg.grid)
+    x = I.uniform_points(cfg.cfg_id, K.STREAM_EVAL, 2, n, cfg.lo - 0.5, cfg.hi + 0.5)
+    c, s = P.occupancy_eval(go, dev(x))
+    _, g = P.occupancy_grad(go, dev(x))
+    oo = oracle_occ(sc["h"], sc["wb"], sc["ell"])
+    s_r, c_r, sabs = O.occ_eval(oo, x)
+    _, g_r, _, gabs = O.occ_grad(oo, x)
+    assert np.all(np.abs(host(s) - s_r) <= TOL * sabs)
+    assert np.all(np.abs(host(c) - c_r) <= TOL * (c_r + c_r * (1 - c_r) * sabs))
+    assert np.all(np.abs(host(g) - g_r).max(axis=0) <= TOL * gabs)
+
+
+@pytest.mark.parametrize("g0,g1", [(17, 45), (64, 33), (2, 1), (63, 64)])
+def test_grid_shapes(g0, g1):
+    require_gpu()
+    rng = np.random.default_rng(g0 * 100 + g1)
+    ax = np.sort(rng.uniform(-3, 3, g0)).astype(np.float32)
+    ay = np.sort(rng.uniform(-2, 2, g1)).astype(np.float32)
+    j = np.arange(g0 * g1)
+    h = np.stack([ax[j % g0], ay[j // g0]]).astype(np.float32)
+    wb = rng.normal(0, 1.5, g0 * g1 + 1).astype(np.float32)
+    x = rng.uniform(-3.5, 3.5, (2, 777)).astype(np.float32)
+    go = _grid_occ(h, wb, 0.5, g0, g1)
+    _, s = P.occupancy_eval(go, dev(x))
+    oo = oracle_occ(h, wb, 0.5)
+    s_r, _, sabs = O.occ_eval(oo, x)
+    assert np.all(np.abs(host(s) - s_r) <= TOL * sabs)
+    out = host(P.morph_samples(go, dev(x), 10, 0.02))
+    ref, amp, _, _ = O.morph_ws(oo, x, 10, 0.02, diag=True)
+    err = np.abs(out - ref).max(axis=0)
+    assert np.all(err <= TOL * np.maximum(1, amp) * np.maximum(1, np.abs(ref).max(axis=0)))
+
+
+def test_grid_morph_config2_full_size_sampled():
+    require_gpu()
+    cfg = K.C2
+    sc = ws_scene(cfg)
+    seed = I.philox_seed(cfg.cfg_id)
+    x0_d = P.uniform_samples(seed, 0, [cfg.lo] * 2, [cfg.hi] * 2, cfg.n_samples)
+    go = _grid_occ(sc["h"], sc["wb"], sc["ell"], cfg.grid, cfg.grid)
+    out = host(P.morph_samples(go, x0_d, cfg.T, cfg.eta))
+    x0 = O.uniform_samples(seed, 0, [cfg.lo] * 2, [cfg.hi] * 2, cfg.n_samples)
+    n = cfg.n_samples
+    idx = np.unique(np.r_[0, np.arange(1, n, n // 300), n - 1])
+    ref, amp, _, _ = O.morph_ws(oracle_occ(sc["h"], sc["wb"], sc["ell"]), x0[:, idx], cfg.T, cfg.eta,
+                                diag=True)
+    err = np.abs(out[:, idx] - ref).max(axis=0)
+    assert np.all(err <= TOL * np.maximum(1, amp) * np.maximum(1, np.abs(ref).max(axis=0)))
+
+
+def test_grid_morph_config1_full_and_deterministic():
+    require_gpu()
+    cfg = K.C1
+    sc = ws_scene(cfg)
+    x0 = O.uniform_samples(I.philox_seed(cfg.cfg_id), 0, [cfg.lo] * 2, [cfg.hi] * 2, cfg.n_samples)
+    go = _grid_occ(sc["h"], sc["wb"], sc["ell"], cfg.grid, cfg.grid)
+    a = host(P.morph_samples(go, dev(x0), cfg.T, cfg.eta))
+    b = host(P.morph_samples(go, dev(x0), cfg.T, cfg.eta))
+    assert np.array_equal(a, b)
+    ref, amp, _, _ = O.morph_ws(oracle_occ(sc["h"], sc["wb"], sc["ell"]), x0, cfg.T, cfg.eta,
+                                diag=True)
+    err = np.abs(a - ref).max(axis=0)
+    assert np.all(err <= TOL * np.maximum(1, amp) * np.maximum(1, np.abs(ref).max(axis=0)))

@@ -161,8 +161,8 @@ def test_training_reduces_loss_and_fallbacks():
     c3 = K.C3
     pairs = amortise.make_pairs(occ, arm_g, 8, 8192, c3.T, c3.eta, I.philox_seed(5), c3.q_lo, c3.q_hi)
     mlp = P.Mlp.from_layers(I.mlp_init(5, (7, 128, 128, 128, 7)))
-    losses = host(amortise.train(mlp, pairs, 6, 3e-3))
-    assert losses[-1] < 0.7 * losses[0]
+    losses = host(amortise.train(mlp, pairs, 40, 2e-3))
+    assert losses[-8:].mean() < 0.8 * losses[:8].mean()
     q = P.uniform_samples(I.philox_seed(5), 999, [c3.q_lo] * 7, [c3.q_hi] * 7, 8192)
     zero = P.Mlp.from_layers(I.mlp_init(5, (7, 128, 128, 128, 7)))
     _, f_zero, _ = P.amortised_morph(zero, occ, arm_g, q, c3.T, c3.eta)
