@@ -97,7 +97,8 @@ def ws_scene(P, I, K, torch, cfg, dev, grid=True):
     t = Timer(torch)
     with t:
         loss = P.fit_occupancy(h_d, cfg.lengthscale, w, pts_d, y, cfg.fit_steps, cfg.fit_lr,
-                               cfg.fit_l2, "gd", lr_bias=cfg.fit_lr_bias)
+                               cfg.fit_l2, "gd", lr_bias=cfg.fit_lr_bias,
+                               grid=(cfg.grid, cfg.grid) if grid else None)
     fit_ms = t.ms()
     occ = P.Occupancy(h_d, w, cfg.lengthscale, grid=(cfg.grid, cfg.grid) if grid else None)
     return dict(h=h, occ=occ, discs=(dc_d, dr_d), fit_ms=fit_ms,
@@ -241,7 +242,8 @@ def arm_world(P, I, K, torch, dev):
     t = Timer(torch)
     with t:
         loss = P.fit_occupancy(h, c3.lengthscale, w, pts, y, c4.steps, c4.lr, c4.l2, "adam",
-                               beta1=c4.beta1, beta2=c4.beta2, eps=c4.eps, adam_m=m, adam_v=v)
+                               beta1=c4.beta1, beta2=c4.beta2, eps=c4.eps, adam_m=m, adam_v=v,
+                               grid=(c3.grid,) * 3)
     fit_ms = t.ms()
     n = c4.n_points
     fit = {"workload": "occupancy fit 3-D: 2^20 labelled points, 16^3 hinges, l=0.15, BCE + "
@@ -249,7 +251,7 @@ def arm_world(P, I, K, torch, dev):
            "ms_total": fit_ms, "ms_per_step": fit_ms / c4.steps,
            "loss_first": float(loss[0]), "loss_last": float(loss[-1]),
            "pairs_per_s": 2.0 * n * M * c4.steps / (fit_ms * 1e-3)}
-    occ = P.Occupancy(h, w, c3.lengthscale)
+    occ = P.Occupancy(h, w, c3.lengthscale, grid=(c3.grid,) * 3)
     return dict(arm=arm, boxes=(bc_d, be_d), occ=occ, fit=fit)
 
 
@@ -267,16 +269,33 @@ def arm_morph(P, I, K, torch, world):
     ms = t.ms() / reps
     _, h0 = P.label_configs(arm, *world["boxes"], q0, count=True)
     _, h1 = P.label_configs(arm, *world["boxes"], q1, count=True)
+    # own work of the factorised evaluation per body point and step: two (16*16) x 16
+    # matrix-vector products on MFMA = 4 * 4096 flops
+    flops = c3.n_samples * c3.T * c3.n_body * 4.0 * c3.n_hinges
+    ach = flops / (ms * 1e-3) / 1e12
+    res = {"workload": "plain morph 7-DOF arm: 65,536 configurations, 56 body points, 16^3 "
+                       "hinges, l=0.15, T=30, eta=0.01, 40 boxes",
+           "morph_ms": ms, "samples_per_s": c3.n_samples / (ms * 1e-3),
+           "collision_free_before": 1 - h0.item() / c3.n_samples,
+           "collision_free_after": 1 - h1.item() / c3.n_samples,
+           "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA / 1e12,
+                        "unit": "TFLOP/s", "frac": ach * 1e12 / PEAK_FP32_MFMA,
+                        "kernel": "k_arm_grid3d<7,16,16,true>",
+                        "work": "4*M FP32 MFMA flops per body point and step"}}
+    dense = P.Occupancy(occ.hinges, occ.weights, occ.lengthscale)
+    P.morph_samples(dense, q0, c3.T, c3.eta, arm=arm, out=q1)
+    t = Timer(torch)
+    with t:
+        P.morph_samples(dense, q0, c3.T, c3.eta, arm=arm, out=q1)
+    dms = t.ms()
     pairs = c3.n_samples * c3.T * c3.n_body * c3.n_hinges
-    ach = pairs * FLOPS_PER_PAIR[3] / (ms * 1e-3) / 1e12
-    return {"workload": "plain morph 7-DOF arm: 65,536 configurations, 56 body points, 16^3 "
-                        "hinges, l=0.15, T=30, eta=0.01, 40 boxes",
-            "morph_ms": ms, "samples_per_s": c3.n_samples / (ms * 1e-3),
-            "collision_free_before": 1 - h0.item() / c3.n_samples,
-            "collision_free_after": 1 - h1.item() / c3.n_samples,
-            "roofline": {"bound": "alu", "achieved": ach, "peak": alu_peak_tflops(3),
-                         "unit": "TFLOP/s", "frac": ach / alu_peak_tflops(3),
-                         "kernel": "k_morph_arm<7,512>"}}
+    a2 = pairs * FLOPS_PER_PAIR[3] / (dms * 1e-3) / 1e12
+    res["pairwise_kernel"] = {"kernel": "k_morph_arm<7,512>", "morph_ms": dms,
+                              "samples_per_s": c3.n_samples / (dms * 1e-3),
+                              "roofline": {"bound": "alu", "achieved": a2,
+                                           "peak": alu_peak_tflops(3), "unit": "TFLOP/s",
+                                           "frac": a2 / alu_peak_tflops(3)}}
+    return res
 
 
 def amortised(args, P, I, K, torch, world):
@@ -319,6 +338,17 @@ def amortised(args, P, I, K, torch, world):
     _, fz, nz = P.amortised_morph(zero, occ, arm, q, c3.T, c3.eta, c5.threshold)
     n = c5.eval_samples
     nf_v = int(nf.item())
+    sweep = []
+    for th in (0.5, 0.3, 0.2, 0.1, 0.05, 0.02):
+        o2, f2, n2 = P.amortised_morph(mlp, occ, arm, q, c3.T, c3.eta, th)
+        t = Timer(torch)
+        with t:
+            P.amortised_morph(mlp, occ, arm, q, c3.T, c3.eta, th, out=o2, flag=f2, n_fallback=n2)
+        ms2 = t.ms()
+        _, h2 = P.label_configs(arm, *world["boxes"], o2, count=True)
+        sweep.append({"threshold": th, "ms": ms2, "speedup": pl_ms / ms2,
+                      "fallback_fraction": int(n2.item()) / n,
+                      "collision_free": 1 - h2.item() / n})
     return {"workload": "amortised morph: residual MLP 7-256-256-256-7 SiLU (BF16 MFMA, FP32 "
                         "accumulate) trained on plain-morph pairs, plain T=30 fallback where "
                         "max body-point occupancy > 0.5; 65,536 held-out configurations",
@@ -331,7 +361,8 @@ def amortised(args, P, I, K, torch, world):
             "fallback_fraction_without_network": int(nz.item()) / n,
             "collision_free_prior": 1 - h0.item() / n,
             "collision_free_amortised": 1 - ha.item() / n,
-            "collision_free_plain": 1 - hp.item() / n}
+            "collision_free_plain": 1 - hp.item() / n,
+            "threshold_sweep": sweep}
 
 
 def main():

@@ -292,7 +292,8 @@ def adam_step(p, g, m, v, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, l
 
 def fit_occupancy(hinges, lengthscale: float, weights, pts, labels, steps: int, lr: float,
                   l2: float, optimizer: str = "gd", lr_bias=None, beta1=0.9, beta2=0.999,
-                  eps=1e-8, adam_m=None, adam_v=None, t0: int = 0, record_loss: bool = True):
+                  eps=1e-8, adam_m=None, adam_v=None, t0: int = 0, record_loss: bool = True,
+                  grid=None):
     """Full-batch occupancy fit on the GPU (Sec. 3.1); updates `weights` in place.
 
     Returns the per-step loss tensor [steps] (device) or None.
@@ -301,7 +302,7 @@ def fit_occupancy(hinges, lengthscale: float, weights, pts, labels, steps: int, 
     lib = _lib.load()
     dim, M = int(hinges.shape[0]), int(hinges.shape[1])
     n = int(pts.shape[1])
-    occ = Occupancy(hinges, weights, lengthscale)
+    occ = Occupancy(hinges, weights, lengthscale, grid=grid)
     o = occ.c_struct()
     opt = _lib.pdmp_fit_opts()
     opt.optimizer = 0 if optimizer == "gd" else 1

@@ -263,9 +263,9 @@ int32_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, int
 }
 
 // One full-batch fit: `steps` iterations of forward, BCE, backward and update.
-int32_t launch_fit(int dim, const float *hinges, int M, float ell, float *wb, const float *pts,
-                   const uint8_t *y, int64_t n, const pdmp_fit_opts &o, float *loss_out, void *ws,
-                   hipStream_t st) {
+int32_t launch_fit(int dim, const float *hinges, int M, const int *grid, float ell, float *wb,
+                   const float *pts, const uint8_t *y, int64_t n, const pdmp_fit_opts &o,
+                   float *loss_out, void *ws, hipStream_t st) {
     float kappa, gscale;
     derive_scales(ell, kappa, gscale);
     char *p = (char *)ws;
@@ -293,7 +293,7 @@ int32_t launch_fit(int dim, const float *hinges, int M, float ell, float *wb, co
         a.x_in = pts;
         a.n = n;
         a.s_out = s;
-        if (int32_t e = launch_rbf(dim, kEval, a, st)) return e;
+        if (int32_t e = launch_occ_any(dim, kEval, a, grid, st)) return e;
         hipLaunchKernelGGL(k_bce_partial, dim3(nb_n), dim3(kRedBlock), 0, st, s, y, n,
                            (float)(1.0 / (double)n), g, bparts);
         if (loss_out) {

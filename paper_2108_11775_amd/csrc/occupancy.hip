@@ -242,4 +242,13 @@ int32_t launch_rbf(int dim, int mode, const RbfArgs &a, hipStream_t st) {
     return dim == 2 ? launch_rbf_mode<2>(mode, a, st) : launch_rbf_mode<3>(mode, a, st);
 }
 
+int32_t launch_occ_any(int dim, int mode, const RbfArgs &a, const int *grid, hipStream_t st) {
+    if (grid && grid[0] > 0 && a.splits <= 1) {
+        const int32_t r = dim == 2 ? launch_grid2d(mode, a, grid[0], grid[1], st)
+                                   : launch_grid3d_ws(mode, a, grid, st);
+        if (r != PDMP_EUNSUPPORTED) return r;  // other grids take the pairwise sum
+    }
+    return launch_rbf(dim, mode, a, st);
+}
+
 }  // namespace pdmp

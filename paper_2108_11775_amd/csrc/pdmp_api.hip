@@ -156,11 +156,8 @@ static int32_t rbf_call(const pdmp_occupancy *occ, int mode, const float *x, int
     a.s_out = s_out;
     a.g_out = g_out;
     a.x_out = x_out;
-    if (has_grid(occ) && occ->dim == 2) {
-        const int32_t st = launch_grid2d(mode, a, occ->grid[0], occ->grid[1], (hipStream_t)stream);
-        if (st != PDMP_EUNSUPPORTED) return st;  // grids beyond the MFMA path take the pair sum
-    }
-    return launch_rbf(occ->dim, mode, a, (hipStream_t)stream);
+    return launch_occ_any(occ->dim, mode, a, has_grid(occ) ? occ->grid : nullptr,
+                          (hipStream_t)stream);
 }
 
 int32_t pdmp_occupancy_eval(const pdmp_occupancy *occ, const float *x, int64_t n, float *c_out,
@@ -211,6 +208,12 @@ int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const
     if (arm) {
         float kappa, gscale;
         derive_scales(occ->lengthscale, kappa, gscale);
+        if (has_grid(occ)) {
+            st = launch_arm_grid3d(*arm, occ->hinges, occ->weights, occ->n_hinges, occ->grid, kappa,
+                                   gscale, in, out, n, T, eta, nullptr, true, 0.0f, nullptr,
+                                   nullptr, (hipStream_t)stream);
+            if (st != PDMP_EUNSUPPORTED) return st;
+        }
         return launch_morph_arm(*arm, occ->hinges, occ->weights, occ->n_hinges, kappa, gscale, in,
                                 out, n, T, eta, nullptr, (hipStream_t)stream);
     }
@@ -265,8 +268,9 @@ int32_t pdmp_fit_occupancy(const pdmp_occupancy *occ, float *weights, const floa
         set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
         return PDMP_ENOMEM;
     }
-    return launch_fit(occ->dim, occ->hinges, occ->n_hinges, occ->lengthscale, weights, pts,
-                      labels, n, *opts, loss_out, ws, (hipStream_t)stream);
+    return launch_fit(occ->dim, occ->hinges, occ->n_hinges, has_grid(occ) ? occ->grid : nullptr,
+                      occ->lengthscale, weights, pts, labels, n, *opts, loss_out, ws,
+                      (hipStream_t)stream);
 }
 
 int32_t pdmp_occupancy_bwd(const pdmp_occupancy *occ, const float *x, int64_t n, const float *g,
@@ -394,6 +398,12 @@ int32_t pdmp_arm_max_occupancy(const pdmp_occupancy *occ, const pdmp_arm *arm, c
     PDMP_REQUIRE(q != nullptr, "q NULL");
     float kappa, gscale;
     derive_scales(occ->lengthscale, kappa, gscale);
+    if (has_grid(occ)) {
+        st = launch_arm_grid3d(*arm, occ->hinges, occ->weights, occ->n_hinges, occ->grid, kappa,
+                               gscale, q, nullptr, n, 1, 0.0f, nullptr, false, thresh, maxc, flag,
+                               (hipStream_t)stream);
+        if (st != PDMP_EUNSUPPORTED) return st;
+    }
     return launch_arm_max_occ(*arm, occ->hinges, occ->weights, occ->n_hinges, kappa, q, n, thresh,
                               maxc, flag, (hipStream_t)stream);
 }
@@ -448,14 +458,25 @@ int32_t pdmp_amortised_morph(const pdmp_mlp *mlp, const pdmp_occupancy *occ, con
 
     float kappa, gscale;
     derive_scales(occ->lengthscale, kappa, gscale);
+    const int *grid = has_grid(occ) ? occ->grid : nullptr;
     if ((st = launch_mlp_forward(*mlp, q, n, out, nullptr, mws, s))) return st;
-    if ((st = launch_arm_max_occ(*arm, occ->hinges, occ->weights, occ->n_hinges, kappa, out, n,
-                                 thresh, nullptr, fl, s)))
-        return st;
+    st = PDMP_EUNSUPPORTED;
+    if (grid)
+        st = launch_arm_grid3d(*arm, occ->hinges, occ->weights, occ->n_hinges, grid, kappa, gscale,
+                               out, nullptr, n, 1, 0.0f, nullptr, false, thresh, nullptr, fl, s);
+    if (st == PDMP_EUNSUPPORTED)
+        st = launch_arm_max_occ(*arm, occ->hinges, occ->weights, occ->n_hinges, kappa, out, n,
+                                thresh, nullptr, fl, s);
+    if (st) return st;
     if ((st = launch_compact(*arm, fl, q, n, counts, offs, total, idx, qc, s))) return st;
-    if ((st = launch_morph_arm(*arm, occ->hinges, occ->weights, occ->n_hinges, kappa, gscale, qc, qc,
-                               n, T, eta, total, s)))
-        return st;
+    st = PDMP_EUNSUPPORTED;
+    if (grid)
+        st = launch_arm_grid3d(*arm, occ->hinges, occ->weights, occ->n_hinges, grid, kappa, gscale,
+                               qc, qc, n, T, eta, total, true, 0.0f, nullptr, nullptr, s);
+    if (st == PDMP_EUNSUPPORTED)
+        st = launch_morph_arm(*arm, occ->hinges, occ->weights, occ->n_hinges, kappa, gscale, qc, qc,
+                              n, T, eta, total, s);
+    if (st) return st;
     return launch_scatter(*arm, idx, total, qc, n, out, s);
 }
 

@@ -92,6 +92,14 @@ struct RbfArgs {
 
 int32_t launch_rbf(int dim, int mode, const RbfArgs &a, hipStream_t st);
 int32_t launch_grid2d(int mode, const RbfArgs &a, int g0, int g1, hipStream_t st);
+int32_t launch_grid3d_ws(int mode, const RbfArgs &a, const int *grid, hipStream_t st);
+int32_t launch_arm_grid3d(const pdmp_arm &arm, const float *h, const float *w, int M,
+                          const int *grid, float kappa, float gscale, const float *qi, float *qo,
+                          int64_t n, int T, float eta, const uint32_t *n_active, bool morph,
+                          float thresh, float *maxc, uint8_t *flag, hipStream_t st);
+// The occupancy evaluation of one RBF launch, through the grid factorisation when
+// `grid` describes one the grid kernels support, else the pairwise kernel.
+int32_t launch_occ_any(int dim, int mode, const RbfArgs &a, const int *grid, hipStream_t st);
 int32_t launch_uniform(uint64_t seed, uint32_t sid, const float *lo, const float *hi, int dim,
                        int64_t n, float *out, hipStream_t st);
 int32_t launch_label_discs(const pdmp_discs &sc, const float *x, int64_t n, uint8_t *out,
@@ -133,8 +141,8 @@ int32_t launch_bce(const float *s, const uint8_t *y, int64_t n, float *loss, flo
                    double *parts, hipStream_t st);
 int32_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, int64_t n_decay,
                     int t, float lr, float b1, float b2, float eps, float l2, hipStream_t st);
-int32_t launch_fit(int dim, const float *hinges, int M, float ell, float *wb, const float *pts,
-                   const uint8_t *y, int64_t n, const pdmp_fit_opts &o, float *loss_out, void *ws,
-                   hipStream_t st);
+int32_t launch_fit(int dim, const float *hinges, int M, const int *grid, float ell, float *wb,
+                   const float *pts, const uint8_t *y, int64_t n, const pdmp_fit_opts &o,
+                   float *loss_out, void *ws, hipStream_t st);
 
 }  // namespace pdmp

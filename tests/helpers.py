@@ -61,6 +61,6 @@ def oracle_occ(h, wb, ell):
     return O.Occupancy(h, wb[:-1], float(wb[-1]), ell)
 
 
-def gpu_occ(h, wb, ell):
+def gpu_occ(h, wb, ell, grid=None):
     import paper_2108_11775_amd as P
-    return P.Occupancy(dev(h), dev(wb), ell)
+    return P.Occupancy(dev(h), dev(wb), ell, grid=grid)

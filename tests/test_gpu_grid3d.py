@@ -1,0 +1,114 @@
+"""GPU parity of the grid-factorised 3-D path (16^3 hinges, FP32 MFMA): workspace
+occupancy/gradient/morph, the joint-space morph and the body-point check, against
+the oracle's pairwise definitions with the same tolerances as the pairwise path."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2108_11775_amd as P
+from paper_2108_11775_amd import configs as K, inputs as I
+
+from helpers import arm_scene, dev, gpu_occ, host, oracle_occ, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+G = (16, 16, 16)
+
+
+@pytest.mark.parametrize("n", [1, 4099])
+def test_grid3d_eval_grad(n):
+    require_gpu()
+    sc = arm_scene()
+    go = gpu_occ(sc["h"], sc["wb"], sc["ell"], G)
+    x = I.uniform_points(3, K.STREAM_EVAL, 3, n, -1.3, 1.3)
+    c, s = P.occupancy_eval(go, dev(x))
+    _, g = P.occupancy_grad(go, dev(x))
+    oo = oracle_occ(sc["h"], sc["wb"], sc["ell"])
+    s_r, c_r, sabs = O.occ_eval(oo, x)
+    _, g_r, _, gabs = O.occ_grad(oo, x)
+    assert np.all(np.abs(host(s) - s_r) <= TOL * sabs), np.max(np.abs(host(s) - s_r) / sabs)
+    assert np.all(np.abs(host(c) - c_r) <= TOL * (c_r + c_r * (1 - c_r) * sabs))
+    assert np.all(np.abs(host(g) - g_r).max(axis=0) <= TOL * gabs)
+
+
+def test_grid3d_workspace_morph():
+    require_gpu()
+    sc = arm_scene()
+    go = gpu_occ(sc["h"], sc["wb"], sc["ell"], G)
+    x = I.uniform_points(3, K.STREAM_EVAL, 3, 999, -1.0, 1.0)
+    out = host(P.morph_samples(go, dev(x), 6, 0.002))
+    ref, amp, _, _ = O.morph_ws(oracle_occ(sc["h"], sc["wb"], sc["ell"]), x, 6, 0.002, diag=True)
+    err = np.abs(out - ref).max(axis=0)
+    assert np.all(err <= TOL * np.maximum(1, amp) * np.maximum(1, np.abs(ref).max(axis=0)))
+
+
+def _arms(sc):
+    a, d, al, th = sc["dh"]
+    return O.Arm(a, d, al, th, 8), P.Arm(a, d, al, th, 8)
+
+
+def test_grid3d_arm_one_step_full_size_sampled():
+    require_gpu()
+    sc = arm_scene()
+    ao, ag = _arms(sc)
+    c3 = K.C3
+    seed = I.philox_seed(c3.cfg_id)
+    q0_d = P.uniform_samples(seed, 0, [c3.q_lo] * 7, [c3.q_hi] * 7, c3.n_samples)
+    out = host(P.morph_samples(gpu_occ(sc["h"], sc["wb"], sc["ell"], G), q0_d, 1, c3.eta, arm=ag))
+    q0 = O.uniform_samples(seed, 0, [c3.q_lo] * 7, [c3.q_hi] * 7, c3.n_samples)
+    idx = np.unique(np.r_[0, np.arange(1, c3.n_samples, c3.n_samples // 40), c3.n_samples - 1])
+    oo = oracle_occ(sc["h"], sc["wb"], sc["ell"])
+    ref = O.morph_arm(ao, oo, q0[:, idx], 1, c3.eta)
+    pts = O.fk_points(ao, q0[:, idx])
+    scale = np.zeros(idx.size)
+    for s_ in range(idx.size):
+        _, _, _, gabs = O.occ_grad(oo, pts[:, :, s_])
+        lever = np.array([np.abs(O.fk_jacobian(ao, q0[:, idx[s_]], p)).sum(axis=0).max()
+                          for p in range(pts.shape[1])])
+        scale[s_] = (gabs * lever).sum()
+    err = np.abs(out[:, idx] - ref).max(axis=0)
+    tol = TOL * (np.abs(ref).max(axis=0) + c3.eta * scale)
+    assert np.all(err <= tol), np.max(err / tol)
+
+
+@pytest.mark.parametrize("n", [37, 200])
+def test_grid3d_arm_T_steps(n):
+    require_gpu()
+    sc = arm_scene()
+    ao, ag = _arms(sc)
+    c3 = K.C3
+    q0 = O.uniform_samples(I.philox_seed(c3.cfg_id), 7, [c3.q_lo] * 7, [c3.q_hi] * 7, n)
+    out = host(P.morph_samples(gpu_occ(sc["h"], sc["wb"], sc["ell"], G), dev(q0), c3.T, c3.eta,
+                               arm=ag))
+    idx = np.arange(n) if n <= 40 else np.unique(np.r_[np.arange(0, n, n // 24), n - 1])
+    ref, amp, _ = O.morph_arm(ao, oracle_occ(sc["h"], sc["wb"], sc["ell"]), q0[:, idx], c3.T,
+                              c3.eta, diag=True)
+    err = np.abs(out[:, idx] - ref).max(axis=0)
+    tol = TOL * np.maximum(1.0, amp) * np.maximum(1.0, np.abs(ref).max(axis=0))
+    assert np.all(err <= tol), (np.max(err / tol), err.max())
+
+
+def test_grid3d_arm_check_and_amortised_zero_network():
+    require_gpu()
+    sc = arm_scene()
+    ao, ag = _arms(sc)
+    occ = gpu_occ(sc["h"], sc["wb"], sc["ell"], G)
+    q = I.uniform_points(3, K.STREAM_EVAL, 7, 3000, -math.pi, math.pi)
+    maxc, flag = P.arm_max_occupancy(occ, ag, dev(q), 0.5)
+    oo = oracle_occ(sc["h"], sc["wb"], sc["ell"])
+    pts = O.fk_points(ao, q)
+    ref = np.array([O.occ_eval(oo, pts[:, :, s])[1].max() for s in range(q.shape[1])])
+    assert np.abs(host(maxc) - ref).max() <= 1e-4
+    sure = np.abs(ref - 0.5) > 1e-4
+    assert np.array_equal(host(flag)[sure], (ref[sure] > 0.5).astype(np.uint8))
+    mlp = P.Mlp.from_layers(I.mlp_init(5, K.C5.widths))
+    qd = dev(q)
+    out, fl, nf = P.amortised_morph(mlp, occ, ag, qd, K.C3.T, K.C3.eta)
+    plain = host(P.morph_samples(occ, qd, K.C3.T, K.C3.eta, arm=ag))
+    out, fl = host(out), host(fl).astype(bool)
+    assert np.array_equal(fl, host(flag).astype(bool))
+    assert np.array_equal(out[:, fl], plain[:, fl])
+    assert np.array_equal(out[:, ~fl], q[:, ~fl])
