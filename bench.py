@@ -38,6 +38,22 @@ PEAK_EXP = 256 * 4 * 16 * 0.5 * 2.4e9
 FLOPS_PER_PAIR = {2: 12, 3: 17}    # 5*dim + 2 algorithmic FP32 flops per sample-hinge pair
 
 
+# HBM traffic per launch of the headline kernel from the two rocprofv3 --pmc runs in
+# profiles/k_grid2d_morph_ws2d_1M.md (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the
+# factors a plain 256 MiB device copy reads under the same counters).  Valid only
+# while grid2d.hip is the source the counters were taken on.
+GRID2D_TRAFFIC = {"bytes": (4232.5 * 2.0 + 8192.0) * 1024,
+                  "sha256": "214af559c0e5c1879e08bbc0db22836c1871253a6beb4824be719d5093b62c49"}
+
+
+def grid2d_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2108_11775_amd", "csrc", "grid2d.hip")
+    with open(src, "rb") as f:
+        ok = hashlib.sha256(f.read()).hexdigest() == GRID2D_TRAFFIC["sha256"]
+    return GRID2D_TRAFFIC["bytes"] if ok else None
+
+
 def alu_peak_tflops(dim):
     f = FLOPS_PER_PAIR[dim]
     return f / max(f / PEAK_FP32_VALU, 1.0 / PEAK_EXP) / 1e12
@@ -59,6 +75,8 @@ def parse():
                    help="skip the secondary workloads (profiling runs)")
     p.add_argument("--dense", action="store_true",
                    help="headline with the pairwise kernel instead of the grid factorisation")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="run a plain 256 MiB device copy first (scales profiler byte counters)")
     p.add_argument("--train-epochs", type=int, default=None)
     p.add_argument("--train-batches", type=int, default=None)
     return p.parse_args()
@@ -173,9 +191,12 @@ def headline(args, P, I, K, torch, dev):
         achieved = flops / (morph_ms * 1e-3) / 1e12
         res["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA / 1e12,
                            "unit": "TFLOP/s", "frac": achieved * 1e12 / PEAK_FP32_MFMA,
-                           "traffic": None, "kernel": "k_grid2d<2,kMorph>",
+                           "traffic": grid2d_traffic(), "kernel": "k_grid2d<2,kMorph>",
                            "kernel_ms": morph_ms,
-                           "work": "4*G0*G1 FP32 MFMA flops per sample-step (64x64 grid)"}
+                           "work": "4*G0*G1 FP32 MFMA flops per sample-step (64x64 grid)",
+                           "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE + "
+                                           "WRITE_SIZE, copy-calibrated); algorithmic "
+                                           f"{N * 2 * 4 * 2} bytes"}
         # the pairwise kernel on the same batch, for reference
         dense = P.Occupancy(occ.hinges, occ.weights, occ.lengthscale)
         P.morph_samples(dense, x0, cfg.T, cfg.eta, out=x1)
@@ -380,6 +401,14 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     dev = torch.device("cuda", 0)
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 2 x 256 MiB device copies")
+        del src, dst
     hl = headline(args, P, I, K, torch, dev)
     cfg = hl["cfg"]
     out = {

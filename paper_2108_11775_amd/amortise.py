@@ -29,11 +29,13 @@ def make_pairs(occ: Occupancy, arm: Arm, n_batches: int, batch: int, T: int, eta
 
 
 def train(mlp: Mlp, pairs, epochs: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
-          log=None):
+          log=None, schedule: str = "constant"):
     """Adam on the MSE between q + f(q) and the plain-morph target.
 
+    schedule "cosine" anneals the step as lr * (1 + cos(pi t / steps)) / 2.
     Returns the per-step loss as a device tensor [epochs * len(pairs)].
     """
+    import math
     dev = mlp.params.device
     B = int(pairs[0][0].shape[1])
     steps = epochs * len(pairs)
@@ -50,7 +52,8 @@ def train(mlp: Mlp, pairs, epochs: int, lr: float, beta1=0.9, beta2=0.999, eps=1
             mlp.forward(q, acts=acts, out=qhat)
             mlp.backward(qhat, tgt, acts, grad=grad, loss=losses[t:t + 1])
             t += 1
-            adam_step(mlp.params, grad, m, v, t, lr, beta1, beta2, eps)
+            lr_t = lr if schedule == "constant" else 0.5 * lr * (1.0 + math.cos(math.pi * (t - 1) / steps))
+            adam_step(mlp.params, grad, m, v, t, lr_t, beta1, beta2, eps)
             mlp.pack()
         if log is not None:
             log(f"epoch {ep + 1}/{epochs}: loss {losses[t - 1].item():.5f} "
