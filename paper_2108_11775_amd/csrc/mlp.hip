@@ -73,6 +73,44 @@ constexpr int kGK = 32;      // K per LDS stage
 constexpr int kGPad = 8;     // row padding (bf16) against bank conflicts
 constexpr int kGRow = kGK + kGPad;
 
+// Stage a 64 x 32 (rows x k) tile of X(row, k) = X[row*s_row + k*s_k] into T[row][k]
+// (row stride kGRow).  k-contiguous and row-contiguous operands use 16-byte loads
+// when the whole tile is in range; anything else goes element by element.
+__device__ __forceinline__ void stage_tile(const uint16_t *__restrict__ X, int64_t s_row,
+                                           int64_t s_k, int rows, int r0, int k0, int ke,
+                                           bool k_vec, bool r_vec, int lrow, int lseg, int kr,
+                                           int rseg, uint16_t *T) {
+    const bool full = r0 + kGT <= rows && k0 + kGK <= ke;
+    if (full && k_vec) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(X + (int64_t)(r0 + lrow) * s_row + k0 + lseg);
+        *reinterpret_cast<uint4 *>(&T[lrow * kGRow + lseg]) = v;
+        return;
+    }
+    if (full && r_vec) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(X + (int64_t)(k0 + kr) * s_k + r0 + rseg);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            T[(rseg + 2 * j) * kGRow + kr] = (uint16_t)(w[j] & 0xffffu);
+            T[(rseg + 2 * j + 1) * kGRow + kr] = (uint16_t)(w[j] >> 16);
+        }
+        return;
+    }
+    const int r = r0 + lrow;
+    uint16_t v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int k = k0 + lseg + j;
+        v[j] = (k < ke && r < rows) ? X[(int64_t)r * s_row + (int64_t)k * s_k] : (uint16_t)0;
+    }
+    uint4 p;
+    p.x = v[0] | ((uint32_t)v[1] << 16);
+    p.y = v[2] | ((uint32_t)v[3] << 16);
+    p.z = v[4] | ((uint32_t)v[5] << 16);
+    p.w = v[6] | ((uint32_t)v[7] << 16);
+    *reinterpret_cast<uint4 *>(&T[lrow * kGRow + lseg]) = p;
+}
+
 template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     __shared__ __attribute__((aligned(16))) uint16_t As[kGT * kGRow];
@@ -89,30 +127,16 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 
     const int lrow = tid >> 2;        // 0..63: tile row this thread stages
     const int lseg = (tid & 3) * 8;   // 8 consecutive k
+    const int kr = tid >> 3;          // 0..31: k this thread stages (row-contiguous operands)
+    const int rseg = (tid & 7) * 8;   // 8 consecutive rows
+    // 16-byte loads when an operand is contiguous along k or along its rows
+    const bool a_k = g.a_sk == 1 && (g.a_sm & 7) == 0 && ((uintptr_t)g.A & 15) == 0;
+    const bool b_k = g.b_sk == 1 && (g.b_sn & 7) == 0 && ((uintptr_t)g.B & 15) == 0;
+    const bool a_r = g.a_sm == 1 && (g.a_sk & 7) == 0 && ((uintptr_t)g.A & 15) == 0;
+    const bool b_r = g.b_sn == 1 && (g.b_sk & 7) == 0 && ((uintptr_t)g.B & 15) == 0;
     for (int k0 = kb; k0 < ke; k0 += kGK) {
-        {
-            const int m = m0 + lrow;
-            uint16_t va[8], vb[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = k0 + lseg + j;
-                const bool okk = k < ke;
-                va[j] = (okk && m < g.M) ? g.A[(int64_t)m * g.a_sm + (int64_t)k * g.a_sk] : (uint16_t)0;
-                const int n = n0 + lrow;
-                vb[j] = (okk && n < g.N) ? g.B[(int64_t)n * g.b_sn + (int64_t)k * g.b_sk] : (uint16_t)0;
-            }
-            uint4 pa, pb;
-            pa.x = va[0] | ((uint32_t)va[1] << 16);
-            pa.y = va[2] | ((uint32_t)va[3] << 16);
-            pa.z = va[4] | ((uint32_t)va[5] << 16);
-            pa.w = va[6] | ((uint32_t)va[7] << 16);
-            pb.x = vb[0] | ((uint32_t)vb[1] << 16);
-            pb.y = vb[2] | ((uint32_t)vb[3] << 16);
-            pb.z = vb[4] | ((uint32_t)vb[5] << 16);
-            pb.w = vb[6] | ((uint32_t)vb[7] << 16);
-            *reinterpret_cast<uint4 *>(&As[lrow * kGRow + lseg]) = pa;
-            *reinterpret_cast<uint4 *>(&Bs[lrow * kGRow + lseg]) = pb;
-        }
+        stage_tile(g.A, g.a_sm, g.a_sk, g.M, m0, k0, ke, a_k, a_r, lrow, lseg, kr, rseg, As);
+        stage_tile(g.B, g.b_sn, g.b_sk, g.N, n0, k0, ke, b_k, b_r, lrow, lseg, kr, rseg, Bs);
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < kGK; kk += 16) {
@@ -223,17 +247,23 @@ __global__ void k_sum_splits(const float *__restrict__ part, int S, int64_t MN, 
     out[j] = (float)acc;
 }
 
-// Column sums of a BF16 [B][N] matrix: partial over row range blockIdx.y, then
-// k_sum_splits.  part[y * N + col].
-__global__ void k_colsum_partial(const uint16_t *__restrict__ x, int64_t B, int N, int64_t rows_per,
-                                 float *part) {
-    const int col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= N) return;
+// Column sums of a BF16 [B][N] matrix over the row range of blockIdx.y: 64 columns
+// per block, four row phases per column combined in a fixed order; then
+// k_sum_splits adds the range partials.  part[y * N + col].
+__global__ void __launch_bounds__(256)
+k_colsum_partial(const uint16_t *__restrict__ x, int64_t B, int N, int64_t rows_per, float *part) {
+    __shared__ float sh[4][64];
+    const int cl = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int col = blockIdx.x * 64 + cl;
     const int64_t r0 = (int64_t)blockIdx.y * rows_per;
     const int64_t r1 = r0 + rows_per < B ? r0 + rows_per : B;
-    double acc = 0.0;
-    for (int64_t r = r0; r < r1; ++r) acc += bf16_to_f32(x[r * N + col]);
-    part[(int64_t)blockIdx.y * N + col] = (float)acc;
+    float acc = 0.0f;
+    if (col < N)
+        for (int64_t r = r0 + ph; r < r1; r += 4) acc += bf16_to_f32(x[r * N + col]);
+    sh[ph][cl] = acc;
+    __syncthreads();
+    if (ph == 0 && col < N)
+        part[(int64_t)blockIdx.y * N + col] = ((sh[0][cl] + sh[1][cl]) + sh[2][cl]) + sh[3][cl];
 }
 
 // ------------------------------------------------------------------ host ---
@@ -358,7 +388,7 @@ static int wgrad_splits(int64_t B) {
 size_t mlp_bwd_ws_bytes(const pdmp_mlp &m, int64_t B) {
     const MlpLayout ly = layout_of(m);
     const int S = wgrad_splits(B);
-    const int64_t rows_per = 2048;
+    const int64_t rows_per = 256;
     const int64_t cs = (B + rows_per - 1) / rows_per;
     const int wmax = ly.H > ly.n_in ? ly.H : ly.n_in;
     return 2 * al256((size_t)B * wmax * 2) + al256((size_t)S * wmax * wmax * 4) +
@@ -372,7 +402,7 @@ int32_t launch_mlp_backward(const pdmp_mlp &m, const float *qhat, const float *t
     const MlpLayout ly = layout_of(m);
     ActPtrs ap = act_ptrs(ly, acts, B);
     const int S = wgrad_splits(B);
-    const int64_t rows_per = 2048;
+    const int64_t rows_per = 256;
     const int cs = (int)((B + rows_per - 1) / rows_per);
     const int wmax = ly.H > ly.n_in ? ly.H : ly.n_in;
     char *c = (char *)ws;
@@ -417,7 +447,7 @@ int32_t launch_mlp_backward(const pdmp_mlp &m, const float *qhat, const float *t
         hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)(((int64_t)O * I + 255) / 256)), dim3(256), 0,
                            st, part, splits, (int64_t)O * I, grad + ly.woff(l));
         // db_l[o] = sum_b dZ[b][o]
-        hipLaunchKernelGGL(k_colsum_partial, dim3((O + 255) / 256, cs), dim3(256), 0, st, dz[cur], B,
+        hipLaunchKernelGGL(k_colsum_partial, dim3((O + 63) / 64, cs), dim3(256), 0, st, dz[cur], B,
                            O, rows_per, cpart);
         hipLaunchKernelGGL(k_sum_splits, dim3((O + 255) / 256), dim3(256), 0, st, cpart, cs,
                            (int64_t)O, grad + ly.boff(l));
