@@ -95,15 +95,22 @@ k_final(const double *__restrict__ a, int na, double sa, const double *__restric
     if (threadIdx.x == 0) *out = (float)(sa * ta + sb * tb);
 }
 
-// out[j] = scale * sum_{r < rows} part[r * m + j] (+ add[j] * add_scale), fixed r order.
+// out[j] = scale * sum_{r < rows} part[r * m + j] (+ add[j] * add_scale).  A block
+// owns 64 columns; its four waves sum the rows r = ph (mod 4) in increasing order and
+// the four sums are added in a fixed order.
 __global__ void __launch_bounds__(256)
 k_sum_rows(const float *__restrict__ part, int rows, int64_t m, double scale,
            const float *__restrict__ add, float add_scale, float *out) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
+    __shared__ double sh[4][64];
+    const int cl = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 64 + cl;
     double acc = 0.0;
-    for (int r = 0; r < rows; ++r) acc += part[(size_t)r * m + j];
-    float v = (float)(acc * scale);
+    if (j < m)
+        for (int r = ph; r < rows; r += 4) acc += part[(size_t)r * m + j];
+    sh[ph][cl] = acc;
+    __syncthreads();
+    if (ph != 0 || j >= m) return;
+    float v = (float)((((sh[0][cl] + sh[1][cl]) + sh[2][cl]) + sh[3][cl]) * scale);
     if (add) v = fmaf(add_scale, add[j], v);
     out[j] = v;
 }
@@ -161,10 +168,34 @@ static int bwd_splits(int dim, int M, int64_t n) {
     return (int)s;
 }
 
+// Partial rows: enough for the pairwise splits and for the grid kernels.
+static size_t bwd_rows(int dim, int M, int64_t n) {
+    const size_t a = (size_t)bwd_splits(dim, M, n), b = wgrad_rows_max(n);
+    return a > b ? a : b;
+}
+
 size_t bwd_ws_bytes(int dim, int M, int64_t n) {
-    const int S = bwd_splits(dim, M, n);
-    return align256((size_t)S * M * sizeof(float)) + align256((size_t)n * sizeof(float)) +
+    return align256(bwd_rows(dim, M, n) * M * sizeof(float)) + align256((size_t)n * sizeof(float)) +
            align256(kRedMaxBlocks * sizeof(double));
+}
+
+// Phi^T g by the pairwise kernel with the roles exchanged: the data points are the
+// weighted set and the hinges the lanes; S ranges of points give S partial rows.
+static int32_t launch_pairwise_wgrad(int dim, const float *hinges, int M, float kappa,
+                                     float gscale, const float *x, int64_t n, const float *gw,
+                                     float *part, int S, hipStream_t st) {
+    RbfArgs a;
+    a.hinges = x;
+    a.weights = gw;
+    a.M = (int)n;
+    a.bias = nullptr;
+    a.kappa = kappa;
+    a.gscale = gscale;
+    a.x_in = hinges;
+    a.n = M;
+    a.s_out = part;
+    a.splits = S;
+    return launch_rbf(dim, kEval, a, st);
 }
 
 size_t bce_ws_bytes(int64_t n) { return align256(kRedMaxBlocks * sizeof(double)); }
@@ -185,16 +216,15 @@ int32_t launch_sum(const float *x, int64_t n, int mode, double scale, float *out
 
 // Backward of the logit: grad_w[0..M) = Phi^T g_eff, grad_w[M] = sum g_eff,
 // grad_x = g (sigma'(s))? grad s.  `ws` holds partial rows, g_eff and reduce parts.
-int32_t launch_logit_bwd(int dim, const float *hinges, const float *weights, int M, float ell,
-                         const float *x, int64_t n, const float *g, const float *s_fwd,
-                         float *grad_w, float *grad_x, float grad_scale, const float *decay_w,
-                         float l2, void *ws, hipStream_t st) {
+int32_t launch_logit_bwd(int dim, const float *hinges, const float *weights, int M,
+                         const int *grid, float ell, const float *x, int64_t n, const float *g,
+                         const float *s_fwd, float *grad_w, float *grad_x, float grad_scale,
+                         const float *decay_w, float l2, void *ws, hipStream_t st) {
     float kappa, gscale;
     derive_scales(ell, kappa, gscale);
-    const int S = bwd_splits(dim, M, n);
     char *p = (char *)ws;
     float *part = (float *)p;
-    p += align256((size_t)S * M * sizeof(float));
+    p += align256(bwd_rows(dim, M, n) * M * sizeof(float));
     float *geff = (float *)p;
     p += align256((size_t)n * sizeof(float));
     double *rparts = (double *)p;
@@ -207,22 +237,17 @@ int32_t launch_logit_bwd(int dim, const float *hinges, const float *weights, int
         gw = geff;
     }
     if (grad_w) {
-        RbfArgs a;
-        a.hinges = x;       // data points are the weighted set ...
-        a.weights = gw;     // ... weighted by the upstream gradient
-        a.M = (int)n;
-        a.bias = nullptr;
-        a.kappa = kappa;
-        a.gscale = gscale;
-        a.x_in = hinges;    // hinges are the lanes
-        a.n = M;
-        a.s_out = part;
-        a.splits = S;
-        if (int32_t e = launch_rbf(dim, kEval, a, st)) return e;
-        hipLaunchKernelGGL(k_sum_rows, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, part, S,
+        int S = 0;
+        int32_t e = launch_grid_wgrad(dim, hinges, M, grid, kappa, x, n, gw, part, &S, st);
+        if (e == PDMP_EUNSUPPORTED) {
+            S = bwd_splits(dim, M, n);
+            e = launch_pairwise_wgrad(dim, hinges, M, kappa, gscale, x, n, gw, part, S, st);
+        }
+        if (e) return e;
+        hipLaunchKernelGGL(k_sum_rows, dim3((unsigned)((M + 63) / 64)), dim3(256), 0, st, part, S,
                            (int64_t)M, (double)grad_scale, decay_w, l2, grad_w);
-        if (int32_t e = check_launch("k_sum_rows")) return e;
-        if (int32_t e = launch_sum(gw, n, 0, (double)grad_scale, grad_w + M, rparts, st)) return e;
+        if (int32_t e2 = check_launch("k_sum_rows")) return e2;
+        if (int32_t e2 = launch_sum(gw, n, 0, (double)grad_scale, grad_w + M, rparts, st)) return e2;
     }
     if (grad_x) {
         RbfArgs a;
@@ -304,7 +329,7 @@ int32_t launch_fit(int dim, const float *hinges, int M, const int *grid, float e
         }
         if (int32_t e = check_launch("fit step")) return e;
         // grad = Phi^T g + l2 w, grad_beta = sum g  (g already holds r_i / n)
-        if (int32_t e = launch_logit_bwd(dim, hinges, wb, M, ell, pts, n, g, nullptr, grad,
+        if (int32_t e = launch_logit_bwd(dim, hinges, wb, M, grid, ell, pts, n, g, nullptr, grad,
                                          nullptr, 1.0f, nullptr, 0.0f, bwd_ws, st))
             return e;
         if (o.optimizer == 0) {

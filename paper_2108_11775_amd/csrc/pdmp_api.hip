@@ -290,9 +290,9 @@ int32_t pdmp_occupancy_bwd(const pdmp_occupancy *occ, const float *x, int64_t n,
         set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
         return PDMP_ENOMEM;
     }
-    return launch_logit_bwd(occ->dim, occ->hinges, occ->weights, occ->n_hinges, occ->lengthscale,
-                            x, n, g, s_fwd, grad_w, grad_x, 1.0f, nullptr, 0.0f, ws,
-                            (hipStream_t)stream);
+    return launch_logit_bwd(occ->dim, occ->hinges, occ->weights, occ->n_hinges,
+                            has_grid(occ) ? occ->grid : nullptr, occ->lengthscale, x, n, g, s_fwd,
+                            grad_w, grad_x, 1.0f, nullptr, 0.0f, ws, (hipStream_t)stream);
 }
 
 int32_t pdmp_bce_logits(const float *s, const uint8_t *y, int64_t n, float *loss, float *g_s,

@@ -133,10 +133,16 @@ int32_t launch_fk_points(const pdmp_arm &arm, const float *q, int64_t n, float *
 size_t bwd_ws_bytes(int dim, int M, int64_t n);
 size_t bce_ws_bytes(int64_t n);
 size_t fit_ws_bytes(int dim, int M, int64_t n);
-int32_t launch_logit_bwd(int dim, const float *hinges, const float *weights, int M, float ell,
-                         const float *x, int64_t n, const float *g, const float *s_fwd,
-                         float *grad_w, float *grad_x, float grad_scale, const float *decay_w,
-                         float l2, void *ws, hipStream_t st);
+// Backward of the logit; grad_w goes through the grid kernels when `grid` fits them.
+int32_t launch_logit_bwd(int dim, const float *hinges, const float *weights, int M,
+                         const int *grid, float ell, const float *x, int64_t n, const float *g,
+                         const float *s_fwd, float *grad_w, float *grad_x, float grad_scale,
+                         const float *decay_w, float l2, void *ws, hipStream_t st);
+// Partial rows of Phi^T g on a hinge grid (PDMP_EUNSUPPORTED if it does not fit).
+int32_t launch_grid_wgrad(int dim, const float *hinges, int M, const int *grid, float kappa,
+                          const float *x, int64_t n, const float *g, float *part, int *rows,
+                          hipStream_t st);
+size_t wgrad_rows_max(int64_t n);
 int32_t launch_bce(const float *s, const uint8_t *y, int64_t n, float *loss, float *g_out,
                    double *parts, hipStream_t st);
 int32_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, int64_t n_decay,

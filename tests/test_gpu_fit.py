@@ -24,15 +24,16 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 
 
-def _bwd_case(h, wb, ell, x, g, chain):
-    go, oo = gpu_occ(h, wb, ell), oracle_occ(h, wb, ell)
+def _bwd_case(h, wb, ell, x, g, chain, grid=None, want_x=True):
+    go, oo = gpu_occ(h, wb, ell, grid=grid), oracle_occ(h, wb, ell)
     M = h.shape[1]
     s_fwd = None
     if chain:
         _, s_d = P.occupancy_eval(go, dev(x))
         s_fwd = s_d
-    gw, gx = P.occupancy_bwd(go, dev(x), dev(g), s_fwd=s_fwd)
-    gw, gx = host(gw), host(gx)
+    gw, gx = P.occupancy_bwd(go, dev(x), dev(g), s_fwd=s_fwd, want_x=want_x)
+    gw = host(gw)
+    gx = host(gx) if want_x else None
     s_r, c_r, _ = O.occ_eval(oo, x)
     sp = c_r * (1 - c_r) if chain else np.ones_like(c_r)
     geff = g.astype(np.float64) * sp
@@ -48,27 +49,71 @@ def _bwd_case(h, wb, ell, x, g, chain):
     else:
         scale_x = np.abs(g) * graw
     assert np.all(np.abs(gw - ref_w) <= TOL * scale_w + 1e-30), np.max(np.abs(gw - ref_w) / scale_w)
+    if not want_x:
+        return gw, None
     err_x = np.abs(gx - ref_x).max(axis=0)
     assert np.all(err_x <= TOL * scale_x + 1e-30), np.max(err_x / scale_x)
     return gw, gx
 
 
+@pytest.mark.parametrize("on_grid", [False, True])
 @pytest.mark.parametrize("chain", [False, True])
-def test_backward_2d(chain):
+def test_backward_2d(chain, on_grid):
     require_gpu()
     sc = ws_scene(K.C1)
     x = I.uniform_points(1, K.STREAM_EVAL, 2, 3001, -10, 10)
     g = I.rng(1, 9).normal(size=3001).astype(np.float32)
-    _bwd_case(sc["h"], sc["wb"], sc["ell"], x, g, chain)
+    grid = (K.C1.grid, K.C1.grid) if on_grid else None
+    _bwd_case(sc["h"], sc["wb"], sc["ell"], x, g, chain, grid=grid)
 
 
+@pytest.mark.parametrize("on_grid", [False, True])
 @pytest.mark.parametrize("chain", [False, True])
-def test_backward_3d(chain):
+def test_backward_3d(chain, on_grid):
     require_gpu()
     sc = arm_scene()
     x = I.uniform_points(4, K.STREAM_EVAL, 3, 5001, -1, 1)
     g = I.rng(4, 9).normal(size=5001).astype(np.float32)
-    _bwd_case(sc["h"], sc["wb"], sc["ell"], x, g, chain)
+    grid = (K.C3.grid,) * 3 if on_grid else None
+    _bwd_case(sc["h"], sc["wb"], sc["ell"], x, g, chain, grid=grid)
+
+
+def _ragged_grid(shape, seed):
+    """Hinges on a tensor grid with unequal, unevenly spaced axes (x fastest)."""
+    rng = np.random.default_rng(seed)
+    axes = [np.sort(rng.uniform(-1.5, 1.5, k)) for k in shape]
+    j = np.arange(int(np.prod(shape)))
+    idx, stride = [], 1
+    for k in shape:
+        idx.append((j // stride) % k)
+        stride *= k
+    h = np.stack([axes[d][idx[d]] for d in range(len(shape))]).astype(np.float32)
+    wb = rng.normal(0, 1.0, h.shape[1] + 1).astype(np.float32)
+    return h, wb, rng
+
+
+# grids that fill and that pad the MFMA tiles; n spans one partial round, several
+# rounds per block (n > 512 * 256) and ragged tails
+@pytest.mark.parametrize("shape,n", [((64, 64), 140001), ((37, 50), 70001), ((5, 3), 1),
+                                     ((33, 20), 257), ((16, 16, 16), 140001), ((5, 7, 3), 255),
+                                     ((16, 9, 11), 3001), ((1, 16, 16), 512)])
+def test_grid_weight_gradient_shapes(shape, n):
+    require_gpu()
+    h, wb, rng = _ragged_grid(shape, 31 * n + len(shape))
+    x = rng.uniform(-1.8, 1.8, (len(shape), n)).astype(np.float32)
+    g = rng.normal(size=n).astype(np.float32)
+    _bwd_case(h, wb, 0.3, x, g, False, grid=shape, want_x=False)
+
+
+def test_grid_weight_gradient_deterministic():
+    require_gpu()
+    sc = arm_scene()
+    x = I.uniform_points(4, K.STREAM_EVAL, 3, 200003, -1, 1)
+    g = I.rng(4, 13).normal(size=200003).astype(np.float32)
+    go = gpu_occ(sc["h"], sc["wb"], sc["ell"], grid=(16, 16, 16))
+    a, _ = P.occupancy_bwd(go, dev(x), dev(g), want_x=False)
+    b, _ = P.occupancy_bwd(go, dev(x), dev(g), want_x=False)
+    assert np.array_equal(host(a), host(b))
 
 
 def test_backward_against_finite_differences():
@@ -102,7 +147,8 @@ def test_backward_against_finite_differences():
         assert abs(gw[j] - fd) <= 1e-4 * max(abs(fd), 1e-3)
 
 
-def test_backward_full_size_sampled():
+@pytest.mark.parametrize("on_grid", [False, True])
+def test_backward_full_size_sampled(on_grid):
     """d/dw at the 2^20-point, 4096-hinge size of the 3-D fit, on sampled hinges."""
     require_gpu()
     sc = arm_scene()
@@ -110,7 +156,8 @@ def test_backward_full_size_sampled():
     n = K.C4.n_points
     x = I.uniform_points(K.C4.cfg_id, K.STREAM_FIT, 3, n, -1, 1)
     g = (I.rng(4, 11).normal(size=n) / n).astype(np.float32)
-    gw, _ = P.occupancy_bwd(gpu_occ(h, wb, ell), dev(x), dev(g), want_x=False)
+    grid = (16, 16, 16) if on_grid else None
+    gw, _ = P.occupancy_bwd(gpu_occ(h, wb, ell, grid=grid), dev(x), dev(g), want_x=False)
     gw = host(gw)
     js = np.r_[0, 1, 777, 2048, 4095]
     ref, scale = O.logit_bwd_w_subset(h, ell, x, g, js)
@@ -155,14 +202,16 @@ def _fit_problem_2d():
     return cfg, sc, pts, y
 
 
-def test_fit_one_step_from_identical_state():
+@pytest.mark.parametrize("on_grid", [False, True])
+def test_fit_one_step_from_identical_state(on_grid):
     require_gpu()
     cfg, sc, pts, y = _fit_problem_2d()
     wb = sc["wb"]
     M = wb.size - 1
     w_d = dev(wb.copy())
     loss = P.fit_occupancy(dev(sc["h"]), sc["ell"], w_d, dev(pts), dev(y), 1, cfg.fit_lr,
-                           cfg.fit_l2, "gd", lr_bias=cfg.fit_lr_bias)
+                           cfg.fit_l2, "gd", lr_bias=cfg.fit_lr_bias,
+                           grid=(cfg.grid, cfg.grid) if on_grid else None)
     L, g, gsc = O.fit_loss_grad(sc["h"], sc["ell"], wb, pts, y, cfg.fit_l2)
     ref = wb.astype(np.float64).copy()
     ref[:M] -= cfg.fit_lr * g[:M]
@@ -175,7 +224,8 @@ def test_fit_one_step_from_identical_state():
     assert abs(host(loss)[0] - L) <= 1e-6 * L
 
 
-def test_fit_adam_one_step_from_identical_state():
+@pytest.mark.parametrize("on_grid", [False, True])
+def test_fit_adam_one_step_from_identical_state(on_grid):
     require_gpu()
     sc = arm_scene()
     c4 = K.C4
@@ -189,7 +239,7 @@ def test_fit_adam_one_step_from_identical_state():
     v0 = (rng.uniform(size=M + 1) * 1e-5).astype(np.float32)
     w_d, m_d, v_d = dev(wb.copy()), dev(m0), dev(v0)
     P.fit_occupancy(dev(sc["h"]), sc["ell"], w_d, dev(pts), dev(y), 1, c4.lr, c4.l2, "adam",
-                    adam_m=m_d, adam_v=v_d, t0=9)
+                    adam_m=m_d, adam_v=v_d, t0=9, grid=(16, 16, 16) if on_grid else None)
     ref, mr, vr, _ = O.fit(sc["h"], sc["ell"], pts, y, 1, 1, c4.lr, c4.l2, wb0=wb, m=m0, v=v0, t0=9)
     # Adam's step is lr * m_hat / (sqrt(v_hat) + eps): with gradients near zero the
     # ratio is ill-conditioned, so compare the moments tightly and the step to lr.
