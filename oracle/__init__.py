@@ -83,6 +83,14 @@ def _load():
         "orc_amortised_morph": (None, [C.c_int, _ip, _dp, C.c_int, C.c_int, _dp, C.c_int, _dp,
                                        _dp, C.c_double, C.c_double, _dp, _i64, C.c_int,
                                        C.c_double, C.c_double, _dp, _u8p, _dp]),
+        "orc_tanh_nparams": (C.c_int64, [C.c_int, C.c_int, C.c_int]),
+        "orc_tanh_eval": (None, [C.c_int, C.c_int, C.c_int, _dp, _dp, _i64, _dp, _dp, _dp]),
+        "orc_tanh_grad": (None, [C.c_int, C.c_int, C.c_int, _dp, _dp, _i64, _dp, _dp, _dp, _dp,
+                                 _dp]),
+        "orc_tanh_morph": (None, [C.c_int, C.c_int, C.c_int, _dp, _dp, _i64, C.c_int,
+                                  C.c_double, _dp, _dp]),
+        "orc_tanh_loss_grad": (C.c_double, [C.c_int, C.c_int, C.c_int, _dp, _dp, _u8p, _i64,
+                                            C.c_double, _dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -449,3 +457,89 @@ def amortised_morph(widths, P, arm: Arm, occ: Occupancy, q, T, eta, thresh=0.5):
                                 _P(arm.dh()), M, h, w, beta, ell, _P(q), n, int(T),
                                 float(eta), float(thresh), _P(out), _P(flag, _u8p), _P(maxc))
     return out, flag, maxc
+
+
+# ---------------------------------------------- the paper's tanh network ---
+
+@dataclass
+class TanhNet:
+    """The paper's occupancy network (Sec. 3.1): L hidden tanh layers of width H,
+    sigmoid output.  P is flat: W_l [H][n_l], b_l [H] for each layer, then v [H], b_o."""
+    dim: int
+    H: int
+    L: int
+    P: np.ndarray
+
+    def args(self):
+        self._p64 = _d(self.P)
+        assert self._p64.size == tanh_nparams(self.dim, self.H, self.L)
+        return (int(self.dim), int(self.H), int(self.L), _P(self._p64))
+
+
+def tanh_nparams(dim: int, H: int, L: int) -> int:
+    return int(_load().orc_tanh_nparams(int(dim), int(H), int(L)))
+
+
+def tanh_layers(net: TanhNet):
+    """[(W_l, b_l)] for the hidden layers and (v, b_o), as views of net.P."""
+    P = np.asarray(net.P)
+    out, o, nin = [], 0, net.dim
+    for _ in range(net.L):
+        W = P[o:o + net.H * nin].reshape(net.H, nin)
+        o += net.H * nin
+        out.append((W, P[o:o + net.H]))
+        o += net.H
+        nin = net.H
+    return out, (P[o:o + net.H], P[o + net.H])
+
+
+def tanh_eval(net: TanhNet, x):
+    """(s, c, S_abs) at [dim][n] points."""
+    x = _d(x)
+    n = x.shape[1]
+    s, c, sa = _zeros(n), _zeros(n), _zeros(n)
+    _load().orc_tanh_eval(*net.args(), _P(x), n, _P(s), _P(c), _P(sa))
+    return s, c, sa
+
+
+def tanh_grad(net: TanhNet, x):
+    """(s, grad s, grad c, S_abs, G_abs) at [dim][n] points (chain rule, reverse order)."""
+    x = _d(x)
+    dim, n = x.shape
+    s, gs, gc, sa, ga = _zeros(n), _zeros(dim, n), _zeros(dim, n), _zeros(n), _zeros(n)
+    _load().orc_tanh_grad(*net.args(), _P(x), n, _P(s), _P(gs), _P(gc), _P(sa), _P(ga))
+    return s, gs, gc, sa, ga
+
+
+def tanh_morph(net: TanhNet, x, T: int, eta: float, diag: bool = False):
+    """Explicit-Euler morph (Eq. 1) with the network's occupancy; with diag also the
+    per-sample product of |I - eta Hc|_2 along the path."""
+    x = _d(x)
+    dim, n = x.shape
+    out = _zeros(dim, n)
+    amp = _zeros(n) if diag else None
+    _load().orc_tanh_morph(*net.args(), _P(x), n, int(T), float(eta), _P(out), _P(amp))
+    return (out, amp) if diag else out
+
+
+def tanh_loss_grad(net: TanhNet, pts, y, l2: float):
+    """(loss, grad [nparams]) of mean BCE + (l2/2) |weights|^2 (biases not decayed)."""
+    pts = _d(pts)
+    y = np.ascontiguousarray(y, dtype=np.uint8)
+    g = _zeros(tanh_nparams(net.dim, net.H, net.L))
+    L = _load().orc_tanh_loss_grad(*net.args(), _P(pts), _P(y, _u8p), pts.shape[1], float(l2),
+                                   _P(g))
+    return L, g
+
+
+def tanh_fit(net: TanhNet, pts, y, steps: int, lr: float, l2: float, b1=0.9, b2=0.999,
+             eps=1e-8):
+    """Full-batch Adam on the BCE objective (Sec. 3.1); returns (P, loss per step)."""
+    P = _d(net.P).copy()
+    m, v = np.zeros_like(P), np.zeros_like(P)
+    losses = np.zeros(steps)
+    cur = TanhNet(net.dim, net.H, net.L, P)
+    for t in range(steps):
+        losses[t], g = tanh_loss_grad(cur, pts, y, l2)
+        adam_step(P, g, m, v, t + 1, lr, b1, b2, eps)
+    return P, losses

@@ -968,3 +968,284 @@ void orc_amortised_morph(int L, const int *widths, const double *P, int ndof, in
     }
     free(qh);
 }
+
+/* ------------------------------------------------------------------------- */
+/* The paper's occupancy network (Sec. 3.1): a fully connected network with    */
+/* tanh activations between hidden layers and a sigmoid at the output,         */
+/* c(x) = sigma(s(x)), trained with binary cross-entropy.                      */
+/*                                                                             */
+/* L hidden layers of width H.  Flat parameters: for l = 0..L-1 the matrix     */
+/* W_l [H][n_l] (row-major; n_0 = dim, n_l = H after) and the bias b_l [H];    */
+/* then the output weights v [H] and the output bias b_o:                      */
+/*   a_0 = x,  a_{l+1} = tanh(W_l a_l + b_l),  s = v . a_L + b_o.              */
+/* Reverse mode (chain rule) for the input gradient:                           */
+/*   d_l = 1 - a_l^2 (l >= 1),  e_L = v * d_L,                                 */
+/*   e_l = d_l * (W_l^T e_{l+1})  (l = L-1..1),  grad_x s = W_0^T e_1.         */
+/* ------------------------------------------------------------------------- */
+
+#define ORC_TANH_MAXH 256
+#define ORC_TANH_MAXL 6
+
+int64_t orc_tanh_nparams(int dim, int H, int L) {
+    return (int64_t)H * dim + H + (int64_t)(L - 1) * (H * H + H) + H + 1;
+}
+
+typedef struct {
+    double a[ORC_TANH_MAXL + 1][ORC_TANH_MAXH];  /* a[l] for l >= 1 (a[0] unused) */
+    double zs[ORC_TANH_MAXL + 1][ORC_TANH_MAXH]; /* error scale of each pre-activation */
+    double s, sabs;
+} tanh_fwd;
+
+/* Forward pass.  Error scales: a pre-activation z = b + sum W a' gets
+ * |b| + sum |W| A', where A' = |a'| + (1 - a'^2) Z' is the scale of an input a'
+ * = tanh(z') including the rounding carried from z' (scale Z'); for the inputs
+ * A' = |x|.  sabs is the same sum for s. */
+static void tanh_forward(int dim, int H, int L, const double *P, const double *x, tanh_fwd *f) {
+    const double *p = P;
+    double in[ORC_TANH_MAXH], inabs[ORC_TANH_MAXH];
+    int nin = dim;
+    for (int k = 0; k < dim; ++k) {
+        in[k] = x[k];
+        inabs[k] = fabs(x[k]);
+    }
+    for (int l = 0; l < L; ++l) {
+        const double *W = p, *b = p + (int64_t)H * nin;
+        p = b + H;
+        for (int u = 0; u < H; ++u) {
+            double z = b[u], za = fabs(b[u]);
+            for (int k = 0; k < nin; ++k) {
+                z += W[(int64_t)u * nin + k] * in[k];
+                za += fabs(W[(int64_t)u * nin + k]) * inabs[k];
+            }
+            f->a[l + 1][u] = tanh(z);
+            f->zs[l + 1][u] = za;
+        }
+        for (int u = 0; u < H; ++u) {
+            double a = f->a[l + 1][u];
+            in[u] = a;
+            inabs[u] = fabs(a) + (1.0 - a * a) * f->zs[l + 1][u];
+        }
+        nin = H;
+    }
+    const double *v = p, bo = p[H];
+    double s = bo, sa = fabs(bo);
+    for (int u = 0; u < H; ++u) {
+        s += v[u] * in[u];
+        sa += fabs(v[u]) * inabs[u];
+    }
+    f->s = s;
+    f->sabs = sa;
+}
+
+/* Input gradient of s by the chain rule (reverse order).  gabs (nullable) gets
+ * the error scale of the largest component: the same recursion on absolute
+ * values, each layer's derivative d widened by (1 + 2|a| Z) for the rounding of
+ * the forward value it is computed from. */
+static void tanh_backward_x(int dim, int H, int L, const double *P, const tanh_fwd *f,
+                            double *g, double *gabs) {
+    int64_t off[ORC_TANH_MAXL + 1];
+    int64_t o = 0;
+    for (int l = 0; l < L; ++l) {
+        off[l] = o;
+        int nin = l == 0 ? dim : H;
+        o += (int64_t)H * nin + H;
+    }
+    const double *v = P + o;
+    double e[ORC_TANH_MAXH], ea[ORC_TANH_MAXH], t[ORC_TANH_MAXH], ta[ORC_TANH_MAXH];
+    for (int u = 0; u < H; ++u) {
+        double a = f->a[L][u], d = 1.0 - a * a;
+        e[u] = v[u] * d;
+        ea[u] = fabs(v[u]) * d * (1.0 + 2.0 * fabs(a) * f->zs[L][u]);
+    }
+    for (int l = L - 1; l >= 1; --l) {
+        const double *W = P + off[l]; /* W_l: [H][H], maps a_l -> z_{l+1} */
+        for (int i = 0; i < H; ++i) {
+            double acc = 0.0, acca = 0.0;
+            for (int u = 0; u < H; ++u) {
+                acc += W[(int64_t)u * H + i] * e[u];
+                acca += fabs(W[(int64_t)u * H + i]) * ea[u];
+            }
+            double a = f->a[l][i], d = 1.0 - a * a;
+            t[i] = d * acc;
+            ta[i] = d * (1.0 + 2.0 * fabs(a) * f->zs[l][i]) * acca;
+        }
+        for (int i = 0; i < H; ++i) {
+            e[i] = t[i];
+            ea[i] = ta[i];
+        }
+    }
+    const double *W0 = P; /* [H][dim] */
+    double gm = 0.0;
+    for (int k = 0; k < dim; ++k) {
+        double acc = 0.0, acca = 0.0;
+        for (int u = 0; u < H; ++u) {
+            acc += W0[(int64_t)u * dim + k] * e[u];
+            acca += fabs(W0[(int64_t)u * dim + k]) * ea[u];
+        }
+        g[k] = acc;
+        if (acca > gm) gm = acca;
+    }
+    if (gabs) *gabs = gm;
+}
+
+/* s, c = sigma(s) and the error scale of s at each point; x is [dim][n]. */
+void orc_tanh_eval(int dim, int H, int L, const double *P, const double *x, int64_t n, double *s,
+                   double *c, double *sabs) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double xi[ORC_MAX_DIM];
+        for (int k = 0; k < dim; ++k) xi[k] = x[(int64_t)k * n + i];
+        tanh_fwd f;
+        tanh_forward(dim, H, L, P, xi, &f);
+        if (s) s[i] = f.s;
+        if (c) c[i] = sigmoid(f.s);
+        if (sabs) sabs[i] = f.sabs;
+    }
+}
+
+/* grad_x s ([dim][n]) and grad_x c = sigma'(s) grad_x s, with the error scales of
+ * s and of grad_x s. */
+void orc_tanh_grad(int dim, int H, int L, const double *P, const double *x, int64_t n, double *s,
+                   double *gs, double *gc, double *sabs, double *gabs) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double xi[ORC_MAX_DIM], g[ORC_MAX_DIM], ga;
+        for (int k = 0; k < dim; ++k) xi[k] = x[(int64_t)k * n + i];
+        tanh_fwd f;
+        tanh_forward(dim, H, L, P, xi, &f);
+        tanh_backward_x(dim, H, L, P, &f, g, &ga);
+        double c = sigmoid(f.s), sp = c * (1.0 - c);
+        for (int k = 0; k < dim; ++k) {
+            if (gs) gs[(int64_t)k * n + i] = g[k];
+            if (gc) gc[(int64_t)k * n + i] = sp * g[k];
+        }
+        if (s) s[i] = f.s;
+        if (sabs) sabs[i] = f.sabs;
+        if (gabs) gabs[i] = ga;
+    }
+}
+
+static void tanh_grad_c(int dim, int H, int L, const double *P, const double *x, double *gc) {
+    tanh_fwd f;
+    double g[ORC_MAX_DIM];
+    tanh_forward(dim, H, L, P, x, &f);
+    tanh_backward_x(dim, H, L, P, &f, g, NULL);
+    double c = sigmoid(f.s), sp = c * (1.0 - c);
+    for (int k = 0; k < dim; ++k) gc[k] = sp * g[k];
+}
+
+/* Plain morph with the network's occupancy (Eq. 1 with explicit Euler steps):
+ * x_{k+1} = x_k - eta grad c(x_k), T steps.  amp (nullable) gets the product over
+ * steps of |I - eta Hc|_2, with Hc from central differences of grad c (FP64,
+ * step 1e-5 max(1, |x|)); it only sizes the FP32 tolerance. */
+void orc_tanh_morph(int dim, int H, int L, const double *P, const double *xin, int64_t n, int T,
+                    double eta, double *xout, double *amp) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double x[ORC_MAX_DIM], g[ORC_MAX_DIM];
+        for (int k = 0; k < dim; ++k) x[k] = xin[(int64_t)k * n + i];
+        double A = 1.0;
+        for (int t = 0; t < T; ++t) {
+            if (amp) {
+                double Hm[ORC_MAX_DIM * ORC_MAX_DIM];
+                for (int j = 0; j < dim; ++j) {
+                    double xp[ORC_MAX_DIM], xm[ORC_MAX_DIM], gp[ORC_MAX_DIM], gm[ORC_MAX_DIM];
+                    double hstep = 1e-5 * (fabs(x[j]) > 1.0 ? fabs(x[j]) : 1.0);
+                    for (int k = 0; k < dim; ++k) xp[k] = xm[k] = x[k];
+                    xp[j] += hstep;
+                    xm[j] -= hstep;
+                    tanh_grad_c(dim, H, L, P, xp, gp);
+                    tanh_grad_c(dim, H, L, P, xm, gm);
+                    for (int k = 0; k < dim; ++k) Hm[k * dim + j] = (gp[k] - gm[k]) / (2.0 * hstep);
+                }
+                double nm, det, hn;
+                step_jac_stats(dim, Hm, eta, &nm, &det, &hn);
+                A *= nm;
+            }
+            tanh_grad_c(dim, H, L, P, x, g);
+            for (int k = 0; k < dim; ++k) x[k] = x[k] - eta * g[k];
+        }
+        for (int k = 0; k < dim; ++k) xout[(int64_t)k * n + i] = x[k];
+        if (amp) amp[i] = A;
+    }
+}
+
+/* Fit objective of the network (Sec. 3.1): mean BCE of sigma(s(x_i)) against
+ * y_i plus (l2/2) times the squared weights (the matrices W_l and v, not the
+ * biases).  Returns the loss; grad ([nparams]) gets its gradient by the chain
+ * rule through every layer (reverse order). */
+double orc_tanh_loss_grad(int dim, int H, int L, const double *P, const double *pts,
+                          const uint8_t *y, int64_t n, double l2, double *grad) {
+    const int64_t np = orc_tanh_nparams(dim, H, L);
+    int64_t off[ORC_TANH_MAXL + 1];
+    int64_t o = 0;
+    for (int l = 0; l < L; ++l) {
+        off[l] = o;
+        o += (int64_t)H * (l == 0 ? dim : H) + H;
+    }
+    off[L] = o; /* v, then b_o */
+    int nt = orc_num_threads();
+    double *acc = (double *)calloc((size_t)nt * (size_t)np, sizeof(double));
+    double *lsum = (double *)calloc((size_t)nt, sizeof(double));
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *G = acc + (int64_t)tid * np;
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double xi[ORC_MAX_DIM];
+            for (int k = 0; k < dim; ++k) xi[k] = pts[(int64_t)k * n + i];
+            tanh_fwd f;
+            tanh_forward(dim, H, L, P, xi, &f);
+            double yi = (double)y[i];
+            lsum[tid] += bce_logit(f.s, yi);
+            double r = sigmoid(f.s) - yi; /* dBCE/ds */
+            const double *v = P + off[L];
+            for (int u = 0; u < H; ++u) G[off[L] + u] += r * f.a[L][u];
+            G[off[L] + H] += r;
+            double e[ORC_TANH_MAXH], t[ORC_TANH_MAXH];
+            for (int u = 0; u < H; ++u) e[u] = r * v[u] * (1.0 - f.a[L][u] * f.a[L][u]);
+            for (int l = L - 1; l >= 0; --l) {
+                int nin = l == 0 ? dim : H;
+                const double *ain = l == 0 ? xi : f.a[l];
+                double *GW = G + off[l], *Gb = G + off[l] + (int64_t)H * nin;
+                for (int u = 0; u < H; ++u) {
+                    for (int k = 0; k < nin; ++k) GW[(int64_t)u * nin + k] += e[u] * ain[k];
+                    Gb[u] += e[u];
+                }
+                if (l == 0) break;
+                const double *W = P + off[l];
+                for (int k = 0; k < H; ++k) {
+                    double s2 = 0.0;
+                    for (int u = 0; u < H; ++u) s2 += W[(int64_t)u * H + k] * e[u];
+                    t[k] = s2 * (1.0 - f.a[l][k] * f.a[l][k]);
+                }
+                for (int k = 0; k < H; ++k) e[k] = t[k];
+            }
+        }
+    }
+    double loss = 0.0;
+    for (int t = 0; t < nt; ++t) loss += lsum[t];
+    loss /= (double)n;
+    for (int64_t j = 0; j < np; ++j) {
+        double s2 = 0.0;
+        for (int t = 0; t < nt; ++t) s2 += acc[(int64_t)t * np + j];
+        grad[j] = s2 / (double)n;
+    }
+    /* weight decay on the matrices and v */
+    double wsq = 0.0;
+    for (int l = 0; l <= L; ++l) {
+        int64_t cnt = l < L ? (int64_t)H * (l == 0 ? dim : H) : H;
+        for (int64_t j = 0; j < cnt; ++j) {
+            double w = P[off[l] + j];
+            grad[off[l] + j] += l2 * w;
+            wsq += w * w;
+        }
+    }
+    free(acc);
+    free(lsum);
+    return loss + 0.5 * l2 * wsq;
+}

@@ -27,6 +27,7 @@ STREAM_DH = 3
 STREAM_MLP = 4
 STREAM_SHUFFLE = 5
 STREAM_EVAL = 6
+STREAM_TANH = 7
 
 
 @dataclass(frozen=True)
@@ -120,18 +121,38 @@ class Amortised:
     eval_samples: int = 65_536
 
 
+@dataclass(frozen=True)
+class TanhOcc:
+    """The paper's own occupancy (Sec. 3.1): a fully connected network with tanh
+    between hidden layers and a sigmoid output, on the 2-D disc worlds of configs 1
+    and 2 (same scenes, fit points, samples, T and eta as the RBF occupancy)."""
+    name: str = "tanh-occ"
+    hidden: int = 64
+    layers: int = 3
+    lr: float = 1e-2        # full-batch Adam on mean BCE + (l2/2)|weights|^2
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    steps: tuple = (1000, 1500)   # configs 1, 2
+    l2: tuple = (1e-5, 1e-6)
+
+
 C1 = Workspace2D(cfg_id=1, name="ws2d-4096")
 C2 = Workspace2D(cfg_id=2, name="ws2d-1M", n_discs=100, grid=64, lengthscale=0.4,
                  fit_lr=128.0, n_samples=1 << 20, T=50, eta=0.02)
 C3 = Arm7()
 C4 = Fit3D()
 C5 = Amortised()
+TANH = TanhOcc()
 
 CONFIGS = {1: C1, 2: C2, 3: C3, 4: C4, 5: C5}
 
 # Readings of points the paper leaves open (each is listed with its reason in the
 # design notes).  They are frozen here so that every side uses the same ones.
 READINGS = {
+    "tanh_network": "3 hidden tanh layers of 64 on raw coordinates (the paper gives no "
+                    "widths); Glorot init with the first layer divided by the domain "
+                    "half-width; Adam lr 1e-2 on all parameters, L2 on weights only",
     "rbf": "phi_j(x) = exp(-|x-h_j|^2 / (2 l^2))",
     "bias": "scalar beta, unregularised, stored as weights[M]",
     "grid": "linspace(lo, hi, g) per axis, both ends included, x fastest",

@@ -17,11 +17,12 @@ from __future__ import annotations
 import numpy as np
 
 from .configs import (ENTROPY, STREAM_SCENE, STREAM_FIT, STREAM_BASE, STREAM_DH,
-                      STREAM_MLP, STREAM_SHUFFLE, STREAM_EVAL)
+                      STREAM_MLP, STREAM_SHUFFLE, STREAM_EVAL, STREAM_TANH)
 
 __all__ = ["rng", "philox_seed", "discs", "boxes", "hinge_grid", "dh_params",
            "uniform_points", "mlp_init", "STREAM_SCENE", "STREAM_FIT", "STREAM_BASE",
-           "STREAM_DH", "STREAM_MLP", "STREAM_SHUFFLE", "STREAM_EVAL"]
+           "STREAM_DH", "STREAM_MLP", "STREAM_SHUFFLE", "STREAM_EVAL", "STREAM_TANH",
+           "tanh_init"]
 
 
 def rng(cfg_id: int, stream: int) -> np.random.Generator:
@@ -118,3 +119,27 @@ def mlp_init(cfg_id: int, widths, zero_last: bool = True):
             b[:] = 0
         layers.append((np.ascontiguousarray(w), b))
     return layers
+
+
+def tanh_init(cfg_id: int, dim: int, H: int, L: int, in_scale: float) -> np.ndarray:
+    """Flat float32 parameters of a tanh occupancy network (L hidden layers of width H).
+
+    Layout: W_l [H][n_l], b_l [H] per hidden layer (n_0 = dim), then v [H], b_o.
+    Weights ~ U(+-sqrt(6 / (fan_in + fan_out))) (Glorot), the first layer's divided
+    by in_scale (the half-width of the domain, so W_0 x is O(1)); first-layer
+    biases ~ U(-1, 1), the others zero.
+    """
+    g = rng(cfg_id, STREAM_TANH)
+    parts = []
+    nin = dim
+    for li in range(L):
+        bound = np.sqrt(6.0 / (nin + H))
+        w = g.uniform(-bound, bound, size=(H, nin))
+        if li == 0:
+            w /= in_scale
+        b = g.uniform(-1.0, 1.0, size=H) if li == 0 else np.zeros(H)
+        parts += [w.ravel(), b]
+        nin = H
+    bound = np.sqrt(6.0 / (H + 1))
+    parts += [g.uniform(-bound, bound, size=H), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
