@@ -319,6 +319,43 @@ def arm_morph(P, I, K, torch, world):
     return res
 
 
+def tanh_morph(P, I, K, torch, dev):
+    """The morph of the large 2-D workload with the paper's own occupancy, the tanh
+    network of Sec. 3.1 (weights fitted by the FP64 reference fit in tests/golden/)."""
+    import numpy as np
+    cfg, tc = K.C2, K.TANH
+    params = np.load(os.path.join(ROOT, "tests", "golden", "tanh_c2.npy")).astype(np.float32)
+    net = P.TanhNet(2, tc.hidden, tc.layers, torch.from_numpy(params).to(dev))
+    N = cfg.n_samples
+    x0 = P.uniform_samples(I.philox_seed(cfg.cfg_id), 0, [cfg.lo] * 2, [cfg.hi] * 2, N)
+    x1 = torch.empty_like(x0)
+    P.tanh_morph_samples(net, x0, cfg.T, cfg.eta, out=x1)
+    reps = 3
+    t = Timer(torch)
+    with t:
+        for _ in range(reps):
+            P.tanh_morph_samples(net, x0, cfg.T, cfg.eta, out=x1)
+    ms = t.ms() / reps
+    dc, dr = I.discs(cfg.cfg_id, cfg.n_discs, cfg.lo, cfg.hi, cfg.r_min, cfg.r_max)
+    dc_d, dr_d = torch.from_numpy(dc).to(dev), torch.from_numpy(dr).to(dev)
+    _, h0 = P.label_points_discs(dc_d, dr_d, x0, count=True)
+    _, h1 = P.label_points_discs(dc_d, dr_d, x1, count=True)
+    H, L = tc.hidden, tc.layers
+    # hidden-to-hidden products forward (W a) and backward (W^T e) on MFMA:
+    # 4 (L-1) H^2 flops per sample and step
+    flops = N * cfg.T * 4.0 * (L - 1) * H * H
+    ach = flops / (ms * 1e-3) / 1e12
+    return {"workload": f"plain morph 2-D large with the paper's tanh occupancy (2-{H}x{L}-1, "
+                        f"sigmoid): 1,048,576 samples, T={cfg.T}, eta={cfg.eta}, 100 discs",
+            "morph_ms": ms, "samples_per_s": N / (ms * 1e-3),
+            "collision_free_before": 1 - h0.item() / N,
+            "collision_free_after": 1 - h1.item() / N,
+            "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA / 1e12,
+                         "unit": "TFLOP/s", "frac": ach * 1e12 / PEAK_FP32_MFMA,
+                         "kernel": f"k_tanh_net<2,4,{L},kMorph>",
+                         "work": "4*(L-1)*H^2 FP32 MFMA flops per sample-step"}}
+
+
 def amortised(args, P, I, K, torch, world):
     from paper_2108_11775_amd import amortise
     c3, c5 = K.C3, K.C5
@@ -441,6 +478,8 @@ def main():
         try:
             wl["ws2d_small"] = small_2d(P, I, K, torch, dev)
             log("small 2-D done")
+            wl["tanh_ws2d"] = tanh_morph(P, I, K, torch, dev)
+            log(f"tanh-network morph: {wl['tanh_ws2d']['morph_ms']:.2f} ms")
             world = arm_world(P, I, K, torch, dev)
             wl["fit3d"] = world["fit"]
             log(f"3-D fit: {world['fit']['ms_total']:.0f} ms")

@@ -267,6 +267,35 @@ int32_t pdmp_amortised_morph(const pdmp_mlp *mlp, const pdmp_occupancy *occ, con
                              float thresh, uint8_t *flag, uint32_t *n_fallback, void *ws,
                              size_t ws_bytes, void *stream);
 
+/* ---- the paper's occupancy network (Sec. 3.1): a fully connected network with
+ * tanh activations between hidden layers and a sigmoid output, c(x) = sigma(s(x)),
+ *   a_1 = tanh(W_0 x + b_0),  a_{l+1} = tanh(W_l a_l + b_l),  s = v . a_L + b_o,
+ * and its input gradient by the chain rule.  params (device, FP32, read-only) is
+ * flat: for l = 0..n_hidden-1 the matrix W_l [hidden][n_l] (row-major; n_0 = dim,
+ * n_l = hidden after) and b_l [hidden]; then v [hidden] and b_o.  Supported:
+ * dim 2 or 3, 1 <= hidden <= 64, 1 <= n_hidden <= 4 (else PDMP_EINVAL). */
+typedef struct {
+    int32_t dim;
+    int32_t hidden;
+    int32_t n_hidden;
+    const float *params;
+} pdmp_tanh_net;
+
+/* Length of params: hidden*dim + hidden + (n_hidden-1)(hidden^2 + hidden) + hidden + 1,
+ * or -1 for an unsupported shape. */
+int64_t pdmp_tanh_num_params(const pdmp_tanh_net *net);
+/* c_out (nullable) [n] = c(x_i), s_out (nullable) [n] = s(x_i); x [dim][n]. */
+int32_t pdmp_tanh_occupancy_eval(const pdmp_tanh_net *net, const float *x, int64_t n,
+                                 float *c_out, float *s_out, void *stream);
+/* grad_out [dim][n] = grad_x c = sigma'(s) grad_x s; c_out (nullable) [n]. */
+int32_t pdmp_tanh_occupancy_grad(const pdmp_tanh_net *net, const float *x, int64_t n,
+                                 float *c_out, float *grad_out, void *stream);
+/* The workspace morph of Sec. 3.2 (Eq. 1, explicit Euler) with the network's
+ * occupancy: x_{k+1} = x_k - eta grad c(x_k), T >= 0 steps; in, out [dim][n],
+ * in == out allowed, other overlap not. */
+int32_t pdmp_tanh_morph_samples(const pdmp_tanh_net *net, const float *in, float *out, int64_t n,
+                                int32_t T, float eta, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

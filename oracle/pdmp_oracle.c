@@ -983,6 +983,13 @@ void orc_amortised_morph(int L, const int *widths, const double *P, int ndof, in
 /*   e_l = d_l * (W_l^T e_{l+1})  (l = L-1..1),  grad_x s = W_0^T e_1.         */
 /* ------------------------------------------------------------------------- */
 
+/* sigma'(s) = sigma(s)(1 - sigma(s)), written as e/(1 + e)^2 with e = exp(-|s|) so
+ * that it keeps its relative accuracy where sigma(s) rounds to 0 or 1. */
+static double sigmoid_slope(double s) {
+    double e = exp(-fabs(s));
+    return e / ((1.0 + e) * (1.0 + e));
+}
+
 #define ORC_TANH_MAXH 256
 #define ORC_TANH_MAXL 6
 
@@ -1114,7 +1121,7 @@ void orc_tanh_grad(int dim, int H, int L, const double *P, const double *x, int6
         tanh_fwd f;
         tanh_forward(dim, H, L, P, xi, &f);
         tanh_backward_x(dim, H, L, P, &f, g, &ga);
-        double c = sigmoid(f.s), sp = c * (1.0 - c);
+        double sp = sigmoid_slope(f.s);
         for (int k = 0; k < dim; ++k) {
             if (gs) gs[(int64_t)k * n + i] = g[k];
             if (gc) gc[(int64_t)k * n + i] = sp * g[k];
@@ -1130,7 +1137,7 @@ static void tanh_grad_c(int dim, int H, int L, const double *P, const double *x,
     double g[ORC_MAX_DIM];
     tanh_forward(dim, H, L, P, x, &f);
     tanh_backward_x(dim, H, L, P, &f, g, NULL);
-    double c = sigmoid(f.s), sp = c * (1.0 - c);
+    double sp = sigmoid_slope(f.s);
     for (int k = 0; k < dim; ++k) gc[k] = sp * g[k];
 }
 

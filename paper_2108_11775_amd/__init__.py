@@ -23,7 +23,8 @@ __all__ = ["Occupancy", "Arm", "PdmpError", "abi_version", "uniform_samples",
            "label_points_discs", "label_points_boxes", "label_configs", "occupancy_eval",
            "occupancy_grad", "morph_samples", "fk_body_points", "sync", "occupancy_bwd",
            "bce_logits", "adam_step", "fit_occupancy", "Mlp", "arm_max_occupancy",
-           "amortised_morph"]
+           "amortised_morph", "TanhNet", "tanh_occupancy_eval", "tanh_occupancy_grad",
+           "tanh_morph_samples"]
 
 
 def _torch():
@@ -450,3 +451,63 @@ def amortised_morph(mlp: Mlp, occ: Occupancy, arm: Arm, q, T: int, eta: float,
               n, int(T), float(eta), float(thresh), _dev(flag, "flag", torch.uint8, (n,)),
               _dev(n_fallback, "n_fallback"), _dev(ws, "ws"), ws.numel(), _stream(q.device))
     return out, flag, n_fallback
+
+
+# ------------------------------------------- the paper's tanh occupancy ---
+
+class TanhNet:
+    """The paper's occupancy network (Sec. 3.1): n_hidden tanh layers of width
+    `hidden`, sigmoid output.  params: flat FP32 device tensor, per layer W_l
+    [hidden][n_l] then b_l [hidden], and last v [hidden], b_o."""
+
+    def __init__(self, dim: int, hidden: int, n_hidden: int, params):
+        self.dim, self.hidden, self.n_hidden = int(dim), int(hidden), int(n_hidden)
+        s = _lib.pdmp_tanh_net(self.dim, self.hidden, self.n_hidden, None)
+        n = _lib.load().pdmp_tanh_num_params(C.byref(s))
+        if n < 0:
+            raise ValueError(f"unsupported network shape dim={dim} hidden={hidden} "
+                             f"n_hidden={n_hidden}")
+        self.params = params
+        _dev(params, "params", _torch().float32, (n,))
+
+    def c_struct(self):
+        return _lib.pdmp_tanh_net(self.dim, self.hidden, self.n_hidden,
+                                  C.c_void_p(self.params.data_ptr()))
+
+
+def tanh_occupancy_eval(net: TanhNet, x):
+    """(c, s) of the network at [dim][n] points."""
+    torch = _torch()
+    n = int(x.shape[1])
+    c = torch.empty(n, dtype=torch.float32, device=x.device)
+    s = torch.empty(n, dtype=torch.float32, device=x.device)
+    o = net.c_struct()
+    _lib.call("pdmp_tanh_occupancy_eval", C.byref(o), _dev(x, "x", torch.float32, (net.dim, n)),
+              n, _dev(c, "c"), _dev(s, "s"), _stream(x.device))
+    return c, s
+
+
+def tanh_occupancy_grad(net: TanhNet, x):
+    """(c, grad_x c) of the network at [dim][n] points."""
+    torch = _torch()
+    n = int(x.shape[1])
+    c = torch.empty(n, dtype=torch.float32, device=x.device)
+    g = torch.empty((net.dim, n), dtype=torch.float32, device=x.device)
+    o = net.c_struct()
+    _lib.call("pdmp_tanh_occupancy_grad", C.byref(o), _dev(x, "x", torch.float32, (net.dim, n)),
+              n, _dev(c, "c"), _dev(g, "grad"), _stream(x.device))
+    return c, g
+
+
+def tanh_morph_samples(net: TanhNet, x, T: int, eta: float, out=None):
+    """Explicit-Euler morph (Eq. 1) of [dim][n] points with the network's occupancy."""
+    torch = _torch()
+    n = int(x.shape[1])
+    _dev(x, "x", torch.float32, (net.dim, n))
+    if out is None:
+        out = torch.empty_like(x)
+    o = net.c_struct()
+    _lib.call("pdmp_tanh_morph_samples", C.byref(o), C.c_void_p(x.data_ptr()),
+              _dev(out, "out", torch.float32, (net.dim, n)), n, int(T), float(eta),
+              _stream(x.device))
+    return out

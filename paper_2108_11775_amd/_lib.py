@@ -45,6 +45,11 @@ class pdmp_mlp(C.Structure):
                 ("params", C.c_void_p), ("params_bf16", C.c_void_p)]
 
 
+class pdmp_tanh_net(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("hidden", C.c_int32), ("n_hidden", C.c_int32),
+                ("params", C.c_void_p)]
+
+
 _vp, _i32, _i64, _u32, _u64, _f = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float
 _P = C.POINTER
 
@@ -71,6 +76,10 @@ SIGNATURES = {
     "pdmp_bce_logits": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t, _vp]),
     "pdmp_adam_step": (_i32, [_vp, _vp, _vp, _vp, _i64, _i64, _i32, _f, _f, _f, _f, _f, _vp]),
     "pdmp_mlp_num_params": (_i64, [_P(pdmp_mlp)]),
+    "pdmp_tanh_num_params": (_i64, [_P(pdmp_tanh_net)]),
+    "pdmp_tanh_occupancy_eval": (_i32, [_P(pdmp_tanh_net), _vp, _i64, _vp, _vp, _vp]),
+    "pdmp_tanh_occupancy_grad": (_i32, [_P(pdmp_tanh_net), _vp, _i64, _vp, _vp, _vp]),
+    "pdmp_tanh_morph_samples": (_i32, [_P(pdmp_tanh_net), _vp, _vp, _i64, _i32, _f, _vp]),
     "pdmp_mlp_pack": (_i32, [_P(pdmp_mlp), _vp, _vp]),
     "pdmp_mlp_acts_size": (C.c_size_t, [_P(pdmp_mlp), _i64]),
     "pdmp_mlp_workspace_size": (C.c_size_t, [_P(pdmp_mlp), _i64]),

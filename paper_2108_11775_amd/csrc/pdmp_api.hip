@@ -480,4 +480,74 @@ int32_t pdmp_amortised_morph(const pdmp_mlp *mlp, const pdmp_occupancy *occ, con
     return launch_scatter(*arm, idx, total, qc, n, out, s);
 }
 
+// ---- the tanh occupancy network ----
+
+static int64_t tanh_nparams(const pdmp_tanh_net *net) {
+    const int64_t H = net->hidden, D = net->dim, L = net->n_hidden;
+    return H * D + H + (L - 1) * (H * H + H) + H + 1;
+}
+
+static int32_t check_tanh(const pdmp_tanh_net *net) {
+    PDMP_REQUIRE(net != nullptr, "net is NULL");
+    PDMP_REQUIRE(net->dim == 2 || net->dim == 3, "dim %d not 2 or 3", net->dim);
+    PDMP_REQUIRE(net->hidden >= 1 && net->hidden <= 64, "hidden %d not in [1,64]", net->hidden);
+    PDMP_REQUIRE(net->n_hidden >= 1 && net->n_hidden <= 4, "n_hidden %d not in [1,4]",
+                 net->n_hidden);
+    PDMP_REQUIRE(net->params != nullptr, "params NULL");
+    return PDMP_OK;
+}
+
+int64_t pdmp_tanh_num_params(const pdmp_tanh_net *net) {
+    if (!net || (net->dim != 2 && net->dim != 3) || net->hidden < 1 || net->hidden > 64 ||
+        net->n_hidden < 1 || net->n_hidden > 4)
+        return -1;
+    return tanh_nparams(net);
+}
+
+int32_t pdmp_tanh_occupancy_eval(const pdmp_tanh_net *net, const float *x, int64_t n,
+                                 float *c_out, float *s_out, void *stream) {
+    int32_t st = check_tanh(net);
+    if (st) return st;
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    if (n == 0) return PDMP_OK;
+    PDMP_REQUIRE(x != nullptr, "x NULL");
+    PDMP_REQUIRE(c_out || s_out, "c_out and s_out both NULL");
+    return launch_tanh_net(*net, kEval, x, n, 1, 0.0f, c_out, s_out, nullptr, nullptr,
+                           (hipStream_t)stream);
+}
+
+int32_t pdmp_tanh_occupancy_grad(const pdmp_tanh_net *net, const float *x, int64_t n,
+                                 float *c_out, float *grad_out, void *stream) {
+    int32_t st = check_tanh(net);
+    if (st) return st;
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    if (n == 0) return PDMP_OK;
+    PDMP_REQUIRE(x && grad_out, "x/grad_out NULL");
+    return launch_tanh_net(*net, kGrad, x, n, 1, 0.0f, c_out, nullptr, grad_out, nullptr,
+                           (hipStream_t)stream);
+}
+
+int32_t pdmp_tanh_morph_samples(const pdmp_tanh_net *net, const float *in, float *out, int64_t n,
+                                int32_t T, float eta, void *stream) {
+    int32_t st = check_tanh(net);
+    if (st) return st;
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    PDMP_REQUIRE(T >= 0, "T < 0");
+    PDMP_REQUIRE(std::isfinite(eta), "eta not finite");
+    if (n == 0) return PDMP_OK;
+    PDMP_REQUIRE(in && out, "in/out NULL");
+    if (T == 0) {
+        if (in == out) return PDMP_OK;
+        hipError_t e = hipMemcpyAsync(out, in, (size_t)net->dim * (size_t)n * sizeof(float),
+                                      hipMemcpyDeviceToDevice, (hipStream_t)stream);
+        if (e != hipSuccess) {
+            set_error("hipMemcpyAsync: %s", hipGetErrorString(e));
+            return PDMP_EDEVICE;
+        }
+        return PDMP_OK;
+    }
+    return launch_tanh_net(*net, kMorph, in, n, T, eta, nullptr, nullptr, nullptr, out,
+                           (hipStream_t)stream);
+}
+
 }  // extern "C"

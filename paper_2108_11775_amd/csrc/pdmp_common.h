@@ -143,6 +143,10 @@ int32_t launch_grid_wgrad(int dim, const float *hinges, int M, const int *grid, 
                           const float *x, int64_t n, const float *g, float *part, int *rows,
                           hipStream_t st);
 size_t wgrad_rows_max(int64_t n);
+// The tanh occupancy network: kEval, kGrad or kMorph over n >= 1 points.
+int32_t launch_tanh_net(const pdmp_tanh_net &net, int mode, const float *x, int64_t n, int T,
+                        float eta, float *c_out, float *s_out, float *g_out, float *x_out,
+                        hipStream_t st);
 int32_t launch_bce(const float *s, const uint8_t *y, int64_t n, float *loss, float *g_out,
                    double *parts, hipStream_t st);
 int32_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, int64_t n_decay,

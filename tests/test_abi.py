@@ -73,3 +73,23 @@ def test_binding_refuses_cpu_tensors():
     occ = P.Occupancy(torch.zeros(2, 4), torch.zeros(5), 0.5)
     with pytest.raises(TypeError):
         P.occupancy_eval(occ, torch.zeros(2, 3))
+
+
+def test_tanh_network_shapes_checked_on_the_host():
+    lib = _lib.load()
+    net = _lib.pdmp_tanh_net(2, 64, 3, None)
+    assert lib.pdmp_tanh_num_params(C.byref(net)) == 64 * 2 + 64 + 2 * (64 * 64 + 64) + 64 + 1
+    for bad in [(4, 8, 2), (2, 65, 2), (2, 0, 2), (3, 8, 0), (3, 8, 5)]:
+        b = _lib.pdmp_tanh_net(*bad, None)
+        assert lib.pdmp_tanh_num_params(C.byref(b)) == -1
+        assert lib.pdmp_tanh_occupancy_eval(C.byref(b), None, 1, None, None, None) == \
+            _lib.PDMP_EINVAL
+    assert lib.pdmp_tanh_occupancy_grad(C.byref(net), None, 1, None, None, None) == \
+        _lib.PDMP_EINVAL  # params NULL
+    fake = _lib.pdmp_tanh_net(2, 8, 1, C.c_void_p(16))
+    assert lib.pdmp_tanh_morph_samples(C.byref(fake), None, None, 1, -1, 0.1, None) == \
+        _lib.PDMP_EINVAL
+    assert lib.pdmp_tanh_morph_samples(C.byref(fake), None, None, 0, 3, 0.1, None) == 0
+    import paper_2108_11775_amd as P
+    with pytest.raises(ValueError):
+        P.TanhNet(2, 100, 2, None)

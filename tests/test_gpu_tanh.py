@@ -1,0 +1,157 @@
+"""GPU parity of the paper's tanh-network occupancy (Sec. 3.1) and of the morph on
+it (Eq. 1) against the FP64 oracle, through the C ABI on identical inputs.
+
+Tolerances (FP32 against FP64, 1e-5 relative to the scale the rounding acts on;
+S_abs and G_abs are the oracle's error scales of s and grad s, which propagate
+|W| |a| sums and the rounding of each tanh through the layers):
+  logit     |s_gpu - s| <= 1e-5 S_abs
+  occupancy |c_gpu - c| <= 1e-5 (c + sigma' S_abs)
+  gradient  |g_gpu - g|_inf <= 1e-5 (sigma' G_abs + |sigma''| |grad s| S_abs)
+  morph     |x_gpu - x|_inf <= 1e-5 max(1, A) max(1, |x_T|_inf) per sample, with A
+            the product of |I - eta Hess c|_2 along the oracle's path.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2108_11775_amd as P
+from paper_2108_11775_amd import configs as K, inputs as I
+
+from helpers import GOLDEN, dev, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _golden(cfg):
+    name = {1: "tanh_c1.npy", 2: "tanh_c2.npy"}[cfg.cfg_id]
+    return np.load(os.path.join(GOLDEN, name)).astype(np.float32)
+
+
+def _pair(dim, H, L, params):
+    params = np.asarray(params, np.float32)
+    return P.TanhNet(dim, H, L, dev(params)), O.TanhNet(dim, H, L, params.astype(np.float64))
+
+
+def _check_eval_grad(gnet, onet, x):
+    c, s = P.tanh_occupancy_eval(gnet, dev(x))
+    c2, g = P.tanh_occupancy_grad(gnet, dev(x))
+    s_r, gs_r, gc_r, sabs, gabs = O.tanh_grad(onet, x)
+    c_r = 1 / (1 + np.exp(-s_r))
+    e = np.exp(-np.abs(s_r))
+    sp = e / (1 + e) ** 2  # sigma'(s) without the cancellation of c (1 - c)
+    assert np.all(np.abs(host(s) - s_r) <= TOL * sabs), np.max(np.abs(host(s) - s_r) / sabs)
+    assert np.all(np.abs(host(c) - c_r) <= TOL * (c_r + sp * sabs))
+    assert np.array_equal(host(c), host(c2))
+    scale = sp * gabs + np.abs(sp * (1 - 2 * c_r)) * np.abs(gs_r).max(axis=0) * sabs
+    err = np.abs(host(g) - gc_r).max(axis=0)
+    assert np.all(err <= TOL * scale + 1e-30), np.max(err / scale)
+
+
+@pytest.mark.parametrize("cfg", [K.C1, K.C2], ids=["config1", "config2"])
+@pytest.mark.parametrize("n", [1, 17, 5001])
+def test_eval_grad_fitted_networks(cfg, n):
+    require_gpu()
+    tc = K.TANH
+    gnet, onet = _pair(2, tc.hidden, tc.layers, _golden(cfg))
+    x = I.uniform_points(cfg.cfg_id, K.STREAM_EVAL, 2, n, cfg.lo, cfg.hi)
+    _check_eval_grad(gnet, onet, x)
+
+
+# every width class (1, 2 and 4 row tiles of 16, padded and full) and depth
+@pytest.mark.parametrize("dim,H,L", [(2, 1, 1), (2, 7, 2), (3, 16, 3), (2, 17, 4), (3, 32, 1),
+                                     (2, 33, 3), (3, 48, 2), (2, 64, 4), (3, 64, 3)])
+def test_eval_grad_shapes(dim, H, L):
+    require_gpu()
+    rng = np.random.default_rng(100 * dim + 10 * L + H)
+    n_p = O.tanh_nparams(dim, H, L)
+    params = rng.normal(0, 1.0 / np.sqrt(max(H, dim)), n_p) * 1.5
+    gnet, onet = _pair(dim, H, L, params)
+    x = rng.uniform(-2, 2, (dim, 1237)).astype(np.float32)
+    _check_eval_grad(gnet, onet, x)
+
+
+def _morph_check(onet, x0, T, eta, out, idx=None):
+    if idx is not None:
+        x0, out = x0[:, idx], out[:, idx]
+    ref, amp = O.tanh_morph(onet, x0, T, eta, diag=True)
+    err = np.abs(out - ref).max(axis=0)
+    bound = TOL * np.maximum(1, amp) * np.maximum(1, np.abs(ref).max(axis=0))
+    assert np.all(err <= bound), np.max(err / bound)
+
+
+def test_morph_config1_full():
+    require_gpu()
+    cfg = K.C1
+    tc = K.TANH
+    gnet, onet = _pair(2, tc.hidden, tc.layers, _golden(cfg))
+    x0 = O.uniform_samples(I.philox_seed(cfg.cfg_id), 0, [cfg.lo] * 2, [cfg.hi] * 2, cfg.n_samples)
+    out = host(P.tanh_morph_samples(gnet, dev(x0), cfg.T, cfg.eta))
+    _morph_check(onet, x0, cfg.T, cfg.eta, out)
+
+
+def test_morph_config2_full_size_sampled():
+    """The 2^20-sample, T = 50 morph in the launch configuration of the benchmark."""
+    require_gpu()
+    cfg = K.C2
+    tc = K.TANH
+    gnet, onet = _pair(2, tc.hidden, tc.layers, _golden(cfg))
+    seed = I.philox_seed(cfg.cfg_id)
+    x0_d = P.uniform_samples(seed, 0, [cfg.lo] * 2, [cfg.hi] * 2, cfg.n_samples)
+    out = host(P.tanh_morph_samples(gnet, x0_d, cfg.T, cfg.eta))
+    x0 = O.uniform_samples(seed, 0, [cfg.lo] * 2, [cfg.hi] * 2, cfg.n_samples)
+    n = cfg.n_samples
+    idx = np.unique(np.r_[0, np.arange(1, n, n // 400), n - 1])
+    _morph_check(onet, x0, cfg.T, cfg.eta, out, idx)
+
+
+@pytest.mark.parametrize("n", [1, 15, 16, 4097])
+def test_morph_3d_ragged(n):
+    require_gpu()
+    rng = np.random.default_rng(n)
+    params = rng.normal(0, 0.4, O.tanh_nparams(3, 24, 2))
+    gnet, onet = _pair(3, 24, 2, params)
+    x0 = rng.uniform(-2, 2, (3, n)).astype(np.float32)
+    out = host(P.tanh_morph_samples(gnet, dev(x0), 12, 0.05))
+    _morph_check(onet, x0, 12, 0.05, out)
+
+
+def test_identities_in_place_and_determinism():
+    require_gpu()
+    cfg = K.C1
+    tc = K.TANH
+    gnet, _ = _pair(2, tc.hidden, tc.layers, _golden(cfg))
+    x = dev(I.uniform_points(1, K.STREAM_EVAL, 2, 5000, cfg.lo, cfg.hi))
+    assert np.array_equal(host(P.tanh_morph_samples(gnet, x, 0, 0.05)), host(x))
+    assert np.array_equal(host(P.tanh_morph_samples(gnet, x, 7, 0.0)), host(x))
+    a = host(P.tanh_morph_samples(gnet, x, cfg.T, cfg.eta))
+    b = host(P.tanh_morph_samples(gnet, x, cfg.T, cfg.eta))
+    assert np.array_equal(a, b)
+    y = x.clone()
+    P.tanh_morph_samples(gnet, y, cfg.T, cfg.eta, out=y)
+    assert np.array_equal(host(y), a)
+    # a constant network (all weights zero) leaves the points where they are
+    z = np.zeros(O.tanh_nparams(2, tc.hidden, tc.layers), np.float32)
+    z[-1] = 1.5
+    znet, _ = _pair(2, tc.hidden, tc.layers, z)
+    assert np.array_equal(host(P.tanh_morph_samples(znet, x, 10, 0.5)), host(x))
+    c, s = P.tanh_occupancy_eval(znet, x)
+    assert np.all(host(s) == np.float32(1.5))
+
+
+def test_free_fraction_rises_after_gpu_morph():
+    require_gpu()
+    cfg = K.C2
+    tc = K.TANH
+    gnet, _ = _pair(2, tc.hidden, tc.layers, _golden(cfg))
+    dc, dr = I.discs(cfg.cfg_id, cfg.n_discs, cfg.lo, cfg.hi, cfg.r_min, cfg.r_max)
+    x0 = P.uniform_samples(I.philox_seed(cfg.cfg_id), 0, [cfg.lo] * 2, [cfg.hi] * 2, 1 << 18)
+    x1 = P.tanh_morph_samples(gnet, x0, cfg.T, cfg.eta)
+    _, h0 = P.label_points_discs(dev(dc), dev(dr), x0, count=True)
+    _, h1 = P.label_points_discs(dev(dc), dev(dr), x1, count=True)
+    before = 1 - int(host(h0)[0]) / x0.shape[1]
+    after = 1 - int(host(h1)[0]) / x0.shape[1]
+    assert after > before + 0.1, (before, after)
