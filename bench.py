@@ -321,11 +321,21 @@ def arm_morph(P, I, K, torch, world):
 
 def tanh_morph(P, I, K, torch, dev):
     """The morph of the large 2-D workload with the paper's own occupancy, the tanh
-    network of Sec. 3.1 (weights fitted by the FP64 reference fit in tests/golden/)."""
-    import numpy as np
+    network of Sec. 3.1, fitted on the GPU first (full-batch Adam on the BCE)."""
     cfg, tc = K.C2, K.TANH
-    params = np.load(os.path.join(ROOT, "tests", "golden", "tanh_c2.npy")).astype(np.float32)
-    net = P.TanhNet(2, tc.hidden, tc.layers, torch.from_numpy(params).to(dev))
+    H, L = tc.hidden, tc.layers
+    dc, dr = I.discs(cfg.cfg_id, cfg.n_discs, cfg.lo, cfg.hi, cfg.r_min, cfg.r_max)
+    dc_d, dr_d = torch.from_numpy(dc).to(dev), torch.from_numpy(dr).to(dev)
+    pts = torch.from_numpy(I.uniform_points(cfg.cfg_id, K.STREAM_FIT, 2, cfg.fit_points, cfg.lo,
+                                            cfg.hi)).to(dev)
+    y = P.label_points_discs(dc_d, dr_d, pts)
+    init = torch.from_numpy(I.tanh_init(cfg.cfg_id, 2, H, L, cfg.hi)).to(dev)
+    net = P.TanhNet(2, H, L, init)
+    t = Timer(torch)
+    with t:
+        loss = P.tanh_fit(net, pts, y, tc.steps[1], tc.lr, tc.l2[1], tc.beta1, tc.beta2, tc.eps)
+    fit_ms = t.ms()
+    log(f"tanh-network fit: {fit_ms:.0f} ms, loss {float(loss[0]):.4f} -> {float(loss[-1]):.4f}")
     N = cfg.n_samples
     x0 = P.uniform_samples(I.philox_seed(cfg.cfg_id), 0, [cfg.lo] * 2, [cfg.hi] * 2, N)
     x1 = torch.empty_like(x0)
@@ -336,17 +346,16 @@ def tanh_morph(P, I, K, torch, dev):
         for _ in range(reps):
             P.tanh_morph_samples(net, x0, cfg.T, cfg.eta, out=x1)
     ms = t.ms() / reps
-    dc, dr = I.discs(cfg.cfg_id, cfg.n_discs, cfg.lo, cfg.hi, cfg.r_min, cfg.r_max)
-    dc_d, dr_d = torch.from_numpy(dc).to(dev), torch.from_numpy(dr).to(dev)
     _, h0 = P.label_points_discs(dc_d, dr_d, x0, count=True)
     _, h1 = P.label_points_discs(dc_d, dr_d, x1, count=True)
-    H, L = tc.hidden, tc.layers
     # hidden-to-hidden products forward (W a) and backward (W^T e) on MFMA:
     # 4 (L-1) H^2 flops per sample and step
     flops = N * cfg.T * 4.0 * (L - 1) * H * H
     ach = flops / (ms * 1e-3) / 1e12
     return {"workload": f"plain morph 2-D large with the paper's tanh occupancy (2-{H}x{L}-1, "
                         f"sigmoid): 1,048,576 samples, T={cfg.T}, eta={cfg.eta}, 100 discs",
+            "fit": {"steps": tc.steps[1], "points": cfg.fit_points, "ms_total": fit_ms,
+                    "loss_first": float(loss[0]), "loss_last": float(loss[-1])},
             "morph_ms": ms, "samples_per_s": N / (ms * 1e-3),
             "collision_free_before": 1 - h0.item() / N,
             "collision_free_after": 1 - h1.item() / N,

@@ -296,6 +296,25 @@ int32_t pdmp_tanh_occupancy_grad(const pdmp_tanh_net *net, const float *x, int64
 int32_t pdmp_tanh_morph_samples(const pdmp_tanh_net *net, const float *in, float *out, int64_t n,
                                 int32_t T, float eta, void *stream);
 
+/* Fit of the network (Sec. 3.1: binary cross-entropy minimised by a gradient-descent
+ * optimiser), full batch over n >= 1 labelled points pts [dim][n], labels u8 [n]:
+ *   L = (1/n) sum_i BCE(sigma(s(x_i)), y_i) + (l2/2) (sum_l |W_l|^2 + |v|^2)
+ * (biases not decayed).  Parameter gradients by the chain rule through every layer
+ * (reverse order), summed over the points in a fixed order (deterministic).
+ * pdmp_tanh_loss_grad: loss (nullable, device [1]) and grad (device [num_params]).
+ * pdmp_tanh_fit: opts->steps Adam steps (opts->optimizer must be 1; lr, l2, beta1,
+ *   beta2, eps, adam_m, adam_v [num_params] in/out, t0 as for pdmp_fit_occupancy;
+ *   lr_bias unused) updating net->params IN PLACE (it must point to writable device
+ *   memory); loss_out (nullable, device [steps]) gets the loss before each step.
+ * ws: device scratch of pdmp_tanh_fit_workspace_size bytes (PDMP_ENOMEM if short). */
+size_t pdmp_tanh_fit_workspace_size(const pdmp_tanh_net *net, int64_t n);
+int32_t pdmp_tanh_loss_grad(const pdmp_tanh_net *net, const float *pts, const uint8_t *labels,
+                            int64_t n, float l2, float *loss, float *grad, void *ws,
+                            size_t ws_bytes, void *stream);
+int32_t pdmp_tanh_fit(const pdmp_tanh_net *net, const float *pts, const uint8_t *labels,
+                      int64_t n, const pdmp_fit_opts *opts, float *loss_out, void *ws,
+                      size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

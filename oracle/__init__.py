@@ -90,7 +90,7 @@ def _load():
         "orc_tanh_morph": (None, [C.c_int, C.c_int, C.c_int, _dp, _dp, _i64, C.c_int,
                                   C.c_double, _dp, _dp]),
         "orc_tanh_loss_grad": (C.c_double, [C.c_int, C.c_int, C.c_int, _dp, _dp, _u8p, _i64,
-                                            C.c_double, _dp]),
+                                            C.c_double, _dp, _dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -522,14 +522,16 @@ def tanh_morph(net: TanhNet, x, T: int, eta: float, diag: bool = False):
     return (out, amp) if diag else out
 
 
-def tanh_loss_grad(net: TanhNet, pts, y, l2: float):
-    """(loss, grad [nparams]) of mean BCE + (l2/2) |weights|^2 (biases not decayed)."""
+def tanh_loss_grad(net: TanhNet, pts, y, l2: float, with_scale: bool = False):
+    """(loss, grad [nparams][, grad error scale]) of mean BCE + (l2/2) |weights|^2
+    (biases not decayed)."""
     pts = _d(pts)
     y = np.ascontiguousarray(y, dtype=np.uint8)
     g = _zeros(tanh_nparams(net.dim, net.H, net.L))
+    gs = _zeros(g.size) if with_scale else None
     L = _load().orc_tanh_loss_grad(*net.args(), _P(pts), _P(y, _u8p), pts.shape[1], float(l2),
-                                   _P(g))
-    return L, g
+                                   _P(g), _P(gs))
+    return (L, g, gs) if with_scale else (L, g)
 
 
 def tanh_fit(net: TanhNet, pts, y, steps: int, lr: float, l2: float, b1=0.9, b2=0.999,

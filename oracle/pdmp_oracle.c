@@ -1180,9 +1180,12 @@ void orc_tanh_morph(int dim, int H, int L, const double *P, const double *xin, i
 /* Fit objective of the network (Sec. 3.1): mean BCE of sigma(s(x_i)) against
  * y_i plus (l2/2) times the squared weights (the matrices W_l and v, not the
  * biases).  Returns the loss; grad ([nparams]) gets its gradient by the chain
- * rule through every layer (reverse order). */
+ * rule through every layer (reverse order).  gscale (nullable, [nparams]) gets
+ * the error scale of each gradient entry: the same sums over absolute values, with
+ * r = sigma(s) - y widened by sigma'(s) S_abs and every layer's forward value and
+ * slope widened as in the input-gradient scale, plus l2 |w|. */
 double orc_tanh_loss_grad(int dim, int H, int L, const double *P, const double *pts,
-                          const uint8_t *y, int64_t n, double l2, double *grad) {
+                          const uint8_t *y, int64_t n, double l2, double *grad, double *gscale) {
     const int64_t np = orc_tanh_nparams(dim, H, L);
     int64_t off[ORC_TANH_MAXL + 1];
     int64_t o = 0;
@@ -1192,7 +1195,9 @@ double orc_tanh_loss_grad(int dim, int H, int L, const double *P, const double *
     }
     off[L] = o; /* v, then b_o */
     int nt = orc_num_threads();
+    int want_s = gscale != NULL;
     double *acc = (double *)calloc((size_t)nt * (size_t)np, sizeof(double));
+    double *acca = want_s ? (double *)calloc((size_t)nt * (size_t)np, sizeof(double)) : NULL;
     double *lsum = (double *)calloc((size_t)nt, sizeof(double));
 #pragma omp parallel
     {
@@ -1201,6 +1206,7 @@ double orc_tanh_loss_grad(int dim, int H, int L, const double *P, const double *
         tid = omp_get_thread_num();
 #endif
         double *G = acc + (int64_t)tid * np;
+        double *GA = want_s ? acca + (int64_t)tid * np : NULL;
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
             double xi[ORC_MAX_DIM];
@@ -1209,28 +1215,59 @@ double orc_tanh_loss_grad(int dim, int H, int L, const double *P, const double *
             tanh_forward(dim, H, L, P, xi, &f);
             double yi = (double)y[i];
             lsum[tid] += bce_logit(f.s, yi);
-            double r = sigmoid(f.s) - yi; /* dBCE/ds */
+            /* dBCE/ds = sigma(s) - y, formed as sigma(s) (y = 0) or -sigma(-s) (y = 1) so
+             * that it keeps its relative accuracy where sigma(s) is within rounding of y */
+            double r = y[i] ? -sigmoid(-f.s) : sigmoid(f.s);
+            double ra = fabs(r) + sigmoid_slope(f.s) * f.sabs;
             const double *v = P + off[L];
-            for (int u = 0; u < H; ++u) G[off[L] + u] += r * f.a[L][u];
+            double aa[ORC_TANH_MAXH]; /* forward scale of the layer input */
+            for (int u = 0; u < H; ++u) {
+                double a = f.a[L][u];
+                G[off[L] + u] += r * a;
+                if (GA) GA[off[L] + u] += ra * (fabs(a) + (1.0 - a * a) * f.zs[L][u]);
+            }
             G[off[L] + H] += r;
-            double e[ORC_TANH_MAXH], t[ORC_TANH_MAXH];
-            for (int u = 0; u < H; ++u) e[u] = r * v[u] * (1.0 - f.a[L][u] * f.a[L][u]);
+            if (GA) GA[off[L] + H] += ra;
+            double e[ORC_TANH_MAXH], t[ORC_TANH_MAXH], ea[ORC_TANH_MAXH], ta[ORC_TANH_MAXH];
+            for (int u = 0; u < H; ++u) {
+                double a = f.a[L][u], d = 1.0 - a * a;
+                e[u] = r * v[u] * d;
+                ea[u] = ra * fabs(v[u]) * d * (1.0 + 2.0 * fabs(a) * f.zs[L][u]);
+            }
             for (int l = L - 1; l >= 0; --l) {
                 int nin = l == 0 ? dim : H;
                 const double *ain = l == 0 ? xi : f.a[l];
+                for (int k = 0; k < nin; ++k)
+                    aa[k] = l == 0 ? fabs(xi[k])
+                                   : fabs(ain[k]) + (1.0 - ain[k] * ain[k]) * f.zs[l][k];
                 double *GW = G + off[l], *Gb = G + off[l] + (int64_t)H * nin;
                 for (int u = 0; u < H; ++u) {
                     for (int k = 0; k < nin; ++k) GW[(int64_t)u * nin + k] += e[u] * ain[k];
                     Gb[u] += e[u];
                 }
+                if (GA) {
+                    double *GAW = GA + off[l], *GAb = GA + off[l] + (int64_t)H * nin;
+                    for (int u = 0; u < H; ++u) {
+                        for (int k = 0; k < nin; ++k) GAW[(int64_t)u * nin + k] += ea[u] * aa[k];
+                        GAb[u] += ea[u];
+                    }
+                }
                 if (l == 0) break;
                 const double *W = P + off[l];
                 for (int k = 0; k < H; ++k) {
-                    double s2 = 0.0;
-                    for (int u = 0; u < H; ++u) s2 += W[(int64_t)u * H + k] * e[u];
-                    t[k] = s2 * (1.0 - f.a[l][k] * f.a[l][k]);
+                    double s2 = 0.0, s2a = 0.0;
+                    for (int u = 0; u < H; ++u) {
+                        s2 += W[(int64_t)u * H + k] * e[u];
+                        s2a += fabs(W[(int64_t)u * H + k]) * ea[u];
+                    }
+                    double a = f.a[l][k], d = 1.0 - a * a;
+                    t[k] = s2 * d;
+                    ta[k] = s2a * d * (1.0 + 2.0 * fabs(a) * f.zs[l][k]);
                 }
-                for (int k = 0; k < H; ++k) e[k] = t[k];
+                for (int k = 0; k < H; ++k) {
+                    e[k] = t[k];
+                    ea[k] = ta[k];
+                }
             }
         }
     }
@@ -1238,9 +1275,13 @@ double orc_tanh_loss_grad(int dim, int H, int L, const double *P, const double *
     for (int t = 0; t < nt; ++t) loss += lsum[t];
     loss /= (double)n;
     for (int64_t j = 0; j < np; ++j) {
-        double s2 = 0.0;
-        for (int t = 0; t < nt; ++t) s2 += acc[(int64_t)t * np + j];
+        double s2 = 0.0, s2a = 0.0;
+        for (int t = 0; t < nt; ++t) {
+            s2 += acc[(int64_t)t * np + j];
+            if (want_s) s2a += acca[(int64_t)t * np + j];
+        }
         grad[j] = s2 / (double)n;
+        if (want_s) gscale[j] = s2a / (double)n;
     }
     /* weight decay on the matrices and v */
     double wsq = 0.0;
@@ -1249,10 +1290,12 @@ double orc_tanh_loss_grad(int dim, int H, int L, const double *P, const double *
         for (int64_t j = 0; j < cnt; ++j) {
             double w = P[off[l] + j];
             grad[off[l] + j] += l2 * w;
+            if (want_s) gscale[off[l] + j] += l2 * fabs(w);
             wsq += w * w;
         }
     }
     free(acc);
+    free(acca);
     free(lsum);
     return loss + 0.5 * l2 * wsq;
 }

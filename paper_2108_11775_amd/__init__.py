@@ -24,7 +24,7 @@ __all__ = ["Occupancy", "Arm", "PdmpError", "abi_version", "uniform_samples",
            "occupancy_grad", "morph_samples", "fk_body_points", "sync", "occupancy_bwd",
            "bce_logits", "adam_step", "fit_occupancy", "Mlp", "arm_max_occupancy",
            "amortised_morph", "TanhNet", "tanh_occupancy_eval", "tanh_occupancy_grad",
-           "tanh_morph_samples"]
+           "tanh_morph_samples", "tanh_loss_grad", "tanh_fit"]
 
 
 def _torch():
@@ -511,3 +511,47 @@ def tanh_morph_samples(net: TanhNet, x, T: int, eta: float, out=None):
               _dev(out, "out", torch.float32, (net.dim, n)), n, int(T), float(eta),
               _stream(x.device))
     return out
+
+
+def _tanh_ws(net: TanhNet, n: int, device):
+    lib = _lib.load()
+    o = net.c_struct()
+    return _workspace(lib.pdmp_tanh_fit_workspace_size(C.byref(o), n), device)
+
+
+def tanh_loss_grad(net: TanhNet, pts, labels, l2: float):
+    """(loss [1], grad [num_params]) of the network's fit objective (Sec. 3.1):
+    mean BCE over the labelled points + (l2/2) |weights|^2 (biases not decayed)."""
+    torch = _torch()
+    n = int(pts.shape[1])
+    loss = torch.empty(1, dtype=torch.float32, device=pts.device)
+    grad = torch.empty_like(net.params)
+    ws = _tanh_ws(net, n, pts.device)
+    o = net.c_struct()
+    _lib.call("pdmp_tanh_loss_grad", C.byref(o), _dev(pts, "pts", torch.float32, (net.dim, n)),
+              _dev(labels, "labels", torch.uint8, (n,)), n, float(l2), _dev(loss, "loss"),
+              _dev(grad, "grad"), _dev(ws, "ws"), ws.numel(), _stream(pts.device))
+    return loss, grad
+
+
+def tanh_fit(net: TanhNet, pts, labels, steps: int, lr: float, l2: float, beta1=0.9,
+             beta2=0.999, eps=1e-8, adam_m=None, adam_v=None, t0: int = 0,
+             record_loss: bool = True):
+    """Full-batch Adam fit of the network on the GPU (Sec. 3.1); updates net.params in
+    place and returns the per-step loss tensor [steps] (device) or None."""
+    torch = _torch()
+    n = int(pts.shape[1])
+    m = adam_m if adam_m is not None else torch.zeros_like(net.params)
+    v = adam_v if adam_v is not None else torch.zeros_like(net.params)
+    loss = torch.empty(max(steps, 1), dtype=torch.float32, device=pts.device) if record_loss \
+        else None
+    ws = _tanh_ws(net, n, pts.device)
+    opts = _lib.pdmp_fit_opts(1, int(steps), float(lr), 0.0, float(l2), float(beta1),
+                              float(beta2), float(eps), int(t0), _dev(m, "adam_m"),
+                              _dev(v, "adam_v"))
+    o = net.c_struct()
+    _lib.call("pdmp_tanh_fit", C.byref(o), _dev(pts, "pts", torch.float32, (net.dim, n)),
+              _dev(labels, "labels", torch.uint8, (n,)), n, C.byref(opts),
+              _dev(loss, "loss") if loss is not None else None, _dev(ws, "ws"), ws.numel(),
+              _stream(pts.device))
+    return loss[:steps] if loss is not None else None

@@ -80,6 +80,11 @@ SIGNATURES = {
     "pdmp_tanh_occupancy_eval": (_i32, [_P(pdmp_tanh_net), _vp, _i64, _vp, _vp, _vp]),
     "pdmp_tanh_occupancy_grad": (_i32, [_P(pdmp_tanh_net), _vp, _i64, _vp, _vp, _vp]),
     "pdmp_tanh_morph_samples": (_i32, [_P(pdmp_tanh_net), _vp, _vp, _i64, _i32, _f, _vp]),
+    "pdmp_tanh_fit_workspace_size": (C.c_size_t, [_P(pdmp_tanh_net), _i64]),
+    "pdmp_tanh_loss_grad": (_i32, [_P(pdmp_tanh_net), _vp, _vp, _i64, _f, _vp, _vp, _vp,
+                                   C.c_size_t, _vp]),
+    "pdmp_tanh_fit": (_i32, [_P(pdmp_tanh_net), _vp, _vp, _i64, _P(pdmp_fit_opts), _vp, _vp,
+                             C.c_size_t, _vp]),
     "pdmp_mlp_pack": (_i32, [_P(pdmp_mlp), _vp, _vp]),
     "pdmp_mlp_acts_size": (C.c_size_t, [_P(pdmp_mlp), _i64]),
     "pdmp_mlp_workspace_size": (C.c_size_t, [_P(pdmp_mlp), _i64]),

@@ -214,6 +214,21 @@ int32_t launch_sum(const float *x, int64_t n, int mode, double scale, float *out
     return check_launch("k_sum");
 }
 
+int32_t launch_sum_rows(const float *part, int rows, int64_t m, double scale, const float *add,
+                        float add_scale, float *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_rows, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, st, part, rows, m,
+                       scale, add, add_scale, out);
+    return check_launch("k_sum_rows");
+}
+
+int32_t launch_sum_with(const float *x, int64_t n, double sa, const double *b, int nb, double sb,
+                        float *out, double *parts, hipStream_t st) {
+    const int nblk = red_blocks(n);
+    hipLaunchKernelGGL(k_sum_partial, dim3(nblk), dim3(kRedBlock), 0, st, x, n, 0, parts);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedBlock), 0, st, parts, nblk, sa, b, nb, sb, out);
+    return check_launch("k_sum_with");
+}
+
 // Backward of the logit: grad_w[0..M) = Phi^T g_eff, grad_w[M] = sum g_eff,
 // grad_x = g (sigma'(s))? grad s.  `ws` holds partial rows, g_eff and reduce parts.
 int32_t launch_logit_bwd(int dim, const float *hinges, const float *weights, int M,

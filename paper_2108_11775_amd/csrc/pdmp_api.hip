@@ -550,4 +550,53 @@ int32_t pdmp_tanh_morph_samples(const pdmp_tanh_net *net, const float *in, float
                            (hipStream_t)stream);
 }
 
+size_t pdmp_tanh_fit_workspace_size(const pdmp_tanh_net *net, int64_t n) {
+    if (pdmp_tanh_num_params(net) < 0 || n < 1) return 0;
+    return tanh_fit_ws_bytes(*net, n);
+}
+
+static int32_t check_tanh_fit_args(const pdmp_tanh_net *net, const float *pts,
+                                   const uint8_t *labels, int64_t n, void *ws, size_t ws_bytes) {
+    int32_t st = check_tanh(net);
+    if (st) return st;
+    PDMP_REQUIRE(n >= 1, "n < 1");
+    PDMP_REQUIRE(pts && labels, "pts/labels NULL");
+    const size_t need = tanh_fit_ws_bytes(*net, n);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+        return PDMP_ENOMEM;
+    }
+    return PDMP_OK;
+}
+
+int32_t pdmp_tanh_loss_grad(const pdmp_tanh_net *net, const float *pts, const uint8_t *labels,
+                            int64_t n, float l2, float *loss, float *grad, void *ws,
+                            size_t ws_bytes, void *stream) {
+    int32_t st = check_tanh_fit_args(net, pts, labels, n, ws, ws_bytes);
+    if (st) return st;
+    PDMP_REQUIRE(grad != nullptr, "grad NULL");
+    PDMP_REQUIRE(std::isfinite(l2) && l2 >= 0.0f, "l2 must be finite and >= 0");
+    return launch_tanh_loss_grad(*net, pts, labels, n, l2, loss, grad, ws, (hipStream_t)stream);
+}
+
+int32_t pdmp_tanh_fit(const pdmp_tanh_net *net, const float *pts, const uint8_t *labels,
+                      int64_t n, const pdmp_fit_opts *opts, float *loss_out, void *ws,
+                      size_t ws_bytes, void *stream) {
+    int32_t st = check_tanh_fit_args(net, pts, labels, n, ws, ws_bytes);
+    if (st) return st;
+    PDMP_REQUIRE(opts != nullptr, "opts NULL");
+    PDMP_REQUIRE(opts->optimizer == 1, "the network fit uses Adam (optimizer 1)");
+    PDMP_REQUIRE(opts->steps >= 0, "steps < 0");
+    PDMP_REQUIRE(opts->adam_m && opts->adam_v, "adam_m/adam_v NULL");
+    PDMP_REQUIRE(std::isfinite(opts->lr) && std::isfinite(opts->l2) && opts->l2 >= 0.0f,
+                 "lr/l2 invalid");
+    PDMP_REQUIRE(opts->beta1 >= 0.0f && opts->beta1 < 1.0f && opts->beta2 >= 0.0f &&
+                     opts->beta2 < 1.0f && opts->eps > 0.0f,
+                 "Adam hyperparameters out of range");
+    PDMP_REQUIRE(opts->t0 >= 0, "t0 < 0");
+    return launch_tanh_fit(*net, pts, labels, n, opts->steps, opts->lr, opts->l2, opts->beta1,
+                           opts->beta2, opts->eps, opts->adam_m, opts->adam_v, opts->t0, loss_out,
+                           ws, (hipStream_t)stream);
+}
+
 }  // extern "C"

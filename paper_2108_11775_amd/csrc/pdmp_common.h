@@ -143,6 +143,19 @@ int32_t launch_grid_wgrad(int dim, const float *hinges, int M, const int *grid, 
                           const float *x, int64_t n, const float *g, float *part, int *rows,
                           hipStream_t st);
 size_t wgrad_rows_max(int64_t n);
+// out[j] = scale * sum_r part[r m + j] (+ add_scale add[j]), fixed order.
+int32_t launch_sum_rows(const float *part, int rows, int64_t m, double scale, const float *add,
+                        float add_scale, float *out, hipStream_t st);
+// out = sa * sum(x[0..n)) + sb * sum(b[0..nb)), fixed order; parts: 1024 doubles.
+int32_t launch_sum_with(const float *x, int64_t n, double sa, const double *b, int nb, double sb,
+                        float *out, double *parts, hipStream_t st);
+size_t tanh_fit_ws_bytes(const pdmp_tanh_net &net, int64_t n);
+int32_t launch_tanh_loss_grad(const pdmp_tanh_net &net, const float *x, const uint8_t *y,
+                              int64_t n, float l2, float *loss, float *grad, void *ws,
+                              hipStream_t st);
+int32_t launch_tanh_fit(const pdmp_tanh_net &net, const float *x, const uint8_t *y, int64_t n,
+                        int steps, float lr, float l2, float b1, float b2, float eps, float *m,
+                        float *v, int t0, float *loss_out, void *ws, hipStream_t st);
 // The tanh occupancy network: kEval, kGrad or kMorph over n >= 1 points.
 int32_t launch_tanh_net(const pdmp_tanh_net &net, int mode, const float *x, int64_t n, int T,
                         float eta, float *c_out, float *s_out, float *g_out, float *x_out,

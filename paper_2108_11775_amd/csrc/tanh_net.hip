@@ -311,4 +311,400 @@ int32_t launch_tanh_net(const pdmp_tanh_net &net, int mode, const float *x, int6
     return check_launch("k_tanh_net");
 }
 
+
+// ------------------------------------------------------------------ fit ---
+//
+// BCE fit of the network (Sec. 3.1), full batch over n labelled points.  One step:
+//   k_tanh_fb      per point: forward, r = (sigma(s) - y)/n, the per-point BCE, and
+//                  the reverse pass e_L = r v (1 - a_L^2), e_l = (1 - a_l^2) W_l^T e_{l+1};
+//                  stores a_l and e_l ([layer][unit][point], coalesced per unit);
+//   k_tanh_wgrad   dW_l = sum_i e_{l+1,i} [a_{l,i}; 1]^T (the bias as a column of ones;
+//                  layer L: r against [a_L; 1]) as 16 x 16 tiles on FP32 MFMA with the
+//                  points as contraction index, in fixed point ranges -> partial rows;
+//   k_sum_rows     fixed-order sum of the partial rows (fit.hip);
+//   k_tanh_decay   + l2 w on the weight entries (not the biases);
+//   Adam           (fit.hip).
+
+template <int DIM, int NT, int L>
+__global__ void __launch_bounds__(kTnBlock)
+k_tanh_fb(const float *__restrict__ P, int H, const float *__restrict__ x,
+          const uint8_t *__restrict__ y, int64_t n, float inv_n, float *__restrict__ A,
+          float *__restrict__ E, float *__restrict__ r_out, float *__restrict__ bce_out) {
+    __shared__ __attribute__((aligned(16))) TnLds<DIM, NT, L> S;
+    tn_stage<DIM, NT, L>(S, P, H);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, quad = lane >> 4, u4 = 4 * quad;
+    const int64_t tiles = (n + kTnPts - 1) / kTnPts;
+    const int64_t wstride = (int64_t)gridDim.x * (kTnBlock / 64);
+    for (int64_t tile = (int64_t)blockIdx.x * (kTnBlock / 64) + (threadIdx.x >> 6); tile < tiles;
+         tile += wstride) {
+        const int64_t i = tile * kTnPts + (lane & 15);
+        const bool ok = i < n;
+        const int64_t ic = ok ? i : n - 1;
+        // opaque per tile: keeps the fragment reads and the per-unit store offsets
+        // inside the loop instead of hoisting them all into registers
+        int lf = lane;
+        asm volatile("" : "+v"(lf));
+        size_t nn = (size_t)n;
+        asm volatile("" : "+s"(nn));
+        float xv[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) xv[k] = x[(size_t)k * n + ic];
+        f32x4_tn a[NT];
+        f32x4_tn d[L][NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int u0 = 16 * t + u4;
+            const float4 bb = tn_ld4(&S.bias[0][u0]);
+            float z[4] = {bb.x, bb.y, bb.z, bb.w};
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                const float4 w = tn_ld4(&S.w0t[k][u0]);
+                z[0] = fmaf(w.x, xv[k], z[0]);
+                z[1] = fmaf(w.y, xv[k], z[1]);
+                z[2] = fmaf(w.z, xv[k], z[2]);
+                z[3] = fmaf(w.w, xv[k], z[3]);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float av, dv;
+                tanh_slope(z[v], av, dv);
+                a[t][v] = av;
+                d[0][t][v] = dv;
+                if (ok && u0 + v < H) A[(size_t)(u0 + v) * nn + i] = av;
+            }
+        }
+#pragma unroll
+        for (int l = 1; l < L; ++l) {
+            f32x4_tn z[NT];
+#pragma unroll
+            for (int to = 0; to < NT; ++to) {
+                const float4 bb = tn_ld4(&S.bias[l][16 * to + u4]);
+                z[to][0] = bb.x;
+                z[to][1] = bb.y;
+                z[to][2] = bb.z;
+                z[to][3] = bb.w;
+            }
+            const float *fw = S.fw + (l - 1) * NT * NT * 256;
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int to = 0; to < NT; ++to)
+                        z[to] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            fw[((to * NT + ti) * 4 + v) * 64 + lf], a[ti][v], z[to], 0, 0, 0);
+#pragma unroll
+            for (int to = 0; to < NT; ++to)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    float av, dv;
+                    tanh_slope(z[to][v], av, dv);
+                    a[to][v] = av;
+                    d[l][to][v] = dv;
+                    const int u = 16 * to + u4 + v;
+                    if (ok && u < H) A[((size_t)l * H + u) * nn + i] = av;
+                }
+        }
+        float p = 0.0f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const float4 vv = tn_ld4(&S.vo[16 * t + u4]);
+            p = fmaf(vv.x, a[t][0], p);
+            p = fmaf(vv.y, a[t][1], p);
+            p = fmaf(vv.z, a[t][2], p);
+            p = fmaf(vv.w, a[t][3], p);
+        }
+        const float s = tn_sum4(p) + S.bo;
+        const bool yes = ok && y[ic];
+        const float yv = yes ? 1.0f : 0.0f;
+        // dBCE/ds = sigma(s) - y as sigma(s) (y = 0) or -sigma(-s) (y = 1): full relative
+        // accuracy also where sigma(s) rounds to y; e1 = exp(-|s|)
+        const float e1 = exp2_fast(-fabsf(s) * kLog2e);
+        const float inv = 1.0f / (1.0f + e1);
+        const float sig_pos = s >= 0.0f ? inv : e1 * inv, sig_neg = s >= 0.0f ? e1 * inv : inv;
+        const float r = ok ? (yes ? -sig_neg : sig_pos) * inv_n : 0.0f;
+        if (ok && quad == 0) {
+            r_out[i] = r;
+            bce_out[i] = fmaxf(s, 0.0f) - yv * s + log1pf(e1);
+        }
+        f32x4_tn e[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const float4 vv = tn_ld4(&S.vo[16 * t + u4]);
+            e[t][0] = r * vv.x * d[L - 1][t][0];
+            e[t][1] = r * vv.y * d[L - 1][t][1];
+            e[t][2] = r * vv.z * d[L - 1][t][2];
+            e[t][3] = r * vv.w * d[L - 1][t][3];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int u = 16 * t + u4 + v;
+                if (ok && u < H) E[((size_t)(L - 1) * H + u) * nn + i] = e[t][v];
+            }
+        }
+#pragma unroll
+        for (int l = L - 1; l >= 1; --l) {
+            f32x4_tn G[NT];
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti) G[ti][0] = G[ti][1] = G[ti][2] = G[ti][3] = 0.0f;
+            const float *bw = S.bw + (l - 1) * NT * NT * 256;
+#pragma unroll
+            for (int to = 0; to < NT; ++to)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int ti = 0; ti < NT; ++ti)
+                        G[ti] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            bw[((ti * NT + to) * 4 + v) * 64 + lf], e[to][v], G[ti], 0, 0, 0);
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    e[ti][v] = G[ti][v] * d[l - 1][ti][v];
+                    const int u = 16 * ti + u4 + v;
+                    if (ok && u < H) E[((size_t)(l - 1) * H + u) * nn + i] = e[ti][v];
+                }
+        }
+    }
+}
+
+// Tiles of the weight-gradient products, layer by layer (at most kTnMaxLayers + 1).
+constexpr int kTnMaxLayers = 4;
+struct TnGradTiles {
+    int start[kTnMaxLayers + 2];  // first global tile of layer l; start[L+1] = total
+    int ct[kTnMaxLayers + 1];     // column tiles of layer l
+};
+
+// Partial rows of the loss gradient: block (tile, split).  Layer l < L: rows o of
+// E_{l+1} (H), columns i of [a_l; 1] (n_l + 1, a_0 = x); layer L: the single row r
+// against [a_L; 1].  Points of split s: [s kps, min(n, (s+1) kps)).
+__global__ void __launch_bounds__(256)
+k_tanh_wgrad(int dim, int H, int L, const float *__restrict__ x, const float *__restrict__ A,
+             const float *__restrict__ E, const float *__restrict__ r, int64_t n, int64_t kps,
+             TnGradTiles tt, int64_t np, float *__restrict__ part) {
+    __shared__ float red[256];
+    const int tile = blockIdx.x;
+    int l = 0;
+    while (l < L && tile >= tt.start[l + 1]) ++l;
+    const int lt = tile - tt.start[l];
+    const int ro = lt / tt.ct[l], co = lt % tt.ct[l];
+    const int rows = l < L ? H : 1;
+    const int nl = l == 0 ? dim : H;  // columns before the ones column
+    const float *X = l < L ? E + (size_t)l * H * n : r;
+    const float *Y = l == 0 ? x : A + (size_t)(l - 1) * H * n;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int orow = 16 * ro + (lane & 15), icol = 16 * co + (lane & 15);
+    const int64_t ks = (int64_t)blockIdx.y * kps;
+    const int64_t ke = ks + kps < n ? ks + kps : n;
+    f32x4_tn acc;
+    acc[0] = acc[1] = acc[2] = acc[3] = 0.0f;
+    for (int64_t k0 = ks + 16 * wv; k0 < ke; k0 += 64) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t k = k0 + 4 * (lane >> 4) + j;
+            const bool kin = k < ke;
+            float av = 0.0f, bv = 0.0f;
+            if (kin && orow < rows) av = X[(size_t)orow * n + k];
+            if (kin && icol < nl) bv = Y[(size_t)icol * n + k];
+            else if (kin && icol == nl) bv = 1.0f;
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+        }
+    }
+    // wave sums in a fixed order: ((w0 + w1) + w2) + w3; entry v of lane l is
+    // (row 4(l/16) + v, column l%16) of the tile
+    for (int w = 0; w < 4; ++w) {
+        if (wv == w)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float &dst = red[(4 * (lane >> 4) + v) * 16 + (lane & 15)];
+                dst = w == 0 ? acc[v] : dst + acc[v];
+            }
+        __syncthreads();
+    }
+    const int o = 16 * ro + (threadIdx.x >> 4), i = 16 * co + (threadIdx.x & 15);
+    if (o >= rows || i > nl) return;
+    const int64_t off = (int64_t)(l == 0 ? 0 : (int64_t)H * dim + H + (int64_t)(l - 1) * (H * H + H));
+    int64_t j;
+    if (l < L) j = i < nl ? off + (int64_t)o * nl + i : off + (int64_t)H * nl + o;
+    else j = off + i;  // v entries, then b_o at i == H
+    part[(size_t)blockIdx.y * np + j] = red[threadIdx.x];
+}
+
+// grad += l2 w on the weight entries (W_l and v), not on the biases.
+__global__ void __launch_bounds__(256)
+k_tanh_decay(float *grad, const float *__restrict__ P, int dim, int H, int L, int64_t np,
+             float l2) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= np) return;
+    int64_t off = 0;
+    bool w = false;
+    for (int l = 0; l <= L; ++l) {
+        const int64_t nw = l < L ? (int64_t)H * (l == 0 ? dim : H) : H;
+        const int64_t nb = l < L ? H : 1;
+        if (j < off + nw) {
+            w = true;
+            break;
+        }
+        if (j < off + nw + nb) break;
+        off += nw + nb;
+    }
+    if (w) grad[j] = fmaf(l2, P[j], grad[j]);
+}
+
+// out[0] = sum of squares of the weight entries, one block, fixed order.
+__global__ void __launch_bounds__(256)
+k_tanh_wsq(const float *__restrict__ P, int dim, int H, int L, double *out) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    int64_t off = 0;
+    for (int l = 0; l <= L; ++l) {
+        const int64_t nw = l < L ? (int64_t)H * (l == 0 ? dim : H) : H;
+        for (int64_t j = threadIdx.x; j < nw; j += 256) {
+            const double w = P[off + j];
+            acc += w * w;
+        }
+        off += nw + (l < L ? H : 1);
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s2 = 128; s2 >= 1; s2 >>= 1) {
+        if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+static void tn_grad_tiles(int dim, int H, int L, TnGradTiles &tt) {
+    int acc = 0;
+    for (int l = 0; l <= L; ++l) {
+        const int rows = l < L ? H : 1, cols = (l == 0 ? dim : H) + 1;
+        tt.start[l] = acc;
+        tt.ct[l] = (cols + 15) / 16;
+        acc += ((rows + 15) / 16) * tt.ct[l];
+    }
+    tt.start[L + 1] = acc;
+}
+
+static int tn_splits(int64_t n, int tiles, int64_t &kps) {
+    int64_t s = (1024 + tiles - 1) / tiles;
+    const int64_t smax = (n + 63) / 64;
+    if (s > smax) s = smax;
+    if (s < 1) s = 1;
+    kps = ((n + s - 1) / s + 63) / 64 * 64;
+    return (int)((n + kps - 1) / kps);
+}
+
+static size_t al256t(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t tanh_fit_ws_bytes(const pdmp_tanh_net &net, int64_t n) {
+    const int64_t H = net.hidden, L = net.n_hidden;
+    const int64_t np = H * net.dim + H + (L - 1) * (H * H + H) + H + 1;
+    TnGradTiles tt;
+    tn_grad_tiles(net.dim, net.hidden, net.n_hidden, tt);
+    int64_t kps;
+    const int S = tn_splits(n, tt.start[L + 1], kps);
+    return 2 * al256t((size_t)(L * H * n) * 4) + 2 * al256t((size_t)n * 4) +
+           al256t((size_t)S * np * 4) + al256t((size_t)np * 4) + al256t(1024 * 8) + al256t(8);
+}
+
+template <int DIM, int NT, int L>
+static void tn_fb_launch(const pdmp_tanh_net &net, const float *x, const uint8_t *y, int64_t n,
+                         float *A, float *E, float *r, float *bce, hipStream_t st) {
+    const int64_t tiles = (n + kTnPts - 1) / kTnPts;
+    int64_t blocks = (tiles + 3) / 4;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL((k_tanh_fb<DIM, NT, L>), dim3((unsigned)blocks), dim3(kTnBlock), 0, st,
+                       net.params, net.hidden, x, y, n, (float)(1.0 / (double)n), A, E, r, bce);
+}
+
+template <int DIM, int NT>
+static void tn_fb_depth(const pdmp_tanh_net &net, const float *x, const uint8_t *y, int64_t n,
+                        float *A, float *E, float *r, float *bce, hipStream_t st) {
+    switch (net.n_hidden) {
+        case 1: tn_fb_launch<DIM, NT, 1>(net, x, y, n, A, E, r, bce, st); break;
+        case 2: tn_fb_launch<DIM, NT, 2>(net, x, y, n, A, E, r, bce, st); break;
+        case 3: tn_fb_launch<DIM, NT, 3>(net, x, y, n, A, E, r, bce, st); break;
+        default: tn_fb_launch<DIM, NT, 4>(net, x, y, n, A, E, r, bce, st); break;
+    }
+}
+
+// Loss (nullable, device [1]) and gradient (device [np]) of the fit objective at the
+// current parameters.  `ws` holds tanh_fit_ws_bytes(net, n) bytes.
+int32_t launch_tanh_loss_grad(const pdmp_tanh_net &net, const float *x, const uint8_t *y,
+                              int64_t n, float l2, float *loss, float *grad, void *ws,
+                              hipStream_t st) {
+    const int dim = net.dim, H = net.hidden, L = net.n_hidden;
+    const int64_t np = (int64_t)H * dim + H + (int64_t)(L - 1) * (H * H + H) + H + 1;
+    TnGradTiles tt;
+    tn_grad_tiles(dim, H, L, tt);
+    int64_t kps;
+    const int S = tn_splits(n, tt.start[L + 1], kps);
+    char *p = (char *)ws;
+    float *A = (float *)p;
+    p += al256t((size_t)L * H * n * 4);
+    float *E = (float *)p;
+    p += al256t((size_t)L * H * n * 4);
+    float *r = (float *)p;
+    p += al256t((size_t)n * 4);
+    float *bce = (float *)p;
+    p += al256t((size_t)n * 4);
+    float *part = (float *)p;
+    p += al256t((size_t)S * np * 4);
+    p += al256t((size_t)np * 4);  // spare (keeps the layout of the fit workspace)
+    double *rparts = (double *)p;
+    p += al256t(1024 * 8);
+    double *wsq = (double *)p;
+
+#define PDMP_TNFB(D)                                                                 \
+    if (H <= 16) tn_fb_depth<D, 1>(net, x, y, n, A, E, r, bce, st);                  \
+    else if (H <= 32) tn_fb_depth<D, 2>(net, x, y, n, A, E, r, bce, st);             \
+    else tn_fb_depth<D, 4>(net, x, y, n, A, E, r, bce, st)
+    if (dim == 2) {
+        PDMP_TNFB(2);
+    } else {
+        PDMP_TNFB(3);
+    }
+#undef PDMP_TNFB
+    if (int32_t e = check_launch("k_tanh_fb")) return e;
+    hipLaunchKernelGGL(k_tanh_wgrad, dim3((unsigned)tt.start[L + 1], (unsigned)S), dim3(256), 0, st,
+                       dim, H, L, x, A, E, r, n, kps, tt, np, part);
+    if (int32_t e = check_launch("k_tanh_wgrad")) return e;
+    if (int32_t e = launch_sum_rows(part, S, np, 1.0, nullptr, 0.0f, grad, st)) return e;
+    hipLaunchKernelGGL(k_tanh_decay, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, grad,
+                       net.params, dim, H, L, np, l2);
+    if (int32_t e = check_launch("k_tanh_decay")) return e;
+    if (loss) {
+        hipLaunchKernelGGL(k_tanh_wsq, dim3(1), dim3(256), 0, st, net.params, dim, H, L, wsq);
+        if (int32_t e = check_launch("k_tanh_wsq")) return e;
+        if (int32_t e = launch_sum_with(bce, n, 1.0 / (double)n, wsq, 1, 0.5 * (double)l2, loss,
+                                        rparts, st))
+            return e;
+    }
+    return PDMP_OK;
+}
+
+// `steps` full-batch Adam steps on the fit objective; the parameters (net.params)
+// are updated in place, m and v are the Adam state, the step counter continues from t0.
+int32_t launch_tanh_fit(const pdmp_tanh_net &net, const float *x, const uint8_t *y, int64_t n,
+                        int steps, float lr, float l2, float b1, float b2, float eps, float *m,
+                        float *v, int t0, float *loss_out, void *ws, hipStream_t st) {
+    const int dim = net.dim, H = net.hidden, L = net.n_hidden;
+    const int64_t np = (int64_t)H * dim + H + (int64_t)(L - 1) * (H * H + H) + H + 1;
+    TnGradTiles tt;
+    tn_grad_tiles(dim, H, L, tt);
+    int64_t kps;
+    const int S = tn_splits(n, tt.start[L + 1], kps);
+    char *p = (char *)ws;
+    p += 2 * al256t((size_t)L * H * n * 4) + 2 * al256t((size_t)n * 4) + al256t((size_t)S * np * 4);
+    float *grad = (float *)p;
+    for (int t = 0; t < steps; ++t) {
+        if (int32_t e = launch_tanh_loss_grad(net, x, y, n, l2, loss_out ? loss_out + t : nullptr,
+                                              grad, ws, st))
+            return e;
+        if (int32_t e = launch_adam((float *)net.params, grad, m, v, np, 0, t0 + t + 1, lr, b1, b2,
+                                    eps, 0.0f, st))
+            return e;
+    }
+    return PDMP_OK;
+}
 }  // namespace pdmp

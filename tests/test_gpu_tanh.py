@@ -155,3 +155,81 @@ def test_free_fraction_rises_after_gpu_morph():
     before = 1 - int(host(h0)[0]) / x0.shape[1]
     after = 1 - int(host(h1)[0]) / x0.shape[1]
     assert after > before + 0.1, (before, after)
+
+
+# ---------------------------------------------------------------- the fit ---
+
+def _fit_data(cfg, n):
+    dc, dr = I.discs(cfg.cfg_id, cfg.n_discs, cfg.lo, cfg.hi, cfg.r_min, cfg.r_max)
+    pts = I.uniform_points(cfg.cfg_id, K.STREAM_FIT, 2, n, cfg.lo, cfg.hi)
+    return pts, O.label_discs(dc, dr, pts)
+
+
+def _check_loss_grad(gnet, onet, pts, y, l2):
+    loss, g = P.tanh_loss_grad(gnet, dev(pts), dev(y), l2)
+    L, g_r, gsc = O.tanh_loss_grad(onet, pts, y, l2, with_scale=True)
+    assert abs(host(loss)[0] - L) <= 1e-6 * L
+    err = np.abs(host(g) - g_r)
+    assert np.all(err <= TOL * gsc + 1e-12), np.max(err / (gsc + 1e-30))
+
+
+@pytest.mark.parametrize("n", [1, 63, 10000])
+def test_loss_grad_fitted_network(n):
+    require_gpu()
+    tc = K.TANH
+    gnet, onet = _pair(2, tc.hidden, tc.layers, _golden(K.C2))
+    pts, y = _fit_data(K.C2, n)
+    _check_loss_grad(gnet, onet, pts, y, tc.l2[1])
+
+
+@pytest.mark.parametrize("dim,H,L", [(2, 5, 1), (3, 16, 2), (2, 40, 3), (3, 64, 4)])
+def test_loss_grad_shapes(dim, H, L):
+    require_gpu()
+    rng = np.random.default_rng(7 * H + L)
+    params = rng.normal(0, 1.0 / np.sqrt(max(H, dim)), O.tanh_nparams(dim, H, L))
+    gnet, onet = _pair(dim, H, L, params)
+    pts = rng.uniform(-2, 2, (dim, 3001)).astype(np.float32)
+    y = (rng.uniform(size=3001) < 0.35).astype(np.uint8)
+    _check_loss_grad(gnet, onet, pts, y, 1e-3)
+
+
+def test_fit_adam_one_step_from_identical_state():
+    require_gpu()
+    tc = K.TANH
+    params = _golden(K.C1)
+    gnet, onet = _pair(2, tc.hidden, tc.layers, params)
+    pts, y = _fit_data(K.C1, 4000)
+    rng = np.random.default_rng(5)
+    m0 = (rng.normal(size=params.size) * 1e-3).astype(np.float32)
+    v0 = (rng.uniform(size=params.size) * 1e-5).astype(np.float32)
+    m_d, v_d = dev(m0), dev(v0)
+    lr, l2 = float(np.float32(tc.lr)), float(np.float32(tc.l2[0]))
+    b1, b2, eps = (float(np.float32(v)) for v in (tc.beta1, tc.beta2, tc.eps))
+    P.tanh_fit(gnet, dev(pts), dev(y), 1, lr, l2, b1, b2, eps, adam_m=m_d, adam_v=v_d, t0=3)
+    _, g, gsc = O.tanh_loss_grad(onet, pts, y, l2, with_scale=True)
+    p_r, m_r, v_r = params.astype(np.float64), m0.astype(np.float64), v0.astype(np.float64)
+    O.adam_step(p_r, g, m_r, v_r, 4, lr, b1, b2, eps)
+    # the moments follow the gradient tightly; Adam's step direction m/sqrt(v) is
+    # ill-conditioned where the gradient is near zero, so the step is compared to lr
+    assert np.all(np.abs(host(m_d) - m_r) <= TOL * (0.1 * gsc + np.abs(m_r)) + 1e-12)
+    assert np.abs(host(gnet.params) - p_r).max() <= 2e-3 * lr
+
+
+def test_fit_reduces_the_loss_and_is_deterministic():
+    require_gpu()
+    tc = K.TANH
+    cfg = K.C1
+    pts, y = _fit_data(cfg, cfg.fit_points)
+    init = I.tanh_init(cfg.cfg_id, 2, tc.hidden, tc.layers, cfg.hi)
+    runs = []
+    for _ in range(2):
+        gnet = P.TanhNet(2, tc.hidden, tc.layers, dev(init.copy()))
+        loss = P.tanh_fit(gnet, dev(pts), dev(y), 200, tc.lr, tc.l2[0])
+        runs.append((host(loss), host(gnet.params)))
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    loss = runs[0][0]
+    assert loss[-1] < 0.5 * loss[0]
+    # the loss the GPU reports for step 0 is the oracle's at the initial parameters
+    L0, _ = O.tanh_loss_grad(O.TanhNet(2, tc.hidden, tc.layers, init.astype(np.float64)), pts, y,
+                             tc.l2[0])
+    assert abs(loss[0] - L0) <= 1e-6 * L0

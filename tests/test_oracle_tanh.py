@@ -177,3 +177,38 @@ def test_error_scale_bounds_a_float32_evaluation():
         e = ((layers[li][0].astype(f32).T @ e) * ds[li - 1]).astype(f32)
     g32 = layers[0][0].astype(f32).T @ e
     assert np.all(np.abs(g32 - g64).max(axis=0) <= 1e-5 * gabs)
+
+
+def test_gradient_error_scale_bounds_a_float32_evaluation():
+    """A plain float32 loss gradient stays within 1e-5 of the oracle's gradient error
+    scale, entry by entry."""
+    net = _net(2, 24, 3, 31, scale=0.4)
+    rng = np.random.default_rng(32)
+    pts = rng.uniform(-3, 3, (2, 800))
+    y = (rng.uniform(size=800) < 0.3).astype(np.uint8)
+    l2 = 1e-3
+    _, g64, gsc = O.tanh_loss_grad(net, pts, y, l2, with_scale=True)
+    layers, (v, bo) = O.tanh_layers(net)
+    f32 = np.float32
+    n = pts.shape[1]
+    a = pts.astype(f32)
+    ins, ds = [a], []
+    for W, b in layers:
+        a = np.tanh(W.astype(f32) @ a + b.astype(f32)[:, None]).astype(f32)
+        ins.append(a)
+        ds.append((1 - a * a).astype(f32))
+    s = v.astype(f32) @ a + f32(bo)
+    r = np.where(y == 1, -1 / (1 + np.exp(s)), 1 / (1 + np.exp(-s))).astype(f32) / f32(n)
+    grads = []
+    e = (v.astype(f32)[:, None] * ds[-1] * r[None, :]).astype(f32)
+    for li in range(len(layers) - 1, -1, -1):
+        W = layers[li][0].astype(f32)
+        grads.append(((e @ ins[li].T) + f32(l2) * W, e.sum(axis=1)))
+        if li > 0:
+            e = ((W.T @ e) * ds[li - 1]).astype(f32)
+    flat = []
+    for gW, gb in reversed(grads):
+        flat += [gW.ravel(), gb]
+    flat += [ins[-1] @ r + f32(l2) * v.astype(f32), np.array([r.sum()])]
+    g32 = np.concatenate(flat)
+    assert np.all(np.abs(g32 - g64) <= 1e-5 * gsc + 1e-12)
