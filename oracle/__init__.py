@@ -91,6 +91,11 @@ def _load():
                                   C.c_double, _dp, _dp]),
         "orc_tanh_loss_grad": (C.c_double, [C.c_int, C.c_int, C.c_int, _dp, _dp, _u8p, _i64,
                                             C.c_double, _dp, _dp]),
+        "orc_morph_logdet": (None, [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_double, _dp,
+                                    _i64, C.c_int, C.c_double, _dp, _dp, _dp]),
+        "orc_morph_inverse": (None, [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_double, _dp,
+                                     _i64, C.c_int, C.c_double, C.c_int, _dp, _dp, _dp, _dp]),
+        "orc_mixture_coins": (None, [C.c_uint64, C.c_uint32, _i64, C.c_double, _u8p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -235,6 +240,35 @@ def morph_ws(occ: Occupancy, x, T: int, eta: float, diag: bool = False, traj: bo
     if traj:
         res += [tr]
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def morph_logdet(occ: Occupancy, x, T: int, eta: float):
+    """(x_T, logdet, ldscale): the forward morph with sum_k log|det(I - eta Hc(x_k))|
+    and the FP32 error scale of that sum."""
+    x = _d(x)
+    dim, n = x.shape
+    out, ld, sc = _zeros(dim, n), _zeros(n), _zeros(n)
+    _load().orc_morph_logdet(*occ.args(), _P(x), n, int(T), float(eta), _P(out), _P(ld), _P(sc))
+    return out, ld, sc
+
+
+def morph_inverse(occ: Occupancy, z, T: int, eta: float, iters: int):
+    """(y, logdet, ldscale, resid): the inverse of the T-step morph by fixed point
+    (iters iterations per step, in reverse step order), the forward log-determinant
+    along the reconstructed path and the largest fixed-point residual."""
+    z = _d(z)
+    dim, n = z.shape
+    y, ld, sc, r = _zeros(dim, n), _zeros(n), _zeros(n), _zeros(n)
+    _load().orc_morph_inverse(*occ.args(), _P(z), n, int(T), float(eta), int(iters), _P(y),
+                              _P(ld), _P(sc), _P(r))
+    return y, ld, sc, r
+
+
+def mixture_coins(seed: int, stream: int, n: int, eps: float) -> np.ndarray:
+    """keep[i] = 1 where sample i stays at its prior value in the epsilon mixture."""
+    out = np.zeros(n, dtype=np.uint8)
+    _load().orc_mixture_coins(int(seed), int(stream), int(n), float(eps), _P(out, _u8p))
+    return out
 
 
 # --------------------------------------------------------------------- fit ---

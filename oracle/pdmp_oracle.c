@@ -1299,3 +1299,140 @@ double orc_tanh_loss_grad(int dim, int H, int L, const double *P, const double *
     free(lsum);
     return loss + 0.5 * l2 * wsq;
 }
+
+/* ------------------------------------------------------------------------- */
+/* The inverse of the morph and the log-determinant of its Jacobian (Sec. 3.2: */
+/* the flow phi has the inverse obtained by integrating the reversed field;    */
+/* for the explicit-Euler map the exact inverse of one step                    */
+/* x_{k+1} = x_k - eta grad c(x_k) is the fixed point x_k = x_{k+1} + eta      */
+/* grad c(x_k), a contraction when eta Lip(grad c) < 1), and the epsilon       */
+/* mixture with the prior (Sec. 3.3).                                          */
+/* ------------------------------------------------------------------------- */
+
+/* det of a dim x dim matrix (dim <= 3), row-major. */
+static double det_small(int dim, const double *A) {
+    if (dim == 1) return A[0];
+    if (dim == 2) return A[0] * A[3] - A[1] * A[2];
+    return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+           A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+/* log|det(I - eta Hc(x))| at one point and the error scale of that term for an FP32
+ * evaluation: the Hessian entries carry the scale
+ *   Habs = sigma' Hs_abs + |sigma''| (S_abs |Hs|_max + 2 |grad s| G_raw + |grad s|^2)
+ *          + |sigma'''| S_abs |grad s|^2,
+ * Hs_abs = l^-2 sum |w| phi (|x - h|^2 / l^2 + 1), and a perturbation dH of the entries
+ * moves det by at most eta |dH| dim (1 + eta |H|_max dim)^(dim-1). */
+static double step_logdet(int dim, int M, const double *h, const double *w, double beta,
+                          double ell, const double *x, double eta, double *scale) {
+    occ_val o;
+    rbf_val v;
+    occ_point(dim, M, h, w, beta, ell, x, 1, &o, &v);
+    double A[ORC_MAX_DIM * ORC_MAX_DIM] = {0};
+    double hmax = 0.0, hsmax = 0.0;
+    for (int a = 0; a < dim; ++a)
+        for (int b = 0; b < dim; ++b) {
+            A[a * dim + b] = (a == b ? 1.0 : 0.0) - eta * o.H[a * dim + b];
+            if (fabs(o.H[a * dim + b]) > hmax) hmax = fabs(o.H[a * dim + b]);
+            if (fabs(v.Hs[a * dim + b]) > hsmax) hsmax = fabs(v.Hs[a * dim + b]);
+        }
+    double det = det_small(dim, A);
+    if (scale) {
+        double il2 = 1.0 / (ell * ell), habs = 0.0;
+        for (int j = 0; j < M; ++j) {
+            double r2 = 0.0;
+            for (int k = 0; k < dim; ++k) {
+                double d = x[k] - h[(int64_t)k * M + j];
+                r2 += d * d;
+            }
+            habs += fabs(w[j]) * exp(-0.5 * r2 * il2) * il2 * (r2 * il2 + 1.0);
+        }
+        double c = o.c, d1 = o.dc, d2 = d1 * (1.0 - 2.0 * c), d3 = d1 * (1.0 - 6.0 * c * (1.0 - c));
+        double gn = 0.0;
+        for (int k = 0; k < dim; ++k) gn += v.gs[k] * v.gs[k];
+        double Habs = d1 * habs + fabs(d2) * (v.sabs * hsmax + 2.0 * sqrt(gn) * v.graw + gn) +
+                      fabs(d3) * v.sabs * gn;
+        double grow = pow(1.0 + eta * hmax * dim, dim - 1);
+        *scale = eta * Habs * dim * grow / fabs(det);
+    }
+    return log(fabs(det));
+}
+
+/* Forward morph with the log-determinant of its Jacobian,
+ *   logdet = sum_k log|det(I - eta Hc(x_k))|  (so p_z(z) = p_y(y) exp(-logdet)),
+ * and ldscale = the sum of the per-step error scales (both nullable). */
+void orc_morph_logdet(int dim, int M, const double *h, const double *w, double beta, double ell,
+                      const double *xin, int64_t n, int T, double eta, double *xout,
+                      double *logdet, double *ldscale) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double x[ORC_MAX_DIM];
+        for (int k = 0; k < dim; ++k) x[k] = xin[(int64_t)k * n + i];
+        double ld = 0.0, sc = 0.0;
+        for (int t = 0; t < T; ++t) {
+            double s1;
+            ld += step_logdet(dim, M, h, w, beta, ell, x, eta, &s1);
+            sc += s1;
+            occ_val o;
+            occ_point(dim, M, h, w, beta, ell, x, 0, &o, NULL);
+            for (int k = 0; k < dim; ++k) x[k] = x[k] - eta * o.g[k];
+        }
+        for (int k = 0; k < dim; ++k) xout[(int64_t)k * n + i] = x[k];
+        if (logdet) logdet[i] = ld;
+        if (ldscale) ldscale[i] = sc;
+    }
+}
+
+/* Inverse of the T-step morph by fixed point, step by step in reverse: from
+ * z = x_T, for each step x^(0) = x_{k+1}, x^(j+1) = x_{k+1} + eta grad c(x^(j)) for
+ * j < iters, and x_k = x^(iters).  resid (nullable) gets the largest fixed-point
+ * residual |x_k - x_{k+1} - eta grad c(x_k)|_inf over the steps; logdet and ldscale
+ * (nullable) the forward log-determinant along the reconstructed path, evaluated at
+ * each x_k. */
+void orc_morph_inverse(int dim, int M, const double *h, const double *w, double beta, double ell,
+                       const double *zin, int64_t n, int T, double eta, int iters, double *yout,
+                       double *logdet, double *ldscale, double *resid) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double x[ORC_MAX_DIM], zt[ORC_MAX_DIM];
+        for (int k = 0; k < dim; ++k) x[k] = zin[(int64_t)k * n + i];
+        double ld = 0.0, sc = 0.0, rmax = 0.0;
+        for (int t = 0; t < T; ++t) {
+            for (int k = 0; k < dim; ++k) zt[k] = x[k];
+            for (int j = 0; j < iters; ++j) {
+                occ_val o;
+                occ_point(dim, M, h, w, beta, ell, x, 0, &o, NULL);
+                for (int k = 0; k < dim; ++k) x[k] = zt[k] + eta * o.g[k];
+            }
+            occ_val o;
+            occ_point(dim, M, h, w, beta, ell, x, 0, &o, NULL);
+            for (int k = 0; k < dim; ++k) {
+                double r = fabs(x[k] - zt[k] - eta * o.g[k]);
+                if (r > rmax) rmax = r;
+            }
+            if (logdet || ldscale) {
+                double s1;
+                ld += step_logdet(dim, M, h, w, beta, ell, x, eta, &s1);
+                sc += s1;
+            }
+        }
+        for (int k = 0; k < dim; ++k) yout[(int64_t)k * n + i] = x[k];
+        if (logdet) logdet[i] = ld;
+        if (ldscale) ldscale[i] = sc;
+        if (resid) resid[i] = rmax;
+    }
+}
+
+/* Epsilon mixture with the prior: sample i keeps its prior value iff u_i < eps, with
+ * u_i from word 0 of Philox4x32-10 at counter {i_lo, i_hi, 0xffffffff, stream} and
+ * key {seed_lo, seed_hi}, u = (word >> 8) 2^-24 (a counter the coordinates never use). */
+void orc_mixture_coins(uint64_t seed, uint32_t stream, int64_t n, double eps, uint8_t *keep) {
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t ctr[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), 0xffffffffu, stream};
+        uint32_t r[4];
+        orc_philox4x32_10(ctr, key, r);
+        double u = (double)(r[0] >> 8) * (1.0 / 16777216.0);
+        keep[i] = (uint8_t)(u < eps);
+    }
+}
