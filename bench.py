@@ -365,6 +365,61 @@ def tanh_morph(P, I, K, torch, dev):
                          "work": "4*(L-1)*H^2 FP32 MFMA flops per sample-step"}}
 
 
+def density_workload(P, I, K, torch, hl):
+    """Log-determinant of the morph, its inverse by fixed point and the epsilon
+    mixture on the large 2-D workload (same occupancy and prior batch as the headline)."""
+    cfg = K.C2
+    occ, x0, N = hl["sc"]["occ"], hl["x0"], hl["N"]
+    G0 = G1 = cfg.grid
+    out = torch.empty_like(x0)
+    P.morph_logdet(occ, x0, cfg.T, cfg.eta, out=out)
+    t = Timer(torch)
+    with t:
+        _, ld = P.morph_logdet(occ, x0, cfg.T, cfg.eta, out=out)
+    ld_ms = t.ms()
+    iters = 10
+    t = Timer(torch)
+    with t:
+        y, ld_inv, resid = P.morph_inverse(occ, out, cfg.T, cfg.eta, iters)
+    inv_ms = t.ms()
+    rt = (y - x0).abs().amax(dim=0)
+    ldd = (ld_inv - ld).abs().max().item()
+    seed = I.philox_seed(cfg.cfg_id)
+    eps = 0.1
+    P.mixture_samples(occ, seed, 7, [cfg.lo] * 2, [cfg.hi] * 2, N, eps, cfg.T, cfg.eta)
+    t = Timer(torch)
+    with t:
+        _, mixed, keep = P.mixture_samples(occ, seed, 7, [cfg.lo] * 2, [cfg.hi] * 2, N, eps,
+                                           cfg.T, cfg.eta)
+    mix_ms = t.ms()
+    dc_d, dr_d = hl["sc"]["discs"]
+    _, hm = P.label_points_discs(dc_d, dr_d, mixed, count=True)
+    # U, V, Q products (6 G0 G1 MFMA flops) per sample-step on the logdet path
+    ach = N * cfg.T * 6.0 * G0 * G1 / (ld_ms * 1e-3) / 1e12
+    inv_flops = N * cfg.T * (iters * 4.0 + 6.0) * G0 * G1
+    return {"workload": "log-det, inverse (fixed point, 10 iterations per step) and epsilon "
+                        "mixture (eps=0.1) of the 2-D large morph: 1,048,576 samples, 64x64 "
+                        "hinges, T=50, eta=0.02",
+            "logdet_ms": ld_ms, "logdet_samples_per_s": N / (ld_ms * 1e-3),
+            "inverse_ms": inv_ms, "inverse_samples_per_s": N / (inv_ms * 1e-3),
+            "inverse_residual_max": resid.max().item(),
+            "round_trip_err_max": rt.max().item(), "round_trip_err_median": rt.median().item(),
+            "logdet_roundtrip_diff_max": ldd,
+            "logdet_mean": ld.mean().item(),
+            "mixture_ms": mix_ms, "mixture_kept_fraction": keep.float().mean().item(),
+            "mixture_collision_free": 1 - hm.item() / N,
+            "roofline_logdet": {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA / 1e12,
+                                "unit": "TFLOP/s", "frac": ach * 1e12 / PEAK_FP32_MFMA,
+                                "kernel": "k_grid2d_inv<2,kLogdet>",
+                                "work": "6*G0*G1 FP32 MFMA flops per sample-step"},
+            "roofline_inverse": {"bound": "mfma",
+                                 "achieved": inv_flops / (inv_ms * 1e-3) / 1e12,
+                                 "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
+                                 "frac": inv_flops / (inv_ms * 1e-3) / PEAK_FP32_MFMA,
+                                 "kernel": "k_grid2d_inv<2,kInverse>",
+                                 "work": "(4*iters + 6)*G0*G1 FP32 MFMA flops per sample-step"}}
+
+
 def amortised(args, P, I, K, torch, world):
     from paper_2108_11775_amd import amortise
     c3, c5 = K.C3, K.C5
@@ -487,6 +542,10 @@ def main():
         try:
             wl["ws2d_small"] = small_2d(P, I, K, torch, dev)
             log("small 2-D done")
+            if hl["sc"]["occ"].grid:
+                wl["density_ws2d"] = density_workload(P, I, K, torch, hl)
+                log(f"log-det / inverse: {wl['density_ws2d']['logdet_ms']:.1f} / "
+                    f"{wl['density_ws2d']['inverse_ms']:.1f} ms")
             wl["tanh_ws2d"] = tanh_morph(P, I, K, torch, dev)
             log(f"tanh-network morph: {wl['tanh_ws2d']['morph_ms']:.2f} ms")
             world = arm_world(P, I, K, torch, dev)

@@ -154,6 +154,38 @@ int32_t pdmp_occupancy_grad(const pdmp_occupancy *occ, const float *x, int64_t n
 int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,
                            float *out, int64_t n, int32_t T, float eta, void *stream);
 
+/* ---- the density of the morphed samples and the inverse map (Sec. 3.2: the flow's
+ * inverse integrates the reversed field; the change of variables gives the
+ * density p_z(z) = p_y(y) / |det D phi(y)|).  Workspace morph only (no arm);
+ * 2-D hinges on a grid (occ->grid) take the FP32-MFMA path, any other hinge set
+ * (2-D or 3-D) a pairwise kernel.
+ * pdmp_morph_logdet: the plain morph of in into out (as pdmp_morph_samples) and
+ *   logdet [n] = sum_k log|det(I - eta Hc(x_k))| along each path (nullable).
+ * pdmp_morph_inverse: y = phi^{-1}(z) for the T-step explicit-Euler map, each step
+ *   inverted by fixed point in reverse order: x^(0) = x_{k+1},
+ *   x^(j+1) = x_{k+1} + eta grad c(x^(j)) for j < iters (>= 1), x_k = x^(iters) --
+ *   a contraction when eta Lip(grad c) < 1.  resid (nullable, [n]) gets the largest
+ *   residual |x_k - x_{k+1} - eta grad c(x_k)|_inf over the steps, logdet (nullable)
+ *   the forward log-determinant along the reconstructed path.
+ * in/z, out/y: [dim][n]; in == out allowed. */
+int32_t pdmp_morph_logdet(const pdmp_occupancy *occ, const float *in, float *out, int64_t n,
+                          int32_t T, float eta, float *logdet, void *stream);
+int32_t pdmp_morph_inverse(const pdmp_occupancy *occ, const float *z, float *y, int64_t n,
+                           int32_t T, float eta, int32_t iters, float *logdet, float *resid,
+                           void *stream);
+
+/* ---- epsilon mixture with the prior (Sec. 3.3: sampling with an epsilon bias toward
+ * the base distribution keeps regions the morph stretches thin reachable).
+ * Draws the prior batch x0 [dim][n] exactly as pdmp_uniform_samples(seed, stream_id,
+ * lo, hi) (lo, hi: HOST arrays [occ->dim]), morphs it (as pdmp_morph_samples, T steps)
+ * into out [dim][n], then keeps the prior value for every sample i with u_i < eps,
+ * u_i = (word >> 8) 2^-24 from word 0 of Philox4x32-10 at counter
+ * {i_lo, i_hi, 0xffffffff, stream_id}, key {seed_lo, seed_hi}.  keep (nullable) [n]
+ * marks those samples.  0 <= eps <= 1. */
+int32_t pdmp_mixture_samples(const pdmp_occupancy *occ, uint64_t seed, uint32_t stream_id,
+                             const float *lo, const float *hi, int64_t n, float eps, int32_t T,
+                             float eta, float *x0, float *out, uint8_t *keep, void *stream);
+
 /* ---- forward kinematics (Sec. 3.2): body points of configurations q [n_dof][n]
  * in FP32, written to pts [3][n_dof*pts_per_link][n]. */
 int32_t pdmp_fk_body_points(const pdmp_arm *arm, const float *q, int64_t n, float *pts,

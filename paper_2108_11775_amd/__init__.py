@@ -24,7 +24,8 @@ __all__ = ["Occupancy", "Arm", "PdmpError", "abi_version", "uniform_samples",
            "occupancy_grad", "morph_samples", "fk_body_points", "sync", "occupancy_bwd",
            "bce_logits", "adam_step", "fit_occupancy", "Mlp", "arm_max_occupancy",
            "amortised_morph", "TanhNet", "tanh_occupancy_eval", "tanh_occupancy_grad",
-           "tanh_morph_samples", "tanh_loss_grad", "tanh_fit"]
+           "tanh_morph_samples", "tanh_loss_grad", "tanh_fit", "morph_logdet", "morph_inverse",
+           "mixture_samples"]
 
 
 def _torch():
@@ -226,6 +227,56 @@ def morph_samples(occ: Occupancy, x, T: int, eta: float, arm: Optional[Arm] = No
               _dev(out, "out", torch.float32, (rows, n)), n, int(T), float(eta),
               _stream(x.device))
     return out
+
+
+def morph_logdet(occ: Occupancy, x, T: int, eta: float, out=None):
+    """(x_T, logdet): the workspace morph of x [dim][n] and, per sample,
+    sum_k log|det(I - eta Hc(x_k))| (the log-Jacobian of the map, Sec. 3.2)."""
+    torch = _torch()
+    n = int(x.shape[1])
+    _dev(x, "x", torch.float32, (occ.dim, n))
+    if out is None:
+        out = torch.empty_like(x)
+    ld = torch.empty(n, dtype=torch.float32, device=x.device)
+    o = occ.c_struct()
+    _lib.call("pdmp_morph_logdet", C.byref(o), C.c_void_p(x.data_ptr()),
+              _dev(out, "out", torch.float32, (occ.dim, n)), n, int(T), float(eta),
+              _dev(ld, "logdet"), _stream(x.device))
+    return out, ld
+
+
+def morph_inverse(occ: Occupancy, z, T: int, eta: float, iters: int = 30):
+    """(y, logdet, resid): the inverse of the T-step morph at z [dim][n] by fixed point
+    (iters iterations per step), the forward log-determinant along the reconstructed
+    path and the largest fixed-point residual per sample."""
+    torch = _torch()
+    n = int(z.shape[1])
+    _dev(z, "z", torch.float32, (occ.dim, n))
+    y = torch.empty_like(z)
+    ld = torch.empty(n, dtype=torch.float32, device=z.device)
+    r = torch.empty(n, dtype=torch.float32, device=z.device)
+    o = occ.c_struct()
+    _lib.call("pdmp_morph_inverse", C.byref(o), C.c_void_p(z.data_ptr()), _dev(y, "y"), n,
+              int(T), float(eta), int(iters), _dev(ld, "logdet"), _dev(r, "resid"),
+              _stream(z.device))
+    return y, ld, r
+
+
+def mixture_samples(occ: Occupancy, seed: int, stream_id: int, lo, hi, n: int, eps: float,
+                    T: int, eta: float, device="cuda"):
+    """(x0, out, keep): a Philox prior batch, its morph, and the epsilon mixture that
+    keeps the prior value of each sample with probability eps (Sec. 3.3)."""
+    torch = _torch()
+    lo_a = (C.c_float * occ.dim)(*[float(v) for v in lo])
+    hi_a = (C.c_float * occ.dim)(*[float(v) for v in hi])
+    x0 = torch.empty((occ.dim, n), dtype=torch.float32, device=device)
+    out = torch.empty_like(x0)
+    keep = torch.empty(n, dtype=torch.uint8, device=device)
+    o = occ.c_struct()
+    _lib.call("pdmp_mixture_samples", C.byref(o), int(seed), int(stream_id), lo_a, hi_a, n,
+              float(eps), int(T), float(eta), _dev(x0, "x0"), _dev(out, "out"), _dev(keep, "keep"),
+              _stream(x0.device))
+    return x0, out, keep
 
 
 def fk_body_points(arm: Arm, q):

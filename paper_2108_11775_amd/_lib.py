@@ -76,6 +76,11 @@ SIGNATURES = {
     "pdmp_bce_logits": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t, _vp]),
     "pdmp_adam_step": (_i32, [_vp, _vp, _vp, _vp, _i64, _i64, _i32, _f, _f, _f, _f, _f, _vp]),
     "pdmp_mlp_num_params": (_i64, [_P(pdmp_mlp)]),
+    "pdmp_morph_logdet": (_i32, [_P(pdmp_occupancy), _vp, _vp, _i64, _i32, _f, _vp, _vp]),
+    "pdmp_morph_inverse": (_i32, [_P(pdmp_occupancy), _vp, _vp, _i64, _i32, _f, _i32, _vp, _vp,
+                                  _vp]),
+    "pdmp_mixture_samples": (_i32, [_P(pdmp_occupancy), _u64, _u32, _P(_f), _P(_f), _i64, _f,
+                                    _i32, _f, _vp, _vp, _vp, _vp]),
     "pdmp_tanh_num_params": (_i64, [_P(pdmp_tanh_net)]),
     "pdmp_tanh_occupancy_eval": (_i32, [_P(pdmp_tanh_net), _vp, _i64, _vp, _vp, _vp]),
     "pdmp_tanh_occupancy_grad": (_i32, [_P(pdmp_tanh_net), _vp, _i64, _vp, _vp, _vp]),

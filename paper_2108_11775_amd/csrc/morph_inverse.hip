@@ -1,0 +1,330 @@
+// morph_inverse.hip -- the inverse of the morph and the log-determinant of its
+// Jacobian (Sec. 3.2).  The flow's inverse integrates the reversed field; for the
+// explicit-Euler map the exact inverse of one step x_{k+1} = x_k - eta grad c(x_k) is
+// the fixed point x_k = x_{k+1} + eta grad c(x_k), a contraction when
+// eta Lip(grad c) < 1.  The density of the morphed samples follows from the change of
+// variables, p_z(z) = p_y(y) / prod_k |det(I - eta Hc(x_k))|.
+//
+// Per step of the inverse: x^(0) = x_{k+1}, x^(j+1) = x_{k+1} + eta grad c(x^(j)) for
+// j < iters, x_k = x^(iters); one more evaluation at x_k gives the fixed-point residual
+// and the Hessian for the log-determinant.  The forward variant evaluates the Hessian
+// at every x_k of the plain morph.
+//
+// Hessian of c = sigma(s):  Hc = sigma' Hs + sigma'' grad s grad s^T, with
+//   Hs = sum_j w_j phi_j ((x - h_j)(x - h_j)^T / l^4 - I / l^2).
+// Grid path (2-D hinges on a tensor grid): the G1 x G0 products U = W ex, V = W ex dx
+// of the plain morph and a third one, Q = W ex dx^2, on FP32 MFMA; the y sums run on
+// the accumulator layout as in the plain morph (same lane mapping, same xor-32 pair
+// sum).  Pairwise path (any hinges, 2-D or 3-D): one point per thread, hinges staged
+// in LDS tiles.
+#include "pdmp_common.h"
+
+namespace pdmp {
+
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_iv;
+
+constexpr int kIvBlock = 256;
+
+// log|det(I - eta Hc)| for a 2 x 2 or 3 x 3 Hc (row-major).
+template <int DIM>
+__device__ __forceinline__ float step_logdet(const float (&H)[DIM][DIM], float eta) {
+    float A[DIM][DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) A[a][b] = (a == b ? 1.0f : 0.0f) - eta * H[a][b];
+    float det;
+    if (DIM == 2) {
+        det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+    } else {
+        det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+              A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+              A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    }
+    return logf(fabsf(det));
+}
+
+// ------------------------------------------------------------ grid path ---
+
+// Sums at the prescaled point (xs, ys): s' (without beta), (sx, sy) with
+// grad s = -gscale (sx, sy), and with HESS (sxx, sxy, syy) with
+// Hs = gscale^2 [[sxx, sxy], [sxy, syy]] - (1/l^2) s' I.
+template <int TB, bool HESS>
+__device__ __forceinline__ void g2i_eval(const float *frag, const float *gxs, const float *gys,
+                                         int ks, float xs, float ys, float &s, float &sx,
+                                         float &sy, float &sxx, float &sxy, float &syy) {
+    const int lane = threadIdx.x & 63, half = lane >> 5;
+    f32x16_iv U[TB], V[TB], Q[TB];
+#pragma unroll
+    for (int t = 0; t < TB; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) U[t][v] = V[t][v] = Q[t][v] = 0.0f;
+    for (int kk = 0; kk < ks; ++kk) {
+        const float d = xs - gxs[2 * kk + half];
+        const float e = exp2_fast(-d * d);
+        const float de = e * d;
+        const float dde = de * d;
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            const float wfr = frag[(kk * TB + t) * 64 + lane];
+            U[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(wfr, e, U[t], 0, 0, 0);
+            V[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(wfr, de, V[t], 0, 0, 0);
+            if (HESS) Q[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(wfr, dde, Q[t], 0, 0, 0);
+        }
+    }
+    s = sx = sy = sxx = sxy = syy = 0.0f;
+#pragma unroll
+    for (int t = 0; t < TB; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int b = 32 * t + 8 * (v >> 2) + 4 * half + (v & 3);
+            const float d = ys - gys[b];
+            const float e = exp2_fast(-d * d);
+            const float ed = e * d;
+            s = fmaf(e, U[t][v], s);
+            sx = fmaf(e, V[t][v], sx);
+            sy = fmaf(ed, U[t][v], sy);
+            if (HESS) {
+                sxx = fmaf(e, Q[t][v], sxx);
+                sxy = fmaf(ed, V[t][v], sxy);
+                syy = fmaf(ed * d, U[t][v], syy);
+            }
+        }
+    s += __shfl_xor(s, 32, 64);
+    sx += __shfl_xor(sx, 32, 64);
+    sy += __shfl_xor(sy, 32, 64);
+    if (HESS) {
+        sxx += __shfl_xor(sxx, 32, 64);
+        sxy += __shfl_xor(sxy, 32, 64);
+        syy += __shfl_xor(syy, 32, 64);
+    }
+}
+
+// MODE kLogdet: forward morph with the log-determinant.  MODE kInverse: inverse by
+// fixed point (iters per step) with residual and log-determinant.
+template <int TB, int MODE>
+__global__ void __launch_bounds__(kIvBlock)
+k_grid2d_inv(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
+             float kappa, float gscale, const float *x_in, int64_t n, int T, float eta, int iters,
+             float *x_out, float *logdet_out, float *resid_out) {
+    __shared__ float frag[32 * TB * 64];
+    __shared__ float gxs[64];
+    __shared__ float gys[32 * TB];
+    const int M = g0 * g1;
+    const int ks = (g0 + 1) / 2;
+    for (int idx = threadIdx.x; idx < ks * TB * 64; idx += kIvBlock) {
+        const int ln = idx & 63, t = (idx >> 6) % TB, kk = idx / (64 * TB);
+        const int b = 32 * t + (ln & 31), a = 2 * kk + (ln >> 5);
+        frag[idx] = (a < g0 && b < g1) ? weights[a + (int64_t)g0 * b] : 0.0f;
+    }
+    for (int a = threadIdx.x; a < 2 * ks; a += kIvBlock) gxs[a] = a < g0 ? kappa * hinges[a] : 0.0f;
+    for (int b = threadIdx.x; b < 32 * TB; b += kIvBlock)
+        gys[b] = b < g1 ? kappa * hinges[(size_t)M + (size_t)g0 * b] : 0.0f;
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, half = lane >> 5;
+    const int64_t wave = (int64_t)blockIdx.x * (kIvBlock / 64) + (threadIdx.x >> 6);
+    const int64_t i = wave * 32 + (lane & 31);
+    const int64_t ic = i < n ? i : n - 1;
+    float x = x_in[ic], y = x_in[(size_t)n + ic];
+    const float beta = weights[M];
+    const float il2 = gscale * kappa;  // 1 / l^2
+    const float g2 = gscale * gscale;
+    float ld = 0.0f, rmax = 0.0f;
+    for (int st = 0; st < T; ++st) {
+        const float zx = x, zy = y;
+        const int evals = MODE == kInverse ? iters + 1 : 1;
+        for (int j = 0; j < evals; ++j) {
+            const bool last = j == evals - 1;
+            float s, sx, sy, sxx = 0.0f, sxy = 0.0f, syy = 0.0f;
+            if (last)
+                g2i_eval<TB, true>(frag, gxs, gys, ks, kappa * x, kappa * y, s, sx, sy, sxx, sxy,
+                                   syy);
+            else
+                g2i_eval<TB, false>(frag, gxs, gys, ks, kappa * x, kappa * y, s, sx, sy, sxx, sxy,
+                                    syy);
+            float c, sp;
+            sigmoid_and_slope(s + beta, c, sp);
+            const float gx = -gscale * sx, gy = -gscale * sy;  // grad s
+            if (last) {
+                const float spp = sp * (1.0f - 2.0f * c);
+                float H[2][2];
+                H[0][0] = sp * fmaf(g2, sxx, -il2 * s) + spp * gx * gx;
+                H[0][1] = sp * g2 * sxy + spp * gx * gy;
+                H[1][0] = H[0][1];
+                H[1][1] = sp * fmaf(g2, syy, -il2 * s) + spp * gy * gy;
+                ld += step_logdet<2>(H, eta);
+            }
+            const float cx = sp * gx, cy = sp * gy;  // grad c
+            if (MODE == kInverse) {
+                if (!last) {
+                    x = fmaf(eta, cx, zx);
+                    y = fmaf(eta, cy, zy);
+                } else {
+                    const float rx = fabsf(x - fmaf(eta, cx, zx)), ry = fabsf(y - fmaf(eta, cy, zy));
+                    rmax = fmaxf(rmax, fmaxf(rx, ry));
+                }
+            } else {
+                x = fmaf(-eta, cx, x);
+                y = fmaf(-eta, cy, y);
+            }
+        }
+    }
+    if (half != 0 || i >= n) return;
+    x_out[i] = x;
+    x_out[(size_t)n + i] = y;
+    if (logdet_out) logdet_out[i] = ld;
+    if (resid_out) resid_out[i] = rmax;
+}
+
+// -------------------------------------------------------- pairwise path ---
+
+constexpr int kIvTile = 1024;  // hinges per LDS tile
+
+// One point per thread; s' (without beta), grad s and Hs at x.
+template <int DIM>
+__device__ __forceinline__ void rbfi_eval(const float *__restrict__ hinges,
+                                          const float *__restrict__ weights, int M, float i2l2,
+                                          float il2, float *sh_h, float *sh_w, const float (&x)[DIM],
+                                          float &s, float (&g)[DIM], float (&Hs)[DIM][DIM]) {
+    s = 0.0f;
+    float hx[DIM][DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        g[a] = 0.0f;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) hx[a][b] = 0.0f;
+    }
+    for (int j0 = 0; j0 < M; j0 += kIvTile) {
+        const int cnt = M - j0 < kIvTile ? M - j0 : kIvTile;
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) sh_h[k * kIvTile + j] = hinges[(size_t)k * M + j0 + j];
+            sh_w[j] = weights[j0 + j];
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            float d[DIM], r2 = 0.0f;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                d[k] = x[k] - sh_h[k * kIvTile + j];
+                r2 = fmaf(d[k], d[k], r2);
+            }
+            const float wp = sh_w[j] * __expf(-r2 * i2l2);
+            s += wp;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                g[a] = fmaf(wp, d[a], g[a]);
+#pragma unroll
+                for (int b = a; b < DIM; ++b) hx[a][b] = fmaf(wp * d[a], d[b], hx[a][b]);
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        g[a] *= -il2;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            const float v = a <= b ? hx[a][b] : hx[b][a];
+            Hs[a][b] = v * il2 * il2 - (a == b ? il2 * s : 0.0f);
+        }
+    }
+}
+
+template <int DIM, int MODE>
+__global__ void __launch_bounds__(kIvBlock)
+k_rbf_inv(const float *__restrict__ hinges, const float *__restrict__ weights, int M, float ell,
+          const float *x_in, int64_t n, int T, float eta, int iters, float *x_out,
+          float *logdet_out, float *resid_out) {
+    __shared__ float sh_h[DIM * kIvTile], sh_w[kIvTile];
+    const int64_t i = (int64_t)blockIdx.x * kIvBlock + threadIdx.x;
+    const int64_t ic = i < n ? i : n - 1;
+    const float il2 = 1.0f / (ell * ell), i2l2 = 0.5f * il2;
+    const float beta = weights[M];
+    float x[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) x[k] = x_in[(size_t)k * n + ic];
+    float ld = 0.0f, rmax = 0.0f;
+    for (int st = 0; st < T; ++st) {
+        float z[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) z[k] = x[k];
+        const int evals = MODE == kInverse ? iters + 1 : 1;
+        for (int j = 0; j < evals; ++j) {
+            const bool last = j == evals - 1;
+            float s, g[DIM], Hs[DIM][DIM];
+            rbfi_eval<DIM>(hinges, weights, M, i2l2, il2, sh_h, sh_w, x, s, g, Hs);
+            float c, sp;
+            sigmoid_and_slope(s + beta, c, sp);
+            if (last) {
+                const float spp = sp * (1.0f - 2.0f * c);
+                float H[DIM][DIM];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                    for (int b = 0; b < DIM; ++b) H[a][b] = sp * Hs[a][b] + spp * g[a] * g[b];
+                ld += step_logdet<DIM>(H, eta);
+            }
+            if (MODE == kInverse) {
+                if (!last) {
+#pragma unroll
+                    for (int k = 0; k < DIM; ++k) x[k] = fmaf(eta, sp * g[k], z[k]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < DIM; ++k)
+                        rmax = fmaxf(rmax, fabsf(x[k] - fmaf(eta, sp * g[k], z[k])));
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) x[k] = fmaf(-eta, sp * g[k], x[k]);
+            }
+        }
+    }
+    if (i >= n) return;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) x_out[(size_t)k * n + i] = x[k];
+    if (logdet_out) logdet_out[i] = ld;
+    if (resid_out) resid_out[i] = rmax;
+}
+
+// mode kLogdet or kInverse; grid (nullable) selects the MFMA path for a 2-D grid.
+int32_t launch_morph_inverse(int dim, int mode, const float *hinges, const float *weights, int M,
+                             const int *grid, float ell, const float *x_in, int64_t n, int T,
+                             float eta, int iters, float *x_out, float *logdet, float *resid,
+                             hipStream_t st) {
+    float kappa, gscale;
+    derive_scales(ell, kappa, gscale);
+    if (dim == 2 && grid && grid[0] >= 1 && grid[1] >= 1 && grid[0] <= 64 && grid[1] <= 64 &&
+        grid[0] * grid[1] == M) {
+        const int g0 = grid[0], g1 = grid[1];
+        const dim3 blocks((unsigned)((n + 127) / 128)), blk(kIvBlock);
+#define PDMP_G2I(TB, MD)                                                                        \
+    hipLaunchKernelGGL((k_grid2d_inv<TB, MD>), blocks, blk, 0, st, hinges, weights, g0, g1, kappa, \
+                       gscale, x_in, n, T, eta, iters, x_out, logdet, resid)
+        if (g1 <= 32) {
+            if (mode == kInverse) PDMP_G2I(1, kInverse);
+            else PDMP_G2I(1, kLogdet);
+        } else {
+            if (mode == kInverse) PDMP_G2I(2, kInverse);
+            else PDMP_G2I(2, kLogdet);
+        }
+#undef PDMP_G2I
+        return check_launch("k_grid2d_inv");
+    }
+    const dim3 blocks((unsigned)((n + kIvBlock - 1) / kIvBlock)), blk(kIvBlock);
+#define PDMP_RI(D, MD)                                                                        \
+    hipLaunchKernelGGL((k_rbf_inv<D, MD>), blocks, blk, 0, st, hinges, weights, M, ell, x_in, n, \
+                       T, eta, iters, x_out, logdet, resid)
+    if (dim == 2) {
+        if (mode == kInverse) PDMP_RI(2, kInverse);
+        else PDMP_RI(2, kLogdet);
+    } else {
+        if (mode == kInverse) PDMP_RI(3, kInverse);
+        else PDMP_RI(3, kLogdet);
+    }
+#undef PDMP_RI
+    return check_launch("k_rbf_inv");
+}
+
+}  // namespace pdmp

@@ -220,6 +220,57 @@ int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const
     return rbf_call(occ, kMorph, in, n, nullptr, nullptr, nullptr, out, T, eta, stream);
 }
 
+int32_t pdmp_morph_logdet(const pdmp_occupancy *occ, const float *in, float *out, int64_t n,
+                          int32_t T, float eta, float *logdet, void *stream) {
+    int32_t st = check_occ(occ);
+    if (st) return st;
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    PDMP_REQUIRE(T >= 0, "T < 0");
+    PDMP_REQUIRE(std::isfinite(eta), "eta not finite");
+    if (n == 0) return PDMP_OK;
+    PDMP_REQUIRE(in && out, "in/out NULL");
+    return launch_morph_inverse(occ->dim, kLogdet, occ->hinges, occ->weights, occ->n_hinges,
+                                has_grid(occ) ? occ->grid : nullptr, occ->lengthscale, in, n, T,
+                                eta, 0, out, logdet, nullptr, (hipStream_t)stream);
+}
+
+int32_t pdmp_morph_inverse(const pdmp_occupancy *occ, const float *z, float *y, int64_t n,
+                           int32_t T, float eta, int32_t iters, float *logdet, float *resid,
+                           void *stream) {
+    int32_t st = check_occ(occ);
+    if (st) return st;
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    PDMP_REQUIRE(T >= 0, "T < 0");
+    PDMP_REQUIRE(iters >= 1, "iters < 1");
+    PDMP_REQUIRE(std::isfinite(eta), "eta not finite");
+    if (n == 0) return PDMP_OK;
+    PDMP_REQUIRE(z && y, "z/y NULL");
+    return launch_morph_inverse(occ->dim, kInverse, occ->hinges, occ->weights, occ->n_hinges,
+                                has_grid(occ) ? occ->grid : nullptr, occ->lengthscale, z, n, T,
+                                eta, iters, y, logdet, resid, (hipStream_t)stream);
+}
+
+int32_t pdmp_mixture_samples(const pdmp_occupancy *occ, uint64_t seed, uint32_t stream_id,
+                             const float *lo, const float *hi, int64_t n, float eps, int32_t T,
+                             float eta, float *x0, float *out, uint8_t *keep, void *stream) {
+    int32_t st = check_occ(occ);
+    if (st) return st;
+    PDMP_REQUIRE(n >= 0, "n < 0");
+    PDMP_REQUIRE(T >= 0, "T < 0");
+    PDMP_REQUIRE(std::isfinite(eta), "eta not finite");
+    PDMP_REQUIRE(eps >= 0.0f && eps <= 1.0f, "eps not in [0, 1]");
+    PDMP_REQUIRE(lo && hi, "lo/hi NULL");
+    for (int k = 0; k < occ->dim; ++k)
+        PDMP_REQUIRE(std::isfinite(lo[k]) && std::isfinite(hi[k]) && lo[k] <= hi[k],
+                     "bad range on axis %d", k);
+    if (n == 0) return PDMP_OK;
+    PDMP_REQUIRE(x0 && out && x0 != out, "x0/out NULL or aliased");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = launch_uniform(seed, stream_id, lo, hi, occ->dim, n, x0, s))) return st;
+    if ((st = pdmp_morph_samples(occ, nullptr, x0, out, n, T, eta, stream))) return st;
+    return launch_mix_select(seed, stream_id, eps, occ->dim, n, x0, out, keep, s);
+}
+
 int32_t pdmp_fk_body_points(const pdmp_arm *arm, const float *q, int64_t n, float *pts,
                             void *stream) {
     int32_t st = check_arm(arm, PDMP_MAX_PTS_PER_LINK);

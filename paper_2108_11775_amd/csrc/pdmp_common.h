@@ -70,7 +70,7 @@ inline void derive_scales(float ell, float &kappa, float &gscale) {
 
 // ---- launchers (host side, one per kernel family) ----
 
-enum RbfMode { kEval = 0, kGrad = 1, kMorph = 2, kGradBwd = 3 };
+enum RbfMode { kEval = 0, kGrad = 1, kMorph = 2, kGradBwd = 3, kLogdet = 4, kInverse = 5 };
 
 // One RBF-sum launch: for every "sample" x_i (n of them) sum over the weighted
 // "hinge" set (M of them).  The roles are symmetric: with hinges = data points,
@@ -143,6 +143,14 @@ int32_t launch_grid_wgrad(int dim, const float *hinges, int M, const int *grid, 
                           const float *x, int64_t n, const float *g, float *part, int *rows,
                           hipStream_t st);
 size_t wgrad_rows_max(int64_t n);
+// Forward morph with log-determinant (kLogdet) or its inverse by fixed point (kInverse).
+int32_t launch_morph_inverse(int dim, int mode, const float *hinges, const float *weights, int M,
+                             const int *grid, float ell, const float *x_in, int64_t n, int T,
+                             float eta, int iters, float *x_out, float *logdet, float *resid,
+                             hipStream_t st);
+// Epsilon mixture: keep[i] = (u_i < eps) from Philox, out[:, i] = x0[:, i] where kept.
+int32_t launch_mix_select(uint64_t seed, uint32_t sid, float eps, int dim, int64_t n,
+                          const float *x0, float *out, uint8_t *keep, hipStream_t st);
 // out[j] = scale * sum_r part[r m + j] (+ add_scale add[j]), fixed order.
 int32_t launch_sum_rows(const float *part, int rows, int64_t m, double scale, const float *add,
                         float add_scale, float *out, hipStream_t st);

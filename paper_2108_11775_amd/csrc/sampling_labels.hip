@@ -69,6 +69,31 @@ int32_t launch_uniform(uint64_t seed, uint32_t sid, const float *lo, const float
     return check_launch("k_uniform");
 }
 
+// Epsilon mixture with the prior (Sec. 3.3): sample i keeps its prior value iff
+// u_i < eps, u_i from word 0 of Philox at counter {i_lo, i_hi, 0xffffffff, sid} (a
+// counter the coordinates never use), u = (word >> 8) 2^-24.
+__global__ void __launch_bounds__(256)
+k_mix_select(uint32_t k0, uint32_t k1, uint32_t sid, double eps, int dim, int64_t n,
+             const float *__restrict__ x0, float *out, uint8_t *keep) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), 0xffffffffu, sid};
+    philox4x32_10(c, k0, k1);
+    const double u = (double)(c[0] >> 8) * (1.0 / 16777216.0);
+    const bool k = u < eps;
+    if (keep) keep[i] = (uint8_t)k;
+    if (k)
+        for (int d = 0; d < dim; ++d) out[(size_t)d * n + i] = x0[(size_t)d * n + i];
+}
+
+int32_t launch_mix_select(uint64_t seed, uint32_t sid, float eps, int dim, int64_t n,
+                          const float *x0, float *out, uint8_t *keep, hipStream_t st) {
+    hipLaunchKernelGGL(k_mix_select, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), sid, (double)eps, dim, n, x0, out,
+                       keep);
+    return check_launch("k_mix_select");
+}
+
 __global__ void k_zero_u64(uint64_t *p) {
     if (threadIdx.x == 0) *p = 0;
 }
