@@ -420,6 +420,80 @@ def density_workload(P, I, K, torch, hl):
                                  "work": "(4*iters + 6)*G0*G1 FP32 MFMA flops per sample-step"}}
 
 
+def pipeline_workload(P, I, K, torch, dev, hl):
+    """The producer/consumer of Sec. 3.3: a background GPU sampler filling the bucket,
+    a plane RRT drawing from it (prior when empty).  (a) time to solution in config 1's
+    world, morph sampler against the prior, 10 runs each; (b) the morphed share of the
+    consumed samples over time and the producer's delivered rate in config 2's world."""
+    import numpy as np
+    out = {}
+    c1 = K.C1
+    sc1 = ws_scene(P, I, K, torch, c1, dev)
+    dc1, dr1 = I.discs(c1.cfg_id, c1.n_discs, c1.lo, c1.hi, c1.r_min, c1.r_max)
+    start, goal = K.RRT_START_GOAL[1]
+    runs = {"prior": [], "morph": []}
+    for r in range(10):
+        for kind in ("prior", "morph"):
+            s = P.Sampler(sc1["occ"] if kind == "morph" else None, 2, [c1.lo] * 2, [c1.hi] * 2,
+                          c1.T, c1.eta, c1.n_samples, 1 << 16, seed=I.philox_seed(c1.cfg_id),
+                          stream_id=1000 * r, prior_stream_id=50 + r)
+            if kind == "morph":
+                s.start()
+            res = P.rrt_run(s, start, goal, 0.5, 0.5, (dc1, dr1), 200000, 5.0)
+            runs[kind].append({"solved": res["solved"], "iters": res["iters"],
+                               "nodes": res["n_nodes"], "s": res["elapsed_s"],
+                               "from_bucket": res["from_bucket"], "path_len": res["path_len"]})
+            s.close()
+    for kind, rs in runs.items():
+        ok = [x for x in rs if x["solved"]]
+        out[f"config1_{kind}"] = {
+            "solved": len(ok), "runs": len(rs),
+            "iters_mean": float(np.mean([x["iters"] for x in ok])) if ok else None,
+            "seconds_mean": float(np.mean([x["s"] for x in ok])) if ok else None,
+            "path_len_mean": float(np.mean([x["path_len"] for x in ok])) if ok else None,
+            "morphed_share": float(np.sum([x["from_bucket"] for x in rs]) /
+                                   max(1, np.sum([x["iters"] for x in rs])))}
+    c2 = K.C2
+    dc2, dr2 = hl["sc"]["discs"]
+    s = P.Sampler(hl["sc"]["occ"], 2, [c2.lo] * 2, [c2.hi] * 2, c2.T, c2.eta, 65536, 1 << 20,
+                  seed=I.philox_seed(c2.cfg_id), stream_id=5000, prior_stream_id=77)
+    s.start()
+    start2, goal2 = K.RRT_START_GOAL[2]
+    res = P.rrt_run(s, start2, goal2, 0.5, -1.0, (dc2.cpu().numpy(), dr2.cpu().numpy()),
+                    3_000_000, 1.0)
+    st = s.stats()
+    s.close()
+    t, fb = res["t_sample"], res["sample_from_bucket"].astype(np.int64)
+    share = []
+    for cp in (0.001, 0.002, 0.005, 0.01, 0.02, 0.05, 0.1, 0.2, 0.5, 1.0):
+        k = int(np.searchsorted(t, cp, side="right"))
+        nb = int(fb[:k].sum())
+        share.append({"t_s": cp, "from_bucket": nb, "from_prior": k - nb})
+    out["config2_share_over_time"] = share
+    out["config2_consumer"] = {"iters": res["iters"], "nodes": res["n_nodes"],
+                               "from_bucket": res["from_bucket"], "from_prior": res["from_prior"],
+                               "seconds": res["elapsed_s"]}
+    out["config2_producer_during_run"] = {"batches": st["batches"], "produced": st["produced"],
+                                          "status": st["status"]}
+    # the producer alone: time to fill an empty bucket of 2^23 samples
+    cap = 1 << 23
+    s = P.Sampler(hl["sc"]["occ"], 2, [c2.lo] * 2, [c2.hi] * 2, c2.T, c2.eta, 65536, cap,
+                  seed=I.philox_seed(c2.cfg_id), stream_id=9000, prior_stream_id=78)
+    t0 = time.perf_counter()
+    s.start()
+    while s.stats()["produced"] < cap and time.perf_counter() - t0 < 10.0:
+        time.sleep(0.0005)
+    dt = time.perf_counter() - t0
+    st = s.stats()
+    s.close()
+    out["producer"] = {"produced": st["produced"], "seconds": dt,
+                       "samples_per_s": st["produced"] / dt, "status": st["status"],
+                       "note": "morph (T=50, 65,536-sample batches) + PCIe copy to pinned host "
+                               "memory + push into the bucket, from thread start to a full "
+                               "2^23-sample bucket"}
+    return out
+
+
 def amortised(args, P, I, K, torch, world):
     from paper_2108_11775_amd import amortise
     c3, c5 = K.C3, K.C5
@@ -546,6 +620,8 @@ def main():
                 wl["density_ws2d"] = density_workload(P, I, K, torch, hl)
                 log(f"log-det / inverse: {wl['density_ws2d']['logdet_ms']:.1f} / "
                     f"{wl['density_ws2d']['inverse_ms']:.1f} ms")
+            wl["pipeline"] = pipeline_workload(P, I, K, torch, dev, hl)
+            log("producer/consumer done")
             wl["tanh_ws2d"] = tanh_morph(P, I, K, torch, dev)
             log(f"tanh-network morph: {wl['tanh_ws2d']['morph_ms']:.2f} ms")
             world = arm_world(P, I, K, torch, dev)

@@ -347,6 +347,109 @@ int32_t pdmp_tanh_fit(const pdmp_tanh_net *net, const float *pts, const uint8_t 
                       int64_t n, const pdmp_fit_opts *opts, float *loss_out, void *ws,
                       size_t ws_bytes, void *stream);
 
+/* ---- the producer/consumer of Sec. 3.3: a background diffeomorphic sampler keeps a
+ * bounded concurrent bucket S filled with morphed samples; the planner's main thread
+ * draws from S and never waits -- when S is empty it draws from the prior instead,
+ * so a slow or failed GPU only reverts the planner to plain sampling.  Host memory;
+ * all functions are host calls. */
+typedef struct pdmp_bucket pdmp_bucket;
+typedef struct pdmp_sampler pdmp_sampler;
+
+/* Bucket: a single-producer single-consumer ring of `capacity` (a power of two)
+ * samples of `dim` floats (1..16), each with a 64-bit index.  One thread may push and
+ * one other thread may pop concurrently; neither call blocks.
+ * push: samples [start, n) of the SoA batch x [dim][ld] (ld >= n) with indices
+ *   base_index + j, as many as fit; returns the number pushed (-1 on bad arguments).
+ * pop: one sample into x [dim] and its index (nullable); returns 1, or 0 if empty. */
+int32_t pdmp_bucket_create(int32_t dim, int64_t capacity, pdmp_bucket **out);
+int64_t pdmp_bucket_push(pdmp_bucket *b, const float *x, int64_t ld, int64_t start, int64_t n,
+                         int64_t base_index);
+int32_t pdmp_bucket_pop(pdmp_bucket *b, float *x, int64_t *index);
+int64_t pdmp_bucket_size(const pdmp_bucket *b);
+void pdmp_bucket_destroy(pdmp_bucket *b);
+
+/* Sampler options.  Batch b of the producer is the Philox prior of stream
+ * (stream_id + b) on the box [lo, hi)^dim (as pdmp_uniform_samples), morphed T steps
+ * (as pdmp_morph_samples with arm == NULL); its sample i enters S with index
+ * b * batch + i.  The k-th prior fallback draw is sample k of the prior of stream
+ * prior_stream_id (same values as pdmp_uniform_samples) and gets index -1 - k. */
+typedef struct {
+    int32_t dim;              /* 2 or 3 */
+    int32_t T;                /* >= 0 */
+    float eta;
+    int64_t batch;            /* samples per GPU batch, >= 1 */
+    int64_t capacity;         /* bucket capacity in samples, a power of two */
+    uint64_t seed;
+    uint32_t stream_id;
+    uint32_t prior_stream_id;
+    float lo[3], hi[3];
+} pdmp_sampler_opts;
+
+typedef struct {
+    int64_t batches;          /* GPU batches completed */
+    int64_t produced;         /* samples pushed into S */
+    int64_t popped_bucket;    /* samples the consumer took from S */
+    int64_t popped_prior;     /* samples the consumer drew from the prior */
+    int64_t bucket_size;
+    int32_t status;           /* the producer's first failure (PDMP_OK if none) */
+    int32_t running;
+    double producer_busy_s;   /* producer wall time with a batch in flight */
+    double elapsed_s;         /* since pdmp_sampler_start */
+} pdmp_sampler_stats;
+
+/* create: occ (nullable: a prior-only sampler) is copied; the device buffers it
+ *   points to must outlive the sampler.  start: spawns the producer thread on the
+ *   calling thread's current device (its own non-blocking HIP stream, default
+ *   priority, device and pinned host buffers of a few batches).  pause: the
+ *   producer stops launching and pushing while paused != 0 (forces an empty S).
+ *   pop: n samples into x [n][dim] (row per sample), index [n] and from_bucket [n]
+ *   (both nullable); never waits.  Single consumer thread.  destroy: stops and
+ *   joins the producer, frees everything, returns the producer's status. */
+int32_t pdmp_sampler_create(const pdmp_occupancy *occ, const pdmp_sampler_opts *opts,
+                            pdmp_sampler **out);
+int32_t pdmp_sampler_start(pdmp_sampler *s);
+int32_t pdmp_sampler_pause(pdmp_sampler *s, int32_t paused);
+int32_t pdmp_sampler_pop(pdmp_sampler *s, int64_t n, float *x, int64_t *index,
+                         uint8_t *from_bucket);
+int32_t pdmp_sampler_get_stats(const pdmp_sampler *s, pdmp_sampler_stats *st);
+int32_t pdmp_sampler_destroy(pdmp_sampler *s);
+
+/* The planner's main thread in its simplest form (an RRT in the plane, Sec. 3.3):
+ * each iteration pops one sample from the sampler (dim 2), finds the nearest node
+ * (squared distance in FP64, ties to the lowest index), steers at most `step` toward
+ * the sample (FP64, stored as FP32), and adds the node if the edge misses every disc
+ * (closed discs, FP64 segment distance); it stops when a new node within goal_tol of
+ * the goal connects to it by a free edge (the goal becomes the last node), after
+ * max_iters iterations, or when time_budget_s (> 0) has passed (goal_tol < 0: no
+ * goal, the tree grows until one of the other two).
+ * nodes [max_iters + 2][2], parent [max_iters + 2] (root -1); samples [max_iters][2],
+ * from_bucket [max_iters] and t_sample [max_iters] (seconds since the start) record
+ * each iteration's draw (all three nullable). */
+typedef struct {
+    int32_t max_iters;
+    float step;
+    float goal_tol;
+    float start[2];
+    float goal[2];
+    double time_budget_s;
+    int32_t n_discs;
+    const double *disc_x, *disc_y, *disc_r;  /* host [n_discs] */
+} pdmp_rrt_opts;
+
+typedef struct {
+    int32_t solved;
+    int32_t iters;
+    int32_t n_nodes;
+    int64_t from_bucket;
+    int64_t from_prior;
+    double path_len;
+    double elapsed_s;
+} pdmp_rrt_result;
+
+int32_t pdmp_rrt_run(pdmp_sampler *s, const pdmp_rrt_opts *o, float *nodes, int32_t *parent,
+                     float *samples, uint8_t *from_bucket, double *t_sample,
+                     pdmp_rrt_result *res);
+
 #ifdef __cplusplus
 }
 #endif

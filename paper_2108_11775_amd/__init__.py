@@ -25,7 +25,7 @@ __all__ = ["Occupancy", "Arm", "PdmpError", "abi_version", "uniform_samples",
            "bce_logits", "adam_step", "fit_occupancy", "Mlp", "arm_max_occupancy",
            "amortised_morph", "TanhNet", "tanh_occupancy_eval", "tanh_occupancy_grad",
            "tanh_morph_samples", "tanh_loss_grad", "tanh_fit", "morph_logdet", "morph_inverse",
-           "mixture_samples"]
+           "mixture_samples", "Bucket", "Sampler", "rrt_run"]
 
 
 def _torch():
@@ -606,3 +606,144 @@ def tanh_fit(net: TanhNet, pts, labels, steps: int, lr: float, l2: float, beta1=
               _dev(loss, "loss") if loss is not None else None, _dev(ws, "ws"), ws.numel(),
               _stream(pts.device))
     return loss[:steps] if loss is not None else None
+
+
+# ------------------------------------------ producer / consumer (Sec. 3.3) ---
+
+class Bucket:
+    """Host SPSC ring of samples (the concurrent bucket S); push/pop never block."""
+
+    def __init__(self, dim: int, capacity: int):
+        lib = _lib.load()
+        self.dim = int(dim)
+        h = C.c_void_p()
+        _lib.call("pdmp_bucket_create", int(dim), int(capacity), C.byref(h))
+        self._h = h
+        self._lib = lib
+
+    def push(self, x, start: int = 0, base_index: int = 0) -> int:
+        """Push samples [start, n) of a contiguous float32 numpy array x [dim][n]."""
+        import numpy as np
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        n = x.shape[1]
+        r = self._lib.pdmp_bucket_push(self._h, x.ctypes.data, n, int(start), n, int(base_index))
+        if r < 0:
+            raise ValueError("bad push arguments")
+        return int(r)
+
+    def pop(self):
+        """(x [dim] float32, index) or None when empty."""
+        import numpy as np
+        x = np.zeros(self.dim, np.float32)
+        idx = C.c_int64()
+        r = self._lib.pdmp_bucket_pop(self._h, x.ctypes.data, C.byref(idx))
+        return (x, idx.value) if r == 1 else None
+
+    def size(self) -> int:
+        return int(self._lib.pdmp_bucket_size(self._h))
+
+    def close(self):
+        if self._h:
+            self._lib.pdmp_bucket_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Sampler:
+    """The background diffeomorphic sampler of Sec. 3.3: a producer thread keeps the
+    bucket filled with morphed Philox prior batches; pop() never waits and falls back
+    to the prior when the bucket is empty.  occ None gives a prior-only sampler."""
+
+    def __init__(self, occ, dim: int, lo, hi, T: int, eta: float, batch: int, capacity: int,
+                 seed: int, stream_id: int = 0, prior_stream_id: int = 0xFFFF):
+        lib = _lib.load()
+        o = _lib.pdmp_sampler_opts()
+        o.dim, o.T, o.eta, o.batch, o.capacity = int(dim), int(T), float(eta), int(batch), \
+            int(capacity)
+        o.seed, o.stream_id, o.prior_stream_id = int(seed), int(stream_id), int(prior_stream_id)
+        for k in range(int(dim)):
+            o.lo[k], o.hi[k] = float(lo[k]), float(hi[k])
+        self.dim = int(dim)
+        self.occ = occ  # keeps the device buffers alive
+        self._occ_struct = occ.c_struct() if occ is not None else None
+        h = C.c_void_p()
+        _lib.call("pdmp_sampler_create",
+                  C.byref(self._occ_struct) if occ is not None else None, C.byref(o), C.byref(h))
+        self._h = h
+        self._lib = lib
+
+    def start(self):
+        _lib.call("pdmp_sampler_start", self._h)
+
+    def pause(self, paused: bool = True):
+        _lib.call("pdmp_sampler_pause", self._h, 1 if paused else 0)
+
+    def pop(self, n: int):
+        """(x [n][dim] float32, index [n] int64, from_bucket [n] uint8)."""
+        import numpy as np
+        x = np.zeros((n, self.dim), np.float32)
+        idx = np.zeros(n, np.int64)
+        fb = np.zeros(n, np.uint8)
+        _lib.call("pdmp_sampler_pop", self._h, int(n), x.ctypes.data, idx.ctypes.data,
+                  fb.ctypes.data)
+        return x, idx, fb
+
+    def stats(self) -> dict:
+        st = _lib.pdmp_sampler_stats()
+        _lib.call("pdmp_sampler_get_stats", self._h, C.byref(st))
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def close(self) -> int:
+        """Stop and join the producer; returns its status."""
+        if not self._h:
+            return 0
+        r = self._lib.pdmp_sampler_destroy(self._h)
+        self._h = None
+        return int(r)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rrt_run(sampler: Sampler, start, goal, step: float, goal_tol: float, discs,
+            max_iters: int, time_budget_s: float = 0.0):
+    """The planner's main thread (a plane RRT, Sec. 3.3) drawing from `sampler`.
+
+    discs: (centres [2][K] or [K][2], radii [K]) host arrays.  Returns a dict with the
+    result fields and the arrays nodes, parent, samples, sample_from_bucket, t_sample."""
+    import numpy as np
+    cen, rad = discs
+    cen = np.asarray(cen, np.float64)
+    if cen.shape[0] != 2:
+        cen = cen.T
+    dx = np.ascontiguousarray(cen[0], np.float64)
+    dy = np.ascontiguousarray(cen[1], np.float64)
+    dr = np.ascontiguousarray(rad, np.float64)
+    o = _lib.pdmp_rrt_opts()
+    o.max_iters, o.step, o.goal_tol = int(max_iters), float(step), float(goal_tol)
+    o.start[0], o.start[1] = float(start[0]), float(start[1])
+    o.goal[0], o.goal[1] = float(goal[0]), float(goal[1])
+    o.time_budget_s = float(time_budget_s)
+    o.n_discs = int(dr.size)
+    o.disc_x, o.disc_y, o.disc_r = dx.ctypes.data, dy.ctypes.data, dr.ctypes.data
+    nodes = np.zeros((max_iters + 2, 2), np.float32)
+    parent = np.zeros(max_iters + 2, np.int32)
+    samples = np.zeros((max_iters, 2), np.float32)
+    fb = np.zeros(max_iters, np.uint8)
+    ts = np.zeros(max_iters, np.float64)
+    res = _lib.pdmp_rrt_result()
+    _lib.call("pdmp_rrt_run", sampler._h, C.byref(o), nodes.ctypes.data, parent.ctypes.data,
+              samples.ctypes.data, fb.ctypes.data, ts.ctypes.data, C.byref(res))
+    out = {f: getattr(res, f) for f, _ in res._fields_}
+    k, m = res.iters, res.n_nodes
+    out.update(nodes=nodes[:m], parent=parent[:m], samples=samples[:k], sample_from_bucket=fb[:k],
+               t_sample=ts[:k])
+    return out

@@ -50,6 +50,32 @@ class pdmp_tanh_net(C.Structure):
                 ("params", C.c_void_p)]
 
 
+class pdmp_sampler_opts(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("T", C.c_int32), ("eta", C.c_float), ("batch", C.c_int64),
+                ("capacity", C.c_int64), ("seed", C.c_uint64), ("stream_id", C.c_uint32),
+                ("prior_stream_id", C.c_uint32), ("lo", C.c_float * 3), ("hi", C.c_float * 3)]
+
+
+class pdmp_sampler_stats(C.Structure):
+    _fields_ = [("batches", C.c_int64), ("produced", C.c_int64), ("popped_bucket", C.c_int64),
+                ("popped_prior", C.c_int64), ("bucket_size", C.c_int64), ("status", C.c_int32),
+                ("running", C.c_int32), ("producer_busy_s", C.c_double),
+                ("elapsed_s", C.c_double)]
+
+
+class pdmp_rrt_opts(C.Structure):
+    _fields_ = [("max_iters", C.c_int32), ("step", C.c_float), ("goal_tol", C.c_float),
+                ("start", C.c_float * 2), ("goal", C.c_float * 2), ("time_budget_s", C.c_double),
+                ("n_discs", C.c_int32), ("disc_x", C.c_void_p), ("disc_y", C.c_void_p),
+                ("disc_r", C.c_void_p)]
+
+
+class pdmp_rrt_result(C.Structure):
+    _fields_ = [("solved", C.c_int32), ("iters", C.c_int32), ("n_nodes", C.c_int32),
+                ("from_bucket", C.c_int64), ("from_prior", C.c_int64), ("path_len", C.c_double),
+                ("elapsed_s", C.c_double)]
+
+
 _vp, _i32, _i64, _u32, _u64, _f = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float
 _P = C.POINTER
 
@@ -76,6 +102,19 @@ SIGNATURES = {
     "pdmp_bce_logits": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t, _vp]),
     "pdmp_adam_step": (_i32, [_vp, _vp, _vp, _vp, _i64, _i64, _i32, _f, _f, _f, _f, _f, _vp]),
     "pdmp_mlp_num_params": (_i64, [_P(pdmp_mlp)]),
+    "pdmp_bucket_create": (_i32, [_i32, _i64, _P(_vp)]),
+    "pdmp_bucket_push": (_i64, [_vp, _vp, _i64, _i64, _i64, _i64]),
+    "pdmp_bucket_pop": (_i32, [_vp, _vp, _vp]),
+    "pdmp_bucket_size": (_i64, [_vp]),
+    "pdmp_bucket_destroy": (None, [_vp]),
+    "pdmp_sampler_create": (_i32, [_P(pdmp_occupancy), _P(pdmp_sampler_opts), _P(_vp)]),
+    "pdmp_sampler_start": (_i32, [_vp]),
+    "pdmp_sampler_pause": (_i32, [_vp, _i32]),
+    "pdmp_sampler_pop": (_i32, [_vp, _i64, _vp, _vp, _vp]),
+    "pdmp_sampler_get_stats": (_i32, [_vp, _P(pdmp_sampler_stats)]),
+    "pdmp_sampler_destroy": (_i32, [_vp]),
+    "pdmp_rrt_run": (_i32, [_vp, _P(pdmp_rrt_opts), _vp, _vp, _vp, _vp, _vp,
+                            _P(pdmp_rrt_result)]),
     "pdmp_morph_logdet": (_i32, [_P(pdmp_occupancy), _vp, _vp, _i64, _i32, _f, _vp, _vp]),
     "pdmp_morph_inverse": (_i32, [_P(pdmp_occupancy), _vp, _vp, _i64, _i32, _f, _i32, _vp, _vp,
                                   _vp]),

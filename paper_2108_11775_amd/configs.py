@@ -147,6 +147,10 @@ TANH = TanhOcc()
 
 CONFIGS = {1: C1, 2: C2, 3: C3, 4: C4, 5: C5}
 
+# RRT consumer of the producer/consumer workload: start and goal in the disc worlds,
+# points of largest clearance on a 0.5 lattice near opposite corners.
+RRT_START_GOAL = {1: ((-10.0, -10.0), (8.0, 10.0)), 2: ((-10.0, -8.0), (10.0, 10.0))}
+
 # Readings of points the paper leaves open (each is listed with its reason in the
 # design notes).  They are frozen here so that every side uses the same ones.
 READINGS = {

@@ -28,13 +28,6 @@ int32_t check_launch(const char *what) {
     return PDMP_OK;
 }
 
-#define PDMP_REQUIRE(cond, ...)           \
-    do {                                  \
-        if (!(cond)) {                    \
-            ::pdmp::set_error(__VA_ARGS__); \
-            return PDMP_EINVAL;           \
-        }                                 \
-    } while (0)
 
 static int32_t check_occ(const pdmp_occupancy *occ) {
     PDMP_REQUIRE(occ != nullptr, "occupancy is NULL");

@@ -21,6 +21,16 @@ const char *last_error();
 // launch on this thread failed.
 int32_t check_launch(const char *what);
 
+// Argument check of an extern "C" entry point: on failure, record the message and
+// return PDMP_EINVAL.
+#define PDMP_REQUIRE(cond, ...)           \
+    do {                                  \
+        if (!(cond)) {                    \
+            ::pdmp::set_error(__VA_ARGS__); \
+            return PDMP_EINVAL;           \
+        }                                 \
+    } while (0)
+
 // log2(e): exp(-r^2/(2 l^2)) = exp2(-(kappa*r)^2) with kappa^2 = log2(e)/(2 l^2).
 constexpr float kLog2e = 1.4426950408889634f;
 
