@@ -96,6 +96,10 @@ def _load():
         "orc_morph_inverse": (None, [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_double, _dp,
                                      _i64, C.c_int, C.c_double, C.c_int, _dp, _dp, _dp, _dp]),
         "orc_mixture_coins": (None, [C.c_uint64, C.c_uint32, _i64, C.c_double, _u8p]),
+        "orc_cull_eval": (None, [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_double, _fp,
+                                 C.c_float, _ip, _dp, _i64, _dp, _dp]),
+        "orc_morph_culled": (None, [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_double, _fp,
+                                    C.c_float, _ip, _dp, _i64, C.c_int, C.c_double, _dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -579,3 +583,48 @@ def tanh_fit(net: TanhNet, pts, y, steps: int, lr: float, l2: float, b1=0.9, b2=
         losses[t], g = tanh_loss_grad(cur, pts, y, l2)
         adam_step(P, g, m, v, t + 1, lr, b1, b2, eps)
     return P, losses
+
+
+# ----------------------------------------------- compact-support culling ---
+
+@dataclass
+class CullGrid:
+    """Cells of side `cell` (>= the cutoff) on the box starting at `lo`, nc per axis;
+    inv_cell = 1/cell rounded to single precision, as the GPU uses it."""
+    lo: np.ndarray
+    inv_cell: float
+    nc: np.ndarray
+
+    @staticmethod
+    def make(lo, hi, cutoff):
+        lo = np.asarray(lo, np.float32)
+        hi = np.asarray(hi, np.float32)
+        inv = np.float32(1.0) / np.float32(cutoff)
+        # cell side from the rounded inverse, so that a cell is never below the cutoff
+        while 1.0 / float(inv) < float(cutoff):
+            inv = np.nextafter(inv, np.float32(0))
+        nc = np.maximum(1, np.floor((hi.astype(np.float64) - lo) * float(inv)).astype(np.int64) + 1)
+        return CullGrid(lo, float(inv), nc.astype(np.intc))
+
+    def args(self):
+        self._lo = np.ascontiguousarray(self.lo, np.float32)
+        self._nc = np.ascontiguousarray(self.nc, np.intc)
+        return (_P(self._lo, _fp), float(self.inv_cell), _P(self._nc, _ip))
+
+
+def cull_eval(occ: Occupancy, grid: CullGrid, x):
+    """(s, grad c) of the culled occupancy at [dim][n] points."""
+    x = _d(x)
+    dim, n = x.shape
+    s, gc = _zeros(n), _zeros(dim, n)
+    _load().orc_cull_eval(*occ.args(), *grid.args(), _P(x), n, _P(s), _P(gc))
+    return s, gc
+
+
+def morph_culled(occ: Occupancy, grid: CullGrid, x, T: int, eta: float):
+    """The plain morph (Eq. 1) on the culled occupancy."""
+    x = _d(x)
+    dim, n = x.shape
+    out = _zeros(dim, n)
+    _load().orc_morph_culled(*occ.args(), *grid.args(), _P(x), n, int(T), float(eta), _P(out))
+    return out

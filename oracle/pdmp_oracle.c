@@ -1436,3 +1436,82 @@ void orc_mixture_coins(uint64_t seed, uint32_t stream, int64_t n, double eps, ui
         keep[i] = (uint8_t)(u < eps);
     }
 }
+
+/* ------------------------------------------------------------------------- */
+/* Compact-support culling (a variant beyond the paper): a point takes only   */
+/* the hinges whose cell lies in the 3^dim block of cells around its own.     */
+/* Cells have side `cell` >= the cutoff r_c on the box [lo, lo + nc cell);    */
+/* a coordinate's cell is floor((v - lo) * inv_cell) in double precision from */
+/* the single-precision v, lo and inv_cell, clamped to [0, nc - 1].  Every    */
+/* hinge within r_c of the point is then included, so the dropped part of the */
+/* logit is at most sum_j |w_j| exp(-r_c^2 / (2 l^2)).                        */
+/* ------------------------------------------------------------------------- */
+
+static int cull_cell(float v, float lo, float inv_cell, int nc) {
+    double t = ((double)v - (double)lo) * (double)inv_cell;
+    double f = floor(t);
+    if (f < 0.0) return 0;
+    if (f > (double)(nc - 1)) return nc - 1;
+    return (int)f;
+}
+
+/* Logit, gradient of c over the culled hinge set at one point. */
+static void cull_point(int dim, int M, const double *h, const double *w, double beta, double ell,
+                       const float *lo, float inv_cell, const int *nc, const double *x,
+                       double *s_out, double *gc) {
+    int cx[ORC_MAX_DIM];
+    for (int k = 0; k < dim; ++k) cx[k] = cull_cell((float)x[k], lo[k], inv_cell, nc[k]);
+    double il2 = 1.0 / (ell * ell), i2l2 = 0.5 * il2;
+    double s = beta, gs[ORC_MAX_DIM] = {0};
+    for (int j = 0; j < M; ++j) {
+        int near = 1;
+        for (int k = 0; k < dim; ++k) {
+            int hc = cull_cell((float)h[(int64_t)k * M + j], lo[k], inv_cell, nc[k]);
+            if (hc < cx[k] - 1 || hc > cx[k] + 1) near = 0;
+        }
+        if (!near) continue;
+        double r2 = 0.0, d[ORC_MAX_DIM];
+        for (int k = 0; k < dim; ++k) {
+            d[k] = x[k] - h[(int64_t)k * M + j];
+            r2 += d[k] * d[k];
+        }
+        double wp = w[j] * exp(-r2 * i2l2);
+        s += wp;
+        for (int k = 0; k < dim; ++k) gs[k] += -il2 * wp * d[k];
+    }
+    double c = sigmoid(s), sp = c * (1.0 - c);
+    if (s_out) *s_out = s;
+    if (gc)
+        for (int k = 0; k < dim; ++k) gc[k] = sp * gs[k];
+}
+
+/* s and grad c of the culled occupancy at n points. */
+void orc_cull_eval(int dim, int M, const double *h, const double *w, double beta, double ell,
+                   const float *lo, float inv_cell, const int *nc, const double *x, int64_t n,
+                   double *s, double *gc) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double xi[ORC_MAX_DIM], g[ORC_MAX_DIM];
+        for (int k = 0; k < dim; ++k) xi[k] = x[(int64_t)k * n + i];
+        cull_point(dim, M, h, w, beta, ell, lo, inv_cell, nc, xi, s ? &s[i] : NULL, g);
+        if (gc)
+            for (int k = 0; k < dim; ++k) gc[(int64_t)k * n + i] = g[k];
+    }
+}
+
+/* The plain morph (Eq. 1, explicit Euler) on the culled occupancy; the cells are
+ * re-evaluated at every step from the current point. */
+void orc_morph_culled(int dim, int M, const double *h, const double *w, double beta, double ell,
+                      const float *lo, float inv_cell, const int *nc, const double *xin,
+                      int64_t n, int T, double eta, double *xout) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double x[ORC_MAX_DIM], g[ORC_MAX_DIM];
+        for (int k = 0; k < dim; ++k) x[k] = xin[(int64_t)k * n + i];
+        for (int t = 0; t < T; ++t) {
+            cull_point(dim, M, h, w, beta, ell, lo, inv_cell, nc, x, NULL, g);
+            for (int k = 0; k < dim; ++k) x[k] = x[k] - eta * g[k];
+        }
+        for (int k = 0; k < dim; ++k) xout[(int64_t)k * n + i] = x[k];
+    }
+}
