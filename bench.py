@@ -494,6 +494,64 @@ def pipeline_workload(P, I, K, torch, dev, hl):
     return out
 
 
+def culled_workload(P, I, K, torch, hl):
+    """Compact-support hinge culling (a variant beyond the paper) on the large 2-D
+    workload: each point takes the hinges of the 3x3 cells (side >= 5.5 l) around it."""
+    import numpy as np
+    cfg = K.C2
+    occ, x0, N = hl["sc"]["occ"], hl["x0"], hl["N"]
+    dense = P.Occupancy(occ.hinges, occ.weights, occ.lengthscale)
+    rc = 5.5 * cfg.lengthscale
+    g = P.cull_grid(2, [cfg.lo] * 2, [cfg.hi] * 2, rc)
+    out = torch.empty_like(x0)
+    P.morph_culled(dense, g, x0, cfg.T, cfg.eta, out=out)
+    t = Timer(torch)
+    reps = 3
+    with t:
+        for _ in range(reps):
+            P.morph_culled(dense, g, x0, cfg.T, cfg.eta, out=out)
+    ms = t.ms() / reps
+    # own work: the pairs of each point with the hinges of its 3x3 cells, counted at the
+    # start and at the end of the path (the mean of the two stands for every step)
+    h = occ.hinges.cpu().numpy().astype(np.float64)
+    nc = [g.nc[0], g.nc[1]]
+    inv = float(g.inv_cell)
+
+    def cells(v, k):
+        c = np.floor((v.astype(np.float64) - float(g.lo[k])) * inv)
+        return np.clip(c, 0, nc[k] - 1).astype(np.int64)
+
+    hc = np.zeros((nc[1] + 2, nc[0] + 2), np.int64)
+    np.add.at(hc, (cells(h[1], 1) + 1, cells(h[0], 0) + 1), 1)
+    box = sum(np.roll(np.roll(hc, dy, 0), dx, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1))
+
+    def pairs(x):
+        xn = x.cpu().numpy()
+        return float(box[cells(xn[1], 1) + 1, cells(xn[0], 0) + 1].mean())
+
+    per_point = 0.5 * (pairs(x0) + pairs(out))
+    flops = N * cfg.T * per_point * FLOPS_PER_PAIR[2]
+    ach = flops / (ms * 1e-3) / 1e12
+    dc_d, dr_d = hl["sc"]["discs"]
+    _, h1 = P.label_points_discs(dc_d, dr_d, out, count=True)
+    ref = P.morph_samples(dense, x0, cfg.T, cfg.eta)
+    dev_max = (ref - out).abs().amax(dim=0)
+    W = float(occ.weights[:-1].abs().sum())
+    return {"workload": "culled pairwise morph 2-D large: 1,048,576 samples, 64x64 hinges, "
+                        "l=0.4, cutoff 5.5 l (3x3 cells of side 2.2), T=50, eta=0.02",
+            "morph_ms": ms, "samples_per_s": N / (ms * 1e-3),
+            "pairs_per_point_step": per_point, "dense_pairs_per_point_step": cfg.n_hinges,
+            "logit_tail_bound": W * float(np.exp(-rc * rc / (2 * cfg.lengthscale ** 2))),
+            "max_dev_from_dense_morph": dev_max.max().item(),
+            "median_dev_from_dense_morph": dev_max.median().item(),
+            "collision_free_after": 1 - h1.item() / N,
+            "roofline": {"bound": "alu", "achieved": ach, "peak": alu_peak_tflops(2),
+                         "unit": "TFLOP/s", "frac": ach / alu_peak_tflops(2),
+                         "kernel": "k_cull_morph<2>",
+                         "work": "12 FP32 flops + 1 exp per kept (point, hinge) pair, own "
+                                 "culled pairs only"}}
+
+
 def amortised(args, P, I, K, torch, world):
     from paper_2108_11775_amd import amortise
     c3, c5 = K.C3, K.C5
@@ -620,6 +678,8 @@ def main():
                 wl["density_ws2d"] = density_workload(P, I, K, torch, hl)
                 log(f"log-det / inverse: {wl['density_ws2d']['logdet_ms']:.1f} / "
                     f"{wl['density_ws2d']['inverse_ms']:.1f} ms")
+            wl["culled_ws2d"] = culled_workload(P, I, K, torch, hl)
+            log(f"culled morph: {wl['culled_ws2d']['morph_ms']:.2f} ms")
             wl["pipeline"] = pipeline_workload(P, I, K, torch, dev, hl)
             log("producer/consumer done")
             wl["tanh_ws2d"] = tanh_morph(P, I, K, torch, dev)

@@ -186,6 +186,34 @@ int32_t pdmp_mixture_samples(const pdmp_occupancy *occ, uint64_t seed, uint32_t 
                              const float *lo, const float *hi, int64_t n, float eps, int32_t T,
                              float eta, float *x0, float *out, uint8_t *keep, void *stream);
 
+/* ---- compact-support hinge culling for the workspace morph (a variant beyond the
+ * paper; the RBF feature decays as exp(-r^2/(2 l^2))).  A point takes only the hinges
+ * of the 3^dim cells around its own: cells of side 1/inv_cell >= the cutoff r_c on the
+ * box from lo with nc cells per axis, a coordinate's cell being
+ * floor((v - lo) * inv_cell) in FP64 from the FP32 values, clamped to [0, nc - 1].  Every
+ * hinge within r_c of the point is kept, so the dropped part of the logit is at most
+ * sum_j |w_j| exp(-r_c^2 / (2 l^2)) at every step; the hinges should lie in the box.
+ * pdmp_cull_grid_make (host): inv_cell = 1/cutoff rounded to FP32, lowered by ulps until
+ *   1/inv_cell >= cutoff; nc[k] = floor((hi[k] - lo[k]) inv_cell) + 1 (FP64).
+ * pdmp_morph_culled: the plain morph (as pdmp_morph_samples, arm == NULL) on the culled
+ *   occupancy, the cells re-evaluated at every step; in == out allowed.  ws: device
+ *   scratch of pdmp_morph_culled_workspace_size bytes.  Deterministic; a point's result
+ *   does not depend on the rest of the batch. */
+typedef struct {
+    int32_t dim;
+    float lo[3];
+    float inv_cell;
+    int32_t nc[3];
+} pdmp_cull_grid;
+
+int32_t pdmp_cull_grid_make(int32_t dim, const float *lo, const float *hi, float cutoff,
+                            pdmp_cull_grid *g);
+size_t pdmp_morph_culled_workspace_size(const pdmp_occupancy *occ, const pdmp_cull_grid *g,
+                                        int64_t n);
+int32_t pdmp_morph_culled(const pdmp_occupancy *occ, const pdmp_cull_grid *g, const float *in,
+                          float *out, int64_t n, int32_t T, float eta, void *ws, size_t ws_bytes,
+                          void *stream);
+
 /* ---- forward kinematics (Sec. 3.2): body points of configurations q [n_dof][n]
  * in FP32, written to pts [3][n_dof*pts_per_link][n]. */
 int32_t pdmp_fk_body_points(const pdmp_arm *arm, const float *q, int64_t n, float *pts,

@@ -599,7 +599,8 @@ class CullGrid:
     def make(lo, hi, cutoff):
         lo = np.asarray(lo, np.float32)
         hi = np.asarray(hi, np.float32)
-        inv = np.float32(1.0) / np.float32(cutoff)
+        cutoff = np.float32(cutoff)
+        inv = np.float32(1.0) / cutoff
         # cell side from the rounded inverse, so that a cell is never below the cutoff
         while 1.0 / float(inv) < float(cutoff):
             inv = np.nextafter(inv, np.float32(0))

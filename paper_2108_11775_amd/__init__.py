@@ -25,7 +25,7 @@ __all__ = ["Occupancy", "Arm", "PdmpError", "abi_version", "uniform_samples",
            "bce_logits", "adam_step", "fit_occupancy", "Mlp", "arm_max_occupancy",
            "amortised_morph", "TanhNet", "tanh_occupancy_eval", "tanh_occupancy_grad",
            "tanh_morph_samples", "tanh_loss_grad", "tanh_fit", "morph_logdet", "morph_inverse",
-           "mixture_samples", "Bucket", "Sampler", "rrt_run"]
+           "mixture_samples", "Bucket", "Sampler", "rrt_run", "cull_grid", "morph_culled"]
 
 
 def _torch():
@@ -746,4 +746,31 @@ def rrt_run(sampler: Sampler, start, goal, step: float, goal_tol: float, discs,
     k, m = res.iters, res.n_nodes
     out.update(nodes=nodes[:m], parent=parent[:m], samples=samples[:k], sample_from_bucket=fb[:k],
                t_sample=ts[:k])
+    return out
+
+
+# ----------------------------------------------- compact-support culling ---
+
+def cull_grid(dim: int, lo, hi, cutoff: float):
+    """The cell grid of the culled morph (cells of side >= cutoff on the box [lo, hi])."""
+    g = _lib.pdmp_cull_grid()
+    lo_a = (C.c_float * dim)(*[float(v) for v in lo])
+    hi_a = (C.c_float * dim)(*[float(v) for v in hi])
+    _lib.call("pdmp_cull_grid_make", int(dim), lo_a, hi_a, float(cutoff), C.byref(g))
+    return g
+
+
+def morph_culled(occ: Occupancy, grid, x, T: int, eta: float, out=None):
+    """The workspace morph with compact-support hinge culling (3^dim cells per point)."""
+    torch = _torch()
+    lib = _lib.load()
+    n = int(x.shape[1])
+    _dev(x, "x", torch.float32, (occ.dim, n))
+    if out is None:
+        out = torch.empty_like(x)
+    o = occ.c_struct()
+    ws = _workspace(lib.pdmp_morph_culled_workspace_size(C.byref(o), C.byref(grid), n), x.device)
+    _lib.call("pdmp_morph_culled", C.byref(o), C.byref(grid), C.c_void_p(x.data_ptr()),
+              _dev(out, "out", torch.float32, (occ.dim, n)), n, int(T), float(eta), _dev(ws, "ws"),
+              ws.numel(), _stream(x.device))
     return out

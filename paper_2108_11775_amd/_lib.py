@@ -76,6 +76,11 @@ class pdmp_rrt_result(C.Structure):
                 ("elapsed_s", C.c_double)]
 
 
+class pdmp_cull_grid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("lo", C.c_float * 3), ("inv_cell", C.c_float),
+                ("nc", C.c_int32 * 3)]
+
+
 _vp, _i32, _i64, _u32, _u64, _f = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_float
 _P = C.POINTER
 
@@ -102,6 +107,11 @@ SIGNATURES = {
     "pdmp_bce_logits": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t, _vp]),
     "pdmp_adam_step": (_i32, [_vp, _vp, _vp, _vp, _i64, _i64, _i32, _f, _f, _f, _f, _f, _vp]),
     "pdmp_mlp_num_params": (_i64, [_P(pdmp_mlp)]),
+    "pdmp_cull_grid_make": (_i32, [_i32, _P(_f), _P(_f), _f, _P(pdmp_cull_grid)]),
+    "pdmp_morph_culled_workspace_size": (C.c_size_t, [_P(pdmp_occupancy), _P(pdmp_cull_grid),
+                                                      _i64]),
+    "pdmp_morph_culled": (_i32, [_P(pdmp_occupancy), _P(pdmp_cull_grid), _vp, _vp, _i64, _i32, _f,
+                                 _vp, C.c_size_t, _vp]),
     "pdmp_bucket_create": (_i32, [_i32, _i64, _P(_vp)]),
     "pdmp_bucket_push": (_i64, [_vp, _vp, _i64, _i64, _i64, _i64]),
     "pdmp_bucket_pop": (_i32, [_vp, _vp, _vp]),

@@ -264,6 +264,69 @@ int32_t pdmp_mixture_samples(const pdmp_occupancy *occ, uint64_t seed, uint32_t 
     return launch_mix_select(seed, stream_id, eps, occ->dim, n, x0, out, keep, s);
 }
 
+int32_t pdmp_cull_grid_make(int32_t dim, const float *lo, const float *hi, float cutoff,
+                            pdmp_cull_grid *g) {
+    PDMP_REQUIRE(g && lo && hi, "NULL argument");
+    PDMP_REQUIRE(dim == 2 || dim == 3, "dim must be 2 or 3");
+    PDMP_REQUIRE(std::isfinite(cutoff) && cutoff > 0.0f, "cutoff must be finite and > 0");
+    float inv = 1.0f / cutoff;
+    while (1.0 / (double)inv < (double)cutoff) inv = std::nextafter(inv, 0.0f);
+    std::memset(g, 0, sizeof(*g));
+    g->dim = dim;
+    g->inv_cell = inv;
+    int64_t cells = 1;
+    for (int k = 0; k < dim; ++k) {
+        PDMP_REQUIRE(std::isfinite(lo[k]) && std::isfinite(hi[k]) && lo[k] <= hi[k],
+                     "bad box on axis %d", k);
+        const double c = std::floor(((double)hi[k] - (double)lo[k]) * (double)inv) + 1.0;
+        PDMP_REQUIRE(c <= (double)(1 << 20), "too many cells on axis %d", k);
+        g->lo[k] = lo[k];
+        g->nc[k] = c < 1.0 ? 1 : (int32_t)c;
+        cells *= g->nc[k];
+    }
+    PDMP_REQUIRE(cells <= (int64_t)1 << 24, "too many cells (%lld)", (long long)cells);
+    return PDMP_OK;
+}
+
+static int32_t check_cull_grid(const pdmp_occupancy *occ, const pdmp_cull_grid *g) {
+    PDMP_REQUIRE(g != nullptr, "grid NULL");
+    PDMP_REQUIRE(g->dim == occ->dim, "grid dim %d differs from the occupancy's %d", g->dim,
+                 occ->dim);
+    PDMP_REQUIRE(std::isfinite(g->inv_cell) && g->inv_cell > 0.0f, "inv_cell invalid");
+    int64_t cells = 1;
+    for (int k = 0; k < g->dim; ++k) {
+        PDMP_REQUIRE(g->nc[k] >= 1 && g->nc[k] <= (1 << 20), "nc out of range");
+        cells *= g->nc[k];
+    }
+    PDMP_REQUIRE(cells <= (int64_t)1 << 24, "too many cells");
+    return PDMP_OK;
+}
+
+size_t pdmp_morph_culled_workspace_size(const pdmp_occupancy *occ, const pdmp_cull_grid *g,
+                                        int64_t n) {
+    if (check_occ(occ) || check_cull_grid(occ, g) || n < 1) return 0;
+    return cull_ws_bytes(*g, occ->n_hinges, n);
+}
+
+int32_t pdmp_morph_culled(const pdmp_occupancy *occ, const pdmp_cull_grid *g, const float *in,
+                          float *out, int64_t n, int32_t T, float eta, void *ws, size_t ws_bytes,
+                          void *stream) {
+    int32_t st = check_occ(occ);
+    if (st) return st;
+    if ((st = check_cull_grid(occ, g))) return st;
+    PDMP_REQUIRE(n >= 0 && n < ((int64_t)1 << 31), "n out of range");
+    PDMP_REQUIRE(T >= 0, "T < 0");
+    PDMP_REQUIRE(std::isfinite(eta), "eta not finite");
+    if (n == 0) return PDMP_OK;
+    PDMP_REQUIRE(in && out, "in/out NULL");
+    const size_t need = cull_ws_bytes(*g, occ->n_hinges, n);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+        return PDMP_ENOMEM;
+    }
+    return launch_morph_culled(*occ, *g, in, out, n, T, eta, ws, (hipStream_t)stream);
+}
+
 int32_t pdmp_fk_body_points(const pdmp_arm *arm, const float *q, int64_t n, float *pts,
                             void *stream) {
     int32_t st = check_arm(arm, PDMP_MAX_PTS_PER_LINK);

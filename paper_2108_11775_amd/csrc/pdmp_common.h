@@ -161,6 +161,9 @@ int32_t launch_morph_inverse(int dim, int mode, const float *hinges, const float
 // Epsilon mixture: keep[i] = (u_i < eps) from Philox, out[:, i] = x0[:, i] where kept.
 int32_t launch_mix_select(uint64_t seed, uint32_t sid, float eps, int dim, int64_t n,
                           const float *x0, float *out, uint8_t *keep, hipStream_t st);
+size_t cull_ws_bytes(const pdmp_cull_grid &g, int M, int64_t n);
+int32_t launch_morph_culled(const pdmp_occupancy &occ, const pdmp_cull_grid &cg, const float *in,
+                            float *out, int64_t n, int T, float eta, void *ws, hipStream_t st);
 // out[j] = scale * sum_r part[r m + j] (+ add_scale add[j]), fixed order.
 int32_t launch_sum_rows(const float *part, int rows, int64_t m, double scale, const float *add,
                         float add_scale, float *out, hipStream_t st);
