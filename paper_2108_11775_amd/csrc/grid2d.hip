@@ -29,22 +29,24 @@ constexpr int kG2MaxKS = 32;    // G0 <= 64
 constexpr int kG2MaxTB = 2;     // G1 <= 64
 
 template <int TB, int MODE>
-__global__ void __launch_bounds__(kG2Block)
+__global__ void __launch_bounds__(kG2Block) __attribute__((amdgpu_waves_per_eu(3)))
 k_grid2d(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
          float kappa, float gscale, const float *x_in, int64_t n, int T, float eta, float *c_out,
          float *s_out, float *g_out, float *x_out) {
     // fragments: frag[kk][t][lane] = W[b = 32t + lane%32][a = 2kk + lane/32] (0 outside)
-    __shared__ float frag[kG2MaxKS * TB * 64];
-    __shared__ float gxs[2 * kG2MaxKS];
+    // one k-step of padding so that the next step's operands can always be read ahead
+    __shared__ float frag[(kG2MaxKS + 1) * TB * 64];
+    __shared__ float gxs[2 * (kG2MaxKS + 1)];
     __shared__ float gys[32 * TB];
     const int M = g0 * g1;
     const int ks = (g0 + 1) / 2;
-    for (int idx = threadIdx.x; idx < ks * TB * 64; idx += kG2Block) {
+    for (int idx = threadIdx.x; idx < (ks + 1) * TB * 64; idx += kG2Block) {
         const int ln = idx & 63, t = (idx >> 6) % TB, kk = idx / (64 * TB);
         const int b = 32 * t + (ln & 31), a = 2 * kk + (ln >> 5);
         frag[idx] = (a < g0 && b < g1) ? weights[a + (int64_t)g0 * b] : 0.0f;
     }
-    for (int a = threadIdx.x; a < 2 * ks; a += kG2Block) gxs[a] = a < g0 ? kappa * hinges[a] : 0.0f;
+    for (int a = threadIdx.x; a < 2 * (ks + 1); a += kG2Block)
+        gxs[a] = a < g0 ? kappa * hinges[a] : 0.0f;
     for (int b = threadIdx.x; b < 32 * TB; b += kG2Block)
         gys[b] = b < g1 ? kappa * hinges[(size_t)M + (size_t)g0 * b] : 0.0f;
     __syncthreads();
@@ -61,19 +63,42 @@ k_grid2d(const float *__restrict__ hinges, const float *__restrict__ weights, in
     for (int st = 0; st < steps; ++st) {
         const float xs = kappa * x, ys = kappa * y;
         f32x16_t U[TB], V[TB];
+        // k-step 0 starts the accumulators from the zero constant (no register clears);
+        // the LDS operands of step kk + 1 are read while step kk's products run
+        float gx_n = gxs[half], w_n[TB];
 #pragma unroll
-        for (int t = 0; t < TB; ++t)
+        for (int t = 0; t < TB; ++t) w_n[t] = frag[t * 64 + lane];
+        {
+            const float d = xs - gx_n;
+            const float e = exp2_fast(-d * d);
+            const float de = e * d;
+            float w_c[TB];
 #pragma unroll
-            for (int v = 0; v < 16; ++v) U[t][v] = V[t][v] = 0.0f;
-        for (int kk = 0; kk < ks; ++kk) {
-            const float d = xs - gxs[2 * kk + half];
+            for (int t = 0; t < TB; ++t) w_c[t] = w_n[t];
+            gx_n = gxs[2 + half];
+#pragma unroll
+            for (int t = 0; t < TB; ++t) w_n[t] = frag[(TB + t) * 64 + lane];
+            const f32x16_t zero = {};
+#pragma unroll
+            for (int t = 0; t < TB; ++t) {
+                U[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], e, zero, 0, 0, 0);
+                V[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], de, zero, 0, 0, 0);
+            }
+        }
+        for (int kk = 1; kk < ks; ++kk) {
+            const float d = xs - gx_n;
+            float w_c[TB];
+#pragma unroll
+            for (int t = 0; t < TB; ++t) w_c[t] = w_n[t];
+            gx_n = gxs[2 * (kk + 1) + half];
+#pragma unroll
+            for (int t = 0; t < TB; ++t) w_n[t] = frag[((kk + 1) * TB + t) * 64 + lane];
             const float e = exp2_fast(-d * d);
             const float de = e * d;
 #pragma unroll
             for (int t = 0; t < TB; ++t) {
-                const float wfr = frag[(kk * TB + t) * 64 + lane];
-                U[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(wfr, e, U[t], 0, 0, 0);
-                V[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(wfr, de, V[t], 0, 0, 0);
+                U[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], e, U[t], 0, 0, 0);
+                V[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], de, V[t], 0, 0, 0);
             }
         }
         s = 0.0f;
