@@ -170,7 +170,32 @@ k_cull_morph(CullGridDev g, const float *__restrict__ hs, const float *__restric
                     const int cid = cx + g.nc[0] * (cy + g.nc[1] * cz);
                     const int a = cell_start[cid], b = cell_start[cid + 1];
                     if (!near) continue;
-                    for (int j = a; j < b; ++j) {
+                    // groups of 8 hinges: one batch of scalar loads per group, so the
+                    // memory latency is paid once per 8 pairs
+                    int j = a;
+                    for (; j + 8 <= b; j += 8) {
+                        float hv[DIM][8], wv[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+#pragma unroll
+                            for (int k = 0; k < DIM; ++k) hv[k][u] = hs[(size_t)k * M + j + u];
+                            wv[u] = ws[j + u];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            float d[DIM], r2 = 0.0f;
+#pragma unroll
+                            for (int k = 0; k < DIM; ++k) {
+                                d[k] = x[k] - hv[k][u];
+                                r2 = fmaf(d[k], d[k], r2);
+                            }
+                            const float wp = wv[u] * exp2_fast(-r2 * kexp);
+                            s += wp;
+#pragma unroll
+                            for (int k = 0; k < DIM; ++k) gx[k] = fmaf(wp, d[k], gx[k]);
+                        }
+                    }
+                    for (; j < b; ++j) {
                         float d[DIM], r2 = 0.0f;
 #pragma unroll
                         for (int k = 0; k < DIM; ++k) {

@@ -61,7 +61,12 @@ __device__ __forceinline__ void g3_point(const float *frag, const float *ax, con
                                          const float *az, float xs, float ys, float zs, float &s,
                                          float &sx, float &sy, float &sz) {
     using C = G3<G0, G2>;
-    const int lane = threadIdx.x & 63, h = lane >> 5;
+    const int lane0 = threadIdx.x & 63, h = lane0 >> 5;
+    // The weight fragments are the same at every call; an opaque copy of the lane
+    // index keeps the compiler from hoisting their LDS reads out of the callers'
+    // loops into registers.
+    int lane = lane0;
+    asm volatile("" : "+v"(lane));
     float e[C::KS], de[C::KS];
 #pragma unroll
     for (int kk = 0; kk < C::KS; ++kk) {
@@ -88,25 +93,39 @@ __device__ __forceinline__ void g3_point(const float *frag, const float *ax, con
             ez[cc] = exp2_fast(-d * d);
             dez[cc] = ez[cc] * d;
         }
+        // k-step 0 from the zero accumulator (no register clears per tile)
+        const f32x16_g3 zero = {};
         f32x16_g3 U, V;
+        {
+            const float w = frag[(t * C::KS) * 64 + lane];
+            U = __builtin_amdgcn_mfma_f32_32x32x2f32(w, e[0], zero, 0, 0, 0);
+            if (GRAD) V = __builtin_amdgcn_mfma_f32_32x32x2f32(w, de[0], zero, 0, 0, 0);
+        }
 #pragma unroll
-        for (int v = 0; v < 16; ++v) U[v] = V[v] = 0.0f;
-#pragma unroll
-        for (int kk = 0; kk < C::KS; ++kk) {
+        for (int kk = 1; kk < C::KS; ++kk) {
             const float w = frag[(t * C::KS + kk) * 64 + lane];
             U = __builtin_amdgcn_mfma_f32_32x32x2f32(w, e[kk], U, 0, 0, 0);
             if (GRAD) V = __builtin_amdgcn_mfma_f32_32x32x2f32(w, de[kk], V, 0, 0, 0);
         }
-        // row i = 8(v/4) + 4h + v%4 of tile t: b = i mod 16 (table slot v%8), c = 2t + v/8
+        // row i = 8(v/4) + 4h + v%4 of tile t: b = i mod 16 (table slot v%8), c = 2t + v/8;
+        // the y sums of each z-plane first, then one ez (dez) factor per plane
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int u = v & 7, c = v >> 3;
-            const float ezey = ez[c] * ey[u];
-            s = fmaf(ezey, U[v], s);
+        for (int c = 0; c < 2; ++c) {
+            float py = 0.0f, pyx = 0.0f, pdy = 0.0f;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int v = 8 * c + u;
+                py = fmaf(ey[u], U[v], py);
+                if (GRAD) {
+                    pyx = fmaf(ey[u], V[v], pyx);
+                    pdy = fmaf(dey[u], U[v], pdy);
+                }
+            }
+            s = fmaf(ez[c], py, s);
             if (GRAD) {
-                sx = fmaf(ezey, V[v], sx);
-                sy = fmaf(ez[c] * dey[u], U[v], sy);
-                sz = fmaf(dez[c] * ey[u], U[v], sz);
+                sx = fmaf(ez[c], pyx, sx);
+                sy = fmaf(ez[c], pdy, sy);
+                sz = fmaf(dez[c], py, sz);
             }
         }
     }
@@ -211,7 +230,7 @@ __device__ __forceinline__ float sum8(float v) {
 // ---- joint-space morph (MORPH) or largest body-point occupancy (check) ----
 // 4 configurations per wave; lane%32 = 8*cfg + k, body point k of every link.
 template <int NDOF, int G0, int G2, bool MORPH>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_arm_grid3d(pdmp_arm arm, const float *__restrict__ hinges, const float *__restrict__ weights,
              float kappa, float gscale, const float *q_in, float *q_out, int64_t n, int T,
              float eta, const uint32_t *__restrict__ n_active, float thresh, float *maxc_out,

@@ -24,7 +24,8 @@ namespace pdmp {
 
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_tn;
 
-constexpr int kTnBlock = 256;   // 4 waves, 16 points each
+constexpr int kTnBlock = 256;   // 4 waves, 16 points each (fit)
+constexpr int kTnMorphBlock = 512;  // 8 waves share one LDS copy of the weights (morph)
 constexpr int kTnPts = 16;      // points per wave
 
 // tanh(z) and its slope 1 - tanh^2 from e = exp(-2|z|) in (0, 1]:
@@ -218,7 +219,7 @@ __device__ __forceinline__ void tn_point(const TnLds<DIM, NT, L> &S, const float
 }
 
 template <int DIM, int NT, int L, int MODE>
-__global__ void __launch_bounds__(kTnBlock)
+__global__ void __launch_bounds__(kTnMorphBlock)
 k_tanh_net(const float *__restrict__ P, int H, const float *x_in, int64_t n, int T, float eta,
            float *c_out, float *s_out, float *g_out, float *x_out) {
     __shared__ __attribute__((aligned(16))) TnLds<DIM, NT, L> S;
@@ -226,8 +227,8 @@ k_tanh_net(const float *__restrict__ P, int H, const float *x_in, int64_t n, int
     __syncthreads();
     const int lane = threadIdx.x & 63, quad = lane >> 4;
     const int64_t tiles = (n + kTnPts - 1) / kTnPts;
-    const int64_t wstride = (int64_t)gridDim.x * (kTnBlock / 64);
-    for (int64_t tile = (int64_t)blockIdx.x * (kTnBlock / 64) + (threadIdx.x >> 6); tile < tiles;
+    const int64_t wstride = (int64_t)gridDim.x * (kTnMorphBlock / 64);
+    for (int64_t tile = (int64_t)blockIdx.x * (kTnMorphBlock / 64) + (threadIdx.x >> 6); tile < tiles;
          tile += wstride) {
         const int64_t i = tile * kTnPts + (lane & 15);
         const int64_t ic = i < n ? i : n - 1;
@@ -267,9 +268,10 @@ template <int DIM, int NT, int L>
 static void tn_launch(int mode, const pdmp_tanh_net &net, const float *x, int64_t n, int T,
                       float eta, float *c, float *s, float *g, float *xo, hipStream_t st) {
     const int64_t tiles = (n + kTnPts - 1) / kTnPts;
-    int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 1024) blocks = 1024;
-    const dim3 grid((unsigned)blocks), blk(kTnBlock);
+    constexpr int wpb = kTnMorphBlock / 64;
+    int64_t blocks = (tiles + wpb - 1) / wpb;
+    if (blocks > 512) blocks = 512;
+    const dim3 grid((unsigned)blocks), blk(kTnMorphBlock);
     if (mode == kEval)
         hipLaunchKernelGGL((k_tanh_net<DIM, NT, L, kEval>), grid, blk, 0, st, net.params,
                            net.hidden, x, n, T, eta, c, s, g, xo);
