@@ -42,8 +42,8 @@ FLOPS_PER_PAIR = {2: 12, 3: 17}    # 5*dim + 2 algorithmic FP32 flops per sample
 # profiles/k_grid2d_morph_ws2d_1M.md (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the
 # factors a plain 256 MiB device copy reads under the same counters).  Valid only
 # while grid2d.hip is the source the counters were taken on.
-GRID2D_TRAFFIC = {"bytes": (4232.5 * 2.0 + 8192.0) * 1024,
-                  "sha256": "214af559c0e5c1879e08bbc0db22836c1871253a6beb4824be719d5093b62c49"}
+GRID2D_TRAFFIC = {"bytes": (4222.5 * 2.0 + 8192.0) * 1024,
+                  "sha256": "84d22bf2a579b7c21fecd0f876bb4ea0d6e397064491b38005c0b35972e0da02"}
 
 
 def grid2d_traffic():
