@@ -51,3 +51,20 @@ def test_within_the_tail_bound(dim, rc_l):
     assert np.all(np.abs(gc - gc_d).max(axis=0) <= bound * (1 + 1e-9) + 1e-15)
     # and the culling really drops hinges: the sums differ somewhere
     assert np.any(s != s_d)
+
+
+def test_points_beyond_the_box_take_the_last_cell():
+    # box [0, 10] with unit cells: 11 cells, the last one [10, 11).  A point at
+    # x = 11.5 belongs to the clamped cell 10, so it takes the hinges of cells 9 and 10
+    # only: the hinge at 9.5 (distance 2) is kept, the one at 8.5 (cell 8) is not.
+    h = np.array([[8.5, 9.5, 1.5, 2.5], [0.5, 0.5, 0.5, 0.5]])
+    w = np.array([1.0, 2.0, 3.0, 4.0])
+    occ = O.Occupancy(h, w, 0.25, 5.0)
+    g = O.CullGrid.make([0.0, 0.0], [10.0, 10.0], 1.0)
+    assert list(g.nc) == [11, 11]
+    s, _ = O.cull_eval(occ, g, np.array([[11.5], [0.5]]))
+    assert abs(s[0] - (0.25 + 2.0 * math.exp(-4.0 / 50.0))) <= 1e-15
+    # x = -1.5 is clamped to cell 0: cells 0 and 1 only, so the hinge at 1.5 is kept
+    # and the one at 2.5 (cell 2) is not
+    s2, _ = O.cull_eval(occ, g, np.array([[-1.5], [0.5]]))
+    assert abs(s2[0] - (0.25 + 3.0 * math.exp(-9.0 / 50.0))) <= 1e-15

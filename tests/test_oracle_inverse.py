@@ -110,3 +110,16 @@ def test_logdet_3d_matches_finite_difference_jacobian():
     z = O.morph_ws(occ, x, T, eta)
     y, ld_i, _, r = O.morph_inverse(occ, z, T, eta, 50)
     assert np.allclose(y, x, rtol=0, atol=1e-11) and np.allclose(ld_i, ld, rtol=0, atol=1e-10)
+
+
+def test_mixture_coins_strict_threshold_and_counter():
+    seed, sid = I.philox_seed(3), 11
+    key = [seed & 0xffffffff, seed >> 32]
+    us = np.array([(O.philox4x32_10([i, 0, 0xffffffff, sid], key)[0] >> 8) * 2.0 ** -24
+                   for i in range(300)])
+    # the coin is u < eps, taken on the counter with third word 0xffffffff
+    keep = O.mixture_coins(seed, sid, 300, 0.3)
+    assert np.array_equal(keep, (us < 0.3).astype(np.uint8))
+    j = int(np.argmax(us))
+    at = O.mixture_coins(seed, sid, 300, float(us[j]))
+    assert at[j] == 0 and at.sum() == int((us < us[j]).sum())
