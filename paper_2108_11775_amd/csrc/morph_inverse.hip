@@ -53,23 +53,41 @@ template <int TB, bool HESS>
 __device__ __forceinline__ void g2i_eval(const float *frag, const float *gxs, const float *gys,
                                          int ks, float xs, float ys, float &s, float &sx,
                                          float &sy, float &sxx, float &sxy, float &syy) {
-    const int lane = threadIdx.x & 63, half = lane >> 5;
+    const int lane0 = threadIdx.x & 63, half = lane0 >> 5;
+    int lane = lane0;  // opaque: the fragment reads stay inside the callers' loops
+    asm volatile("" : "+v"(lane));
     f32x16_iv U[TB], V[TB], Q[TB];
+    // k-step 0 from the zero accumulator; the next step's LDS operands are read ahead
+    // (the arrays carry one step of padding)
+    float gx_n = gxs[half], w_n[TB];
 #pragma unroll
-    for (int t = 0; t < TB; ++t)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) U[t][v] = V[t][v] = Q[t][v] = 0.0f;
+    for (int t = 0; t < TB; ++t) w_n[t] = frag[t * 64 + lane];
     for (int kk = 0; kk < ks; ++kk) {
-        const float d = xs - gxs[2 * kk + half];
+        const float d = xs - gx_n;
+        float w_c[TB];
+#pragma unroll
+        for (int t = 0; t < TB; ++t) w_c[t] = w_n[t];
+        gx_n = gxs[2 * (kk + 1) + half];
+#pragma unroll
+        for (int t = 0; t < TB; ++t) w_n[t] = frag[((kk + 1) * TB + t) * 64 + lane];
         const float e = exp2_fast(-d * d);
         const float de = e * d;
         const float dde = de * d;
+        if (kk == 0) {
+            const f32x16_iv zero = {};
 #pragma unroll
-        for (int t = 0; t < TB; ++t) {
-            const float wfr = frag[(kk * TB + t) * 64 + lane];
-            U[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(wfr, e, U[t], 0, 0, 0);
-            V[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(wfr, de, V[t], 0, 0, 0);
-            if (HESS) Q[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(wfr, dde, Q[t], 0, 0, 0);
+            for (int t = 0; t < TB; ++t) {
+                U[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], e, zero, 0, 0, 0);
+                V[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], de, zero, 0, 0, 0);
+                if (HESS) Q[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], dde, zero, 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < TB; ++t) {
+                U[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], e, U[t], 0, 0, 0);
+                V[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], de, V[t], 0, 0, 0);
+                if (HESS) Q[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], dde, Q[t], 0, 0, 0);
+            }
         }
     }
     s = sx = sy = sxx = sxy = syy = 0.0f;
@@ -103,21 +121,22 @@ __device__ __forceinline__ void g2i_eval(const float *frag, const float *gxs, co
 // MODE kLogdet: forward morph with the log-determinant.  MODE kInverse: inverse by
 // fixed point (iters per step) with residual and log-determinant.
 template <int TB, int MODE>
-__global__ void __launch_bounds__(kIvBlock)
+__global__ void __launch_bounds__(kIvBlock) __attribute__((amdgpu_waves_per_eu(3)))
 k_grid2d_inv(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
              float kappa, float gscale, const float *x_in, int64_t n, int T, float eta, int iters,
              float *x_out, float *logdet_out, float *resid_out) {
-    __shared__ float frag[32 * TB * 64];
-    __shared__ float gxs[64];
+    __shared__ float frag[33 * TB * 64];  // one k-step of padding for the read-ahead
+    __shared__ float gxs[66];
     __shared__ float gys[32 * TB];
     const int M = g0 * g1;
     const int ks = (g0 + 1) / 2;
-    for (int idx = threadIdx.x; idx < ks * TB * 64; idx += kIvBlock) {
+    for (int idx = threadIdx.x; idx < (ks + 1) * TB * 64; idx += kIvBlock) {
         const int ln = idx & 63, t = (idx >> 6) % TB, kk = idx / (64 * TB);
         const int b = 32 * t + (ln & 31), a = 2 * kk + (ln >> 5);
         frag[idx] = (a < g0 && b < g1) ? weights[a + (int64_t)g0 * b] : 0.0f;
     }
-    for (int a = threadIdx.x; a < 2 * ks; a += kIvBlock) gxs[a] = a < g0 ? kappa * hinges[a] : 0.0f;
+    for (int a = threadIdx.x; a < 2 * (ks + 1); a += kIvBlock)
+        gxs[a] = a < g0 ? kappa * hinges[a] : 0.0f;
     for (int b = threadIdx.x; b < 32 * TB; b += kIvBlock)
         gys[b] = b < g1 ? kappa * hinges[(size_t)M + (size_t)g0 * b] : 0.0f;
     __syncthreads();

@@ -187,8 +187,7 @@ __device__ __forceinline__ void tn_point(const TnLds<DIM, NT, L> &S, const float
 #pragma unroll
     for (int l = L - 1; l >= 1; --l) {
         f32x4_tn G[NT];
-#pragma unroll
-        for (int ti = 0; ti < NT; ++ti) G[ti][0] = G[ti][1] = G[ti][2] = G[ti][3] = 0.0f;
+        const f32x4_tn zero = {};  // the first product starts from the zero accumulator
         const float *bw = S.bw + (l - 1) * NT * NT * 256;
 #pragma unroll
         for (int to = 0; to < NT; ++to)
@@ -197,7 +196,8 @@ __device__ __forceinline__ void tn_point(const TnLds<DIM, NT, L> &S, const float
 #pragma unroll
                 for (int ti = 0; ti < NT; ++ti)
                     G[ti] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                        bw[((ti * NT + to) * 4 + v) * 64 + lane], e[to][v], G[ti], 0, 0, 0);
+                        bw[((ti * NT + to) * 4 + v) * 64 + lane], e[to][v],
+                        (to == 0 && v == 0) ? zero : G[ti], 0, 0, 0);
 #pragma unroll
         for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
@@ -447,8 +447,7 @@ k_tanh_fb(const float *__restrict__ P, int H, const float *__restrict__ x,
 #pragma unroll
         for (int l = L - 1; l >= 1; --l) {
             f32x4_tn G[NT];
-#pragma unroll
-            for (int ti = 0; ti < NT; ++ti) G[ti][0] = G[ti][1] = G[ti][2] = G[ti][3] = 0.0f;
+            const f32x4_tn zero = {};
             const float *bw = S.bw + (l - 1) * NT * NT * 256;
 #pragma unroll
             for (int to = 0; to < NT; ++to)
@@ -457,7 +456,8 @@ k_tanh_fb(const float *__restrict__ P, int H, const float *__restrict__ x,
 #pragma unroll
                     for (int ti = 0; ti < NT; ++ti)
                         G[ti] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            bw[((ti * NT + to) * 4 + v) * 64 + lf], e[to][v], G[ti], 0, 0, 0);
+                            bw[((ti * NT + to) * 4 + v) * 64 + lf], e[to][v],
+                            (to == 0 && v == 0) ? zero : G[ti], 0, 0, 0);
 #pragma unroll
             for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
