@@ -432,7 +432,9 @@ typedef struct {
  *   producer stops launching and pushing while paused != 0 (forces an empty S).
  *   pop: n samples into x [n][dim] (row per sample), index [n] and from_bucket [n]
  *   (both nullable); never waits.  Single consumer thread.  destroy: stops and
- *   joins the producer, frees everything, returns the producer's status. */
+ *   joins the producer, frees everything, returns the producer's status.  When
+ *   that status is not PDMP_OK, get_stats and destroy also leave the producer's
+ *   message in the calling thread's pdmp_last_error(). */
 int32_t pdmp_sampler_create(const pdmp_occupancy *occ, const pdmp_sampler_opts *opts,
                             pdmp_sampler **out);
 int32_t pdmp_sampler_start(pdmp_sampler *s);

@@ -694,9 +694,14 @@ class Sampler:
         return x, idx, fb
 
     def stats(self) -> dict:
+        """Counters of pdmp_sampler_stats; "error" holds the producer's message once
+        its status is not PDMP_OK."""
         st = _lib.pdmp_sampler_stats()
         _lib.call("pdmp_sampler_get_stats", self._h, C.byref(st))
-        return {f: getattr(st, f) for f, _ in st._fields_}
+        out = {f: getattr(st, f) for f, _ in st._fields_}
+        msg = self._lib.pdmp_last_error() if st.status != _lib.PDMP_OK else None
+        out["error"] = msg.decode() if msg else ""
+        return out
 
     def close(self) -> int:
         """Stop and join the producer; returns its status."""

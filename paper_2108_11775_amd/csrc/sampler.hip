@@ -135,6 +135,7 @@ struct pdmp_sampler {
     std::thread th;
     std::atomic<bool> stop{false}, paused{false}, running{false};
     std::atomic<int32_t> status{PDMP_OK};
+    char err[512] = "";  // producer's message, written before status is published
     std::atomic<int64_t> batches{0}, produced{0};
     std::atomic<double> busy_s{0.0};
     int64_t popped_bucket = 0, popped_prior = 0, prior_next = 0;  // consumer side
@@ -151,8 +152,9 @@ void producer_main(pdmp_sampler *s) {
     hipEvent_t ev[2] = {nullptr, nullptr};
     auto fail = [&](hipError_t e, const char *what) {
         if (e != hipSuccess) {
-            set_error("sampler producer: %s: %s", what, hipGetErrorString(e));
-            s->status.store(PDMP_EDEVICE);
+            snprintf(s->err, sizeof(s->err), "sampler producer: %s: %s", what,
+                     hipGetErrorString(e));
+            s->status.store(PDMP_EDEVICE, std::memory_order_release);
             return true;
         }
         return false;
@@ -175,7 +177,9 @@ void producer_main(pdmp_sampler *s) {
                                          dim, B, x0, st);
         if (!r) r = pdmp_morph_samples(&s->occ, nullptr, x0, x1[u], B, s->o.T, s->o.eta, st);
         if (r) {
-            s->status.store(r);
+            // the message sits in this thread's error buffer: hand it to the consumer
+            snprintf(s->err, sizeof(s->err), "sampler producer: %s", pdmp_last_error());
+            s->status.store(r, std::memory_order_release);
             return false;
         }
         return !fail(hipMemcpyAsync(h[u], x1[u], sizeof(float) * dim * B, hipMemcpyDeviceToHost,
@@ -354,7 +358,8 @@ int32_t pdmp_sampler_get_stats(const pdmp_sampler *s, pdmp_sampler_stats *st) {
     st->popped_bucket = s->popped_bucket;
     st->popped_prior = s->popped_prior;
     st->bucket_size = s->bucket.size();
-    st->status = s->status.load();
+    st->status = s->status.load(std::memory_order_acquire);
+    if (st->status != PDMP_OK) set_error("%s", s->err);
     st->running = s->running.load() ? 1 : 0;
     st->producer_busy_s = s->busy_s.load();
     st->elapsed_s = s->t_start > 0.0 ? now_s() - s->t_start : 0.0;
@@ -365,7 +370,8 @@ int32_t pdmp_sampler_destroy(pdmp_sampler *s) {
     if (!s) return PDMP_OK;
     s->stop.store(true, std::memory_order_release);
     if (s->th.joinable()) s->th.join();
-    const int32_t st = s->status.load();
+    const int32_t st = s->status.load(std::memory_order_acquire);
+    if (st != PDMP_OK) set_error("%s", s->err);
     delete s;
     return st;
 }

@@ -81,3 +81,29 @@ def test_rrt_on_the_sampler_matches_the_oracle_replay():
     assert np.array_equal(nodes, res["nodes"]) and np.array_equal(parents, res["parent"])
     assert res["from_bucket"] > 0
     assert s.close() == 0
+
+
+def test_producer_failure_reaches_the_consumer():
+    """A producer whose device allocation fails (a batch far beyond device memory:
+    hipMalloc returns an error, nothing is launched) stops with PDMP_EDEVICE; the
+    consumer sees the status and the producer's message, and keeps drawing from
+    the prior without waiting."""
+    require_gpu()
+    cfg = K.C2
+    sc = ws_scene(cfg)
+    go = gpu_occ(sc["h"], sc["wb"], sc["ell"], grid=(cfg.grid, cfg.grid))
+    s = P.Sampler(go, 2, [cfg.lo] * 2, [cfg.hi] * 2, cfg.T, cfg.eta, 1 << 42, 1 << 10,
+                  seed=I.philox_seed(2), stream_id=100, prior_stream_id=7)
+    s.start()
+    t0 = time.time()
+    while s.stats()["running"]:
+        assert time.time() - t0 < 20.0
+        time.sleep(0.005)
+    st = s.stats()
+    assert st["status"] == 3 and st["produced"] == 0
+    assert st["error"].startswith("sampler producer: hipMalloc"), st["error"]
+    x, idx, fb = s.pop(5)
+    assert not fb.any() and list(idx) == [-1, -2, -3, -4, -5]
+    ref = O.uniform_samples(I.philox_seed(2), 7, [cfg.lo] * 2, [cfg.hi] * 2, 5)
+    assert np.array_equal(x, ref.T)
+    assert s.close() == 3
