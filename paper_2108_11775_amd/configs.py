@@ -113,7 +113,8 @@ class Amortised:
     train_pairs: int = 1 << 22
     batch: int = 65_536
     epochs: int = 50
-    lr: float = 1e-3
+    lr: float = 3e-3
+    schedule: str = "cosine"  # lr (1 + cos(pi t / steps)) / 2 over the 3,200 Adam steps
     beta1: float = 0.9
     beta2: float = 0.999
     eps: float = 1e-8

@@ -7,8 +7,9 @@
 // kept set is a property of the point alone.
 //
 // Layout: the hinges are sorted by cell once per call (counting sort; each cell's
-// hinges in increasing index order, so sums are deterministic), with cell_start[]
-// giving each cell's range.  The samples are sorted by their starting cell so that a
+// hinges in increasing index order, so sums are deterministic) and prescaled by
+// kappa = sqrt(log2(e) / (2 l^2)), so that phi = exp2(-|kappa x - kappa h|^2) needs
+// no multiply before v_exp_f32; cell_start[] gives each cell's range.  The samples are sorted by their starting cell so that a
 // wave's points are close; at every step a wave takes the rectangle of cells covering
 // its points' neighbourhoods, walks it cell by cell (wave-uniform bounds, hinge reads
 // through the scalar unit), and each lane accumulates only the cells within one of
@@ -120,6 +121,12 @@ k_cull_sort_cells(const int *__restrict__ start, int m, uint32_t *order) {
     }
 }
 
+// p[i] *= a for i < n.
+__global__ void k_scale_f32(float *p, int64_t n, float a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = a * p[i];
+}
+
 // dst[k][pos] = src[k][order[pos]] for the rows k < rows of an SoA array [rows][n].
 __global__ void __launch_bounds__(kCullBlock)
 k_cull_gather(const float *__restrict__ src, int rows, int64_t n, const uint32_t *__restrict__ order,
@@ -133,7 +140,7 @@ k_cull_gather(const float *__restrict__ src, int rows, int64_t n, const uint32_t
 template <int DIM>
 __global__ void __launch_bounds__(kCullBlock)
 k_cull_morph(CullGridDev g, const float *__restrict__ hs, const float *__restrict__ ws, int M,
-             const float *__restrict__ bias, const int *__restrict__ cell_start, float kexp, float il2,
+             const float *__restrict__ bias, const int *__restrict__ cell_start, float kappa, float gscale,
              const float *__restrict__ xs, const uint32_t *__restrict__ order, int64_t n, int T,
              float eta, float *x_out) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -145,8 +152,10 @@ k_cull_morph(CullGridDev g, const float *__restrict__ hs, const float *__restric
     for (int k = 0; k < DIM; ++k) x[k] = xs[(size_t)k * n + pc];
     for (int st = 0; st < T; ++st) {
         int my[DIM], lo[DIM], hi[DIM];
+        float xk[DIM];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
+            xk[k] = kappa * x[k];
             my[k] = cull_cell(x[k], g.lo[k], g.inv_cell, g.nc[k]);
             int mn = my[k], mx = my[k];
 #pragma unroll
@@ -186,10 +195,10 @@ k_cull_morph(CullGridDev g, const float *__restrict__ hs, const float *__restric
                             float d[DIM], r2 = 0.0f;
 #pragma unroll
                             for (int k = 0; k < DIM; ++k) {
-                                d[k] = x[k] - hv[k][u];
+                                d[k] = xk[k] - hv[k][u];
                                 r2 = fmaf(d[k], d[k], r2);
                             }
-                            const float wp = wv[u] * exp2_fast(-r2 * kexp);
+                            const float wp = wv[u] * exp2_fast(-r2);
                             s += wp;
 #pragma unroll
                             for (int k = 0; k < DIM; ++k) gx[k] = fmaf(wp, d[k], gx[k]);
@@ -199,10 +208,10 @@ k_cull_morph(CullGridDev g, const float *__restrict__ hs, const float *__restric
                         float d[DIM], r2 = 0.0f;
 #pragma unroll
                         for (int k = 0; k < DIM; ++k) {
-                            d[k] = x[k] - hs[(size_t)k * M + j];
+                            d[k] = xk[k] - hs[(size_t)k * M + j];
                             r2 = fmaf(d[k], d[k], r2);
                         }
-                        const float wp = ws[j] * exp2_fast(-r2 * kexp);
+                        const float wp = ws[j] * exp2_fast(-r2);
                         s += wp;
 #pragma unroll
                         for (int k = 0; k < DIM; ++k) gx[k] = fmaf(wp, d[k], gx[k]);
@@ -210,7 +219,7 @@ k_cull_morph(CullGridDev g, const float *__restrict__ hs, const float *__restric
                 }
         float c, sp;
         sigmoid_and_slope(s + beta, c, sp);
-        const float step = eta * sp * il2;  // grad s = -il2 sum w phi (x - h)
+        const float step = eta * sp * gscale;  // grad s = -gscale * sum w phi (kappa x - kappa h)
 #pragma unroll
         for (int k = 0; k < DIM; ++k) x[k] = fmaf(step, gx[k], x[k]);
     }
@@ -302,15 +311,17 @@ int32_t launch_morph_culled(const pdmp_occupancy &occ, const pdmp_cull_grid &cg,
     }
 #undef PDMP_CULL_D
     if (int32_t r = check_launch("cull setup")) return r;
-    const float il2 = 1.0f / (occ.lengthscale * occ.lengthscale);
-    const float kexp = 0.5f * il2 * kLog2e;  // exp(-r^2 / (2 l^2)) = exp2(-r^2 kexp)
+    float kappa, gscale;
+    derive_scales(occ.lengthscale, kappa, gscale);
+    hipLaunchKernelGGL(k_scale_f32, dim3((unsigned)((dim * M + kCullBlock - 1) / kCullBlock)), blk, 0,
+                       st, hsw, (int64_t)dim * M, kappa);
     const float *bias = occ.weights + M;
     if (dim == 2)
         hipLaunchKernelGGL((k_cull_morph<2>), bs, blk, 0, st, g, hsw, hsw + (size_t)2 * M, M, bias,
-                           hstart, kexp, il2, xs, sorder, n, T, eta, out);
+                           hstart, kappa, gscale, xs, sorder, n, T, eta, out);
     else
         hipLaunchKernelGGL((k_cull_morph<3>), bs, blk, 0, st, g, hsw, hsw + (size_t)3 * M, M, bias,
-                           hstart, kexp, il2, xs, sorder, n, T, eta, out);
+                           hstart, kappa, gscale, xs, sorder, n, T, eta, out);
     return check_launch("k_cull_morph");
 }
 
