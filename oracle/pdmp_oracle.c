@@ -186,6 +186,13 @@ static void rbf_point(int dim, int M, const double *h, const double *w, double b
 
 static double sigmoid(double s) { return 1.0 / (1.0 + exp(-s)); }
 
+/* sigma'(s) = sigma(s)(1 - sigma(s)), written as e/(1 + e)^2 with e = exp(-|s|) so
+ * that it keeps its relative accuracy where sigma(s) rounds to 0 or 1. */
+static double sigmoid_slope(double s) {
+    double e = exp(-fabs(s));
+    return e / ((1.0 + e) * (1.0 + e));
+}
+
 /* c, grad c, Hessian of c and the gradient error scale G_abs from the logit. */
 typedef struct {
     double c, dc;                       /* sigma(s), sigma'(s) */
@@ -199,7 +206,7 @@ static void occ_point(int dim, int M, const double *h, const double *w, double b
     rbf_val v;
     rbf_point(dim, M, h, w, beta, ell, x, want_hess, &v);
     double c = sigmoid(v.s);
-    double d1 = c * (1.0 - c);
+    double d1 = sigmoid_slope(v.s);
     double d2 = d1 * (1.0 - 2.0 * c);
     o->c = c;
     o->dc = d1;
@@ -983,13 +990,6 @@ void orc_amortised_morph(int L, const int *widths, const double *P, int ndof, in
 /*   e_l = d_l * (W_l^T e_{l+1})  (l = L-1..1),  grad_x s = W_0^T e_1.         */
 /* ------------------------------------------------------------------------- */
 
-/* sigma'(s) = sigma(s)(1 - sigma(s)), written as e/(1 + e)^2 with e = exp(-|s|) so
- * that it keeps its relative accuracy where sigma(s) rounds to 0 or 1. */
-static double sigmoid_slope(double s) {
-    double e = exp(-fabs(s));
-    return e / ((1.0 + e) * (1.0 + e));
-}
-
 #define ORC_TANH_MAXH 256
 #define ORC_TANH_MAXL 6
 
@@ -1347,7 +1347,7 @@ static double step_logdet(int dim, int M, const double *h, const double *w, doub
             }
             habs += fabs(w[j]) * exp(-0.5 * r2 * il2) * il2 * (r2 * il2 + 1.0);
         }
-        double c = o.c, d1 = o.dc, d2 = d1 * (1.0 - 2.0 * c), d3 = d1 * (1.0 - 6.0 * c * (1.0 - c));
+        double c = o.c, d1 = o.dc, d2 = d1 * (1.0 - 2.0 * c), d3 = d1 * (1.0 - 6.0 * d1);
         double gn = 0.0;
         for (int k = 0; k < dim; ++k) gn += v.gs[k] * v.gs[k];
         double Habs = d1 * habs + fabs(d2) * (v.sabs * hsmax + 2.0 * sqrt(gn) * v.graw + gn) +
@@ -1479,7 +1479,7 @@ static void cull_point(int dim, int M, const double *h, const double *w, double 
         s += wp;
         for (int k = 0; k < dim; ++k) gs[k] += -il2 * wp * d[k];
     }
-    double c = sigmoid(s), sp = c * (1.0 - c);
+    double sp = sigmoid_slope(s);
     if (s_out) *s_out = s;
     if (gc)
         for (int k = 0; k < dim; ++k) gc[k] = sp * gs[k];

@@ -38,6 +38,22 @@ def test_single_hinge_closed_forms():
         np.testing.assert_allclose(gc[:, 0], sp * (1 - sp) * gs_ref, rtol=1e-13, atol=1e-15)
 
 
+@pytest.mark.parametrize("beta", [36.0, -36.0, 45.0, -80.0])
+def test_gradient_keeps_relative_accuracy_at_large_logits(beta):
+    """Where sigma(s) rounds to within a few ulp of 1, sigma'(s) must still be
+    e^{-|s|} / (1 + e^{-|s|})^2 to FP64 relative accuracy (c (1 - c) would be off by
+    up to 50 % at s = 36): the closed form for one hinge."""
+    ell, w = 0.5, 1.1
+    occ = O.Occupancy(np.zeros((2, 1)), np.array([w]), beta, ell)
+    x = np.array([[0.3], [-0.2]])
+    phi = math.exp(-0.13 / (2 * ell ** 2))
+    e = math.exp(-abs(w * phi + beta))
+    sp = e / (1 + e) ** 2
+    _, gc, gs, _ = O.occ_grad(occ, x)
+    np.testing.assert_allclose(gs[:, 0], -w * phi * x[:, 0] / ell ** 2, rtol=1e-13)
+    np.testing.assert_allclose(gc[:, 0], sp * gs[:, 0], rtol=1e-13)
+
+
 def test_single_hinge_gradient_peaks_at_lengthscale():
     ell = 0.4
     occ = O.Occupancy(np.zeros((2, 1)), np.array([2.0]), 0.0, ell)
