@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks (256 CUs, 2.4 GHz).
 PEAK_FP32_VALU = 157.3e12          # FLOP/s, dense FP32 vector (packed issue)
 PEAK_FP32_MFMA = 157.3e12          # FLOP/s, dense FP32 matrix
+PEAK_BF16_MFMA = 2.5e15            # FLOP/s, dense BF16 matrix
 # v_exp_f32 runs at half rate (8 cycles per wave64 on a 16-lane SIMD), i.e. 4 SIMDs x
 # 16 lanes x 1/2 per clock per CU; measured on the part it overlaps with
 # independent VALU work, so a pair costs max(flop time, exp time).
@@ -39,11 +40,11 @@ FLOPS_PER_PAIR = {2: 12, 3: 17}    # 5*dim + 2 algorithmic FP32 flops per sample
 
 
 # HBM traffic per launch of the headline kernel from the two rocprofv3 --pmc runs in
-# profiles/k_grid2d_morph_ws2d_1M.md (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the
+# profiles/k_grid2d_x6_morph_ws2d_1M.md (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the
 # factors a plain 256 MiB device copy reads under the same counters).  Valid only
 # while grid2d.hip is the source the counters were taken on.
-GRID2D_TRAFFIC = {"bytes": (4222.5 * 2.0 + 8192.0) * 1024,
-                  "sha256": "84d22bf2a579b7c21fecd0f876bb4ea0d6e397064491b38005c0b35972e0da02"}
+GRID2D_TRAFFIC = {"bytes": (4257.0 * 2.0 + 8192.0) * 1024,
+                  "sha256": "cc1600218edb0f2108efe3ec562a3b9b02e6d69409a182b7fd22a99a432bf92a"}
 
 
 def grid2d_traffic():
@@ -185,15 +186,20 @@ def headline(args, P, I, K, torch, dev):
                seed=seed, x0=x0)
     G0 = G1 = cfg.grid
     if occ.grid:
-        # own algorithmic work of the factorised evaluation, per sample and step:
-        # two G1 x G0 matrix-vector products (4 G0 G1 flops, on MFMA)
-        flops = N * cfg.T * 4.0 * G0 * G1
-        achieved = flops / (morph_ms * 1e-3) / 1e12
-        res["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA / 1e12,
-                           "unit": "TFLOP/s", "frac": achieved * 1e12 / PEAK_FP32_MFMA,
-                           "traffic": grid2d_traffic(), "kernel": "k_grid2d<2,kMorph>",
+        # own algorithmic work of the factorised evaluation, per sample and step: two
+        # G1 x G0 matrix-vector products (4 G0 G1 FP32 flops), each FP32 multiply-add
+        # carried out as six BF16 products of three-way splits (24 G0 G1 BF16 flops)
+        fp32_tf = N * cfg.T * 4.0 * G0 * G1 / (morph_ms * 1e-3) / 1e12
+        achieved = 6.0 * fp32_tf
+        res["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_MFMA / 1e12,
+                           "unit": "TFLOP/s", "frac": achieved * 1e12 / PEAK_BF16_MFMA,
+                           "traffic": grid2d_traffic(), "kernel": "k_grid2d_x6<2,4,kMorph>",
                            "kernel_ms": morph_ms,
-                           "work": "4*G0*G1 FP32 MFMA flops per sample-step (64x64 grid)",
+                           "work": "24*G0*G1 BF16 MFMA flops per sample-step (64x64 grid): the "
+                                   "two FP32 contractions (4*G0*G1 flops) as the six leading "
+                                   "BF16 products of three-way splits",
+                           "fp32_equivalent_tflops": fp32_tf,
+                           "fp32_equivalent_frac_of_fp32_mfma_peak": fp32_tf * 1e12 / PEAK_FP32_MFMA,
                            "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE + "
                                            "WRITE_SIZE, copy-calibrated); algorithmic "
                                            f"{N * 2 * 4 * 2} bytes"}
@@ -662,7 +668,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32+bf16x6",
         "data": "synthetic (seeded disc world, Philox prior samples, occupancy fitted on the GPU)",
         "config": {"workload": "plain morph 2-D large: 1,048,576 samples, 64x64 hinges, "
                                "l=0.4, T=50, eta=0.02, 100 discs",

@@ -1,5 +1,5 @@
 // grid2d.hip -- the occupancy and the fused T-step morph for hinges on a regular 2-D
-// grid, as a dense FP32 MFMA contraction.
+// grid, as a dense contraction on the matrix cores.
 //
 // With hinges h_{a + G0 b} = (gx_a, gy_b) the RBF feature factorises,
 //   phi_ab(x) = ex_a(x) ey_b(y),  ex_a = exp(-(x - gx_a)^2 / (2 l^2)),
@@ -9,11 +9,10 @@
 //   ds/dy  = -(1/l^2) sum_b ey_b (y - gy_b) U_b
 // which is the same s and grad s as the pairwise sum (rounding aside).  Per sample
 // and step that is G0 + G1 exponentials and two G1 x G0 matrix-vector products,
-// instead of G0 G1 exponentials.  The products for 32 samples at a time are
-// v_mfma_f32_32x32x2_f32: A = W (rows b, k = a), B = [ex | ex * dx] (k = a, column =
-// sample).  Lane l computes the exponentials of its own B entries (a = 2kk + l/32,
-// sample l%32), so no exponential is evaluated twice; W is staged once per block in
-// LDS in MFMA fragment order (one conflict-free ds_read per fragment).  The y
+// instead of G0 G1 exponentials.  The products for 32 samples at a time run on the
+// matrix cores with A = W (rows b, k = a) and B = [ex | ex * dx] (k = a, column =
+// sample); each lane computes the exponentials of its own B entries, so none is
+// evaluated twice, and W is staged once per block in LDS in fragment order.  The y
 // contraction runs on the accumulator layout: lane l owns rows b = 8(v/4) + 4(l/32)
 // + v%4 of sample l%32, evaluates ey_b for them and the two lanes of a sample are
 // summed by one xor-32 exchange (bit-identical in both lanes).  The T-step loop
@@ -25,27 +24,102 @@ namespace pdmp {
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
 
 constexpr int kG2Block = 256;   // 4 waves, 32 samples each
-constexpr int kG2MaxKS = 32;    // G0 <= 64
-constexpr int kG2MaxTB = 2;     // G1 <= 64
 
-template <int TB, int MODE>
-__global__ void __launch_bounds__(kG2Block) __attribute__((amdgpu_waves_per_eu(3)))
-k_grid2d(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
-         float kappa, float gscale, const float *x_in, int64_t n, int T, float eta, float *c_out,
-         float *s_out, float *g_out, float *x_out) {
-    // fragments: frag[kk][t][lane] = W[b = 32t + lane%32][a = 2kk + lane/32] (0 outside)
-    // one k-step of padding so that the next step's operands can always be read ahead
-    __shared__ float frag[(kG2MaxKS + 1) * TB * 64];
-    __shared__ float gxs[2 * (kG2MaxKS + 1)];
+// The contractions run on BF16 MFMA at FP32 accuracy.
+//
+// Each FP32 operand v is split, rounding to nearest even, into three bf16 parts
+// v = v1 + v2 + v3 + r with |v2| <= 2^-8 |v|, |v3| <= 2^-16 |v| and |r| <= 2^-24 |v|
+// (bf16 carries 8 significant bits; every difference is exact in FP32).  Of the nine
+// products of the parts of W and of [ex | ex * dx], the six with v_i w_j, i + j <= 4,
+// are kept: the three dropped ones are below 2^-24 of the product.  Products of bf16
+// parts are exact and v_mfma_f32_32x32x16_bf16 accumulates them in FP32, so U and V
+// carry FP32-class error (a few units of 2^-24 of sum |W ex|) at 6 x 16 = 96 bf16
+// flops per FP32 multiply-add; the dense BF16 MFMA rate is 16 times the FP32 one, so
+// the contraction takes 6/16 of the matrix-core time of v_mfma_f32_32x32x2_f32, and
+// the splitting adds about 5.5 VALU per B operand.
+// Layout: lane l holds A[i = l%32][k = 8(l/32) + j] and B[k = 8(l/32) + j][n = l%32],
+// j < 8, per 16-wide k-step; the accumulator (D) layout is lane l, register v ->
+// row 8(v/4) + 4(l/32) + v%4, column l%32.
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// v = p1 + p2 + p3 + r, each part rounded to nearest even in bf16.
+__device__ __forceinline__ void split3(const float (&v)[8], bf16x8_t &p1, bf16x8_t &p2,
+                                       bf16x8_t &p3) {
+#pragma unroll
+    for (int j = 0; j < 8; j += 2) {
+        const f32x2_t a = {v[j], v[j + 1]};
+        const bf16x2_t h = __builtin_convertvector(a, bf16x2_t);
+        const f32x2_t r = a - __builtin_convertvector(h, f32x2_t);
+        const bf16x2_t m = __builtin_convertvector(r, bf16x2_t);
+        const f32x2_t r2 = r - __builtin_convertvector(m, f32x2_t);
+        const bf16x2_t l = __builtin_convertvector(r2, bf16x2_t);
+        p1[j] = h[0];
+        p1[j + 1] = h[1];
+        p2[j] = m[0];
+        p2[j + 1] = m[1];
+        p3[j] = l[0];
+        p3[j + 1] = l[1];
+    }
+}
+
+// acc += (a1 + a2 + a3)(b1 + b2 + b3) to FP32 accuracy: the six leading products,
+// smallest first.
+__device__ __forceinline__ f32x16_t mfma_x6(const bf16x8_t &a1, const bf16x8_t &a2,
+                                            const bf16x8_t &a3, const bf16x8_t &b1,
+                                            const bf16x8_t &b2, const bf16x8_t &b3,
+                                            f32x16_t acc) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3, b1, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b2, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b3, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b1, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b2, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc, 0, 0, 0);
+}
+
+// The x-side operands of k-step ks for this lane: ex and ex * dx at a = 16ks + 8half + j.
+__device__ __forceinline__ void x6_operands(const float *gxs, float xs, int ks, int half,
+                                            bf16x8_t (&e)[3], bf16x8_t (&de)[3]) {
+    float ev[8], dv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float d = xs - gxs[16 * ks + 8 * half + j];
+        ev[j] = exp2_fast(-d * d);
+        dv[j] = ev[j] * d;
+    }
+    split3(ev, e[0], e[1], e[2]);
+    split3(dv, de[0], de[1], de[2]);
+}
+
+template <int TB, int KS, int MODE>
+__global__ void __launch_bounds__(kG2Block) __attribute__((amdgpu_waves_per_eu(2)))
+k_grid2d_x6(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
+            float kappa, float gscale, const float *x_in, int64_t n, int T, float eta,
+            float *c_out, float *s_out, float *g_out, float *x_out) {
+    // fragments: frag[(p * KS + ks) * TB + t][lane] = part p of
+    //   W[b = 32t + lane%32][a = 16ks + 8(lane/32) + j], j < 8 (0 outside the grid)
+    __shared__ bf16x8_t frag[3 * KS * TB * 64];
+    __shared__ float gxs[16 * KS];
     __shared__ float gys[32 * TB];
     const int M = g0 * g1;
-    const int ks = (g0 + 1) / 2;
-    for (int idx = threadIdx.x; idx < (ks + 1) * TB * 64; idx += kG2Block) {
-        const int ln = idx & 63, t = (idx >> 6) % TB, kk = idx / (64 * TB);
-        const int b = 32 * t + (ln & 31), a = 2 * kk + (ln >> 5);
-        frag[idx] = (a < g0 && b < g1) ? weights[a + (int64_t)g0 * b] : 0.0f;
+    for (int idx = threadIdx.x; idx < KS * TB * 64; idx += kG2Block) {
+        const int ln = idx & 63, t = (idx >> 6) % TB, ks = idx / (64 * TB);
+        const int b = 32 * t + (ln & 31);
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int a = 16 * ks + 8 * (ln >> 5) + j;
+            v[j] = (a < g0 && b < g1) ? weights[a + (int64_t)g0 * b] : 0.0f;
+        }
+        bf16x8_t p1, p2, p3;
+        split3(v, p1, p2, p3);
+        frag[(0 * KS + ks) * TB * 64 + t * 64 + ln] = p1;
+        frag[(1 * KS + ks) * TB * 64 + t * 64 + ln] = p2;
+        frag[(2 * KS + ks) * TB * 64 + t * 64 + ln] = p3;
     }
-    for (int a = threadIdx.x; a < 2 * (ks + 1); a += kG2Block)
+    for (int a = threadIdx.x; a < 16 * KS; a += kG2Block)
         gxs[a] = a < g0 ? kappa * hinges[a] : 0.0f;
     for (int b = threadIdx.x; b < 32 * TB; b += kG2Block)
         gys[b] = b < g1 ? kappa * hinges[(size_t)M + (size_t)g0 * b] : 0.0f;
@@ -63,42 +137,26 @@ k_grid2d(const float *__restrict__ hinges, const float *__restrict__ weights, in
     for (int st = 0; st < steps; ++st) {
         const float xs = kappa * x, ys = kappa * y;
         f32x16_t U[TB], V[TB];
-        // k-step 0 starts the accumulators from the zero constant (no register clears);
-        // the LDS operands of step kk + 1 are read while step kk's products run
-        float gx_n = gxs[half], w_n[TB];
+        // an opaque copy of the lane index keeps the fragment reads inside the step
+        // loop (hoisted, the loop-invariant W parts would take 96 registers)
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        // the operands of k-step ks + 1 are formed while k-step ks's products run;
+        // k-step 0 starts the accumulators from the zero constant
+        bf16x8_t e[3], de[3];
+        x6_operands(gxs, xs, 0, half, e, de);
 #pragma unroll
-        for (int t = 0; t < TB; ++t) w_n[t] = frag[t * 64 + lane];
-        {
-            const float d = xs - gx_n;
-            const float e = exp2_fast(-d * d);
-            const float de = e * d;
-            float w_c[TB];
-#pragma unroll
-            for (int t = 0; t < TB; ++t) w_c[t] = w_n[t];
-            gx_n = gxs[2 + half];
-#pragma unroll
-            for (int t = 0; t < TB; ++t) w_n[t] = frag[(TB + t) * 64 + lane];
-            const f32x16_t zero = {};
+        for (int ks = 0; ks < KS; ++ks) {
+            bf16x8_t ec[3] = {e[0], e[1], e[2]}, dc[3] = {de[0], de[1], de[2]};
+            if (ks + 1 < KS) x6_operands(gxs, xs, ks + 1, half, e, de);
 #pragma unroll
             for (int t = 0; t < TB; ++t) {
-                U[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], e, zero, 0, 0, 0);
-                V[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], de, zero, 0, 0, 0);
-            }
-        }
-        for (int kk = 1; kk < ks; ++kk) {
-            const float d = xs - gx_n;
-            float w_c[TB];
-#pragma unroll
-            for (int t = 0; t < TB; ++t) w_c[t] = w_n[t];
-            gx_n = gxs[2 * (kk + 1) + half];
-#pragma unroll
-            for (int t = 0; t < TB; ++t) w_n[t] = frag[((kk + 1) * TB + t) * 64 + lane];
-            const float e = exp2_fast(-d * d);
-            const float de = e * d;
-#pragma unroll
-            for (int t = 0; t < TB; ++t) {
-                U[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], e, U[t], 0, 0, 0);
-                V[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], de, V[t], 0, 0, 0);
+                const bf16x8_t a1 = frag[(0 * KS + ks) * TB * 64 + t * 64 + ln];
+                const bf16x8_t a2 = frag[(1 * KS + ks) * TB * 64 + t * 64 + ln];
+                const bf16x8_t a3 = frag[(2 * KS + ks) * TB * 64 + t * 64 + ln];
+                const f32x16_t zero = {};
+                U[t] = mfma_x6(a1, a2, a3, ec[0], ec[1], ec[2], ks == 0 ? zero : U[t]);
+                V[t] = mfma_x6(a1, a2, a3, dc[0], dc[1], dc[2], ks == 0 ? zero : V[t]);
             }
         }
         s = 0.0f;
@@ -121,7 +179,7 @@ k_grid2d(const float *__restrict__ hinges, const float *__restrict__ weights, in
         if (MODE == kMorph) {
             float c, sp;
             sigmoid_and_slope(s + beta, c, sp);
-            const float step = eta * sp * gscale;  // x - eta sigma' grad s, grad s = -gscale (sx, sy)
+            const float step = eta * sp * gscale;
             x = fmaf(step, sx, x);
             y = fmaf(step, sy, y);
         }
@@ -146,24 +204,32 @@ k_grid2d(const float *__restrict__ hinges, const float *__restrict__ weights, in
 
 // Returns PDMP_EUNSUPPORTED (without launching) when the grid does not fit.
 int32_t launch_grid2d(int mode, const RbfArgs &a, int g0, int g1, hipStream_t st) {
-    if (g0 < 1 || g1 < 1 || g0 > 2 * kG2MaxKS || g1 > 32 * kG2MaxTB || (int64_t)g0 * g1 != a.M)
+    if (g0 < 1 || g1 < 1 || g0 > 64 || g1 > 64 || (int64_t)g0 * g1 != a.M)
         return PDMP_EUNSUPPORTED;
     if (mode != kEval && mode != kGrad && mode != kMorph) return PDMP_EUNSUPPORTED;
     const int64_t blocks = (a.n + 127) / 128;
     const dim3 grid((unsigned)blocks), blk(kG2Block);
-#define PDMP_G2(TB, MODE)                                                                      \
-    hipLaunchKernelGGL((k_grid2d<TB, MODE>), grid, blk, 0, st, a.hinges, a.weights, g0, g1, \
-                       a.kappa, a.gscale, a.x_in, a.n, a.T, a.eta, a.c_out, a.s_out, a.g_out,  \
-                       a.x_out)
-    if (g1 <= 32) {
-        if (mode == kEval) PDMP_G2(1, kEval);
-        else if (mode == kGrad) PDMP_G2(1, kGrad);
-        else PDMP_G2(1, kMorph);
-    } else {
-        if (mode == kEval) PDMP_G2(2, kEval);
-        else if (mode == kGrad) PDMP_G2(2, kGrad);
-        else PDMP_G2(2, kMorph);
+#define PDMP_G2(TB, KS, MODE)                                                                \
+    hipLaunchKernelGGL((k_grid2d_x6<TB, KS, MODE>), grid, blk, 0, st, a.hinges, a.weights, g0, \
+                       g1, a.kappa, a.gscale, a.x_in, a.n, a.T, a.eta, a.c_out, a.s_out,        \
+                       a.g_out, a.x_out)
+#define PDMP_G2_KS(TB, MODE)                      \
+    switch ((g0 + 15) / 16) {                     \
+        case 1: PDMP_G2(TB, 1, MODE); break;      \
+        case 2: PDMP_G2(TB, 2, MODE); break;      \
+        case 3: PDMP_G2(TB, 3, MODE); break;      \
+        default: PDMP_G2(TB, 4, MODE); break;     \
     }
+    if (g1 <= 32) {
+        if (mode == kEval) PDMP_G2_KS(1, kEval)
+        else if (mode == kGrad) PDMP_G2_KS(1, kGrad)
+        else PDMP_G2_KS(1, kMorph)
+    } else {
+        if (mode == kEval) PDMP_G2_KS(2, kEval)
+        else if (mode == kGrad) PDMP_G2_KS(2, kGrad)
+        else PDMP_G2_KS(2, kMorph)
+    }
+#undef PDMP_G2_KS
 #undef PDMP_G2
     return check_launch("k_grid2d");
 }

@@ -86,3 +86,31 @@ def test_grid_morph_config1_full_and_deterministic():
                                 diag=True)
     err = np.abs(a - ref).max(axis=0)
     assert np.all(err <= TOL * np.maximum(1, amp) * np.maximum(1, np.abs(ref).max(axis=0)))
+
+
+def test_grid_split_precision_wide_range():
+    """The contractions run on three-way bf16 splits: weights over six decades with
+    random signs and samples up to 8 lengthscales outside the grid (every feature
+    tiny but normal in FP32) still meet the FP32 tolerance of the absolute sums.
+    Weights stay below 10 so that sigma' stays a normal FP32 number."""
+    require_gpu()
+    rng = np.random.default_rng(2108)
+    g0, g1, ell = 64, 48, 0.3
+    ax = np.linspace(-3, 3, g0).astype(np.float32)
+    ay = np.linspace(-2, 2, g1).astype(np.float32)
+    j = np.arange(g0 * g1)
+    h = np.stack([ax[j % g0], ay[j // g0]]).astype(np.float32)
+    mag = 10.0 ** rng.uniform(-5, 1, g0 * g1 + 1)
+    wb = (mag * rng.choice([-1.0, 1.0], g0 * g1 + 1)).astype(np.float32)
+    wb[-1] = 0.0  # no bias: the tolerance of far samples is then set by their tiny sums
+    far = np.stack([rng.uniform(-3 - 8 * ell, 3 + 8 * ell, 500),
+                    rng.uniform(-2 - 8 * ell, 2 + 8 * ell, 500)])
+    x = np.concatenate([rng.uniform(-3.2, 3.2, (2, 500)), far], axis=1).astype(np.float32)
+    go = _grid_occ(h, wb, ell, g0, g1)
+    _, s = P.occupancy_eval(go, dev(x))
+    _, g = P.occupancy_grad(go, dev(x))
+    oo = oracle_occ(h, wb, ell)
+    s_r, _, sabs = O.occ_eval(oo, x)
+    _, g_r, _, gabs = O.occ_grad(oo, x)
+    assert np.all(np.abs(host(s) - s_r) <= TOL * sabs)
+    assert np.all(np.abs(host(g) - g_r).max(axis=0) <= TOL * gabs)
