@@ -297,18 +297,22 @@ def arm_morph(P, I, K, torch, world):
     _, h0 = P.label_configs(arm, *world["boxes"], q0, count=True)
     _, h1 = P.label_configs(arm, *world["boxes"], q1, count=True)
     # own work of the factorised evaluation per body point and step: two (16*16) x 16
-    # matrix-vector products on MFMA = 4 * 4096 flops
-    flops = c3.n_samples * c3.T * c3.n_body * 4.0 * c3.n_hinges
-    ach = flops / (ms * 1e-3) / 1e12
+    # matrix-vector products = 4 * 4096 FP32 flops, each multiply-add as six BF16
+    # products of three-way splits = 24 * 4096 BF16 MFMA flops
+    fp32_tf = c3.n_samples * c3.T * c3.n_body * 4.0 * c3.n_hinges / (ms * 1e-3) / 1e12
+    ach = 6.0 * fp32_tf
     res = {"workload": "plain morph 7-DOF arm: 65,536 configurations, 56 body points, 16^3 "
                        "hinges, l=0.15, T=30, eta=0.01, 40 boxes",
            "morph_ms": ms, "samples_per_s": c3.n_samples / (ms * 1e-3),
            "collision_free_before": 1 - h0.item() / c3.n_samples,
            "collision_free_after": 1 - h1.item() / c3.n_samples,
-           "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA / 1e12,
-                        "unit": "TFLOP/s", "frac": ach * 1e12 / PEAK_FP32_MFMA,
+           "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_MFMA / 1e12,
+                        "unit": "TFLOP/s", "frac": ach * 1e12 / PEAK_BF16_MFMA,
                         "kernel": "k_arm_grid3d<7,16,16,true>",
-                        "work": "4*M FP32 MFMA flops per body point and step"}}
+                        "work": "24*M BF16 MFMA flops per body point and step (the two FP32 "
+                                "contractions, 4*M flops, as six BF16 products of three-way "
+                                "splits)",
+                        "fp32_equivalent_tflops": fp32_tf}}
     dense = P.Occupancy(occ.hinges, occ.weights, occ.lengthscale)
     P.morph_samples(dense, q0, c3.T, c3.eta, arm=arm, out=q1)
     t = Timer(torch)
@@ -414,16 +418,21 @@ def density_workload(P, I, K, torch, hl):
             "logdet_mean": ld.mean().item(),
             "mixture_ms": mix_ms, "mixture_kept_fraction": keep.float().mean().item(),
             "mixture_collision_free": 1 - hm.item() / N,
-            "roofline_logdet": {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA / 1e12,
-                                "unit": "TFLOP/s", "frac": ach * 1e12 / PEAK_FP32_MFMA,
-                                "kernel": "k_grid2d_inv<2,kLogdet>",
-                                "work": "6*G0*G1 FP32 MFMA flops per sample-step"},
+            "roofline_logdet": {"bound": "mfma", "achieved": 6.0 * ach,
+                                "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
+                                "frac": 6.0 * ach * 1e12 / PEAK_BF16_MFMA,
+                                "kernel": "k_grid2d_inv<2,4,kLogdet>",
+                                "work": "36*G0*G1 BF16 MFMA flops per sample-step (the three "
+                                        "FP32 contractions, 6*G0*G1 flops, as six BF16 products "
+                                        "of three-way splits)",
+                                "fp32_equivalent_tflops": ach},
             "roofline_inverse": {"bound": "mfma",
-                                 "achieved": inv_flops / (inv_ms * 1e-3) / 1e12,
-                                 "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                                 "frac": inv_flops / (inv_ms * 1e-3) / PEAK_FP32_MFMA,
-                                 "kernel": "k_grid2d_inv<2,kInverse>",
-                                 "work": "(4*iters + 6)*G0*G1 FP32 MFMA flops per sample-step"}}
+                                 "achieved": 6.0 * inv_flops / (inv_ms * 1e-3) / 1e12,
+                                 "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
+                                 "frac": 6.0 * inv_flops / (inv_ms * 1e-3) / PEAK_BF16_MFMA,
+                                 "kernel": "k_grid2d_inv<2,4,kInverse>",
+                                 "work": "6*(4*iters + 6)*G0*G1 BF16 MFMA flops per sample-step",
+                                 "fp32_equivalent_tflops": inv_flops / (inv_ms * 1e-3) / 1e12}}
 
 
 def pipeline_workload(P, I, K, torch, dev, hl):

@@ -17,67 +17,15 @@
 // + v%4 of sample l%32, evaluates ey_b for them and the two lanes of a sample are
 // summed by one xor-32 exchange (bit-identical in both lanes).  The T-step loop
 // runs in registers.
+#include "mfma_split.h"
 #include "pdmp_common.h"
 
 namespace pdmp {
 
-typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
-
 constexpr int kG2Block = 256;   // 4 waves, 32 samples each
 
-// The contractions run on BF16 MFMA at FP32 accuracy.
-//
-// Each FP32 operand v is split, rounding to nearest even, into three bf16 parts
-// v = v1 + v2 + v3 + r with |v2| <= 2^-8 |v|, |v3| <= 2^-16 |v| and |r| <= 2^-24 |v|
-// (bf16 carries 8 significant bits; every difference is exact in FP32).  Of the nine
-// products of the parts of W and of [ex | ex * dx], the six with v_i w_j, i + j <= 4,
-// are kept: the three dropped ones are below 2^-24 of the product.  Products of bf16
-// parts are exact and v_mfma_f32_32x32x16_bf16 accumulates them in FP32, so U and V
-// carry FP32-class error (a few units of 2^-24 of sum |W ex|) at 6 x 16 = 96 bf16
-// flops per FP32 multiply-add; the dense BF16 MFMA rate is 16 times the FP32 one, so
-// the contraction takes 6/16 of the matrix-core time of v_mfma_f32_32x32x2_f32, and
-// the splitting adds about 5.5 VALU per B operand.
-// Layout: lane l holds A[i = l%32][k = 8(l/32) + j] and B[k = 8(l/32) + j][n = l%32],
-// j < 8, per 16-wide k-step; the accumulator (D) layout is lane l, register v ->
-// row 8(v/4) + 4(l/32) + v%4, column l%32.
-
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-typedef float f32x2_t __attribute__((ext_vector_type(2)));
-
-// v = p1 + p2 + p3 + r, each part rounded to nearest even in bf16.
-__device__ __forceinline__ void split3(const float (&v)[8], bf16x8_t &p1, bf16x8_t &p2,
-                                       bf16x8_t &p3) {
-#pragma unroll
-    for (int j = 0; j < 8; j += 2) {
-        const f32x2_t a = {v[j], v[j + 1]};
-        const bf16x2_t h = __builtin_convertvector(a, bf16x2_t);
-        const f32x2_t r = a - __builtin_convertvector(h, f32x2_t);
-        const bf16x2_t m = __builtin_convertvector(r, bf16x2_t);
-        const f32x2_t r2 = r - __builtin_convertvector(m, f32x2_t);
-        const bf16x2_t l = __builtin_convertvector(r2, bf16x2_t);
-        p1[j] = h[0];
-        p1[j + 1] = h[1];
-        p2[j] = m[0];
-        p2[j + 1] = m[1];
-        p3[j] = l[0];
-        p3[j + 1] = l[1];
-    }
-}
-
-// acc += (a1 + a2 + a3)(b1 + b2 + b3) to FP32 accuracy: the six leading products,
-// smallest first.
-__device__ __forceinline__ f32x16_t mfma_x6(const bf16x8_t &a1, const bf16x8_t &a2,
-                                            const bf16x8_t &a3, const bf16x8_t &b1,
-                                            const bf16x8_t &b2, const bf16x8_t &b3,
-                                            f32x16_t acc) {
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3, b1, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b2, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b3, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b1, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b2, acc, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc, 0, 0, 0);
-}
+// The contractions run on BF16 MFMA at FP32 accuracy (three-way bf16 splits, six
+// leading products; mfma_split.h).
 
 // The x-side operands of k-step ks for this lane: ex and ex * dx at a = 16ks + 8half + j.
 __device__ __forceinline__ void x6_operands(const float *gxs, float xs, int ks, int half,

@@ -1,5 +1,6 @@
 // grid3d.hip -- occupancy, joint-space morph and body-point check for hinges on a
-// regular 3-D grid with 16 points on the y axis, as dense FP32 MFMA contractions.
+// regular 3-D grid with 16 points on the y axis, as dense contractions on the matrix
+// cores (BF16 MFMA at FP32 accuracy, mfma_split.h).
 //
 // With hinges h_{a + G0 (b + 16 c)} = (X_a, Y_b, Z_c) the feature factorises,
 // phi = ex_a ey_b ez_c, so with rows r = b + 16 c of W[r][a] = w_{a + G0 r}
@@ -10,8 +11,9 @@
 //   ds/dz    = -(1/l^2) sum_c ez_c (z - Z_c) sum_b ey_b U_r
 // the same s and grad s as the pairwise sum (rounding aside) for G0 + 16 + G2
 // exponentials and two (16 G2) x G0 matrix-vector products per point.  32 points
-// per wave go through v_mfma_f32_32x32x2_f32 (A = W rows, B = [ex | ex dx] of the
-// lane's own point, k = a); each 32-row tile holds two z-planes (c = 2t, 2t+1), so
+// per wave go through v_mfma_f32_32x32x16_bf16 (A = W rows, B = [ex | ex dx] of the
+// lane's own point, k = a, G0 = 16 in one k-step; three-way bf16 splits of both, six
+// products per contraction); each 32-row tile holds two z-planes (c = 2t, 2t+1), so
 // in the accumulator layout lane l owns the fixed y indices b = (8(v/4) + 4(l/32)
 // + v%4) mod 16 and the y/z contractions need only per-lane tables of ey and ez.
 // The two lanes of a point are summed by one xor-32 exchange (bit-identical).
@@ -19,35 +21,40 @@
 // Arm mapping: a wave carries 4 configurations x 8 body points of one link at a
 // time (lane = 8*config + point, mirrored in the upper 32 lanes), walks the links
 // from the tip down, and keeps only the running suffix sums of the Eq. 3 pull-back.
+#include "mfma_split.h"
 #include "pdmp_common.h"
 
 namespace pdmp {
-
-typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_g3;
 
 constexpr int kG3Y = 16;  // points on the y axis (two z-planes per 32-row MFMA tile)
 
 template <int G0, int G2>
 struct G3 {
-    static_assert(G0 % 2 == 0 && G0 <= 32, "G0 even, <= 32");
+    static_assert(G0 == 16, "G0 = 16: one 16-wide k-step");
     static_assert(G2 % 2 == 0 && G2 <= 32, "G2 even, <= 32");
-    static constexpr int KS = G0 / 2;          // MFMA k-steps
     static constexpr int TB = kG3Y * G2 / 32;  // 32-row tiles
-    static constexpr int FRAG = TB * KS * 64;  // floats of W fragments
+    static constexpr int FRAG = 3 * TB * 64;   // bf16x8 fragments: 3 parts x TB tiles
 };
 
-// Stage W fragments (frag[(t*KS + kk)*64 + lane] = W[32t + lane%32][2kk + lane/32])
-// and the prescaled axes into LDS.
+// Stage W fragments (frag[(p*TB + t)*64 + lane] = part p of W[32t + lane%32][8(lane/32)
+// + j], j < 8) and the prescaled axes into LDS.
 template <int G0, int G2>
-__device__ __forceinline__ void g3_stage(float *frag, float *ax, float *ay, float *az,
+__device__ __forceinline__ void g3_stage(bf16x8_t *frag, float *ax, float *ay, float *az,
                                          const float *__restrict__ hinges,
                                          const float *__restrict__ weights, float kappa) {
     using C = G3<G0, G2>;
     constexpr int M = G0 * kG3Y * G2;
-    for (int idx = threadIdx.x; idx < C::FRAG; idx += blockDim.x) {
-        const int ln = idx & 63, q = idx >> 6, kk = q % C::KS, t = q / C::KS;
-        const int r = 32 * t + (ln & 31), a = 2 * kk + (ln >> 5);
-        frag[idx] = weights[a + G0 * r];
+    for (int idx = threadIdx.x; idx < C::TB * 64; idx += blockDim.x) {
+        const int ln = idx & 63, t = idx >> 6;
+        const int r = 32 * t + (ln & 31);
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = weights[8 * (ln >> 5) + j + G0 * r];
+        bf16x8_t p1, p2, p3;
+        split3(v, p1, p2, p3);
+        frag[(0 * C::TB + t) * 64 + ln] = p1;
+        frag[(1 * C::TB + t) * 64 + ln] = p2;
+        frag[(2 * C::TB + t) * 64 + ln] = p3;
     }
     for (int i = threadIdx.x; i < G0; i += blockDim.x) ax[i] = kappa * hinges[i];
     for (int i = threadIdx.x; i < kG3Y; i += blockDim.x) ay[i] = kappa * hinges[M + G0 * i];
@@ -57,7 +64,7 @@ __device__ __forceinline__ void g3_stage(float *frag, float *ax, float *ay, floa
 // s (without beta) and, with GRAD, the unscaled logit-gradient sums (sx, sy, sz) at the
 // prescaled point (xs, ys, zs) this lane shares with its xor-32 partner.
 template <int G0, int G2, bool GRAD>
-__device__ __forceinline__ void g3_point(const float *frag, const float *ax, const float *ay,
+__device__ __forceinline__ void g3_point(const bf16x8_t *frag, const float *ax, const float *ay,
                                          const float *az, float xs, float ys, float zs, float &s,
                                          float &sx, float &sy, float &sz) {
     using C = G3<G0, G2>;
@@ -67,12 +74,17 @@ __device__ __forceinline__ void g3_point(const float *frag, const float *ax, con
     // loops into registers.
     int lane = lane0;
     asm volatile("" : "+v"(lane));
-    float e[C::KS], de[C::KS];
+    bf16x8_t e1, e2, e3, d1, d2, d3;
+    {
+        float e[8], de[8];
 #pragma unroll
-    for (int kk = 0; kk < C::KS; ++kk) {
-        const float d = xs - ax[2 * kk + h];
-        e[kk] = exp2_fast(-d * d);
-        de[kk] = e[kk] * d;
+        for (int j = 0; j < 8; ++j) {
+            const float d = xs - ax[8 * h + j];
+            e[j] = exp2_fast(-d * d);
+            de[j] = e[j] * d;
+        }
+        split3(e, e1, e2, e3);
+        if (GRAD) split3(de, d1, d2, d3);
     }
     float ey[8], dey[8];  // the lane's 8 distinct y indices
 #pragma unroll
@@ -93,20 +105,14 @@ __device__ __forceinline__ void g3_point(const float *frag, const float *ax, con
             ez[cc] = exp2_fast(-d * d);
             dez[cc] = ez[cc] * d;
         }
-        // k-step 0 from the zero accumulator (no register clears per tile)
-        const f32x16_g3 zero = {};
-        f32x16_g3 U, V;
-        {
-            const float w = frag[(t * C::KS) * 64 + lane];
-            U = __builtin_amdgcn_mfma_f32_32x32x2f32(w, e[0], zero, 0, 0, 0);
-            if (GRAD) V = __builtin_amdgcn_mfma_f32_32x32x2f32(w, de[0], zero, 0, 0, 0);
-        }
-#pragma unroll
-        for (int kk = 1; kk < C::KS; ++kk) {
-            const float w = frag[(t * C::KS + kk) * 64 + lane];
-            U = __builtin_amdgcn_mfma_f32_32x32x2f32(w, e[kk], U, 0, 0, 0);
-            if (GRAD) V = __builtin_amdgcn_mfma_f32_32x32x2f32(w, de[kk], V, 0, 0, 0);
-        }
+        // one k-step (G0 = 16) from the zero accumulator
+        const f32x16_t zero = {};
+        const bf16x8_t a1 = frag[(0 * C::TB + t) * 64 + lane];
+        const bf16x8_t a2 = frag[(1 * C::TB + t) * 64 + lane];
+        const bf16x8_t a3 = frag[(2 * C::TB + t) * 64 + lane];
+        const f32x16_t U = mfma_x6(a1, a2, a3, e1, e2, e3, zero);
+        f32x16_t V;
+        if (GRAD) V = mfma_x6(a1, a2, a3, d1, d2, d3, zero);
         // row i = 8(v/4) + 4h + v%4 of tile t: b = i mod 16 (table slot v%8), c = 2t + v/8;
         // the y sums of each z-plane first, then one ez (dez) factor per plane
 #pragma unroll
@@ -144,7 +150,7 @@ k_grid3d_ws(const float *__restrict__ hinges, const float *__restrict__ weights,
             float gscale, const float *x_in, int64_t n, int T, float eta, float *c_out,
             float *s_out, float *g_out, float *x_out) {
     using C = G3<G0, G2>;
-    __shared__ float frag[C::FRAG];
+    __shared__ bf16x8_t frag[C::FRAG];
     __shared__ float ax[G0], ay[kG3Y], az[G2];
     g3_stage<G0, G2>(frag, ax, ay, az, hinges, weights, kappa);
     __syncthreads();
@@ -237,7 +243,7 @@ k_arm_grid3d(pdmp_arm arm, const float *__restrict__ hinges, const float *__rest
              uint8_t *flag_out) {
     using C = G3<G0, G2>;
     constexpr int KIN = 3 * (NDOF + 1) + 3 * NDOF + NDOF;  // o, z, grad_q per configuration
-    __shared__ float frag[C::FRAG];
+    __shared__ bf16x8_t frag[C::FRAG];
     __shared__ float ax[G0], ay[kG3Y], az[G2];
     __shared__ float kin[16 * KIN];
     const int64_t n_eff = n_active ? min((int64_t)*n_active, n) : n;

@@ -1,0 +1,61 @@
+// mfma_split.h -- FP32-accurate contractions on BF16 MFMA (gfx950).
+//
+// Each FP32 operand v is split, rounding to nearest even, into three bf16 parts
+// v = v1 + v2 + v3 + r with |v2| <= 2^-8 |v|, |v3| <= 2^-16 |v| and |r| <= 2^-24 |v|
+// (bf16 carries 8 significant bits; every difference is exact in FP32).  Of the nine
+// products of the parts of two operands, the six with v_i w_j, i + j <= 4, are kept:
+// the three dropped ones are below 2^-24 of the product.  Products of bf16 parts are
+// exact and v_mfma_f32_32x32x16_bf16 accumulates them in FP32, so a contraction
+// carries FP32-class error (a few units of 2^-24 of the sum of absolute products) at
+// 6 x 16 = 96 bf16 flops per FP32 multiply-add; the dense BF16 MFMA rate is 16 times
+// the FP32 one, so the contraction takes 6/16 of the matrix-core time of
+// v_mfma_f32_32x32x2_f32, and the splitting adds about 5.5 VALU per operand value.
+// Layout of v_mfma_f32_32x32x16_bf16: lane l holds A[i = l%32][k = 8(l/32) + j] and
+// B[k = 8(l/32) + j][n = l%32], j < 8; the accumulator (D) is lane l, register v ->
+// row 8(v/4) + 4(l/32) + v%4, column l%32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pdmp {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+
+// v = p1 + p2 + p3 + r, each part rounded to nearest even in bf16.
+__device__ __forceinline__ void split3(const float (&v)[8], bf16x8_t &p1, bf16x8_t &p2,
+                                       bf16x8_t &p3) {
+#pragma unroll
+    for (int j = 0; j < 8; j += 2) {
+        const f32x2_t a = {v[j], v[j + 1]};
+        const bf16x2_t h = __builtin_convertvector(a, bf16x2_t);
+        const f32x2_t r = a - __builtin_convertvector(h, f32x2_t);
+        const bf16x2_t m = __builtin_convertvector(r, bf16x2_t);
+        const f32x2_t r2 = r - __builtin_convertvector(m, f32x2_t);
+        const bf16x2_t l = __builtin_convertvector(r2, bf16x2_t);
+        p1[j] = h[0];
+        p1[j + 1] = h[1];
+        p2[j] = m[0];
+        p2[j + 1] = m[1];
+        p3[j] = l[0];
+        p3[j + 1] = l[1];
+    }
+}
+
+// acc += (a1 + a2 + a3)(b1 + b2 + b3) to FP32 accuracy: the six leading products,
+// smallest first.
+__device__ __forceinline__ f32x16_t mfma_x6(const bf16x8_t &a1, const bf16x8_t &a2,
+                                            const bf16x8_t &a3, const bf16x8_t &b1,
+                                            const bf16x8_t &b2, const bf16x8_t &b3,
+                                            f32x16_t acc) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a3, b1, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b2, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b3, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b1, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b2, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc, 0, 0, 0);
+}
+
+}  // namespace pdmp

@@ -13,15 +13,15 @@
 // Hessian of c = sigma(s):  Hc = sigma' Hs + sigma'' grad s grad s^T, with
 //   Hs = sum_j w_j phi_j ((x - h_j)(x - h_j)^T / l^4 - I / l^2).
 // Grid path (2-D hinges on a tensor grid): the G1 x G0 products U = W ex, V = W ex dx
-// of the plain morph and a third one, Q = W ex dx^2, on FP32 MFMA; the y sums run on
+// of the plain morph and a third one, Q = W ex dx^2, on BF16 MFMA at FP32 accuracy
+// (three-way bf16 splits, six leading products: mfma_split.h); the y sums run on
 // the accumulator layout as in the plain morph (same lane mapping, same xor-32 pair
 // sum).  Pairwise path (any hinges, 2-D or 3-D): one point per thread, hinges staged
 // in LDS tiles.
+#include "mfma_split.h"
 #include "pdmp_common.h"
 
 namespace pdmp {
-
-typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_iv;
 
 constexpr int kIvBlock = 256;
 
@@ -46,48 +46,54 @@ __device__ __forceinline__ float step_logdet(const float (&H)[DIM][DIM], float e
 
 // ------------------------------------------------------------ grid path ---
 
+// The x-side B operands of k-step ks for this lane (a = 16ks + 8half + j): ex, ex dx
+// and, with HESS, ex dx^2, each split into three bf16 parts.
+template <bool HESS>
+__device__ __forceinline__ void g2i_operands(const float *gxs, float xs, int ks, int half,
+                                             bf16x8_t (&e)[3], bf16x8_t (&de)[3],
+                                             bf16x8_t (&dde)[3]) {
+    float ev[8], dv[8], ddv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float d = xs - gxs[16 * ks + 8 * half + j];
+        ev[j] = exp2_fast(-d * d);
+        dv[j] = ev[j] * d;
+        ddv[j] = dv[j] * d;
+    }
+    split3(ev, e[0], e[1], e[2]);
+    split3(dv, de[0], de[1], de[2]);
+    if (HESS) split3(ddv, dde[0], dde[1], dde[2]);
+}
+
 // Sums at the prescaled point (xs, ys): s' (without beta), (sx, sy) with
 // grad s = -gscale (sx, sy), and with HESS (sxx, sxy, syy) with
 // Hs = gscale^2 [[sxx, sxy], [sxy, syy]] - (1/l^2) s' I.
-template <int TB, bool HESS>
-__device__ __forceinline__ void g2i_eval(const float *frag, const float *gxs, const float *gys,
-                                         int ks, float xs, float ys, float &s, float &sx,
-                                         float &sy, float &sxx, float &sxy, float &syy) {
+template <int TB, int KS, bool HESS>
+__device__ __forceinline__ void g2i_eval(const bf16x8_t *frag, const float *gxs, const float *gys,
+                                         float xs, float ys, float &s, float &sx, float &sy,
+                                         float &sxx, float &sxy, float &syy) {
     const int lane0 = threadIdx.x & 63, half = lane0 >> 5;
     int lane = lane0;  // opaque: the fragment reads stay inside the callers' loops
     asm volatile("" : "+v"(lane));
-    f32x16_iv U[TB], V[TB], Q[TB];
-    // k-step 0 from the zero accumulator; the next step's LDS operands are read ahead
-    // (the arrays carry one step of padding)
-    float gx_n = gxs[half], w_n[TB];
+    f32x16_t U[TB], V[TB], Q[TB];
+    // the operands of k-step ks + 1 are formed while k-step ks's products run; k-step 0
+    // starts the accumulators from the zero constant
+    bf16x8_t e[3], de[3], dde[3];
+    g2i_operands<HESS>(gxs, xs, 0, half, e, de, dde);
 #pragma unroll
-    for (int t = 0; t < TB; ++t) w_n[t] = frag[t * 64 + lane];
-    for (int kk = 0; kk < ks; ++kk) {
-        const float d = xs - gx_n;
-        float w_c[TB];
+    for (int ks = 0; ks < KS; ++ks) {
+        bf16x8_t ec[3] = {e[0], e[1], e[2]}, dc[3] = {de[0], de[1], de[2]},
+                 qc[3] = {dde[0], dde[1], dde[2]};
+        if (ks + 1 < KS) g2i_operands<HESS>(gxs, xs, ks + 1, half, e, de, dde);
 #pragma unroll
-        for (int t = 0; t < TB; ++t) w_c[t] = w_n[t];
-        gx_n = gxs[2 * (kk + 1) + half];
-#pragma unroll
-        for (int t = 0; t < TB; ++t) w_n[t] = frag[((kk + 1) * TB + t) * 64 + lane];
-        const float e = exp2_fast(-d * d);
-        const float de = e * d;
-        const float dde = de * d;
-        if (kk == 0) {
-            const f32x16_iv zero = {};
-#pragma unroll
-            for (int t = 0; t < TB; ++t) {
-                U[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], e, zero, 0, 0, 0);
-                V[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], de, zero, 0, 0, 0);
-                if (HESS) Q[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], dde, zero, 0, 0, 0);
-            }
-        } else {
-#pragma unroll
-            for (int t = 0; t < TB; ++t) {
-                U[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], e, U[t], 0, 0, 0);
-                V[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], de, V[t], 0, 0, 0);
-                if (HESS) Q[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(w_c[t], dde, Q[t], 0, 0, 0);
-            }
+        for (int t = 0; t < TB; ++t) {
+            const bf16x8_t a1 = frag[(0 * KS + ks) * TB * 64 + t * 64 + lane];
+            const bf16x8_t a2 = frag[(1 * KS + ks) * TB * 64 + t * 64 + lane];
+            const bf16x8_t a3 = frag[(2 * KS + ks) * TB * 64 + t * 64 + lane];
+            const f32x16_t zero = {};
+            U[t] = mfma_x6(a1, a2, a3, ec[0], ec[1], ec[2], ks == 0 ? zero : U[t]);
+            V[t] = mfma_x6(a1, a2, a3, dc[0], dc[1], dc[2], ks == 0 ? zero : V[t]);
+            if (HESS) Q[t] = mfma_x6(a1, a2, a3, qc[0], qc[1], qc[2], ks == 0 ? zero : Q[t]);
         }
     }
     s = sx = sy = sxx = sxy = syy = 0.0f;
@@ -120,22 +126,33 @@ __device__ __forceinline__ void g2i_eval(const float *frag, const float *gxs, co
 
 // MODE kLogdet: forward morph with the log-determinant.  MODE kInverse: inverse by
 // fixed point (iters per step) with residual and log-determinant.
-template <int TB, int MODE>
-__global__ void __launch_bounds__(kIvBlock) __attribute__((amdgpu_waves_per_eu(3)))
+template <int TB, int KS, int MODE>
+__global__ void __launch_bounds__(kIvBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_grid2d_inv(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
              float kappa, float gscale, const float *x_in, int64_t n, int T, float eta, int iters,
              float *x_out, float *logdet_out, float *resid_out) {
-    __shared__ float frag[33 * TB * 64];  // one k-step of padding for the read-ahead
-    __shared__ float gxs[66];
+    // fragments: frag[(p * KS + ks) * TB + t][lane] = part p of
+    //   W[b = 32t + lane%32][a = 16ks + 8(lane/32) + j], j < 8 (0 outside the grid)
+    __shared__ bf16x8_t frag[3 * KS * TB * 64];
+    __shared__ float gxs[16 * KS];
     __shared__ float gys[32 * TB];
     const int M = g0 * g1;
-    const int ks = (g0 + 1) / 2;
-    for (int idx = threadIdx.x; idx < (ks + 1) * TB * 64; idx += kIvBlock) {
-        const int ln = idx & 63, t = (idx >> 6) % TB, kk = idx / (64 * TB);
-        const int b = 32 * t + (ln & 31), a = 2 * kk + (ln >> 5);
-        frag[idx] = (a < g0 && b < g1) ? weights[a + (int64_t)g0 * b] : 0.0f;
+    for (int idx = threadIdx.x; idx < KS * TB * 64; idx += kIvBlock) {
+        const int ln = idx & 63, t = (idx >> 6) % TB, ks = idx / (64 * TB);
+        const int b = 32 * t + (ln & 31);
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int a = 16 * ks + 8 * (ln >> 5) + j;
+            v[j] = (a < g0 && b < g1) ? weights[a + (int64_t)g0 * b] : 0.0f;
+        }
+        bf16x8_t p1, p2, p3;
+        split3(v, p1, p2, p3);
+        frag[(0 * KS + ks) * TB * 64 + t * 64 + ln] = p1;
+        frag[(1 * KS + ks) * TB * 64 + t * 64 + ln] = p2;
+        frag[(2 * KS + ks) * TB * 64 + t * 64 + ln] = p3;
     }
-    for (int a = threadIdx.x; a < 2 * (ks + 1); a += kIvBlock)
+    for (int a = threadIdx.x; a < 16 * KS; a += kIvBlock)
         gxs[a] = a < g0 ? kappa * hinges[a] : 0.0f;
     for (int b = threadIdx.x; b < 32 * TB; b += kIvBlock)
         gys[b] = b < g1 ? kappa * hinges[(size_t)M + (size_t)g0 * b] : 0.0f;
@@ -157,11 +174,11 @@ k_grid2d_inv(const float *__restrict__ hinges, const float *__restrict__ weights
             const bool last = j == evals - 1;
             float s, sx, sy, sxx = 0.0f, sxy = 0.0f, syy = 0.0f;
             if (last)
-                g2i_eval<TB, true>(frag, gxs, gys, ks, kappa * x, kappa * y, s, sx, sy, sxx, sxy,
-                                   syy);
+                g2i_eval<TB, KS, true>(frag, gxs, gys, kappa * x, kappa * y, s, sx, sy, sxx, sxy,
+                                       syy);
             else
-                g2i_eval<TB, false>(frag, gxs, gys, ks, kappa * x, kappa * y, s, sx, sy, sxx, sxy,
-                                    syy);
+                g2i_eval<TB, KS, false>(frag, gxs, gys, kappa * x, kappa * y, s, sx, sy, sxx, sxy,
+                                        syy);
             float c, sp;
             sigmoid_and_slope(s + beta, c, sp);
             const float gx = -gscale * sx, gy = -gscale * sy;  // grad s
@@ -318,16 +335,24 @@ int32_t launch_morph_inverse(int dim, int mode, const float *hinges, const float
         grid[0] * grid[1] == M) {
         const int g0 = grid[0], g1 = grid[1];
         const dim3 blocks((unsigned)((n + 127) / 128)), blk(kIvBlock);
-#define PDMP_G2I(TB, MD)                                                                        \
-    hipLaunchKernelGGL((k_grid2d_inv<TB, MD>), blocks, blk, 0, st, hinges, weights, g0, g1, kappa, \
-                       gscale, x_in, n, T, eta, iters, x_out, logdet, resid)
+#define PDMP_G2I(TB, KS, MD)                                                               \
+    hipLaunchKernelGGL((k_grid2d_inv<TB, KS, MD>), blocks, blk, 0, st, hinges, weights, g0, g1, \
+                       kappa, gscale, x_in, n, T, eta, iters, x_out, logdet, resid)
+#define PDMP_G2I_KS(TB, MD)                      \
+    switch ((g0 + 15) / 16) {                    \
+        case 1: PDMP_G2I(TB, 1, MD); break;      \
+        case 2: PDMP_G2I(TB, 2, MD); break;      \
+        case 3: PDMP_G2I(TB, 3, MD); break;      \
+        default: PDMP_G2I(TB, 4, MD); break;     \
+    }
         if (g1 <= 32) {
-            if (mode == kInverse) PDMP_G2I(1, kInverse);
-            else PDMP_G2I(1, kLogdet);
+            if (mode == kInverse) PDMP_G2I_KS(1, kInverse)
+            else PDMP_G2I_KS(1, kLogdet)
         } else {
-            if (mode == kInverse) PDMP_G2I(2, kInverse);
-            else PDMP_G2I(2, kLogdet);
+            if (mode == kInverse) PDMP_G2I_KS(2, kInverse)
+            else PDMP_G2I_KS(2, kLogdet)
         }
+#undef PDMP_G2I_KS
 #undef PDMP_G2I
         return check_launch("k_grid2d_inv");
     }
