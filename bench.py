@@ -42,17 +42,24 @@ FLOPS_PER_PAIR = {2: 12, 3: 17}    # 5*dim + 2 algorithmic FP32 flops per sample
 # HBM traffic per launch of the headline kernel from the two rocprofv3 --pmc runs in
 # profiles/k_grid2d_x6_morph_ws2d_1M.md (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the
 # factors a plain 256 MiB device copy reads under the same counters).  Valid only
-# while grid2d.hip is the source the counters were taken on.
+# while the kernel's sources (grid2d.hip and the headers it includes) are the ones
+# the counters were taken on.
+GRID2D_SOURCES = ("grid2d.hip", "mfma_split.h", "pdmp_common.h")
 GRID2D_TRAFFIC = {"bytes": (4257.0 * 2.0 + 8192.0) * 1024,
-                  "sha256": "cc1600218edb0f2108efe3ec562a3b9b02e6d69409a182b7fd22a99a432bf92a"}
+                  "sha256": "81f169d1632b11e10b18eb6c1b969aec4cd330a43362e29883d14a0fe66727b1"}
+
+
+def grid2d_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in GRID2D_SOURCES:
+        with open(os.path.join(ROOT, "paper_2108_11775_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def grid2d_traffic():
-    import hashlib
-    src = os.path.join(ROOT, "paper_2108_11775_amd", "csrc", "grid2d.hip")
-    with open(src, "rb") as f:
-        ok = hashlib.sha256(f.read()).hexdigest() == GRID2D_TRAFFIC["sha256"]
-    return GRID2D_TRAFFIC["bytes"] if ok else None
+    return GRID2D_TRAFFIC["bytes"] if grid2d_sources_sha() == GRID2D_TRAFFIC["sha256"] else None
 
 
 def alu_peak_tflops(dim):
