@@ -18,6 +18,8 @@
 // speed.
 #include "pdmp_common.h"
 
+#include <algorithm>
+
 namespace pdmp {
 
 constexpr int kCullBlock = 256;
@@ -88,6 +90,64 @@ k_cull_scan(const int *__restrict__ counts, int m, int *start, int *cursor) {
         run += counts[c];
     }
     if (t == 1023) start[m] = part[1023];
+}
+
+// Block-privatised counting for the samples (grids of at most kCullLdsCells cells):
+// block b takes samples [b chunk, (b + 1) chunk) and counts them per cell in LDS.
+constexpr int kCullLdsCells = 8192;
+constexpr int kCullSortBlocks = 256;
+
+template <int DIM>
+__global__ void __launch_bounds__(1024)
+k_cull_bcount(CullGridDev g, const float *__restrict__ x, int64_t n, int m, int64_t chunk,
+              int *bc) {
+    __shared__ int hist[kCullLdsCells];
+    for (int c = threadIdx.x; c < m; c += blockDim.x) hist[c] = 0;
+    __syncthreads();
+    const int64_t a = (int64_t)blockIdx.x * chunk, b = min(a + chunk, n);
+    for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) {
+        float p[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) p[k] = x[(size_t)k * n + i];
+        atomicAdd(&hist[cell_id<DIM>(g, p)], 1);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < m; c += blockDim.x) bc[(size_t)blockIdx.x * m + c] = hist[c];
+}
+
+// Per cell: the total over blocks, and each block's offset within the cell (bc is
+// overwritten by the exclusive prefix over blocks).
+__global__ void __launch_bounds__(kCullBlock)
+k_cull_bprefix(int *bc, int nblk, int m, int *total) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    int run = 0;
+    for (int b = 0; b < nblk; ++b) {
+        const int v = bc[(size_t)b * m + c];
+        bc[(size_t)b * m + c] = run;
+        run += v;
+    }
+    total[c] = run;
+}
+
+// order[start[cell] + block offset + rank within the block] = i (the rank is the
+// arrival order of the block's LDS atomics; the sample order only affects speed)
+template <int DIM>
+__global__ void __launch_bounds__(1024)
+k_cull_bscatter(CullGridDev g, const float *__restrict__ x, int64_t n, int m, int64_t chunk,
+                const int *__restrict__ start, const int *__restrict__ boff, uint32_t *order) {
+    __shared__ int cur[kCullLdsCells];
+    for (int c = threadIdx.x; c < m; c += blockDim.x)
+        cur[c] = start[c] + boff[(size_t)blockIdx.x * m + c];
+    __syncthreads();
+    const int64_t a = (int64_t)blockIdx.x * chunk, b = min(a + chunk, n);
+    for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) {
+        float p[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) p[k] = x[(size_t)k * n + i];
+        const int pos = atomicAdd(&cur[cell_id<DIM>(g, p)], 1);
+        order[pos] = (uint32_t)i;
+    }
 }
 
 // pos = cursor[cell]++ ; order[pos] = i   (order within a cell: arrival order)
@@ -237,10 +297,16 @@ static int64_t cull_cells(const pdmp_cull_grid &g) {
     return m;
 }
 
+// Per-block cell counts of the samples (LDS path only).
+static int64_t cull_bc_ints(int64_t m) {
+    return m <= kCullLdsCells ? (int64_t)kCullSortBlocks * m : 0;
+}
+
 size_t cull_ws_bytes(const pdmp_cull_grid &g, int M, int64_t n) {
     const int64_t m = cull_cells(g);
     return 2 * al256c((size_t)(g.dim + 1) * M * 4) + al256c((size_t)M * 4) +
-           6 * al256c((size_t)(m + 1) * 4) + al256c((size_t)n * 4) + al256c((size_t)g.dim * n * 4);
+           6 * al256c((size_t)(m + 1) * 4) + al256c((size_t)n * 4) + al256c((size_t)g.dim * n * 4) +
+           al256c((size_t)cull_bc_ints(m) * 4);
 }
 
 int32_t launch_morph_culled(const pdmp_occupancy &occ, const pdmp_cull_grid &cg, const float *in,
@@ -275,6 +341,11 @@ int32_t launch_morph_culled(const pdmp_occupancy &occ, const pdmp_cull_grid &cg,
     uint32_t *sorder = (uint32_t *)p;
     p += al256c((size_t)n * 4);
     float *xs = (float *)p;
+    p += al256c((size_t)dim * n * 4);
+    int *bcnt = (int *)p;  // [kCullSortBlocks][m] (LDS path)
+    const bool lds_sort = m <= kCullLdsCells;
+    const int nblk = (int)std::min<int64_t>(kCullSortBlocks, (n + 1023) / 1024);
+    const int64_t chunk = (n + nblk - 1) / nblk;
 
     auto fill = [&](int *q, int64_t cnt) {
         hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, q,
@@ -292,7 +363,7 @@ int32_t launch_morph_culled(const pdmp_occupancy &occ, const pdmp_cull_grid &cg,
         return PDMP_EDEVICE;
     }
     fill(hcount, m);
-    fill(scount, m);
+    if (!lds_sort) fill(scount, m);
 #define PDMP_CULL_D(D)                                                                          \
     hipLaunchKernelGGL((k_cull_count<D>), bh, blk, 0, st, g, occ.hinges, (int64_t)M, hcount);   \
     hipLaunchKernelGGL(k_cull_scan, dim3(1), dim3(1024), 0, st, hcount, (int)m, hstart, hcur);  \
@@ -300,9 +371,20 @@ int32_t launch_morph_culled(const pdmp_occupancy &occ, const pdmp_cull_grid &cg,
                        horder);                                                                 \
     hipLaunchKernelGGL(k_cull_sort_cells, bc, blk, 0, st, hstart, (int)m, horder);              \
     hipLaunchKernelGGL(k_cull_gather, bh, blk, 0, st, hw, D + 1, (int64_t)M, horder, hsw);      \
-    hipLaunchKernelGGL((k_cull_count<D>), bs, blk, 0, st, g, in, n, scount);                    \
-    hipLaunchKernelGGL(k_cull_scan, dim3(1), dim3(1024), 0, st, scount, (int)m, sstart, scur);  \
-    hipLaunchKernelGGL((k_cull_scatter<D>), bs, blk, 0, st, g, in, n, scur, sorder);            \
+    if (lds_sort) {                                                                             \
+        hipLaunchKernelGGL((k_cull_bcount<D>), dim3(nblk), dim3(1024), 0, st, g, in, n, (int)m, \
+                           chunk, bcnt);                                                        \
+        hipLaunchKernelGGL(k_cull_bprefix, bc, blk, 0, st, bcnt, nblk, (int)m, scount);         \
+        hipLaunchKernelGGL(k_cull_scan, dim3(1), dim3(1024), 0, st, scount, (int)m, sstart,     \
+                           scur);                                                               \
+        hipLaunchKernelGGL((k_cull_bscatter<D>), dim3(nblk), dim3(1024), 0, st, g, in, n,       \
+                           (int)m, chunk, sstart, bcnt, sorder);                                \
+    } else {                                                                                    \
+        hipLaunchKernelGGL((k_cull_count<D>), bs, blk, 0, st, g, in, n, scount);                \
+        hipLaunchKernelGGL(k_cull_scan, dim3(1), dim3(1024), 0, st, scount, (int)m, sstart,     \
+                           scur);                                                               \
+        hipLaunchKernelGGL((k_cull_scatter<D>), bs, blk, 0, st, g, in, n, scur, sorder);        \
+    }                                                                                           \
     hipLaunchKernelGGL(k_cull_gather, bs, blk, 0, st, in, D, n, sorder, xs)
     if (dim == 2) {
         PDMP_CULL_D(2);
