@@ -376,10 +376,13 @@ def tanh_morph(P, I, K, torch, dev):
             "morph_ms": ms, "samples_per_s": N / (ms * 1e-3),
             "collision_free_before": 1 - h0.item() / N,
             "collision_free_after": 1 - h1.item() / N,
-            "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA / 1e12,
-                         "unit": "TFLOP/s", "frac": ach * 1e12 / PEAK_FP32_MFMA,
+            "roofline": {"bound": "mfma", "achieved": 6.0 * ach, "peak": PEAK_BF16_MFMA / 1e12,
+                         "unit": "TFLOP/s", "frac": 6.0 * ach * 1e12 / PEAK_BF16_MFMA,
                          "kernel": f"k_tanh_net<2,4,{L},kMorph>",
-                         "work": "4*(L-1)*H^2 FP32 MFMA flops per sample-step"}}
+                         "work": "24*(L-1)*H^2 BF16 MFMA flops per sample-step (the forward "
+                                 "and backward hidden products, 4*(L-1)*H^2 FP32 flops, as six "
+                                 "BF16 products of three-way splits)",
+                         "fp32_equivalent_tflops": ach}}
 
 
 def density_workload(P, I, K, torch, hl):

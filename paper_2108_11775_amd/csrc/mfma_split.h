@@ -58,4 +58,21 @@ __device__ __forceinline__ f32x16_t mfma_x6(const bf16x8_t &a1, const bf16x8_t &
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc, 0, 0, 0);
 }
 
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+
+// The same six products on v_mfma_f32_16x16x32_bf16 (lane l holds A[i = l%16][k =
+// 8(l/16) + j] and B[k = 8(l/16) + j][n = l%16]; D: lane l, register v -> row
+// 4(l/16) + v, column l%16).
+__device__ __forceinline__ f32x4_t mfma16_x6(const bf16x8_t &a1, const bf16x8_t &a2,
+                                             const bf16x8_t &a3, const bf16x8_t &b1,
+                                             const bf16x8_t &b2, const bf16x8_t &b3,
+                                             f32x4_t acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3, b1, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b2, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b3, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b1, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b2, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc, 0, 0, 0);
+}
+
 }  // namespace pdmp

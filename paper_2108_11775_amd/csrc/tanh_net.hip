@@ -6,18 +6,22 @@
 //   e_L = v * (1 - a_L^2),   e_l = (1 - a_l^2) * (W_l^T e_{l+1}),  grad s = W_0^T e_1
 //
 // One wave carries 16 points (four lanes per point) through the whole network.  The
-// hidden-to-hidden products, forward (W_l a) and backward (W_l^T e), are FP32 MFMA
-// (v_mfma_f32_16x16x4_f32) with the points as the 16 columns.  The accumulator of a
-// 16-row tile t gives lane l the units 16t + 4(l/16) + v (v = 0..3) of point l%16;
-// the contraction of the next product is ordered the same way (step (t, v) takes
-// units 16t + 4k + v, k = 0..3), so each lane feeds its own accumulator entries back
-// as the B operand -- activations never leave the registers.  The matching
+// hidden-to-hidden products, forward (W_l a) and backward (W_l^T e), run on the matrix
+// cores with the points as the 16 columns.  The accumulator of a 16-row tile t gives
+// lane l the units 16t + 4(l/16) + v (v = 0..3) of point l%16; the contraction of the
+// next product is ordered to match, so each lane feeds its own accumulator entries
+// back as the B operand -- activations never leave the registers.  The matching
 // permutation is applied once to the weights when they are staged in LDS in
-// fragment order (one conflict-free ds_read_b32 per MFMA).  The input layer
+// fragment order.  The morph, value and gradient kernel runs the products on BF16
+// MFMA at FP32 accuracy (v_mfma_f32_16x16x32_bf16, three-way bf16 splits, six
+// leading products: mfma_split.h); a 32-wide k-block takes tiles 2kb and 2kb + 1,
+// lane l supplying units 16(2kb + j/4) + 4(l/16) + j%4, j < 8.  The fit kernels stay
+// on FP32 MFMA (v_mfma_f32_16x16x4_f32, step (t, v) takes units 16t + 4k + v).  The input layer
 // (K = dim) and the output dot product are VALU work; the four lanes of a point are
 // summed by xor-16 and xor-32 exchanges (the same sum in all four).  Widths up to 64
 // run as 1, 2 or 4 tiles of 16, padded units having zero weights (tanh(0) = 0, so
 // they add nothing).
+#include "mfma_split.h"
 #include "pdmp_common.h"
 
 namespace pdmp {
@@ -97,10 +101,85 @@ __device__ __forceinline__ float tn_sum4(float p) {
     return p + __shfl_xor(p, 32, 64);
 }
 
+// ---- BF16-MFMA form (morph, value, gradient) ----
+
+template <int DIM, int NT, int L>
+struct TnLdsX6 {
+    static constexpr int HP = 16 * NT;
+    static constexpr int KB = (NT + 1) / 2;                      // 32-wide k-blocks
+    static constexpr int NF = (L - 1) * NT * KB * 3 * 64;        // bf16x8 fragments per direction
+    // fw[((l-1) NT + to) KB + kb][p][lane] = part p of W_l[16to + lane%16][unit(kb, lane, j)]
+    // bw[((l-1) NT + ti) KB + kb][p][lane] = part p of W_l[unit(kb, lane, j)][16ti + lane%16]
+    // with unit(kb, lane, j) = 16(2kb + j/4) + 4(lane/16) + j%4, j < 8
+    bf16x8_t fw[NF > 0 ? NF : 1];
+    bf16x8_t bw[NF > 0 ? NF : 1];
+    float w0t[DIM][HP];  // W_0 transposed
+    float bias[L][HP];
+    float vo[HP];
+    float bo;
+};
+
+template <int DIM, int NT, int L>
+__device__ void tn_stage_x6(TnLdsX6<DIM, NT, L> &S, const float *__restrict__ P, int H) {
+    using LD = TnLdsX6<DIM, NT, L>;
+    for (int idx = threadIdx.x; idx < LD::NF / 3; idx += blockDim.x) {
+        const int ln = idx & 63, q = idx >> 6;  // q = ((l-1) NT + first) KB + kb
+        const int kb = q % LD::KB, first = (q / LD::KB) % NT, l = 1 + q / (LD::KB * NT);
+        const float *W = P + tn_w_off(l, DIM, H);
+        float vf[8], vb[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int t = 2 * kb + j / 4;
+            const int unit = 16 * t + 4 * (ln >> 4) + (j & 3);
+            const int other = 16 * first + (ln & 15);
+            const bool ok = t < NT && unit < H && other < H;
+            vf[j] = ok ? W[(int64_t)other * H + unit] : 0.0f;  // forward: row other, col unit
+            vb[j] = ok ? W[(int64_t)unit * H + other] : 0.0f;  // backward: W^T
+        }
+        bf16x8_t f1, f2, f3, b1, b2, b3;
+        split3(vf, f1, f2, f3);
+        split3(vb, b1, b2, b3);
+        const int base = q * 3 * 64 + ln;
+        S.fw[base] = f1;
+        S.fw[base + 64] = f2;
+        S.fw[base + 128] = f3;
+        S.bw[base] = b1;
+        S.bw[base + 64] = b2;
+        S.bw[base + 128] = b3;
+    }
+    for (int idx = threadIdx.x; idx < LD::HP; idx += blockDim.x) {
+        const bool ok = idx < H;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) S.w0t[k][idx] = ok ? P[(int64_t)idx * DIM + k] : 0.0f;
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const int64_t bo = tn_w_off(l, DIM, H) + (int64_t)H * (l == 0 ? DIM : H);
+            S.bias[l][idx] = ok ? P[bo + idx] : 0.0f;
+        }
+        S.vo[idx] = ok ? P[tn_w_off(L, DIM, H) + idx] : 0.0f;
+    }
+    if (threadIdx.x == 0) S.bo = P[tn_w_off(L, DIM, H) + H];
+}
+
+// The lane's B operand of k-block kb from its accumulator-layout values v[t][0..3],
+// split into three bf16 parts.
+template <int NT>
+__device__ __forceinline__ void tn_kblock(const f32x4_tn (&v)[NT], int kb, bf16x8_t &p1,
+                                          bf16x8_t &p2, bf16x8_t &p3) {
+    float b[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int t = 2 * kb + j / 4;
+        b[j] = t < NT ? v[t < NT ? t : 0][j & 3] : 0.0f;
+    }
+    split3(b, p1, p2, p3);
+}
+
 // s (all four lanes of the point) and, with GRAD, grad_x s at the point x.
 template <int DIM, int NT, int L, bool GRAD>
-__device__ __forceinline__ void tn_point(const TnLds<DIM, NT, L> &S, const float (&x)[DIM],
-                                         float &s, float (&g)[DIM]) {
+__device__ __forceinline__ void tn_point_x6(const TnLdsX6<DIM, NT, L> &S, const float (&x)[DIM],
+                                            float &s, float (&g)[DIM]) {
+    using LD = TnLdsX6<DIM, NT, L>;
     const int lane0 = threadIdx.x & 63, u4 = 4 * (lane0 >> 4);
     // The weight fragments are the same on every call; an opaque copy of the lane
     // index keeps the compiler from hoisting their LDS reads out of the step loop
@@ -131,7 +210,7 @@ __device__ __forceinline__ void tn_point(const TnLds<DIM, NT, L> &S, const float
             d[0][t][v] = dv;
         }
     }
-    // hidden layers: z = b_l + W_l a  (MFMA, the bias preloaded in the accumulator)
+    // hidden layers: z = b_l + W_l a  (the bias preloaded in the accumulator)
 #pragma unroll
     for (int l = 1; l < L; ++l) {
         f32x4_tn z[NT];
@@ -143,15 +222,16 @@ __device__ __forceinline__ void tn_point(const TnLds<DIM, NT, L> &S, const float
             z[to][2] = bb.z;
             z[to][3] = bb.w;
         }
-        const float *fw = S.fw + (l - 1) * NT * NT * 256;
 #pragma unroll
-        for (int ti = 0; ti < NT; ++ti)
+        for (int kb = 0; kb < LD::KB; ++kb) {
+            bf16x8_t b1, b2, b3;
+            tn_kblock<NT>(a, kb, b1, b2, b3);
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-#pragma unroll
-                for (int to = 0; to < NT; ++to)
-                    z[to] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                        fw[((to * NT + ti) * 4 + v) * 64 + lane], a[ti][v], z[to], 0, 0, 0);
+            for (int to = 0; to < NT; ++to) {
+                const bf16x8_t *f = S.fw + (((l - 1) * NT + to) * LD::KB + kb) * 3 * 64 + lane;
+                z[to] = mfma16_x6(f[0], f[64], f[128], b1, b2, b3, z[to]);
+            }
+        }
 #pragma unroll
         for (int to = 0; to < NT; ++to)
 #pragma unroll
@@ -187,17 +267,17 @@ __device__ __forceinline__ void tn_point(const TnLds<DIM, NT, L> &S, const float
 #pragma unroll
     for (int l = L - 1; l >= 1; --l) {
         f32x4_tn G[NT];
-        const f32x4_tn zero = {};  // the first product starts from the zero accumulator
-        const float *bw = S.bw + (l - 1) * NT * NT * 256;
+        const f32x4_tn zero = {};  // the first k-block starts from the zero accumulator
 #pragma unroll
-        for (int to = 0; to < NT; ++to)
+        for (int kb = 0; kb < LD::KB; ++kb) {
+            bf16x8_t b1, b2, b3;
+            tn_kblock<NT>(e, kb, b1, b2, b3);
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-#pragma unroll
-                for (int ti = 0; ti < NT; ++ti)
-                    G[ti] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                        bw[((ti * NT + to) * 4 + v) * 64 + lane], e[to][v],
-                        (to == 0 && v == 0) ? zero : G[ti], 0, 0, 0);
+            for (int ti = 0; ti < NT; ++ti) {
+                const bf16x8_t *f = S.bw + (((l - 1) * NT + ti) * LD::KB + kb) * 3 * 64 + lane;
+                G[ti] = mfma16_x6(f[0], f[64], f[128], b1, b2, b3, kb == 0 ? zero : G[ti]);
+            }
+        }
 #pragma unroll
         for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
@@ -222,8 +302,8 @@ template <int DIM, int NT, int L, int MODE>
 __global__ void __launch_bounds__(kTnMorphBlock)
 k_tanh_net(const float *__restrict__ P, int H, const float *x_in, int64_t n, int T, float eta,
            float *c_out, float *s_out, float *g_out, float *x_out) {
-    __shared__ __attribute__((aligned(16))) TnLds<DIM, NT, L> S;
-    tn_stage<DIM, NT, L>(S, P, H);
+    __shared__ __attribute__((aligned(16))) TnLdsX6<DIM, NT, L> S;
+    tn_stage_x6<DIM, NT, L>(S, P, H);
     __syncthreads();
     const int lane = threadIdx.x & 63, quad = lane >> 4;
     const int64_t tiles = (n + kTnPts - 1) / kTnPts;
@@ -237,7 +317,7 @@ k_tanh_net(const float *__restrict__ P, int H, const float *x_in, int64_t n, int
         for (int k = 0; k < DIM; ++k) x[k] = x_in[(size_t)k * n + ic];
         const int steps = MODE == kMorph ? T : 1;
         for (int st = 0; st < steps; ++st) {
-            tn_point<DIM, NT, L, MODE != kEval>(S, x, s, g);
+            tn_point_x6<DIM, NT, L, MODE != kEval>(S, x, s, g);
             if (MODE == kMorph) {
                 float c, sp;
                 sigmoid_and_slope(s, c, sp);
