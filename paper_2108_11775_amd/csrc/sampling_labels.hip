@@ -99,33 +99,76 @@ __global__ void k_zero_u64(uint64_t *p) {
 }
 
 // Count of 1-labels: one integer atomic per wave (deterministic).
-__device__ __forceinline__ void count_hits(bool hit, uint64_t *n_hit) {
+// Adds the block's hits (c per thread) with one global atomic per block: a single
+// counter updated by every wave of a large launch serialises in L2 and had cost more
+// than the labelling itself.  Every thread of the block calls it (uniform).
+__device__ __forceinline__ void count_hits_block(int c, uint64_t *n_hit) {
+    __shared__ unsigned int blk;
     if (!n_hit) return;
-    const uint64_t m = __ballot(hit);
-    if ((threadIdx.x & 63) == 0 && m) atomicAdd((unsigned long long *)n_hit, (unsigned long long)__popcll(m));
+    if (threadIdx.x == 0) blk = 0;
+    __syncthreads();
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&blk, (unsigned int)c);
+    __syncthreads();
+    if (threadIdx.x == 0 && blk) atomicAdd((unsigned long long *)n_hit, (unsigned long long)blk);
 }
 
-__global__ void __launch_bounds__(256)
+// Discs staged in LDS as FP64 (cx, cy, r^2) tiles: r^2 of an FP32 radius is exact in
+// FP64, so every decision is the one of the plain per-disc loop; each thread carries
+// kLabPts points (coalesced: point base + u * blockDim).
+constexpr int kLabBlock = 256;
+constexpr int kLabPts = 4;
+constexpr int kLabTile = 1024;
+
+__global__ void __launch_bounds__(kLabBlock)
 k_label_discs(const float *__restrict__ cen, const float *__restrict__ rad, int K,
               const float *__restrict__ x, int64_t n, uint8_t *out, uint64_t *n_hit) {
 #pragma clang fp contract(off)
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool hit = false;
-    if (i < n) {
-        const double px = x[i], py = x[(size_t)n + i];
-        for (int k = 0; k < K; ++k) {
-            const double dx = px - (double)cen[k];
-            const double dy = py - (double)cen[K + k];
-            const double a = dx * dx;
-            const double b = dy * dy;
-            const double d2 = a + b;
-            const double r = rad[k];
-            const double rr = r * r;
-            if (d2 <= rr) hit = true;
-        }
-        out[i] = hit ? 1 : 0;
+    __shared__ double sd[3][kLabTile];
+    const int64_t base = (int64_t)blockIdx.x * kLabBlock * kLabPts + threadIdx.x;
+    double px[kLabPts], py[kLabPts];
+    bool hit[kLabPts];
+#pragma unroll
+    for (int u = 0; u < kLabPts; ++u) {
+        const int64_t i = base + (int64_t)u * kLabBlock;
+        const int64_t ic = i < n ? i : n - 1;
+        px[u] = x[ic];
+        py[u] = x[(size_t)n + ic];
+        hit[u] = false;
     }
-    count_hits(hit, n_hit);
+    for (int k0 = 0; k0 < K; k0 += kLabTile) {
+        const int kn = min(kLabTile, K - k0);
+        __syncthreads();
+        for (int j = threadIdx.x; j < kn; j += kLabBlock) {
+            sd[0][j] = (double)cen[k0 + j];
+            sd[1][j] = (double)cen[K + k0 + j];
+            const double r = rad[k0 + j];
+            sd[2][j] = r * r;
+        }
+        __syncthreads();
+        for (int k = 0; k < kn; ++k) {
+            const double cx = sd[0][k], cy = sd[1][k], rr = sd[2][k];
+#pragma unroll
+            for (int u = 0; u < kLabPts; ++u) {
+                const double dx = px[u] - cx;
+                const double dy = py[u] - cy;
+                const double a = dx * dx;
+                const double b = dy * dy;
+                const double d2 = a + b;
+                hit[u] = hit[u] || d2 <= rr;
+            }
+        }
+    }
+    int c = 0;
+#pragma unroll
+    for (int u = 0; u < kLabPts; ++u) {
+        const int64_t i = base + (int64_t)u * kLabBlock;
+        const bool h = i < n && hit[u];
+        if (i < n) out[i] = h ? 1 : 0;
+        c += h ? 1 : 0;
+    }
+    count_hits_block(c, n_hit);
 }
 
 __device__ __forceinline__ bool in_any_box(const double p[3], const float *__restrict__ cen,
@@ -151,7 +194,7 @@ k_label_boxes(const float *__restrict__ cen, const float *__restrict__ half, int
         hit = in_any_box(p, cen, half, K);
         out[i] = hit ? 1 : 0;
     }
-    count_hits(hit, n_hit);
+    count_hits_block(hit ? 1 : 0, n_hit);
 }
 
 // Standard-DH chain in FP64 for the label decision (same operation order as the
@@ -196,7 +239,7 @@ k_label_configs(pdmp_arm arm, const float *__restrict__ cen, const float *__rest
         }
         out[s] = hit ? 1 : 0;
     }
-    count_hits(hit, n_hit);
+    count_hits_block(hit ? 1 : 0, n_hit);
 }
 
 int32_t launch_label_discs(const pdmp_discs &sc, const float *x, int64_t n, uint8_t *out,
@@ -207,8 +250,9 @@ int32_t launch_label_discs(const pdmp_discs &sc, const float *x, int64_t n, uint
         if (int32_t e = check_launch("k_zero_u64")) return e;
     }
     if (n == 0) return PDMP_OK;
-    hipLaunchKernelGGL(k_label_discs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                       sc.centres, sc.radii, sc.n, x, n, out, n_hit);
+    const int64_t per = (int64_t)kLabBlock * kLabPts;
+    hipLaunchKernelGGL(k_label_discs, dim3((unsigned)((n + per - 1) / per)), dim3(kLabBlock), 0,
+                       st, sc.centres, sc.radii, sc.n, x, n, out, n_hit);
     return check_launch("k_label_discs");
 }
 
