@@ -1,4 +1,5 @@
-"""GPU parity of the grid-factorised 3-D path (16^3 hinges, FP32 MFMA): workspace
+"""GPU parity of the grid-factorised 3-D path (16^3 hinges, BF16 MFMA at FP32
+accuracy): workspace
 occupancy/gradient/morph, the joint-space morph and the body-point check, against
 the oracle's pairwise definitions with the same tolerances as the pairwise path."""
 import math
@@ -31,6 +32,31 @@ def test_grid3d_eval_grad(n):
     _, g_r, _, gabs = O.occ_grad(oo, x)
     assert np.all(np.abs(host(s) - s_r) <= TOL * sabs), np.max(np.abs(host(s) - s_r) / sabs)
     assert np.all(np.abs(host(c) - c_r) <= TOL * (c_r + c_r * (1 - c_r) * sabs))
+    assert np.all(np.abs(host(g) - g_r).max(axis=0) <= TOL * gabs)
+
+
+def test_grid3d_split_precision_wide_range():
+    """Three-way bf16 splits on the 3-D grid: weights over six decades with random
+    signs, no bias, and points up to 6 lengthscales outside the grid in every axis
+    (features tiny but normal in FP32) meet the FP32 tolerance of the absolute sums."""
+    require_gpu()
+    rng = np.random.default_rng(3108)
+    ell = 0.15
+    ax = np.linspace(-1, 1, 16)
+    gz, gy, gx = np.meshgrid(ax, ax, ax, indexing="ij")
+    h = np.stack([gx.ravel(), gy.ravel(), gz.ravel()]).astype(np.float32)
+    mag = 10.0 ** rng.uniform(-5, 1, 4097)
+    wb = (mag * rng.choice([-1.0, 1.0], 4097)).astype(np.float32)
+    wb[-1] = 0.0
+    x = np.concatenate([rng.uniform(-1.05, 1.05, (3, 600)),
+                        rng.uniform(-1 - 6 * ell, 1 + 6 * ell, (3, 600))], axis=1).astype(np.float32)
+    go = gpu_occ(h, wb, ell, G)
+    _, s = P.occupancy_eval(go, dev(x))
+    _, g = P.occupancy_grad(go, dev(x))
+    oo = oracle_occ(h, wb, ell)
+    s_r, _, sabs = O.occ_eval(oo, x)
+    _, g_r, _, gabs = O.occ_grad(oo, x)
+    assert np.all(np.abs(host(s) - s_r) <= TOL * sabs), np.max(np.abs(host(s) - s_r) / sabs)
     assert np.all(np.abs(host(g) - g_r).max(axis=0) <= TOL * gabs)
 
 
