@@ -46,7 +46,7 @@ FLOPS_PER_PAIR = {2: 12, 3: 17}    # 5*dim + 2 algorithmic FP32 flops per sample
 # the counters were taken on.
 GRID2D_SOURCES = ("grid2d.hip", "mfma_split.h", "pdmp_common.h")
 GRID2D_TRAFFIC = {"bytes": (4257.0 * 2.0 + 8192.0) * 1024,
-                  "sha256": "81f169d1632b11e10b18eb6c1b969aec4cd330a43362e29883d14a0fe66727b1"}
+                  "sha256": "169117012544c82937144bf758074de90d97b7114388ea32637a1246c0a36033"}
 
 
 def grid2d_sources_sha():
