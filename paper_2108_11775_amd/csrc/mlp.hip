@@ -238,12 +238,21 @@ k_final_scaled(const double *__restrict__ parts, int np, double scale, float *ou
     if (threadIdx.x == 0) *out = (float)(sh[0] * scale);
 }
 
-// out[j] = sum_{s < S} part[s * MN + j], fixed order
+// out[j] = sum_{s < S} part[s * MN + j], fixed order; the loads go out eight at a
+// time (the adds keep the order), so the sum is not a chain of dependent loads.
 __global__ void k_sum_splits(const float *__restrict__ part, int S, int64_t MN, float *out) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= MN) return;
     double acc = 0.0;
-    for (int s = 0; s < S; ++s) acc += part[(int64_t)s * MN + j];
+    int s = 0;
+    for (; s + 8 <= S; s += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(s + u) * MN + j];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; s < S; ++s) acc += part[(int64_t)s * MN + j];
     out[j] = (float)acc;
 }
 
