@@ -96,21 +96,37 @@ k_final(const double *__restrict__ a, int na, double sa, const double *__restric
 }
 
 // out[j] = scale * sum_{r < rows} part[r * m + j] (+ add[j] * add_scale).  A block
-// owns 64 columns; its four waves sum the rows r = ph (mod 4) in increasing order and
-// the four sums are added in a fixed order.
-__global__ void __launch_bounds__(256)
+// owns 64 columns; its sixteen waves sum the rows r = ph (mod 16) in increasing order,
+// issuing the loads four at a time (the adds keep the order), and the sixteen sums are
+// added in a fixed order.  With few columns (4096 weights: 64 blocks) each thread's
+// chain of loads is short.
+constexpr int kSumPh = 16;
+
+__global__ void __launch_bounds__(64 * kSumPh)
 k_sum_rows(const float *__restrict__ part, int rows, int64_t m, double scale,
            const float *__restrict__ add, float add_scale, float *out) {
-    __shared__ double sh[4][64];
+    __shared__ double sh[kSumPh][64];
     const int cl = threadIdx.x & 63, ph = threadIdx.x >> 6;
     const int64_t j = (int64_t)blockIdx.x * 64 + cl;
     double acc = 0.0;
-    if (j < m)
-        for (int r = ph; r < rows; r += 4) acc += part[(size_t)r * m + j];
+    if (j < m) {
+        int r = ph;
+        for (; r + 3 * kSumPh < rows; r += 4 * kSumPh) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = part[(size_t)(r + u * kSumPh) * m + j];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc += v[u];
+        }
+        for (; r < rows; r += kSumPh) acc += part[(size_t)r * m + j];
+    }
     sh[ph][cl] = acc;
     __syncthreads();
     if (ph != 0 || j >= m) return;
-    float v = (float)((((sh[0][cl] + sh[1][cl]) + sh[2][cl]) + sh[3][cl]) * scale);
+    double t = sh[0][cl];
+#pragma unroll
+    for (int q = 1; q < kSumPh; ++q) t += sh[q][cl];
+    float v = (float)(t * scale);
     if (add) v = fmaf(add_scale, add[j], v);
     out[j] = v;
 }
@@ -216,8 +232,8 @@ int32_t launch_sum(const float *x, int64_t n, int mode, double scale, float *out
 
 int32_t launch_sum_rows(const float *part, int rows, int64_t m, double scale, const float *add,
                         float add_scale, float *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_sum_rows, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, st, part, rows, m,
-                       scale, add, add_scale, out);
+    hipLaunchKernelGGL(k_sum_rows, dim3((unsigned)((m + 63) / 64)), dim3(64 * kSumPh), 0, st, part,
+                       rows, m, scale, add, add_scale, out);
     return check_launch("k_sum_rows");
 }
 
@@ -259,7 +275,7 @@ int32_t launch_logit_bwd(int dim, const float *hinges, const float *weights, int
             e = launch_pairwise_wgrad(dim, hinges, M, kappa, gscale, x, n, gw, part, S, st);
         }
         if (e) return e;
-        hipLaunchKernelGGL(k_sum_rows, dim3((unsigned)((M + 63) / 64)), dim3(256), 0, st, part, S,
+        hipLaunchKernelGGL(k_sum_rows, dim3((unsigned)((M + 63) / 64)), dim3(64 * kSumPh), 0, st, part, S,
                            (int64_t)M, (double)grad_scale, decay_w, l2, grad_w);
         if (int32_t e2 = check_launch("k_sum_rows")) return e2;
         if (int32_t e2 = launch_sum(gw, n, 0, (double)grad_scale, grad_w + M, rparts, st)) return e2;
