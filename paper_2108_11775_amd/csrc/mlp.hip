@@ -267,8 +267,17 @@ k_colsum_partial(const uint16_t *__restrict__ x, int64_t B, int N, int64_t rows_
     const int64_t r0 = (int64_t)blockIdx.y * rows_per;
     const int64_t r1 = r0 + rows_per < B ? r0 + rows_per : B;
     float acc = 0.0f;
-    if (col < N)
-        for (int64_t r = r0 + ph; r < r1; r += 4) acc += bf16_to_f32(x[r * N + col]);
+    if (col < N) {
+        int64_t r = r0 + ph;
+        for (; r + 28 < r1; r += 32) {  // eight loads in flight, added in row order
+            uint16_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = x[(r + 4 * u) * N + col];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += bf16_to_f32(v[u]);
+        }
+        for (; r < r1; r += 4) acc += bf16_to_f32(x[r * N + col]);
+    }
     sh[ph][cl] = acc;
     __syncthreads();
     if (ph == 0 && col < N)
