@@ -150,11 +150,167 @@ k_grid2d_x6(const float *__restrict__ hinges, const float *__restrict__ weights,
     }
 }
 
+// ---- small batches: 16 samples per wave on v_mfma_f32_16x16x32_bf16 ----
+//
+// A batch of fewer than 2^17 samples gives the 32-sample waves above fewer than four
+// waves per SIMD, and a lone wave's T-step chain is then its latency.  Here four lanes
+// share a sample (lane l: sample l%16, group g = l/16): each lane forms the B entries
+// ex_a, ex_a dx_a of a = 32kb + 8g + j (j < 8) and, in the accumulator layout, owns the
+// rows b = 16t + 4g + v (v < 4) of every 16-row tile t; the four lanes of a sample are
+// summed by xor-16 and xor-32 exchanges (the same value in all four).  A lane forms
+// half the B entries and owns half the rows of the 32-wide kernel's lanes, so a step's
+// chain is about half as long, and the batch spreads over twice as many waves.
+constexpr int kG2sBlock = 256;  // 4 waves, 16 samples each
+
+template <int TB16, int KB, int MODE>
+__global__ void __launch_bounds__(kG2sBlock)
+k_grid2d_x6s(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
+             float kappa, float gscale, const float *x_in, int64_t n, int T, float eta,
+             float *c_out, float *s_out, float *g_out, float *x_out) {
+    // fragments: frag[(p * KB + kb) * TB16 + t][lane] = part p of
+    //   W[b = 16t + lane%16][a = 32kb + 8(lane/16) + j], j < 8 (0 outside the grid)
+    __shared__ bf16x8_t frag[3 * KB * TB16 * 64];
+    __shared__ float gxs[32 * KB];
+    __shared__ float gys[16 * TB16];
+    const int M = g0 * g1;
+    for (int idx = threadIdx.x; idx < KB * TB16 * 64; idx += kG2sBlock) {
+        const int ln = idx & 63, t = (idx >> 6) % TB16, kb = idx / (64 * TB16);
+        const int b = 16 * t + (ln & 15);
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int a = 32 * kb + 8 * (ln >> 4) + j;
+            v[j] = (a < g0 && b < g1) ? weights[a + (int64_t)g0 * b] : 0.0f;
+        }
+        bf16x8_t p1, p2, p3;
+        split3(v, p1, p2, p3);
+        frag[(0 * KB + kb) * TB16 * 64 + t * 64 + ln] = p1;
+        frag[(1 * KB + kb) * TB16 * 64 + t * 64 + ln] = p2;
+        frag[(2 * KB + kb) * TB16 * 64 + t * 64 + ln] = p3;
+    }
+    for (int a = threadIdx.x; a < 32 * KB; a += kG2sBlock)
+        gxs[a] = a < g0 ? kappa * hinges[a] : 0.0f;
+    for (int b = threadIdx.x; b < 16 * TB16; b += kG2sBlock)
+        gys[b] = b < g1 ? kappa * hinges[(size_t)M + (size_t)g0 * b] : 0.0f;
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, grp = lane >> 4;
+    const int64_t wave = (int64_t)blockIdx.x * (kG2sBlock / 64) + (threadIdx.x >> 6);
+    const int64_t i = wave * 16 + (lane & 15);
+    const int64_t ic = i < n ? i : n - 1;
+    float x = x_in[ic], y = x_in[(size_t)n + ic];
+    const float beta = weights[M];
+
+    float s = 0.0f, sx = 0.0f, sy = 0.0f;
+    const int steps = MODE == kMorph ? T : 1;
+    for (int st = 0; st < steps; ++st) {
+        const float xs = kappa * x, ys = kappa * y;
+        int ln = lane;  // opaque: keeps the fragment reads inside the step loop
+        asm volatile("" : "+v"(ln));
+        f32x4_t U[TB16], V[TB16];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            float ev[8], dv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float d = xs - gxs[32 * kb + 8 * grp + j];
+                ev[j] = exp2_fast(-d * d);
+                dv[j] = ev[j] * d;
+            }
+            bf16x8_t e1, e2, e3, d1, d2, d3;
+            split3(ev, e1, e2, e3);
+            split3(dv, d1, d2, d3);
+#pragma unroll
+            for (int t = 0; t < TB16; ++t) {
+                const bf16x8_t a1 = frag[(0 * KB + kb) * TB16 * 64 + t * 64 + ln];
+                const bf16x8_t a2 = frag[(1 * KB + kb) * TB16 * 64 + t * 64 + ln];
+                const bf16x8_t a3 = frag[(2 * KB + kb) * TB16 * 64 + t * 64 + ln];
+                const f32x4_t zero = {};
+                U[t] = mfma16_x6(a1, a2, a3, e1, e2, e3, kb == 0 ? zero : U[t]);
+                V[t] = mfma16_x6(a1, a2, a3, d1, d2, d3, kb == 0 ? zero : V[t]);
+            }
+        }
+        s = 0.0f;
+        sx = 0.0f;
+        sy = 0.0f;
+#pragma unroll
+        for (int t = 0; t < TB16; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int b = 16 * t + 4 * grp + v;
+                const float d = ys - gys[b];
+                const float e = exp2_fast(-d * d);
+                s = fmaf(e, U[t][v], s);
+                sx = fmaf(e, V[t][v], sx);
+                sy = fmaf(e * d, U[t][v], sy);
+            }
+        s += __shfl_xor(s, 16, 64);
+        sx += __shfl_xor(sx, 16, 64);
+        sy += __shfl_xor(sy, 16, 64);
+        s += __shfl_xor(s, 32, 64);
+        sx += __shfl_xor(sx, 32, 64);
+        sy += __shfl_xor(sy, 32, 64);
+        if (MODE == kMorph) {
+            float c, sp;
+            sigmoid_and_slope(s + beta, c, sp);
+            const float step = eta * sp * gscale;
+            x = fmaf(step, sx, x);
+            y = fmaf(step, sy, y);
+        }
+    }
+    if (grp != 0 || i >= n) return;
+    if (MODE == kMorph) {
+        x_out[i] = x;
+        x_out[(size_t)n + i] = y;
+    } else {
+        const float sv = s + beta;
+        float c, sp;
+        sigmoid_and_slope(sv, c, sp);
+        if (c_out) c_out[i] = c;
+        if (MODE == kEval) {
+            if (s_out) s_out[i] = sv;
+        } else {
+            g_out[i] = -sp * gscale * sx;
+            g_out[(size_t)n + i] = -sp * gscale * sy;
+        }
+    }
+}
+
+// Morphs of fewer samples than this take the 16-sample waves.
+constexpr int64_t kG2SmallBatch = (int64_t)1 << 17;
+
+static int32_t launch_grid2d_small(const RbfArgs &a, int g0, int g1, hipStream_t st) {
+    const int64_t blocks = (a.n + 63) / 64;
+    const dim3 grid((unsigned)blocks), blk(kG2sBlock);
+#define PDMP_G2S(TB, KB)                                                                         \
+    hipLaunchKernelGGL((k_grid2d_x6s<TB, KB, kMorph>), grid, blk, 0, st, a.hinges, a.weights, g0, \
+                       g1, a.kappa, a.gscale, a.x_in, a.n, a.T, a.eta, a.c_out, a.s_out,          \
+                       a.g_out, a.x_out)
+#define PDMP_G2S_T(KB)                             \
+    switch ((g1 + 15) / 16) {                      \
+        case 1: PDMP_G2S(1, KB); break;            \
+        case 2: PDMP_G2S(2, KB); break;            \
+        case 3: PDMP_G2S(3, KB); break;            \
+        default: PDMP_G2S(4, KB); break;           \
+    }
+    if (g0 <= 32) {
+        PDMP_G2S_T(1)
+    } else {
+        PDMP_G2S_T(2)
+    }
+#undef PDMP_G2S_T
+#undef PDMP_G2S
+    return check_launch("k_grid2d_x6s");
+}
+
 // Returns PDMP_EUNSUPPORTED (without launching) when the grid does not fit.
 int32_t launch_grid2d(int mode, const RbfArgs &a, int g0, int g1, hipStream_t st) {
     if (g0 < 1 || g1 < 1 || g0 > 64 || g1 > 64 || (int64_t)g0 * g1 != a.M)
         return PDMP_EUNSUPPORTED;
     if (mode != kEval && mode != kGrad && mode != kMorph) return PDMP_EUNSUPPORTED;
+    // a single evaluation would pay the per-block staging of W twice over: only the
+    // multi-step morph takes the 16-sample waves
+    if (a.n < kG2SmallBatch && mode == kMorph && a.T > 1) return launch_grid2d_small(a, g0, g1, st);
     const int64_t blocks = (a.n + 127) / 128;
     const dim3 grid((unsigned)blocks), blk(kG2Block);
 #define PDMP_G2(TB, KS, MODE)                                                                \

@@ -114,3 +114,29 @@ def test_grid_split_precision_wide_range():
     _, g_r, _, gabs = O.occ_grad(oo, x)
     assert np.all(np.abs(host(s) - s_r) <= TOL * sabs)
     assert np.all(np.abs(host(g) - g_r).max(axis=0) <= TOL * gabs)
+
+
+def test_grid_large_batch_ragged_grid_sampled():
+    """Morphs of 2^17 samples and more take the 32-sample waves (smaller morphs the
+    16-sample waves, which the other morph cases here exercise): a ragged 45 x 37
+    grid, 2^17 + 333 samples, outputs sampled every 293rd sample."""
+    require_gpu()
+    rng = np.random.default_rng(4537)
+    g0, g1 = 45, 37
+    ax = np.sort(rng.uniform(-3, 3, g0)).astype(np.float32)
+    ay = np.sort(rng.uniform(-2, 2, g1)).astype(np.float32)
+    j = np.arange(g0 * g1)
+    h = np.stack([ax[j % g0], ay[j // g0]]).astype(np.float32)
+    wb = rng.normal(0, 1.5, g0 * g1 + 1).astype(np.float32)
+    n = (1 << 17) + 333
+    x = rng.uniform(-3.5, 3.5, (2, n)).astype(np.float32)
+    go = _grid_occ(h, wb, 0.5, g0, g1)
+    _, s = P.occupancy_eval(go, dev(x))
+    out = host(P.morph_samples(go, dev(x), 5, 0.02))
+    idx = np.unique(np.r_[0, np.arange(1, n, 293), n - 1])
+    oo = oracle_occ(h, wb, 0.5)
+    s_r, _, sabs = O.occ_eval(oo, x[:, idx])
+    assert np.all(np.abs(host(s)[idx] - s_r) <= TOL * sabs)
+    ref, amp, _, _ = O.morph_ws(oo, x[:, idx], 5, 0.02, diag=True)
+    err = np.abs(out[:, idx] - ref).max(axis=0)
+    assert np.all(err <= TOL * np.maximum(1, amp) * np.maximum(1, np.abs(ref).max(axis=0)))
