@@ -81,3 +81,20 @@ def test_culled_morph_3d(n):
     g, og = _grids(3, [-1] * 3, [1] * 3, 4.0 * 0.15)
     x0 = rng.uniform(-1.1, 1.1, (3, n)).astype(np.float32)
     _check(go, oo, g, og, x0, 10, 0.005)
+
+
+def test_culled_morph_many_cells():
+    """More than 8192 cells (100 x 100 of side >= 0.2 on the config-2 box): the samples'
+    counting sort takes its global-atomic path instead of the per-block LDS
+    histograms; the result is the oracle's culled morph on the same cells.  A cutoff
+    of half a lengthscale makes the culled field jump at cell faces, so one step
+    (both sides choose cells from the same input) keeps the comparison free of a
+    rounding-decided cell change."""
+    require_gpu()
+    cfg = K.C2
+    sc = ws_scene(cfg)
+    go, oo = gpu_occ(sc["h"], sc["wb"], sc["ell"]), oracle_occ(sc["h"], sc["wb"], sc["ell"])
+    g, og = _grids(2, [cfg.lo] * 2, [cfg.hi] * 2, 0.2)
+    assert g.nc[0] * g.nc[1] > 8192
+    x0 = I.uniform_points(cfg.cfg_id, K.STREAM_EVAL, 2, 3000, cfg.lo, cfg.hi)
+    _check(go, oo, g, og, x0, 1, cfg.eta)
