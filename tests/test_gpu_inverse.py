@@ -91,6 +91,27 @@ def test_inverse_config1(grid):
     assert np.all(np.abs(y - y0).max(axis=0) <= 1e-4 * A * np.maximum(1, np.abs(y0).max(axis=0)))
 
 
+def test_inverse_config2_grid_sampled():
+    """The inverse at the benchmark's grid size (64 x 64: two row tiles, four k-steps
+    of the split contraction) and iteration count, on a sampled subset of a batch."""
+    require_gpu()
+    cfg = K.C2
+    _, go, oo = _scene(cfg, True)
+    y0 = O.uniform_samples(I.philox_seed(cfg.cfg_id), 0, [cfg.lo] * 2, [cfg.hi] * 2, 1 << 14)
+    idx = np.unique(np.r_[0, np.arange(1, 1 << 14, 211), (1 << 14) - 1])
+    z_all = P.morph_samples(go, dev(y0), cfg.T, cfg.eta)
+    y, ld, resid = P.morph_inverse(go, z_all, cfg.T, cfg.eta, 10)
+    y, ld, resid = host(y)[:, idx], host(ld)[idx], host(resid)[idx]
+    z = host(z_all)[:, idx]
+    y_r, ld_r, ldsc, _ = O.morph_inverse(oo, z, cfg.T, cfg.eta, 10)
+    _, amp, _, _ = O.morph_ws(oo, y_r, cfg.T, cfg.eta, diag=True)
+    A = np.maximum(1, amp)
+    err = np.abs(y - y_r).max(axis=0)
+    assert np.all(err <= TOL * A * np.maximum(1, np.abs(y_r).max(axis=0))), np.max(err)
+    assert np.all(np.abs(ld - ld_r) <= TOL * (ldsc + A * cfg.T))
+    assert np.all(resid <= 4 * 2.0 ** -23 * np.maximum(1, np.abs(y).max(axis=0)))
+
+
 @pytest.mark.parametrize("n", [1, 255, 1000])
 def test_pairwise_3d(n):
     require_gpu()
