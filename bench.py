@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_VALU = 157.3e12          # FLOP/s, dense FP32 vector (packed issue)
 PEAK_FP32_MFMA = 157.3e12          # FLOP/s, dense FP32 matrix
 PEAK_BF16_MFMA = 2.5e15            # FLOP/s, dense BF16 matrix
+PEAK_F16_MFMA = 2.5e15             # FLOP/s, dense FP16 matrix
 # v_exp_f32 runs at half rate (8 cycles per wave64 on a 16-lane SIMD), i.e. 4 SIMDs x
 # 16 lanes x 1/2 per clock per CU; measured on the part it overlaps with
 # independent VALU work, so a pair costs max(flop time, exp time).
@@ -40,13 +41,13 @@ FLOPS_PER_PAIR = {2: 12, 3: 17}    # 5*dim + 2 algorithmic FP32 flops per sample
 
 
 # HBM traffic per launch of the headline kernel from the two rocprofv3 --pmc runs in
-# profiles/k_grid2d_x6_morph_ws2d_1M.md (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the
+# profiles/k_grid2d_mfma_morph_ws2d_1M.md (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the
 # factors a plain 256 MiB device copy reads under the same counters).  Valid only
 # while the kernel's sources (grid2d.hip and the headers it includes) are the ones
 # the counters were taken on.
 GRID2D_SOURCES = ("grid2d.hip", "mfma_split.h", "pdmp_common.h")
-GRID2D_TRAFFIC = {"bytes": (4256.7 * 2.0 + 8192.0) * 1024,
-                  "sha256": "f178a757f5ea999ab48934d9a95de2f23a79db345ae7187fce1c53dc239cc699"}
+GRID2D_TRAFFIC = {"bytes": (4274.0 * 2.0 + 8192.0) * 1024,
+                  "sha256": "4b165a9b9e6834fbe39c9b9f96a858c1810b059f7cbac054a023080dce796cc8"}
 
 
 def grid2d_sources_sha():
@@ -195,16 +196,18 @@ def headline(args, P, I, K, torch, dev):
     if occ.grid:
         # own algorithmic work of the factorised evaluation, per sample and step: two
         # G1 x G0 matrix-vector products (4 G0 G1 FP32 flops), each FP32 multiply-add
-        # carried out as six BF16 products of three-way splits (24 G0 G1 BF16 flops)
+        # carried out as three FP16 products of two-part splits (12 G0 G1 FP16 flops;
+        # this workload's weights and hinges are inside the FP16 scheme's range)
         fp32_tf = N * cfg.T * 4.0 * G0 * G1 / (morph_ms * 1e-3) / 1e12
-        achieved = 6.0 * fp32_tf
-        res["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_MFMA / 1e12,
-                           "unit": "TFLOP/s", "frac": achieved * 1e12 / PEAK_BF16_MFMA,
-                           "traffic": grid2d_traffic(), "kernel": "k_grid2d_x6<2,4,kMorph>",
+        achieved = 3.0 * fp32_tf
+        res["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK_F16_MFMA / 1e12,
+                           "unit": "TFLOP/s", "frac": achieved * 1e12 / PEAK_F16_MFMA,
+                           "traffic": grid2d_traffic(), "kernel": "k_grid2d_mfma<2,4,kMorph>",
                            "kernel_ms": morph_ms,
-                           "work": "24*G0*G1 BF16 MFMA flops per sample-step (64x64 grid): the "
-                                   "two FP32 contractions (4*G0*G1 flops) as the six leading "
-                                   "BF16 products of three-way splits",
+                           "work": "12*G0*G1 FP16 MFMA flops per sample-step (64x64 grid): the "
+                                   "two FP32 contractions (4*G0*G1 flops) as the three leading "
+                                   "FP16 products of two-part splits of power-of-two-scaled "
+                                   "operands",
                            "fp32_equivalent_tflops": fp32_tf,
                            "fp32_equivalent_frac_of_fp32_mfma_peak": fp32_tf * 1e12 / PEAK_FP32_MFMA,
                            "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE + "
@@ -687,12 +690,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+bf16x6",
+        "dtype": "f32+f16x3",
         "data": "synthetic (seeded disc world, Philox prior samples, occupancy fitted on the GPU)",
         "config": {"workload": "plain morph 2-D large: 1,048,576 samples, 64x64 hinges, "
                                "l=0.4, T=50, eta=0.02, 100 discs",
                    "N": hl["N"], "T": cfg.T, "M": cfg.n_hinges, "eta": cfg.eta,
-                   "path": "grid factorisation (FP32 MFMA)" if hl["sc"]["occ"].grid else
+                   "path": "grid factorisation (FP32-accurate split MFMA)" if hl["sc"]["occ"].grid else
                            "pairwise RBF sum"},
         "collision_free_before": hl["free_before"],
         "collision_free_after": hl["free_after"],

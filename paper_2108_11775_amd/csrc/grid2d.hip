@@ -24,8 +24,26 @@ namespace pdmp {
 
 constexpr int kG2Block = 256;   // 4 waves, 32 samples each
 
-// The contractions run on BF16 MFMA at FP32 accuracy (three-way bf16 splits, six
-// leading products; mfma_split.h).
+// The contractions run at FP32 accuracy on the matrix cores, on one of two split
+// schemes chosen per launch from the operands' range (every block reaches the same
+// choice from the same weights and hinges; morphs and batches of 2^17 samples or more
+// only -- a smaller single evaluation keeps the BF16 scheme and skips the check):
+//  * FP16 (two-part splits, three products; mfma_split.h) when FP16's exponent range
+//    can hold the operands after power-of-two scaling: W is scaled so that
+//    2^14 <= max|W| < 2^15, and every nonzero |W| is at least 2^-19 max|W| (its two
+//    parts then stay normal, or their rounding stays within 2^-19 of it); the x-side
+//    operands of a sample are scaled by 2^c with c = 15 - k + floor(m), m the squared
+//    (kappa-scaled) distance of the sample from the hinge x-range [gmin, gmax] and
+//    2^k >= sqrt(m), so the largest 2^c ex_a is at most 2^15 and at least 2^(14-k)
+//    outside the range; inside it, every point lies within 3 (kappa units) of a
+//    hinge when no two consecutive hinge x-coordinates are more than 6 apart, and then
+//    the largest 2^15 ex_a is at least 2^6.  2^c ex_a dx_a stays below 2^15 as well.
+//    The sums are scaled back by 2^-(sW + c) with ldexp (exact).
+//  * BF16 (three-part splits, six products) otherwise: bf16 has FP32's exponent range.
+// The FP16 scheme needs half the matrix-core work and about half the splitting VALU.
+
+constexpr int kG2RangeLog2 = 19;    // nonzero |W| >= 2^-19 max|W|
+constexpr float kG2MaxGap = 6.0f;   // consecutive kappa-scaled hinge x-coordinates
 
 // The x-side operands of k-step ks for this lane: ex and ex * dx at a = 16ks + 8half + j.
 __device__ __forceinline__ void x6_operands(const float *gxs, float xs, int ks, int half,
@@ -41,97 +59,45 @@ __device__ __forceinline__ void x6_operands(const float *gxs, float xs, int ks, 
     split3(dv, de[0], de[1], de[2]);
 }
 
-template <int TB, int KS, int MODE>
-__global__ void __launch_bounds__(kG2Block) __attribute__((amdgpu_waves_per_eu(2)))
-k_grid2d_x6(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
-            float kappa, float gscale, const float *x_in, int64_t n, int T, float eta,
-            float *c_out, float *s_out, float *g_out, float *x_out) {
-    // fragments: frag[(p * KS + ks) * TB + t][lane] = part p of
-    //   W[b = 32t + lane%32][a = 16ks + 8(lane/32) + j], j < 8 (0 outside the grid)
-    __shared__ bf16x8_t frag[3 * KS * TB * 64];
-    __shared__ float gxs[16 * KS];
-    __shared__ float gys[32 * TB];
-    const int M = g0 * g1;
-    for (int idx = threadIdx.x; idx < KS * TB * 64; idx += kG2Block) {
-        const int ln = idx & 63, t = (idx >> 6) % TB, ks = idx / (64 * TB);
-        const int b = 32 * t + (ln & 31);
-        float v[8];
+// The same operands scaled by 2^c (c folded into the exponent) as FP16 pairs.
+__device__ __forceinline__ void h3_operands(const float *gxs, float xs, float cf, int ks,
+                                            int half, f16x8_t (&e)[2], f16x8_t (&de)[2]) {
+    float ev[8], dv[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int a = 16 * ks + 8 * (ln >> 5) + j;
-            v[j] = (a < g0 && b < g1) ? weights[a + (int64_t)g0 * b] : 0.0f;
-        }
-        bf16x8_t p1, p2, p3;
-        split3(v, p1, p2, p3);
-        frag[(0 * KS + ks) * TB * 64 + t * 64 + ln] = p1;
-        frag[(1 * KS + ks) * TB * 64 + t * 64 + ln] = p2;
-        frag[(2 * KS + ks) * TB * 64 + t * 64 + ln] = p3;
+    for (int j = 0; j < 8; ++j) {
+        const float d = xs - gxs[16 * ks + 8 * half + j];
+        ev[j] = exp2_fast(fmaf(-d, d, cf));
+        dv[j] = ev[j] * d;
     }
-    for (int a = threadIdx.x; a < 16 * KS; a += kG2Block)
-        gxs[a] = a < g0 ? kappa * hinges[a] : 0.0f;
-    for (int b = threadIdx.x; b < 32 * TB; b += kG2Block)
-        gys[b] = b < g1 ? kappa * hinges[(size_t)M + (size_t)g0 * b] : 0.0f;
-    __syncthreads();
+    split2h(ev, e[0], e[1]);
+    split2h(dv, de[0], de[1]);
+}
 
-    const int lane = threadIdx.x & 63, half = lane >> 5;
-    const int64_t wave = (int64_t)blockIdx.x * (kG2Block / 64) + (threadIdx.x >> 6);
-    const int64_t i = wave * 32 + (lane & 31);
-    const int64_t ic = i < n ? i : n - 1;
-    float x = x_in[ic], y = x_in[(size_t)n + ic];
-    const float beta = weights[M];
+// Per-block operand range: max|W| and the smallest nonzero |W| (as FP32 bit patterns,
+// which order like the values for non-negative numbers and put NaN above infinity)
+// and the hinge x-range and largest gap in kappa units.
+struct G2Range {
+    uint32_t wmax[kG2Block / 64], wmin[kG2Block / 64];
+    float gmin, gmax, gap;
+};
 
-    float s = 0.0f, sx = 0.0f, sy = 0.0f;
-    const int steps = MODE == kMorph ? T : 1;
-    for (int st = 0; st < steps; ++st) {
-        const float xs = kappa * x, ys = kappa * y;
-        f32x16_t U[TB], V[TB];
-        // an opaque copy of the lane index keeps the fragment reads inside the step
-        // loop (hoisted, the loop-invariant W parts would take 96 registers)
-        int ln = lane;
-        asm volatile("" : "+v"(ln));
-        // the operands of k-step ks + 1 are formed while k-step ks's products run;
-        // k-step 0 starts the accumulators from the zero constant
-        bf16x8_t e[3], de[3];
-        x6_operands(gxs, xs, 0, half, e, de);
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            bf16x8_t ec[3] = {e[0], e[1], e[2]}, dc[3] = {de[0], de[1], de[2]};
-            if (ks + 1 < KS) x6_operands(gxs, xs, ks + 1, half, e, de);
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
 #pragma unroll
-            for (int t = 0; t < TB; ++t) {
-                const bf16x8_t a1 = frag[(0 * KS + ks) * TB * 64 + t * 64 + ln];
-                const bf16x8_t a2 = frag[(1 * KS + ks) * TB * 64 + t * 64 + ln];
-                const bf16x8_t a3 = frag[(2 * KS + ks) * TB * 64 + t * 64 + ln];
-                const f32x16_t zero = {};
-                U[t] = mfma_x6(a1, a2, a3, ec[0], ec[1], ec[2], ks == 0 ? zero : U[t]);
-                V[t] = mfma_x6(a1, a2, a3, dc[0], dc[1], dc[2], ks == 0 ? zero : V[t]);
-            }
-        }
-        s = 0.0f;
-        sx = 0.0f;
-        sy = 0.0f;
-#pragma unroll
-        for (int t = 0; t < TB; ++t)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int b = 32 * t + 8 * (v >> 2) + 4 * half + (v & 3);
-                const float d = ys - gys[b];
-                const float e = exp2_fast(-d * d);
-                s = fmaf(e, U[t][v], s);
-                sx = fmaf(e, V[t][v], sx);
-                sy = fmaf(e * d, U[t][v], sy);
-            }
-        s += __shfl_xor(s, 32, 64);
-        sx += __shfl_xor(sx, 32, 64);
-        sy += __shfl_xor(sy, 32, 64);
-        if (MODE == kMorph) {
-            float c, sp;
-            sigmoid_and_slope(s + beta, c, sp);
-            const float step = eta * sp * gscale;
-            x = fmaf(step, sx, x);
-            y = fmaf(step, sy, y);
-        }
-    }
+    for (int off = 32; off >= 1; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return v;
+}
+
+// The state of one sample's lane pair across the steps, and its outputs.
+template <int MODE>
+__device__ __forceinline__ void g2_finish(float s, float sx, float sy, float beta, float gscale,
+                                          float x, float y, int half, int64_t i, int64_t n,
+                                          float *c_out, float *s_out, float *g_out,
+                                          float *x_out) {
     if (half != 0 || i >= n) return;
     if (MODE == kMorph) {
         x_out[i] = x;
@@ -148,6 +114,250 @@ k_grid2d_x6(const float *__restrict__ hinges, const float *__restrict__ weights,
             g_out[(size_t)n + i] = -sp * gscale * sy;
         }
     }
+}
+
+// The y contraction on the accumulator layout and the xor-32 sum of the lane pair.
+template <int TB>
+__device__ __forceinline__ void g2_ysum(const float *gys, float ys, int half,
+                                        const f32x16_t (&U)[TB], const f32x16_t (&V)[TB],
+                                        float &s, float &sx, float &sy) {
+    s = 0.0f;
+    sx = 0.0f;
+    sy = 0.0f;
+#pragma unroll
+    for (int t = 0; t < TB; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int b = 32 * t + 8 * (v >> 2) + 4 * half + (v & 3);
+            const float d = ys - gys[b];
+            const float e = exp2_fast(-d * d);
+            s = fmaf(e, U[t][v], s);
+            sx = fmaf(e, V[t][v], sx);
+            sy = fmaf(e * d, U[t][v], sy);
+        }
+    s += __shfl_xor(s, 32, 64);
+    sx += __shfl_xor(sx, 32, 64);
+    sy += __shfl_xor(sy, 32, 64);
+}
+
+template <int TB, int KS, int MODE>
+__global__ void __launch_bounds__(kG2Block) __attribute__((amdgpu_waves_per_eu(2)))
+k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
+              float kappa, float gscale, const float *x_in, int64_t n, int T, float eta,
+              int allow_fp16, float *c_out, float *s_out, float *g_out, float *x_out) {
+    // fragments, BF16 scheme: frag[(p * KS + ks) * TB + t][lane] = part p < 3 of
+    //   W[b = 32t + lane%32][a = 16ks + 8(lane/32) + j], j < 8 (0 outside the grid);
+    // FP16 scheme: the same with parts p < 2 of 2^sW W
+    __shared__ uint4 fraw[3 * KS * TB * 64];
+    __shared__ float gxs[16 * KS];
+    __shared__ float gys[32 * TB];
+    __shared__ G2Range rg;
+    const int M = g0 * g1;
+    const int lane = threadIdx.x & 63, half = lane >> 5, wv = threadIdx.x >> 6;
+
+    // hinge coordinates (kappa-scaled); padding x-coordinates lie far away so that
+    // their features are 0 on both schemes (their weights are 0)
+    for (int a = threadIdx.x; a < 16 * KS; a += kG2Block)
+        gxs[a] = a < g0 ? kappa * hinges[a] : 1e18f;
+    for (int b = threadIdx.x; b < 32 * TB; b += kG2Block)
+        gys[b] = b < g1 ? kappa * hinges[(size_t)M + (size_t)g0 * b] : 0.0f;
+    // this thread's share of W in fragment order, kept in registers through the range
+    // check; its largest and smallest nonzero magnitude
+    constexpr int kNI = (KS * TB * 64 + kG2Block - 1) / kG2Block;
+    float wv8[kNI][8];
+    {
+        uint32_t mx = 0, mn = 0xffffffffu;
+#pragma unroll
+        for (int it = 0; it < kNI; ++it) {
+            const int idx = threadIdx.x + it * kG2Block;
+            const int ln = idx & 63, t = (idx >> 6) % TB, ks = idx / (64 * TB);
+            const int b = 32 * t + (ln & 31);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int a = 16 * ks + 8 * (ln >> 5) + j;
+                const float w = (idx < KS * TB * 64 && a < g0 && b < g1)
+                                    ? weights[a + (int64_t)g0 * b] : 0.0f;
+                wv8[it][j] = w;
+                const uint32_t u = __float_as_uint(w) & 0x7fffffffu;
+                mx = max(mx, u);
+                if (u != 0) mn = min(mn, u);
+            }
+        }
+        if (allow_fp16) {
+            mx = wave_max_u32(mx);
+            mn = wave_min_u32(mn);
+            if (lane == 0) {
+                rg.wmax[wv] = mx;
+                rg.wmin[wv] = mn;
+            }
+        }
+    }
+    if (allow_fp16 && wv == 0) {
+        // g0 <= 64: one hinge x-coordinate per lane; the next larger coordinate of
+        // each by a scan over the lanes
+        const bool act = lane < g0;
+        const float g = act ? kappa * hinges[lane] : 0.0f;
+        float lo = act ? g : INFINITY, hi = act ? g : -INFINITY, nxt = INFINITY;
+        for (int b = 0; b < g0; ++b) {
+            const float o = __builtin_bit_cast(float, __builtin_amdgcn_readlane(
+                                                          __builtin_bit_cast(int, g), b));
+            if (o > g) nxt = fminf(nxt, o);
+        }
+        float gap = act && nxt < INFINITY ? nxt - g : 0.0f;
+        if (act && !(g == g)) gap = INFINITY;  // a NaN coordinate fails the check
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            lo = fminf(lo, __shfl_xor(lo, off, 64));
+            hi = fmaxf(hi, __shfl_xor(hi, off, 64));
+            gap = fmaxf(gap, __shfl_xor(gap, off, 64));
+        }
+        if (lane == 0) {
+            rg.gmin = lo;
+            rg.gmax = hi;
+            rg.gap = gap;
+        }
+    }
+    __syncthreads();
+    // FP16 scheme: finite weights within 2^-19 of their largest magnitude (or all zero),
+    // finite hinge x-range, no x-gap above kG2MaxGap
+    int sw = 0;
+    float gmin = 0.0f, gmax = 0.0f;
+    uint32_t wmx = 0, wmn = 0;
+    bool fp16 = false;
+    if (allow_fp16) {
+        wmx = rg.wmax[0];
+        wmn = rg.wmin[0];
+#pragma unroll
+        for (int w = 1; w < kG2Block / 64; ++w) {
+            wmx = max(wmx, rg.wmax[w]);
+            wmn = min(wmn, rg.wmin[w]);
+        }
+        gmin = rg.gmin;
+        gmax = rg.gmax;
+        fp16 = wmx < 0x7f800000u && rg.gap <= kG2MaxGap && gmax - gmin < INFINITY;
+    }
+    if (fp16 && wmx != 0) {
+        int e;
+        (void)frexpf(__uint_as_float(wmx), &e);  // max|W| = f 2^e, f in [0.5, 1)
+        sw = 15 - e;
+        fp16 = __uint_as_float(wmn) >= ldexpf(__uint_as_float(wmx), -kG2RangeLog2);
+    }
+    fp16 = __builtin_amdgcn_readfirstlane((int)fp16) != 0;
+
+    const int64_t wave = (int64_t)blockIdx.x * (kG2Block / 64) + wv;
+    const int64_t i = wave * 32 + (lane & 31);
+    const int64_t ic = i < n ? i : n - 1;
+    float x = x_in[ic], y = x_in[(size_t)n + ic];
+    const float beta = weights[M];
+    const int steps = MODE == kMorph ? T : 1;
+    float s = 0.0f, sx = 0.0f, sy = 0.0f;
+
+    if (fp16) {
+        f16x8_t *frag = reinterpret_cast<f16x8_t *>(fraw);
+#pragma unroll
+        for (int it = 0; it < kNI; ++it) {
+            const int idx = threadIdx.x + it * kG2Block;
+            if (idx >= KS * TB * 64) break;
+            const int ln = idx & 63, t = (idx >> 6) % TB, ks = idx / (64 * TB);
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = ldexpf(wv8[it][j], sw);
+            f16x8_t p1, p2;
+            split2h(v, p1, p2);
+            frag[(0 * KS + ks) * TB * 64 + t * 64 + ln] = p1;
+            frag[(1 * KS + ks) * TB * 64 + t * 64 + ln] = p2;
+        }
+        __syncthreads();
+        for (int st = 0; st < steps; ++st) {
+            const float xs = kappa * x, ys = kappa * y;
+            // the operand scale 2^c of this sample (both lanes of the pair agree)
+            const float dist = fmaxf(fmaxf(gmin - xs, xs - gmax), 0.0f);
+            const float m = floorf(fminf(dist * dist, 256.0f));
+            int k;
+            (void)frexpf(dist, &k);  // dist < 2^k
+            k = max(k, 0);
+            const int c = 15 - k + (int)m;
+            f32x16_t U[TB], V[TB];
+            int ln = lane;  // opaque: keeps the fragment reads inside the step loop
+            asm volatile("" : "+v"(ln));
+            f16x8_t e[2], de[2];
+            h3_operands(gxs, xs, (float)c, 0, half, e, de);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                f16x8_t ec[2] = {e[0], e[1]}, dc[2] = {de[0], de[1]};
+                if (ks + 1 < KS) h3_operands(gxs, xs, (float)c, ks + 1, half, e, de);
+#pragma unroll
+                for (int t = 0; t < TB; ++t) {
+                    const f16x8_t a1 = frag[(0 * KS + ks) * TB * 64 + t * 64 + ln];
+                    const f16x8_t a2 = frag[(1 * KS + ks) * TB * 64 + t * 64 + ln];
+                    const f32x16_t zero = {};
+                    U[t] = mfma_h3(a1, a2, ec[0], ec[1], ks == 0 ? zero : U[t]);
+                    V[t] = mfma_h3(a1, a2, dc[0], dc[1], ks == 0 ? zero : V[t]);
+                }
+            }
+            g2_ysum<TB>(gys, ys, half, U, V, s, sx, sy);
+            const int un = -(sw + c);
+            s = ldexpf(s, un);
+            sx = ldexpf(sx, un);
+            sy = ldexpf(sy, un);
+            if (MODE == kMorph) {
+                float cc, sp;
+                sigmoid_and_slope(s + beta, cc, sp);
+                const float step = eta * sp * gscale;
+                x = fmaf(step, sx, x);
+                y = fmaf(step, sy, y);
+            }
+        }
+    } else {
+        bf16x8_t *frag = reinterpret_cast<bf16x8_t *>(fraw);
+#pragma unroll
+        for (int it = 0; it < kNI; ++it) {
+            const int idx = threadIdx.x + it * kG2Block;
+            if (idx >= KS * TB * 64) break;
+            const int ln = idx & 63, t = (idx >> 6) % TB, ks = idx / (64 * TB);
+            bf16x8_t p1, p2, p3;
+            split3(wv8[it], p1, p2, p3);
+            frag[(0 * KS + ks) * TB * 64 + t * 64 + ln] = p1;
+            frag[(1 * KS + ks) * TB * 64 + t * 64 + ln] = p2;
+            frag[(2 * KS + ks) * TB * 64 + t * 64 + ln] = p3;
+        }
+        __syncthreads();
+        for (int st = 0; st < steps; ++st) {
+            const float xs = kappa * x, ys = kappa * y;
+            f32x16_t U[TB], V[TB];
+            // an opaque copy of the lane index keeps the fragment reads inside the step
+            // loop (hoisted, the loop-invariant W parts would take 96 registers)
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            // the operands of k-step ks + 1 are formed while k-step ks's products run;
+            // k-step 0 starts the accumulators from the zero constant
+            bf16x8_t e[3], de[3];
+            x6_operands(gxs, xs, 0, half, e, de);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                bf16x8_t ec[3] = {e[0], e[1], e[2]}, dc[3] = {de[0], de[1], de[2]};
+                if (ks + 1 < KS) x6_operands(gxs, xs, ks + 1, half, e, de);
+#pragma unroll
+                for (int t = 0; t < TB; ++t) {
+                    const bf16x8_t a1 = frag[(0 * KS + ks) * TB * 64 + t * 64 + ln];
+                    const bf16x8_t a2 = frag[(1 * KS + ks) * TB * 64 + t * 64 + ln];
+                    const bf16x8_t a3 = frag[(2 * KS + ks) * TB * 64 + t * 64 + ln];
+                    const f32x16_t zero = {};
+                    U[t] = mfma_x6(a1, a2, a3, ec[0], ec[1], ec[2], ks == 0 ? zero : U[t]);
+                    V[t] = mfma_x6(a1, a2, a3, dc[0], dc[1], dc[2], ks == 0 ? zero : V[t]);
+                }
+            }
+            g2_ysum<TB>(gys, ys, half, U, V, s, sx, sy);
+            if (MODE == kMorph) {
+                float c, sp;
+                sigmoid_and_slope(s + beta, c, sp);
+                const float step = eta * sp * gscale;
+                x = fmaf(step, sx, x);
+                y = fmaf(step, sy, y);
+            }
+        }
+    }
+    g2_finish<MODE>(s, sx, sy, beta, gscale, x, y, half, i, n, c_out, s_out, g_out, x_out);
 }
 
 // ---- small batches: 16 samples per wave on v_mfma_f32_16x16x32_bf16 ----
@@ -313,10 +523,13 @@ int32_t launch_grid2d(int mode, const RbfArgs &a, int g0, int g1, hipStream_t st
     if (a.n < kG2SmallBatch && mode == kMorph && a.T > 1) return launch_grid2d_small(a, g0, g1, st);
     const int64_t blocks = (a.n + 127) / 128;
     const dim3 grid((unsigned)blocks), blk(kG2Block);
-#define PDMP_G2(TB, KS, MODE)                                                                \
-    hipLaunchKernelGGL((k_grid2d_x6<TB, KS, MODE>), grid, blk, 0, st, a.hinges, a.weights, g0, \
-                       g1, a.kappa, a.gscale, a.x_in, a.n, a.T, a.eta, a.c_out, a.s_out,        \
-                       a.g_out, a.x_out)
+    // the FP16 scheme's per-block range check pays off over a morph's T steps or a
+    // large batch; a small single evaluation keeps the BF16 scheme without the check
+    const int allow16 = mode == kMorph || a.n >= kG2SmallBatch;
+#define PDMP_G2(TB, KS, MODE)                                                                  \
+    hipLaunchKernelGGL((k_grid2d_mfma<TB, KS, MODE>), grid, blk, 0, st, a.hinges, a.weights, g0, \
+                       g1, a.kappa, a.gscale, a.x_in, a.n, a.T, a.eta, allow16, a.c_out,        \
+                       a.s_out, a.g_out, a.x_out)
 #define PDMP_G2_KS(TB, MODE)                      \
     switch ((g0 + 15) / 16) {                     \
         case 1: PDMP_G2(TB, 1, MODE); break;      \

@@ -75,4 +75,50 @@ __device__ __forceinline__ f32x4_t mfma16_x6(const bf16x8_t &a1, const bf16x8_t 
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc, 0, 0, 0);
 }
 
+// ---- two-part FP16 splits (for operands whose range has been brought inside FP16's) ----
+//
+// v = h1 + h2 + r with both parts FP16 rounded to nearest even: |h2| <= 2^-11 |v| and
+// |r| <= max(2^-22 |v|, 2^-25), 2^-25 being half the FP16 subnormal spacing, for any
+// |v| <= 65504.  The residual v - h1 is exact in FP32.  Of the four products of two split operands the three with h1 are kept:
+// the dropped h2 g2 is below 2^-22 of the product, so a product carries at most
+// 3 x 2^-22 of its magnitude, and the FP16 products are exact in the FP32
+// accumulator.  Values above 65504 overflow: callers scale both operands by powers
+// of two first.
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+
+// The residual v - h1 is one v_fma_mix_f32 (h1 read as FP16 from its half of the
+// packed register, times -1 from a register, plus v; exact), which the compiler forms
+// for only some of the values by itself.
+__device__ __forceinline__ void split2h(const float (&v)[8], f16x8_t &p1, f16x8_t &p2) {
+    float neg1 = -1.0f;
+    asm volatile("" : "+v"(neg1));  // a register operand: no inline constant in the mix
+#pragma unroll
+    for (int j = 0; j < 8; j += 2) {
+        const f32x2_t a = {v[j], v[j + 1]};
+        const f16x2_t h = __builtin_convertvector(a, f16x2_t);
+        float r0, r1;
+        asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[1,0,0]"
+            : "=v"(r0) : "v"(h), "v"(neg1), "v"(v[j]));
+        asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+            : "=v"(r1) : "v"(h), "v"(neg1), "v"(v[j + 1]));
+        const f32x2_t r = {r0, r1};
+        const f16x2_t l = __builtin_convertvector(r, f16x2_t);
+        p1[j] = h[0];
+        p1[j + 1] = h[1];
+        p2[j] = l[0];
+        p2[j + 1] = l[1];
+    }
+}
+
+// acc += (a1 + a2)(b1 + b2) less a2 b2 on v_mfma_f32_32x32x16_f16 (the bf16 layout
+// above), smallest product first.
+__device__ __forceinline__ f32x16_t mfma_h3(const f16x8_t &a1, const f16x8_t &a2,
+                                            const f16x8_t &b1, const f16x8_t &b2,
+                                            f32x16_t acc) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a2, b1, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, b2, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, b1, acc, 0, 0, 0);
+}
+
 }  // namespace pdmp

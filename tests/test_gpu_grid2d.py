@@ -1,5 +1,6 @@
-"""GPU parity of the grid-factorised 2-D path (FP32 MFMA) against the oracle's
-pairwise definition, with the same condition-aware tolerances as the pairwise path."""
+"""GPU parity of the grid-factorised 2-D path (FP32-accurate split contractions on the
+matrix cores) against the oracle's pairwise definition, with the same condition-aware
+tolerances as the pairwise path."""
 import numpy as np
 import pytest
 
@@ -89,9 +90,10 @@ def test_grid_morph_config1_full_and_deterministic():
 
 
 def test_grid_split_precision_wide_range():
-    """The contractions run on three-way bf16 splits: weights over six decades with
-    random signs and samples up to 8 lengthscales outside the grid (every feature
-    tiny but normal in FP32) still meet the FP32 tolerance of the absolute sums.
+    """Weights over six decades (wider than the FP16 scheme's 2^-19, so the three-way
+    bf16 splits run) with random signs and samples up to 8 lengthscales outside the
+    grid (every feature tiny but normal in FP32) still meet the FP32 tolerance of the
+    absolute sums.
     Weights stay below 10 so that sigma' stays a normal FP32 number."""
     require_gpu()
     rng = np.random.default_rng(2108)
@@ -114,6 +116,59 @@ def test_grid_split_precision_wide_range():
     _, g_r, _, gabs = O.occ_grad(oo, x)
     assert np.all(np.abs(host(s) - s_r) <= TOL * sabs)
     assert np.all(np.abs(host(g) - g_r).max(axis=0) <= TOL * gabs)
+
+
+def _wide_case(rng, g0, g1, ell, ax, ay, log2_range):
+    j = np.arange(g0 * g1)
+    h = np.stack([ax[j % g0], ay[j // g0]]).astype(np.float32)
+    mag = 10.0 * 2.0 ** rng.uniform(-log2_range, 0, g0 * g1 + 1)
+    wb = (mag * rng.choice([-1.0, 1.0], g0 * g1 + 1)).astype(np.float32)
+    wb[-1] = 0.0
+    lo, hi = ax.min(), ax.max()
+    far = np.stack([rng.uniform(lo - 8 * ell, hi + 8 * ell, 500),
+                    rng.uniform(ay.min() - 8 * ell, ay.max() + 8 * ell, 500)])
+    x = np.concatenate([rng.uniform(lo - 0.2, hi + 0.2, (2, 500)), far], axis=1).astype(np.float32)
+    go = _grid_occ(h, wb, ell, g0, g1)
+    # evaluations of 2^17 samples or more may take the FP16 scheme (smaller ones keep
+    # the bf16 splits): the points are tiled past that, the first copy checked
+    xt = dev(np.ascontiguousarray(np.tile(x, (1, 132))))
+    s = host(P.occupancy_eval(go, xt)[1])[:1000]
+    g = host(P.occupancy_grad(go, xt)[1])[:, :1000]
+    oo = oracle_occ(h, wb, ell)
+    s_r, _, sabs = O.occ_eval(oo, x)
+    _, g_r, _, gabs = O.occ_grad(oo, x)
+    assert np.all(np.abs(s - s_r) <= TOL * sabs)
+    assert np.all(np.abs(g - g_r).max(axis=0) <= TOL * gabs)
+    # small evaluations (bf16 splits) agree to the same tolerance
+    _, s2 = P.occupancy_eval(go, dev(x))
+    assert np.all(np.abs(host(s2) - s_r) <= TOL * sabs)
+    xi = x[:, :500]
+    out = host(P.morph_samples(go, dev(xi), 10, 0.002))
+    ref, amp, _, _ = O.morph_ws(oo, xi, 10, 0.002, diag=True)
+    err = np.abs(out - ref).max(axis=0)
+    assert np.all(err <= TOL * np.maximum(1, amp) * np.maximum(1, np.abs(ref).max(axis=0)))
+
+
+def test_grid_fp16_scheme_range_edge():
+    """The FP16 split scheme at the edge of its range: nonzero weights down to 2^-18.9 of
+    the largest (the scheme takes 2^-19), random signs, samples up to 8 lengthscales
+    outside the grid, where each sample's operand scale 2^c carries the features that
+    FP16 alone could not hold."""
+    require_gpu()
+    rng = np.random.default_rng(1619)
+    g0, g1, ell = 64, 48, 0.3
+    _wide_case(rng, g0, g1, ell, np.linspace(-3, 3, g0).astype(np.float32),
+               np.linspace(-2, 2, g1).astype(np.float32), 18.9)
+
+
+def test_grid_bf16_fallback_gapped_axis():
+    """A hinge x-axis with a gap of 3 (10 lengthscales, above the FP16 scheme's 6 kappa
+    units) takes the three-part bf16 splits; weights within the FP16 range."""
+    require_gpu()
+    rng = np.random.default_rng(1620)
+    g0, g1, ell = 40, 30, 0.3
+    ax = np.r_[np.linspace(-3, -1.5, 20), np.linspace(1.5, 3, 20)].astype(np.float32)
+    _wide_case(rng, g0, g1, ell, ax, np.linspace(-2, 2, g1).astype(np.float32), 10.0)
 
 
 def test_grid_large_batch_ragged_grid_sampled():
