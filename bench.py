@@ -46,8 +46,8 @@ FLOPS_PER_PAIR = {2: 12, 3: 17}    # 5*dim + 2 algorithmic FP32 flops per sample
 # while the kernel's sources (grid2d.hip and the headers it includes) are the ones
 # the counters were taken on.
 GRID2D_SOURCES = ("grid2d.hip", "mfma_split.h", "pdmp_common.h")
-GRID2D_TRAFFIC = {"bytes": (4274.0 * 2.0 + 8192.0) * 1024,
-                  "sha256": "4b165a9b9e6834fbe39c9b9f96a858c1810b059f7cbac054a023080dce796cc8"}
+GRID2D_TRAFFIC = {"bytes": (4272.0 * 2.0 + 8192.0) * 1024,
+                  "sha256": "70362d51bce7f908b005a3ea6fea3d6d3d9808e3c442bad7114155ab3587fae7"}
 
 
 def grid2d_sources_sha():
@@ -61,6 +61,24 @@ def grid2d_sources_sha():
 
 def grid2d_traffic():
     return GRID2D_TRAFFIC["bytes"] if grid2d_sources_sha() == GRID2D_TRAFFIC["sha256"] else None
+
+
+def split_scheme(x_axis, weights, ell):
+    """The split scheme the grid morph kernels take for these operands (each block of
+    the kernel decides the same from the same data): two-part FP16 splits, three
+    products, when every nonzero |w| is at least 2^-19 of the largest and no two
+    consecutive hinge x-coordinates are more than 6 apart in kappa units; three-part
+    BF16 splits, six products, otherwise."""
+    import numpy as np
+    w = np.abs(np.asarray(weights, dtype=np.float32))
+    kappa = np.float32(np.sqrt(np.log2(np.e) / 2.0) / ell)
+    g = np.unique(kappa * np.asarray(x_axis, dtype=np.float32))
+    ok = bool(np.all(np.isfinite(w)) and np.all(np.isfinite(g)))
+    if ok and len(g) > 1:
+        ok = float(np.diff(g).max()) <= 6.0
+    if ok and w.max() > 0:
+        ok = float(w[w > 0].min()) >= float(w.max()) * 2.0 ** -19
+    return ("fp16", 3) if ok else ("bf16", 6)
 
 
 def alu_peak_tflops(dim):
@@ -196,18 +214,21 @@ def headline(args, P, I, K, torch, dev):
     if occ.grid:
         # own algorithmic work of the factorised evaluation, per sample and step: two
         # G1 x G0 matrix-vector products (4 G0 G1 FP32 flops), each FP32 multiply-add
-        # carried out as three FP16 products of two-part splits (12 G0 G1 FP16 flops;
-        # this workload's weights and hinges are inside the FP16 scheme's range)
+        # carried out as the split scheme's products (three FP16 or six BF16)
+        scheme, nprod = split_scheme(occ.hinges[0, :G0].cpu().numpy(),
+                                     occ.weights[:-1].cpu().numpy(), occ.lengthscale)
         fp32_tf = N * cfg.T * 4.0 * G0 * G1 / (morph_ms * 1e-3) / 1e12
-        achieved = 3.0 * fp32_tf
-        res["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK_F16_MFMA / 1e12,
-                           "unit": "TFLOP/s", "frac": achieved * 1e12 / PEAK_F16_MFMA,
+        achieved = nprod * fp32_tf
+        peak = PEAK_F16_MFMA if scheme == "fp16" else PEAK_BF16_MFMA
+        res["scheme"] = scheme
+        res["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak / 1e12,
+                           "unit": "TFLOP/s", "frac": achieved * 1e12 / peak,
                            "traffic": grid2d_traffic(), "kernel": "k_grid2d_mfma<2,4,kMorph>",
-                           "kernel_ms": morph_ms,
-                           "work": "12*G0*G1 FP16 MFMA flops per sample-step (64x64 grid): the "
-                                   "two FP32 contractions (4*G0*G1 flops) as the three leading "
-                                   "FP16 products of two-part splits of power-of-two-scaled "
-                                   "operands",
+                           "kernel_ms": morph_ms, "split_scheme": scheme,
+                           "work": f"{4 * nprod}*G0*G1 {scheme.upper()} MFMA flops per "
+                                   "sample-step (64x64 grid): the two FP32 contractions "
+                                   f"(4*G0*G1 flops) as the {nprod} leading products of the "
+                                   f"{scheme.upper()} splits",
                            "fp32_equivalent_tflops": fp32_tf,
                            "fp32_equivalent_frac_of_fp32_mfma_peak": fp32_tf * 1e12 / PEAK_FP32_MFMA,
                            "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE + "
@@ -307,21 +328,24 @@ def arm_morph(P, I, K, torch, world):
     _, h0 = P.label_configs(arm, *world["boxes"], q0, count=True)
     _, h1 = P.label_configs(arm, *world["boxes"], q1, count=True)
     # own work of the factorised evaluation per body point and step: two (16*16) x 16
-    # matrix-vector products = 4 * 4096 FP32 flops, each multiply-add as six BF16
-    # products of three-way splits = 24 * 4096 BF16 MFMA flops
+    # matrix-vector products = 4 * 4096 FP32 flops, each multiply-add as the split
+    # scheme's products (three FP16 or six BF16)
+    scheme, nprod = split_scheme(occ.hinges[0, :c3.grid].cpu().numpy(),
+                                 occ.weights[:-1].cpu().numpy(), occ.lengthscale)
+    peak = PEAK_F16_MFMA if scheme == "fp16" else PEAK_BF16_MFMA
     fp32_tf = c3.n_samples * c3.T * c3.n_body * 4.0 * c3.n_hinges / (ms * 1e-3) / 1e12
-    ach = 6.0 * fp32_tf
+    ach = nprod * fp32_tf
     res = {"workload": "plain morph 7-DOF arm: 65,536 configurations, 56 body points, 16^3 "
                        "hinges, l=0.15, T=30, eta=0.01, 40 boxes",
            "morph_ms": ms, "samples_per_s": c3.n_samples / (ms * 1e-3),
            "collision_free_before": 1 - h0.item() / c3.n_samples,
            "collision_free_after": 1 - h1.item() / c3.n_samples,
-           "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_MFMA / 1e12,
-                        "unit": "TFLOP/s", "frac": ach * 1e12 / PEAK_BF16_MFMA,
-                        "kernel": "k_arm_grid3d<7,16,16,true>",
-                        "work": "24*M BF16 MFMA flops per body point and step (the two FP32 "
-                                "contractions, 4*M flops, as six BF16 products of three-way "
-                                "splits)",
+           "roofline": {"bound": "mfma", "achieved": ach, "peak": peak / 1e12,
+                        "unit": "TFLOP/s", "frac": ach * 1e12 / peak,
+                        "kernel": "k_arm_grid3d<7,16,16,true>", "split_scheme": scheme,
+                        "work": f"{4 * nprod}*M {scheme.upper()} MFMA flops per body point "
+                                "and step (the two FP32 contractions, 4*M flops, as the "
+                                f"{nprod} leading products of the {scheme.upper()} splits)",
                         "fp32_equivalent_tflops": fp32_tf}}
     dense = P.Occupancy(occ.hinges, occ.weights, occ.lengthscale)
     P.morph_samples(dense, q0, c3.T, c3.eta, arm=arm, out=q1)
@@ -690,7 +714,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f16x3",
+        "dtype": "f32+" + {"fp16": "f16x3", "bf16": "bf16x6"}.get(hl.get("scheme"), "f32"),
         "data": "synthetic (seeded disc world, Philox prior samples, occupancy fitted on the GPU)",
         "config": {"workload": "plain morph 2-D large: 1,048,576 samples, 64x64 hinges, "
                                "l=0.4, T=50, eta=0.02, 100 discs",

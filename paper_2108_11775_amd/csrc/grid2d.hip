@@ -26,8 +26,8 @@ constexpr int kG2Block = 256;   // 4 waves, 32 samples each
 
 // The contractions run at FP32 accuracy on the matrix cores, on one of two split
 // schemes chosen per launch from the operands' range (every block reaches the same
-// choice from the same weights and hinges; morphs and batches of 2^17 samples or more
-// only -- a smaller single evaluation keeps the BF16 scheme and skips the check):
+// choice from the same weights and hinges; morphs only -- a single evaluation keeps
+// the BF16 scheme and skips the check):
 //  * FP16 (two-part splits, three products; mfma_split.h) when FP16's exponent range
 //    can hold the operands after power-of-two scaling: W is scaled so that
 //    2^14 <= max|W| < 2^15, and every nonzero |W| is at least 2^-19 max|W| (its two
@@ -144,7 +144,10 @@ template <int TB, int KS, int MODE>
 __global__ void __launch_bounds__(kG2Block) __attribute__((amdgpu_waves_per_eu(2)))
 k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
               float kappa, float gscale, const float *x_in, int64_t n, int T, float eta,
-              int allow_fp16, float *c_out, float *s_out, float *g_out, float *x_out) {
+              float *c_out, float *s_out, float *g_out, float *x_out) {
+    // the FP16 scheme's per-block range check pays off over a morph's steps; a single
+    // evaluation, whose blocks mostly stage W, keeps the BF16 scheme without it
+    constexpr bool allow_fp16 = MODE == kMorph;
     // fragments, BF16 scheme: frag[(p * KS + ks) * TB + t][lane] = part p < 3 of
     //   W[b = 32t + lane%32][a = 16ks + 8(lane/32) + j], j < 8 (0 outside the grid);
     // FP16 scheme: the same with parts p < 2 of 2^sW W
@@ -217,7 +220,7 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
             rg.gap = gap;
         }
     }
-    __syncthreads();
+    if (allow_fp16) __syncthreads();  // otherwise the staging's own barrier below serves
     // FP16 scheme: finite weights within 2^-19 of their largest magnitude (or all zero),
     // finite hinge x-range, no x-gap above kG2MaxGap
     int sw = 0;
@@ -252,7 +255,7 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
     const int steps = MODE == kMorph ? T : 1;
     float s = 0.0f, sx = 0.0f, sy = 0.0f;
 
-    if (fp16) {
+    if (allow_fp16 && fp16) {
         f16x8_t *frag = reinterpret_cast<f16x8_t *>(fraw);
 #pragma unroll
         for (int it = 0; it < kNI; ++it) {
@@ -523,13 +526,10 @@ int32_t launch_grid2d(int mode, const RbfArgs &a, int g0, int g1, hipStream_t st
     if (a.n < kG2SmallBatch && mode == kMorph && a.T > 1) return launch_grid2d_small(a, g0, g1, st);
     const int64_t blocks = (a.n + 127) / 128;
     const dim3 grid((unsigned)blocks), blk(kG2Block);
-    // the FP16 scheme's per-block range check pays off over a morph's T steps or a
-    // large batch; a small single evaluation keeps the BF16 scheme without the check
-    const int allow16 = mode == kMorph || a.n >= kG2SmallBatch;
 #define PDMP_G2(TB, KS, MODE)                                                                  \
     hipLaunchKernelGGL((k_grid2d_mfma<TB, KS, MODE>), grid, blk, 0, st, a.hinges, a.weights, g0, \
-                       g1, a.kappa, a.gscale, a.x_in, a.n, a.T, a.eta, allow16, a.c_out,        \
-                       a.s_out, a.g_out, a.x_out)
+                       g1, a.kappa, a.gscale, a.x_in, a.n, a.T, a.eta, a.c_out, a.s_out,        \
+                       a.g_out, a.x_out)
 #define PDMP_G2_KS(TB, MODE)                      \
     switch ((g0 + 15) / 16) {                     \
         case 1: PDMP_G2(TB, 1, MODE); break;      \

@@ -1,6 +1,6 @@
 // grid3d.hip -- occupancy, joint-space morph and body-point check for hinges on a
 // regular 3-D grid with 16 points on the y axis, as dense contractions on the matrix
-// cores (BF16 MFMA at FP32 accuracy, mfma_split.h).
+// cores (FP16 or BF16 MFMA at FP32 accuracy, mfma_split.h).
 //
 // With hinges h_{a + G0 (b + 16 c)} = (X_a, Y_b, Z_c) the feature factorises,
 // phi = ex_a ey_b ez_c, so with rows r = b + 16 c of W[r][a] = w_{a + G0 r}
@@ -12,8 +12,9 @@
 // the same s and grad s as the pairwise sum (rounding aside) for G0 + 16 + G2
 // exponentials and two (16 G2) x G0 matrix-vector products per point.  32 points
 // per wave go through v_mfma_f32_32x32x16_bf16 (A = W rows, B = [ex | ex dx] of the
-// lane's own point, k = a, G0 = 16 in one k-step; three-way bf16 splits of both, six
-// products per contraction); each 32-row tile holds two z-planes (c = 2t, 2t+1), so
+// lane's own point, k = a, G0 = 16 in one k-step; two-part FP16 splits of both, three
+// products per contraction, or three-way bf16 splits and six products when the
+// operands' range needs FP32's exponent range); each 32-row tile holds two z-planes (c = 2t, 2t+1), so
 // in the accumulator layout lane l owns the fixed y indices b = (8(v/4) + 4(l/32)
 // + v%4) mod 16 and the y/z contractions need only per-lane tables of ey and ez.
 // The two lanes of a point are summed by one xor-32 exchange (bit-identical).
@@ -27,46 +28,186 @@
 namespace pdmp {
 
 constexpr int kG3Y = 16;  // points on the y axis (two z-planes per 32-row MFMA tile)
+constexpr int kG3Block = 256;
+
+// The x contraction runs on one of two split schemes, chosen in every block from the
+// same weights and hinges (the rules of the 2-D grid kernel): FP16 two-part splits
+// (three products) when every nonzero |W| is at least 2^-19 of the largest and no two
+// consecutive hinge x-coordinates are more than 6 apart in kappa units -- W scaled
+// to [2^14, 2^15), each point's x-side operands by 2^c from its distance to the hinge
+// x-range, the sums scaled back with ldexp -- and three-part bf16 splits (six
+// products) otherwise or where the caller does not allow the check.
+constexpr int kG3RangeLog2 = 19;
+constexpr float kG3MaxGap = 6.0f;
 
 template <int G0, int G2>
 struct G3 {
     static_assert(G0 == 16, "G0 = 16: one 16-wide k-step");
     static_assert(G2 % 2 == 0 && G2 <= 32, "G2 even, <= 32");
     static constexpr int TB = kG3Y * G2 / 32;  // 32-row tiles
-    static constexpr int FRAG = 3 * TB * 64;   // bf16x8 fragments: 3 parts x TB tiles
+    static constexpr int FRAG = 3 * TB * 64;   // 16-byte fragments: up to 3 parts x TB tiles
 };
 
+struct G3Range {
+    uint32_t wmax[kG3Block / 64], wmin[kG3Block / 64];
+    float gmin, gmax, gap;
+};
+
+// The block's scheme: FP16 parts with W scaled by 2^sw and the hinge x-range
+// [gmin, gmax] (kappa units), or BF16 parts.
+struct G3Scheme {
+    int fp16, sw;
+    float gmin, gmax;
+};
+
+__device__ __forceinline__ uint32_t g3_wave_max(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return v;
+}
+__device__ __forceinline__ uint32_t g3_wave_min(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return v;
+}
+
 // Stage W fragments (frag[(p*TB + t)*64 + lane] = part p of W[32t + lane%32][8(lane/32)
-// + j], j < 8) and the prescaled axes into LDS.
+// + j], j < 8) and the prescaled axes into LDS, choosing the scheme.  All kG3Block
+// threads call it; the caller synchronises before reading the fragments.
 template <int G0, int G2>
-__device__ __forceinline__ void g3_stage(bf16x8_t *frag, float *ax, float *ay, float *az,
-                                         const float *__restrict__ hinges,
-                                         const float *__restrict__ weights, float kappa) {
+__device__ __forceinline__ G3Scheme g3_stage(uint4 *fraw, float *ax, float *ay, float *az,
+                                             G3Range &rg, const float *__restrict__ hinges,
+                                             const float *__restrict__ weights, float kappa,
+                                             bool allow16) {
     using C = G3<G0, G2>;
     constexpr int M = G0 * kG3Y * G2;
-    for (int idx = threadIdx.x; idx < C::TB * 64; idx += blockDim.x) {
-        const int ln = idx & 63, t = idx >> 6;
-        const int r = 32 * t + (ln & 31);
-        float v[8];
+    if (!allow16) {
+        // BF16 parts straight from global memory, no range check
+        bf16x8_t *frag = reinterpret_cast<bf16x8_t *>(fraw);
+        for (int idx = threadIdx.x; idx < C::TB * 64; idx += kG3Block) {
+            const int ln = idx & 63, t = idx >> 6;
+            const int r = 32 * t + (ln & 31);
+            float v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = weights[8 * (ln >> 5) + j + G0 * r];
-        bf16x8_t p1, p2, p3;
-        split3(v, p1, p2, p3);
-        frag[(0 * C::TB + t) * 64 + ln] = p1;
-        frag[(1 * C::TB + t) * 64 + ln] = p2;
-        frag[(2 * C::TB + t) * 64 + ln] = p3;
+            for (int j = 0; j < 8; ++j) v[j] = weights[8 * (ln >> 5) + j + G0 * r];
+            bf16x8_t p1, p2, p3;
+            split3(v, p1, p2, p3);
+            frag[(0 * C::TB + t) * 64 + ln] = p1;
+            frag[(1 * C::TB + t) * 64 + ln] = p2;
+            frag[(2 * C::TB + t) * 64 + ln] = p3;
+        }
+        for (int i = threadIdx.x; i < G0; i += kG3Block) ax[i] = kappa * hinges[i];
+        for (int i = threadIdx.x; i < kG3Y; i += kG3Block) ay[i] = kappa * hinges[M + G0 * i];
+        for (int i = threadIdx.x; i < G2; i += kG3Block)
+            az[i] = kappa * hinges[2 * M + G0 * kG3Y * i];
+        return G3Scheme{0, 0, 0.0f, 0.0f};
     }
-    for (int i = threadIdx.x; i < G0; i += blockDim.x) ax[i] = kappa * hinges[i];
-    for (int i = threadIdx.x; i < kG3Y; i += blockDim.x) ay[i] = kappa * hinges[M + G0 * i];
-    for (int i = threadIdx.x; i < G2; i += blockDim.x) az[i] = kappa * hinges[2 * M + G0 * kG3Y * i];
+    constexpr int NI = (C::TB * 64 + kG3Block - 1) / kG3Block;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float w8[NI][8];
+    uint32_t mx = 0, mn = 0xffffffffu;
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int idx = threadIdx.x + it * kG3Block;
+        const int ln = idx & 63, r = 32 * (idx >> 6) + (ln & 31);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float w = idx < C::TB * 64 ? weights[8 * (ln >> 5) + j + G0 * r] : 0.0f;
+            w8[it][j] = w;
+            const uint32_t u = __float_as_uint(w) & 0x7fffffffu;
+            mx = max(mx, u);
+            if (u != 0) mn = min(mn, u);
+        }
+    }
+    {
+        mx = g3_wave_max(mx);
+        mn = g3_wave_min(mn);
+        if (lane == 0) {
+            rg.wmax[wv] = mx;
+            rg.wmin[wv] = mn;
+        }
+        if (wv == 0) {
+            // one hinge x-coordinate per lane; the next larger one of each by a scan
+            const bool act = lane < G0;
+            const float g = act ? kappa * hinges[lane] : 0.0f;
+            float lo = act ? g : INFINITY, hi = act ? g : -INFINITY, nxt = INFINITY;
+#pragma unroll
+            for (int b = 0; b < G0; ++b) {
+                const float o = __builtin_bit_cast(
+                    float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, g), b));
+                if (o > g) nxt = fminf(nxt, o);
+            }
+            float gap = act && nxt < INFINITY ? nxt - g : 0.0f;
+            if (act && !(g == g)) gap = INFINITY;  // a NaN coordinate fails the check
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                lo = fminf(lo, __shfl_xor(lo, off, 64));
+                hi = fmaxf(hi, __shfl_xor(hi, off, 64));
+                gap = fmaxf(gap, __shfl_xor(gap, off, 64));
+            }
+            if (lane == 0) {
+                rg.gmin = lo;
+                rg.gmax = hi;
+                rg.gap = gap;
+            }
+        }
+    }
+    for (int i = threadIdx.x; i < G0; i += kG3Block) ax[i] = kappa * hinges[i];
+    for (int i = threadIdx.x; i < kG3Y; i += kG3Block) ay[i] = kappa * hinges[M + G0 * i];
+    for (int i = threadIdx.x; i < G2; i += kG3Block) az[i] = kappa * hinges[2 * M + G0 * kG3Y * i];
+    __syncthreads();
+    G3Scheme sc = {0, 0, 0.0f, 0.0f};
+    {
+        uint32_t wmx = rg.wmax[0], wmn = rg.wmin[0];
+#pragma unroll
+        for (int w = 1; w < kG3Block / 64; ++w) {
+            wmx = max(wmx, rg.wmax[w]);
+            wmn = min(wmn, rg.wmin[w]);
+        }
+        sc.gmin = rg.gmin;
+        sc.gmax = rg.gmax;
+        bool ok = wmx < 0x7f800000u && rg.gap <= kG3MaxGap && sc.gmax - sc.gmin < INFINITY;
+        if (ok && wmx != 0) {
+            int e;
+            (void)frexpf(__uint_as_float(wmx), &e);  // max|W| = f 2^e, f in [0.5, 1)
+            sc.sw = 15 - e;
+            ok = __uint_as_float(wmn) >= ldexpf(__uint_as_float(wmx), -kG3RangeLog2);
+        }
+        sc.fp16 = __builtin_amdgcn_readfirstlane((int)ok);
+    }
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int idx = threadIdx.x + it * kG3Block;
+        if (idx >= C::TB * 64) break;
+        const int ln = idx & 63, t = idx >> 6;
+        if (sc.fp16) {
+            f16x8_t *frag = reinterpret_cast<f16x8_t *>(fraw);
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = ldexpf(w8[it][j], sc.sw);
+            f16x8_t p1, p2;
+            split2h(v, p1, p2);
+            frag[(0 * C::TB + t) * 64 + ln] = p1;
+            frag[(1 * C::TB + t) * 64 + ln] = p2;
+        } else {
+            bf16x8_t *frag = reinterpret_cast<bf16x8_t *>(fraw);
+            bf16x8_t p1, p2, p3;
+            split3(w8[it], p1, p2, p3);
+            frag[(0 * C::TB + t) * 64 + ln] = p1;
+            frag[(1 * C::TB + t) * 64 + ln] = p2;
+            frag[(2 * C::TB + t) * 64 + ln] = p3;
+        }
+    }
+    return sc;
 }
 
 // s (without beta) and, with GRAD, the unscaled logit-gradient sums (sx, sy, sz) at the
-// prescaled point (xs, ys, zs) this lane shares with its xor-32 partner.
-template <int G0, int G2, bool GRAD>
-__device__ __forceinline__ void g3_point(const bf16x8_t *frag, const float *ax, const float *ay,
-                                         const float *az, float xs, float ys, float zs, float &s,
-                                         float &sx, float &sy, float &sz) {
+// prescaled point (xs, ys, zs) this lane shares with its xor-32 partner, on the
+// block's split scheme (F16 = sc.fp16).
+template <int G0, int G2, bool GRAD, bool F16>
+__device__ __forceinline__ void g3_point(const uint4 *fraw, const G3Scheme &sc, const float *ax,
+                                         const float *ay, const float *az, float xs, float ys,
+                                         float zs, float &s, float &sx, float &sy, float &sz) {
     using C = G3<G0, G2>;
     const int lane0 = threadIdx.x & 63, h = lane0 >> 5;
     // The weight fragments are the same at every call; an opaque copy of the lane
@@ -75,16 +216,32 @@ __device__ __forceinline__ void g3_point(const bf16x8_t *frag, const float *ax, 
     int lane = lane0;
     asm volatile("" : "+v"(lane));
     bf16x8_t e1, e2, e3, d1, d2, d3;
+    f16x8_t h1, h2, k1, k2;
+    int c = 0;  // FP16 scheme: this point's operand scale 2^c
     {
+        float cf = 0.0f;
+        if (F16) {
+            const float dist = fmaxf(fmaxf(sc.gmin - xs, xs - sc.gmax), 0.0f);
+            const float m = floorf(fminf(dist * dist, 256.0f));
+            int k;
+            (void)frexpf(dist, &k);  // dist < 2^k
+            c = 15 - max(k, 0) + (int)m;
+            cf = (float)c;
+        }
         float e[8], de[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const float d = xs - ax[8 * h + j];
-            e[j] = exp2_fast(-d * d);
+            e[j] = exp2_fast(F16 ? fmaf(-d, d, cf) : -d * d);
             de[j] = e[j] * d;
         }
-        split3(e, e1, e2, e3);
-        if (GRAD) split3(de, d1, d2, d3);
+        if (F16) {
+            split2h(e, h1, h2);
+            if (GRAD) split2h(de, k1, k2);
+        } else {
+            split3(e, e1, e2, e3);
+            if (GRAD) split3(de, d1, d2, d3);
+        }
     }
     float ey[8], dey[8];  // the lane's 8 distinct y indices
 #pragma unroll
@@ -107,31 +264,40 @@ __device__ __forceinline__ void g3_point(const bf16x8_t *frag, const float *ax, 
         }
         // one k-step (G0 = 16) from the zero accumulator
         const f32x16_t zero = {};
-        const bf16x8_t a1 = frag[(0 * C::TB + t) * 64 + lane];
-        const bf16x8_t a2 = frag[(1 * C::TB + t) * 64 + lane];
-        const bf16x8_t a3 = frag[(2 * C::TB + t) * 64 + lane];
-        const f32x16_t U = mfma_x6(a1, a2, a3, e1, e2, e3, zero);
-        f32x16_t V;
-        if (GRAD) V = mfma_x6(a1, a2, a3, d1, d2, d3, zero);
+        f32x16_t U, V;
+        if (F16) {
+            const f16x8_t *frag = reinterpret_cast<const f16x8_t *>(fraw);
+            const f16x8_t a1 = frag[(0 * C::TB + t) * 64 + lane];
+            const f16x8_t a2 = frag[(1 * C::TB + t) * 64 + lane];
+            U = mfma_h3(a1, a2, h1, h2, zero);
+            if (GRAD) V = mfma_h3(a1, a2, k1, k2, zero);
+        } else {
+            const bf16x8_t *frag = reinterpret_cast<const bf16x8_t *>(fraw);
+            const bf16x8_t a1 = frag[(0 * C::TB + t) * 64 + lane];
+            const bf16x8_t a2 = frag[(1 * C::TB + t) * 64 + lane];
+            const bf16x8_t a3 = frag[(2 * C::TB + t) * 64 + lane];
+            U = mfma_x6(a1, a2, a3, e1, e2, e3, zero);
+            if (GRAD) V = mfma_x6(a1, a2, a3, d1, d2, d3, zero);
+        }
         // row i = 8(v/4) + 4h + v%4 of tile t: b = i mod 16 (table slot v%8), c = 2t + v/8;
         // the y sums of each z-plane first, then one ez (dez) factor per plane
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int cz = 0; cz < 2; ++cz) {
             float py = 0.0f, pyx = 0.0f, pdy = 0.0f;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int v = 8 * c + u;
+                const int v = 8 * cz + u;
                 py = fmaf(ey[u], U[v], py);
                 if (GRAD) {
                     pyx = fmaf(ey[u], V[v], pyx);
                     pdy = fmaf(dey[u], U[v], pdy);
                 }
             }
-            s = fmaf(ez[c], py, s);
+            s = fmaf(ez[cz], py, s);
             if (GRAD) {
-                sx = fmaf(ez[c], pyx, sx);
-                sy = fmaf(ez[c], pdy, sy);
-                sz = fmaf(dez[c], py, sz);
+                sx = fmaf(ez[cz], pyx, sx);
+                sy = fmaf(ez[cz], pdy, sy);
+                sz = fmaf(dez[cz], py, sz);
             }
         }
     }
@@ -141,30 +307,33 @@ __device__ __forceinline__ void g3_point(const bf16x8_t *frag, const float *ax, 
         sy += __shfl_xor(sy, 32, 64);
         sz += __shfl_xor(sz, 32, 64);
     }
+    if (F16) {
+        const int un = -(sc.sw + c);
+        s = ldexpf(s, un);
+        if (GRAD) {
+            sx = ldexpf(sx, un);
+            sy = ldexpf(sy, un);
+            sz = ldexpf(sz, un);
+        }
+    }
 }
 
 // ---- workspace points [3][n]: eval / grad / morph, 32 points per wave ----
-template <int G0, int G2, int MODE>
-__global__ void __launch_bounds__(256)
-k_grid3d_ws(const float *__restrict__ hinges, const float *__restrict__ weights, float kappa,
-            float gscale, const float *x_in, int64_t n, int T, float eta, float *c_out,
-            float *s_out, float *g_out, float *x_out) {
-    using C = G3<G0, G2>;
-    __shared__ bf16x8_t frag[C::FRAG];
-    __shared__ float ax[G0], ay[kG3Y], az[G2];
-    g3_stage<G0, G2>(frag, ax, ay, az, hinges, weights, kappa);
-    __syncthreads();
-    constexpr int M = G0 * kG3Y * G2;
+template <int G0, int G2, int MODE, bool F16>
+__device__ __forceinline__ void g3_ws_body(const uint4 *fraw, const G3Scheme &sc, const float *ax,
+                                           const float *ay, const float *az, float beta,
+                                           float kappa, float gscale, const float *x_in,
+                                           int64_t n, int T, float eta, float *c_out,
+                                           float *s_out, float *g_out, float *x_out) {
     const int lane = threadIdx.x & 63;
     const int64_t i = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32 + (lane & 31);
     const int64_t ic = i < n ? i : n - 1;
     float x = x_in[ic], y = x_in[(size_t)n + ic], z = x_in[2 * (size_t)n + ic];
-    const float beta = weights[M];
     float s, sx, sy, sz;
     const int steps = MODE == kMorph ? T : 1;
     for (int st = 0; st < steps; ++st) {
-        g3_point<G0, G2, MODE != kEval>(frag, ax, ay, az, kappa * x, kappa * y, kappa * z, s, sx,
-                                        sy, sz);
+        g3_point<G0, G2, MODE != kEval, F16>(fraw, sc, ax, ay, az, kappa * x, kappa * y,
+                                             kappa * z, s, sx, sy, sz);
         if (MODE == kMorph) {
             float c, sp;
             sigmoid_and_slope(s + beta, c, sp);
@@ -192,6 +361,30 @@ k_grid3d_ws(const float *__restrict__ hinges, const float *__restrict__ weights,
             g_out[2 * (size_t)n + i] = f * sz;
         }
     }
+}
+
+template <int G0, int G2, int MODE>
+__global__ void __launch_bounds__(kG3Block)
+k_grid3d_ws(const float *__restrict__ hinges, const float *__restrict__ weights, float kappa,
+            float gscale, const float *x_in, int64_t n, int T, float eta, float *c_out,
+            float *s_out, float *g_out, float *x_out) {
+    using C = G3<G0, G2>;
+    __shared__ uint4 fraw[C::FRAG];
+    __shared__ float ax[G0], ay[kG3Y], az[G2];
+    __shared__ G3Range rg;
+    // the range check pays off over a morph's steps; a single evaluation, whose blocks
+    // mostly stage W, keeps the BF16 scheme without it
+    const G3Scheme sc = g3_stage<G0, G2>(fraw, ax, ay, az, rg, hinges, weights, kappa,
+                                         MODE == kMorph);
+    __syncthreads();
+    constexpr int M = G0 * kG3Y * G2;
+    const float beta = weights[M];
+    if (MODE == kMorph && sc.fp16)
+        g3_ws_body<G0, G2, MODE, true>(fraw, sc, ax, ay, az, beta, kappa, gscale, x_in, n, T, eta,
+                                       c_out, s_out, g_out, x_out);
+    else
+        g3_ws_body<G0, G2, MODE, false>(fraw, sc, ax, ay, az, beta, kappa, gscale, x_in, n, T,
+                                        eta, c_out, s_out, g_out, x_out);
 }
 
 // FP32 DH chain (same convention as the pairwise arm kernel).
@@ -235,22 +428,14 @@ __device__ __forceinline__ float sum8(float v) {
 
 // ---- joint-space morph (MORPH) or largest body-point occupancy (check) ----
 // 4 configurations per wave; lane%32 = 8*cfg + k, body point k of every link.
-template <int NDOF, int G0, int G2, bool MORPH>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-k_arm_grid3d(pdmp_arm arm, const float *__restrict__ hinges, const float *__restrict__ weights,
-             float kappa, float gscale, const float *q_in, float *q_out, int64_t n, int T,
-             float eta, const uint32_t *__restrict__ n_active, float thresh, float *maxc_out,
-             uint8_t *flag_out) {
-    using C = G3<G0, G2>;
+template <int NDOF, int G0, int G2, bool MORPH, bool F16>
+__device__ __forceinline__ void arm_body(const pdmp_arm &arm, const uint4 *fraw,
+                                         const G3Scheme &sc, const float *ax, const float *ay,
+                                         const float *az, float *kin, float beta, float kappa,
+                                         float gscale, const float *q_in, float *q_out, int64_t n,
+                                         int64_t n_eff, int T, float eta, float thresh,
+                                         float *maxc_out, uint8_t *flag_out) {
     constexpr int KIN = 3 * (NDOF + 1) + 3 * NDOF + NDOF;  // o, z, grad_q per configuration
-    __shared__ bf16x8_t frag[C::FRAG];
-    __shared__ float ax[G0], ay[kG3Y], az[G2];
-    __shared__ float kin[16 * KIN];
-    const int64_t n_eff = n_active ? min((int64_t)*n_active, n) : n;
-    if ((int64_t)blockIdx.x * 16 >= n_eff) return;  // whole block idle (uniform)
-    g3_stage<G0, G2>(frag, ax, ay, az, hinges, weights, kappa);
-    __syncthreads();
-    constexpr int M = G0 * kG3Y * G2;
     const int lane = threadIdx.x & 63;
     const int k = lane & 7;
     const int slot = (threadIdx.x >> 6) * 4 + ((lane & 31) >> 3);  // configuration in block
@@ -264,7 +449,6 @@ k_arm_grid3d(pdmp_arm arm, const float *__restrict__ hinges, const float *__rest
     float q[NDOF];
 #pragma unroll
     for (int j = 0; j < NDOF; ++j) q[j] = q_in[(size_t)j * n + cs];
-    const float beta = weights[M];
 
     const int steps = MORPH ? T : 1;
     float mc = -1.0f;
@@ -296,8 +480,8 @@ k_arm_grid3d(pdmp_arm arm, const float *__restrict__ hinges, const float *__rest
                 p[e] = ol[e] + frac * (ko[3 * (l + 1) + e] - ol[e]);
             }
             float s, sx, sy, sz;
-            g3_point<G0, G2, MORPH>(frag, ax, ay, az, kappa * p[0], kappa * p[1], kappa * p[2], s,
-                                    sx, sy, sz);
+            g3_point<G0, G2, MORPH, F16>(fraw, sc, ax, ay, az, kappa * p[0], kappa * p[1],
+                                         kappa * p[2], s, sx, sy, sz);
             float c, sp;
             sigmoid_and_slope(s + beta, c, sp);
             if (MORPH) {
@@ -341,6 +525,36 @@ k_arm_grid3d(pdmp_arm arm, const float *__restrict__ hinges, const float *__rest
     }
 }
 
+template <int NDOF, int G0, int G2, bool MORPH>
+__global__ void __launch_bounds__(kG3Block) __attribute__((amdgpu_waves_per_eu(3)))
+k_arm_grid3d(pdmp_arm arm, const float *__restrict__ hinges, const float *__restrict__ weights,
+             float kappa, float gscale, const float *q_in, float *q_out, int64_t n, int T,
+             float eta, const uint32_t *__restrict__ n_active, float thresh, float *maxc_out,
+             uint8_t *flag_out) {
+    using C = G3<G0, G2>;
+    constexpr int KIN = 3 * (NDOF + 1) + 3 * NDOF + NDOF;  // o, z, grad_q per configuration
+    __shared__ uint4 fraw[C::FRAG];
+    __shared__ float ax[G0], ay[kG3Y], az[G2];
+    __shared__ float kin[16 * KIN];
+    __shared__ G3Range rg;
+    const int64_t n_eff = n_active ? min((int64_t)*n_active, n) : n;
+    if ((int64_t)blockIdx.x * 16 >= n_eff) return;  // whole block idle (uniform)
+    // the range check pays off over the T steps of a morph; the single check pass
+    // keeps the BF16 scheme
+    const G3Scheme sc = g3_stage<G0, G2>(fraw, ax, ay, az, rg, hinges, weights, kappa, MORPH);
+    __syncthreads();
+    constexpr int M = G0 * kG3Y * G2;
+    const float beta = weights[M];
+    if (MORPH && sc.fp16)
+        arm_body<NDOF, G0, G2, MORPH, true>(arm, fraw, sc, ax, ay, az, kin, beta, kappa, gscale,
+                                            q_in, q_out, n, n_eff, T, eta, thresh, maxc_out,
+                                            flag_out);
+    else
+        arm_body<NDOF, G0, G2, MORPH, false>(arm, fraw, sc, ax, ay, az, kin, beta, kappa, gscale,
+                                             q_in, q_out, n, n_eff, T, eta, thresh, maxc_out,
+                                             flag_out);
+}
+
 static bool g3_supported(const int *grid, int M) {
     return grid && grid[0] == 16 && grid[1] == kG3Y && grid[2] == 16 && M == 4096;
 }
@@ -348,7 +562,7 @@ static bool g3_supported(const int *grid, int M) {
 int32_t launch_grid3d_ws(int mode, const RbfArgs &a, const int *grid, hipStream_t st) {
     if (!g3_supported(grid, a.M) || (mode != kEval && mode != kGrad && mode != kMorph))
         return PDMP_EUNSUPPORTED;
-    const dim3 g((unsigned)((a.n + 127) / 128)), b(256);
+    const dim3 g((unsigned)((a.n + 127) / 128)), b(kG3Block);
 #define PDMP_G3(MODE)                                                                         \
     hipLaunchKernelGGL((k_grid3d_ws<16, 16, MODE>), g, b, 0, st, a.hinges, a.weights, a.kappa, \
                        a.gscale, a.x_in, a.n, a.T, a.eta, a.c_out, a.s_out, a.g_out, a.x_out)
@@ -364,7 +578,7 @@ int32_t launch_arm_grid3d(const pdmp_arm &arm, const float *h, const float *w, i
                           int64_t n, int T, float eta, const uint32_t *n_active, bool morph,
                           float thresh, float *maxc, uint8_t *flag, hipStream_t st) {
     if (!g3_supported(grid, M) || arm.pts_per_link > 8) return PDMP_EUNSUPPORTED;
-    const dim3 g((unsigned)((n + 15) / 16)), b(256);
+    const dim3 g((unsigned)((n + 15) / 16)), b(kG3Block);
     switch (arm.n_dof) {
 #define PDMP_CASE(N)                                                                            \
     case N:                                                                                     \

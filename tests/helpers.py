@@ -64,3 +64,24 @@ def oracle_occ(h, wb, ell):
 def gpu_occ(h, wb, ell, grid=None):
     import paper_2108_11775_amd as P
     return P.Occupancy(dev(h), dev(wb), ell, grid=grid)
+
+
+def one_step_grad_check(go, oo, x, tol=1e-5):
+    """One morph step x1 = x0 - eta grad c with eta G_abs between 1 and 10 (G_abs the
+    oracle's gradient error scale) resolves the gradient's error to the tolerance of
+    a single evaluation, tol G_abs, on whatever kernel path a morph takes: the points
+    are grouped by the decade of G_abs and each group is stepped with its own eta."""
+    import oracle as O
+    import paper_2108_11775_amd as P
+    _, g_r, _, gabs = O.occ_grad(oo, x)
+    dec = np.floor(np.log10(gabs)).astype(int)
+    for d in np.unique(dec):
+        sel = np.flatnonzero(dec == d)
+        eta = float(np.float32(10.0 ** (-d)))
+        xs = np.ascontiguousarray(x[:, sel])
+        out = host(P.morph_samples(go, dev(xs), 1, eta))
+        ref = xs.astype(np.float64) - eta * g_r[:, sel]
+        # the gradient's tolerance carried by eta, plus the rounding of x1
+        bound = tol * eta * gabs[sel] + 2.0 ** -22 * np.maximum(np.abs(ref), np.abs(xs))
+        err = np.abs(out - ref)
+        assert np.all(err <= bound), (d, float(np.max(err / bound)))

@@ -8,7 +8,7 @@ import oracle as O
 import paper_2108_11775_amd as P
 from paper_2108_11775_amd import configs as K, inputs as I
 
-from helpers import dev, host, oracle_occ, require_gpu, ws_scene
+from helpers import dev, host, one_step_grad_check, oracle_occ, require_gpu, ws_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -116,6 +116,7 @@ def test_grid_split_precision_wide_range():
     _, g_r, _, gabs = O.occ_grad(oo, x)
     assert np.all(np.abs(host(s) - s_r) <= TOL * sabs)
     assert np.all(np.abs(host(g) - g_r).max(axis=0) <= TOL * gabs)
+    one_step_grad_check(go, oo, x)
 
 
 def _wide_case(rng, g0, g1, ell, ax, ay, log2_range):
@@ -129,19 +130,17 @@ def _wide_case(rng, g0, g1, ell, ax, ay, log2_range):
                     rng.uniform(ay.min() - 8 * ell, ay.max() + 8 * ell, 500)])
     x = np.concatenate([rng.uniform(lo - 0.2, hi + 0.2, (2, 500)), far], axis=1).astype(np.float32)
     go = _grid_occ(h, wb, ell, g0, g1)
-    # evaluations of 2^17 samples or more may take the FP16 scheme (smaller ones keep
-    # the bf16 splits): the points are tiled past that, the first copy checked
-    xt = dev(np.ascontiguousarray(np.tile(x, (1, 132))))
-    s = host(P.occupancy_eval(go, xt)[1])[:1000]
-    g = host(P.occupancy_grad(go, xt)[1])[:, :1000]
     oo = oracle_occ(h, wb, ell)
+    # single evaluations keep the bf16 splits
+    _, s = P.occupancy_eval(go, dev(x))
+    _, g = P.occupancy_grad(go, dev(x))
     s_r, _, sabs = O.occ_eval(oo, x)
     _, g_r, _, gabs = O.occ_grad(oo, x)
-    assert np.all(np.abs(s - s_r) <= TOL * sabs)
-    assert np.all(np.abs(g - g_r).max(axis=0) <= TOL * gabs)
-    # small evaluations (bf16 splits) agree to the same tolerance
-    _, s2 = P.occupancy_eval(go, dev(x))
-    assert np.all(np.abs(host(s2) - s_r) <= TOL * sabs)
+    assert np.all(np.abs(host(s) - s_r) <= TOL * sabs)
+    assert np.all(np.abs(host(g) - g_r).max(axis=0) <= TOL * gabs)
+    # morphs take the block's scheme: one step per decade of G_abs checks the gradient
+    # to the same tolerance, far points included
+    one_step_grad_check(go, oo, x)
     xi = x[:, :500]
     out = host(P.morph_samples(go, dev(xi), 10, 0.002))
     ref, amp, _, _ = O.morph_ws(oo, xi, 10, 0.002, diag=True)
@@ -150,10 +149,10 @@ def _wide_case(rng, g0, g1, ell, ax, ay, log2_range):
 
 
 def test_grid_fp16_scheme_range_edge():
-    """The FP16 split scheme at the edge of its range: nonzero weights down to 2^-18.9 of
-    the largest (the scheme takes 2^-19), random signs, samples up to 8 lengthscales
-    outside the grid, where each sample's operand scale 2^c carries the features that
-    FP16 alone could not hold."""
+    """The FP16 split scheme (morphs) at the edge of its range: nonzero weights down to
+    2^-18.9 of the largest (the scheme takes 2^-19), random signs, samples up to 8
+    lengthscales outside the grid, where each sample's operand scale 2^c carries the
+    features that FP16 alone could not hold."""
     require_gpu()
     rng = np.random.default_rng(1619)
     g0, g1, ell = 64, 48, 0.3

@@ -1,5 +1,5 @@
-"""GPU parity of the grid-factorised 3-D path (16^3 hinges, BF16 MFMA at FP32
-accuracy): workspace
+"""GPU parity of the grid-factorised 3-D path (16^3 hinges, split contractions on the
+matrix cores at FP32 accuracy): workspace
 occupancy/gradient/morph, the joint-space morph and the body-point check, against
 the oracle's pairwise definitions with the same tolerances as the pairwise path."""
 import math
@@ -11,7 +11,7 @@ import oracle as O
 import paper_2108_11775_amd as P
 from paper_2108_11775_amd import configs as K, inputs as I
 
-from helpers import arm_scene, dev, gpu_occ, host, oracle_occ, require_gpu
+from helpers import arm_scene, dev, gpu_occ, host, one_step_grad_check, oracle_occ, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -58,6 +58,44 @@ def test_grid3d_split_precision_wide_range():
     _, g_r, _, gabs = O.occ_grad(oo, x)
     assert np.all(np.abs(host(s) - s_r) <= TOL * sabs), np.max(np.abs(host(s) - s_r) / sabs)
     assert np.all(np.abs(host(g) - g_r).max(axis=0) <= TOL * gabs)
+    one_step_grad_check(go, oo, x)
+
+
+def _grid3(ax):
+    gz, gy, gx = np.meshgrid(np.linspace(-1, 1, 16), np.linspace(-1, 1, 16), ax, indexing="ij")
+    return np.stack([gx.ravel(), gy.ravel(), gz.ravel()]).astype(np.float32)
+
+
+@pytest.mark.parametrize("gapped", [False, True], ids=["fp16-edge", "bf16-gapped-axis"])
+def test_grid3d_split_schemes(gapped):
+    """Morphs on the 3-D grid take the FP16 split scheme when the weights lie within
+    2^-19 of the largest and the hinge x-axis has no gap above 6 kappa units: weights
+    down to 2^-18.9 with random signs and points up to 6 lengthscales outside the grid
+    (each point's operand scale 2^c), checked by one morph step per decade of G_abs;
+    a gap of 2 (13 lengthscales) in the x-axis takes the three-way bf16 splits."""
+    require_gpu()
+    rng = np.random.default_rng(3109 + gapped)
+    ell = 0.15
+    ax = (np.r_[np.linspace(-2, -1, 8), np.linspace(1, 2, 8)] if gapped
+          else np.linspace(-1, 1, 16))
+    h = _grid3(ax)
+    mag = 2.0 ** rng.uniform(-18.9, 0, 4097)
+    wb = (mag * rng.choice([-1.0, 1.0], 4097)).astype(np.float32)
+    wb[-1] = 0.0
+    lo, hi = ax.min(), ax.max()
+    x = np.concatenate([
+        np.stack([rng.uniform(lo, hi, 600), rng.uniform(-1, 1, 600), rng.uniform(-1, 1, 600)]),
+        np.stack([rng.uniform(lo - 6 * ell, hi + 6 * ell, 600),
+                  rng.uniform(-1 - 6 * ell, 1 + 6 * ell, 600),
+                  rng.uniform(-1 - 6 * ell, 1 + 6 * ell, 600)])], axis=1).astype(np.float32)
+    go = gpu_occ(h, wb, ell, G)
+    oo = oracle_occ(h, wb, ell)
+    one_step_grad_check(go, oo, x)
+    xi = np.ascontiguousarray(x[:, :600])
+    out = host(P.morph_samples(go, dev(xi), 6, 0.002))
+    ref, amp, _, _ = O.morph_ws(oo, xi, 6, 0.002, diag=True)
+    err = np.abs(out - ref).max(axis=0)
+    assert np.all(err <= TOL * np.maximum(1, amp) * np.maximum(1, np.abs(ref).max(axis=0)))
 
 
 def test_grid3d_workspace_morph():
