@@ -92,6 +92,83 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
     return v;
 }
 
+// The block's scheme: FP16 parts with W scaled by 2^sw and the hinge x-range
+// [gmin, gmax] (kappa units), or BF16 parts.
+struct G2Scheme {
+    int fp16, sw;
+    float gmin, gmax;
+};
+
+// The FP16 scheme's test, from each thread's largest and smallest nonzero weight
+// magnitude (FP32 bit patterns) and the hinge x-axis (g0 <= 64 coordinates): finite
+// weights within 2^-19 of their largest magnitude (or all zero), a finite hinge
+// x-range and no x-gap above kG2MaxGap.  Every thread of the kG2Block-thread block
+// calls it; it synchronises the block once and returns the same scheme everywhere.
+__device__ __forceinline__ G2Scheme g2_decide(uint32_t mx, uint32_t mn,
+                                              const float *__restrict__ hinges, int g0,
+                                              float kappa, G2Range &rg) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    mx = wave_max_u32(mx);
+    mn = wave_min_u32(mn);
+    if (lane == 0) {
+        rg.wmax[wv] = mx;
+        rg.wmin[wv] = mn;
+    }
+    if (wv == 0) {
+        // one hinge x-coordinate per lane; the next larger coordinate of each by a
+        // scan over the lanes
+        const bool act = lane < g0;
+        const float g = act ? kappa * hinges[lane] : 0.0f;
+        float lo = act ? g : INFINITY, hi = act ? g : -INFINITY, nxt = INFINITY;
+        for (int b = 0; b < g0; ++b) {
+            const float o = __builtin_bit_cast(float, __builtin_amdgcn_readlane(
+                                                          __builtin_bit_cast(int, g), b));
+            if (o > g) nxt = fminf(nxt, o);
+        }
+        float gap = act && nxt < INFINITY ? nxt - g : 0.0f;
+        if (act && !(g == g)) gap = INFINITY;  // a NaN coordinate fails the check
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            lo = fminf(lo, __shfl_xor(lo, off, 64));
+            hi = fmaxf(hi, __shfl_xor(hi, off, 64));
+            gap = fmaxf(gap, __shfl_xor(gap, off, 64));
+        }
+        if (lane == 0) {
+            rg.gmin = lo;
+            rg.gmax = hi;
+            rg.gap = gap;
+        }
+    }
+    __syncthreads();
+    uint32_t wmx = rg.wmax[0], wmn = rg.wmin[0];
+#pragma unroll
+    for (int w = 1; w < kG2Block / 64; ++w) {
+        wmx = max(wmx, rg.wmax[w]);
+        wmn = min(wmn, rg.wmin[w]);
+    }
+    G2Scheme sc = {0, 0, rg.gmin, rg.gmax};
+    bool ok = wmx < 0x7f800000u && rg.gap <= kG2MaxGap && sc.gmax - sc.gmin < INFINITY;
+    if (ok && wmx != 0) {
+        int e;
+        (void)frexpf(__uint_as_float(wmx), &e);  // max|W| = f 2^e, f in [0.5, 1)
+        sc.sw = 15 - e;
+        ok = __uint_as_float(wmn) >= ldexpf(__uint_as_float(wmx), -kG2RangeLog2);
+    }
+    sc.fp16 = __builtin_amdgcn_readfirstlane((int)ok);
+    return sc;
+}
+
+// This sample's FP16 operand scale 2^c: c = 15 - k + floor(m), m the squared distance
+// of xs from [gmin, gmax] (capped at 256, where every feature underflows anyway) and
+// 2^k > sqrt(m).
+__device__ __forceinline__ int g2_scale_exp(float xs, float gmin, float gmax) {
+    const float dist = fmaxf(fmaxf(gmin - xs, xs - gmax), 0.0f);
+    const float m = floorf(fminf(dist * dist, 256.0f));
+    int k;
+    (void)frexpf(dist, &k);  // dist < 2^k
+    return 15 - max(k, 0) + (int)m;
+}
+
 // The state of one sample's lane pair across the steps, and its outputs.
 template <int MODE>
 __device__ __forceinline__ void g2_finish(float s, float sx, float sy, float beta, float gscale,
@@ -168,6 +245,7 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
     // check; its largest and smallest nonzero magnitude
     constexpr int kNI = (KS * TB * 64 + kG2Block - 1) / kG2Block;
     float wv8[kNI][8];
+    G2Scheme sc = {0, 0, 0.0f, 0.0f};
     {
         uint32_t mx = 0, mn = 0xffffffffu;
 #pragma unroll
@@ -186,66 +264,11 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
                 if (u != 0) mn = min(mn, u);
             }
         }
-        if (allow_fp16) {
-            mx = wave_max_u32(mx);
-            mn = wave_min_u32(mn);
-            if (lane == 0) {
-                rg.wmax[wv] = mx;
-                rg.wmin[wv] = mn;
-            }
-        }
+        if (allow_fp16) sc = g2_decide(mx, mn, hinges, g0, kappa, rg);
     }
-    if (allow_fp16 && wv == 0) {
-        // g0 <= 64: one hinge x-coordinate per lane; the next larger coordinate of
-        // each by a scan over the lanes
-        const bool act = lane < g0;
-        const float g = act ? kappa * hinges[lane] : 0.0f;
-        float lo = act ? g : INFINITY, hi = act ? g : -INFINITY, nxt = INFINITY;
-        for (int b = 0; b < g0; ++b) {
-            const float o = __builtin_bit_cast(float, __builtin_amdgcn_readlane(
-                                                          __builtin_bit_cast(int, g), b));
-            if (o > g) nxt = fminf(nxt, o);
-        }
-        float gap = act && nxt < INFINITY ? nxt - g : 0.0f;
-        if (act && !(g == g)) gap = INFINITY;  // a NaN coordinate fails the check
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            lo = fminf(lo, __shfl_xor(lo, off, 64));
-            hi = fmaxf(hi, __shfl_xor(hi, off, 64));
-            gap = fmaxf(gap, __shfl_xor(gap, off, 64));
-        }
-        if (lane == 0) {
-            rg.gmin = lo;
-            rg.gmax = hi;
-            rg.gap = gap;
-        }
-    }
-    if (allow_fp16) __syncthreads();  // otherwise the staging's own barrier below serves
-    // FP16 scheme: finite weights within 2^-19 of their largest magnitude (or all zero),
-    // finite hinge x-range, no x-gap above kG2MaxGap
-    int sw = 0;
-    float gmin = 0.0f, gmax = 0.0f;
-    uint32_t wmx = 0, wmn = 0;
-    bool fp16 = false;
-    if (allow_fp16) {
-        wmx = rg.wmax[0];
-        wmn = rg.wmin[0];
-#pragma unroll
-        for (int w = 1; w < kG2Block / 64; ++w) {
-            wmx = max(wmx, rg.wmax[w]);
-            wmn = min(wmn, rg.wmin[w]);
-        }
-        gmin = rg.gmin;
-        gmax = rg.gmax;
-        fp16 = wmx < 0x7f800000u && rg.gap <= kG2MaxGap && gmax - gmin < INFINITY;
-    }
-    if (fp16 && wmx != 0) {
-        int e;
-        (void)frexpf(__uint_as_float(wmx), &e);  // max|W| = f 2^e, f in [0.5, 1)
-        sw = 15 - e;
-        fp16 = __uint_as_float(wmn) >= ldexpf(__uint_as_float(wmx), -kG2RangeLog2);
-    }
-    fp16 = __builtin_amdgcn_readfirstlane((int)fp16) != 0;
+    const bool fp16 = allow_fp16 && sc.fp16;
+    const int sw = sc.sw;
+    const float gmin = sc.gmin, gmax = sc.gmax;
 
     const int64_t wave = (int64_t)blockIdx.x * (kG2Block / 64) + wv;
     const int64_t i = wave * 32 + (lane & 31);
@@ -255,7 +278,7 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
     const int steps = MODE == kMorph ? T : 1;
     float s = 0.0f, sx = 0.0f, sy = 0.0f;
 
-    if (allow_fp16 && fp16) {
+    if (fp16) {
         f16x8_t *frag = reinterpret_cast<f16x8_t *>(fraw);
 #pragma unroll
         for (int it = 0; it < kNI; ++it) {
@@ -274,12 +297,7 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
         for (int st = 0; st < steps; ++st) {
             const float xs = kappa * x, ys = kappa * y;
             // the operand scale 2^c of this sample (both lanes of the pair agree)
-            const float dist = fmaxf(fmaxf(gmin - xs, xs - gmax), 0.0f);
-            const float m = floorf(fminf(dist * dist, 256.0f));
-            int k;
-            (void)frexpf(dist, &k);  // dist < 2^k
-            k = max(k, 0);
-            const int c = 15 - k + (int)m;
+            const int c = g2_scale_exp(xs, gmin, gmax);
             f32x16_t U[TB], V[TB];
             int ln = lane;  // opaque: keeps the fragment reads inside the step loop
             asm volatile("" : "+v"(ln));
@@ -363,7 +381,7 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
     g2_finish<MODE>(s, sx, sy, beta, gscale, x, y, half, i, n, c_out, s_out, g_out, x_out);
 }
 
-// ---- small batches: 16 samples per wave on v_mfma_f32_16x16x32_bf16 ----
+// ---- small batches: 16 samples per wave on the 16x16x32 MFMAs (f16 or bf16) ----
 //
 // A batch of fewer than 2^17 samples gives the 32-sample waves above fewer than four
 // waves per SIMD, and a lone wave's T-step chain is then its latency.  Here four lanes
@@ -372,39 +390,100 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
 // rows b = 16t + 4g + v (v < 4) of every 16-row tile t; the four lanes of a sample are
 // summed by xor-16 and xor-32 exchanges (the same value in all four).  A lane forms
 // half the B entries and owns half the rows of the 32-wide kernel's lanes, so a step's
-// chain is about half as long, and the batch spreads over twice as many waves.
+// chain is about half as long, and the batch spreads over twice as many waves.  The
+// split scheme is chosen as in the 32-sample kernel (only morphs come here).
 constexpr int kG2sBlock = 256;  // 4 waves, 16 samples each
+
+// The y contraction on the 16x16 accumulator layout and the sum over the four lanes
+// of a sample.
+template <int TB16>
+__device__ __forceinline__ void g2s_ysum(const float *gys, float ys, int grp,
+                                         const f32x4_t (&U)[TB16], const f32x4_t (&V)[TB16],
+                                         float &s, float &sx, float &sy) {
+    s = 0.0f;
+    sx = 0.0f;
+    sy = 0.0f;
+#pragma unroll
+    for (int t = 0; t < TB16; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int b = 16 * t + 4 * grp + v;
+            const float d = ys - gys[b];
+            const float e = exp2_fast(-d * d);
+            s = fmaf(e, U[t][v], s);
+            sx = fmaf(e, V[t][v], sx);
+            sy = fmaf(e * d, U[t][v], sy);
+        }
+    s += __shfl_xor(s, 16, 64);
+    sx += __shfl_xor(sx, 16, 64);
+    sy += __shfl_xor(sy, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    sx += __shfl_xor(sx, 32, 64);
+    sy += __shfl_xor(sy, 32, 64);
+}
 
 template <int TB16, int KB, int MODE>
 __global__ void __launch_bounds__(kG2sBlock)
-k_grid2d_x6s(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
-             float kappa, float gscale, const float *x_in, int64_t n, int T, float eta,
-             float *c_out, float *s_out, float *g_out, float *x_out) {
+k_grid2d_small(const float *__restrict__ hinges, const float *__restrict__ weights, int g0,
+               int g1, float kappa, float gscale, const float *x_in, int64_t n, int T, float eta,
+               float *c_out, float *s_out, float *g_out, float *x_out) {
+    static_assert(kG2sBlock == kG2Block, "the scheme test assumes the large kernel's block");
     // fragments: frag[(p * KB + kb) * TB16 + t][lane] = part p of
-    //   W[b = 16t + lane%16][a = 32kb + 8(lane/16) + j], j < 8 (0 outside the grid)
-    __shared__ bf16x8_t frag[3 * KB * TB16 * 64];
+    //   W[b = 16t + lane%16][a = 32kb + 8(lane/16) + j], j < 8 (0 outside the grid);
+    // three bf16 parts of W or two FP16 parts of 2^sw W (the large kernel's schemes)
+    __shared__ uint4 fraw[3 * KB * TB16 * 64];
     __shared__ float gxs[32 * KB];
     __shared__ float gys[16 * TB16];
+    __shared__ G2Range rg;
     const int M = g0 * g1;
-    for (int idx = threadIdx.x; idx < KB * TB16 * 64; idx += kG2sBlock) {
+    // padding x-coordinates far away: their features are 0 on both schemes
+    for (int a = threadIdx.x; a < 32 * KB; a += kG2sBlock)
+        gxs[a] = a < g0 ? kappa * hinges[a] : 1e18f;
+    for (int b = threadIdx.x; b < 16 * TB16; b += kG2sBlock)
+        gys[b] = b < g1 ? kappa * hinges[(size_t)M + (size_t)g0 * b] : 0.0f;
+    constexpr int kNI = (KB * TB16 * 64 + kG2sBlock - 1) / kG2sBlock;
+    float wv8[kNI][8];
+    uint32_t mx = 0, mn = 0xffffffffu;
+#pragma unroll
+    for (int it = 0; it < kNI; ++it) {
+        const int idx = threadIdx.x + it * kG2sBlock;
         const int ln = idx & 63, t = (idx >> 6) % TB16, kb = idx / (64 * TB16);
         const int b = 16 * t + (ln & 15);
-        float v[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int a = 32 * kb + 8 * (ln >> 4) + j;
-            v[j] = (a < g0 && b < g1) ? weights[a + (int64_t)g0 * b] : 0.0f;
+            const float w = (idx < KB * TB16 * 64 && a < g0 && b < g1)
+                                ? weights[a + (int64_t)g0 * b] : 0.0f;
+            wv8[it][j] = w;
+            const uint32_t u = __float_as_uint(w) & 0x7fffffffu;
+            mx = max(mx, u);
+            if (u != 0) mn = min(mn, u);
         }
-        bf16x8_t p1, p2, p3;
-        split3(v, p1, p2, p3);
-        frag[(0 * KB + kb) * TB16 * 64 + t * 64 + ln] = p1;
-        frag[(1 * KB + kb) * TB16 * 64 + t * 64 + ln] = p2;
-        frag[(2 * KB + kb) * TB16 * 64 + t * 64 + ln] = p3;
     }
-    for (int a = threadIdx.x; a < 32 * KB; a += kG2sBlock)
-        gxs[a] = a < g0 ? kappa * hinges[a] : 0.0f;
-    for (int b = threadIdx.x; b < 16 * TB16; b += kG2sBlock)
-        gys[b] = b < g1 ? kappa * hinges[(size_t)M + (size_t)g0 * b] : 0.0f;
+    const G2Scheme sc = g2_decide(mx, mn, hinges, g0, kappa, rg);
+#pragma unroll
+    for (int it = 0; it < kNI; ++it) {
+        const int idx = threadIdx.x + it * kG2sBlock;
+        if (idx >= KB * TB16 * 64) break;
+        const int ln = idx & 63, t = (idx >> 6) % TB16, kb = idx / (64 * TB16);
+        if (sc.fp16) {
+            f16x8_t *frag = reinterpret_cast<f16x8_t *>(fraw);
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = ldexpf(wv8[it][j], sc.sw);
+            f16x8_t p1, p2;
+            split2h(v, p1, p2);
+            frag[(0 * KB + kb) * TB16 * 64 + t * 64 + ln] = p1;
+            frag[(1 * KB + kb) * TB16 * 64 + t * 64 + ln] = p2;
+        } else {
+            bf16x8_t *frag = reinterpret_cast<bf16x8_t *>(fraw);
+            bf16x8_t p1, p2, p3;
+            split3(wv8[it], p1, p2, p3);
+            frag[(0 * KB + kb) * TB16 * 64 + t * 64 + ln] = p1;
+            frag[(1 * KB + kb) * TB16 * 64 + t * 64 + ln] = p2;
+            frag[(2 * KB + kb) * TB16 * 64 + t * 64 + ln] = p3;
+        }
+    }
     __syncthreads();
 
     const int lane = threadIdx.x & 63, grp = lane >> 4;
@@ -421,48 +500,61 @@ k_grid2d_x6s(const float *__restrict__ hinges, const float *__restrict__ weights
         int ln = lane;  // opaque: keeps the fragment reads inside the step loop
         asm volatile("" : "+v"(ln));
         f32x4_t U[TB16], V[TB16];
+        if (sc.fp16) {
+            const f16x8_t *frag = reinterpret_cast<const f16x8_t *>(fraw);
+            const int c = g2_scale_exp(xs, sc.gmin, sc.gmax);
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-            float ev[8], dv[8];
+            for (int kb = 0; kb < KB; ++kb) {
+                float ev[8], dv[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const float d = xs - gxs[32 * kb + 8 * grp + j];
-                ev[j] = exp2_fast(-d * d);
-                dv[j] = ev[j] * d;
+                for (int j = 0; j < 8; ++j) {
+                    const float d = xs - gxs[32 * kb + 8 * grp + j];
+                    ev[j] = exp2_fast(fmaf(-d, d, (float)c));
+                    dv[j] = ev[j] * d;
+                }
+                f16x8_t e1, e2, d1, d2;
+                split2h(ev, e1, e2);
+                split2h(dv, d1, d2);
+#pragma unroll
+                for (int t = 0; t < TB16; ++t) {
+                    const f16x8_t a1 = frag[(0 * KB + kb) * TB16 * 64 + t * 64 + ln];
+                    const f16x8_t a2 = frag[(1 * KB + kb) * TB16 * 64 + t * 64 + ln];
+                    const f32x4_t zero = {};
+                    U[t] = mfma16_h3(a1, a2, e1, e2, kb == 0 ? zero : U[t]);
+                    V[t] = mfma16_h3(a1, a2, d1, d2, kb == 0 ? zero : V[t]);
+                }
             }
-            bf16x8_t e1, e2, e3, d1, d2, d3;
-            split3(ev, e1, e2, e3);
-            split3(dv, d1, d2, d3);
+            g2s_ysum<TB16>(gys, ys, grp, U, V, s, sx, sy);
+            const int un = -(sc.sw + c);
+            s = ldexpf(s, un);
+            sx = ldexpf(sx, un);
+            sy = ldexpf(sy, un);
+        } else {
+            const bf16x8_t *frag = reinterpret_cast<const bf16x8_t *>(fraw);
 #pragma unroll
-            for (int t = 0; t < TB16; ++t) {
-                const bf16x8_t a1 = frag[(0 * KB + kb) * TB16 * 64 + t * 64 + ln];
-                const bf16x8_t a2 = frag[(1 * KB + kb) * TB16 * 64 + t * 64 + ln];
-                const bf16x8_t a3 = frag[(2 * KB + kb) * TB16 * 64 + t * 64 + ln];
-                const f32x4_t zero = {};
-                U[t] = mfma16_x6(a1, a2, a3, e1, e2, e3, kb == 0 ? zero : U[t]);
-                V[t] = mfma16_x6(a1, a2, a3, d1, d2, d3, kb == 0 ? zero : V[t]);
+            for (int kb = 0; kb < KB; ++kb) {
+                float ev[8], dv[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const float d = xs - gxs[32 * kb + 8 * grp + j];
+                    ev[j] = exp2_fast(-d * d);
+                    dv[j] = ev[j] * d;
+                }
+                bf16x8_t e1, e2, e3, d1, d2, d3;
+                split3(ev, e1, e2, e3);
+                split3(dv, d1, d2, d3);
+#pragma unroll
+                for (int t = 0; t < TB16; ++t) {
+                    const bf16x8_t a1 = frag[(0 * KB + kb) * TB16 * 64 + t * 64 + ln];
+                    const bf16x8_t a2 = frag[(1 * KB + kb) * TB16 * 64 + t * 64 + ln];
+                    const bf16x8_t a3 = frag[(2 * KB + kb) * TB16 * 64 + t * 64 + ln];
+                    const f32x4_t zero = {};
+                    U[t] = mfma16_x6(a1, a2, a3, e1, e2, e3, kb == 0 ? zero : U[t]);
+                    V[t] = mfma16_x6(a1, a2, a3, d1, d2, d3, kb == 0 ? zero : V[t]);
+                }
             }
+            g2s_ysum<TB16>(gys, ys, grp, U, V, s, sx, sy);
         }
-        s = 0.0f;
-        sx = 0.0f;
-        sy = 0.0f;
-#pragma unroll
-        for (int t = 0; t < TB16; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int b = 16 * t + 4 * grp + v;
-                const float d = ys - gys[b];
-                const float e = exp2_fast(-d * d);
-                s = fmaf(e, U[t][v], s);
-                sx = fmaf(e, V[t][v], sx);
-                sy = fmaf(e * d, U[t][v], sy);
-            }
-        s += __shfl_xor(s, 16, 64);
-        sx += __shfl_xor(sx, 16, 64);
-        sy += __shfl_xor(sy, 16, 64);
-        s += __shfl_xor(s, 32, 64);
-        sx += __shfl_xor(sx, 32, 64);
-        sy += __shfl_xor(sy, 32, 64);
         if (MODE == kMorph) {
             float c, sp;
             sigmoid_and_slope(s + beta, c, sp);
@@ -496,7 +588,7 @@ static int32_t launch_grid2d_small(const RbfArgs &a, int g0, int g1, hipStream_t
     const int64_t blocks = (a.n + 63) / 64;
     const dim3 grid((unsigned)blocks), blk(kG2sBlock);
 #define PDMP_G2S(TB, KB)                                                                         \
-    hipLaunchKernelGGL((k_grid2d_x6s<TB, KB, kMorph>), grid, blk, 0, st, a.hinges, a.weights, g0, \
+    hipLaunchKernelGGL((k_grid2d_small<TB, KB, kMorph>), grid, blk, 0, st, a.hinges, a.weights, g0, \
                        g1, a.kappa, a.gscale, a.x_in, a.n, a.T, a.eta, a.c_out, a.s_out,          \
                        a.g_out, a.x_out)
 #define PDMP_G2S_T(KB)                             \
@@ -513,7 +605,7 @@ static int32_t launch_grid2d_small(const RbfArgs &a, int g0, int g1, hipStream_t
     }
 #undef PDMP_G2S_T
 #undef PDMP_G2S
-    return check_launch("k_grid2d_x6s");
+    return check_launch("k_grid2d_small");
 }
 
 // Returns PDMP_EUNSUPPORTED (without launching) when the grid does not fit.

@@ -121,4 +121,13 @@ __device__ __forceinline__ f32x16_t mfma_h3(const f16x8_t &a1, const f16x8_t &a2
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(a1, b1, acc, 0, 0, 0);
 }
 
+// The same three products on v_mfma_f32_16x16x32_f16 (the 16x16x32 bf16 layout above).
+__device__ __forceinline__ f32x4_t mfma16_h3(const f16x8_t &a1, const f16x8_t &a2,
+                                             const f16x8_t &b1, const f16x8_t &b2,
+                                             f32x4_t acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2, b1, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, b2, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, b1, acc, 0, 0, 0);
+}
+
 }  // namespace pdmp
