@@ -441,7 +441,12 @@ def density_workload(P, I, K, torch, hl):
     mix_ms = t.ms()
     dc_d, dr_d = hl["sc"]["discs"]
     _, hm = P.label_points_discs(dc_d, dr_d, mixed, count=True)
-    # U, V, Q products (6 G0 G1 MFMA flops) per sample-step on the logdet path
+    # U, V, Q products (6 G0 G1 FP32-equivalent flops) per sample-step on the logdet
+    # path, each multiply-add as the split scheme's products (three FP16 or six BF16)
+    scheme, nprod = split_scheme(occ.hinges[0, :G0].cpu().numpy(),
+                                 occ.weights[:-1].cpu().numpy(), occ.lengthscale)
+    peak = PEAK_F16_MFMA if scheme == "fp16" else PEAK_BF16_MFMA
+    sname = scheme.upper()
     ach = N * cfg.T * 6.0 * G0 * G1 / (ld_ms * 1e-3) / 1e12
     inv_flops = N * cfg.T * (iters * 4.0 + 6.0) * G0 * G1
     return {"workload": "log-det, inverse (fixed point, 10 iterations per step) and epsilon "
@@ -455,20 +460,21 @@ def density_workload(P, I, K, torch, hl):
             "logdet_mean": ld.mean().item(),
             "mixture_ms": mix_ms, "mixture_kept_fraction": keep.float().mean().item(),
             "mixture_collision_free": 1 - hm.item() / N,
-            "roofline_logdet": {"bound": "mfma", "achieved": 6.0 * ach,
-                                "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
-                                "frac": 6.0 * ach * 1e12 / PEAK_BF16_MFMA,
-                                "kernel": "k_grid2d_inv<2,4,kLogdet>",
-                                "work": "36*G0*G1 BF16 MFMA flops per sample-step (the three "
-                                        "FP32 contractions, 6*G0*G1 flops, as six BF16 products "
-                                        "of three-way splits)",
+            "roofline_logdet": {"bound": "mfma", "achieved": nprod * ach,
+                                "peak": peak / 1e12, "unit": "TFLOP/s",
+                                "frac": nprod * ach * 1e12 / peak,
+                                "kernel": "k_grid2d_inv<2,4,kLogdet>", "split_scheme": scheme,
+                                "work": f"{6 * nprod}*G0*G1 {sname} MFMA flops per sample-step "
+                                        "(the three FP32 contractions, 6*G0*G1 flops, as the "
+                                        f"{nprod} leading products of the {sname} splits)",
                                 "fp32_equivalent_tflops": ach},
             "roofline_inverse": {"bound": "mfma",
-                                 "achieved": 6.0 * inv_flops / (inv_ms * 1e-3) / 1e12,
-                                 "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
-                                 "frac": 6.0 * inv_flops / (inv_ms * 1e-3) / PEAK_BF16_MFMA,
-                                 "kernel": "k_grid2d_inv<2,4,kInverse>",
-                                 "work": "6*(4*iters + 6)*G0*G1 BF16 MFMA flops per sample-step",
+                                 "achieved": nprod * inv_flops / (inv_ms * 1e-3) / 1e12,
+                                 "peak": peak / 1e12, "unit": "TFLOP/s",
+                                 "frac": nprod * inv_flops / (inv_ms * 1e-3) / peak,
+                                 "kernel": "k_grid2d_inv<2,4,kInverse>", "split_scheme": scheme,
+                                 "work": f"{nprod}*(4*iters + 6)*G0*G1 {sname} MFMA flops per "
+                                         "sample-step",
                                  "fp32_equivalent_tflops": inv_flops / (inv_ms * 1e-3) / 1e12}}
 
 

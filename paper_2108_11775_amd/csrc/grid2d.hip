@@ -23,27 +23,14 @@
 namespace pdmp {
 
 constexpr int kG2Block = 256;   // 4 waves, 32 samples each
+static_assert(kG2Block == 64 * kSplitWaves, "the scheme test's block");
 
 // The contractions run at FP32 accuracy on the matrix cores, on one of two split
-// schemes chosen per launch from the operands' range (every block reaches the same
-// choice from the same weights and hinges; morphs only -- a single evaluation keeps
-// the BF16 scheme and skips the check):
-//  * FP16 (two-part splits, three products; mfma_split.h) when FP16's exponent range
-//    can hold the operands after power-of-two scaling: W is scaled so that
-//    2^14 <= max|W| < 2^15, and every nonzero |W| is at least 2^-19 max|W| (its two
-//    parts then stay normal, or their rounding stays within 2^-19 of it); the x-side
-//    operands of a sample are scaled by 2^c with c = 15 - k + floor(m), m the squared
-//    (kappa-scaled) distance of the sample from the hinge x-range [gmin, gmax] and
-//    2^k >= sqrt(m), so the largest 2^c ex_a is at most 2^15 and at least 2^(14-k)
-//    outside the range; inside it, every point lies within 3 (kappa units) of a
-//    hinge when no two consecutive hinge x-coordinates are more than 6 apart, and then
-//    the largest 2^15 ex_a is at least 2^6.  2^c ex_a dx_a stays below 2^15 as well.
-//    The sums are scaled back by 2^-(sW + c) with ldexp (exact).
-//  * BF16 (three-part splits, six products) otherwise: bf16 has FP32's exponent range.
-// The FP16 scheme needs half the matrix-core work and about half the splitting VALU.
-
-constexpr int kG2RangeLog2 = 19;    // nonzero |W| >= 2^-19 max|W|
-constexpr float kG2MaxGap = 6.0f;   // consecutive kappa-scaled hinge x-coordinates
+// schemes (mfma_split.h): two-part FP16 splits with three products where the
+// operands' range allows, three-part BF16 splits with six products otherwise.  Morphs
+// only -- a single evaluation, whose blocks mostly stage W, keeps the BF16 scheme and
+// skips the check.  The FP16 scheme needs half the matrix-core work and about half
+// the splitting VALU.
 
 // The x-side operands of k-step ks for this lane: ex and ex * dx at a = 16ks + 8half + j.
 __device__ __forceinline__ void x6_operands(const float *gxs, float xs, int ks, int half,
@@ -71,102 +58,6 @@ __device__ __forceinline__ void h3_operands(const float *gxs, float xs, float cf
     }
     split2h(ev, e[0], e[1]);
     split2h(dv, de[0], de[1]);
-}
-
-// Per-block operand range: max|W| and the smallest nonzero |W| (as FP32 bit patterns,
-// which order like the values for non-negative numbers and put NaN above infinity)
-// and the hinge x-range and largest gap in kappa units.
-struct G2Range {
-    uint32_t wmax[kG2Block / 64], wmin[kG2Block / 64];
-    float gmin, gmax, gap;
-};
-
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
-    return v;
-}
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, 64));
-    return v;
-}
-
-// The block's scheme: FP16 parts with W scaled by 2^sw and the hinge x-range
-// [gmin, gmax] (kappa units), or BF16 parts.
-struct G2Scheme {
-    int fp16, sw;
-    float gmin, gmax;
-};
-
-// The FP16 scheme's test, from each thread's largest and smallest nonzero weight
-// magnitude (FP32 bit patterns) and the hinge x-axis (g0 <= 64 coordinates): finite
-// weights within 2^-19 of their largest magnitude (or all zero), a finite hinge
-// x-range and no x-gap above kG2MaxGap.  Every thread of the kG2Block-thread block
-// calls it; it synchronises the block once and returns the same scheme everywhere.
-__device__ __forceinline__ G2Scheme g2_decide(uint32_t mx, uint32_t mn,
-                                              const float *__restrict__ hinges, int g0,
-                                              float kappa, G2Range &rg) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    mx = wave_max_u32(mx);
-    mn = wave_min_u32(mn);
-    if (lane == 0) {
-        rg.wmax[wv] = mx;
-        rg.wmin[wv] = mn;
-    }
-    if (wv == 0) {
-        // one hinge x-coordinate per lane; the next larger coordinate of each by a
-        // scan over the lanes
-        const bool act = lane < g0;
-        const float g = act ? kappa * hinges[lane] : 0.0f;
-        float lo = act ? g : INFINITY, hi = act ? g : -INFINITY, nxt = INFINITY;
-        for (int b = 0; b < g0; ++b) {
-            const float o = __builtin_bit_cast(float, __builtin_amdgcn_readlane(
-                                                          __builtin_bit_cast(int, g), b));
-            if (o > g) nxt = fminf(nxt, o);
-        }
-        float gap = act && nxt < INFINITY ? nxt - g : 0.0f;
-        if (act && !(g == g)) gap = INFINITY;  // a NaN coordinate fails the check
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            lo = fminf(lo, __shfl_xor(lo, off, 64));
-            hi = fmaxf(hi, __shfl_xor(hi, off, 64));
-            gap = fmaxf(gap, __shfl_xor(gap, off, 64));
-        }
-        if (lane == 0) {
-            rg.gmin = lo;
-            rg.gmax = hi;
-            rg.gap = gap;
-        }
-    }
-    __syncthreads();
-    uint32_t wmx = rg.wmax[0], wmn = rg.wmin[0];
-#pragma unroll
-    for (int w = 1; w < kG2Block / 64; ++w) {
-        wmx = max(wmx, rg.wmax[w]);
-        wmn = min(wmn, rg.wmin[w]);
-    }
-    G2Scheme sc = {0, 0, rg.gmin, rg.gmax};
-    bool ok = wmx < 0x7f800000u && rg.gap <= kG2MaxGap && sc.gmax - sc.gmin < INFINITY;
-    if (ok && wmx != 0) {
-        int e;
-        (void)frexpf(__uint_as_float(wmx), &e);  // max|W| = f 2^e, f in [0.5, 1)
-        sc.sw = 15 - e;
-        ok = __uint_as_float(wmn) >= ldexpf(__uint_as_float(wmx), -kG2RangeLog2);
-    }
-    sc.fp16 = __builtin_amdgcn_readfirstlane((int)ok);
-    return sc;
-}
-
-// This sample's FP16 operand scale 2^c: c = 15 - k + floor(m), m the squared distance
-// of xs from [gmin, gmax] (capped at 256, where every feature underflows anyway) and
-// 2^k > sqrt(m).
-__device__ __forceinline__ int g2_scale_exp(float xs, float gmin, float gmax) {
-    const float dist = fmaxf(fmaxf(gmin - xs, xs - gmax), 0.0f);
-    const float m = floorf(fminf(dist * dist, 256.0f));
-    int k;
-    (void)frexpf(dist, &k);  // dist < 2^k
-    return 15 - max(k, 0) + (int)m;
 }
 
 // The state of one sample's lane pair across the steps, and its outputs.
@@ -231,7 +122,7 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
     __shared__ uint4 fraw[3 * KS * TB * 64];
     __shared__ float gxs[16 * KS];
     __shared__ float gys[32 * TB];
-    __shared__ G2Range rg;
+    __shared__ SplitRange rg;
     const int M = g0 * g1;
     const int lane = threadIdx.x & 63, half = lane >> 5, wv = threadIdx.x >> 6;
 
@@ -245,7 +136,7 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
     // check; its largest and smallest nonzero magnitude
     constexpr int kNI = (KS * TB * 64 + kG2Block - 1) / kG2Block;
     float wv8[kNI][8];
-    G2Scheme sc = {0, 0, 0.0f, 0.0f};
+    SplitScheme sc = {0, 0, 0.0f, 0.0f};
     {
         uint32_t mx = 0, mn = 0xffffffffu;
 #pragma unroll
@@ -264,7 +155,7 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
                 if (u != 0) mn = min(mn, u);
             }
         }
-        if (allow_fp16) sc = g2_decide(mx, mn, hinges, g0, kappa, rg);
+        if (allow_fp16) sc = split_decide(mx, mn, hinges, g0, kappa, rg);
     }
     const bool fp16 = allow_fp16 && sc.fp16;
     const int sw = sc.sw;
@@ -297,7 +188,7 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
         for (int st = 0; st < steps; ++st) {
             const float xs = kappa * x, ys = kappa * y;
             // the operand scale 2^c of this sample (both lanes of the pair agree)
-            const int c = g2_scale_exp(xs, gmin, gmax);
+            const int c = split_scale_exp(xs, gmin, gmax);
             f32x16_t U[TB], V[TB];
             int ln = lane;  // opaque: keeps the fragment reads inside the step loop
             asm volatile("" : "+v"(ln));
@@ -434,7 +325,7 @@ k_grid2d_small(const float *__restrict__ hinges, const float *__restrict__ weigh
     __shared__ uint4 fraw[3 * KB * TB16 * 64];
     __shared__ float gxs[32 * KB];
     __shared__ float gys[16 * TB16];
-    __shared__ G2Range rg;
+    __shared__ SplitRange rg;
     const int M = g0 * g1;
     // padding x-coordinates far away: their features are 0 on both schemes
     for (int a = threadIdx.x; a < 32 * KB; a += kG2sBlock)
@@ -460,7 +351,7 @@ k_grid2d_small(const float *__restrict__ hinges, const float *__restrict__ weigh
             if (u != 0) mn = min(mn, u);
         }
     }
-    const G2Scheme sc = g2_decide(mx, mn, hinges, g0, kappa, rg);
+    const SplitScheme sc = split_decide(mx, mn, hinges, g0, kappa, rg);
 #pragma unroll
     for (int it = 0; it < kNI; ++it) {
         const int idx = threadIdx.x + it * kG2sBlock;
@@ -502,7 +393,7 @@ k_grid2d_small(const float *__restrict__ hinges, const float *__restrict__ weigh
         f32x4_t U[TB16], V[TB16];
         if (sc.fp16) {
             const f16x8_t *frag = reinterpret_cast<const f16x8_t *>(fraw);
-            const int c = g2_scale_exp(xs, sc.gmin, sc.gmax);
+            const int c = split_scale_exp(xs, sc.gmin, sc.gmax);
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb) {
                 float ev[8], dv[8];

@@ -30,15 +30,11 @@ namespace pdmp {
 constexpr int kG3Y = 16;  // points on the y axis (two z-planes per 32-row MFMA tile)
 constexpr int kG3Block = 256;
 
-// The x contraction runs on one of two split schemes, chosen in every block from the
-// same weights and hinges (the rules of the 2-D grid kernel): FP16 two-part splits
-// (three products) when every nonzero |W| is at least 2^-19 of the largest and no two
-// consecutive hinge x-coordinates are more than 6 apart in kappa units -- W scaled
-// to [2^14, 2^15), each point's x-side operands by 2^c from its distance to the hinge
-// x-range, the sums scaled back with ldexp -- and three-part bf16 splits (six
-// products) otherwise or where the caller does not allow the check.
-constexpr int kG3RangeLog2 = 19;
-constexpr float kG3MaxGap = 6.0f;
+// The x contraction runs on one of two split schemes (mfma_split.h): two-part FP16
+// splits with three products where the operands' range allows, three-part BF16
+// splits with six products otherwise; morphs only (a single evaluation skips the
+// check and keeps the BF16 scheme).
+static_assert(kG3Block == 64 * kSplitWaves, "the scheme test's block");
 
 template <int G0, int G2>
 struct G3 {
@@ -48,35 +44,12 @@ struct G3 {
     static constexpr int FRAG = 3 * TB * 64;   // 16-byte fragments: up to 3 parts x TB tiles
 };
 
-struct G3Range {
-    uint32_t wmax[kG3Block / 64], wmin[kG3Block / 64];
-    float gmin, gmax, gap;
-};
-
-// The block's scheme: FP16 parts with W scaled by 2^sw and the hinge x-range
-// [gmin, gmax] (kappa units), or BF16 parts.
-struct G3Scheme {
-    int fp16, sw;
-    float gmin, gmax;
-};
-
-__device__ __forceinline__ uint32_t g3_wave_max(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
-    return v;
-}
-__device__ __forceinline__ uint32_t g3_wave_min(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, 64));
-    return v;
-}
-
 // Stage W fragments (frag[(p*TB + t)*64 + lane] = part p of W[32t + lane%32][8(lane/32)
 // + j], j < 8) and the prescaled axes into LDS, choosing the scheme.  All kG3Block
 // threads call it; the caller synchronises before reading the fragments.
 template <int G0, int G2>
-__device__ __forceinline__ G3Scheme g3_stage(uint4 *fraw, float *ax, float *ay, float *az,
-                                             G3Range &rg, const float *__restrict__ hinges,
+__device__ __forceinline__ SplitScheme g3_stage(uint4 *fraw, float *ax, float *ay, float *az,
+                                             SplitRange &rg, const float *__restrict__ hinges,
                                              const float *__restrict__ weights, float kappa,
                                              bool allow16) {
     using C = G3<G0, G2>;
@@ -100,10 +73,9 @@ __device__ __forceinline__ G3Scheme g3_stage(uint4 *fraw, float *ax, float *ay, 
         for (int i = threadIdx.x; i < kG3Y; i += kG3Block) ay[i] = kappa * hinges[M + G0 * i];
         for (int i = threadIdx.x; i < G2; i += kG3Block)
             az[i] = kappa * hinges[2 * M + G0 * kG3Y * i];
-        return G3Scheme{0, 0, 0.0f, 0.0f};
+        return SplitScheme{0, 0, 0.0f, 0.0f};
     }
     constexpr int NI = (C::TB * 64 + kG3Block - 1) / kG3Block;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     float w8[NI][8];
     uint32_t mx = 0, mn = 0xffffffffu;
 #pragma unroll
@@ -119,62 +91,10 @@ __device__ __forceinline__ G3Scheme g3_stage(uint4 *fraw, float *ax, float *ay, 
             if (u != 0) mn = min(mn, u);
         }
     }
-    {
-        mx = g3_wave_max(mx);
-        mn = g3_wave_min(mn);
-        if (lane == 0) {
-            rg.wmax[wv] = mx;
-            rg.wmin[wv] = mn;
-        }
-        if (wv == 0) {
-            // one hinge x-coordinate per lane; the next larger one of each by a scan
-            const bool act = lane < G0;
-            const float g = act ? kappa * hinges[lane] : 0.0f;
-            float lo = act ? g : INFINITY, hi = act ? g : -INFINITY, nxt = INFINITY;
-#pragma unroll
-            for (int b = 0; b < G0; ++b) {
-                const float o = __builtin_bit_cast(
-                    float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, g), b));
-                if (o > g) nxt = fminf(nxt, o);
-            }
-            float gap = act && nxt < INFINITY ? nxt - g : 0.0f;
-            if (act && !(g == g)) gap = INFINITY;  // a NaN coordinate fails the check
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                lo = fminf(lo, __shfl_xor(lo, off, 64));
-                hi = fmaxf(hi, __shfl_xor(hi, off, 64));
-                gap = fmaxf(gap, __shfl_xor(gap, off, 64));
-            }
-            if (lane == 0) {
-                rg.gmin = lo;
-                rg.gmax = hi;
-                rg.gap = gap;
-            }
-        }
-    }
     for (int i = threadIdx.x; i < G0; i += kG3Block) ax[i] = kappa * hinges[i];
     for (int i = threadIdx.x; i < kG3Y; i += kG3Block) ay[i] = kappa * hinges[M + G0 * i];
     for (int i = threadIdx.x; i < G2; i += kG3Block) az[i] = kappa * hinges[2 * M + G0 * kG3Y * i];
-    __syncthreads();
-    G3Scheme sc = {0, 0, 0.0f, 0.0f};
-    {
-        uint32_t wmx = rg.wmax[0], wmn = rg.wmin[0];
-#pragma unroll
-        for (int w = 1; w < kG3Block / 64; ++w) {
-            wmx = max(wmx, rg.wmax[w]);
-            wmn = min(wmn, rg.wmin[w]);
-        }
-        sc.gmin = rg.gmin;
-        sc.gmax = rg.gmax;
-        bool ok = wmx < 0x7f800000u && rg.gap <= kG3MaxGap && sc.gmax - sc.gmin < INFINITY;
-        if (ok && wmx != 0) {
-            int e;
-            (void)frexpf(__uint_as_float(wmx), &e);  // max|W| = f 2^e, f in [0.5, 1)
-            sc.sw = 15 - e;
-            ok = __uint_as_float(wmn) >= ldexpf(__uint_as_float(wmx), -kG3RangeLog2);
-        }
-        sc.fp16 = __builtin_amdgcn_readfirstlane((int)ok);
-    }
+    const SplitScheme sc = split_decide(mx, mn, hinges, G0, kappa, rg);
 #pragma unroll
     for (int it = 0; it < NI; ++it) {
         const int idx = threadIdx.x + it * kG3Block;
@@ -205,7 +125,7 @@ __device__ __forceinline__ G3Scheme g3_stage(uint4 *fraw, float *ax, float *ay, 
 // prescaled point (xs, ys, zs) this lane shares with its xor-32 partner, on the
 // block's split scheme (F16 = sc.fp16).
 template <int G0, int G2, bool GRAD, bool F16>
-__device__ __forceinline__ void g3_point(const uint4 *fraw, const G3Scheme &sc, const float *ax,
+__device__ __forceinline__ void g3_point(const uint4 *fraw, const SplitScheme &sc, const float *ax,
                                          const float *ay, const float *az, float xs, float ys,
                                          float zs, float &s, float &sx, float &sy, float &sz) {
     using C = G3<G0, G2>;
@@ -221,11 +141,7 @@ __device__ __forceinline__ void g3_point(const uint4 *fraw, const G3Scheme &sc, 
     {
         float cf = 0.0f;
         if (F16) {
-            const float dist = fmaxf(fmaxf(sc.gmin - xs, xs - sc.gmax), 0.0f);
-            const float m = floorf(fminf(dist * dist, 256.0f));
-            int k;
-            (void)frexpf(dist, &k);  // dist < 2^k
-            c = 15 - max(k, 0) + (int)m;
+            c = split_scale_exp(xs, sc.gmin, sc.gmax);
             cf = (float)c;
         }
         float e[8], de[8];
@@ -320,7 +236,7 @@ __device__ __forceinline__ void g3_point(const uint4 *fraw, const G3Scheme &sc, 
 
 // ---- workspace points [3][n]: eval / grad / morph, 32 points per wave ----
 template <int G0, int G2, int MODE, bool F16>
-__device__ __forceinline__ void g3_ws_body(const uint4 *fraw, const G3Scheme &sc, const float *ax,
+__device__ __forceinline__ void g3_ws_body(const uint4 *fraw, const SplitScheme &sc, const float *ax,
                                            const float *ay, const float *az, float beta,
                                            float kappa, float gscale, const float *x_in,
                                            int64_t n, int T, float eta, float *c_out,
@@ -371,10 +287,10 @@ k_grid3d_ws(const float *__restrict__ hinges, const float *__restrict__ weights,
     using C = G3<G0, G2>;
     __shared__ uint4 fraw[C::FRAG];
     __shared__ float ax[G0], ay[kG3Y], az[G2];
-    __shared__ G3Range rg;
+    __shared__ SplitRange rg;
     // the range check pays off over a morph's steps; a single evaluation, whose blocks
     // mostly stage W, keeps the BF16 scheme without it
-    const G3Scheme sc = g3_stage<G0, G2>(fraw, ax, ay, az, rg, hinges, weights, kappa,
+    const SplitScheme sc = g3_stage<G0, G2>(fraw, ax, ay, az, rg, hinges, weights, kappa,
                                          MODE == kMorph);
     __syncthreads();
     constexpr int M = G0 * kG3Y * G2;
@@ -430,7 +346,7 @@ __device__ __forceinline__ float sum8(float v) {
 // 4 configurations per wave; lane%32 = 8*cfg + k, body point k of every link.
 template <int NDOF, int G0, int G2, bool MORPH, bool F16>
 __device__ __forceinline__ void arm_body(const pdmp_arm &arm, const uint4 *fraw,
-                                         const G3Scheme &sc, const float *ax, const float *ay,
+                                         const SplitScheme &sc, const float *ax, const float *ay,
                                          const float *az, float *kin, float beta, float kappa,
                                          float gscale, const float *q_in, float *q_out, int64_t n,
                                          int64_t n_eff, int T, float eta, float thresh,
@@ -536,12 +452,12 @@ k_arm_grid3d(pdmp_arm arm, const float *__restrict__ hinges, const float *__rest
     __shared__ uint4 fraw[C::FRAG];
     __shared__ float ax[G0], ay[kG3Y], az[G2];
     __shared__ float kin[16 * KIN];
-    __shared__ G3Range rg;
+    __shared__ SplitRange rg;
     const int64_t n_eff = n_active ? min((int64_t)*n_active, n) : n;
     if ((int64_t)blockIdx.x * 16 >= n_eff) return;  // whole block idle (uniform)
     // the range check pays off over the T steps of a morph; the single check pass
     // keeps the BF16 scheme
-    const G3Scheme sc = g3_stage<G0, G2>(fraw, ax, ay, az, rg, hinges, weights, kappa, MORPH);
+    const SplitScheme sc = g3_stage<G0, G2>(fraw, ax, ay, az, rg, hinges, weights, kappa, MORPH);
     __syncthreads();
     constexpr int M = G0 * kG3Y * G2;
     const float beta = weights[M];

@@ -130,4 +130,122 @@ __device__ __forceinline__ f32x4_t mfma16_h3(const f16x8_t &a1, const f16x8_t &a
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, b1, acc, 0, 0, 0);
 }
 
+// ---- choosing a grid contraction's split scheme ----
+//
+// A grid kernel contracts W (rows: the other axes' hinges, k: the x-axis hinges a)
+// with the x-side operands ex_a = 2^-(xs - gx_a)^2 and ex_a (xs - gx_a) of each point
+// (kappa units).  The FP16 scheme needs both inside FP16's exponent range after
+// power-of-two scaling; every block of a launch decides from the same data, so all
+// reach the same choice:
+//  * W is scaled by 2^sw so that 2^14 <= max|W| < 2^15; every nonzero |W| must be at
+//    least 2^-19 max|W| (its two FP16 parts then stay normal, or their rounding within
+//    2^-19 of it) and all of W finite;
+//  * a point's x-side operands are scaled by 2^c, c = 15 - k + floor(m), m the squared
+//    distance of xs from the hinge x-range [gmin, gmax] and 2^k > sqrt(m): the largest
+//    2^c ex_a is at most 2^15 and at least 2^(14-k) outside the range, and
+//    2^c ex_a |dx_a| stays below 2^15; inside the range every point lies within 3 of a
+//    hinge when no two consecutive hinge x-coordinates are more than 6 apart, so the
+//    largest 2^15 ex_a is at least 2^6;
+//  * the sums are scaled back by 2^-(sw + c) with ldexp (exact).
+// Otherwise the kernel takes the three-part BF16 splits, which have FP32's range.
+constexpr int kSplitRangeLog2 = 19;   // nonzero |W| >= 2^-19 max|W|
+constexpr float kSplitMaxGap = 6.0f;  // consecutive hinge x-coordinates, kappa units
+constexpr int kSplitWaves = 4;        // the grid kernels' 256-thread blocks
+
+struct SplitRange {
+    uint32_t wmax[kSplitWaves], wmin[kSplitWaves];
+    float gmin, gmax, gap;
+};
+
+// The block's scheme: FP16 parts with W scaled by 2^sw and the hinge x-range
+// [gmin, gmax] (kappa units), or (fp16 == 0) BF16 parts.
+struct SplitScheme {
+    int fp16, sw;
+    float gmin, gmax;
+};
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return v;
+}
+
+// The scheme from each thread's largest and smallest nonzero weight magnitude (FP32
+// bit patterns, which order like the values for non-negative numbers and put NaN
+// above infinity) and the g0 <= 64 hinge x-coordinates xaxis[0..g0).  Every thread of
+// the 256-thread block calls it; it synchronises the block once.
+__device__ __forceinline__ SplitScheme split_decide(uint32_t mx, uint32_t mn,
+                                                    const float *__restrict__ xaxis, int g0,
+                                                    float kappa, SplitRange &rg) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    mx = wave_max_u32(mx);
+    mn = wave_min_u32(mn);
+    if (lane == 0) {
+        rg.wmax[wv] = mx;
+        rg.wmin[wv] = mn;
+    }
+    if (wv == 0) {
+        // one hinge x-coordinate per lane; the next larger coordinate of each by a
+        // scan over the lanes
+        const bool act = lane < g0;
+        const float g = act ? kappa * xaxis[lane] : 0.0f;
+        float lo = act ? g : INFINITY, hi = act ? g : -INFINITY, nxt = INFINITY;
+        for (int b = 0; b < g0; ++b) {
+            const float o = __builtin_bit_cast(float, __builtin_amdgcn_readlane(
+                                                          __builtin_bit_cast(int, g), b));
+            if (o > g) nxt = fminf(nxt, o);
+        }
+        float gap = act && nxt < INFINITY ? nxt - g : 0.0f;
+        if (act && !(g == g)) gap = INFINITY;  // a NaN coordinate fails the check
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            lo = fminf(lo, __shfl_xor(lo, off, 64));
+            hi = fmaxf(hi, __shfl_xor(hi, off, 64));
+            gap = fmaxf(gap, __shfl_xor(gap, off, 64));
+        }
+        if (lane == 0) {
+            rg.gmin = lo;
+            rg.gmax = hi;
+            rg.gap = gap;
+        }
+    }
+    __syncthreads();
+    uint32_t wmx = rg.wmax[0], wmn = rg.wmin[0];
+#pragma unroll
+    for (int w = 1; w < kSplitWaves; ++w) {
+        wmx = max(wmx, rg.wmax[w]);
+        wmn = min(wmn, rg.wmin[w]);
+    }
+    SplitScheme sc = {0, 0, rg.gmin, rg.gmax};
+    bool ok = wmx < 0x7f800000u && rg.gap <= kSplitMaxGap && sc.gmax - sc.gmin < INFINITY;
+    if (ok && wmx != 0) {
+        int e;
+        (void)frexpf(__uint_as_float(wmx), &e);  // max|W| = f 2^e, f in [0.5, 1)
+        sc.sw = 15 - e;
+        ok = __uint_as_float(wmn) >= ldexpf(__uint_as_float(wmx), -kSplitRangeLog2);
+    }
+    sc.fp16 = __builtin_amdgcn_readfirstlane((int)ok);
+    return sc;
+}
+
+// A point's FP16 operand scale exponent c (above), with k returned for operands that
+// carry a second factor dx (2^(c-k) ex dx^2 stays below 2^15 as well).  m is capped at
+// 256, where every feature underflows anyway.
+__device__ __forceinline__ int split_scale_exp(float xs, float gmin, float gmax, int &k) {
+    const float dist = fmaxf(fmaxf(gmin - xs, xs - gmax), 0.0f);
+    const float m = floorf(fminf(dist * dist, 256.0f));
+    (void)frexpf(dist, &k);  // dist < 2^k
+    k = max(k, 0);
+    return 15 - k + (int)m;
+}
+__device__ __forceinline__ int split_scale_exp(float xs, float gmin, float gmax) {
+    int k;
+    return split_scale_exp(xs, gmin, gmax, k);
+}
+
 }  // namespace pdmp

@@ -13,8 +13,10 @@
 // Hessian of c = sigma(s):  Hc = sigma' Hs + sigma'' grad s grad s^T, with
 //   Hs = sum_j w_j phi_j ((x - h_j)(x - h_j)^T / l^4 - I / l^2).
 // Grid path (2-D hinges on a tensor grid): the G1 x G0 products U = W ex, V = W ex dx
-// of the plain morph and a third one, Q = W ex dx^2, on BF16 MFMA at FP32 accuracy
-// (three-way bf16 splits, six leading products: mfma_split.h); the y sums run on
+// of the plain morph and a third one, Q = W ex dx^2, on the matrix cores at FP32
+// accuracy (the split schemes of mfma_split.h: two-part FP16 splits and three
+// products where the operands' range allows, three-way bf16 splits and six products
+// otherwise); the y sums run on
 // the accumulator layout as in the plain morph (same lane mapping, same xor-32 pair
 // sum).  Pairwise path (any hinges, 2-D or 3-D): one point per thread, hinges staged
 // in LDS tiles.
@@ -24,6 +26,7 @@
 namespace pdmp {
 
 constexpr int kIvBlock = 256;
+static_assert(kIvBlock == 64 * kSplitWaves, "the scheme test's block");
 
 // log|det(I - eta Hc)| for a 2 x 2 or 3 x 3 Hc (row-major).
 template <int DIM>
@@ -65,35 +68,79 @@ __device__ __forceinline__ void g2i_operands(const float *gxs, float xs, int ks,
     if (HESS) split3(ddv, dde[0], dde[1], dde[2]);
 }
 
+// The same operands on the FP16 scheme: 2^c ex, 2^c ex dx and 2^(c-k) ex dx^2
+// (mfma_split.h), each as two FP16 parts.
+template <bool HESS>
+__device__ __forceinline__ void g2i_operands_h(const float *gxs, float xs, float cf, float sk,
+                                               int ks, int half, f16x8_t (&e)[2],
+                                               f16x8_t (&de)[2], f16x8_t (&dde)[2]) {
+    float ev[8], dv[8], ddv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float d = xs - gxs[16 * ks + 8 * half + j];
+        ev[j] = exp2_fast(fmaf(-d, d, cf));
+        dv[j] = ev[j] * d;
+        ddv[j] = dv[j] * (d * sk);
+    }
+    split2h(ev, e[0], e[1]);
+    split2h(dv, de[0], de[1]);
+    if (HESS) split2h(ddv, dde[0], dde[1]);
+}
+
 // Sums at the prescaled point (xs, ys): s' (without beta), (sx, sy) with
 // grad s = -gscale (sx, sy), and with HESS (sxx, sxy, syy) with
-// Hs = gscale^2 [[sxx, sxy], [sxy, syy]] - (1/l^2) s' I.
-template <int TB, int KS, bool HESS>
-__device__ __forceinline__ void g2i_eval(const bf16x8_t *frag, const float *gxs, const float *gys,
-                                         float xs, float ys, float &s, float &sx, float &sy,
-                                         float &sxx, float &sxy, float &syy) {
+// Hs = gscale^2 [[sxx, sxy], [sxy, syy]] - (1/l^2) s' I, on the block's split scheme.
+template <int TB, int KS, bool HESS, bool F16>
+__device__ __forceinline__ void g2i_eval(const uint4 *fraw, const SplitScheme &sc,
+                                         const float *gxs, const float *gys, float xs, float ys,
+                                         float &s, float &sx, float &sy, float &sxx, float &sxy,
+                                         float &syy) {
     const int lane0 = threadIdx.x & 63, half = lane0 >> 5;
     int lane = lane0;  // opaque: the fragment reads stay inside the callers' loops
     asm volatile("" : "+v"(lane));
     f32x16_t U[TB], V[TB], Q[TB];
     // the operands of k-step ks + 1 are formed while k-step ks's products run; k-step 0
     // starts the accumulators from the zero constant
-    bf16x8_t e[3], de[3], dde[3];
-    g2i_operands<HESS>(gxs, xs, 0, half, e, de, dde);
+    int c = 0, k = 0;
+    if (F16) {
+        const f16x8_t *frag = reinterpret_cast<const f16x8_t *>(fraw);
+        c = split_scale_exp(xs, sc.gmin, sc.gmax, k);
+        const float cf = (float)c, sk = ldexpf(1.0f, -k);
+        f16x8_t e[2], de[2], dde[2];
+        g2i_operands_h<HESS>(gxs, xs, cf, sk, 0, half, e, de, dde);
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        bf16x8_t ec[3] = {e[0], e[1], e[2]}, dc[3] = {de[0], de[1], de[2]},
-                 qc[3] = {dde[0], dde[1], dde[2]};
-        if (ks + 1 < KS) g2i_operands<HESS>(gxs, xs, ks + 1, half, e, de, dde);
+        for (int ks = 0; ks < KS; ++ks) {
+            f16x8_t ec[2] = {e[0], e[1]}, dc[2] = {de[0], de[1]}, qc[2] = {dde[0], dde[1]};
+            if (ks + 1 < KS) g2i_operands_h<HESS>(gxs, xs, cf, sk, ks + 1, half, e, de, dde);
 #pragma unroll
-        for (int t = 0; t < TB; ++t) {
-            const bf16x8_t a1 = frag[(0 * KS + ks) * TB * 64 + t * 64 + lane];
-            const bf16x8_t a2 = frag[(1 * KS + ks) * TB * 64 + t * 64 + lane];
-            const bf16x8_t a3 = frag[(2 * KS + ks) * TB * 64 + t * 64 + lane];
-            const f32x16_t zero = {};
-            U[t] = mfma_x6(a1, a2, a3, ec[0], ec[1], ec[2], ks == 0 ? zero : U[t]);
-            V[t] = mfma_x6(a1, a2, a3, dc[0], dc[1], dc[2], ks == 0 ? zero : V[t]);
-            if (HESS) Q[t] = mfma_x6(a1, a2, a3, qc[0], qc[1], qc[2], ks == 0 ? zero : Q[t]);
+            for (int t = 0; t < TB; ++t) {
+                const f16x8_t a1 = frag[(0 * KS + ks) * TB * 64 + t * 64 + lane];
+                const f16x8_t a2 = frag[(1 * KS + ks) * TB * 64 + t * 64 + lane];
+                const f32x16_t zero = {};
+                U[t] = mfma_h3(a1, a2, ec[0], ec[1], ks == 0 ? zero : U[t]);
+                V[t] = mfma_h3(a1, a2, dc[0], dc[1], ks == 0 ? zero : V[t]);
+                if (HESS) Q[t] = mfma_h3(a1, a2, qc[0], qc[1], ks == 0 ? zero : Q[t]);
+            }
+        }
+    } else {
+        const bf16x8_t *frag = reinterpret_cast<const bf16x8_t *>(fraw);
+        bf16x8_t e[3], de[3], dde[3];
+        g2i_operands<HESS>(gxs, xs, 0, half, e, de, dde);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            bf16x8_t ec[3] = {e[0], e[1], e[2]}, dc[3] = {de[0], de[1], de[2]},
+                     qc[3] = {dde[0], dde[1], dde[2]};
+            if (ks + 1 < KS) g2i_operands<HESS>(gxs, xs, ks + 1, half, e, de, dde);
+#pragma unroll
+            for (int t = 0; t < TB; ++t) {
+                const bf16x8_t a1 = frag[(0 * KS + ks) * TB * 64 + t * 64 + lane];
+                const bf16x8_t a2 = frag[(1 * KS + ks) * TB * 64 + t * 64 + lane];
+                const bf16x8_t a3 = frag[(2 * KS + ks) * TB * 64 + t * 64 + lane];
+                const f32x16_t zero = {};
+                U[t] = mfma_x6(a1, a2, a3, ec[0], ec[1], ec[2], ks == 0 ? zero : U[t]);
+                V[t] = mfma_x6(a1, a2, a3, dc[0], dc[1], dc[2], ks == 0 ? zero : V[t]);
+                if (HESS) Q[t] = mfma_x6(a1, a2, a3, qc[0], qc[1], qc[2], ks == 0 ? zero : Q[t]);
+            }
         }
     }
     s = sx = sy = sxx = sxy = syy = 0.0f;
@@ -122,48 +169,32 @@ __device__ __forceinline__ void g2i_eval(const bf16x8_t *frag, const float *gxs,
         sxy += __shfl_xor(sxy, 32, 64);
         syy += __shfl_xor(syy, 32, 64);
     }
+    if (F16) {
+        const int un = -(sc.sw + c);
+        s = ldexpf(s, un);
+        sx = ldexpf(sx, un);
+        sy = ldexpf(sy, un);
+        if (HESS) {
+            sxx = ldexpf(sxx, un + k);
+            sxy = ldexpf(sxy, un);
+            syy = ldexpf(syy, un);
+        }
+    }
 }
 
 // MODE kLogdet: forward morph with the log-determinant.  MODE kInverse: inverse by
 // fixed point (iters per step) with residual and log-determinant.
-template <int TB, int KS, int MODE>
-__global__ void __launch_bounds__(kIvBlock) __attribute__((amdgpu_waves_per_eu(2)))
-k_grid2d_inv(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
-             float kappa, float gscale, const float *x_in, int64_t n, int T, float eta, int iters,
-             float *x_out, float *logdet_out, float *resid_out) {
-    // fragments: frag[(p * KS + ks) * TB + t][lane] = part p of
-    //   W[b = 32t + lane%32][a = 16ks + 8(lane/32) + j], j < 8 (0 outside the grid)
-    __shared__ bf16x8_t frag[3 * KS * TB * 64];
-    __shared__ float gxs[16 * KS];
-    __shared__ float gys[32 * TB];
-    const int M = g0 * g1;
-    for (int idx = threadIdx.x; idx < KS * TB * 64; idx += kIvBlock) {
-        const int ln = idx & 63, t = (idx >> 6) % TB, ks = idx / (64 * TB);
-        const int b = 32 * t + (ln & 31);
-        float v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int a = 16 * ks + 8 * (ln >> 5) + j;
-            v[j] = (a < g0 && b < g1) ? weights[a + (int64_t)g0 * b] : 0.0f;
-        }
-        bf16x8_t p1, p2, p3;
-        split3(v, p1, p2, p3);
-        frag[(0 * KS + ks) * TB * 64 + t * 64 + ln] = p1;
-        frag[(1 * KS + ks) * TB * 64 + t * 64 + ln] = p2;
-        frag[(2 * KS + ks) * TB * 64 + t * 64 + ln] = p3;
-    }
-    for (int a = threadIdx.x; a < 16 * KS; a += kIvBlock)
-        gxs[a] = a < g0 ? kappa * hinges[a] : 0.0f;
-    for (int b = threadIdx.x; b < 32 * TB; b += kIvBlock)
-        gys[b] = b < g1 ? kappa * hinges[(size_t)M + (size_t)g0 * b] : 0.0f;
-    __syncthreads();
-
+template <int TB, int KS, int MODE, bool F16>
+__device__ __forceinline__ void g2i_body(const uint4 *fraw, const SplitScheme &sc,
+                                         const float *gxs, const float *gys, float beta,
+                                         float kappa, float gscale, const float *x_in, int64_t n,
+                                         int T, float eta, int iters, float *x_out,
+                                         float *logdet_out, float *resid_out) {
     const int lane = threadIdx.x & 63, half = lane >> 5;
     const int64_t wave = (int64_t)blockIdx.x * (kIvBlock / 64) + (threadIdx.x >> 6);
     const int64_t i = wave * 32 + (lane & 31);
     const int64_t ic = i < n ? i : n - 1;
     float x = x_in[ic], y = x_in[(size_t)n + ic];
-    const float beta = weights[M];
     const float il2 = gscale * kappa;  // 1 / l^2
     const float g2 = gscale * gscale;
     float ld = 0.0f, rmax = 0.0f;
@@ -174,11 +205,11 @@ k_grid2d_inv(const float *__restrict__ hinges, const float *__restrict__ weights
             const bool last = j == evals - 1;
             float s, sx, sy, sxx = 0.0f, sxy = 0.0f, syy = 0.0f;
             if (last)
-                g2i_eval<TB, KS, true>(frag, gxs, gys, kappa * x, kappa * y, s, sx, sy, sxx, sxy,
-                                       syy);
+                g2i_eval<TB, KS, true, F16>(fraw, sc, gxs, gys, kappa * x, kappa * y, s, sx, sy,
+                                            sxx, sxy, syy);
             else
-                g2i_eval<TB, KS, false>(frag, gxs, gys, kappa * x, kappa * y, s, sx, sy, sxx, sxy,
-                                        syy);
+                g2i_eval<TB, KS, false, F16>(fraw, sc, gxs, gys, kappa * x, kappa * y, s, sx, sy,
+                                             sxx, sxy, syy);
             float c, sp;
             sigmoid_and_slope(s + beta, c, sp);
             const float gx = -gscale * sx, gy = -gscale * sy;  // grad s
@@ -211,6 +242,78 @@ k_grid2d_inv(const float *__restrict__ hinges, const float *__restrict__ weights
     x_out[(size_t)n + i] = y;
     if (logdet_out) logdet_out[i] = ld;
     if (resid_out) resid_out[i] = rmax;
+}
+
+template <int TB, int KS, int MODE>
+__global__ void __launch_bounds__(kIvBlock) __attribute__((amdgpu_waves_per_eu(2)))
+k_grid2d_inv(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
+             float kappa, float gscale, const float *x_in, int64_t n, int T, float eta, int iters,
+             float *x_out, float *logdet_out, float *resid_out) {
+    // fragments: frag[(p * KS + ks) * TB + t][lane] = part p of
+    //   W[b = 32t + lane%32][a = 16ks + 8(lane/32) + j], j < 8 (0 outside the grid):
+    // three bf16 parts of W or two FP16 parts of 2^sw W (the split schemes of
+    // mfma_split.h; every launch here runs T steps, so the scheme test is always made)
+    __shared__ uint4 fraw[3 * KS * TB * 64];
+    __shared__ float gxs[16 * KS];
+    __shared__ float gys[32 * TB];
+    __shared__ SplitRange rg;
+    const int M = g0 * g1;
+    // padding x-coordinates far away: their features are 0 on both schemes
+    for (int a = threadIdx.x; a < 16 * KS; a += kIvBlock)
+        gxs[a] = a < g0 ? kappa * hinges[a] : 1e18f;
+    for (int b = threadIdx.x; b < 32 * TB; b += kIvBlock)
+        gys[b] = b < g1 ? kappa * hinges[(size_t)M + (size_t)g0 * b] : 0.0f;
+    constexpr int kNI = (KS * TB * 64 + kIvBlock - 1) / kIvBlock;
+    float wv8[kNI][8];
+    uint32_t mx = 0, mn = 0xffffffffu;
+#pragma unroll
+    for (int it = 0; it < kNI; ++it) {
+        const int idx = threadIdx.x + it * kIvBlock;
+        const int ln = idx & 63, t = (idx >> 6) % TB, ks = idx / (64 * TB);
+        const int b = 32 * t + (ln & 31);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int a = 16 * ks + 8 * (ln >> 5) + j;
+            const float w = (idx < KS * TB * 64 && a < g0 && b < g1)
+                                ? weights[a + (int64_t)g0 * b] : 0.0f;
+            wv8[it][j] = w;
+            const uint32_t u = __float_as_uint(w) & 0x7fffffffu;
+            mx = max(mx, u);
+            if (u != 0) mn = min(mn, u);
+        }
+    }
+    const SplitScheme sc = split_decide(mx, mn, hinges, g0, kappa, rg);
+#pragma unroll
+    for (int it = 0; it < kNI; ++it) {
+        const int idx = threadIdx.x + it * kIvBlock;
+        if (idx >= KS * TB * 64) break;
+        const int ln = idx & 63, t = (idx >> 6) % TB, ks = idx / (64 * TB);
+        if (sc.fp16) {
+            f16x8_t *frag = reinterpret_cast<f16x8_t *>(fraw);
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = ldexpf(wv8[it][j], sc.sw);
+            f16x8_t p1, p2;
+            split2h(v, p1, p2);
+            frag[(0 * KS + ks) * TB * 64 + t * 64 + ln] = p1;
+            frag[(1 * KS + ks) * TB * 64 + t * 64 + ln] = p2;
+        } else {
+            bf16x8_t *frag = reinterpret_cast<bf16x8_t *>(fraw);
+            bf16x8_t p1, p2, p3;
+            split3(wv8[it], p1, p2, p3);
+            frag[(0 * KS + ks) * TB * 64 + t * 64 + ln] = p1;
+            frag[(1 * KS + ks) * TB * 64 + t * 64 + ln] = p2;
+            frag[(2 * KS + ks) * TB * 64 + t * 64 + ln] = p3;
+        }
+    }
+    __syncthreads();
+    const float beta = weights[M];
+    if (sc.fp16)
+        g2i_body<TB, KS, MODE, true>(fraw, sc, gxs, gys, beta, kappa, gscale, x_in, n, T, eta,
+                                     iters, x_out, logdet_out, resid_out);
+    else
+        g2i_body<TB, KS, MODE, false>(fraw, sc, gxs, gys, beta, kappa, gscale, x_in, n, T, eta,
+                                      iters, x_out, logdet_out, resid_out);
 }
 
 // -------------------------------------------------------- pairwise path ---

@@ -1,5 +1,6 @@
 """GPU parity of the morph's log-determinant, its inverse by fixed point and the
-epsilon mixture (Sec. 3.2, Sec. 3.3) against the FP64 oracle, through the C ABI.
+epsilon mixture (Sec. 3.2, Sec. 3.3) against the FP64 oracle, through the C ABI
+(grid path: both split schemes of the matrix-core contractions).
 
 Tolerances (FP32 against FP64):
   x_T          as the plain morph: 1e-5 max(1, A) max(1, |x_T|_inf), A the oracle's
@@ -110,6 +111,53 @@ def test_inverse_config2_grid_sampled():
     assert np.all(err <= TOL * A * np.maximum(1, np.abs(y_r).max(axis=0))), np.max(err)
     assert np.all(np.abs(ld - ld_r) <= TOL * (ldsc + A * cfg.T))
     assert np.all(resid <= 4 * 2.0 ** -23 * np.maximum(1, np.abs(y).max(axis=0)))
+
+
+@pytest.mark.parametrize("gapped", [False, True], ids=["fp16-edge", "bf16-gapped-axis"])
+def test_logdet_inverse_split_schemes(gapped):
+    """Both split schemes on the log-determinant and the inverse (a hinge x-axis with a
+    10-lengthscale gap takes the bf16 splits), weights down to 2^-18.9 of the largest
+    with random signs and points up to 8 lengthscales outside the grid, where the FP16
+    scheme scales ex dx^2 by 2^(c-k).  One step per decade of the Hessian's size, eta
+    max|Hc| = 0.1: the log-det of a single step is taken at the input on both sides, so
+    its error is the Hessian's, held to the oracle's per-step scale; the inverse of the
+    oracle's forward step (a tenth of that eta, where the fixed point contracts) against
+    the oracle's inverse."""
+    require_gpu()
+    rng = np.random.default_rng(2211 + gapped)
+    g0, g1, ell = 64, 48, 0.3
+    ax = (np.r_[np.linspace(-3, -1.5, 32), np.linspace(1.5, 3, 32)] if gapped
+          else np.linspace(-3, 3, g0)).astype(np.float32)
+    ay = np.linspace(-2, 2, g1).astype(np.float32)
+    j = np.arange(g0 * g1)
+    h = np.stack([ax[j % g0], ay[j // g0]]).astype(np.float32)
+    wb = (10.0 * 2.0 ** rng.uniform(-18.9, 0, g0 * g1 + 1)
+          * rng.choice([-1.0, 1.0], g0 * g1 + 1)).astype(np.float32)
+    wb[-1] = 0.0
+    far = np.stack([rng.uniform(-3 - 8 * ell, 3 + 8 * ell, 400),
+                    rng.uniform(-2 - 8 * ell, 2 + 8 * ell, 400)])
+    x = np.concatenate([rng.uniform(-3, 3, (2, 400)), far], axis=1).astype(np.float32)
+    go = P.Occupancy(dev(h), dev(wb), ell, grid=(g0, g1))
+    oo = oracle_occ(h, wb, ell)
+    hc, _ = O.occ_hess(oo, x)
+    dec = np.floor(np.log10(np.abs(hc).max(axis=(0, 1)))).astype(int)
+    for d in np.unique(dec):
+        sel = np.flatnonzero(dec == d)
+        eta = float(np.float32(0.1 * 10.0 ** (-d)))
+        xs = np.ascontiguousarray(x[:, sel])
+        _, ld = P.morph_logdet(go, dev(xs), 1, eta)
+        _, ld_r, ldsc = O.morph_logdet(oo, xs, 1, eta)
+        e = np.abs(host(ld) - ld_r)
+        assert np.all(e <= TOL * ldsc), (d, float(np.max(e / ldsc)))
+        # the inverse with a tenth of that step, where the fixed point contracts
+        ei = float(np.float32(0.1 * eta))
+        z = O.morph_ws(oo, xs, 1, ei).astype(np.float32)
+        y, _, _ = P.morph_inverse(go, dev(z), 1, ei, 30)
+        y_r, _, _, r_r = O.morph_inverse(oo, z, 1, ei, 30)
+        assert np.all(r_r <= 1e-6 * np.maximum(1, np.abs(y_r).max(axis=0)))
+        _, amp, _, _ = O.morph_ws(oo, y_r, 1, ei, diag=True)
+        err = np.abs(host(y) - y_r).max(axis=0)
+        assert np.all(err <= TOL * np.maximum(1, amp) * np.maximum(1, np.abs(y_r).max(axis=0)))
 
 
 @pytest.mark.parametrize("n", [1, 255, 1000])
