@@ -104,6 +104,10 @@ def parse():
                    help="headline with the pairwise kernel instead of the grid factorisation")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a plain 256 MiB device copy first (scales profiler byte counters)")
+    p.add_argument("--workloads", default="all",
+                   help="comma-separated secondary workloads after the headline: small, "
+                        "density, culled, pipeline, tanh, arm (the 3-D fit and the arm "
+                        "morph), amortised; or all")
     p.add_argument("--train-epochs", type=int, default=None)
     p.add_argument("--train-batches", type=int, default=None)
     return p.parse_args()
@@ -691,6 +695,10 @@ def main():
                                    "(multi-GPU sharding is designed, not built)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    names = ("small", "density", "culled", "pipeline", "tanh", "arm", "amortised")
+    sel = set(names) if args.workloads == "all" else set(args.workloads.split(","))
+    if sel - set(names):
+        sys.exit(f"unknown workloads {sorted(sel - set(names))}; choose from {names}")
     import torch
     import paper_2108_11775_amd as P
     from paper_2108_11775_amd import configs as K, inputs as I
@@ -737,29 +745,37 @@ def main():
     if not args.headline_only:
         wl = {}
         try:
-            wl["ws2d_small"] = small_2d(P, I, K, torch, dev)
-            log("small 2-D done")
-            if hl["sc"]["occ"].grid:
+            if "small" in sel:
+                wl["ws2d_small"] = small_2d(P, I, K, torch, dev)
+                log("small 2-D done")
+            if "density" in sel and hl["sc"]["occ"].grid:
                 wl["density_ws2d"] = density_workload(P, I, K, torch, hl)
                 log(f"log-det / inverse: {wl['density_ws2d']['logdet_ms']:.1f} / "
                     f"{wl['density_ws2d']['inverse_ms']:.1f} ms")
-            wl["culled_ws2d"] = culled_workload(P, I, K, torch, hl)
-            log(f"culled morph: {wl['culled_ws2d']['morph_ms']:.2f} ms")
-            wl["pipeline"] = pipeline_workload(P, I, K, torch, dev, hl)
-            log("producer/consumer done")
-            wl["tanh_ws2d"] = tanh_morph(P, I, K, torch, dev)
-            log(f"tanh-network morph: {wl['tanh_ws2d']['morph_ms']:.2f} ms")
-            world = arm_world(P, I, K, torch, dev)
-            wl["fit3d"] = world["fit"]
-            log(f"3-D fit: {world['fit']['ms_total']:.0f} ms")
-            wl["arm7"] = arm_morph(P, I, K, torch, world)
-            log(f"arm morph: {wl['arm7']['morph_ms']:.1f} ms")
-            wl["amortised"] = amortised(args, P, I, K, torch, world)
-            am = wl["amortised"]
-            eq = am["at_equal_collision_free"]
-            log(f"amortised: speedup {am['speedup']:.2f}x at threshold {K.C5.threshold}; at equal "
-                f"collision-free fraction "
-                + (f"{eq['speedup']:.2f}x (threshold {eq['threshold']})" if eq else "not reached"))
+            if "culled" in sel:
+                wl["culled_ws2d"] = culled_workload(P, I, K, torch, hl)
+                log(f"culled morph: {wl['culled_ws2d']['morph_ms']:.2f} ms")
+            if "pipeline" in sel:
+                wl["pipeline"] = pipeline_workload(P, I, K, torch, dev, hl)
+                log("producer/consumer done")
+            if "tanh" in sel:
+                wl["tanh_ws2d"] = tanh_morph(P, I, K, torch, dev)
+                log(f"tanh-network morph: {wl['tanh_ws2d']['morph_ms']:.2f} ms")
+            if "arm" in sel or "amortised" in sel:
+                world = arm_world(P, I, K, torch, dev)
+                wl["fit3d"] = world["fit"]
+                log(f"3-D fit: {world['fit']['ms_total']:.0f} ms")
+            if "arm" in sel:
+                wl["arm7"] = arm_morph(P, I, K, torch, world)
+                log(f"arm morph: {wl['arm7']['morph_ms']:.1f} ms")
+            if "amortised" in sel:
+                wl["amortised"] = amortised(args, P, I, K, torch, world)
+                am = wl["amortised"]
+                eq = am["at_equal_collision_free"]
+                log(f"amortised: speedup {am['speedup']:.2f}x at threshold {K.C5.threshold}; "
+                    "at equal collision-free fraction "
+                    + (f"{eq['speedup']:.2f}x (threshold {eq['threshold']})" if eq
+                       else "not reached"))
         except Exception as e:  # report what ran; the headline stands on its own
             wl["error"] = f"{type(e).__name__}: {e}"
         out["workloads"] = wl
