@@ -56,7 +56,11 @@ typedef enum {
  *           (x grid[2] in 3-D) points, x fastest: hinge j = i0 + g0 (i1 + g1 i2) has
  *           coordinates (X0[i0], X1[i1], X2[i2]) read from the hinge array itself.
  *           The library may then evaluate the same sums through the factorisation
- *           phi_j = prod_k exp(-(x_k - X_k[i_k])^2 / (2 l^2)) (equal up to rounding).
+ *           phi_j = prod_k exp(-(x_k - X_k[i_k])^2 / (2 l^2)) (equal up to rounding)
+ *           as contractions on the matrix cores at FP32 accuracy: two-part FP16
+ *           splits when every nonzero |w| is at least 2^-19 of the largest and no
+ *           two consecutive X0 coordinates are more than 6 sqrt(2 ln 2) l apart
+ *           (morphs only), three-part BF16 splits otherwise.
  *           Hinges that are not that grid give undefined results.
  * dim must be 2 or 3, M >= 1, lengthscale > 0 and finite. */
 typedef struct {
@@ -157,8 +161,8 @@ int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const
 /* ---- the density of the morphed samples and the inverse map (Sec. 3.2: the flow's
  * inverse integrates the reversed field; the change of variables gives the
  * density p_z(z) = p_y(y) / |det D phi(y)|).  Workspace morph only (no arm);
- * 2-D hinges on a grid (occ->grid) take the FP32-MFMA path, any other hinge set
- * (2-D or 3-D) a pairwise kernel.
+ * 2-D hinges on a grid (occ->grid) take the matrix-core path (FP32-accurate split
+ * contractions, as for the morph), any other hinge set (2-D or 3-D) a pairwise kernel.
  * pdmp_morph_logdet: the plain morph of in into out (as pdmp_morph_samples) and
  *   logdet [n] = sum_k log|det(I - eta Hc(x_k))| along each path (nullable).
  * pdmp_morph_inverse: y = phi^{-1}(z) for the T-step explicit-Euler map, each step
