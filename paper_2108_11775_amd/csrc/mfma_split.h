@@ -1,6 +1,7 @@
-// mfma_split.h -- FP32-accurate contractions on BF16 MFMA (gfx950).
+// mfma_split.h -- FP32-accurate contractions on BF16 or FP16 MFMA (gfx950), and the
+// per-block choice between the two for the grid kernels.
 //
-// Each FP32 operand v is split, rounding to nearest even, into three bf16 parts
+// BF16 scheme.  Each FP32 operand v is split, rounding to nearest even, into three bf16 parts
 // v = v1 + v2 + v3 + r with |v2| <= 2^-8 |v|, |v3| <= 2^-16 |v| and |r| <= 2^-24 |v|
 // (bf16 carries 8 significant bits; every difference is exact in FP32).  Of the nine
 // products of the parts of two operands, the six with v_i w_j, i + j <= 4, are kept:
@@ -75,7 +76,13 @@ __device__ __forceinline__ f32x4_t mfma16_x6(const bf16x8_t &a1, const bf16x8_t 
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc, 0, 0, 0);
 }
 
-// ---- two-part FP16 splits (for operands whose range has been brought inside FP16's) ----
+// ---- FP16 scheme: two-part FP16 splits (for operands whose range has been brought
+// inside FP16's by power-of-two scaling) ----
+//
+// FP16 carries 11 significant bits, so two parts hold 22 and three products of them
+// reach what six products of three bf16 parts do: 3 x 16 = 48 FP16 flops per FP32
+// multiply-add (half the matrix-core time of the BF16 scheme) and about 2 VALU per
+// operand value for the split.
 //
 // v = h1 + h2 + r with both parts FP16 rounded to nearest even: |h2| <= 2^-11 |v| and
 // |r| <= max(2^-22 |v|, 2^-25), 2^-25 being half the FP16 subnormal spacing, for any
