@@ -17,6 +17,7 @@
 // + v%4 of sample l%32, evaluates ey_b for them and the two lanes of a sample are
 // summed by one xor-32 exchange (bit-identical in both lanes).  The T-step loop
 // runs in registers.
+#include "grid2d_stage.h"
 #include "mfma_split.h"
 #include "pdmp_common.h"
 
@@ -116,47 +117,15 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
     // the FP16 scheme's per-block range check pays off over a morph's steps; a single
     // evaluation, whose blocks mostly stage W, keeps the BF16 scheme without it
     constexpr bool allow_fp16 = MODE == kMorph;
-    // fragments, BF16 scheme: frag[(p * KS + ks) * TB + t][lane] = part p < 3 of
-    //   W[b = 32t + lane%32][a = 16ks + 8(lane/32) + j], j < 8 (0 outside the grid);
-    // FP16 scheme: the same with parts p < 2 of 2^sW W
+    // fragments and axes: grid2d_stage.h
     __shared__ uint4 fraw[3 * KS * TB * 64];
     __shared__ float gxs[16 * KS];
     __shared__ float gys[32 * TB];
     __shared__ SplitRange rg;
     const int M = g0 * g1;
     const int lane = threadIdx.x & 63, half = lane >> 5, wv = threadIdx.x >> 6;
-
-    // hinge coordinates (kappa-scaled); padding x-coordinates lie far away so that
-    // their features are 0 on both schemes (their weights are 0)
-    for (int a = threadIdx.x; a < 16 * KS; a += kG2Block)
-        gxs[a] = a < g0 ? kappa * hinges[a] : 1e18f;
-    for (int b = threadIdx.x; b < 32 * TB; b += kG2Block)
-        gys[b] = b < g1 ? kappa * hinges[(size_t)M + (size_t)g0 * b] : 0.0f;
-    // this thread's share of W in fragment order, kept in registers through the range
-    // check; its largest and smallest nonzero magnitude
-    constexpr int kNI = (KS * TB * 64 + kG2Block - 1) / kG2Block;
-    float wv8[kNI][8];
-    SplitScheme sc = {0, 0, 0.0f, 0.0f};
-    {
-        uint32_t mx = 0, mn = 0xffffffffu;
-#pragma unroll
-        for (int it = 0; it < kNI; ++it) {
-            const int idx = threadIdx.x + it * kG2Block;
-            const int ln = idx & 63, t = (idx >> 6) % TB, ks = idx / (64 * TB);
-            const int b = 32 * t + (ln & 31);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int a = 16 * ks + 8 * (ln >> 5) + j;
-                const float w = (idx < KS * TB * 64 && a < g0 && b < g1)
-                                    ? weights[a + (int64_t)g0 * b] : 0.0f;
-                wv8[it][j] = w;
-                const uint32_t u = __float_as_uint(w) & 0x7fffffffu;
-                mx = max(mx, u);
-                if (u != 0) mn = min(mn, u);
-            }
-        }
-        if (allow_fp16) sc = split_decide(mx, mn, hinges, g0, kappa, rg);
-    }
+    const SplitScheme sc =
+        g2_stage<TB, KS, allow_fp16>(fraw, gxs, gys, rg, hinges, weights, g0, g1, kappa);
     const bool fp16 = allow_fp16 && sc.fp16;
     const int sw = sc.sw;
     const float gmin = sc.gmin, gmax = sc.gmax;
@@ -170,21 +139,7 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
     float s = 0.0f, sx = 0.0f, sy = 0.0f;
 
     if (fp16) {
-        f16x8_t *frag = reinterpret_cast<f16x8_t *>(fraw);
-#pragma unroll
-        for (int it = 0; it < kNI; ++it) {
-            const int idx = threadIdx.x + it * kG2Block;
-            if (idx >= KS * TB * 64) break;
-            const int ln = idx & 63, t = (idx >> 6) % TB, ks = idx / (64 * TB);
-            float v[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = ldexpf(wv8[it][j], sw);
-            f16x8_t p1, p2;
-            split2h(v, p1, p2);
-            frag[(0 * KS + ks) * TB * 64 + t * 64 + ln] = p1;
-            frag[(1 * KS + ks) * TB * 64 + t * 64 + ln] = p2;
-        }
-        __syncthreads();
+        const f16x8_t *frag = reinterpret_cast<const f16x8_t *>(fraw);
         for (int st = 0; st < steps; ++st) {
             const float xs = kappa * x, ys = kappa * y;
             // the operand scale 2^c of this sample (both lanes of the pair agree)
@@ -221,19 +176,7 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
             }
         }
     } else {
-        bf16x8_t *frag = reinterpret_cast<bf16x8_t *>(fraw);
-#pragma unroll
-        for (int it = 0; it < kNI; ++it) {
-            const int idx = threadIdx.x + it * kG2Block;
-            if (idx >= KS * TB * 64) break;
-            const int ln = idx & 63, t = (idx >> 6) % TB, ks = idx / (64 * TB);
-            bf16x8_t p1, p2, p3;
-            split3(wv8[it], p1, p2, p3);
-            frag[(0 * KS + ks) * TB * 64 + t * 64 + ln] = p1;
-            frag[(1 * KS + ks) * TB * 64 + t * 64 + ln] = p2;
-            frag[(2 * KS + ks) * TB * 64 + t * 64 + ln] = p3;
-        }
-        __syncthreads();
+        const bf16x8_t *frag = reinterpret_cast<const bf16x8_t *>(fraw);
         for (int st = 0; st < steps; ++st) {
             const float xs = kappa * x, ys = kappa * y;
             f32x16_t U[TB], V[TB];

@@ -20,6 +20,7 @@
 // the accumulator layout as in the plain morph (same lane mapping, same xor-32 pair
 // sum).  Pairwise path (any hinges, 2-D or 3-D): one point per thread, hinges staged
 // in LDS tiles.
+#include "grid2d_stage.h"
 #include "mfma_split.h"
 #include "pdmp_common.h"
 
@@ -249,64 +250,15 @@ __global__ void __launch_bounds__(kIvBlock) __attribute__((amdgpu_waves_per_eu(2
 k_grid2d_inv(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
              float kappa, float gscale, const float *x_in, int64_t n, int T, float eta, int iters,
              float *x_out, float *logdet_out, float *resid_out) {
-    // fragments: frag[(p * KS + ks) * TB + t][lane] = part p of
-    //   W[b = 32t + lane%32][a = 16ks + 8(lane/32) + j], j < 8 (0 outside the grid):
-    // three bf16 parts of W or two FP16 parts of 2^sw W (the split schemes of
-    // mfma_split.h; every launch here runs T steps, so the scheme test is always made)
+    // fragments and axes (grid2d_stage.h); every launch here runs T steps, so the
+    // scheme test is always made
     __shared__ uint4 fraw[3 * KS * TB * 64];
     __shared__ float gxs[16 * KS];
     __shared__ float gys[32 * TB];
     __shared__ SplitRange rg;
     const int M = g0 * g1;
-    // padding x-coordinates far away: their features are 0 on both schemes
-    for (int a = threadIdx.x; a < 16 * KS; a += kIvBlock)
-        gxs[a] = a < g0 ? kappa * hinges[a] : 1e18f;
-    for (int b = threadIdx.x; b < 32 * TB; b += kIvBlock)
-        gys[b] = b < g1 ? kappa * hinges[(size_t)M + (size_t)g0 * b] : 0.0f;
-    constexpr int kNI = (KS * TB * 64 + kIvBlock - 1) / kIvBlock;
-    float wv8[kNI][8];
-    uint32_t mx = 0, mn = 0xffffffffu;
-#pragma unroll
-    for (int it = 0; it < kNI; ++it) {
-        const int idx = threadIdx.x + it * kIvBlock;
-        const int ln = idx & 63, t = (idx >> 6) % TB, ks = idx / (64 * TB);
-        const int b = 32 * t + (ln & 31);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int a = 16 * ks + 8 * (ln >> 5) + j;
-            const float w = (idx < KS * TB * 64 && a < g0 && b < g1)
-                                ? weights[a + (int64_t)g0 * b] : 0.0f;
-            wv8[it][j] = w;
-            const uint32_t u = __float_as_uint(w) & 0x7fffffffu;
-            mx = max(mx, u);
-            if (u != 0) mn = min(mn, u);
-        }
-    }
-    const SplitScheme sc = split_decide(mx, mn, hinges, g0, kappa, rg);
-#pragma unroll
-    for (int it = 0; it < kNI; ++it) {
-        const int idx = threadIdx.x + it * kIvBlock;
-        if (idx >= KS * TB * 64) break;
-        const int ln = idx & 63, t = (idx >> 6) % TB, ks = idx / (64 * TB);
-        if (sc.fp16) {
-            f16x8_t *frag = reinterpret_cast<f16x8_t *>(fraw);
-            float v[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = ldexpf(wv8[it][j], sc.sw);
-            f16x8_t p1, p2;
-            split2h(v, p1, p2);
-            frag[(0 * KS + ks) * TB * 64 + t * 64 + ln] = p1;
-            frag[(1 * KS + ks) * TB * 64 + t * 64 + ln] = p2;
-        } else {
-            bf16x8_t *frag = reinterpret_cast<bf16x8_t *>(fraw);
-            bf16x8_t p1, p2, p3;
-            split3(wv8[it], p1, p2, p3);
-            frag[(0 * KS + ks) * TB * 64 + t * 64 + ln] = p1;
-            frag[(1 * KS + ks) * TB * 64 + t * 64 + ln] = p2;
-            frag[(2 * KS + ks) * TB * 64 + t * 64 + ln] = p3;
-        }
-    }
-    __syncthreads();
+    const SplitScheme sc =
+        g2_stage<TB, KS, true>(fraw, gxs, gys, rg, hinges, weights, g0, g1, kappa);
     const float beta = weights[M];
     if (sc.fp16)
         g2i_body<TB, KS, MODE, true>(fraw, sc, gxs, gys, beta, kappa, gscale, x_in, n, T, eta,
