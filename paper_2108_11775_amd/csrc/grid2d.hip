@@ -61,7 +61,8 @@ __device__ __forceinline__ void h3_operands(const float *gxs, float xs, float cf
     split2h(dv, de[0], de[1]);
 }
 
-// The state of one sample's lane pair across the steps, and its outputs.
+// One sample's outputs, written by the lower lane of its pair: the morphed point, or
+// the logit / occupancy / gradient of a single evaluation.
 template <int MODE>
 __device__ __forceinline__ void g2_finish(float s, float sx, float sy, float beta, float gscale,
                                           float x, float y, int half, int64_t i, int64_t n,

@@ -16,9 +16,8 @@
 // of the plain morph and a third one, Q = W ex dx^2, on the matrix cores at FP32
 // accuracy (the split schemes of mfma_split.h: two-part FP16 splits and three
 // products where the operands' range allows, three-way bf16 splits and six products
-// otherwise); the y sums run on
-// the accumulator layout as in the plain morph (same lane mapping, same xor-32 pair
-// sum).  Pairwise path (any hinges, 2-D or 3-D): one point per thread, hinges staged
+// otherwise); the y sums run on the accumulator layout as in the plain morph (same
+// lane mapping, same xor-32 pair sum).  Pairwise path (any hinges, 2-D or 3-D): one point per thread, hinges staged
 // in LDS tiles.
 #include "grid2d_stage.h"
 #include "mfma_split.h"
