@@ -11,12 +11,13 @@
 //   ds/dz    = -(1/l^2) sum_c ez_c (z - Z_c) sum_b ey_b U_r
 // the same s and grad s as the pairwise sum (rounding aside) for G0 + 16 + G2
 // exponentials and two (16 G2) x G0 matrix-vector products per point.  32 points
-// per wave go through v_mfma_f32_32x32x16_bf16 (A = W rows, B = [ex | ex dx] of the
-// lane's own point, k = a, G0 = 16 in one k-step; two-part FP16 splits of both, three
+// per wave go through the 32x32x16 MFMAs (A = W rows, B = [ex | ex dx] of the lane's
+// own point, k = a, G0 = 16 in one k-step; two-part FP16 splits of both and three
 // products per contraction, or three-way bf16 splits and six products when the
-// operands' range needs FP32's exponent range); each 32-row tile holds two z-planes (c = 2t, 2t+1), so
-// in the accumulator layout lane l owns the fixed y indices b = (8(v/4) + 4(l/32)
-// + v%4) mod 16 and the y/z contractions need only per-lane tables of ey and ez.
+// operands' range needs FP32's exponent range); each 32-row tile holds two z-planes
+// (c = 2t, 2t+1), so in the accumulator layout lane l owns the fixed y indices
+// b = (8(v/4) + 4(l/32) + v%4) mod 16 and the y/z contractions need only per-lane
+// tables of ey and ez.
 // The two lanes of a point are summed by one xor-32 exchange (bit-identical).
 //
 // Arm mapping: a wave carries 4 configurations x 8 body points of one link at a
@@ -45,8 +46,9 @@ struct G3 {
 };
 
 // Stage W fragments (frag[(p*TB + t)*64 + lane] = part p of W[32t + lane%32][8(lane/32)
-// + j], j < 8) and the prescaled axes into LDS, choosing the scheme.  All kG3Block
-// threads call it; the caller synchronises before reading the fragments.
+// + j], j < 8: three bf16 parts, or two FP16 parts of 2^sw W) and the prescaled axes
+// into LDS, choosing the scheme when allow16 (else the BF16 parts, no check).  All
+// kG3Block threads call it; the caller synchronises before reading the fragments.
 template <int G0, int G2>
 __device__ __forceinline__ SplitScheme g3_stage(uint4 *fraw, float *ax, float *ay, float *az,
                                              SplitRange &rg, const float *__restrict__ hinges,
