@@ -63,6 +63,22 @@ def grid2d_traffic():
     return GRID2D_TRAFFIC["bytes"] if grid2d_sources_sha() == GRID2D_TRAFFIC["sha256"] else None
 
 
+# Issue-slot use of the headline kernel from one rocprofv3 --pmc run on the same launch
+# (profiles/utilisation_ws2d_1M.md): VALU instructions per SIMD per active cycle over
+# the 1-per-4-cycles wave64 issue rate, and the MFMA pipe's busy fraction.  Reported
+# only while the sources are the ones the counters were taken on.
+GRID2D_UTILISATION = {"valu_issue_frac": 0.196 * 4, "mfma_busy_frac": 0.512,
+                      "sha256": GRID2D_TRAFFIC["sha256"]}
+
+
+def grid2d_utilisation():
+    u = GRID2D_UTILISATION
+    if grid2d_sources_sha() != u["sha256"]:
+        return None
+    return {"valu_issue_frac": u["valu_issue_frac"], "mfma_busy_frac": u["mfma_busy_frac"],
+            "binding_unit": "VALU issue", "source": "profiles/utilisation_ws2d_1M.md"}
+
+
 def split_scheme(x_axis, weights, ell):
     """The split scheme the grid morph kernels take for these operands (each block of
     the kernel decides the same from the same data): two-part FP16 splits, three
@@ -229,6 +245,7 @@ def headline(args, P, I, K, torch, dev):
                            "unit": "TFLOP/s", "frac": achieved * 1e12 / peak,
                            "traffic": grid2d_traffic(), "kernel": "k_grid2d_mfma<2,4,kMorph>",
                            "kernel_ms": morph_ms, "split_scheme": scheme,
+                           "utilisation": grid2d_utilisation(),
                            "work": f"{4 * nprod}*G0*G1 {scheme.upper()} MFMA flops per "
                                    "sample-step (64x64 grid): the two FP32 contractions "
                                    f"(4*G0*G1 flops) as the {nprod} leading products of the "
