@@ -124,6 +124,9 @@ def _wide_case(rng, g0, g1, ell, ax, ay, log2_range):
     h = np.stack([ax[j % g0], ay[j // g0]]).astype(np.float32)
     mag = 10.0 * 2.0 ** rng.uniform(-log2_range, 0, g0 * g1 + 1)
     wb = (mag * rng.choice([-1.0, 1.0], g0 * g1 + 1)).astype(np.float32)
+    # a tenth of the weights exactly +0 or -0: the range test skips zeros
+    zero = rng.random(g0 * g1) < 0.1
+    wb[:-1][zero] = np.where(rng.random(zero.sum()) < 0.5, 0.0, -0.0).astype(np.float32)
     wb[-1] = 0.0
     lo, hi = ax.min(), ax.max()
     far = np.stack([rng.uniform(lo - 8 * ell, hi + 8 * ell, 500),
@@ -151,9 +154,9 @@ def _wide_case(rng, g0, g1, ell, ax, ay, log2_range):
 
 def test_grid_fp16_scheme_range_edge():
     """The FP16 split scheme (morphs) at the edge of its range: nonzero weights down to
-    2^-18.9 of the largest (the scheme takes 2^-19), random signs, samples up to 8
-    lengthscales outside the grid, where each sample's operand scale 2^c carries the
-    features that FP16 alone could not hold."""
+    2^-18.9 of the largest (the scheme takes 2^-19), random signs, a tenth of them +-0,
+    samples up to 8 lengthscales outside the grid, where each sample's operand scale
+    2^c carries the features that FP16 alone could not hold."""
     require_gpu()
     rng = np.random.default_rng(1619)
     g0, g1, ell = 64, 48, 0.3

@@ -81,6 +81,8 @@ def test_grid3d_split_schemes(gapped):
     h = _grid3(ax)
     mag = 2.0 ** rng.uniform(-18.9, 0, 4097)
     wb = (mag * rng.choice([-1.0, 1.0], 4097)).astype(np.float32)
+    zero = rng.random(4096) < 0.1  # +-0 weights: the range test skips zeros
+    wb[:-1][zero] = np.where(rng.random(zero.sum()) < 0.5, 0.0, -0.0).astype(np.float32)
     wb[-1] = 0.0
     lo, hi = ax.min(), ax.max()
     x = np.concatenate([
