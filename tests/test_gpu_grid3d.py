@@ -7,6 +7,7 @@ import math
 import numpy as np
 import pytest
 
+import bench
 import oracle as O
 import paper_2108_11775_amd as P
 from paper_2108_11775_amd import configs as K, inputs as I
@@ -140,17 +141,25 @@ def test_grid3d_arm_one_step_full_size_sampled():
     assert np.all(err <= tol), np.max(err / tol)
 
 
+@pytest.mark.parametrize("scheme", ["fp16", "bf16"])
 @pytest.mark.parametrize("n", [37, 200])
-def test_grid3d_arm_T_steps(n):
+def test_grid3d_arm_T_steps(n, scheme):
+    """The arm morph over T steps on either split scheme: the fitted weights take the
+    FP16 splits; one weight set to 2^-30 of the largest puts them outside that scheme's
+    range, so the arm kernel takes the three-way bf16 splits (the field barely moves)."""
     require_gpu()
     sc = arm_scene()
+    wb = sc["wb"].copy()
+    if scheme == "bf16":
+        wb[17] = np.float32(np.abs(wb[:-1]).max() * 2.0 ** -30)
+    assert bench.split_scheme(sc["h"][0, :16], wb[:-1], sc["ell"])[0] == scheme
     ao, ag = _arms(sc)
     c3 = K.C3
     q0 = O.uniform_samples(I.philox_seed(c3.cfg_id), 7, [c3.q_lo] * 7, [c3.q_hi] * 7, n)
-    out = host(P.morph_samples(gpu_occ(sc["h"], sc["wb"], sc["ell"], G), dev(q0), c3.T, c3.eta,
+    out = host(P.morph_samples(gpu_occ(sc["h"], wb, sc["ell"], G), dev(q0), c3.T, c3.eta,
                                arm=ag))
     idx = np.arange(n) if n <= 40 else np.unique(np.r_[np.arange(0, n, n // 24), n - 1])
-    ref, amp, _ = O.morph_arm(ao, oracle_occ(sc["h"], sc["wb"], sc["ell"]), q0[:, idx], c3.T,
+    ref, amp, _ = O.morph_arm(ao, oracle_occ(sc["h"], wb, sc["ell"]), q0[:, idx], c3.T,
                               c3.eta, diag=True)
     err = np.abs(out[:, idx] - ref).max(axis=0)
     tol = TOL * np.maximum(1.0, amp) * np.maximum(1.0, np.abs(ref).max(axis=0))
