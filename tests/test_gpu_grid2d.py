@@ -4,6 +4,7 @@ tolerances as the pairwise path."""
 import numpy as np
 import pytest
 
+import bench
 import oracle as O
 import paper_2108_11775_amd as P
 from paper_2108_11775_amd import configs as K, inputs as I
@@ -174,10 +175,12 @@ def test_grid_bf16_fallback_gapped_axis():
     _wide_case(rng, g0, g1, ell, ax, np.linspace(-2, 2, g1).astype(np.float32), 10.0)
 
 
-def test_grid_large_batch_ragged_grid_sampled():
+@pytest.mark.parametrize("scheme", ["fp16", "bf16"])
+def test_grid_large_batch_ragged_grid_sampled(scheme):
     """Morphs of 2^17 samples and more take the 32-sample waves (smaller morphs the
     16-sample waves, which the other morph cases here exercise): a ragged 45 x 37
-    grid, 2^17 + 333 samples, outputs sampled every 293rd sample."""
+    grid, 2^17 + 333 samples, outputs sampled every 293rd sample; on the FP16 splits,
+    and on the bf16 splits with one weight at 2^-30 of the largest."""
     require_gpu()
     rng = np.random.default_rng(4537)
     g0, g1 = 45, 37
@@ -186,6 +189,9 @@ def test_grid_large_batch_ragged_grid_sampled():
     j = np.arange(g0 * g1)
     h = np.stack([ax[j % g0], ay[j // g0]]).astype(np.float32)
     wb = rng.normal(0, 1.5, g0 * g1 + 1).astype(np.float32)
+    if scheme == "bf16":
+        wb[100] = np.float32(np.abs(wb[:-1]).max() * 2.0 ** -30)
+    assert bench.split_scheme(ax, wb[:-1], 0.5)[0] == scheme
     n = (1 << 17) + 333
     x = rng.uniform(-3.5, 3.5, (2, n)).astype(np.float32)
     go = _grid_occ(h, wb, 0.5, g0, g1)
