@@ -3,7 +3,8 @@
 //
 // BF16 scheme.  Each FP32 operand v is split, rounding to nearest even, into three bf16 parts
 // v = v1 + v2 + v3 + r with |v2| <= 2^-8 |v|, |v3| <= 2^-16 |v| and |r| <= 2^-24 |v|
-// (bf16 carries 8 significant bits; every difference is exact in FP32).  Of the nine
+// (bf16 carries 8 significant bits; every difference is exact in FP32) while the
+// parts are normal numbers, |v| >= 2^-110; below, |r| is at most 2^-133.  Of the nine
 // products of the parts of two operands, the six with v_i w_j, i + j <= 4, are kept:
 // the three dropped ones are below 2^-24 of the product.  Products of bf16 parts are
 // exact and v_mfma_f32_32x32x16_bf16 accumulates them in FP32, so a contraction
