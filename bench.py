@@ -47,7 +47,7 @@ FLOPS_PER_PAIR = {2: 12, 3: 17}    # 5*dim + 2 algorithmic FP32 flops per sample
 # the counters were taken on.
 GRID2D_SOURCES = ("grid2d.hip", "grid2d_stage.h", "mfma_split.h", "pdmp_common.h")
 GRID2D_TRAFFIC = {"bytes": (4277.2 * 2.0 + 8192.0) * 1024,
-                  "sha256": "fc04b23f2be604f5e7e3bfd9e0d09f1f9e9deed0ea7c084438b2d11d3e6962e9"}
+                  "sha256": "d229082475ca13e669b2699802e7c52a3f4696b442ad88bb32c9a3c20c5afdcc"}
 
 
 def grid2d_sources_sha():
@@ -67,7 +67,7 @@ def grid2d_traffic():
 # (profiles/utilisation_ws2d_1M.md): VALU instructions per SIMD per active cycle over
 # the 1-per-4-cycles wave64 issue rate, and the MFMA pipe's busy fraction.  Reported
 # only while the sources are the ones the counters were taken on.
-GRID2D_UTILISATION = {"valu_issue_frac": 0.196 * 4, "mfma_busy_frac": 0.512,
+GRID2D_UTILISATION = {"valu_issue_frac": 0.198 * 4, "mfma_busy_frac": 0.518,
                       "sha256": GRID2D_TRAFFIC["sha256"]}
 
 
