@@ -32,7 +32,7 @@ __device__ __forceinline__ double block_tree_sum(double v, double *sh) {
     sh[threadIdx.x] = v;
     __syncthreads();
 #pragma unroll
-    for (int off = kRedBlock / 2; off >= 1; off >>= 1) {
+    for (unsigned off = kRedBlock / 2; off >= 1; off >>= 1) {
         if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
         __syncthreads();
     }
@@ -214,7 +214,7 @@ static int32_t launch_pairwise_wgrad(int dim, const float *hinges, int M, float 
     return launch_rbf(dim, kEval, a, st);
 }
 
-size_t bce_ws_bytes(int64_t n) { return align256(kRedMaxBlocks * sizeof(double)); }
+size_t bce_ws_bytes(int64_t) { return align256(kRedMaxBlocks * sizeof(double)); }
 
 size_t fit_ws_bytes(int dim, int M, int64_t n) {
     return bwd_ws_bytes(dim, M, n) + 2 * align256((size_t)n * sizeof(float)) +

@@ -217,7 +217,7 @@ k_mse(const float *__restrict__ qhat, const float *__restrict__ tgt, int n_out, 
     }
     sh[threadIdx.x] = acc;
     __syncthreads();
-    for (int off = 128; off >= 1; off >>= 1) {
+    for (unsigned off = 128; off >= 1; off >>= 1) {
         if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
         __syncthreads();
     }
@@ -231,7 +231,7 @@ k_final_scaled(const double *__restrict__ parts, int np, double scale, float *ou
     for (int i = threadIdx.x; i < np; i += 256) acc += parts[i];
     sh[threadIdx.x] = acc;
     __syncthreads();
-    for (int off = 128; off >= 1; off >>= 1) {
+    for (unsigned off = 128; off >= 1; off >>= 1) {
         if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
         __syncthreads();
     }

@@ -649,7 +649,7 @@ k_tanh_wsq(const float *__restrict__ P, int dim, int H, int L, double *out) {
     }
     sh[threadIdx.x] = acc;
     __syncthreads();
-    for (int s2 = 128; s2 >= 1; s2 >>= 1) {
+    for (unsigned s2 = 128; s2 >= 1; s2 >>= 1) {
         if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
         __syncthreads();
     }
