@@ -73,6 +73,12 @@ def test_grid_morph_config2_full_size_sampled():
                                 diag=True)
     err = np.abs(out[:, idx] - ref).max(axis=0)
     assert np.all(err <= TOL * np.maximum(1, amp) * np.maximum(1, np.abs(ref).max(axis=0)))
+    # the same launch again gives the same bits, and a sample's result does not depend
+    # on its place in the batch (the batch rolled by 12,345, same kernel)
+    assert np.array_equal(host(P.morph_samples(go, x0_d, cfg.T, cfg.eta)), out)
+    rolled = host(P.morph_samples(go, dev(np.ascontiguousarray(np.roll(x0, 12345, axis=1))),
+                                  cfg.T, cfg.eta))
+    assert np.array_equal(np.roll(rolled, -12345, axis=1), out)
 
 
 def test_grid_morph_config1_full_and_deterministic():
