@@ -149,6 +149,42 @@ def test_amortised_matches_oracle():
     assert np.all(np.abs(out[:, keep] - ref[:, keep]) <= 2e-2 * (np.abs(ref[:, keep] - q[:, keep]) + 0.05))
 
 
+def test_amortised_config5_full_batch_sampled():
+    """The amortised morph at the workload's size and network: 7-256-256-256-7 (random
+    initialisation, last layer scaled down) on 65,536 configurations in one call, its
+    outputs sampled every 1,600th against the oracle's amortised morph of those
+    configurations (a configuration's result does not depend on the rest of the
+    batch)."""
+    require_gpu()
+    sc = arm_scene()
+    a, d, al, th = sc["dh"]
+    arm_o, arm_g = O.Arm(a, d, al, th, 8), P.Arm(a, d, al, th, 8)
+    widths = (7, 256, 256, 256, 7)
+    layers = _net(widths, seed=9)
+    layers[-1] = (layers[-1][0] * 0.05, layers[-1][1] * 0.05)
+    mlp = P.Mlp.from_layers(layers)
+    c3 = K.C3
+    n = c3.n_samples
+    q = O.uniform_samples(I.philox_seed(c3.cfg_id), 11, [c3.q_lo] * 7, [c3.q_hi] * 7, n)
+    out, flag, _ = P.amortised_morph(mlp, gpu_occ(sc["h"], sc["wb"], sc["ell"]), arm_g,
+                                     dev(q), c3.T, c3.eta)
+    idx = np.unique(np.r_[0, np.arange(1, n, 1600), n - 1])
+    out, flag, qs = host(out)[:, idx], host(flag)[idx], np.ascontiguousarray(q[:, idx])
+    oo = oracle_occ(sc["h"], sc["wb"], sc["ell"])
+    lb = [(_bf16(W), b) for W, b in layers]
+    ref, fref, maxc = O.amortised_morph(widths, O.mlp_pack(lb), arm_o, oo, qs, c3.T, c3.eta)
+    sure = np.abs(maxc - 0.5) > 2e-2
+    assert sure.sum() >= 0.8 * idx.size
+    assert np.array_equal(flag[sure], fref[sure])
+    both = sure & (flag == 1)
+    assert both.any() and (sure & (flag == 0)).any()
+    _, amp, _ = O.morph_arm(arm_o, oo, qs[:, both], c3.T, c3.eta, diag=True)
+    err = np.abs(out[:, both] - ref[:, both]).max(axis=0)
+    assert np.all(err <= 1e-5 * np.maximum(1, amp) * np.maximum(1, np.abs(ref[:, both]).max(axis=0)))
+    keep = sure & (flag == 0)
+    assert np.all(np.abs(out[:, keep] - ref[:, keep]) <= 2e-2 * (np.abs(ref[:, keep] - qs[:, keep]) + 0.05))
+
+
 def test_training_reduces_loss_and_fallbacks():
     """The trained network beats the method without it: fewer fallbacks than the
     zero network (q_hat = q) on held-out configurations."""
