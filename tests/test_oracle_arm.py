@@ -141,3 +141,54 @@ def test_config_labels_match_point_labels_of_body_points():
     assert 0.10 <= free <= 0.60  # within the span of Table 1's prior feasibility
     margin = O.config_label_margin(arm, bc, be, q)
     assert np.all(margin >= 0)
+
+
+def _line_arm():
+    """Two links of length 1 along the base x axis at q = 0 (alpha = d = theta0 = 0),
+    four body points per link: the points are (k/4, 0, 0), k = 1..8, all exact."""
+    return O.Arm(np.array([1.0, 1.0]), np.zeros(2), np.zeros(2), np.zeros(2), 4)
+
+
+@pytest.mark.parametrize("centre,half,margin,label", [
+    # box beyond the arm tip: nearest point (2,0,0), 3 - 2 - 0.5 = 0.5 outside
+    ((3.0, 0.0, 0.0), (0.5, 0.5, 0.5), 0.5, 0),
+    # the tip lies exactly on the box's face x = 2: inside (closed), margin 0
+    ((2.5, 0.0, 0.0), (0.5, 1.0, 1.0), 0.0, 1),
+    # points 0.75, 1, 1.25 inside a box of half-width 0.125 around x = 1: the deepest
+    # point (1,0,0) is 0.125 from the x faces; 0.75 and 1.25 lie on them -> 0
+    ((1.0, 0.25, 0.0), (0.25, 0.5, 0.5), 0.0, 1),
+    ((1.0, 0.25, 0.0), (0.125, 0.5, 0.5), 0.125, 1),
+    # a slab above the arm: every point is 2 - 1.5 = 0.5 below its y face
+    ((1.0, 2.0, 0.0), (5.0, 1.5, 5.0), 0.5, 0),
+    # a box below in z, corner side: max over axes of |p_a - c_a| - e_a is 0.25 (z)
+    ((1.0, 0.0, -0.75), (4.0, 4.0, 0.5), 0.25, 0),
+])
+def test_config_label_margin_hand_built_scene(centre, half, margin, label):
+    arm = _line_arm()
+    c = np.array(centre, np.float64).reshape(3, 1)
+    e = np.array(half, np.float64).reshape(3, 1)
+    q = np.zeros((2, 1))
+    assert O.config_label_margin(arm, c, e, q)[0] == margin
+    assert O.label_configs(arm, c, e, q)[0] == label
+
+
+def test_config_label_margin_is_the_flip_distance():
+    """Moving the box toward the arm by just over the margin flips an outside label;
+    by just under it does not (the margin is a distance, taken over all boxes)."""
+    arm = _line_arm()
+    q = np.zeros((2, 1))
+    e = np.array([[0.5], [0.5], [0.5]])
+    far = np.array([[3.0, 0.0], [0.0, 5.0], [0.0, 0.0]])   # two boxes: x at 0.5, y far
+    ef = np.array([[0.5, 0.5], [0.5, 0.5], [0.5, 0.5]])
+    mg = O.config_label_margin(arm, far, ef, q)[0]
+    assert mg == 0.5
+    for shift, lab in [(mg - 1e-9, 0), (mg + 1e-9, 1)]:
+        c = far.copy()
+        c[0, 0] -= shift
+        assert O.label_configs(arm, c, ef, q)[0] == lab
+    # one box only, moved along y onto the arm by the same rule
+    c = np.array([[1.0], [0.75], [0.0]])
+    mg = O.config_label_margin(arm, c, e, q)[0]
+    assert mg == 0.25
+    assert O.label_configs(arm, c - [[0], [mg - 1e-9], [0]], e, q)[0] == 0
+    assert O.label_configs(arm, c - [[0], [mg + 1e-9], [0]], e, q)[0] == 1

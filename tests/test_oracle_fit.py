@@ -138,3 +138,38 @@ def test_logit_backward_is_exact_change_of_logit():
     assert gw[M] == pytest.approx(g.sum(), rel=1e-13)
     _, _, gs, _ = O.occ_grad(O.Occupancy(h, w, 0.0, ell), pts)
     np.testing.assert_allclose(gx, g[None, :] * gs, rtol=1e-14, atol=1e-16)
+
+
+def test_logit_backward_subset_equals_full_backward_bit_for_bit():
+    """The subset form sums the same terms in the same order as the full weight
+    backward (itself pinned above against the exact change of the logit), so every
+    listed hinge's value is identical; the absolute form equals the full backward of
+    |g|.  Repeated and unordered hinge indices included."""
+    h, ell, pts, _ = _problem(dim=3, M=27, n=301, seed=8, ell=0.7)
+    M = h.shape[1]
+    rng = np.random.default_rng(9)
+    g = rng.normal(size=pts.shape[1])
+    js = np.r_[rng.permutation(M)[:11], 4, 4, 0, M - 1]
+    out, ab = O.logit_bwd_w_subset(h, ell, pts, g, js)
+    gw, _ = O.logit_bwd(h, np.zeros(M), ell, pts, g, want_x=False)
+    gw_abs, _ = O.logit_bwd(h, np.zeros(M), ell, pts, np.abs(g), want_x=False)
+    assert np.array_equal(out, gw[js])
+    assert np.array_equal(ab, gw_abs[js])
+
+
+def test_logit_backward_subset_closed_form():
+    """One hinge at the origin and points on the axes at r = 0, l, 2l, 3l: the
+    features are 1, e^-1/2, e^-2, e^-9/2, so the sums are written out by hand, with
+    mixed-sign upstream gradients for the absolute form."""
+    ell = 0.625
+    h = np.zeros((2, 1))
+    x = np.array([[0.0, ell, 0.0, -2 * ell, 0.0],
+                  [0.0, 0.0, -ell, 0.0, 3 * ell]])
+    g = np.array([0.5, -2.0, 3.0, 1.25, -0.75])
+    phi = np.array([1.0, math.exp(-0.5), math.exp(-0.5), math.exp(-2.0), math.exp(-4.5)])
+    out, ab = O.logit_bwd_w_subset(h, ell, x, g, [0])
+    assert out[0] == pytest.approx(float(np.dot(g, phi)), rel=1e-15)
+    assert ab[0] == pytest.approx(float(np.dot(np.abs(g), phi)), rel=1e-15)
+    # a hinge far from every point: every feature underflows to zero
+    out, ab = O.logit_bwd_w_subset(np.array([[1e3], [0.0]]), ell, x, g, [0])
+    assert out[0] == 0.0 and ab[0] == 0.0
