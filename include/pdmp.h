@@ -158,6 +158,18 @@ int32_t pdmp_occupancy_grad(const pdmp_occupancy *occ, const float *x, int64_t n
 int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,
                            float *out, int64_t n, int32_t T, float eta, void *stream);
 
+/* The same morph (Sec. 3.2, Eq. 1 and Eq. 3) with the explicit-Euler path of every
+ * traj_stride-th sample written out, so that each step can be checked on its own:
+ * traj (device, [(T+1)][rows][nt], rows = occ->dim or arm->n_dof,
+ * nt = ceil(n / traj_stride)) receives state k (k = 0..T; state 0 the input, state T
+ * the output) of sample i, for every i with i % traj_stride == 0, at
+ * traj[(k rows + r) nt + i / traj_stride].  Same kernels, launch and arithmetic as
+ * pdmp_morph_samples: out receives the same bits.  traj_stride >= 1; traj must not
+ * overlap in or out. */
+int32_t pdmp_morph_trajectory(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,
+                              float *out, int64_t n, int32_t T, float eta, float *traj,
+                              int64_t traj_stride, void *stream);
+
 /* ---- the density of the morphed samples and the inverse map (Sec. 3.2: the flow's
  * inverse integrates the reversed field; the change of variables gives the
  * density p_z(z) = p_y(y) / |det D phi(y)|).  Workspace morph only (no arm);
@@ -268,9 +280,10 @@ int32_t pdmp_occupancy_bwd(const pdmp_occupancy *occ, const float *x, int64_t n,
 
 /* Mean binary cross-entropy of sigma(s) against labels y (nonzero = 1), in the
  * overflow-free form max(s,0) - y s + log(1 + exp(-|s|)).  loss (nullable): device
- * [1]; g_s (nullable): device [n], dL/ds_i = (sigma(s_i) - y_i)/n. */
-int32_t pdmp_bce_logits(const float *s, const uint8_t *y, int64_t n, float *loss, float *g_s,
-                        void *ws, size_t ws_bytes, void *stream);
+ * [1]; g_s (nullable): device [n], dL/ds_i = (sigma(s_i) - y_i)/n, times g_scale[0]
+ * when g_scale (nullable, device [1]: the upstream gradient of the loss) is given. */
+int32_t pdmp_bce_logits(const float *s, const uint8_t *y, int64_t n, const float *g_scale,
+                        float *loss, float *g_s, void *ws, size_t ws_bytes, void *stream);
 
 /* One Adam update (Kingma & Ba 2015, Alg. 1) of n device parameters p with gradient
  * g and state m, v (all FP32, in place), at step t >= 1.  The first n_decay entries

@@ -73,7 +73,9 @@ def _load():
                                      C.c_double, _dp, _i64, C.c_int, _dp, _dp]),
         "orc_morph_arm": (None, [C.c_int, C.c_int, _dp, C.c_int, _dp, _dp, C.c_double,
                                  C.c_double, _dp, _i64, C.c_int, C.c_double, _dp, _dp, _dp,
-                                 C.c_double]),
+                                 _dp, C.c_double]),
+        "orc_arm_step_scale": (None, [C.c_int, C.c_int, _dp, C.c_int, _dp, _dp, C.c_double,
+                                      C.c_double, _dp, _i64, _dp]),
         "orc_label_configs": (None, [C.c_int, C.c_int, _dp, _dp, _dp, C.c_int, _dp, _i64, _u8p]),
         "orc_config_label_margin": (None, [C.c_int, C.c_int, _dp, _dp, _dp, C.c_int, _dp, _i64,
                                            _dp]),
@@ -401,17 +403,33 @@ def arm_cost_grad(arm: Arm, occ: Occupancy, q, form: int = 0):
 
 
 def morph_arm(arm: Arm, occ: Occupancy, q, T: int, eta: float, diag: bool = False,
-              fd_h: float = 1e-5):
-    """Joint-space explicit-Euler morph; with diag also (amplification, min det)."""
+              fd_h: float = 1e-5, with_eh: bool = False):
+    """Joint-space explicit-Euler morph; with diag also (amplification, min det), and
+    with with_eh also the largest eta |H_q|_2 along each path."""
     q = _d(q)
     n = q.shape[1]
     out = _zeros(arm.ndof, n)
     amp = _zeros(n) if diag else None
     mdet = _zeros(n) if diag else None
+    meh = _zeros(n) if diag and with_eh else None
     _, M, h, w, beta, ell = occ.args()
     _load().orc_morph_arm(arm.ndof, arm.ppl, _P(arm.dh()), M, h, w, beta, ell, _P(q), n,
-                          int(T), float(eta), _P(out), _P(amp), _P(mdet), float(fd_h))
-    return (out, amp, mdet) if diag else out
+                          int(T), float(eta), _P(out), _P(amp), _P(mdet), _P(meh), float(fd_h))
+    if not diag:
+        return out
+    return (out, amp, mdet, meh) if with_eh else (out, amp, mdet)
+
+
+def arm_step_scale(arm: Arm, occ: Occupancy, q):
+    """Per configuration: sum over body points of max_j |J_p[:, j]|_1 G_abs(p), the
+    scale FP32-class errors of the body-point gradients carry into grad_q."""
+    q = _d(q)
+    n = q.shape[1]
+    out = _zeros(n)
+    _, M, h, w, beta, ell = occ.args()
+    _load().orc_arm_step_scale(arm.ndof, arm.ppl, _P(arm.dh()), M, h, w, beta, ell, _P(q), n,
+                               _P(out))
+    return out
 
 
 def label_configs(arm: Arm, centres, half, q):

@@ -705,17 +705,18 @@ void orc_arm_cost_grad(int ndof, int ppl, const double *dh, int M, const double 
 
 /* Joint-space morph q_{k+1} = q_k - eta * grad_q c(q_k) (brute-force pull-back).
  * amp (nullable): product of |I - eta H_q|_2 with H_q the central-difference
- * Jacobian (step fd_h) of the analytic gradient, symmetrised.  min_det likewise. */
+ * Jacobian (step fd_h) of the analytic gradient, symmetrised.  min_det likewise;
+ * max_eh (nullable): the largest eta |H_q|_2 along the path. */
 void orc_morph_arm(int ndof, int ppl, const double *dh, int M, const double *h, const double *w,
                    double beta, double ell, const double *qin, int64_t n, int T, double eta,
-                   double *qout, double *amp, double *min_det, double fd_h) {
+                   double *qout, double *amp, double *min_det, double *max_eh, double fd_h) {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t s = 0; s < n; ++s) {
         double qs[ORC_MAX_DOF], gq[ORC_MAX_DOF];
-        double A = 1.0, mdet = INFINITY;
+        double A = 1.0, mdet = INFINITY, meh = 0.0;
         for (int j = 0; j < ndof; ++j) qs[j] = qin[(int64_t)j * n + s];
         for (int t = 0; t < T; ++t) {
-            if (amp || min_det) {
+            if (amp || min_det || max_eh) {
                 double H[ORC_MAX_DOF * ORC_MAX_DOF];
                 for (int b = 0; b < ndof; ++b) {
                     double qp[ORC_MAX_DOF], qm[ORC_MAX_DOF], gp[ORC_MAX_DOF], gm[ORC_MAX_DOF];
@@ -731,6 +732,7 @@ void orc_morph_arm(int ndof, int ppl, const double *dh, int M, const double *h, 
                 step_jac_stats(ndof, H, eta, &nm, &det, &hn);
                 A *= nm;
                 if (det < mdet) mdet = det;
+                if (eta * hn > meh) meh = eta * hn;
             }
             arm_cost_grad1(ndof, ppl, dh, M, h, w, beta, ell, qs, 0, gq);
             for (int j = 0; j < ndof; ++j) qs[j] = qs[j] - eta * gq[j];
@@ -738,6 +740,39 @@ void orc_morph_arm(int ndof, int ppl, const double *dh, int M, const double *h, 
         for (int j = 0; j < ndof; ++j) qout[(int64_t)j * n + s] = qs[j];
         if (amp) amp[s] = A;
         if (min_det) min_det[s] = mdet;
+        if (max_eh) max_eh[s] = meh;
+    }
+}
+
+/* Error scale of one joint-space step's gradient: sum over body points p of
+ * max_j |J_p[:, j]|_1 G_abs(p), J_p the positional Jacobian (columns z_j x (p - o_j)
+ * for the joints before p's link) and G_abs(p) the workspace gradient's scale -- the
+ * bound that FP32-class errors of each body point's grad c carry into grad_q. */
+void orc_arm_step_scale(int ndof, int ppl, const double *dh, int M, const double *h,
+                        const double *w, double beta, double ell, const double *q, int64_t n,
+                        double *scale) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < n; ++s) {
+        double qs[ORC_MAX_DOF], o[ORC_MAX_DOF + 1][3], z[ORC_MAX_DOF + 1][3];
+        for (int j = 0; j < ndof; ++j) qs[j] = q[(int64_t)j * n + s];
+        dh_chain(ndof, dh, qs, o, z);
+        double acc = 0.0;
+        for (int i = 1; i <= ndof; ++i)
+            for (int k = 0; k < ppl; ++k) {
+                double p[3];
+                body_point(o, i, k, ppl, p);
+                double lever = 0.0;
+                for (int j = 0; j < i; ++j) {
+                    double r[3] = {p[0] - o[j][0], p[1] - o[j][1], p[2] - o[j][2]}, col[3];
+                    cross3(z[j], r, col);
+                    double l1 = fabs(col[0]) + fabs(col[1]) + fabs(col[2]);
+                    if (l1 > lever) lever = l1;
+                }
+                occ_val ov;
+                occ_point(3, M, h, w, beta, ell, p, 0, &ov, NULL);
+                acc += lever * ov.gabs;
+            }
+        scale[s] = acc;
     }
 }
 

@@ -21,8 +21,8 @@ from ._lib import PdmpError
 
 __all__ = ["Occupancy", "Arm", "PdmpError", "abi_version", "uniform_samples",
            "label_points_discs", "label_points_boxes", "label_configs", "occupancy_eval",
-           "occupancy_grad", "morph_samples", "fk_body_points", "sync", "occupancy_bwd",
-           "bce_logits", "adam_step", "fit_occupancy", "Mlp", "arm_max_occupancy",
+           "occupancy_grad", "morph_samples", "morph_trajectory", "fk_body_points", "sync",
+           "occupancy_bwd", "bce_logits", "adam_step", "fit_occupancy", "Mlp", "arm_max_occupancy",
            "amortised_morph", "TanhNet", "tanh_occupancy_eval", "tanh_occupancy_grad",
            "tanh_morph_samples", "tanh_loss_grad", "tanh_fit", "morph_logdet", "morph_inverse",
            "mixture_samples", "Bucket", "Sampler", "rrt_run", "cull_grid", "morph_culled"]
@@ -229,6 +229,26 @@ def morph_samples(occ: Occupancy, x, T: int, eta: float, arm: Optional[Arm] = No
     return out
 
 
+def morph_trajectory(occ: Occupancy, x, T: int, eta: float, stride: int = 1,
+                     arm: Optional[Arm] = None, out=None):
+    """(x_T, traj): the morph of morph_samples with the path of every stride-th sample,
+    traj [T+1][rows][ceil(n/stride)] (state 0 the input, state T the output)."""
+    torch = _torch()
+    n = int(x.shape[1])
+    rows = arm.n_dof if arm is not None else occ.dim
+    _dev(x, "x", torch.float32, (rows, n))
+    if out is None:
+        out = torch.empty_like(x)
+    nt = (n + int(stride) - 1) // int(stride) if n > 0 else 0
+    traj = torch.empty((int(T) + 1, rows, nt), dtype=torch.float32, device=x.device)
+    o = occ.c_struct()
+    a = C.byref(arm.c_struct()) if arm is not None else None
+    _lib.call("pdmp_morph_trajectory", C.byref(o), a, C.c_void_p(x.data_ptr()),
+              _dev(out, "out", torch.float32, (rows, n)), n, int(T), float(eta),
+              C.c_void_p(traj.data_ptr()), int(stride), _stream(x.device))
+    return out, traj
+
+
 def morph_logdet(occ: Occupancy, x, T: int, eta: float, out=None):
     """(x_T, logdet): the workspace morph of x [dim][n] and, per sample,
     sum_k log|det(I - eta Hc(x_k))| (the log-Jacobian of the map, Sec. 3.2)."""
@@ -317,16 +337,22 @@ def occupancy_bwd(occ: Occupancy, x, g, s_fwd=None, want_w: bool = True, want_x:
     return gw, gx
 
 
-def bce_logits(s, y):
-    """(mean BCE loss [1], dL/ds [n]) of logits s against uint8 labels y."""
+def bce_logits(s, y, g_scale=None, want_loss: bool = True, want_grad: bool = True):
+    """(mean BCE loss [1], dL/ds [n]) of logits s against uint8 labels y; the gradient
+    is multiplied by g_scale (a device tensor of one element) when given.  Outputs not
+    wanted are returned as None."""
     torch = _torch()
     lib = _lib.load()
     n = int(s.shape[0])
-    loss = torch.empty(1, dtype=torch.float32, device=s.device)
-    g = torch.empty(n, dtype=torch.float32, device=s.device)
+    loss = torch.empty(1, dtype=torch.float32, device=s.device) if want_loss else None
+    g = torch.empty(n, dtype=torch.float32, device=s.device) if want_grad else None
+    sc = None
+    if g_scale is not None:
+        sc = _dev(g_scale.reshape(1), "g_scale", torch.float32, (1,))
     ws = _workspace(lib.pdmp_bce_workspace_size(n), s.device)
     _lib.call("pdmp_bce_logits", _dev(s, "s", torch.float32), _dev(y, "y", torch.uint8, (n,)), n,
-              _dev(loss, "loss"), _dev(g, "g"), _dev(ws, "ws"), ws.numel(), _stream(s.device))
+              sc, _dev(loss, "loss") if want_loss else None, _dev(g, "g") if want_grad else None,
+              _dev(ws, "ws"), ws.numel(), _stream(s.device))
     return loss, g
 
 

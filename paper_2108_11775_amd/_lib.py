@@ -96,6 +96,8 @@ SIGNATURES = {
     "pdmp_occupancy_eval": (_i32, [_P(pdmp_occupancy), _vp, _i64, _vp, _vp, _vp]),
     "pdmp_occupancy_grad": (_i32, [_P(pdmp_occupancy), _vp, _i64, _vp, _vp, _vp]),
     "pdmp_morph_samples": (_i32, [_P(pdmp_occupancy), _P(pdmp_arm), _vp, _vp, _i64, _i32, _f, _vp]),
+    "pdmp_morph_trajectory": (_i32, [_P(pdmp_occupancy), _P(pdmp_arm), _vp, _vp, _i64, _i32, _f,
+                                     _vp, _i64, _vp]),
     "pdmp_fk_body_points": (_i32, [_P(pdmp_arm), _vp, _i64, _vp, _vp]),
     "pdmp_fit_workspace_size": (C.c_size_t, [_i32, _i32, _i64]),
     "pdmp_bwd_workspace_size": (C.c_size_t, [_i32, _i32, _i64]),
@@ -104,7 +106,7 @@ SIGNATURES = {
                                   _vp, C.c_size_t, _vp]),
     "pdmp_occupancy_bwd": (_i32, [_P(pdmp_occupancy), _vp, _i64, _vp, _vp, _vp, _vp, _vp,
                                   C.c_size_t, _vp]),
-    "pdmp_bce_logits": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, C.c_size_t, _vp]),
+    "pdmp_bce_logits": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, C.c_size_t, _vp]),
     "pdmp_adam_step": (_i32, [_vp, _vp, _vp, _vp, _i64, _i64, _i32, _f, _f, _f, _f, _f, _vp]),
     "pdmp_mlp_num_params": (_i64, [_P(pdmp_mlp)]),
     "pdmp_cull_grid_make": (_i32, [_i32, _P(_f), _P(_f), _f, _P(pdmp_cull_grid)]),

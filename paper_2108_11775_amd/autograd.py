@@ -53,12 +53,14 @@ class Occupancy(torch.autograd.Function):
 class BCEWithLogits(torch.autograd.Function):
     @staticmethod
     def forward(ctx, s, y):
-        loss, g = bce_logits(s.detach().contiguous(), y)
-        ctx.save_for_backward(g)
+        s = s.detach().contiguous()
+        loss, _ = bce_logits(s, y, want_grad=False)
+        ctx.save_for_backward(s, y)
         return loss[0]
 
     @staticmethod
     def backward(ctx, gout):
-        (g,) = ctx.saved_tensors
-        # gout is a 0-d tensor on the device; the scaling is a single HIP multiply
-        return g * gout, None
+        s, y = ctx.saved_tensors
+        # the upstream gradient (a device scalar) scales dL/ds inside the kernel
+        _, g = bce_logits(s, y, g_scale=gout.detach().contiguous(), want_loss=False)
+        return g, None

@@ -110,7 +110,7 @@ template <int NDOF, int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_morph_arm(pdmp_arm arm, const float *__restrict__ hinges, const float *__restrict__ weights,
             int M, float kappa, float gscale, const float *q_in, float *q_out, int64_t n, int T,
-            float eta, const uint32_t *__restrict__ n_active) {
+            float eta, const uint32_t *__restrict__ n_active, Traj tr) {
     constexpr int L = kArmLanes;
     constexpr int R = 4;  // 3-D chunk rows
     constexpr int TILE = tile_chunks<3>();
@@ -138,7 +138,10 @@ k_morph_arm(pdmp_arm arm, const float *__restrict__ hinges, const float *__restr
         __syncthreads();
     }
 
+    int64_t tc;
+    const bool rec = k == 0 && traj_col(tr, cfg, n_eff, tc);
     for (int t = 0; t < T; ++t) {
+        if (rec) traj_put<NDOF>(tr, t, tc, q);
         float xs[NDOF][3], as[NDOF], ag[NDOF][3];
         {
             // only the prescaled points stay live through the hinge loop; the chain
@@ -209,6 +212,7 @@ k_morph_arm(pdmp_arm arm, const float *__restrict__ hinges, const float *__restr
             q[j] = q[j] - eta * gq;
         }
     }
+    if (rec) traj_put<NDOF>(tr, T, tc, q);
     if (k == 0 && cfg < n_eff) {
 #pragma unroll
         for (int j = 0; j < NDOF; ++j) q_out[(size_t)j * n + cfg] = q[j];
@@ -387,14 +391,15 @@ k_fk_points(pdmp_arm arm, const float *__restrict__ q_in, int64_t n, float *pts)
 template <int NDOF>
 static int32_t launch_morph_arm_n(const pdmp_arm &arm, const float *h, const float *w, int M,
                                   float kappa, float gscale, const float *qi, float *qo, int64_t n,
-                                  int T, float eta, const uint32_t *n_active, hipStream_t st) {
+                                  int T, float eta, const uint32_t *n_active, hipStream_t st,
+                                  const Traj &traj) {
     constexpr int BLOCK = 512;
     constexpr int TILE = tile_chunks<3>();
     const int nchunks = chunks_for(M);
     const size_t lds = (size_t)(nchunks < TILE ? nchunks : TILE) * ChunkLayout<3>::kBytes;
     const int64_t blocks = (n + BLOCK / kArmLanes - 1) / (BLOCK / kArmLanes);
     hipLaunchKernelGGL((k_morph_arm<NDOF, BLOCK>), dim3((unsigned)blocks), dim3(BLOCK), lds, st, arm,
-                       h, w, M, kappa, gscale, qi, qo, n, T, eta, n_active);
+                       h, w, M, kappa, gscale, qi, qo, n, T, eta, n_active, traj);
     return check_launch("k_morph_arm");
 }
 
@@ -464,10 +469,12 @@ int32_t launch_scatter(const pdmp_arm &arm, const uint32_t *idx, const uint32_t 
 
 int32_t launch_morph_arm(const pdmp_arm &arm, const float *h, const float *w, int M, float kappa,
                          float gscale, const float *qi, float *qo, int64_t n, int T, float eta,
-                         const uint32_t *n_active, hipStream_t st) {
+                         const uint32_t *n_active, hipStream_t st, const Traj &traj) {
     switch (arm.n_dof) {
-#define PDMP_CASE(N) \
-    case N: return launch_morph_arm_n<N>(arm, h, w, M, kappa, gscale, qi, qo, n, T, eta, n_active, st);
+#define PDMP_CASE(N)                                                                            \
+    case N:                                                                                     \
+        return launch_morph_arm_n<N>(arm, h, w, M, kappa, gscale, qi, qo, n, T, eta, n_active, st, \
+                                     traj);
         PDMP_CASE(1) PDMP_CASE(2) PDMP_CASE(3) PDMP_CASE(4)
         PDMP_CASE(5) PDMP_CASE(6) PDMP_CASE(7) PDMP_CASE(8)
 #undef PDMP_CASE

@@ -60,18 +60,19 @@ k_sum_partial(const float *__restrict__ x, int64_t n, int mode, double *parts) {
 // max(s,0) - y s + log(1 + exp(-|s|)).
 __global__ void __launch_bounds__(kRedBlock)
 k_bce_partial(const float *__restrict__ s, const uint8_t *__restrict__ y, int64_t n, float inv_n,
-              float *g_out, double *parts) {
+              const float *__restrict__ g_scale, float *g_out, double *parts) {
     __shared__ double sh[kRedBlock];
     const int64_t per = (n + gridDim.x - 1) / gridDim.x;
     const int64_t b0 = (int64_t)blockIdx.x * per;
     const int64_t b1 = b0 + per < n ? b0 + per : n;
     double acc = 0.0;
+    const float gsc = g_scale ? *g_scale : 1.0f;
     for (int64_t i = b0 + threadIdx.x; i < b1; i += kRedBlock) {
         const float sv = s[i];
         const float yv = y[i] ? 1.0f : 0.0f;
         float c, sp;
         sigmoid_and_slope(sv, c, sp);
-        if (g_out) g_out[i] = (c - yv) * inv_n;
+        if (g_out) g_out[i] = g_scale ? (c - yv) * inv_n * gsc : (c - yv) * inv_n;
         const float e = exp2_fast(-fabsf(sv) * kLog2e);
         acc += (double)(fmaxf(sv, 0.0f) - yv * sv) + (double)log1pf(e);
     }
@@ -298,11 +299,11 @@ int32_t launch_logit_bwd(int dim, const float *hinges, const float *weights, int
     return PDMP_OK;
 }
 
-int32_t launch_bce(const float *s, const uint8_t *y, int64_t n, float *loss, float *g_out,
-                   double *parts, hipStream_t st) {
+int32_t launch_bce(const float *s, const uint8_t *y, int64_t n, const float *g_scale, float *loss,
+                   float *g_out, double *parts, hipStream_t st) {
     const int nb = red_blocks(n);
     hipLaunchKernelGGL(k_bce_partial, dim3(nb), dim3(kRedBlock), 0, st, s, y, n,
-                       (float)(1.0 / (double)n), g_out, parts);
+                       (float)(1.0 / (double)n), g_scale, g_out, parts);
     if (loss)
         hipLaunchKernelGGL(k_final, dim3(1), dim3(kRedBlock), 0, st, parts, nb, 1.0 / (double)n,
                            (const double *)nullptr, 0, 0.0, loss);
@@ -351,7 +352,7 @@ int32_t launch_fit(int dim, const float *hinges, int M, const int *grid, float e
         a.s_out = s;
         if (int32_t e = launch_occ_any(dim, kEval, a, grid, st)) return e;
         hipLaunchKernelGGL(k_bce_partial, dim3(nb_n), dim3(kRedBlock), 0, st, s, y, n,
-                           (float)(1.0 / (double)n), g, bparts);
+                           (float)(1.0 / (double)n), (const float *)nullptr, g, bparts);
         if (loss_out) {
             hipLaunchKernelGGL(k_sum_partial, dim3(nb_w), dim3(kRedBlock), 0, st, wb, (int64_t)M, 1,
                                wparts);

@@ -114,7 +114,7 @@ template <int TB, int KS, int MODE>
 __global__ void __launch_bounds__(kG2Block) __attribute__((amdgpu_waves_per_eu(2)))
 k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
               float kappa, float gscale, const float *x_in, int64_t n, int T, float eta,
-              float *c_out, float *s_out, float *g_out, float *x_out) {
+              float *c_out, float *s_out, float *g_out, float *x_out, Traj tr) {
     // the FP16 scheme's per-block range check pays off over a morph's steps; a single
     // evaluation, whose blocks mostly stage W, keeps the BF16 scheme without it
     constexpr bool allow_fp16 = MODE == kMorph;
@@ -138,10 +138,13 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
     const float beta = weights[M];
     const int steps = MODE == kMorph ? T : 1;
     float s = 0.0f, sx = 0.0f, sy = 0.0f;
+    int64_t tc;
+    const bool rec = MODE == kMorph && half == 0 && traj_col(tr, i, n, tc);
 
     if (fp16) {
         const f16x8_t *frag = reinterpret_cast<const f16x8_t *>(fraw);
         for (int st = 0; st < steps; ++st) {
+            if (rec) traj_put<2>(tr, st, tc, {x, y});
             const float xs = kappa * x, ys = kappa * y;
             // the operand scale 2^c of this sample (both lanes of the pair agree)
             const int c = split_scale_exp(xs, gmin, gmax);
@@ -179,6 +182,7 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
     } else {
         const bf16x8_t *frag = reinterpret_cast<const bf16x8_t *>(fraw);
         for (int st = 0; st < steps; ++st) {
+            if (rec) traj_put<2>(tr, st, tc, {x, y});
             const float xs = kappa * x, ys = kappa * y;
             f32x16_t U[TB], V[TB];
             // an opaque copy of the lane index keeps the fragment reads inside the step
@@ -213,6 +217,7 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
             }
         }
     }
+    if (rec) traj_put<2>(tr, steps, tc, {x, y});
     g2_finish<MODE>(s, sx, sy, beta, gscale, x, y, half, i, n, c_out, s_out, g_out, x_out);
 }
 
@@ -261,7 +266,7 @@ template <int TB16, int KB, int MODE>
 __global__ void __launch_bounds__(kG2sBlock)
 k_grid2d_small(const float *__restrict__ hinges, const float *__restrict__ weights, int g0,
                int g1, float kappa, float gscale, const float *x_in, int64_t n, int T, float eta,
-               float *c_out, float *s_out, float *g_out, float *x_out) {
+               float *c_out, float *s_out, float *g_out, float *x_out, Traj tr) {
     static_assert(kG2sBlock == kG2Block, "the scheme test assumes the large kernel's block");
     // fragments: frag[(p * KB + kb) * TB16 + t][lane] = part p of
     //   W[b = 16t + lane%16][a = 32kb + 8(lane/16) + j], j < 8 (0 outside the grid);
@@ -330,7 +335,10 @@ k_grid2d_small(const float *__restrict__ hinges, const float *__restrict__ weigh
 
     float s = 0.0f, sx = 0.0f, sy = 0.0f;
     const int steps = MODE == kMorph ? T : 1;
+    int64_t tc;
+    const bool rec = MODE == kMorph && grp == 0 && traj_col(tr, i, n, tc);
     for (int st = 0; st < steps; ++st) {
+        if (rec) traj_put<2>(tr, st, tc, {x, y});
         const float xs = kappa * x, ys = kappa * y;
         int ln = lane;  // opaque: keeps the fragment reads inside the step loop
         asm volatile("" : "+v"(ln));
@@ -398,6 +406,7 @@ k_grid2d_small(const float *__restrict__ hinges, const float *__restrict__ weigh
             y = fmaf(step, sy, y);
         }
     }
+    if (rec) traj_put<2>(tr, steps, tc, {x, y});
     if (grp != 0 || i >= n) return;
     if (MODE == kMorph) {
         x_out[i] = x;
@@ -425,7 +434,7 @@ static int32_t launch_grid2d_small(const RbfArgs &a, int g0, int g1, hipStream_t
 #define PDMP_G2S(TB, KB)                                                                         \
     hipLaunchKernelGGL((k_grid2d_small<TB, KB, kMorph>), grid, blk, 0, st, a.hinges, a.weights, g0, \
                        g1, a.kappa, a.gscale, a.x_in, a.n, a.T, a.eta, a.c_out, a.s_out,          \
-                       a.g_out, a.x_out)
+                       a.g_out, a.x_out, a.traj)
 #define PDMP_G2S_T(KB)                             \
     switch ((g1 + 15) / 16) {                      \
         case 1: PDMP_G2S(1, KB); break;            \
@@ -456,7 +465,7 @@ int32_t launch_grid2d(int mode, const RbfArgs &a, int g0, int g1, hipStream_t st
 #define PDMP_G2(TB, KS, MODE)                                                                  \
     hipLaunchKernelGGL((k_grid2d_mfma<TB, KS, MODE>), grid, blk, 0, st, a.hinges, a.weights, g0, \
                        g1, a.kappa, a.gscale, a.x_in, a.n, a.T, a.eta, a.c_out, a.s_out,        \
-                       a.g_out, a.x_out)
+                       a.g_out, a.x_out, a.traj)
 #define PDMP_G2_KS(TB, MODE)                      \
     switch ((g0 + 15) / 16) {                     \
         case 1: PDMP_G2(TB, 1, MODE); break;      \

@@ -242,14 +242,18 @@ __device__ __forceinline__ void g3_ws_body(const uint4 *fraw, const SplitScheme 
                                            const float *ay, const float *az, float beta,
                                            float kappa, float gscale, const float *x_in,
                                            int64_t n, int T, float eta, float *c_out,
-                                           float *s_out, float *g_out, float *x_out) {
+                                           float *s_out, float *g_out, float *x_out,
+                                           const Traj &tr) {
     const int lane = threadIdx.x & 63;
     const int64_t i = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32 + (lane & 31);
     const int64_t ic = i < n ? i : n - 1;
     float x = x_in[ic], y = x_in[(size_t)n + ic], z = x_in[2 * (size_t)n + ic];
     float s, sx, sy, sz;
     const int steps = MODE == kMorph ? T : 1;
+    int64_t tc;
+    const bool rec = MODE == kMorph && (lane >> 5) == 0 && traj_col(tr, i, n, tc);
     for (int st = 0; st < steps; ++st) {
+        if (rec) traj_put<3>(tr, st, tc, {x, y, z});
         g3_point<G0, G2, MODE != kEval, F16>(fraw, sc, ax, ay, az, kappa * x, kappa * y,
                                              kappa * z, s, sx, sy, sz);
         if (MODE == kMorph) {
@@ -261,6 +265,7 @@ __device__ __forceinline__ void g3_ws_body(const uint4 *fraw, const SplitScheme 
             z = fmaf(step, sz, z);
         }
     }
+    if (rec) traj_put<3>(tr, steps, tc, {x, y, z});
     if ((lane >> 5) != 0 || i >= n) return;
     if (MODE == kMorph) {
         x_out[i] = x;
@@ -285,7 +290,7 @@ template <int G0, int G2, int MODE>
 __global__ void __launch_bounds__(kG3Block)
 k_grid3d_ws(const float *__restrict__ hinges, const float *__restrict__ weights, float kappa,
             float gscale, const float *x_in, int64_t n, int T, float eta, float *c_out,
-            float *s_out, float *g_out, float *x_out) {
+            float *s_out, float *g_out, float *x_out, Traj tr) {
     using C = G3<G0, G2>;
     __shared__ uint4 fraw[C::FRAG];
     __shared__ float ax[G0], ay[kG3Y], az[G2];
@@ -299,10 +304,10 @@ k_grid3d_ws(const float *__restrict__ hinges, const float *__restrict__ weights,
     const float beta = weights[M];
     if (MODE == kMorph && sc.fp16)
         g3_ws_body<G0, G2, MODE, true>(fraw, sc, ax, ay, az, beta, kappa, gscale, x_in, n, T, eta,
-                                       c_out, s_out, g_out, x_out);
+                                       c_out, s_out, g_out, x_out, tr);
     else
         g3_ws_body<G0, G2, MODE, false>(fraw, sc, ax, ay, az, beta, kappa, gscale, x_in, n, T,
-                                        eta, c_out, s_out, g_out, x_out);
+                                        eta, c_out, s_out, g_out, x_out, tr);
 }
 
 // FP32 DH chain (same convention as the pairwise arm kernel).
@@ -352,7 +357,7 @@ __device__ __forceinline__ void arm_body(const pdmp_arm &arm, const uint4 *fraw,
                                          const float *az, float *kin, float beta, float kappa,
                                          float gscale, const float *q_in, float *q_out, int64_t n,
                                          int64_t n_eff, int T, float eta, float thresh,
-                                         float *maxc_out, uint8_t *flag_out) {
+                                         float *maxc_out, uint8_t *flag_out, const Traj &tr) {
     constexpr int KIN = 3 * (NDOF + 1) + 3 * NDOF + NDOF;  // o, z, grad_q per configuration
     const int lane = threadIdx.x & 63;
     const int k = lane & 7;
@@ -370,7 +375,10 @@ __device__ __forceinline__ void arm_body(const pdmp_arm &arm, const uint4 *fraw,
 
     const int steps = MORPH ? T : 1;
     float mc = -1.0f;
+    int64_t tc;
+    const bool rec = MORPH && writer && traj_col(tr, cfg, n_eff, tc);
     for (int st = 0; st < steps; ++st) {
+        if (rec) traj_put<NDOF>(tr, st, tc, q);
         {
             // the chain of this configuration, parked in LDS so that the link loop
             // below does not hold ~45 registers across the MFMA work
@@ -428,6 +436,7 @@ __device__ __forceinline__ void arm_body(const pdmp_arm &arm, const uint4 *fraw,
         }
         __syncthreads();
     }
+    if (rec) traj_put<NDOF>(tr, steps, tc, q);
     if (!MORPH) {
         mc = fmaxf(mc, __shfl_xor(mc, 1, 64));
         mc = fmaxf(mc, __shfl_xor(mc, 2, 64));
@@ -448,7 +457,7 @@ __global__ void __launch_bounds__(kG3Block) __attribute__((amdgpu_waves_per_eu(3
 k_arm_grid3d(pdmp_arm arm, const float *__restrict__ hinges, const float *__restrict__ weights,
              float kappa, float gscale, const float *q_in, float *q_out, int64_t n, int T,
              float eta, const uint32_t *__restrict__ n_active, float thresh, float *maxc_out,
-             uint8_t *flag_out) {
+             uint8_t *flag_out, Traj tr) {
     using C = G3<G0, G2>;
     constexpr int KIN = 3 * (NDOF + 1) + 3 * NDOF + NDOF;  // o, z, grad_q per configuration
     __shared__ uint4 fraw[C::FRAG];
@@ -466,11 +475,11 @@ k_arm_grid3d(pdmp_arm arm, const float *__restrict__ hinges, const float *__rest
     if (MORPH && sc.fp16)
         arm_body<NDOF, G0, G2, MORPH, true>(arm, fraw, sc, ax, ay, az, kin, beta, kappa, gscale,
                                             q_in, q_out, n, n_eff, T, eta, thresh, maxc_out,
-                                            flag_out);
+                                            flag_out, tr);
     else
         arm_body<NDOF, G0, G2, MORPH, false>(arm, fraw, sc, ax, ay, az, kin, beta, kappa, gscale,
                                              q_in, q_out, n, n_eff, T, eta, thresh, maxc_out,
-                                             flag_out);
+                                             flag_out, tr);
 }
 
 static bool g3_supported(const int *grid, int M) {
@@ -483,7 +492,8 @@ int32_t launch_grid3d_ws(int mode, const RbfArgs &a, const int *grid, hipStream_
     const dim3 g((unsigned)((a.n + 127) / 128)), b(kG3Block);
 #define PDMP_G3(MODE)                                                                         \
     hipLaunchKernelGGL((k_grid3d_ws<16, 16, MODE>), g, b, 0, st, a.hinges, a.weights, a.kappa, \
-                       a.gscale, a.x_in, a.n, a.T, a.eta, a.c_out, a.s_out, a.g_out, a.x_out)
+                       a.gscale, a.x_in, a.n, a.T, a.eta, a.c_out, a.s_out, a.g_out, a.x_out, \
+                       a.traj)
     if (mode == kEval) PDMP_G3(kEval);
     else if (mode == kGrad) PDMP_G3(kGrad);
     else PDMP_G3(kMorph);
@@ -494,7 +504,8 @@ int32_t launch_grid3d_ws(int mode, const RbfArgs &a, const int *grid, hipStream_
 int32_t launch_arm_grid3d(const pdmp_arm &arm, const float *h, const float *w, int M,
                           const int *grid, float kappa, float gscale, const float *qi, float *qo,
                           int64_t n, int T, float eta, const uint32_t *n_active, bool morph,
-                          float thresh, float *maxc, uint8_t *flag, hipStream_t st) {
+                          float thresh, float *maxc, uint8_t *flag, hipStream_t st,
+                          const Traj &traj) {
     if (!g3_supported(grid, M) || arm.pts_per_link > 8) return PDMP_EUNSUPPORTED;
     const dim3 g((unsigned)((n + 15) / 16)), b(kG3Block);
     switch (arm.n_dof) {
@@ -502,10 +513,10 @@ int32_t launch_arm_grid3d(const pdmp_arm &arm, const float *h, const float *w, i
     case N:                                                                                     \
         if (morph)                                                                              \
             hipLaunchKernelGGL((k_arm_grid3d<N, 16, 16, true>), g, b, 0, st, arm, h, w, kappa,  \
-                               gscale, qi, qo, n, T, eta, n_active, thresh, maxc, flag);        \
+                               gscale, qi, qo, n, T, eta, n_active, thresh, maxc, flag, traj);  \
         else                                                                                    \
             hipLaunchKernelGGL((k_arm_grid3d<N, 16, 16, false>), g, b, 0, st, arm, h, w, kappa, \
-                               gscale, qi, qo, n, T, eta, n_active, thresh, maxc, flag);        \
+                               gscale, qi, qo, n, T, eta, n_active, thresh, maxc, flag, traj);  \
         return check_launch("k_arm_grid3d");
         PDMP_CASE(1) PDMP_CASE(2) PDMP_CASE(3) PDMP_CASE(4)
         PDMP_CASE(5) PDMP_CASE(6) PDMP_CASE(7) PDMP_CASE(8)

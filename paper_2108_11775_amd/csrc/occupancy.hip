@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(BLOCK)
 k_rbf(const float *__restrict__ hinges, const float *__restrict__ weights, int M,
       const float *__restrict__ bias_ptr, float kappa, float gscale, const float *x_in, int64_t n,
       int T, float eta, float *c_out, float *s_out, float *g_out, float *x_out,
-      const float *__restrict__ g_in, int chain, int cps) {
+      const float *__restrict__ g_in, int chain, int cps, Traj tr) {
     static_assert(G == 1 || SPL == 1, "lane groups carry one sample");
     constexpr int R = DIM + 1;
     constexpr int TILE = tile_chunks<DIM>();
@@ -121,8 +121,15 @@ k_rbf(const float *__restrict__ hinges, const float *__restrict__ weights, int M
     }
 
     const int steps = (MODE == kMorph) ? T : 1;
+    int64_t tc[SPL];
+    bool rec[SPL];
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) rec[s] = MODE == kMorph && lg == 0 && traj_col(tr, idx[s], n, tc[s]);
     float as[SPL], ag[SPL][DIM];
     for (int t = 0; t < steps; ++t) {
+#pragma unroll
+        for (int s = 0; s < SPL; ++s)
+            if (rec[s]) traj_put<DIM>(tr, t, tc[s], x[s]);
         float xs[SPL][DIM];
 #pragma unroll
         for (int s = 0; s < SPL; ++s) {
@@ -161,6 +168,9 @@ k_rbf(const float *__restrict__ hinges, const float *__restrict__ weights, int M
         }
     }
 
+#pragma unroll
+    for (int s = 0; s < SPL; ++s)
+        if (rec[s]) traj_put<DIM>(tr, steps, tc[s], x[s]);
     if (lg != 0) return;
 #pragma unroll
     for (int s = 0; s < SPL; ++s) {
@@ -213,7 +223,7 @@ static int32_t launch_rbf_v(const RbfArgs &a, hipStream_t st) {
     hipLaunchKernelGGL((k_rbf<DIM, SPL, G, BLOCK, MODE>), dim3((unsigned)blocks, (unsigned)splits),
                        dim3(BLOCK), lds, st, a.hinges, a.weights, a.M, a.bias, a.kappa, a.gscale,
                        a.x_in, a.n, a.T, a.eta, a.c_out, a.s_out, a.g_out, a.x_out, a.g_in,
-                       a.chain, cps);
+                       a.chain, cps, a.traj);
     return check_launch("k_rbf");
 }
 

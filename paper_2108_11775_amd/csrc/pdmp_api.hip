@@ -29,13 +29,8 @@ int32_t check_launch(const char *what) {
 }
 
 
-static int32_t check_occ(const pdmp_occupancy *occ) {
-    PDMP_REQUIRE(occ != nullptr, "occupancy is NULL");
-    PDMP_REQUIRE(occ->dim == 2 || occ->dim == 3, "occupancy dim %d not in {2,3}", occ->dim);
-    PDMP_REQUIRE(occ->n_hinges >= 1, "n_hinges %d < 1", occ->n_hinges);
-    PDMP_REQUIRE(occ->hinges != nullptr && occ->weights != nullptr, "hinges/weights NULL");
-    PDMP_REQUIRE(std::isfinite(occ->lengthscale) && occ->lengthscale > 0.0f,
-                 "lengthscale must be finite and > 0");
+// The grid field: all zero, or per-axis sizes >= 1 whose product is n_hinges.
+static int32_t check_grid_field(const pdmp_occupancy *occ) {
     if (occ->grid[0] || occ->grid[1] || occ->grid[2]) {
         int64_t prod = 1;
         for (int k = 0; k < occ->dim; ++k) {
@@ -49,7 +44,24 @@ static int32_t check_occ(const pdmp_occupancy *occ) {
     return PDMP_OK;
 }
 
+static int32_t check_occ(const pdmp_occupancy *occ) {
+    PDMP_REQUIRE(occ != nullptr, "occupancy is NULL");
+    PDMP_REQUIRE(occ->dim == 2 || occ->dim == 3, "occupancy dim %d not in {2,3}", occ->dim);
+    PDMP_REQUIRE(occ->n_hinges >= 1, "n_hinges %d < 1", occ->n_hinges);
+    PDMP_REQUIRE(occ->hinges != nullptr && occ->weights != nullptr, "hinges/weights NULL");
+    PDMP_REQUIRE(std::isfinite(occ->lengthscale) && occ->lengthscale > 0.0f,
+                 "lengthscale must be finite and > 0");
+    return check_grid_field(occ);
+}
+
 static bool has_grid(const pdmp_occupancy *occ) { return occ->grid[0] > 0; }
+
+// Before a launch that may take the grid factorisation: the device check of the
+// stated grid (deferred report at pdmp_sync).
+static int32_t grid_check(const pdmp_occupancy *occ, void *stream) {
+    if (!has_grid(occ)) return PDMP_OK;
+    return launch_grid_check(occ->dim, occ->hinges, occ->n_hinges, occ->grid, (hipStream_t)stream);
+}
 
 static int32_t check_arm(const pdmp_arm *arm, int max_ppl) {
     PDMP_REQUIRE(arm != nullptr, "arm is NULL");
@@ -83,6 +95,14 @@ int32_t pdmp_sync(void *stream) {
     if (e != hipSuccess) {
         set_error("hipStreamSynchronize: %s", hipGetErrorString(e));
         return PDMP_EDEVICE;
+    }
+    bool mismatch = false;
+    const int32_t st = take_grid_mismatch(mismatch);
+    if (st) return st;
+    if (mismatch) {
+        set_error("an occupancy's hinges are not the tensor grid its grid field states "
+                  "(results of that call are undefined)");
+        return PDMP_EINVAL;
     }
     return PDMP_OK;
 }
@@ -134,8 +154,11 @@ int32_t pdmp_label_configs(const pdmp_arm *arm, const pdmp_boxes *scene, const f
 
 static int32_t rbf_call(const pdmp_occupancy *occ, int mode, const float *x, int64_t n,
                         float *c_out, float *s_out, float *g_out, float *x_out, int32_t T,
-                        float eta, void *stream) {
+                        float eta, void *stream, const Traj &traj = Traj()) {
+    const int32_t gc = grid_check(occ, stream);
+    if (gc) return gc;
     RbfArgs a;
+    a.traj = traj;
     a.hinges = occ->hinges;
     a.weights = occ->weights;
     a.M = occ->n_hinges;
@@ -173,8 +196,10 @@ int32_t pdmp_occupancy_grad(const pdmp_occupancy *occ, const float *x, int64_t n
     return rbf_call(occ, kGrad, x, n, c_out, nullptr, grad_out, nullptr, 1, 0.0f, stream);
 }
 
-int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,
-                           float *out, int64_t n, int32_t T, float eta, void *stream) {
+// The morph of pdmp_morph_samples, recording the paths of traj's samples (if any).
+static int32_t morph_impl(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,
+                          float *out, int64_t n, int32_t T, float eta, const Traj &traj,
+                          void *stream) {
     int32_t st = check_occ(occ);
     if (st) return st;
     PDMP_REQUIRE(n >= 0, "n < 0");
@@ -187,7 +212,7 @@ int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const
     }
     if (n == 0) return PDMP_OK;
     PDMP_REQUIRE(in && out, "in/out NULL");
-    if (T == 0) {
+    if (T == 0 && traj.p == nullptr) {
         if (in == out) return PDMP_OK;
         const size_t rows = arm ? (size_t)arm->n_dof : (size_t)occ->dim;
         hipError_t e = hipMemcpyAsync(out, in, rows * (size_t)n * sizeof(float),
@@ -202,15 +227,33 @@ int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const
         float kappa, gscale;
         derive_scales(occ->lengthscale, kappa, gscale);
         if (has_grid(occ)) {
+            if ((st = grid_check(occ, stream))) return st;
             st = launch_arm_grid3d(*arm, occ->hinges, occ->weights, occ->n_hinges, occ->grid, kappa,
                                    gscale, in, out, n, T, eta, nullptr, true, 0.0f, nullptr,
-                                   nullptr, (hipStream_t)stream);
+                                   nullptr, (hipStream_t)stream, traj);
             if (st != PDMP_EUNSUPPORTED) return st;
         }
         return launch_morph_arm(*arm, occ->hinges, occ->weights, occ->n_hinges, kappa, gscale, in,
-                                out, n, T, eta, nullptr, (hipStream_t)stream);
+                                out, n, T, eta, nullptr, (hipStream_t)stream, traj);
     }
-    return rbf_call(occ, kMorph, in, n, nullptr, nullptr, nullptr, out, T, eta, stream);
+    return rbf_call(occ, kMorph, in, n, nullptr, nullptr, nullptr, out, T, eta, stream, traj);
+}
+
+int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,
+                           float *out, int64_t n, int32_t T, float eta, void *stream) {
+    return morph_impl(occ, arm, in, out, n, T, eta, Traj(), stream);
+}
+
+int32_t pdmp_morph_trajectory(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,
+                              float *out, int64_t n, int32_t T, float eta, float *traj,
+                              int64_t traj_stride, void *stream) {
+    PDMP_REQUIRE(traj != nullptr, "traj NULL");
+    PDMP_REQUIRE(traj_stride >= 1, "traj_stride %lld < 1", (long long)traj_stride);
+    Traj tr;
+    tr.p = traj;
+    tr.stride = traj_stride;
+    tr.nt = n > 0 ? (n + traj_stride - 1) / traj_stride : 0;
+    return morph_impl(occ, arm, in, out, n, T, eta, tr, stream);
 }
 
 int32_t pdmp_morph_logdet(const pdmp_occupancy *occ, const float *in, float *out, int64_t n,
@@ -222,6 +265,7 @@ int32_t pdmp_morph_logdet(const pdmp_occupancy *occ, const float *in, float *out
     PDMP_REQUIRE(std::isfinite(eta), "eta not finite");
     if (n == 0) return PDMP_OK;
     PDMP_REQUIRE(in && out, "in/out NULL");
+    if ((st = grid_check(occ, stream))) return st;
     return launch_morph_inverse(occ->dim, kLogdet, occ->hinges, occ->weights, occ->n_hinges,
                                 has_grid(occ) ? occ->grid : nullptr, occ->lengthscale, in, n, T,
                                 eta, 0, out, logdet, nullptr, (hipStream_t)stream);
@@ -238,6 +282,7 @@ int32_t pdmp_morph_inverse(const pdmp_occupancy *occ, const float *z, float *y, 
     PDMP_REQUIRE(std::isfinite(eta), "eta not finite");
     if (n == 0) return PDMP_OK;
     PDMP_REQUIRE(z && y, "z/y NULL");
+    if ((st = grid_check(occ, stream))) return st;
     return launch_morph_inverse(occ->dim, kInverse, occ->hinges, occ->weights, occ->n_hinges,
                                 has_grid(occ) ? occ->grid : nullptr, occ->lengthscale, z, n, T,
                                 eta, iters, y, logdet, resid, (hipStream_t)stream);
@@ -356,6 +401,8 @@ int32_t pdmp_fit_occupancy(const pdmp_occupancy *occ, float *weights, const floa
     PDMP_REQUIRE(occ->dim == 2 || occ->dim == 3, "occupancy dim %d not in {2,3}", occ->dim);
     PDMP_REQUIRE(occ->n_hinges >= 1 && occ->hinges, "bad hinges");
     PDMP_REQUIRE(std::isfinite(occ->lengthscale) && occ->lengthscale > 0.0f, "bad lengthscale");
+    int32_t st = check_grid_field(occ);
+    if (st) return st;
     PDMP_REQUIRE(weights && pts && labels && opts, "NULL argument");
     PDMP_REQUIRE(n >= 1, "n < 1");
     PDMP_REQUIRE(opts->optimizer == 0 || opts->optimizer == 1, "optimizer %d", opts->optimizer);
@@ -375,6 +422,7 @@ int32_t pdmp_fit_occupancy(const pdmp_occupancy *occ, float *weights, const floa
         set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
         return PDMP_ENOMEM;
     }
+    if ((st = grid_check(occ, stream))) return st;
     return launch_fit(occ->dim, occ->hinges, occ->n_hinges, has_grid(occ) ? occ->grid : nullptr,
                       occ->lengthscale, weights, pts, labels, n, *opts, loss_out, ws,
                       (hipStream_t)stream);
@@ -397,13 +445,14 @@ int32_t pdmp_occupancy_bwd(const pdmp_occupancy *occ, const float *x, int64_t n,
         set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
         return PDMP_ENOMEM;
     }
+    if ((st = grid_check(occ, stream))) return st;
     return launch_logit_bwd(occ->dim, occ->hinges, occ->weights, occ->n_hinges,
                             has_grid(occ) ? occ->grid : nullptr, occ->lengthscale, x, n, g, s_fwd,
                             grad_w, grad_x, 1.0f, nullptr, 0.0f, ws, (hipStream_t)stream);
 }
 
-int32_t pdmp_bce_logits(const float *s, const uint8_t *y, int64_t n, float *loss, float *g_s,
-                        void *ws, size_t ws_bytes, void *stream) {
+int32_t pdmp_bce_logits(const float *s, const uint8_t *y, int64_t n, const float *g_scale,
+                        float *loss, float *g_s, void *ws, size_t ws_bytes, void *stream) {
     PDMP_REQUIRE(n >= 1, "n < 1");
     PDMP_REQUIRE(s && y, "s/y NULL");
     const size_t need = bce_ws_bytes(n);
@@ -411,7 +460,7 @@ int32_t pdmp_bce_logits(const float *s, const uint8_t *y, int64_t n, float *loss
         set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
         return PDMP_ENOMEM;
     }
-    return launch_bce(s, y, n, loss, g_s, (double *)ws, (hipStream_t)stream);
+    return launch_bce(s, y, n, g_scale, loss, g_s, (double *)ws, (hipStream_t)stream);
 }
 
 int32_t pdmp_adam_step(float *p, const float *g, float *m, float *v, int64_t n, int64_t n_decay,
@@ -506,6 +555,7 @@ int32_t pdmp_arm_max_occupancy(const pdmp_occupancy *occ, const pdmp_arm *arm, c
     float kappa, gscale;
     derive_scales(occ->lengthscale, kappa, gscale);
     if (has_grid(occ)) {
+        if ((st = grid_check(occ, stream))) return st;
         st = launch_arm_grid3d(*arm, occ->hinges, occ->weights, occ->n_hinges, occ->grid, kappa,
                                gscale, q, nullptr, n, 1, 0.0f, nullptr, false, thresh, maxc, flag,
                                (hipStream_t)stream);
@@ -566,6 +616,7 @@ int32_t pdmp_amortised_morph(const pdmp_mlp *mlp, const pdmp_occupancy *occ, con
     float kappa, gscale;
     derive_scales(occ->lengthscale, kappa, gscale);
     const int *grid = has_grid(occ) ? occ->grid : nullptr;
+    if ((st = grid_check(occ, stream))) return st;
     if ((st = launch_mlp_forward(*mlp, q, n, out, nullptr, mws, s))) return st;
     st = PDMP_EUNSUPPORTED;
     if (grid)

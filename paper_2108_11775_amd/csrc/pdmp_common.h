@@ -78,6 +78,28 @@ inline void derive_scales(float ell, float &kappa, float &gscale) {
     gscale = (float)(1.0 / (l * l * k));
 }
 
+// Path recording of the morph kernels: state k (k = 0..T, state 0 the input) of every
+// sample i with i % stride == 0 is written to p[(k rows + r) nt + i / stride], r over
+// the sample's rows (dim, or n_dof for the arm).  p == nullptr records nothing; the
+// arithmetic of the morph is the same either way.
+struct Traj {
+    float *p = nullptr;
+    int64_t stride = 1, nt = 0;
+};
+
+// Whether sample i (of n) is recorded, and its column.
+__device__ __forceinline__ bool traj_col(const Traj &tr, int64_t i, int64_t n, int64_t &col) {
+    col = i / tr.stride;
+    return tr.p != nullptr && i < n && i - col * tr.stride == 0;
+}
+
+// Record state k of a recorded sample (rows values).
+template <int R>
+__device__ __forceinline__ void traj_put(const Traj &tr, int k, int64_t col, const float (&v)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) tr.p[((size_t)k * R + r) * (size_t)tr.nt + (size_t)col] = v[r];
+}
+
 // ---- launchers (host side, one per kernel family) ----
 
 enum RbfMode { kEval = 0, kGrad = 1, kMorph = 2, kGradBwd = 3, kLogdet = 4, kInverse = 5 };
@@ -98,6 +120,7 @@ struct RbfArgs {
     const float *g_in = nullptr;  // kGradBwd upstream gradient
     int chain = 0;                // kGradBwd: multiply by sigma'(s)
     int splits = 1;               // kEval: hinge-range splits (partial sums)
+    Traj traj;                    // kMorph: optional path recording
 };
 
 int32_t launch_rbf(int dim, int mode, const RbfArgs &a, hipStream_t st);
@@ -106,7 +129,12 @@ int32_t launch_grid3d_ws(int mode, const RbfArgs &a, const int *grid, hipStream_
 int32_t launch_arm_grid3d(const pdmp_arm &arm, const float *h, const float *w, int M,
                           const int *grid, float kappa, float gscale, const float *qi, float *qo,
                           int64_t n, int T, float eta, const uint32_t *n_active, bool morph,
-                          float thresh, float *maxc, uint8_t *flag, hipStream_t st);
+                          float thresh, float *maxc, uint8_t *flag, hipStream_t st,
+                          const Traj &traj = Traj());
+// Enqueue the device check that the hinges are the tensor grid `grid` states (a
+// mismatch is reported by the next pdmp_sync on the device), and take that report.
+int32_t launch_grid_check(int dim, const float *hinges, int M, const int *grid, hipStream_t st);
+int32_t take_grid_mismatch(bool &mismatch);
 // The occupancy evaluation of one RBF launch, through the grid factorisation when
 // `grid` describes one the grid kernels support, else the pairwise kernel.
 int32_t launch_occ_any(int dim, int mode, const RbfArgs &a, const int *grid, hipStream_t st);
@@ -120,7 +148,7 @@ int32_t launch_label_configs(const pdmp_arm &arm, const pdmp_boxes &sc, const fl
                              uint8_t *out, uint64_t *n_hit, hipStream_t st);
 int32_t launch_morph_arm(const pdmp_arm &arm, const float *h, const float *w, int M, float kappa,
                          float gscale, const float *qi, float *qo, int64_t n, int T, float eta,
-                         const uint32_t *n_active, hipStream_t st);
+                         const uint32_t *n_active, hipStream_t st, const Traj &traj = Traj());
 int32_t launch_arm_max_occ(const pdmp_arm &arm, const float *h, const float *w, int M, float kappa,
                            const float *q, int64_t n, float thresh, float *maxc, uint8_t *flag,
                            hipStream_t st);
@@ -181,8 +209,8 @@ int32_t launch_tanh_fit(const pdmp_tanh_net &net, const float *x, const uint8_t 
 int32_t launch_tanh_net(const pdmp_tanh_net &net, int mode, const float *x, int64_t n, int T,
                         float eta, float *c_out, float *s_out, float *g_out, float *x_out,
                         hipStream_t st);
-int32_t launch_bce(const float *s, const uint8_t *y, int64_t n, float *loss, float *g_out,
-                   double *parts, hipStream_t st);
+int32_t launch_bce(const float *s, const uint8_t *y, int64_t n, const float *g_scale, float *loss,
+                   float *g_out, double *parts, hipStream_t st);
 int32_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, int64_t n_decay,
                     int t, float lr, float b1, float b2, float eps, float l2, hipStream_t st);
 int32_t launch_fit(int dim, const float *hinges, int M, const int *grid, float ell, float *wb,

@@ -42,6 +42,12 @@ def test_invalid_arguments_rejected_before_launch():
     assert lib.pdmp_morph_samples(C.byref(occ), None, None, None, 1, -1, 0.1, None) == E
     assert lib.pdmp_morph_samples(C.byref(occ), None, None, None, 1, 3, float("nan"), None) == E
     assert lib.pdmp_morph_samples(C.byref(occ), None, None, None, -5, 3, 0.1, None) == E
+    # the recording morph: traj and its stride are checked before anything else
+    assert lib.pdmp_morph_trajectory(C.byref(occ), None, None, None, 4, 3, 0.1, None, 1,
+                                     None) == E
+    assert lib.pdmp_morph_trajectory(C.byref(occ), None, None, None, 4, 3, 0.1, C.c_void_p(16),
+                                     0, None) == E
+    assert b"traj_stride" in lib.pdmp_last_error()
     # a 2-D occupancy cannot drive an arm
     arm = _lib.pdmp_arm()
     arm.n_dof, arm.pts_per_link = 7, 8

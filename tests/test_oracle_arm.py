@@ -192,3 +192,33 @@ def test_config_label_margin_is_the_flip_distance():
     assert mg == 0.25
     assert O.label_configs(arm, c - [[0], [mg - 1e-9], [0]], e, q)[0] == 0
     assert O.label_configs(arm, c - [[0], [mg + 1e-9], [0]], e, q)[0] == 1
+
+
+def test_arm_step_scale_against_jacobian_columns():
+    """The per-configuration gradient scale written out from the positional
+    Jacobians (themselves pinned against central differences) and the workspace
+    gradient scale of each body point."""
+    arm = _arm(seed=5)
+    occ = _occ3(seed=6)
+    q = np.random.default_rng(7).uniform(-math.pi, math.pi, (7, 5))
+    got = O.arm_step_scale(arm, occ, q)
+    pts = O.fk_points(arm, q)
+    for s in range(q.shape[1]):
+        _, _, _, gabs = O.occ_grad(occ, pts[:, :, s])
+        lever = np.array([np.abs(O.fk_jacobian(arm, q[:, s], p)).sum(axis=0).max()
+                          for p in range(56)])
+        assert got[s] == pytest.approx(float((lever * gabs).sum()), rel=1e-12)
+
+
+def test_arm_step_hessian_norm_bounds_the_step_jacobian():
+    """For one step, |I - eta H|_2 <= 1 + eta |H|_2 and det(I - eta H) >= (1 - eta |H|_2)^7
+    when eta |H|_2 < 1 (eigenvalues of the symmetrised step Jacobian)."""
+    arm = _arm(seed=8)
+    occ = _occ3(seed=9)
+    q = np.random.default_rng(10).uniform(-math.pi, math.pi, (7, 6))
+    for eta in (1e-3, 2e-2):
+        _, amp, mdet, meh = O.morph_arm(arm, occ, q, 1, eta, diag=True, with_eh=True)
+        assert np.all(meh > 0)
+        assert np.all(amp <= 1 + meh + 1e-12)
+        small = meh < 1
+        assert np.all(mdet[small] >= (1 - meh[small]) ** 7 - 1e-12)
