@@ -29,14 +29,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X published peaks (256 CUs, 2.4 GHz).
-PEAK_FP32_VALU = 157.3e12          # FLOP/s, dense FP32 vector (packed issue)
+PEAK_FP32_VALU = 157.3e12          # FLOP/s, dense FP32 vector
 PEAK_FP32_MFMA = 157.3e12          # FLOP/s, dense FP32 matrix
 PEAK_BF16_MFMA = 2.5e15            # FLOP/s, dense BF16 matrix
 PEAK_F16_MFMA = 2.5e15             # FLOP/s, dense FP16 matrix
-# v_exp_f32 runs at half rate (8 cycles per wave64 on a 16-lane SIMD), i.e. 4 SIMDs x
-# 16 lanes x 1/2 per clock per CU; measured on the part it overlaps with
-# independent VALU work, so a pair costs max(flop time, exp time).
-PEAK_EXP = 256 * 4 * 16 * 0.5 * 2.4e9
+SIMDS, CLOCK_HZ = 1024, 2.4e9      # the peaks' SIMD count and clock
 FLOPS_PER_PAIR = {2: 12, 3: 17}    # 5*dim + 2 algorithmic FP32 flops per sample-hinge pair
 
 
@@ -79,27 +76,45 @@ def grid2d_utilisation():
             "binding_unit": "VALU issue", "source": "profiles/utilisation_ws2d_1M.md"}
 
 
-def split_scheme(x_axis, weights, ell):
-    """The split scheme the grid morph kernels take for these operands (each block of
-    the kernel decides the same from the same data): two-part FP16 splits, three
-    products, when every nonzero |w| is at least 2^-19 of the largest and no two
-    consecutive hinge x-coordinates are more than 6 apart in kappa units; three-part
-    BF16 splits, six products, otherwise."""
-    import numpy as np
-    w = np.abs(np.asarray(weights, dtype=np.float32))
-    kappa = np.float32(np.sqrt(np.log2(np.e) / 2.0) / ell)
-    g = np.unique(kappa * np.asarray(x_axis, dtype=np.float32))
-    ok = bool(np.all(np.isfinite(w)) and np.all(np.isfinite(g)))
-    if ok and len(g) > 1:
-        ok = float(np.diff(g).max()) <= 6.0
-    if ok and w.max() > 0:
-        ok = float(w[w > 0].min()) >= float(w.max()) * 2.0 ** -19
-    return ("fp16", 3) if ok else ("bf16", 6)
+# Issue costs measured on this device at the start of the run (pdmp_issue_rates:
+# shader-clock cycles per wave64 instruction on one SIMD); filled in by main().
+RATES = {}
 
 
 def alu_peak_tflops(dim):
+    """The pairwise kernels' ALU ceiling for their own work, 5 dim + 2 FP32 flops and
+    one exponential per pair, at the published 157.3 TF for the flops and the measured
+    v_exp_f32 cost for the exponential (the mixed probe shows the two classes adding on
+    the issue port, not overlapping), at the peaks' 2.4 GHz."""
     f = FLOPS_PER_PAIR[dim]
-    return f / max(f / PEAK_FP32_VALU, 1.0 / PEAK_EXP) / 1e12
+    exp_per_s = SIMDS * 64 * CLOCK_HZ / RATES["v_exp_f32"]
+    return f / (f / PEAK_FP32_VALU + 1.0 / exp_per_s) / 1e12
+
+
+def grid_ceiling(kind, n_units, per_unit):
+    """Achievable time of a grid kernel under its own formulation, from the measured
+    issue costs: per wave-step (2-D: one wave of 32 samples through one step; arm: one
+    wave of 4 configurations x 8 body points through one link) the MFMA pipe's time for
+    the split products and the least VALU time the formulation needs (the exponentials,
+    offsets, splits of the B operands and the contractions on the accumulator layout;
+    kernel overhead not counted).  Perfect overlap of the two gives the ceiling; the
+    sum is the time with none.  At the peaks' 2.4 GHz."""
+    c_f, c_e = RATES["v_fma_f32"], RATES["v_exp_f32"]
+    c_c, c_m = RATES["v_cvt_pk_f16_f32"], RATES["v_fma_mix_f32"]
+    x_val = 3 * c_f + c_e + 2 * (c_c + c_m)     # offset, argument, exp, ex dx, 2 FP16 splits
+    if kind == "ws2d":
+        xv, yr = per_unit["x_per_lane"], per_unit["y_per_lane"]
+        valu = xv * x_val + yr * (6 * c_f + c_e)    # y row: offset, argument, exp, 3 FMA + 1 mul
+    else:
+        xv, yv, zv, fm = (per_unit[k] for k in ("x_per_lane", "y_per_lane", "z_per_lane",
+                                                "contraction_fma_per_lane"))
+        valu = xv * x_val + (yv + zv) * (3 * c_f + c_e) + fm * c_f
+    mfma = per_unit["mfma"] * RATES["v_mfma_f32_32x32x16_f16"]
+    per_simd = n_units / SIMDS
+    to_ms = per_simd / CLOCK_HZ * 1e3
+    return {"valu_cycles_per_unit": valu, "mfma_cycles_per_unit": mfma,
+            "ceiling_ms": max(valu, mfma) * to_ms, "no_overlap_ms": (valu + mfma) * to_ms,
+            "unit": per_unit["unit"], "units": n_units}
 
 
 def log(msg):
@@ -124,6 +139,12 @@ def parse():
                    help="comma-separated secondary workloads after the headline: small, "
                         "density, culled, pipeline, tanh, arm (the 3-D fit and the arm "
                         "morph), amortised; or all")
+    p.add_argument("--rrt-runs", type=int, default=0,
+                   help="runs of the plane-RRT time-to-solution comparison (morph sampler "
+                        "against the prior) in the pipeline workload; 0 skips it")
+    p.add_argument("--no-trajectory-check", action="store_true",
+                   help="skip the oracle's one-step check along the bench's own GPU paths "
+                        "(it runs with the CPU baseline)")
     p.add_argument("--train-epochs", type=int, default=None)
     p.add_argument("--train-batches", type=int, default=None)
     return p.parse_args()
@@ -170,20 +191,114 @@ def ws_scene(P, I, K, torch, cfg, dev, grid=True):
                 fit_loss=(float(loss[0]), float(loss[-1])), w=w)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(O, h, w, ell, x0_np, cfg, n_sample):
+    """The FP64 oracle's morph on a strided sample of the headline batch, on all the
+    host's threads and (on a sixteenth of that sample) on one."""
     import numpy as np
     idx = np.linspace(0, x0_np.shape[1] - 1, n_sample).astype(np.int64)
     xs = np.ascontiguousarray(x0_np[:, idx])
     wb = w.cpu().numpy()
     occ_np = O.Occupancy(h, wb[:-1], float(wb[-1]), ell)
+    nt = O.num_threads()
     t0 = time.perf_counter()
     O.morph_ws(occ_np, xs, cfg.T, cfg.eta)
     dt = time.perf_counter() - t0
-    return {"value": n_sample / dt, "unit": "samples/s", "cores": O.num_threads(),
-            "kind": "oracle",
+    n1 = max(1, n_sample // 16)
+    O.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.morph_ws(occ_np, np.ascontiguousarray(xs[:, :n1]), cfg.T, cfg.eta)
+        dt1 = time.perf_counter() - t0
+    finally:
+        O.set_num_threads(nt)
+    return {"value": n_sample / dt, "unit": "samples/s", "cores": nt,
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{n_sample} of the {x0_np.shape[1]} prior samples of one batch (evenly "
                       f"strided), full T={cfg.T} FP64 morph over all {h.shape[1]} hinges; "
-                      f"{dt:.2f} s wall"}
+                      f"{dt:.2f} s wall",
+            "one_thread": {"value": n1 / dt1, "unit": "samples/s", "cores": 1,
+                           "sample": f"the first {n1} of those samples; {dt1:.2f} s wall"}}
+
+
+def trajectory_check(O, P, I, K, torch, hl, world):
+    """The oracle's one-step check along the GPU's own paths on this run's GPU-fitted
+    weights (the parity tests use oracle-fitted ones): the recording morph writes every
+    state of a strided subset of the headline batch (and of the arm batch), the oracle
+    takes one FP64 step from each recorded state, and the result is held to the
+    one-step tolerance 1e-5 (|x'| + eta G_abs).  Beside it: the step Jacobian's figures
+    at the visited states and the share of final states within the unscaled 1e-5 of
+    the oracle's own T-step path."""
+    import numpy as np
+    res = {}
+    cfg, occ = hl["cfg"], hl["sc"]["occ"]
+    h = hl["sc"]["h"]
+    wb = occ.weights.cpu().numpy()
+    oo = O.Occupancy(h, wb[:-1], float(wb[-1]), cfg.lengthscale)
+    x0 = P.uniform_samples(hl["seed"], 0, [cfg.lo] * 2, [cfg.hi] * 2, hl["N"])
+    stride = 2048
+    _, tr = P.morph_trajectory(occ, x0, cfg.T, cfg.eta, stride=stride)
+    tr = tr.cpu().numpy()
+    X = np.ascontiguousarray(tr[:-1].transpose(1, 0, 2).reshape(2, -1)).astype(np.float64)
+    Y = tr[1:].transpose(1, 0, 2).reshape(2, -1)
+    ref = O.morph_ws(oo, X, 1, cfg.eta)
+    _, _, _, gabs = O.occ_grad(oo, X)
+    err = np.abs(Y - ref)
+    tol = 1e-5 * (np.abs(ref) + cfg.eta * gabs[None, :])
+    _, _, mdet, meh = O.morph_ws(oo, X, 1, cfg.eta, diag=True)
+    refT = O.morph_ws(oo, tr[0].astype(np.float64), cfg.T, cfg.eta)
+    errT = np.abs(tr[-1] - refT).max(axis=0)
+    res["ws2d_large"] = {
+        "samples": int(tr.shape[2]), "stride": stride, "states": int(X.shape[1]),
+        "one_step_max_err_over_tol": float((err / tol).max()),
+        "one_step_within_tol": bool(np.all(err <= tol)),
+        "share_final_within_unscaled_1e-5": float(
+            np.mean(errT <= 1e-5 * np.maximum(1.0, np.abs(refT).max(axis=0)))),
+        "max_eta_hess": float(meh.max()), "steps_det_nonpositive": int((mdet <= 0).sum())}
+    if world is not None:
+        c3 = K.C3
+        arm, aocc = world["arm"], world["occ"]
+        awb = aocc.weights.cpu().numpy()
+        aoo = O.Occupancy(aocc.hinges.cpu().numpy(), awb[:-1], float(awb[-1]), c3.lengthscale)
+        aarm = O.Arm(*I.dh_params(c3.cfg_id, c3.n_dof, c3.link_min, c3.link_max, c3.alpha),
+                     c3.pts_per_link)
+        q0 = P.uniform_samples(I.philox_seed(c3.cfg_id), 0, [c3.q_lo] * 7, [c3.q_hi] * 7,
+                               c3.n_samples)
+        stride = 1024
+        _, tq = P.morph_trajectory(aocc, q0, c3.T, c3.eta, stride=stride, arm=arm)
+        tq = tq.cpu().numpy()
+        Q = np.ascontiguousarray(tq[:-1].transpose(1, 0, 2).reshape(7, -1)).astype(np.float64)
+        Yq = tq[1:].transpose(1, 0, 2).reshape(7, -1)
+        refq = O.morph_arm(aarm, aoo, Q, 1, c3.eta)
+        scale = O.arm_step_scale(aarm, aoo, Q)
+        errq = np.abs(Yq - refq)
+        tolq = 1e-5 * (np.abs(refq) + c3.eta * scale[None, :])
+        sub = tq[:, :, ::4]
+        Qs = np.ascontiguousarray(sub[:-1].transpose(1, 0, 2).reshape(7, -1)).astype(np.float64)
+        _, _, mdq, mehq = O.morph_arm(aarm, aoo, Qs, 1, c3.eta, diag=True, with_eh=True)
+        refT = O.morph_arm(aarm, aoo, tq[0].astype(np.float64), c3.T, c3.eta)
+        errT = np.abs(tq[-1] - refT).max(axis=0)
+        res["arm7"] = {
+            "configs": int(tq.shape[2]), "stride": stride, "states": int(Q.shape[1]),
+            "one_step_max_err_over_tol": float((errq / tolq).max()),
+            "one_step_within_tol": bool(np.all(errq <= tolq)),
+            "share_final_within_unscaled_1e-5": float(
+                np.mean(errT <= 1e-5 * np.maximum(1.0, np.abs(refT).max(axis=0)))),
+            "diag_configs": int(sub.shape[2]), "max_eta_hess": float(mehq.max()),
+            "steps_det_nonpositive": int((mdq <= 0).sum()),
+            "paths_with_a_folding_step": int((mdq.reshape(c3.T, -1) <= 0).any(axis=0).sum())}
+    return res
 
 
 def headline(args, P, I, K, torch, dev):
@@ -201,9 +316,12 @@ def headline(args, P, I, K, torch, dev):
     hit0 = torch.zeros(1, dtype=torch.int64, device=dev)
     hit1 = torch.zeros(1, dtype=torch.int64, device=dev)
     lo, hi = [cfg.lo] * 2, [cfg.hi] * 2
-    ev = []
+    ev, sev = [], []
 
     def step(i, record):
+        if record:
+            s_ = Timer(torch)
+            s_.__enter__()
         P.uniform_samples(seed, i, lo, hi, N, out=x0)
         P.label_points_discs(dc_d, dr_d, x0, count=True, out=lab0, hit=hit0)
         if record:
@@ -214,6 +332,9 @@ def headline(args, P, I, K, torch, dev):
             e.__exit__()
             ev.append(e)
         P.label_points_discs(dc_d, dr_d, x1, count=True, out=lab1, hit=hit1)
+        if record:
+            s_.__exit__()
+            sev.append(s_)
 
     for i in range(args.warmup):
         step(1000 + i, False)
@@ -225,33 +346,49 @@ def headline(args, P, I, K, torch, dev):
             step(i, True)
     total_ms = tt.ms()
     ms_step = total_ms / args.steps
-    morph_ms = sum(e.ms() for e in ev) / len(ev)
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, morph {morph_ms:.3f} ms")
-    res = dict(cfg=cfg, N=N, ms_step=ms_step, morph_ms=morph_ms,
+    kms = sorted(e.ms() for e in ev)
+    morph_ms = sum(kms) / len(kms)
+    morph_median = kms[len(kms) // 2] if len(kms) % 2 else 0.5 * (kms[len(kms) // 2 - 1] +
+                                                                    kms[len(kms) // 2])
+    sms = sorted(e.ms() for e in sev)
+    step_median = sms[len(sms) // 2] if len(sms) % 2 else 0.5 * (sms[len(sms) // 2 - 1] +
+                                                                   sms[len(sms) // 2])
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step (median {step_median:.3f}), "
+        f"morph {morph_ms:.3f} ms (median {morph_median:.3f})")
+    res = dict(cfg=cfg, N=N, ms_step=ms_step, step_median=step_median, morph_ms=morph_ms,
+               morph_median=morph_median,
                free_before=1.0 - hit0.item() / N, free_after=1.0 - hit1.item() / N, sc=sc,
                seed=seed, x0=x0)
     G0 = G1 = cfg.grid
     if occ.grid:
-        # own algorithmic work of the factorised evaluation, per sample and step: two
-        # G1 x G0 matrix-vector products (4 G0 G1 FP32 flops), each FP32 multiply-add
-        # carried out as the split scheme's products (three FP16 or six BF16)
-        scheme, nprod = split_scheme(occ.hinges[0, :G0].cpu().numpy(),
-                                     occ.weights[:-1].cpu().numpy(), occ.lengthscale)
+        # the scheme the library ran, and the algorithmic work of the factorised
+        # evaluation per sample and step: two G1 x G0 matrix-vector products, 4 G0 G1
+        # FP32 flops, run on the matrix cores at FP32 accuracy as split products
+        scheme, nprod = P.split_scheme(occ)
         fp32_tf = N * cfg.T * 4.0 * G0 * G1 / (morph_ms * 1e-3) / 1e12
-        achieved = nprod * fp32_tf
         peak = PEAK_F16_MFMA if scheme == "fp16" else PEAK_BF16_MFMA
         res["scheme"] = scheme
-        res["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak / 1e12,
-                           "unit": "TFLOP/s", "frac": achieved * 1e12 / peak,
+        ks, tb = (G0 + 15) // 16, (G1 + 31) // 32
+        ceil = grid_ceiling("ws2d", -(-N // 32) * cfg.T,
+                            {"unit": "wave-step (32 samples, one Euler step)",
+                             "x_per_lane": 8 * ks, "y_per_lane": 16 * tb,
+                             "mfma": 2 * nprod * ks * tb}) if scheme == "fp16" else None
+        if ceil:
+            ceil["frac"] = ceil["ceiling_ms"] / morph_ms
+        res["roofline"] = {"bound": "mfma", "achieved": fp32_tf, "peak": peak / 1e12,
+                           "unit": "TFLOP/s", "frac": fp32_tf * 1e12 / peak,
                            "traffic": grid2d_traffic(), "kernel": "k_grid2d_mfma<2,4,kMorph>",
-                           "kernel_ms": morph_ms, "split_scheme": scheme,
+                           "kernel_ms": morph_ms, "kernel_ms_median": morph_median,
+                           "split_scheme": scheme,
+                           "work": "4*G0*G1 FP32-accurate flops per sample-step (64x64 grid): "
+                                   "the two G1 x G0 contractions, on "
+                                   f"{scheme.upper()} MFMA as {nprod} split products each",
+                           "mfma_issue": {"products_per_multiply_add": nprod,
+                                          "achieved": nprod * fp32_tf,
+                                          "frac": nprod * fp32_tf * 1e12 / peak,
+                                          "max_frac": 1.0 / nprod},
+                           "ceiling": ceil,
                            "utilisation": grid2d_utilisation(),
-                           "work": f"{4 * nprod}*G0*G1 {scheme.upper()} MFMA flops per "
-                                   "sample-step (64x64 grid): the two FP32 contractions "
-                                   f"(4*G0*G1 flops) as the {nprod} leading products of the "
-                                   f"{scheme.upper()} splits",
-                           "fp32_equivalent_tflops": fp32_tf,
-                           "fp32_equivalent_frac_of_fp32_mfma_peak": fp32_tf * 1e12 / PEAK_FP32_MFMA,
                            "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE + "
                                            "WRITE_SIZE, copy-calibrated); algorithmic "
                                            f"{N * 2 * 4 * 2} bytes"}
@@ -348,26 +485,36 @@ def arm_morph(P, I, K, torch, world):
     ms = t.ms() / reps
     _, h0 = P.label_configs(arm, *world["boxes"], q0, count=True)
     _, h1 = P.label_configs(arm, *world["boxes"], q1, count=True)
-    # own work of the factorised evaluation per body point and step: two (16*16) x 16
-    # matrix-vector products = 4 * 4096 FP32 flops, each multiply-add as the split
-    # scheme's products (three FP16 or six BF16)
-    scheme, nprod = split_scheme(occ.hinges[0, :c3.grid].cpu().numpy(),
-                                 occ.weights[:-1].cpu().numpy(), occ.lengthscale)
+    # algorithmic work of the factorised evaluation per body point and step: two
+    # (16*16) x 16 matrix-vector products = 4 * 4096 FP32 flops, on the matrix cores at
+    # FP32 accuracy as the split scheme's products (three FP16 or six BF16)
+    scheme, nprod = P.split_scheme(occ)
     peak = PEAK_F16_MFMA if scheme == "fp16" else PEAK_BF16_MFMA
     fp32_tf = c3.n_samples * c3.T * c3.n_body * 4.0 * c3.n_hinges / (ms * 1e-3) / 1e12
-    ach = nprod * fp32_tf
+    ceil = grid_ceiling("arm", (c3.n_samples // 4) * c3.T * c3.n_dof,
+                        {"unit": "wave link-step (4 configurations x 8 body points, one "
+                                 "link, one step)",
+                         "x_per_lane": 8, "y_per_lane": 8, "z_per_lane": 16,
+                         "contraction_fma_per_lane": 8 * 56,
+                         "mfma": 2 * nprod * 8}) if scheme == "fp16" else None
+    if ceil:
+        ceil["frac"] = ceil["ceiling_ms"] / ms
     res = {"workload": "plain morph 7-DOF arm: 65,536 configurations, 56 body points, 16^3 "
                        "hinges, l=0.15, T=30, eta=0.01, 40 boxes",
            "morph_ms": ms, "samples_per_s": c3.n_samples / (ms * 1e-3),
            "collision_free_before": 1 - h0.item() / c3.n_samples,
            "collision_free_after": 1 - h1.item() / c3.n_samples,
-           "roofline": {"bound": "mfma", "achieved": ach, "peak": peak / 1e12,
-                        "unit": "TFLOP/s", "frac": ach * 1e12 / peak,
+           "roofline": {"bound": "mfma", "achieved": fp32_tf, "peak": peak / 1e12,
+                        "unit": "TFLOP/s", "frac": fp32_tf * 1e12 / peak,
                         "kernel": "k_arm_grid3d<7,16,16,true>", "split_scheme": scheme,
-                        "work": f"{4 * nprod}*M {scheme.upper()} MFMA flops per body point "
-                                "and step (the two FP32 contractions, 4*M flops, as the "
-                                f"{nprod} leading products of the {scheme.upper()} splits)",
-                        "fp32_equivalent_tflops": fp32_tf}}
+                        "work": "4*M FP32-accurate flops per body point and step (the two "
+                                f"contractions), on {scheme.upper()} MFMA as {nprod} split "
+                                "products each",
+                        "mfma_issue": {"products_per_multiply_add": nprod,
+                                       "achieved": nprod * fp32_tf,
+                                       "frac": nprod * fp32_tf * 1e12 / peak,
+                                       "max_frac": 1.0 / nprod},
+                        "ceiling": ceil}}
     dense = P.Occupancy(occ.hinges, occ.weights, occ.lengthscale)
     P.morph_samples(dense, q0, c3.T, c3.eta, arm=arm, out=q1)
     t = Timer(torch)
@@ -424,13 +571,15 @@ def tanh_morph(P, I, K, torch, dev):
             "morph_ms": ms, "samples_per_s": N / (ms * 1e-3),
             "collision_free_before": 1 - h0.item() / N,
             "collision_free_after": 1 - h1.item() / N,
-            "roofline": {"bound": "mfma", "achieved": 6.0 * ach, "peak": PEAK_BF16_MFMA / 1e12,
-                         "unit": "TFLOP/s", "frac": 6.0 * ach * 1e12 / PEAK_BF16_MFMA,
+            "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_MFMA / 1e12,
+                         "unit": "TFLOP/s", "frac": ach * 1e12 / PEAK_BF16_MFMA,
                          "kernel": f"k_tanh_net<2,4,{L},kMorph>",
-                         "work": "24*(L-1)*H^2 BF16 MFMA flops per sample-step (the forward "
-                                 "and backward hidden products, 4*(L-1)*H^2 FP32 flops, as six "
-                                 "BF16 products of three-way splits)",
-                         "fp32_equivalent_tflops": ach}}
+                         "work": "4*(L-1)*H^2 FP32-accurate flops per sample-step (the forward "
+                                 "and backward hidden products), on BF16 MFMA as six products "
+                                 "of three-way splits",
+                         "mfma_issue": {"products_per_multiply_add": 6, "achieved": 6.0 * ach,
+                                        "frac": 6.0 * ach * 1e12 / PEAK_BF16_MFMA,
+                                        "max_frac": 1.0 / 6}}}
 
 
 def density_workload(P, I, K, torch, hl):
@@ -464,8 +613,7 @@ def density_workload(P, I, K, torch, hl):
     _, hm = P.label_points_discs(dc_d, dr_d, mixed, count=True)
     # U, V, Q products (6 G0 G1 FP32-equivalent flops) per sample-step on the logdet
     # path, each multiply-add as the split scheme's products (three FP16 or six BF16)
-    scheme, nprod = split_scheme(occ.hinges[0, :G0].cpu().numpy(),
-                                 occ.weights[:-1].cpu().numpy(), occ.lengthscale)
+    scheme, nprod = P.split_scheme(occ)
     peak = PEAK_F16_MFMA if scheme == "fp16" else PEAK_BF16_MFMA
     sname = scheme.upper()
     ach = N * cfg.T * 6.0 * G0 * G1 / (ld_ms * 1e-3) / 1e12
@@ -481,37 +629,40 @@ def density_workload(P, I, K, torch, hl):
             "logdet_mean": ld.mean().item(),
             "mixture_ms": mix_ms, "mixture_kept_fraction": keep.float().mean().item(),
             "mixture_collision_free": 1 - hm.item() / N,
-            "roofline_logdet": {"bound": "mfma", "achieved": nprod * ach,
+            "roofline_logdet": {"bound": "mfma", "achieved": ach,
                                 "peak": peak / 1e12, "unit": "TFLOP/s",
-                                "frac": nprod * ach * 1e12 / peak,
+                                "frac": ach * 1e12 / peak,
                                 "kernel": "k_grid2d_inv<2,4,kLogdet>", "split_scheme": scheme,
-                                "work": f"{6 * nprod}*G0*G1 {sname} MFMA flops per sample-step "
-                                        "(the three FP32 contractions, 6*G0*G1 flops, as the "
-                                        f"{nprod} leading products of the {sname} splits)",
-                                "fp32_equivalent_tflops": ach},
+                                "work": "6*G0*G1 FP32-accurate flops per sample-step (the three "
+                                        f"contractions), on {sname} MFMA as {nprod} split "
+                                        "products each",
+                                "mfma_issue_frac": nprod * ach * 1e12 / peak},
             "roofline_inverse": {"bound": "mfma",
-                                 "achieved": nprod * inv_flops / (inv_ms * 1e-3) / 1e12,
+                                 "achieved": inv_flops / (inv_ms * 1e-3) / 1e12,
                                  "peak": peak / 1e12, "unit": "TFLOP/s",
-                                 "frac": nprod * inv_flops / (inv_ms * 1e-3) / peak,
+                                 "frac": inv_flops / (inv_ms * 1e-3) / peak,
                                  "kernel": "k_grid2d_inv<2,4,kInverse>", "split_scheme": scheme,
-                                 "work": f"{nprod}*(4*iters + 6)*G0*G1 {sname} MFMA flops per "
-                                         "sample-step",
-                                 "fp32_equivalent_tflops": inv_flops / (inv_ms * 1e-3) / 1e12}}
+                                 "work": "(4*iters + 6)*G0*G1 FP32-accurate flops per "
+                                         f"sample-step, on {sname} MFMA as {nprod} split "
+                                         "products each",
+                                 "mfma_issue_frac": nprod * inv_flops / (inv_ms * 1e-3) / peak}}
 
 
-def pipeline_workload(P, I, K, torch, dev, hl):
+def pipeline_workload(args, P, I, K, torch, dev, hl):
     """The producer/consumer of Sec. 3.3: a background GPU sampler filling the bucket,
-    a plane RRT drawing from it (prior when empty).  (a) time to solution in config 1's
-    world, morph sampler against the prior, 10 runs each; (b) the morphed share of the
-    consumed samples over time and the producer's delivered rate in config 2's world."""
+    a plane RRT drawing from it (prior when empty).  (a) the morphed share of the
+    consumed samples over time and the producer's delivered rate in config 2's world;
+    (b) with --rrt-runs R, the plane RRT's time to solution in config 1's world with the
+    morph sampler against the prior, R runs each (a planner comparison, off by
+    default)."""
     import numpy as np
     out = {}
     c1 = K.C1
-    sc1 = ws_scene(P, I, K, torch, c1, dev)
     dc1, dr1 = I.discs(c1.cfg_id, c1.n_discs, c1.lo, c1.hi, c1.r_min, c1.r_max)
     start, goal = K.RRT_START_GOAL[1]
     runs = {"prior": [], "morph": []}
-    for r in range(10):
+    sc1 = ws_scene(P, I, K, torch, c1, dev) if args.rrt_runs > 0 else None
+    for r in range(args.rrt_runs):
         for kind in ("prior", "morph"):
             s = P.Sampler(sc1["occ"] if kind == "morph" else None, 2, [c1.lo] * 2, [c1.hi] * 2,
                           c1.T, c1.eta, c1.n_samples, 1 << 16, seed=I.philox_seed(c1.cfg_id),
@@ -524,6 +675,8 @@ def pipeline_workload(P, I, K, torch, dev, hl):
                                "from_bucket": res["from_bucket"], "path_len": res["path_len"]})
             s.close()
     for kind, rs in runs.items():
+        if not rs:
+            continue
         ok = [x for x in rs if x["solved"]]
         out[f"config1_{kind}"] = {
             "solved": len(ok), "runs": len(rs),
@@ -732,6 +885,9 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 2 x 256 MiB device copies")
         del src, dst
+    RATES.update(P.issue_rates())
+    log("issue costs (cycles per wave64 instruction per SIMD): " +
+        ", ".join(f"{k} {v:.2f}" for k, v in RATES.items()))
     hl = headline(args, P, I, K, torch, dev)
     cfg = hl["cfg"]
     out = {
@@ -742,6 +898,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": hl["ms_step"],
+        "ms_per_step_median": hl["step_median"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -755,10 +912,15 @@ def main():
         "collision_free_before": hl["free_before"],
         "collision_free_after": hl["free_after"],
         "roofline": hl["roofline"],
+        "issue_rates": {"cycles_per_wave64_instruction": {k: v for k, v in RATES.items()
+                                                          if k != "clock_ghz"},
+                        "probe_clock_ghz": RATES["clock_ghz"],
+                        "source": "pdmp_issue_rates on this device, this run"},
     }
     if "pairwise" in hl:
         out["pairwise_kernel"] = hl["pairwise"]
     out["fit_ms"] = hl["sc"]["fit_ms"]
+    world = None
     if not args.headline_only:
         wl = {}
         try:
@@ -773,7 +935,7 @@ def main():
                 wl["culled_ws2d"] = culled_workload(P, I, K, torch, hl)
                 log(f"culled morph: {wl['culled_ws2d']['morph_ms']:.2f} ms")
             if "pipeline" in sel:
-                wl["pipeline"] = pipeline_workload(P, I, K, torch, dev, hl)
+                wl["pipeline"] = pipeline_workload(args, P, I, K, torch, dev, hl)
                 log("producer/consumer done")
             if "tanh" in sel:
                 wl["tanh_ws2d"] = tanh_morph(P, I, K, torch, dev)
@@ -797,12 +959,20 @@ def main():
             wl["error"] = f"{type(e).__name__}: {e}"
         out["workloads"] = wl
     if not args.no_cpu_baseline:
+        # the FP64 oracle on the host: the CPU baseline, and its one-step check along the
+        # GPU paths of this run
         import oracle as O
         log("cpu baseline ...")
         P.uniform_samples(hl["seed"], 0, [cfg.lo] * 2, [cfg.hi] * 2, hl["N"], out=hl["x0"])
         x0_np = hl["x0"].cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(O, hl["sc"]["h"], hl["sc"]["w"], cfg.lengthscale,
                                            x0_np, cfg, args.cpu_sample)
+        if not args.no_trajectory_check:
+            log("one-step check along the GPU paths ...")
+            try:
+                out["trajectory_check"] = trajectory_check(O, P, I, K, torch, hl, world)
+            except Exception as e:  # reported, the headline stands on its own
+                out["trajectory_check"] = {"error": f"{type(e).__name__}: {e}"}
     print(json.dumps(out), flush=True)
 
 

@@ -170,6 +170,14 @@ int32_t pdmp_morph_trajectory(const pdmp_occupancy *occ, const pdmp_arm *arm, co
                               float *out, int64_t n, int32_t T, float eta, float *traj,
                               int64_t traj_stride, void *stream);
 
+/* The split scheme the grid morph kernels take for this occupancy (the grid field
+ * above): *scheme = 2 for two-part FP16 splits (three products per FP32 multiply-add),
+ * 1 for three-part BF16 splits (six products), 0 when the morph takes no grid kernel
+ * (no grid, or a grid the grid kernels do not cover: the pairwise sum).  Decided on
+ * the device by the morph kernels' own staging code from the same data.  scheme is a
+ * HOST pointer; the call waits for `stream`. */
+int32_t pdmp_split_scheme(const pdmp_occupancy *occ, int32_t *scheme, void *stream);
+
 /* ---- the density of the morphed samples and the inverse map (Sec. 3.2: the flow's
  * inverse integrates the reversed field; the change of variables gives the
  * density p_z(z) = p_y(y) / |det D phi(y)|).  Workspace morph only (no arm);
@@ -392,6 +400,20 @@ int32_t pdmp_tanh_fit(const pdmp_tanh_net *net, const float *pts, const uint8_t 
                       int64_t n, const pdmp_fit_opts *opts, float *loss_out, void *ws,
                       size_t ws_bytes, void *stream);
 
+/* ---- diagnostics.  Measured issue costs on the current device, in shader-clock cycles
+ * per wave64 instruction on one SIMD, from probe kernels of one instruction class each
+ * (eight independent dependency chains per lane, eight waves per SIMD):
+ *   out[0] v_fma_f32, out[1] v_exp_f32, out[2] v_cvt_pk_f16_f32, out[3] v_fma_mix_f32;
+ *   out[4] one iteration of 4 v_exp_f32 and 4 v_fma_f32 in independent chains (4 out[1] +
+ *          4 out[0] if the two classes add, less if they overlap);
+ *   out[5] v_mfma_f32_32x32x16_f16 (four independent accumulators, four waves per SIMD);
+ *   out[6] one iteration of 4 such MFMAs and 32 independent v_fma_f32 (four waves per
+ *          SIMD: 4 out[5] + 32 out[0] if they add, the larger of the two if they overlap);
+ *   out[7] the mean shader clock over the probes, GHz.
+ * The first min(n_out, 8) figures are written to out (HOST).  Host-synchronous; allocates
+ * and frees its own device memory.  The benchmark states its ceilings with these. */
+int32_t pdmp_issue_rates(double *out, int32_t n_out);
+
 /* ---- the producer/consumer of Sec. 3.3: a background diffeomorphic sampler keeps a
  * bounded concurrent bucket S filled with morphed samples; the planner's main thread
  * draws from S and never waits -- when S is empty it draws from the prior instead,
@@ -445,7 +467,9 @@ typedef struct {
 /* create: occ (nullable: a prior-only sampler) is copied; the device buffers it
  *   points to must outlive the sampler.  start: spawns the producer thread on the
  *   calling thread's current device (its own non-blocking HIP stream, default
- *   priority, device and pinned host buffers of a few batches).  pause: the
+ *   priority, device and pinned host buffers of a few batches); a producer that has
+ *   stopped on a failure is not restarted (PDMP_EINVAL, the failure's message in
+ *   pdmp_last_error()).  pause: the
  *   producer stops launching and pushing while paused != 0 (forces an empty S).
  *   pop: n samples into x [n][dim] (row per sample), index [n] and from_bucket [n]
  *   (both nullable); never waits.  Single consumer thread.  destroy: stops and

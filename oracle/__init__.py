@@ -43,6 +43,7 @@ def _load():
     lib = C.CDLL(_LIB_PATH)
     sig = {
         "orc_num_threads": (C.c_int, []),
+        "orc_set_num_threads": (None, [C.c_int]),
         "orc_philox4x32_10": (None, [_u32p, _u32p, _u32p]),
         "orc_uniform_samples": (None, [C.c_uint64, C.c_uint32, _fp, _fp, C.c_int, _i64, _fp]),
         "orc_label_discs": (None, [_dp, _dp, _dp, C.c_int, _dp, _i64, _u8p]),
@@ -114,6 +115,11 @@ def _load():
 def num_threads() -> int:
     """OpenMP threads the oracle uses (OMP_NUM_THREADS, else all host cores)."""
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads the oracle's parallel loops use from now on."""
+    _load().orc_set_num_threads(int(n))
 
 
 def _d(a):

@@ -48,6 +48,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads the following parallel regions use (n >= 1). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------- */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011, Sec. 4 and Table 2).  */
 /* ------------------------------------------------------------------------- */

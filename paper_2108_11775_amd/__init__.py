@@ -21,7 +21,8 @@ from ._lib import PdmpError
 
 __all__ = ["Occupancy", "Arm", "PdmpError", "abi_version", "uniform_samples",
            "label_points_discs", "label_points_boxes", "label_configs", "occupancy_eval",
-           "occupancy_grad", "morph_samples", "morph_trajectory", "fk_body_points", "sync",
+           "occupancy_grad", "morph_samples", "morph_trajectory", "split_scheme", "issue_rates",
+           "fk_body_points", "sync",
            "occupancy_bwd", "bce_logits", "adam_step", "fit_occupancy", "Mlp", "arm_max_occupancy",
            "amortised_morph", "TanhNet", "tanh_occupancy_eval", "tanh_occupancy_grad",
            "tanh_morph_samples", "tanh_loss_grad", "tanh_fit", "morph_logdet", "morph_inverse",
@@ -227,6 +228,32 @@ def morph_samples(occ: Occupancy, x, T: int, eta: float, arm: Optional[Arm] = No
               _dev(out, "out", torch.float32, (rows, n)), n, int(T), float(eta),
               _stream(x.device))
     return out
+
+
+SPLIT_SCHEMES = {0: ("pairwise", None), 1: ("bf16", 6), 2: ("fp16", 3)}
+
+
+def split_scheme(occ: Occupancy):
+    """(name, products per FP32 multiply-add) of the split scheme the grid morph
+    kernels take for this occupancy, as the library decides it: ("fp16", 3),
+    ("bf16", 6), or ("pairwise", None) when the morph takes no grid kernel."""
+    torch = _torch()
+    v = C.c_int32(-1)
+    _lib.call("pdmp_split_scheme", C.byref(occ.c_struct()), C.byref(v),
+              _stream(occ.hinges.device if isinstance(occ.hinges, torch.Tensor) else None))
+    return SPLIT_SCHEMES[int(v.value)]
+
+
+ISSUE_RATE_KEYS = ("v_fma_f32", "v_exp_f32", "v_cvt_pk_f16_f32", "v_fma_mix_f32",
+                   "iter_4exp_4fma", "v_mfma_f32_32x32x16_f16", "iter_4mfma_32fma", "clock_ghz")
+
+
+def issue_rates() -> dict:
+    """Measured issue costs on the current device (cycles per wave64 instruction on one
+    SIMD; the two mixed entries are cycles per iteration) and the probes' clock."""
+    out = (C.c_double * len(ISSUE_RATE_KEYS))()
+    _lib.call("pdmp_issue_rates", out, len(ISSUE_RATE_KEYS))
+    return dict(zip(ISSUE_RATE_KEYS, [float(v) for v in out]))
 
 
 def morph_trajectory(occ: Occupancy, x, T: int, eta: float, stride: int = 1,

@@ -425,6 +425,41 @@ k_grid2d_small(const float *__restrict__ hinges, const float *__restrict__ weigh
     }
 }
 
+// The split scheme the 2-D grid morphs take for these operands (every block of those
+// kernels decides the same from the same data): one block runs their staging and
+// writes 2 (two-part FP16 splits) or 1 (three-part BF16 splits).
+template <int TB, int KS>
+__global__ void __launch_bounds__(kG2Block)
+k_grid2d_scheme(const float *__restrict__ hinges, const float *__restrict__ weights, int g0, int g1,
+                float kappa, int32_t *out) {
+    __shared__ uint4 fraw[3 * KS * TB * 64];
+    __shared__ float gxs[16 * KS];
+    __shared__ float gys[32 * TB];
+    __shared__ SplitRange rg;
+    const SplitScheme sc =
+        g2_stage<TB, KS, true>(fraw, gxs, gys, rg, hinges, weights, g0, g1, kappa);
+    if (threadIdx.x == 0) *out = sc.fp16 ? 2 : 1;
+}
+
+int32_t launch_grid2d_scheme(const float *hinges, const float *weights, int g0, int g1,
+                             float kappa, int32_t *out, hipStream_t st) {
+    if (g0 < 1 || g1 < 1 || g0 > 64 || g1 > 64) return PDMP_EUNSUPPORTED;
+    // the morph kernels' own tile counts (the staging pads to them)
+#define PDMP_G2Q(TB, KS)                                                                     \
+    hipLaunchKernelGGL((k_grid2d_scheme<TB, KS>), dim3(1), dim3(kG2Block), 0, st, hinges,    \
+                       weights, g0, g1, kappa, out)
+    const int ks = (g0 + 15) / 16;
+    if (g1 <= 32) {
+        if (ks == 1) PDMP_G2Q(1, 1); else if (ks == 2) PDMP_G2Q(1, 2);
+        else if (ks == 3) PDMP_G2Q(1, 3); else PDMP_G2Q(1, 4);
+    } else {
+        if (ks == 1) PDMP_G2Q(2, 1); else if (ks == 2) PDMP_G2Q(2, 2);
+        else if (ks == 3) PDMP_G2Q(2, 3); else PDMP_G2Q(2, 4);
+    }
+#undef PDMP_G2Q
+    return check_launch("k_grid2d_scheme");
+}
+
 // Morphs of fewer samples than this take the 16-sample waves.
 constexpr int64_t kG2SmallBatch = (int64_t)1 << 17;
 

@@ -486,6 +486,26 @@ static bool g3_supported(const int *grid, int M) {
     return grid && grid[0] == 16 && grid[1] == kG3Y && grid[2] == 16 && M == 4096;
 }
 
+// The split scheme the 3-D grid morphs (workspace and arm) take: one block runs their
+// staging and writes 2 (two-part FP16 splits) or 1 (three-part BF16 splits).
+__global__ void __launch_bounds__(kG3Block)
+k_grid3d_scheme(const float *__restrict__ hinges, const float *__restrict__ weights, float kappa,
+                int32_t *out) {
+    using C = G3<16, 16>;
+    __shared__ uint4 fraw[C::FRAG];
+    __shared__ float ax[16], ay[kG3Y], az[16];
+    __shared__ SplitRange rg;
+    const SplitScheme sc = g3_stage<16, 16>(fraw, ax, ay, az, rg, hinges, weights, kappa, true);
+    if (threadIdx.x == 0) *out = sc.fp16 ? 2 : 1;
+}
+
+int32_t launch_grid3d_scheme(const float *hinges, const float *weights, const int *grid, int M,
+                             float kappa, int32_t *out, hipStream_t st) {
+    if (!g3_supported(grid, M)) return PDMP_EUNSUPPORTED;
+    hipLaunchKernelGGL(k_grid3d_scheme, dim3(1), dim3(kG3Block), 0, st, hinges, weights, kappa, out);
+    return check_launch("k_grid3d_scheme");
+}
+
 int32_t launch_grid3d_ws(int mode, const RbfArgs &a, const int *grid, hipStream_t st) {
     if (!g3_supported(grid, a.M) || (mode != kEval && mode != kGrad && mode != kMorph))
         return PDMP_EUNSUPPORTED;

@@ -256,6 +256,40 @@ int32_t pdmp_morph_trajectory(const pdmp_occupancy *occ, const pdmp_arm *arm, co
     return morph_impl(occ, arm, in, out, n, T, eta, tr, stream);
 }
 
+int32_t pdmp_split_scheme(const pdmp_occupancy *occ, int32_t *scheme, void *stream) {
+    int32_t st = check_occ(occ);
+    if (st) return st;
+    PDMP_REQUIRE(scheme != nullptr, "scheme NULL");
+    *scheme = 0;
+    if (!has_grid(occ)) return PDMP_OK;
+    float kappa, gscale;
+    derive_scales(occ->lengthscale, kappa, gscale);
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(int32_t));
+    if (e != hipSuccess) {
+        set_error("hipMalloc: %s", hipGetErrorString(e));
+        return PDMP_EDEVICE;
+    }
+    st = occ->dim == 2 ? launch_grid2d_scheme(occ->hinges, occ->weights, occ->grid[0],
+                                              occ->grid[1], kappa, d, s)
+                       : launch_grid3d_scheme(occ->hinges, occ->weights, occ->grid,
+                                              occ->n_hinges, kappa, d, s);
+    int32_t v = 0;
+    if (st == PDMP_OK) {
+        e = hipMemcpyAsync(&v, d, sizeof(v), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            set_error("split scheme query: %s", hipGetErrorString(e));
+            st = PDMP_EDEVICE;
+        }
+    }
+    (void)hipFree(d);
+    if (st == PDMP_EUNSUPPORTED) return PDMP_OK;  // the pairwise kernels: *scheme = 0
+    if (st == PDMP_OK) *scheme = v;
+    return st;
+}
+
 int32_t pdmp_morph_logdet(const pdmp_occupancy *occ, const float *in, float *out, int64_t n,
                           int32_t T, float eta, float *logdet, void *stream) {
     int32_t st = check_occ(occ);

@@ -135,6 +135,12 @@ int32_t launch_arm_grid3d(const pdmp_arm &arm, const float *h, const float *w, i
 // mismatch is reported by the next pdmp_sync on the device), and take that report.
 int32_t launch_grid_check(int dim, const float *hinges, int M, const int *grid, hipStream_t st);
 int32_t take_grid_mismatch(bool &mismatch);
+// The split scheme of the grid morph kernels for these operands, written to out (device):
+// 2 (FP16 parts) or 1 (BF16 parts); PDMP_EUNSUPPORTED when no grid kernel covers them.
+int32_t launch_grid2d_scheme(const float *hinges, const float *weights, int g0, int g1,
+                             float kappa, int32_t *out, hipStream_t st);
+int32_t launch_grid3d_scheme(const float *hinges, const float *weights, const int *grid, int M,
+                             float kappa, int32_t *out, hipStream_t st);
 // The occupancy evaluation of one RBF launch, through the grid factorisation when
 // `grid` describes one the grid kernels support, else the pairwise kernel.
 int32_t launch_occ_any(int dim, int mode, const RbfArgs &a, const int *grid, hipStream_t st);

@@ -310,6 +310,16 @@ int32_t pdmp_sampler_start(pdmp_sampler *s) {
     PDMP_REQUIRE(s != nullptr, "sampler NULL");
     PDMP_REQUIRE(s->occ.hinges != nullptr, "the sampler has no occupancy (prior only)");
     PDMP_REQUIRE(!s->running.load(), "already running");
+    if (s->th.joinable()) {
+        // the producer ended on its own, which it does only on a failure: join it and
+        // keep that failure visible instead of starting over
+        s->th.join();
+        const int32_t prev = s->status.load(std::memory_order_acquire);
+        if (prev != PDMP_OK) {
+            set_error("the producer stopped with an error, destroy the sampler (%s)", s->err);
+            return PDMP_EINVAL;
+        }
+    }
     hipError_t e = hipGetDevice(&s->device);
     if (e != hipSuccess) {
         set_error("hipGetDevice: %s", hipGetErrorString(e));

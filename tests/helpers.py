@@ -66,6 +66,24 @@ def gpu_occ(h, wb, ell, grid=None):
     return P.Occupancy(dev(h), dev(wb), ell, grid=grid)
 
 
+def split_rule(x_axis, weights, ell):
+    """The documented rule by which the grid morph kernels choose their split scheme
+    (every block decides the same from the same data), stated independently of the
+    library: two-part FP16 splits, three products, when every nonzero |w| is at least
+    2^-19 of the largest, all weights and axis coordinates are finite and no two
+    consecutive distinct hinge x-coordinates are more than 6 apart in kappa units;
+    three-part BF16 splits, six products, otherwise."""
+    w = np.abs(np.asarray(weights, dtype=np.float32))
+    kappa = np.float32(np.sqrt(np.log2(np.e) / 2.0) / ell)
+    g = np.unique(kappa * np.asarray(x_axis, dtype=np.float32))
+    ok = bool(np.all(np.isfinite(w)) and np.all(np.isfinite(g)))
+    if ok and len(g) > 1:
+        ok = float(np.diff(g).max()) <= 6.0
+    if ok and w.max() > 0:
+        ok = float(w[w > 0].min()) >= float(w.max()) * 2.0 ** -19
+    return ("fp16", 3) if ok else ("bf16", 6)
+
+
 def one_step_grad_check(go, oo, x, tol=1e-5):
     """One morph step x1 = x0 - eta grad c with eta G_abs between 1 and 10 (G_abs the
     oracle's gradient error scale) resolves the gradient's error to the tolerance of

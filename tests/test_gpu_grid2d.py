@@ -4,12 +4,11 @@ tolerances as the pairwise path."""
 import numpy as np
 import pytest
 
-import bench
 import oracle as O
 import paper_2108_11775_amd as P
 from paper_2108_11775_amd import configs as K, inputs as I
 
-from helpers import dev, host, one_step_grad_check, oracle_occ, require_gpu, ws_scene
+from helpers import dev, host, one_step_grad_check, oracle_occ, require_gpu, split_rule, ws_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -197,10 +196,10 @@ def test_grid_large_batch_ragged_grid_sampled(scheme):
     wb = rng.normal(0, 1.5, g0 * g1 + 1).astype(np.float32)
     if scheme == "bf16":
         wb[100] = np.float32(np.abs(wb[:-1]).max() * 2.0 ** -30)
-    assert bench.split_scheme(ax, wb[:-1], 0.5)[0] == scheme
     n = (1 << 17) + 333
     x = rng.uniform(-3.5, 3.5, (2, n)).astype(np.float32)
     go = _grid_occ(h, wb, 0.5, g0, g1)
+    assert split_rule(ax, wb[:-1], 0.5)[0] == scheme == P.split_scheme(go)[0]
     _, s = P.occupancy_eval(go, dev(x))
     out = host(P.morph_samples(go, dev(x), 5, 0.02))
     idx = np.unique(np.r_[0, np.arange(1, n, 293), n - 1])

@@ -7,12 +7,12 @@ import math
 import numpy as np
 import pytest
 
-import bench
 import oracle as O
 import paper_2108_11775_amd as P
 from paper_2108_11775_amd import configs as K, inputs as I
 
-from helpers import arm_scene, dev, gpu_occ, host, one_step_grad_check, oracle_occ, require_gpu
+from helpers import (arm_scene, dev, gpu_occ, host, one_step_grad_check, oracle_occ, require_gpu,
+                     split_rule)
 
 pytestmark = pytest.mark.gpu
 
@@ -152,12 +152,12 @@ def test_grid3d_arm_T_steps(n, scheme):
     wb = sc["wb"].copy()
     if scheme == "bf16":
         wb[17] = np.float32(np.abs(wb[:-1]).max() * 2.0 ** -30)
-    assert bench.split_scheme(sc["h"][0, :16], wb[:-1], sc["ell"])[0] == scheme
+    go = gpu_occ(sc["h"], wb, sc["ell"], G)
+    assert split_rule(sc["h"][0, :16], wb[:-1], sc["ell"])[0] == scheme == P.split_scheme(go)[0]
     ao, ag = _arms(sc)
     c3 = K.C3
     q0 = O.uniform_samples(I.philox_seed(c3.cfg_id), 7, [c3.q_lo] * 7, [c3.q_hi] * 7, n)
-    out = host(P.morph_samples(gpu_occ(sc["h"], wb, sc["ell"], G), dev(q0), c3.T, c3.eta,
-                               arm=ag))
+    out = host(P.morph_samples(go, dev(q0), c3.T, c3.eta, arm=ag))
     idx = np.arange(n) if n <= 40 else np.unique(np.r_[np.arange(0, n, n // 24), n - 1])
     ref, amp, _ = O.morph_arm(ao, oracle_occ(sc["h"], wb, sc["ell"]), q0[:, idx], c3.T,
                               c3.eta, diag=True)

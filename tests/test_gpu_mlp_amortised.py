@@ -204,3 +204,47 @@ def test_training_reduces_loss_and_fallbacks():
     _, f_zero, _ = P.amortised_morph(zero, occ, arm_g, q, c3.T, c3.eta)
     _, f_net, _ = P.amortised_morph(mlp, occ, arm_g, q, c3.T, c3.eta)
     assert host(f_net).mean() < host(f_zero).mean()
+
+
+def test_amortised_config5_grid_path_sampled():
+    """The amortised morph on the bench's own path: the 16^3 hinge grid (the check of
+    q_hat on the grid arm kernel, the fallback morph on the grid arm kernel with the
+    FP16 split scheme this world's weights take) and a non-zero 7-256-256-256-7
+    network, 65,536 configurations in one call, every 1,600th compared with the
+    oracle's amortised morph; the fallbacks are also the plain grid morph's bits."""
+    require_gpu()
+    sc = arm_scene()
+    a, d, al, th = sc["dh"]
+    arm_o, arm_g = O.Arm(a, d, al, th, 8), P.Arm(a, d, al, th, 8)
+    widths = (7, 256, 256, 256, 7)
+    layers = _net(widths, seed=9)
+    layers[-1] = (layers[-1][0] * 0.05, layers[-1][1] * 0.05)
+    mlp = P.Mlp.from_layers(layers)
+    c3 = K.C3
+    n = c3.n_samples
+    q = O.uniform_samples(I.philox_seed(c3.cfg_id), 11, [c3.q_lo] * 7, [c3.q_hi] * 7, n)
+    go = gpu_occ(sc["h"], sc["wb"], sc["ell"], (16, 16, 16))
+    assert P.split_scheme(go) == ("fp16", 3)
+    q_d = dev(q)
+    out, flag, nf = P.amortised_morph(mlp, go, arm_g, q_d, c3.T, c3.eta)
+    plain = host(P.morph_samples(go, q_d, c3.T, c3.eta, arm=arm_g))
+    out, flag = host(out), host(flag)
+    P.sync()
+    assert int(host(nf)[0]) == int(flag.sum()) and 0 < flag.sum() < n
+    fb = flag.astype(bool)
+    assert np.array_equal(out[:, fb], plain[:, fb])
+    idx = np.unique(np.r_[0, np.arange(1, n, 1600), n - 1])
+    out, flag, qs = out[:, idx], flag[idx], np.ascontiguousarray(q[:, idx])
+    oo = oracle_occ(sc["h"], sc["wb"], sc["ell"])
+    lb = [(_bf16(W), b) for W, b in layers]
+    ref, fref, maxc = O.amortised_morph(widths, O.mlp_pack(lb), arm_o, oo, qs, c3.T, c3.eta)
+    sure = np.abs(maxc - 0.5) > 2e-2
+    assert sure.sum() >= 0.8 * idx.size
+    assert np.array_equal(flag[sure], fref[sure])
+    both = sure & (flag == 1)
+    assert both.any() and (sure & (flag == 0)).any()
+    _, amp, _ = O.morph_arm(arm_o, oo, qs[:, both], c3.T, c3.eta, diag=True)
+    err = np.abs(out[:, both] - ref[:, both]).max(axis=0)
+    assert np.all(err <= 1e-5 * np.maximum(1, amp) * np.maximum(1, np.abs(ref[:, both]).max(axis=0)))
+    keep = sure & (flag == 0)
+    assert np.all(np.abs(out[:, keep] - ref[:, keep]) <= 2e-2 * (np.abs(ref[:, keep] - qs[:, keep]) + 0.05))

@@ -106,4 +106,10 @@ def test_producer_failure_reaches_the_consumer():
     assert not fb.any() and list(idx) == [-1, -2, -3, -4, -5]
     ref = O.uniform_samples(I.philox_seed(2), 7, [cfg.lo] * 2, [cfg.hi] * 2, 5)
     assert np.array_equal(x, ref.T)
+    # a second start after the failure is refused with the failure's message (the
+    # stopped producer thread is joined, not replaced)
+    with pytest.raises(P.PdmpError) as e:
+        s.start()
+    assert e.value.status == 1 and "hipMalloc" in str(e.value)
+    assert s.stats()["status"] == 3
     assert s.close() == 3
