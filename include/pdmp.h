@@ -286,6 +286,18 @@ int32_t pdmp_occupancy_bwd(const pdmp_occupancy *occ, const float *x, int64_t n,
                            const float *s_fwd, float *grad_w, float *grad_x, void *ws,
                            size_t ws_bytes, void *stream);
 
+/* The same backward for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops): identical arguments, results and kernels, but
+ * the scratch comes from a static array of 32 MiB that the library keeps on each GPU it
+ * runs on until the process ends, instead of a caller workspace.  A call whose
+ * pdmp_bwd_workspace_size exceeds 32 MiB (about 4M points at 4096 hinges) returns
+ * PDMP_ENOMEM before any launch.  Calls no hipMalloc, hipFree or allocating routine.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other host threads) race and must be ordered by the caller. */
+int32_t pdmp_occupancy_bwd_noalloc(const pdmp_occupancy *occ, const float *x, int64_t n,
+                                   const float *g, const float *s_fwd, float *grad_w,
+                                   float *grad_x, void *stream);
+
 /* Mean binary cross-entropy of sigma(s) against labels y (nonzero = 1), in the
  * overflow-free form max(s,0) - y s + log(1 + exp(-|s|)).  loss (nullable): device
  * [1]; g_s (nullable): device [n], dL/ds_i = (sigma(s_i) - y_i)/n, times g_scale[0]

@@ -23,7 +23,7 @@ __all__ = ["Occupancy", "Arm", "PdmpError", "abi_version", "uniform_samples",
            "label_points_discs", "label_points_boxes", "label_configs", "occupancy_eval",
            "occupancy_grad", "morph_samples", "morph_trajectory", "split_scheme", "issue_rates",
            "fk_body_points", "sync",
-           "occupancy_bwd", "bce_logits", "adam_step", "fit_occupancy", "Mlp", "arm_max_occupancy",
+           "occupancy_bwd", "occupancy_bwd_noalloc", "bce_logits", "adam_step", "fit_occupancy", "Mlp", "arm_max_occupancy",
            "amortised_morph", "TanhNet", "tanh_occupancy_eval", "tanh_occupancy_grad",
            "tanh_morph_samples", "tanh_loss_grad", "tanh_fit", "morph_logdet", "morph_inverse",
            "mixture_samples", "Bucket", "Sampler", "rrt_run", "cull_grid", "morph_culled"]
@@ -362,6 +362,24 @@ def occupancy_bwd(occ: Occupancy, x, g, s_fwd=None, want_w: bool = True, want_x:
               _dev(gw, "grad_w") if want_w else None, _dev(gx, "grad_x") if want_x else None,
               _dev(ws, "ws"), ws.numel(), _stream(x.device))
     return gw, gx
+
+
+def occupancy_bwd_noalloc(occ: Occupancy, x, g, s_fwd=None, grad_w=None, grad_x=None):
+    """The backward of occupancy_bwd through the allocation-free entry point: the
+    library's static per-GPU scratch instead of a workspace.  The caller passes the
+    outputs it wants (grad_w [M+1], grad_x [dim][n], device FP32, written in place) so
+    that the call itself allocates nothing; returns them."""
+    torch = _torch()
+    n = int(x.shape[1])
+    o = occ.c_struct()
+    _lib.call("pdmp_occupancy_bwd_noalloc", C.byref(o),
+              _dev(x, "x", torch.float32, (occ.dim, n)), n, _dev(g, "g", torch.float32, (n,)),
+              _dev(s_fwd, "s_fwd", torch.float32, (n,)) if s_fwd is not None else None,
+              _dev(grad_w, "grad_w", torch.float32, (occ.n_hinges + 1,))
+              if grad_w is not None else None,
+              _dev(grad_x, "grad_x", torch.float32, (occ.dim, n)) if grad_x is not None else None,
+              _stream(x.device))
+    return grad_w, grad_x
 
 
 def bce_logits(s, y, g_scale=None, want_loss: bool = True, want_grad: bool = True):

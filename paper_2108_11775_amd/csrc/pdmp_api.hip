@@ -462,18 +462,48 @@ int32_t pdmp_fit_occupancy(const pdmp_occupancy *occ, float *weights, const floa
                       (hipStream_t)stream);
 }
 
-int32_t pdmp_occupancy_bwd(const pdmp_occupancy *occ, const float *x, int64_t n, const float *g,
-                           const float *s_fwd, float *grad_w, float *grad_x, void *ws,
-                           size_t ws_bytes, void *stream) {
+// The backward's argument checks; *done = true when there is nothing to launch.
+static int32_t check_bwd(const pdmp_occupancy *occ, const float *x, int64_t n, const float *g,
+                         const float *grad_w, const float *grad_x, bool *done) {
     int32_t st = check_occ(occ);
     if (st) return st;
     PDMP_REQUIRE(n >= 0, "n < 0");
+    *done = true;
     if (n == 0) {
         PDMP_REQUIRE(grad_w == nullptr, "grad_w of an empty batch: use n >= 1");
         return PDMP_OK;
     }
     PDMP_REQUIRE(x && g, "x/g NULL");
-    if (!grad_w && !grad_x) return PDMP_OK;
+    *done = !grad_w && !grad_x;
+    return PDMP_OK;
+}
+
+int32_t pdmp_occupancy_bwd_noalloc(const pdmp_occupancy *occ, const float *x, int64_t n,
+                                   const float *g, const float *s_fwd, float *grad_w,
+                                   float *grad_x, void *stream) {
+    bool done = false;
+    int32_t st = check_bwd(occ, x, n, g, grad_w, grad_x, &done);
+    if (st || done) return st;
+    const size_t need = bwd_ws_bytes(occ->dim, occ->n_hinges, n);
+    if (need > noalloc_scratch_bytes()) {
+        set_error("this backward needs %zu bytes of scratch; the static scratch holds %zu "
+                  "(use pdmp_occupancy_bwd with a workspace)", need, noalloc_scratch_bytes());
+        return PDMP_ENOMEM;
+    }
+    void *ws = nullptr;
+    if ((st = noalloc_scratch(&ws))) return st;
+    if ((st = grid_check(occ, stream))) return st;
+    return launch_logit_bwd(occ->dim, occ->hinges, occ->weights, occ->n_hinges,
+                            has_grid(occ) ? occ->grid : nullptr, occ->lengthscale, x, n, g, s_fwd,
+                            grad_w, grad_x, 1.0f, nullptr, 0.0f, ws, (hipStream_t)stream);
+}
+
+int32_t pdmp_occupancy_bwd(const pdmp_occupancy *occ, const float *x, int64_t n, const float *g,
+                           const float *s_fwd, float *grad_w, float *grad_x, void *ws,
+                           size_t ws_bytes, void *stream) {
+    bool done = false;
+    int32_t st = check_bwd(occ, x, n, g, grad_w, grad_x, &done);
+    if (st || done) return st;
     const size_t need = bwd_ws_bytes(occ->dim, occ->n_hinges, n);
     if (!ws || ws_bytes < need) {
         set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);

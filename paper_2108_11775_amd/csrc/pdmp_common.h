@@ -131,6 +131,10 @@ int32_t launch_arm_grid3d(const pdmp_arm &arm, const float *h, const float *w, i
                           int64_t n, int T, float eta, const uint32_t *n_active, bool morph,
                           float thresh, float *maxc, uint8_t *flag, hipStream_t st,
                           const Traj &traj = Traj());
+// The allocation-free entry point's static scratch: its size, and the current
+// device's copy (device address, taken once per device).
+size_t noalloc_scratch_bytes();
+int32_t noalloc_scratch(void **ptr);
 // Enqueue the device check that the hinges are the tensor grid `grid` states (a
 // mismatch is reported by the next pdmp_sync on the device), and take that report.
 int32_t launch_grid_check(int dim, const float *hinges, int M, const int *grid, hipStream_t st);
