@@ -158,6 +158,20 @@ int32_t pdmp_occupancy_grad(const pdmp_occupancy *occ, const float *x, int64_t n
 int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,
                            float *out, int64_t n, int32_t T, float eta, void *stream);
 
+/* The same morph with a caller workspace (pdmp_morph_workspace_size bytes; 0 means the
+ * call needs none and ws is ignored).  A large batch (n >= 2^17, T >= 1) on a 2-D hinge
+ * grid of at most 64 x 64 is first ordered by a counting sort into 32 x 32 cells over
+ * the hinge range, so that the samples of a wave lie close together; each step then
+ * skips, wave by wave, the parts of the factorised sums that are exact zeros for all
+ * of the wave's samples (hinge blocks whose FP16 operands underflow to zero, row tiles
+ * whose y features underflow in FP32).  Every sample gets the same bits as from
+ * pdmp_morph_samples.  PDMP_ENOMEM if ws is short; in == out allowed. */
+size_t pdmp_morph_workspace_size(const pdmp_occupancy *occ, const pdmp_arm *arm, int64_t n,
+                                 int32_t T);
+int32_t pdmp_morph_samples_ws(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,
+                              float *out, int64_t n, int32_t T, float eta, void *ws,
+                              size_t ws_bytes, void *stream);
+
 /* The same morph (Sec. 3.2, Eq. 1 and Eq. 3) with the explicit-Euler path of every
  * traj_stride-th sample written out, so that each step can be checked on its own:
  * traj (device, [(T+1)][rows][nt], rows = occ->dim or arm->n_dof,

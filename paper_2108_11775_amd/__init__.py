@@ -21,7 +21,8 @@ from ._lib import PdmpError
 
 __all__ = ["Occupancy", "Arm", "PdmpError", "abi_version", "uniform_samples",
            "label_points_discs", "label_points_boxes", "label_configs", "occupancy_eval",
-           "occupancy_grad", "morph_samples", "morph_trajectory", "split_scheme", "issue_rates",
+           "occupancy_grad", "morph_samples", "morph_samples_ws", "morph_workspace",
+           "morph_trajectory", "split_scheme", "issue_rates",
            "fk_body_points", "sync",
            "occupancy_bwd", "occupancy_bwd_noalloc", "bce_logits", "adam_step", "fit_occupancy", "Mlp", "arm_max_occupancy",
            "amortised_morph", "TanhNet", "tanh_occupancy_eval", "tanh_occupancy_grad",
@@ -254,6 +255,37 @@ def issue_rates() -> dict:
     out = (C.c_double * len(ISSUE_RATE_KEYS))()
     _lib.call("pdmp_issue_rates", out, len(ISSUE_RATE_KEYS))
     return dict(zip(ISSUE_RATE_KEYS, [float(v) for v in out]))
+
+
+def morph_workspace(occ: Occupancy, n: int, T: int, arm: Optional[Arm] = None):
+    """A device workspace for morph_samples_ws of n samples over T steps (None if the
+    call needs none)."""
+    lib = _lib.load()
+    a = C.byref(arm.c_struct()) if arm is not None else None
+    nb = int(lib.pdmp_morph_workspace_size(C.byref(occ.c_struct()), a, int(n), int(T)))
+    return _workspace(nb, occ.hinges.device) if nb else None
+
+
+def morph_samples_ws(occ: Occupancy, x, T: int, eta: float, arm: Optional[Arm] = None,
+                     out=None, ws=None):
+    """morph_samples with a workspace: a large 2-D grid batch is ordered spatially and
+    each wave skips the exact zeros of the sums (the same bits).  ws from
+    morph_workspace (allocated here if None)."""
+    torch = _torch()
+    n = int(x.shape[1])
+    rows = arm.n_dof if arm is not None else occ.dim
+    _dev(x, "x", torch.float32, (rows, n))
+    if out is None:
+        out = torch.empty_like(x)
+    if ws is None:
+        ws = morph_workspace(occ, n, T, arm)
+    o = occ.c_struct()
+    a = C.byref(arm.c_struct()) if arm is not None else None
+    _lib.call("pdmp_morph_samples_ws", C.byref(o), a, C.c_void_p(x.data_ptr()),
+              _dev(out, "out", torch.float32, (rows, n)), n, int(T), float(eta),
+              _dev(ws, "ws") if ws is not None else None, ws.numel() if ws is not None else 0,
+              _stream(x.device))
+    return out
 
 
 def morph_trajectory(occ: Occupancy, x, T: int, eta: float, stride: int = 1,

@@ -21,6 +21,11 @@
 #include "mfma_split.h"
 #include "pdmp_common.h"
 
+// Every rounding in this file is the one its source states (multiply-adds are written
+// as fmaf): the spatially ordered kernel below must reproduce the unordered kernel's
+// bits, which holds only if the compiler fuses neither kernel's products on its own.
+#pragma clang fp contract(off)
+
 namespace pdmp {
 
 constexpr int kG2Block = 256;   // 4 waves, 32 samples each
@@ -219,6 +224,302 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
     }
     if (rec) traj_put<2>(tr, steps, tc, {x, y});
     g2_finish<MODE>(s, sx, sy, beta, gscale, x, y, half, i, n, c_out, s_out, g_out, x_out);
+}
+
+// ---- large batches in spatial order: the same sums, exact zeros skipped ----
+//
+// A workspace morph of a large batch first orders the samples by a 32 x 32 cell grid
+// over the hinge axes' range (a counting sort into a permutation), so that the 32
+// samples of a wave lie close together.  Every step, the wave then finds, from its
+// samples' distances to each k-step's hinge x-range and to each row tile's y-range:
+//  * k-steps whose B operands are zero for all its samples: on the FP16 scheme an
+//    operand 2^c ex_a (or 2^c ex_a dx_a) rounds to the FP16 zero below 2^-25, which
+//    every hinge of the k-step is when the sample's nearest one lies at dx^2 >= c + 34
+//    (kappa units; the 9 spare binades cover |dx| up to 2^6 and the exponential's
+//    rounding, and beyond |dx| = 2^6 the feature underflows in FP32);
+//  * row tiles whose ey_b = exp2(-dy^2) are zero for all its samples: dy^2 >= 152
+//    puts every row of the tile past FP32's smallest subnormal.
+// Their products and contractions add exact zeros to accumulators that start at +0
+// (an MFMA with an all-zero B column leaves that column of C unchanged; fma(0, U, s)
+// = s), so skipping them gives each sample the bits of the unordered kernel, in any
+// grouping.  The BF16 scheme (R26 in the design notes: operands of FP32 range) takes
+// the dense path, only through the permutation.
+constexpr int kSortCells = 32;  // per axis
+
+__device__ __forceinline__ uint32_t wave_any(bool p) { return __ballot(p) != 0 ? 1u : 0u; }
+
+// The y contraction of one 32-row tile (rows 32t + 8(v/4) + 4 half + v%4).
+__device__ __forceinline__ void g2_ysum_tile(const float *gys, float ys, int half, int t,
+                                             const f32x16_t &U, const f32x16_t &V, float &s,
+                                             float &sx, float &sy) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int b = 32 * t + 8 * (v >> 2) + 4 * half + (v & 3);
+        const float d = ys - gys[b];
+        const float e = exp2_fast(-d * d);
+        s = fmaf(e, U[v], s);
+        sx = fmaf(e, V[v], sx);
+        sy = fmaf(e * d, U[v], sy);
+    }
+}
+
+template <int TB, int KS>
+__global__ void __launch_bounds__(kG2Block) __attribute__((amdgpu_waves_per_eu(2)))
+k_grid2d_sorted(const float *__restrict__ hinges, const float *__restrict__ weights, int g0,
+                int g1, float kappa, float gscale, const float *x_in, int64_t n, int T, float eta,
+                const uint32_t *__restrict__ perm, float *x_out, Traj tr) {
+    __shared__ uint4 fraw[3 * KS * TB * 64];
+    __shared__ float gxs[16 * KS];
+    __shared__ float gys[32 * TB];
+    __shared__ SplitRange rg;
+    const int M = g0 * g1;
+    const int lane = threadIdx.x & 63, half = lane >> 5, wv = threadIdx.x >> 6;
+    const SplitScheme sc = g2_stage<TB, KS, true>(fraw, gxs, gys, rg, hinges, weights, g0, g1, kappa);
+    const int64_t slot = ((int64_t)blockIdx.x * (kG2Block / 64) + wv) * 32 + (lane & 31);
+    const bool live = slot < n;
+    const int64_t ic = perm[live ? slot : n - 1];
+    const int64_t i = live ? (int64_t)ic : n;  // n: a tail lane, writes nothing
+    float x = x_in[ic], y = x_in[(size_t)n + ic];
+    const float beta = weights[M];
+    float s = 0.0f, sx = 0.0f, sy = 0.0f;
+    int64_t tc;
+    const bool rec = half == 0 && traj_col(tr, i, n, tc);
+
+    if (sc.fp16) {
+        const f16x8_t *frag = reinterpret_cast<const f16x8_t *>(fraw);
+        // the x-range of each k-step's hinges and the y-range of each row tile's rows
+        // (kappa units; padding excluded)
+        float klo[KS], khi[KS], tlo[TB], thi[TB];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            klo[ks] = INFINITY;
+            khi[ks] = -INFINITY;
+            for (int a = 16 * ks; a < 16 * ks + 16 && a < g0; ++a) {
+                klo[ks] = fminf(klo[ks], gxs[a]);
+                khi[ks] = fmaxf(khi[ks], gxs[a]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            tlo[t] = INFINITY;
+            thi[t] = -INFINITY;
+            for (int b = 32 * t; b < 32 * t + 32 && b < g1; ++b) {
+                tlo[t] = fminf(tlo[t], gys[b]);
+                thi[t] = fmaxf(thi[t], gys[b]);
+            }
+        }
+        for (int st = 0; st < T; ++st) {
+            if (rec) traj_put<2>(tr, st, tc, {x, y});
+            const float xs = kappa * x, ys = kappa * y;
+            const int c = split_scale_exp(xs, sc.gmin, sc.gmax);
+            const float lim = (float)(c + 34);
+            uint32_t km = 0, tm = 0;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const float d = fmaxf(fmaxf(klo[ks] - xs, xs - khi[ks]), 0.0f);
+                km |= wave_any(d * d < lim) << ks;
+            }
+#pragma unroll
+            for (int t = 0; t < TB; ++t) {
+                const float d = fmaxf(fmaxf(tlo[t] - ys, ys - thi[t]), 0.0f);
+                tm |= wave_any(d * d < 152.0f) << t;
+            }
+            km = __builtin_amdgcn_readfirstlane(km);
+            tm = __builtin_amdgcn_readfirstlane(tm);
+            f32x16_t U[TB], V[TB];
+            int ln = lane;  // opaque: keeps the fragment reads inside the step loop
+            asm volatile("" : "+v"(ln));
+            f16x8_t e[2], de[2];
+            if (km) h3_operands(gxs, xs, (float)c, __builtin_ctz(km), half, e, de);
+            bool first = true;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                if (!((km >> ks) & 1u)) continue;
+                f16x8_t ec[2] = {e[0], e[1]}, dc[2] = {de[0], de[1]};
+                const uint32_t rest = km & ~((2u << ks) - 1u);
+                if (rest) h3_operands(gxs, xs, (float)c, __builtin_ctz(rest), half, e, de);
+#pragma unroll
+                for (int t = 0; t < TB; ++t) {
+                    if (!((tm >> t) & 1u)) continue;
+                    const f16x8_t a1 = frag[(0 * KS + ks) * TB * 64 + t * 64 + ln];
+                    const f16x8_t a2 = frag[(1 * KS + ks) * TB * 64 + t * 64 + ln];
+                    if (first) {
+                        const f32x16_t zero = {};
+                        U[t] = mfma_h3(a1, a2, ec[0], ec[1], zero);
+                        V[t] = mfma_h3(a1, a2, dc[0], dc[1], zero);
+                    } else {
+                        U[t] = mfma_h3(a1, a2, ec[0], ec[1], U[t]);
+                        V[t] = mfma_h3(a1, a2, dc[0], dc[1], V[t]);
+                    }
+                }
+                first = false;
+            }
+            s = 0.0f;
+            sx = 0.0f;
+            sy = 0.0f;
+            if (km) {
+#pragma unroll
+                for (int t = 0; t < TB; ++t)
+                    if ((tm >> t) & 1u) g2_ysum_tile(gys, ys, half, t, U[t], V[t], s, sx, sy);
+            }
+            s += __shfl_xor(s, 32, 64);
+            sx += __shfl_xor(sx, 32, 64);
+            sy += __shfl_xor(sy, 32, 64);
+            const int un = -(sc.sw + c);
+            s = ldexpf(s, un);
+            sx = ldexpf(sx, un);
+            sy = ldexpf(sy, un);
+            float cc, sp;
+            sigmoid_and_slope(s + beta, cc, sp);
+            const float step = eta * sp * gscale;
+            x = fmaf(step, sx, x);
+            y = fmaf(step, sy, y);
+        }
+    } else {
+        const bf16x8_t *frag = reinterpret_cast<const bf16x8_t *>(fraw);
+        for (int st = 0; st < T; ++st) {
+            if (rec) traj_put<2>(tr, st, tc, {x, y});
+            const float xs = kappa * x, ys = kappa * y;
+            f32x16_t U[TB], V[TB];
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            bf16x8_t e[3], de[3];
+            x6_operands(gxs, xs, 0, half, e, de);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                bf16x8_t ec[3] = {e[0], e[1], e[2]}, dc[3] = {de[0], de[1], de[2]};
+                if (ks + 1 < KS) x6_operands(gxs, xs, ks + 1, half, e, de);
+#pragma unroll
+                for (int t = 0; t < TB; ++t) {
+                    const bf16x8_t a1 = frag[(0 * KS + ks) * TB * 64 + t * 64 + ln];
+                    const bf16x8_t a2 = frag[(1 * KS + ks) * TB * 64 + t * 64 + ln];
+                    const bf16x8_t a3 = frag[(2 * KS + ks) * TB * 64 + t * 64 + ln];
+                    const f32x16_t zero = {};
+                    U[t] = mfma_x6(a1, a2, a3, ec[0], ec[1], ec[2], ks == 0 ? zero : U[t]);
+                    V[t] = mfma_x6(a1, a2, a3, dc[0], dc[1], dc[2], ks == 0 ? zero : V[t]);
+                }
+            }
+            g2_ysum<TB>(gys, ys, half, U, V, s, sx, sy);
+            float cc, sp;
+            sigmoid_and_slope(s + beta, cc, sp);
+            const float step = eta * sp * gscale;
+            x = fmaf(step, sx, x);
+            y = fmaf(step, sy, y);
+        }
+    }
+    if (rec) traj_put<2>(tr, T, tc, {x, y});
+    g2_finish<kMorph>(s, sx, sy, beta, gscale, x, y, half, i, n, nullptr, nullptr, nullptr, x_out);
+}
+
+// ---- the spatial order: a counting sort of the samples into 32 x 32 cells ----
+
+// The cell grid over the hinge axes' range (unscaled coordinates): origin and cells
+// per unit on each axis, from the axis entries of the hinge array.
+__device__ __forceinline__ void sort_frame(const float *__restrict__ hinges, int g0, int g1,
+                                           float (&f)[4], float *red) {
+    const int M = g0 * g1;
+    float xlo = INFINITY, xhi = -INFINITY, ylo = INFINITY, yhi = -INFINITY;
+    for (int a = threadIdx.x; a < g0; a += blockDim.x) {
+        xlo = fminf(xlo, hinges[a]);
+        xhi = fmaxf(xhi, hinges[a]);
+    }
+    for (int b = threadIdx.x; b < g1; b += blockDim.x) {
+        const float v = hinges[(size_t)M + (size_t)g0 * b];
+        ylo = fminf(ylo, v);
+        yhi = fmaxf(yhi, v);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        xlo = fminf(xlo, __shfl_xor(xlo, off, 64));
+        xhi = fmaxf(xhi, __shfl_xor(xhi, off, 64));
+        ylo = fminf(ylo, __shfl_xor(ylo, off, 64));
+        yhi = fmaxf(yhi, __shfl_xor(yhi, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        const int w = threadIdx.x >> 6;
+        red[4 * w] = xlo;
+        red[4 * w + 1] = xhi;
+        red[4 * w + 2] = ylo;
+        red[4 * w + 3] = yhi;
+    }
+    __syncthreads();
+    xlo = red[0], xhi = red[1], ylo = red[2], yhi = red[3];
+    for (int w = 1; w < (int)blockDim.x / 64; ++w) {
+        xlo = fminf(xlo, red[4 * w]);
+        xhi = fmaxf(xhi, red[4 * w + 1]);
+        ylo = fminf(ylo, red[4 * w + 2]);
+        yhi = fmaxf(yhi, red[4 * w + 3]);
+    }
+    f[0] = xlo;
+    f[1] = xhi > xlo ? (float)kSortCells / (xhi - xlo) : 0.0f;
+    f[2] = ylo;
+    f[3] = yhi > ylo ? (float)kSortCells / (yhi - ylo) : 0.0f;
+}
+
+// A point's cell (clamped; a NaN coordinate takes cell 0 of its axis).
+__device__ __forceinline__ int sort_cell(float x, float y, const float (&f)[4]) {
+    const float cx = fminf(fmaxf((x - f[0]) * f[1], 0.0f), (float)(kSortCells - 1));
+    const float cy = fminf(fmaxf((y - f[2]) * f[3], 0.0f), (float)(kSortCells - 1));
+    return (int)cy * kSortCells + (int)cx;
+}
+
+constexpr int kSortBlock = 256, kSortChunk = 4096;
+
+__global__ void __launch_bounds__(kSortBlock) k_sort_zero(uint32_t *counts) {
+    for (int b = threadIdx.x; b < kSortCells * kSortCells; b += kSortBlock) counts[b] = 0;
+}
+
+__global__ void __launch_bounds__(kSortBlock)
+k_sort_count(const float *__restrict__ hinges, int g0, int g1, const float *__restrict__ x, int64_t n,
+             uint32_t *counts) {
+    __shared__ uint32_t hist[kSortCells * kSortCells];
+    __shared__ float red[4 * kSortBlock / 64];
+    float f[4];
+    sort_frame(hinges, g0, g1, f, red);
+    for (int b = threadIdx.x; b < kSortCells * kSortCells; b += kSortBlock) hist[b] = 0;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * kSortChunk;
+    for (int64_t i = i0 + threadIdx.x; i < i0 + kSortChunk && i < n; i += kSortBlock)
+        atomicAdd(&hist[sort_cell(x[i], x[(size_t)n + i], f)], 1u);
+    __syncthreads();
+    for (int b = threadIdx.x; b < kSortCells * kSortCells; b += kSortBlock)
+        if (hist[b]) atomicAdd(&counts[b], hist[b]);
+}
+
+// Exclusive prefix sum of the cell counts, in place (one block of 1024 threads).
+__global__ void __launch_bounds__(1024) k_sort_scan(uint32_t *counts) {
+    __shared__ uint32_t sh[kSortCells * kSortCells];
+    const int t = threadIdx.x;
+    sh[t] = counts[t];
+    __syncthreads();
+    for (int off = 1; off < kSortCells * kSortCells; off <<= 1) {
+        const uint32_t v = t >= off ? sh[t - off] : 0u;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
+    }
+    counts[t] = t > 0 ? sh[t - 1] : 0u;
+}
+
+__global__ void __launch_bounds__(kSortBlock)
+k_sort_scatter(const float *__restrict__ hinges, int g0, int g1, const float *__restrict__ x,
+               int64_t n, uint32_t *cursor, uint32_t *perm) {
+    __shared__ uint32_t hist[kSortCells * kSortCells];
+    __shared__ float red[4 * kSortBlock / 64];
+    float f[4];
+    sort_frame(hinges, g0, g1, f, red);
+    for (int b = threadIdx.x; b < kSortCells * kSortCells; b += kSortBlock) hist[b] = 0;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * kSortChunk;
+    for (int64_t i = i0 + threadIdx.x; i < i0 + kSortChunk && i < n; i += kSortBlock)
+        atomicAdd(&hist[sort_cell(x[i], x[(size_t)n + i], f)], 1u);
+    __syncthreads();
+    // this block's range in each cell, then the samples' places within it
+    for (int b = threadIdx.x; b < kSortCells * kSortCells; b += kSortBlock)
+        hist[b] = hist[b] ? atomicAdd(&cursor[b], hist[b]) : 0u;
+    __syncthreads();
+    for (int64_t i = i0 + threadIdx.x; i < i0 + kSortChunk && i < n; i += kSortBlock)
+        perm[atomicAdd(&hist[sort_cell(x[i], x[(size_t)n + i], f)], 1u)] = (uint32_t)i;
 }
 
 // ---- small batches: 16 samples per wave on the 16x16x32 MFMAs (f16 or bf16) ----
@@ -520,6 +821,45 @@ int32_t launch_grid2d(int mode, const RbfArgs &a, int g0, int g1, hipStream_t st
 #undef PDMP_G2_KS
 #undef PDMP_G2
     return check_launch("k_grid2d");
+}
+
+// Workspace bytes of the ordered morph (0: the batch takes another path).
+size_t grid2d_sorted_ws_bytes(int g0, int g1, int64_t n, int T) {
+    if (g0 < 1 || g1 < 1 || g0 > 64 || g1 > 64 || n < kG2SmallBatch || T < 1 || n > 0xffffffffll)
+        return 0;
+    return (((size_t)kSortCells * kSortCells * sizeof(uint32_t) + 255) & ~(size_t)255) +
+           (size_t)n * sizeof(uint32_t);
+}
+
+// The morph of a large batch in spatial order (PDMP_EUNSUPPORTED: not this path).
+int32_t launch_grid2d_sorted(const RbfArgs &a, int g0, int g1, void *ws, hipStream_t st) {
+    if (!grid2d_sorted_ws_bytes(g0, g1, a.n, a.T) || (int64_t)g0 * g1 != a.M)
+        return PDMP_EUNSUPPORTED;
+    uint32_t *cursor = (uint32_t *)ws;
+    uint32_t *perm = (uint32_t *)((char *)ws + (((size_t)kSortCells * kSortCells *
+                                                 sizeof(uint32_t) + 255) & ~(size_t)255));
+    const unsigned nb = (unsigned)((a.n + kSortChunk - 1) / kSortChunk);
+    hipLaunchKernelGGL(k_sort_zero, dim3(1), dim3(kSortBlock), 0, st, cursor);
+    hipLaunchKernelGGL(k_sort_count, dim3(nb), dim3(kSortBlock), 0, st, a.hinges, g0, g1, a.x_in,
+                       a.n, cursor);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kSortCells * kSortCells), 0, st, cursor);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kSortBlock), 0, st, a.hinges, g0, g1, a.x_in,
+                       a.n, cursor, perm);
+    if (int32_t e = check_launch("k_sort")) return e;
+    const dim3 grid((unsigned)((a.n + 127) / 128)), blk(kG2Block);
+#define PDMP_G2O(TB, KS)                                                                         \
+    hipLaunchKernelGGL((k_grid2d_sorted<TB, KS>), grid, blk, 0, st, a.hinges, a.weights, g0, g1, \
+                       a.kappa, a.gscale, a.x_in, a.n, a.T, a.eta, perm, a.x_out, a.traj)
+    const int ks = (g0 + 15) / 16;
+    if (g1 <= 32) {
+        if (ks == 1) PDMP_G2O(1, 1); else if (ks == 2) PDMP_G2O(1, 2);
+        else if (ks == 3) PDMP_G2O(1, 3); else PDMP_G2O(1, 4);
+    } else {
+        if (ks == 1) PDMP_G2O(2, 1); else if (ks == 2) PDMP_G2O(2, 2);
+        else if (ks == 3) PDMP_G2O(2, 3); else PDMP_G2O(2, 4);
+    }
+#undef PDMP_G2O
+    return check_launch("k_grid2d_sorted");
 }
 
 }  // namespace pdmp

@@ -196,10 +196,11 @@ int32_t pdmp_occupancy_grad(const pdmp_occupancy *occ, const float *x, int64_t n
     return rbf_call(occ, kGrad, x, n, c_out, nullptr, grad_out, nullptr, 1, 0.0f, stream);
 }
 
-// The morph of pdmp_morph_samples, recording the paths of traj's samples (if any).
+// The morph of pdmp_morph_samples, recording the paths of traj's samples (if any);
+// with a workspace, a large 2-D grid batch takes the spatially ordered kernel.
 static int32_t morph_impl(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,
                           float *out, int64_t n, int32_t T, float eta, const Traj &traj,
-                          void *stream) {
+                          void *stream, void *ws = nullptr, size_t ws_bytes = 0) {
     int32_t st = check_occ(occ);
     if (st) return st;
     PDMP_REQUIRE(n >= 0, "n < 0");
@@ -236,7 +237,44 @@ static int32_t morph_impl(const pdmp_occupancy *occ, const pdmp_arm *arm, const 
         return launch_morph_arm(*arm, occ->hinges, occ->weights, occ->n_hinges, kappa, gscale, in,
                                 out, n, T, eta, nullptr, (hipStream_t)stream, traj);
     }
+    if (ws && occ->dim == 2 && has_grid(occ)) {
+        const size_t need = grid2d_sorted_ws_bytes(occ->grid[0], occ->grid[1], n, T);
+        if (need && ws_bytes >= need) {
+            if ((st = grid_check(occ, stream))) return st;
+            RbfArgs a;
+            a.traj = traj;
+            a.hinges = occ->hinges;
+            a.weights = occ->weights;
+            a.M = occ->n_hinges;
+            a.bias = occ->weights + occ->n_hinges;
+            derive_scales(occ->lengthscale, a.kappa, a.gscale);
+            a.x_in = in;
+            a.n = n;
+            a.T = T;
+            a.eta = eta;
+            a.x_out = out;
+            st = launch_grid2d_sorted(a, occ->grid[0], occ->grid[1], ws, (hipStream_t)stream);
+            if (st != PDMP_EUNSUPPORTED) return st;
+        }
+    }
     return rbf_call(occ, kMorph, in, n, nullptr, nullptr, nullptr, out, T, eta, stream, traj);
+}
+
+size_t pdmp_morph_workspace_size(const pdmp_occupancy *occ, const pdmp_arm *arm, int64_t n,
+                                 int32_t T) {
+    if (check_occ(occ) || arm || occ->dim != 2 || !has_grid(occ) || n < 1) return 0;
+    return grid2d_sorted_ws_bytes(occ->grid[0], occ->grid[1], n, T);
+}
+
+int32_t pdmp_morph_samples_ws(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,
+                              float *out, int64_t n, int32_t T, float eta, void *ws,
+                              size_t ws_bytes, void *stream) {
+    const size_t need = pdmp_morph_workspace_size(occ, arm, n, T);
+    if (need && (!ws || ws_bytes < need)) {
+        set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+        return PDMP_ENOMEM;
+    }
+    return morph_impl(occ, arm, in, out, n, T, eta, Traj(), stream, need ? ws : nullptr, ws_bytes);
 }
 
 int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,

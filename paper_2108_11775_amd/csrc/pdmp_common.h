@@ -125,6 +125,11 @@ struct RbfArgs {
 
 int32_t launch_rbf(int dim, int mode, const RbfArgs &a, hipStream_t st);
 int32_t launch_grid2d(int mode, const RbfArgs &a, int g0, int g1, hipStream_t st);
+// The morph of a large 2-D grid batch in spatial order (counting sort into `ws`, then
+// the kernel that skips exact zeros); PDMP_EUNSUPPORTED when the batch takes another
+// path, whose workspace size is then 0.
+size_t grid2d_sorted_ws_bytes(int g0, int g1, int64_t n, int T);
+int32_t launch_grid2d_sorted(const RbfArgs &a, int g0, int g1, void *ws, hipStream_t st);
 int32_t launch_grid3d_ws(int mode, const RbfArgs &a, const int *grid, hipStream_t st);
 int32_t launch_arm_grid3d(const pdmp_arm &arm, const float *h, const float *w, int M,
                           const int *grid, float kappa, float gscale, const float *qi, float *qo,

@@ -1,0 +1,109 @@
+"""The spatially ordered morph (pdmp_morph_samples_ws): a large 2-D grid batch is
+sorted into cells and each wave skips the parts of the factorised sums that are exact
+zeros for all its samples.  Every sample must get the same bits as from the plain
+morph (whose parity against the oracle, also along its own paths, the other tests
+hold), on the headline workload at full size, ragged batches, other grid shapes, both
+split schemes, points outside the hinge range and in place."""
+import numpy as np
+import pytest
+
+import paper_2108_11775_amd as P
+from paper_2108_11775_amd import _lib, configs as K, inputs as I
+
+from helpers import dev, gpu_occ, host, require_gpu, split_rule, ws_scene
+
+pytestmark = pytest.mark.gpu
+
+
+def _same(go, x0, T, eta):
+    plain = host(P.morph_samples(go, x0, T, eta))
+    ws = P.morph_workspace(go, int(x0.shape[1]), T)
+    assert ws is not None
+    got = host(P.morph_samples_ws(go, x0, T, eta, ws=ws))
+    assert np.array_equal(got, plain), int((got != plain).sum())
+    return plain
+
+
+def test_ordered_morph_config2_full_size_same_bits():
+    require_gpu()
+    cfg = K.C2
+    sc = ws_scene(cfg)
+    x0 = P.uniform_samples(I.philox_seed(cfg.cfg_id), 0, [cfg.lo] * 2, [cfg.hi] * 2,
+                           cfg.n_samples)
+    go = gpu_occ(sc["h"], sc["wb"], sc["ell"], (cfg.grid, cfg.grid))
+    assert P.split_scheme(go) == ("fp16", 3)
+    ref = _same(go, x0, cfg.T, cfg.eta)
+    # in place
+    x1 = x0.clone()
+    P.morph_samples_ws(go, x1, cfg.T, cfg.eta, out=x1)
+    assert np.array_equal(host(x1), ref)
+    P.sync()
+
+
+@pytest.mark.parametrize("g0,g1,scheme", [(64, 64, "fp16"), (45, 37, "fp16"), (17, 64, "fp16"),
+                                           (64, 20, "bf16"), (33, 45, "bf16")])
+def test_ordered_morph_shapes_and_schemes(g0, g1, scheme):
+    """Random sorted axes (not uniform), weights with random signs over several decades
+    (one at 2^-30 of the largest puts the operands on the BF16 scheme), a ragged batch
+    above 2^17 with points up to 4 lengthscales outside the grid."""
+    require_gpu()
+    rng = np.random.default_rng(g0 * 1000 + g1)
+    ell = 0.35
+    ax = np.sort(rng.uniform(-6, 6, g0)).astype(np.float32)
+    ay = np.sort(rng.uniform(-5, 5, g1)).astype(np.float32)
+    j = np.arange(g0 * g1)
+    h = np.stack([ax[j % g0], ay[j // g0]]).astype(np.float32)
+    wb = (rng.choice([-1.0, 1.0], g0 * g1 + 1) * 2.0 ** rng.uniform(-8, 1, g0 * g1 + 1))
+    wb = wb.astype(np.float32)
+    if scheme == "bf16":
+        wb[3] = np.float32(np.abs(wb[:-1]).max() * 2.0 ** -30)
+    go = gpu_occ(h, wb, ell, (g0, g1))
+    assert split_rule(ax, wb[:-1], ell)[0] == scheme == P.split_scheme(go)[0]
+    n = (1 << 17) + 333
+    x = np.stack([rng.uniform(-6 - 4 * ell, 6 + 4 * ell, n),
+                  rng.uniform(-5 - 4 * ell, 5 + 4 * ell, n)]).astype(np.float32)
+    _same(go, dev(x), 7, 0.05)
+
+
+def test_ordered_morph_clustered_and_far_points():
+    """Points bunched in one corner (every wave in one cell), points far outside the
+    grid (every feature zero: all work skipped) and a few NaN coordinates."""
+    require_gpu()
+    cfg = K.C2
+    sc = ws_scene(cfg)
+    go = gpu_occ(sc["h"], sc["wb"], sc["ell"], (cfg.grid, cfg.grid))
+    rng = np.random.default_rng(5)
+    n = 1 << 17
+    x = np.concatenate([rng.uniform(-10, -9, (2, n // 2)),
+                        rng.uniform(30, 40, (2, n // 4)),
+                        rng.uniform(-10, 10, (2, n - n // 2 - n // 4))], axis=1).astype(np.float32)
+    x[:, 7] = np.nan
+    x[1, 99] = np.nan
+    plain = host(P.morph_samples(go, dev(x), cfg.T, cfg.eta))
+    got = host(P.morph_samples_ws(go, dev(x), cfg.T, cfg.eta))
+    assert np.array_equal(got, plain, equal_nan=True)
+
+
+def test_workspace_rules():
+    require_gpu()
+    cfg = K.C2
+    sc = ws_scene(cfg)
+    go = gpu_occ(sc["h"], sc["wb"], sc["ell"], (cfg.grid, cfg.grid))
+    lib = _lib.load()
+    import ctypes as C
+    o = go.c_struct()
+    # small batches and single steps of no use to the ordering need no workspace
+    assert lib.pdmp_morph_workspace_size(C.byref(o), None, 4096, 50) == 0
+    assert lib.pdmp_morph_workspace_size(C.byref(o), None, 1 << 20, 0) == 0
+    need = lib.pdmp_morph_workspace_size(C.byref(o), None, 1 << 20, 50)
+    assert need >= 4 << 20
+    x = P.uniform_samples(I.philox_seed(2), 3, [cfg.lo] * 2, [cfg.hi] * 2, 1 << 20)
+    with pytest.raises(P.PdmpError) as e:
+        P.morph_samples_ws(go, x, 5, cfg.eta, ws=P._workspace(need - 1, x.device))
+    assert e.value.status == _lib.PDMP_ENOMEM
+    # without a grid the plain path runs (no workspace needed)
+    dense = gpu_occ(sc["h"], sc["wb"], sc["ell"])
+    x2 = P.uniform_samples(I.philox_seed(2), 4, [cfg.lo] * 2, [cfg.hi] * 2, 3000)
+    assert P.morph_workspace(dense, 3000, 5) is None
+    assert np.array_equal(host(P.morph_samples_ws(dense, x2, 5, cfg.eta)),
+                          host(P.morph_samples(dense, x2, 5, cfg.eta)))
