@@ -310,9 +310,11 @@ k_grid3d_ws(const float *__restrict__ hinges, const float *__restrict__ weights,
                                         eta, c_out, s_out, g_out, x_out, tr);
 }
 
-// FP32 DH chain (same convention as the pairwise arm kernel).
+// FP32 DH chain (same convention as the pairwise arm kernel); sa, ca: the sine and
+// cosine of the constant link twists, taken once per kernel.
 template <int NDOF>
-__device__ __forceinline__ void g3_chain(const pdmp_arm &arm, const float (&q)[NDOF],
+__device__ __forceinline__ void g3_chain(const pdmp_arm &arm, const float (&sa_)[NDOF],
+                                         const float (&ca_)[NDOF], const float (&q)[NDOF],
                                          float (&o)[NDOF + 1][3], float (&z)[NDOF][3]) {
     float R[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
     o[0][0] = o[0][1] = o[0][2] = 0.0f;
@@ -321,9 +323,9 @@ __device__ __forceinline__ void g3_chain(const pdmp_arm &arm, const float (&q)[N
         z[i][0] = R[0][2];
         z[i][1] = R[1][2];
         z[i][2] = R[2][2];
-        float st, ct, sa, ca;
+        float st, ct;
         sincosf(arm.theta0[i] + q[i], &st, &ct);
-        sincosf(arm.alpha[i], &sa, &ca);
+        const float sa = sa_[i], ca = ca_[i];
         const float a = arm.a[i], d = arm.d[i];
         const float lx = a * ct, ly = a * st;
 #pragma unroll
@@ -342,10 +344,18 @@ __device__ __forceinline__ void g3_chain(const pdmp_arm &arm, const float (&q)[N
     }
 }
 
+// Sum over the 8 lanes of a group (lanes 8g..8g+7), the same value in each: two
+// quad exchanges and the half-row mirror, all DPP moves (the order of the pairwise
+// sums is that of xor-1, xor-2, xor-4 exchanges).
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL,
+                                                              0xf, 0xf, true));
+}
 __device__ __forceinline__ float sum8(float v) {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 4, 64);
+    v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);  // row_half_mirror
     return v;
 }
 
@@ -369,9 +379,12 @@ __device__ __forceinline__ void arm_body(const pdmp_arm &arm, const uint4 *fraw,
     const int P = arm.pts_per_link;
     const bool own = k < P;
     const float frac = own ? (float)(k + 1) / (float)P : 0.0f;
-    float q[NDOF];
+    float q[NDOF], sa[NDOF], ca[NDOF];
 #pragma unroll
-    for (int j = 0; j < NDOF; ++j) q[j] = q_in[(size_t)j * n + cs];
+    for (int j = 0; j < NDOF; ++j) {
+        q[j] = q_in[(size_t)j * n + cs];
+        sincosf(arm.alpha[j], &sa[j], &ca[j]);
+    }
 
     const int steps = MORPH ? T : 1;
     float mc = -1.0f;
@@ -383,7 +396,7 @@ __device__ __forceinline__ void arm_body(const pdmp_arm &arm, const uint4 *fraw,
             // the chain of this configuration, parked in LDS so that the link loop
             // below does not hold ~45 registers across the MFMA work
             float o[NDOF + 1][3], zx[NDOF][3];
-            g3_chain<NDOF>(arm, q, o, zx);
+            g3_chain<NDOF>(arm, sa, ca, q, o, zx);
             if (writer) {
 #pragma unroll
                 for (int i = 0; i <= NDOF; ++i)
