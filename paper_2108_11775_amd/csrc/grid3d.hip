@@ -359,6 +359,15 @@ __device__ __forceinline__ float sum8(float v) {
     return v;
 }
 
+// The per-configuration records in LDS (chain, axes, joint gradient) are written and
+// read by the lanes of one wave only, and a wave's LDS operations complete in issue
+// order: ordering them needs a compiler barrier, not a block barrier.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---- joint-space morph (MORPH) or largest body-point occupancy (check) ----
 // 4 configurations per wave; lane%32 = 8*cfg + k, body point k of every link.
 template <int NDOF, int G0, int G2, bool MORPH, bool F16>
@@ -408,7 +417,7 @@ __device__ __forceinline__ void arm_body(const pdmp_arm &arm, const uint4 *fraw,
                     for (int e = 0; e < 3; ++e) kz[3 * i + e] = zx[i][e];
             }
         }
-        __syncthreads();
+        wave_lds_sync();
         float SG[3] = {0, 0, 0}, SM[3] = {0, 0, 0};
 #pragma unroll 1
         for (int l = NDOF - 1; l >= 0; --l) {
@@ -442,12 +451,12 @@ __device__ __forceinline__ void arm_body(const pdmp_arm &arm, const uint4 *fraw,
                 mc = fmaxf(mc, c);
             }
         }
-        __syncthreads();
+        wave_lds_sync();
         if (MORPH) {
 #pragma unroll
             for (int j = 0; j < NDOF; ++j) q[j] = q[j] - eta * kg[j];
         }
-        __syncthreads();
+        wave_lds_sync();
     }
     if (rec) traj_put<NDOF>(tr, steps, tc, q);
     if (!MORPH) {
