@@ -394,9 +394,9 @@ def headline(args, P, I, K, torch, dev):
                            "kernel": "k_grid2d_sorted<2,4> (after the 32x32-cell counting sort, "
                                      "timed with it)",
                            "kernel_ms": morph_ms, "kernel_ms_median": morph_median,
-                           "skipping": "each wave skips the hinge blocks and row tiles whose "
-                                       "terms are exact zeros for all its samples; the work "
-                                       "counted is the dense sum's",
+                           "skipping": "each wave skips the 16-hinge blocks and 8-row groups "
+                                       "whose terms are exact zeros for all its samples; the "
+                                       "work counted is the dense sum's",
                            "split_scheme": scheme,
                            "work": "4*G0*G1 FP32-accurate flops per sample-step (64x64 grid): "
                                    "the two G1 x G0 contractions, on "

@@ -83,6 +83,8 @@ def _load():
         "orc_mlp_nparams": (C.c_int64, [C.c_int, _ip]),
         "orc_mlp_forward": (None, [C.c_int, _ip, _dp, _dp, _i64, C.c_int, _dp, _dp]),
         "orc_mlp_loss_grad": (C.c_double, [C.c_int, _ip, _dp, _dp, _dp, _i64, _dp]),
+        "orc_mlp_loss_grad_weighted": (C.c_double, [C.c_int, _ip, _dp, _dp, _dp, _i64, _u8p,
+                                                    C.c_double, _dp]),
         "orc_amortised_morph": (None, [C.c_int, _ip, _dp, C.c_int, C.c_int, _dp, C.c_int, _dp,
                                        _dp, C.c_double, C.c_double, _dp, _i64, C.c_int,
                                        C.c_double, C.c_double, _dp, _u8p, _dp]),
@@ -503,6 +505,19 @@ def mlp_loss_grad(widths, P, q, target):
     g = np.zeros_like(P)
     L = _load().orc_mlp_loss_grad(wd.size - 1, _P(wd, _ip), _P(P), _P(q), _P(t), q.shape[1],
                                   _P(g))
+    return L, g
+
+
+def mlp_loss_grad_weighted(widths, P, q, target, hard, hard_weight):
+    """The MSE with sample weight hard_weight where hard[s] != 0 (1 elsewhere), still
+    normalised by n_out B, and its gradient."""
+    wd = _widths(widths)
+    q, t, P = _d(q), _d(target), _d(P)
+    hard = np.ascontiguousarray(np.asarray(hard, np.uint8))
+    assert hard.shape == (q.shape[1],)
+    g = np.zeros_like(P)
+    L = _load().orc_mlp_loss_grad_weighted(wd.size - 1, _P(wd, _ip), _P(P), _P(q), _P(t),
+                                           q.shape[1], _P(hard, _u8p), float(hard_weight), _P(g))
     return L, g
 
 

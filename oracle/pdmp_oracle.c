@@ -924,10 +924,13 @@ void orc_mlp_forward(int L, const int *widths, const double *P, const double *q,
     }
 }
 
-/* MSE loss (1/(wL*B)) sum |q_hat - target|^2 of the residual network and its
- * gradient with respect to every parameter (same flat layout as P). */
-double orc_mlp_loss_grad(int L, const int *widths, const double *P, const double *q,
-                         const double *target, int64_t B, double *grad) {
+/* MSE loss (1/(wL*B)) sum_s u_s |q_hat_s - target_s|^2 of the residual network and
+ * its gradient with respect to every parameter (same flat layout as P), with sample
+ * weight u_s = hard_w where hard[s] != 0 and 1 elsewhere (hard NULL: all 1, the
+ * plain MSE). */
+static double mlp_loss_grad(int L, const int *widths, const double *P, const double *q,
+                            const double *target, int64_t B, const uint8_t *hard, double hard_w,
+                            double *grad) {
     int w0 = widths[0], wl = widths[L];
     int64_t np = mlp_nparams(L, widths);
     int64_t zlen = 0, alen = w0;
@@ -944,10 +947,11 @@ double orc_mlp_loss_grad(int L, const int *widths, const double *P, const double
         double in[ORC_MLP_MAXW], f[ORC_MLP_MAXW], d[ORC_MLP_MAXW], dn[ORC_MLP_MAXW];
         for (int k = 0; k < w0; ++k) in[k] = q[(int64_t)k * B + s];
         mlp_fwd1(L, widths, P, in, f, z, a);
+        const double u = (hard && hard[s]) ? hard_w : 1.0;
         for (int k = 0; k < wl; ++k) {
             double e = in[k] + f[k] - target[(int64_t)k * B + s];
-            loss += e * e;
-            d[k] = 2.0 * scale * e; /* dL/df = dL/dq_hat */
+            loss += u * (e * e);
+            d[k] = 2.0 * scale * u * e; /* dL/df = dL/dq_hat */
         }
         /* walk layers backwards; d holds dL/dz_l of the current layer */
         int64_t poff = np, zoff = zlen, aoff = alen;
@@ -977,6 +981,17 @@ double orc_mlp_loss_grad(int L, const int *widths, const double *P, const double
     free(z);
     free(a);
     return loss * scale;
+}
+
+double orc_mlp_loss_grad(int L, const int *widths, const double *P, const double *q,
+                         const double *target, int64_t B, double *grad) {
+    return mlp_loss_grad(L, widths, P, q, target, B, NULL, 1.0, grad);
+}
+
+double orc_mlp_loss_grad_weighted(int L, const int *widths, const double *P, const double *q,
+                                  const double *target, int64_t B, const uint8_t *hard,
+                                  double hard_w, double *grad) {
+    return mlp_loss_grad(L, widths, P, q, target, B, hard, hard_w, grad);
 }
 
 /* ------------------------------------------------------------------------- */

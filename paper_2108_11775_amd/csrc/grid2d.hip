@@ -231,43 +231,71 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
 // A workspace morph of a large batch first orders the samples by a 32 x 32 cell grid
 // over the hinge axes' range (a counting sort into a permutation), so that the 32
 // samples of a wave lie close together.  Every step, the wave then finds, from its
-// samples' distances to each k-step's hinge x-range and to each row tile's y-range:
+// samples' distances to each k-step's hinge x-range and to each 8-row group's y-range:
 //  * k-steps whose B operands are zero for all its samples: on the FP16 scheme an
-//    operand 2^c ex_a (or 2^c ex_a dx_a) rounds to the FP16 zero below 2^-25, which
-//    every hinge of the k-step is when the sample's nearest one lies at dx^2 >= c + 34
-//    (kappa units; the 9 spare binades cover |dx| up to 2^6 and the exponential's
-//    rounding, and beyond |dx| = 2^6 the feature underflows in FP32);
-//  * row tiles whose ey_b = exp2(-dy^2) are zero for all its samples: dy^2 >= 152
-//    puts every row of the tile past FP32's smallest subnormal.
+//    operand 2^c ex_a or 2^c ex_a |dx_a| = 2^(c - dx^2 + log2|dx|) rounds (both split
+//    parts) to the FP16 zero at or below 2^-25, which every hinge of the k-step is
+//    when the sample's nearest one lies at dx^2 >= c + 30 (kappa units): for |dx| <
+//    32, log2|dx| < 5 leaves a margin far above the rounding of the exponential and
+//    its argument, and for |dx| >= 32, dx^2 >= 1024 exceeds c + 25 + log2|dx| since
+//    c <= 271;
+//  * 8-row groups whose ey_b = exp2(-dy^2) are zero for all its samples: a sample at
+//    least kYReach = 12.5 below the group's lowest row or above its highest has
+//    dy^2 > 154 for every row, past FP32's smallest subnormal (the 0.5 over sqrt(150)
+//    covers the rounding of the coordinates while the rows lie within 2^20 of 0; rows
+//    beyond that switch the group test off), and row tiles with no such group take no
+//    products at all.
 // Their products and contractions add exact zeros to accumulators that start at +0
 // (an MFMA with an all-zero B column leaves that column of C unchanged; fma(0, U, s)
-// = s), so skipping them gives each sample the bits of the unordered kernel, in any
-// grouping.  The BF16 scheme (R26 in the design notes: operands of FP32 range) takes
-// the dense path, only through the permutation.
+// = s, and the sums never hold -0), so skipping them gives each sample the bits of
+// the unordered kernel, in any grouping.  A wave with a non-finite coordinate in any
+// lane skips nothing (there the unordered kernel's zero features multiply NaN or
+// infinite factors).  The BF16 scheme (for operands of FP32 range, whose features
+// need not underflow) takes the dense path, only through the permutation.
+//
+// The order is kept per part: the batch is cut into kSortParts = 8 contiguous parts,
+// each sorted on its own, and block b of the morph takes its samples from part b mod
+// 8.  Workgroups are handed to the eight XCDs in turn, so each part's samples are
+// read and written by one XCD, whose L2 then holds the part's lines while its waves
+// gather and scatter single coordinates through the permutation: HBM sees about one
+// read and one write of each line instead of one per coordinate.
 constexpr int kSortCells = 32;  // per axis
+constexpr int kSortParts = 8;
+constexpr float kYReach = 12.5f;
 
 __device__ __forceinline__ uint32_t wave_any(bool p) { return __ballot(p) != 0 ? 1u : 0u; }
 
-// The y contraction of one 32-row tile (rows 32t + 8(v/4) + 4 half + v%4).
-__device__ __forceinline__ void g2_ysum_tile(const float *gys, float ys, int half, int t,
+// A wave-uniform value kept in a scalar register.
+__device__ __forceinline__ float uniform_f(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// The y contraction of the 8-row groups of one 32-row tile set in gm (bit j: rows
+// 32t + 8j .. 32t + 8j + 7), from this lane's rows gy[v] = gy_b, b = 32t + 8(v/4) +
+// 4 half + v%4, held in registers.
+__device__ __forceinline__ void g2_ysum_tile(const float (&gy)[16], float ys, uint32_t gm,
                                              const f32x16_t &U, const f32x16_t &V, float &s,
                                              float &sx, float &sy) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int b = 32 * t + 8 * (v >> 2) + 4 * half + (v & 3);
-        const float d = ys - gys[b];
-        const float e = exp2_fast(-d * d);
-        s = fmaf(e, U[v], s);
-        sx = fmaf(e, V[v], sx);
-        sy = fmaf(e * d, U[v], sy);
+    for (int j = 0; j < 4; ++j) {
+        if (!((gm >> j) & 1u)) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int v = 4 * j + r;
+            const float d = ys - gy[v];
+            const float e = exp2_fast(-d * d);
+            s = fmaf(e, U[v], s);
+            sx = fmaf(e, V[v], sx);
+            sy = fmaf(e * d, U[v], sy);
+        }
     }
 }
 
 template <int TB, int KS>
-__global__ void __launch_bounds__(kG2Block) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(kG2Block) __attribute__((amdgpu_waves_per_eu(3)))
 k_grid2d_sorted(const float *__restrict__ hinges, const float *__restrict__ weights, int g0,
                 int g1, float kappa, float gscale, const float *x_in, int64_t n, int T, float eta,
-                const uint32_t *__restrict__ perm, float *x_out, Traj tr) {
+                const uint32_t *__restrict__ perm, int64_t part, float *x_out, Traj tr) {
     __shared__ uint4 fraw[3 * KS * TB * 64];
     __shared__ float gxs[16 * KS];
     __shared__ float gys[32 * TB];
@@ -275,8 +303,11 @@ k_grid2d_sorted(const float *__restrict__ hinges, const float *__restrict__ weig
     const int M = g0 * g1;
     const int lane = threadIdx.x & 63, half = lane >> 5, wv = threadIdx.x >> 6;
     const SplitScheme sc = g2_stage<TB, KS, true>(fraw, gxs, gys, rg, hinges, weights, g0, g1, kappa);
-    const int64_t slot = ((int64_t)blockIdx.x * (kG2Block / 64) + wv) * 32 + (lane & 31);
-    const bool live = slot < n;
+    // part p = b mod 8 holds sorted places [p part, min((p + 1) part, n))
+    const int64_t p = blockIdx.x % kSortParts;
+    const int64_t k = ((int64_t)(blockIdx.x / kSortParts) * (kG2Block / 64) + wv) * 32 + (lane & 31);
+    const int64_t slot = p * part + k;
+    const bool live = k < part && slot < n;
     const int64_t ic = perm[live ? slot : n - 1];
     const int64_t i = live ? (int64_t)ic : n;  // n: a tail lane, writes nothing
     float x = x_in[ic], y = x_in[(size_t)n + ic];
@@ -287,45 +318,62 @@ k_grid2d_sorted(const float *__restrict__ hinges, const float *__restrict__ weig
 
     if (sc.fp16) {
         const f16x8_t *frag = reinterpret_cast<const f16x8_t *>(fraw);
-        // the x-range of each k-step's hinges and the y-range of each row tile's rows
-        // (kappa units; padding excluded)
-        float klo[KS], khi[KS], tlo[TB], thi[TB];
+        // the x-range of each k-step's hinges (kappa units; padding excluded) and the
+        // bounds of each 8-row group past which its ey_b vanish (a group of padding
+        // rows only is never needed: its weights are zero)
+        // (wave-uniform, in scalar registers), and this lane's y rows in registers
+        float klo[KS], khi[KS], ga[4 * TB], gb[4 * TB], gy[TB][16];
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            klo[ks] = INFINITY;
-            khi[ks] = -INFINITY;
+            float lo = INFINITY, hi = -INFINITY;
             for (int a = 16 * ks; a < 16 * ks + 16 && a < g0; ++a) {
-                klo[ks] = fminf(klo[ks], gxs[a]);
-                khi[ks] = fmaxf(khi[ks], gxs[a]);
+                lo = fminf(lo, gxs[a]);
+                hi = fmaxf(hi, gxs[a]);
             }
+            klo[ks] = uniform_f(lo);
+            khi[ks] = uniform_f(hi);
+        }
+        float gmag = 0.0f;
+#pragma unroll
+        for (int g = 0; g < 4 * TB; ++g) {
+            float lo = INFINITY, hi = -INFINITY;
+            for (int b = 8 * g; b < 8 * g + 8 && b < g1; ++b) {
+                lo = fminf(lo, gys[b]);
+                hi = fmaxf(hi, gys[b]);
+                gmag = fmaxf(gmag, fabsf(gys[b]));
+            }
+            ga[g] = uniform_f(lo - kYReach);
+            gb[g] = uniform_f(hi + kYReach);
         }
 #pragma unroll
-        for (int t = 0; t < TB; ++t) {
-            tlo[t] = INFINITY;
-            thi[t] = -INFINITY;
-            for (int b = 32 * t; b < 32 * t + 32 && b < g1; ++b) {
-                tlo[t] = fminf(tlo[t], gys[b]);
-                thi[t] = fmaxf(thi[t], gys[b]);
-            }
-        }
+        for (int t = 0; t < TB; ++t)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) gy[t][v] = gys[32 * t + 8 * (v >> 2) + 4 * half + (v & 3)];
+        const uint32_t all_groups = (1u << (4 * TB)) - 1u;
+        const bool group_test = gmag < 0x1p20f;
         for (int st = 0; st < T; ++st) {
             if (rec) traj_put<2>(tr, st, tc, {x, y});
             const float xs = kappa * x, ys = kappa * y;
             const int c = split_scale_exp(xs, sc.gmin, sc.gmax);
-            const float lim = (float)(c + 34);
-            uint32_t km = 0, tm = 0;
+            const float lim = (float)(c + 30);
+            uint32_t km = 0, gm = 0;
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
                 const float d = fmaxf(fmaxf(klo[ks] - xs, xs - khi[ks]), 0.0f);
                 km |= wave_any(d * d < lim) << ks;
             }
 #pragma unroll
-            for (int t = 0; t < TB; ++t) {
-                const float d = fmaxf(fmaxf(tlo[t] - ys, ys - thi[t]), 0.0f);
-                tm |= wave_any(d * d < 152.0f) << t;
+            for (int g = 0; g < 4 * TB; ++g)
+                gm |= ((__ballot(!(ys <= ga[g])) & __ballot(!(ys >= gb[g]))) != 0 ? 1u : 0u) << g;
+            if (!group_test || __ballot(!__builtin_isfinite(xs) || !__builtin_isfinite(ys)) != 0) {
+                km = (1u << KS) - 1u;
+                gm = all_groups;
             }
             km = __builtin_amdgcn_readfirstlane(km);
-            tm = __builtin_amdgcn_readfirstlane(tm);
+            gm = __builtin_amdgcn_readfirstlane(gm);
+            uint32_t tm = 0;
+#pragma unroll
+            for (int t = 0; t < TB; ++t) tm |= (((gm >> (4 * t)) & 15u) != 0 ? 1u : 0u) << t;
             f32x16_t U[TB], V[TB];
             int ln = lane;  // opaque: keeps the fragment reads inside the step loop
             asm volatile("" : "+v"(ln));
@@ -360,7 +408,8 @@ k_grid2d_sorted(const float *__restrict__ hinges, const float *__restrict__ weig
             if (km) {
 #pragma unroll
                 for (int t = 0; t < TB; ++t)
-                    if ((tm >> t) & 1u) g2_ysum_tile(gys, ys, half, t, U[t], V[t], s, sx, sy);
+                    if ((tm >> t) & 1u)
+                        g2_ysum_tile(gy[t], ys, (gm >> (4 * t)) & 15u, U[t], V[t], s, sx, sy);
             }
             s += __shfl_xor(s, 32, 64);
             sx += __shfl_xor(sx, 32, 64);
@@ -464,61 +513,94 @@ __device__ __forceinline__ int sort_cell(float x, float y, const float (&f)[4]) 
 }
 
 constexpr int kSortBlock = 256, kSortChunk = 4096;
+constexpr int kSortKeys = kSortParts * kSortCells * kSortCells;
+
+// Samples per part: ceil(n / 8).
+__host__ __device__ __forceinline__ int64_t sort_part(int64_t n) {
+    return (n + kSortParts - 1) / kSortParts;
+}
+
+// Chunks of kSortChunk samples are cut within each part, as the morph's places are:
+// block b takes chunk b / 8 of part b mod 8, so a part's reads of x and writes of its
+// counters and permutation entries all come from one XCD.
+__host__ __device__ __forceinline__ int64_t sort_chunks_per_part(int64_t n) {
+    return (sort_part(n) + kSortChunk - 1) / kSortChunk;
+}
 
 __global__ void __launch_bounds__(kSortBlock) k_sort_zero(uint32_t *counts) {
-    for (int b = threadIdx.x; b < kSortCells * kSortCells; b += kSortBlock) counts[b] = 0;
+    for (int b = threadIdx.x; b < kSortKeys; b += kSortBlock) counts[b] = 0;
+}
+
+// This block's chunk [lo, hi) of part p in an LDS histogram over the cells.
+__device__ __forceinline__ void sort_chunk_hist(const float *__restrict__ hinges, int g0, int g1,
+                                                const float *__restrict__ x, int64_t n,
+                                                int64_t part, uint32_t *hist, float *red,
+                                                float (&f)[4], int64_t &p, int64_t &lo,
+                                                int64_t &hi) {
+    sort_frame(hinges, g0, g1, f, red);
+    for (int b = threadIdx.x; b < kSortCells * kSortCells; b += kSortBlock) hist[b] = 0;
+    __syncthreads();
+    p = blockIdx.x % kSortParts;
+    lo = p * part + (int64_t)(blockIdx.x / kSortParts) * kSortChunk;
+    hi = min(min(lo + kSortChunk, (p + 1) * part), n);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kSortBlock)
+        atomicAdd(&hist[sort_cell(x[i], x[(size_t)n + i], f)], 1u);
+    __syncthreads();
 }
 
 __global__ void __launch_bounds__(kSortBlock)
 k_sort_count(const float *__restrict__ hinges, int g0, int g1, const float *__restrict__ x, int64_t n,
-             uint32_t *counts) {
+             int64_t part, uint32_t *counts) {
     __shared__ uint32_t hist[kSortCells * kSortCells];
     __shared__ float red[4 * kSortBlock / 64];
     float f[4];
-    sort_frame(hinges, g0, g1, f, red);
-    for (int b = threadIdx.x; b < kSortCells * kSortCells; b += kSortBlock) hist[b] = 0;
-    __syncthreads();
-    const int64_t i0 = (int64_t)blockIdx.x * kSortChunk;
-    for (int64_t i = i0 + threadIdx.x; i < i0 + kSortChunk && i < n; i += kSortBlock)
-        atomicAdd(&hist[sort_cell(x[i], x[(size_t)n + i], f)], 1u);
-    __syncthreads();
+    int64_t p, lo, hi;
+    sort_chunk_hist(hinges, g0, g1, x, n, part, hist, red, f, p, lo, hi);
     for (int b = threadIdx.x; b < kSortCells * kSortCells; b += kSortBlock)
-        if (hist[b]) atomicAdd(&counts[b], hist[b]);
+        if (hist[b]) atomicAdd(&counts[p * kSortCells * kSortCells + b], hist[b]);
 }
 
-// Exclusive prefix sum of the cell counts, in place (one block of 1024 threads).
+// Exclusive prefix sum of the 8 x 1024 part-cell counts, in place (one block of 1024
+// threads, eight consecutive keys each).
 __global__ void __launch_bounds__(1024) k_sort_scan(uint32_t *counts) {
-    __shared__ uint32_t sh[kSortCells * kSortCells];
+    __shared__ uint32_t sh[1024];
+    constexpr int kPer = kSortKeys / 1024;
     const int t = threadIdx.x;
-    sh[t] = counts[t];
+    uint32_t v[kPer], run = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        v[j] = counts[kPer * t + j];
+        run += v[j];
+    }
+    sh[t] = run;
     __syncthreads();
-    for (int off = 1; off < kSortCells * kSortCells; off <<= 1) {
-        const uint32_t v = t >= off ? sh[t - off] : 0u;
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t u = t >= off ? sh[t - off] : 0u;
         __syncthreads();
-        sh[t] += v;
+        sh[t] += u;
         __syncthreads();
     }
-    counts[t] = t > 0 ? sh[t - 1] : 0u;
+    uint32_t base = t > 0 ? sh[t - 1] : 0u;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        counts[kPer * t + j] = base;
+        base += v[j];
+    }
 }
 
 __global__ void __launch_bounds__(kSortBlock)
 k_sort_scatter(const float *__restrict__ hinges, int g0, int g1, const float *__restrict__ x,
-               int64_t n, uint32_t *cursor, uint32_t *perm) {
+               int64_t n, int64_t part, uint32_t *cursor, uint32_t *perm) {
     __shared__ uint32_t hist[kSortCells * kSortCells];
     __shared__ float red[4 * kSortBlock / 64];
     float f[4];
-    sort_frame(hinges, g0, g1, f, red);
-    for (int b = threadIdx.x; b < kSortCells * kSortCells; b += kSortBlock) hist[b] = 0;
-    __syncthreads();
-    const int64_t i0 = (int64_t)blockIdx.x * kSortChunk;
-    for (int64_t i = i0 + threadIdx.x; i < i0 + kSortChunk && i < n; i += kSortBlock)
-        atomicAdd(&hist[sort_cell(x[i], x[(size_t)n + i], f)], 1u);
-    __syncthreads();
-    // this block's range in each cell, then the samples' places within it
+    int64_t p, lo, hi;
+    sort_chunk_hist(hinges, g0, g1, x, n, part, hist, red, f, p, lo, hi);
+    // this block's range in each of its part's cells, then the samples' places in it
     for (int b = threadIdx.x; b < kSortCells * kSortCells; b += kSortBlock)
-        hist[b] = hist[b] ? atomicAdd(&cursor[b], hist[b]) : 0u;
+        hist[b] = hist[b] ? atomicAdd(&cursor[p * kSortCells * kSortCells + b], hist[b]) : 0u;
     __syncthreads();
-    for (int64_t i = i0 + threadIdx.x; i < i0 + kSortChunk && i < n; i += kSortBlock)
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kSortBlock)
         perm[atomicAdd(&hist[sort_cell(x[i], x[(size_t)n + i], f)], 1u)] = (uint32_t)i;
 }
 
@@ -827,7 +909,7 @@ int32_t launch_grid2d(int mode, const RbfArgs &a, int g0, int g1, hipStream_t st
 size_t grid2d_sorted_ws_bytes(int g0, int g1, int64_t n, int T) {
     if (g0 < 1 || g1 < 1 || g0 > 64 || g1 > 64 || n < kG2SmallBatch || T < 1 || n > 0xffffffffll)
         return 0;
-    return (((size_t)kSortCells * kSortCells * sizeof(uint32_t) + 255) & ~(size_t)255) +
+    return (((size_t)kSortKeys * sizeof(uint32_t) + 255) & ~(size_t)255) +
            (size_t)n * sizeof(uint32_t);
 }
 
@@ -836,20 +918,22 @@ int32_t launch_grid2d_sorted(const RbfArgs &a, int g0, int g1, void *ws, hipStre
     if (!grid2d_sorted_ws_bytes(g0, g1, a.n, a.T) || (int64_t)g0 * g1 != a.M)
         return PDMP_EUNSUPPORTED;
     uint32_t *cursor = (uint32_t *)ws;
-    uint32_t *perm = (uint32_t *)((char *)ws + (((size_t)kSortCells * kSortCells *
-                                                 sizeof(uint32_t) + 255) & ~(size_t)255));
-    const unsigned nb = (unsigned)((a.n + kSortChunk - 1) / kSortChunk);
+    uint32_t *perm =
+        (uint32_t *)((char *)ws + (((size_t)kSortKeys * sizeof(uint32_t) + 255) & ~(size_t)255));
+    const int64_t part = sort_part(a.n);
+    const unsigned nb = (unsigned)(kSortParts * sort_chunks_per_part(a.n));
     hipLaunchKernelGGL(k_sort_zero, dim3(1), dim3(kSortBlock), 0, st, cursor);
     hipLaunchKernelGGL(k_sort_count, dim3(nb), dim3(kSortBlock), 0, st, a.hinges, g0, g1, a.x_in,
-                       a.n, cursor);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kSortCells * kSortCells), 0, st, cursor);
+                       a.n, part, cursor);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, st, cursor);
     hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kSortBlock), 0, st, a.hinges, g0, g1, a.x_in,
-                       a.n, cursor, perm);
+                       a.n, part, cursor, perm);
     if (int32_t e = check_launch("k_sort")) return e;
-    const dim3 grid((unsigned)((a.n + 127) / 128)), blk(kG2Block);
+    // kSortParts interleaved runs of blocks, each covering one part
+    const dim3 grid((unsigned)(kSortParts * ((part + 127) / 128))), blk(kG2Block);
 #define PDMP_G2O(TB, KS)                                                                         \
     hipLaunchKernelGGL((k_grid2d_sorted<TB, KS>), grid, blk, 0, st, a.hinges, a.weights, g0, g1, \
-                       a.kappa, a.gscale, a.x_in, a.n, a.T, a.eta, perm, a.x_out, a.traj)
+                       a.kappa, a.gscale, a.x_in, a.n, a.T, a.eta, perm, part, a.x_out, a.traj)
     const int ks = (g0 + 15) / 16;
     if (g1 <= 32) {
         if (ks == 1) PDMP_G2O(1, 1); else if (ks == 2) PDMP_G2O(1, 2);

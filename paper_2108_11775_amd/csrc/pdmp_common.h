@@ -61,10 +61,11 @@ __device__ __forceinline__ float f4c(const float4 &v, int u) {
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // sigma(s) and sigma'(s) = sigma(1 - sigma) from e = exp(-|s|) in (0, 1], which keeps
-// both to a few ulp relative even where sigma is within rounding of 0 or 1.
+// both to a few ulp relative even where sigma is within rounding of 0 or 1.  The
+// reciprocal of 1 + e in [1, 2] is v_rcp_f32's (within 1 ulp; no range to guard).
 __device__ __forceinline__ void sigmoid_and_slope(float s, float &c, float &sp) {
     float e = exp2_fast(-fabsf(s) * kLog2e);
-    float inv = 1.0f / (1.0f + e);
+    float inv = __builtin_amdgcn_rcpf(1.0f + e);
     c = s >= 0.0f ? inv : e * inv;
     sp = e * inv * inv;
 }

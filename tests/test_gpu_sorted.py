@@ -67,7 +67,9 @@ def test_ordered_morph_shapes_and_schemes(g0, g1, scheme):
 
 def test_ordered_morph_clustered_and_far_points():
     """Points bunched in one corner (every wave in one cell), points far outside the
-    grid (every feature zero: all work skipped) and a few NaN coordinates."""
+    grid (every feature zero: all work skipped), a few NaN coordinates, and non-finite
+    coordinates among far points (whose waves would otherwise skip everything, while
+    the plain kernel's zero features times NaN or infinite factors give NaN)."""
     require_gpu()
     cfg = K.C2
     sc = ws_scene(cfg)
@@ -79,6 +81,14 @@ def test_ordered_morph_clustered_and_far_points():
                         rng.uniform(-10, 10, (2, n - n // 2 - n // 4))], axis=1).astype(np.float32)
     x[:, 7] = np.nan
     x[1, 99] = np.nan
+    # a far cluster in the corner cell (x < lo, y > hi) holding non-finite coordinates
+    far = np.arange(1000, 1256)
+    x[0, far] = -40.0
+    x[1, far] = 35.0
+    x[0, far[3]] = np.nan
+    x[0, far[50]] = np.inf
+    x[1, far[100]] = np.inf
+    x[0, far[150]] = -np.inf
     plain = host(P.morph_samples(go, dev(x), cfg.T, cfg.eta))
     got = host(P.morph_samples_ws(go, dev(x), cfg.T, cfg.eta))
     assert np.array_equal(got, plain, equal_nan=True)
@@ -107,3 +117,24 @@ def test_workspace_rules():
     assert P.morph_workspace(dense, 3000, 5) is None
     assert np.array_equal(host(P.morph_samples_ws(dense, x2, 5, cfg.eta)),
                           host(P.morph_samples(dense, x2, 5, cfg.eta)))
+
+
+def test_ordered_morph_grid_far_from_origin():
+    """Hinge rows beyond 2^20 kappa units from 0 switch the row-group test off (its
+    reach no longer covers the rounding of the coordinates); k-steps are still skipped.
+    A 24 x 20 grid of unit spacing near 10^6 with a batch over and around it."""
+    require_gpu()
+    rng = np.random.default_rng(11)
+    ell = 0.4
+    ax = (1.0e6 + np.arange(24)).astype(np.float32)
+    ay = (-1.0e6 + np.arange(20)).astype(np.float32)
+    j = np.arange(24 * 20)
+    h = np.stack([ax[j % 24], ay[j // 24]]).astype(np.float32)
+    wb = (rng.choice([-1.0, 1.0], 24 * 20 + 1) * 2.0 ** rng.uniform(-6, 1, 24 * 20 + 1))
+    wb = wb.astype(np.float32)
+    go = gpu_occ(h, wb, ell, (24, 20))
+    assert P.split_scheme(go)[0] == "fp16"
+    n = (1 << 17) + 5
+    x = np.stack([rng.uniform(ax[0] - 3, ax[-1] + 3, n),
+                  rng.uniform(ay[0] - 3, ay[-1] + 3, n)]).astype(np.float32)
+    _same(go, dev(x), 5, 0.05)

@@ -81,3 +81,29 @@ def test_amortised_zero_network_falls_back_to_plain_morph():
         else:
             np.testing.assert_array_equal(out[:, s], q[:, s])
     assert 0 < flag.sum() < 24
+
+
+def test_weighted_mse_is_the_mse_over_duplicated_samples():
+    """A sample of integer weight u counts as u copies of itself: with the batch
+    normalisation of each side, B L_w(batch) = B' L(batch with the hard samples
+    repeated u times), B' the repeated batch's size, and likewise for the gradient.
+    No weight (or no hard sample) is the plain MSE, bit for bit."""
+    widths = (7, 24, 24, 7)
+    layers = I.mlp_init(8, widths, zero_last=False)
+    P = O.mlp_pack(layers)
+    rng = np.random.default_rng(4)
+    B, u = 30, 3
+    q = rng.uniform(-math.pi, math.pi, (7, B))
+    t = q + rng.normal(0, 0.2, (7, B))
+    hard = (rng.uniform(size=B) < 0.4).astype(np.uint8)
+    assert 0 < hard.sum() < B
+    Lw, gw = O.mlp_loss_grad_weighted(widths, P, q, t, hard, float(u))
+    rep = np.concatenate([np.arange(B)] + [np.flatnonzero(hard)] * (u - 1))
+    Ld, gd = O.mlp_loss_grad(widths, P, q[:, rep], t[:, rep])
+    assert B * Lw == pytest.approx(len(rep) * Ld, rel=1e-12)
+    np.testing.assert_allclose(B * gw, len(rep) * gd, rtol=1e-10, atol=1e-14)
+    L0, g0 = O.mlp_loss_grad(widths, P, q, t)
+    L1, g1 = O.mlp_loss_grad_weighted(widths, P, q, t, np.zeros(B, np.uint8), 7.0)
+    L2, g2 = O.mlp_loss_grad_weighted(widths, P, q, t, hard, 1.0)
+    assert L1 == L0 and L2 == L0
+    assert np.array_equal(g1, g0) and np.array_equal(g2, g0)
