@@ -38,14 +38,15 @@ SIMDS, CLOCK_HZ = 1024, 2.4e9      # the peaks' SIMD count and clock
 FLOPS_PER_PAIR = {2: 12, 3: 17}    # 5*dim + 2 algorithmic FP32 flops per sample-hinge pair
 
 
-# HBM traffic per launch of the headline kernel from the two rocprofv3 --pmc runs in
-# profiles/k_grid2d_mfma_morph_ws2d_1M.md (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the
+# HBM traffic per call of the headline's ordered morph (the counting sort's four kernels
+# and k_grid2d_sorted) from the two rocprofv3 --pmc runs in
+# profiles/k_grid2d_sorted_morph_ws2d_1M.md (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the
 # factors a plain 256 MiB device copy reads under the same counters).  Valid only
-# while the kernel's sources (grid2d.hip and the headers it includes) are the ones
+# while the kernels' sources (grid2d.hip and the headers it includes) are the ones
 # the counters were taken on.
 GRID2D_SOURCES = ("grid2d.hip", "grid2d_stage.h", "mfma_split.h", "pdmp_common.h")
-GRID2D_TRAFFIC = {"bytes": (4277.2 * 2.0 + 8192.0) * 1024,
-                  "sha256": "d229082475ca13e669b2699802e7c52a3f4696b442ad88bb32c9a3c20c5afdcc"}
+GRID2D_TRAFFIC = {"bytes": (14783.5 * 2.0 + 21241.8) * 1024,
+                  "sha256": "4310f006a866938f3f41ab7f11eb06bb7423e35e5677cd2e774ccc975dc982dd"}
 
 
 def grid2d_sources_sha():
@@ -61,20 +62,25 @@ def grid2d_traffic():
     return GRID2D_TRAFFIC["bytes"] if grid2d_sources_sha() == GRID2D_TRAFFIC["sha256"] else None
 
 
-# Issue-slot use of the headline kernel from one rocprofv3 --pmc run on the same launch
-# (profiles/utilisation_ws2d_1M.md): VALU instructions per SIMD per active cycle over
-# the 1-per-4-cycles wave64 issue rate, and the MFMA pipe's busy fraction.  Reported
+# Instructions per wave-step (32 samples, one Euler step) of the ordered kernel from one
+# rocprofv3 --pmc run on the same call (SQ_INSTS_* over 2^20 / 32 x 50 wave-steps,
+# profiles/k_grid2d_sorted_morph_ws2d_1M.md), beside the unordered kernel's on the same
+# batch: the MFMAs the exact-zero skipping leaves and the VALU work it keeps.  Reported
 # only while the sources are the ones the counters were taken on.
-GRID2D_UTILISATION = {"valu_issue_frac": 0.198 * 4, "mfma_busy_frac": 0.518,
-                      "sha256": GRID2D_TRAFFIC["sha256"]}
+GRID2D_COUNTS = {"valu": 432.8, "mfma": 19.23, "salu": 103.7, "lds": 23.5,
+                 "unordered_valu": 581.0, "unordered_mfma": 48.0,
+                 "sha256": GRID2D_TRAFFIC["sha256"]}
 
 
-def grid2d_utilisation():
-    u = GRID2D_UTILISATION
+def grid2d_counts():
+    u = GRID2D_COUNTS
     if grid2d_sources_sha() != u["sha256"]:
         return None
-    return {"valu_issue_frac": u["valu_issue_frac"], "mfma_busy_frac": u["mfma_busy_frac"],
-            "binding_unit": "VALU issue", "source": "profiles/utilisation_ws2d_1M.md"}
+    return {"unit": "instructions per wave-step", "valu": u["valu"], "mfma": u["mfma"],
+            "salu": u["salu"], "lds": u["lds"],
+            "unordered_kernel": {"valu": u["unordered_valu"], "mfma": u["unordered_mfma"]},
+            "mfma_executed_fraction": u["mfma"] / u["unordered_mfma"],
+            "source": "profiles/k_grid2d_sorted_morph_ws2d_1M.md"}
 
 
 # Issue costs measured on this device at the start of the run (pdmp_issue_rates:
@@ -406,10 +412,14 @@ def headline(args, P, I, K, torch, dev):
                                           "frac": nprod * fp32_tf * 1e12 / peak},
                            "frac_ceiling_of_split_scheme": 1.0 / nprod,
                            "ceiling": ceil,
-                           "utilisation": grid2d_utilisation(),
-                           "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE + "
-                                           "WRITE_SIZE, copy-calibrated); algorithmic "
-                                           f"{N * 2 * 4 * 2} bytes"}
+                           "instruction_counts": grid2d_counts(),
+                           "traffic_note": "HBM bytes per call, the sort's kernels included "
+                                           "(rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                           "copy-calibrated); algorithmic "
+                                           f"{N * 2 * 4 * 2} bytes of state in and out, "
+                                           f"{N * 2 * 4 * 4 + N * 4 * 2} with the sort's "
+                                           "two reads of the batch, its permutation "
+                                           "written and read"}
         # the pairwise kernel on the same batch, for reference
         dense = P.Occupancy(occ.hinges, occ.weights, occ.lengthscale)
         P.morph_samples(dense, x0, cfg.T, cfg.eta, out=x1)

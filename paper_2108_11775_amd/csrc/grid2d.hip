@@ -271,9 +271,9 @@ __device__ __forceinline__ float uniform_f(float v) {
 }
 
 // The y contraction of the 8-row groups of one 32-row tile set in gm (bit j: rows
-// 32t + 8j .. 32t + 8j + 7), from this lane's rows gy[v] = gy_b, b = 32t + 8(v/4) +
-// 4 half + v%4, held in registers.
-__device__ __forceinline__ void g2_ysum_tile(const float (&gy)[16], float ys, uint32_t gm,
+// 32t + 8j .. 32t + 8j + 7), from this lane's rows gy[j][r] = gy_b, b = 32t + 8j +
+// 4 half + r.
+__device__ __forceinline__ void g2_ysum_tile(const f32x4_t (&gy)[4], float ys, uint32_t gm,
                                              const f32x16_t &U, const f32x16_t &V, float &s,
                                              float &sx, float &sy) {
 #pragma unroll
@@ -282,7 +282,7 @@ __device__ __forceinline__ void g2_ysum_tile(const float (&gy)[16], float ys, ui
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int v = 4 * j + r;
-            const float d = ys - gy[v];
+            const float d = ys - gy[j][r];
             const float e = exp2_fast(-d * d);
             s = fmaf(e, U[v], s);
             sx = fmaf(e, V[v], sx);
@@ -298,7 +298,7 @@ k_grid2d_sorted(const float *__restrict__ hinges, const float *__restrict__ weig
                 const uint32_t *__restrict__ perm, int64_t part, float *x_out, Traj tr) {
     __shared__ uint4 fraw[3 * KS * TB * 64];
     __shared__ float gxs[16 * KS];
-    __shared__ float gys[32 * TB];
+    __shared__ __align__(16) float gys[32 * TB];
     __shared__ SplitRange rg;
     const int M = g0 * g1;
     const int lane = threadIdx.x & 63, half = lane >> 5, wv = threadIdx.x >> 6;
@@ -308,21 +308,22 @@ k_grid2d_sorted(const float *__restrict__ hinges, const float *__restrict__ weig
     const int64_t k = ((int64_t)(blockIdx.x / kSortParts) * (kG2Block / 64) + wv) * 32 + (lane & 31);
     const int64_t slot = p * part + k;
     const bool live = k < part && slot < n;
-    const int64_t ic = perm[live ? slot : n - 1];
-    const int64_t i = live ? (int64_t)ic : n;  // n: a tail lane, writes nothing
+    const uint32_t ic = perm[live ? slot : n - 1];
+    const uint32_t i = live ? ic : (uint32_t)n;  // n (< 2^32 here): a tail lane, writes nothing
     float x = x_in[ic], y = x_in[(size_t)n + ic];
     const float beta = weights[M];
     float s = 0.0f, sx = 0.0f, sy = 0.0f;
-    int64_t tc;
-    const bool rec = half == 0 && traj_col(tr, i, n, tc);
+    int64_t tc64;
+    const bool rec = half == 0 && traj_col(tr, (int64_t)i, n, tc64);
+    const uint32_t tc = (uint32_t)tc64;  // a column below n < 2^32
 
     if (sc.fp16) {
         const f16x8_t *frag = reinterpret_cast<const f16x8_t *>(fraw);
         // the x-range of each k-step's hinges (kappa units; padding excluded) and the
         // bounds of each 8-row group past which its ey_b vanish (a group of padding
         // rows only is never needed: its weights are zero)
-        // (wave-uniform, in scalar registers), and this lane's y rows in registers
-        float klo[KS], khi[KS], ga[4 * TB], gb[4 * TB], gy[TB][16];
+        // (wave-uniform, in scalar registers)
+        float klo[KS], khi[KS], ga[4 * TB], gb[4 * TB];
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             float lo = INFINITY, hi = -INFINITY;
@@ -345,14 +346,10 @@ k_grid2d_sorted(const float *__restrict__ hinges, const float *__restrict__ weig
             ga[g] = uniform_f(lo - kYReach);
             gb[g] = uniform_f(hi + kYReach);
         }
-#pragma unroll
-        for (int t = 0; t < TB; ++t)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) gy[t][v] = gys[32 * t + 8 * (v >> 2) + 4 * half + (v & 3)];
         const uint32_t all_groups = (1u << (4 * TB)) - 1u;
         const bool group_test = gmag < 0x1p20f;
         for (int st = 0; st < T; ++st) {
-            if (rec) traj_put<2>(tr, st, tc, {x, y});
+            if (rec) traj_put<2>(tr, st, (int64_t)tc, {x, y});
             const float xs = kappa * x, ys = kappa * y;
             const int c = split_scale_exp(xs, sc.gmin, sc.gmax);
             const float lim = (float)(c + 30);
@@ -406,6 +403,16 @@ k_grid2d_sorted(const float *__restrict__ hinges, const float *__restrict__ weig
             sx = 0.0f;
             sy = 0.0f;
             if (km) {
+                // this lane's rows, all read before the group branches (one wait for
+                // the LDS reads instead of one per group)
+                f32x4_t gy[TB][4];
+#pragma unroll
+                for (int t = 0; t < TB; ++t) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        gy[t][j] = *reinterpret_cast<const f32x4_t *>(&gys[32 * t + 8 * j + 4 * half]);
+                    asm volatile("" ::"v"(gy[t][0]), "v"(gy[t][1]), "v"(gy[t][2]), "v"(gy[t][3]));
+                }
 #pragma unroll
                 for (int t = 0; t < TB; ++t)
                     if ((tm >> t) & 1u)
@@ -427,7 +434,7 @@ k_grid2d_sorted(const float *__restrict__ hinges, const float *__restrict__ weig
     } else {
         const bf16x8_t *frag = reinterpret_cast<const bf16x8_t *>(fraw);
         for (int st = 0; st < T; ++st) {
-            if (rec) traj_put<2>(tr, st, tc, {x, y});
+            if (rec) traj_put<2>(tr, st, (int64_t)tc, {x, y});
             const float xs = kappa * x, ys = kappa * y;
             f32x16_t U[TB], V[TB];
             int ln = lane;
@@ -456,8 +463,9 @@ k_grid2d_sorted(const float *__restrict__ hinges, const float *__restrict__ weig
             y = fmaf(step, sy, y);
         }
     }
-    if (rec) traj_put<2>(tr, T, tc, {x, y});
-    g2_finish<kMorph>(s, sx, sy, beta, gscale, x, y, half, i, n, nullptr, nullptr, nullptr, x_out);
+    if (rec) traj_put<2>(tr, T, (int64_t)tc, {x, y});
+    g2_finish<kMorph>(s, sx, sy, beta, gscale, x, y, half, (int64_t)i, n, nullptr, nullptr, nullptr,
+                      x_out);
 }
 
 // ---- the spatial order: a counting sort of the samples into 32 x 32 cells ----
