@@ -155,6 +155,10 @@ def parse():
                         "(it runs with the CPU baseline)")
     p.add_argument("--train-epochs", type=int, default=None)
     p.add_argument("--train-batches", type=int, default=None)
+    p.add_argument("--amortised-variants", action="store_true",
+                   help="also train the amortised network's variants (samples whose output "
+                        "lands occupied weighted up; a longer schedule with restarts) and "
+                        "report each one's fallback-vs-collision-free frontier")
     return p.parse_args()
 
 
@@ -812,6 +816,43 @@ def culled_workload(P, I, K, torch, hl):
                                  "culled pairs only"}}
 
 
+AMORTISED_VARIANTS = (
+    # name, epochs factor, schedule, hard weight, threshold that marks a sample hard
+    ("hard x4 at 0.1", 1, None, 4.0, 0.1),
+    ("hard x16 at 0.1", 1, None, 16.0, 0.1),
+    ("3x epochs, cosine with 4 restarts", 3, "cosine_restarts", None, None),
+)
+AMORTISED_THRESHOLDS = (0.5, 0.3, 0.2, 0.1, 0.05, 0.02)
+# the refining variant: trigger thresholds x plain steps from q_hat
+REFINE_POINTS = tuple((th, tr) for th in (0.1, 0.05, 0.03) for tr in (6, 8, 10, 12))
+
+
+def amortised_frontier(P, K, torch, world, mlp, q, pl_ms, cf_plain, refine=False):
+    """Fallback fraction, collision-free fraction and speedup over the plain morph at each
+    trigger threshold (with refine: at each threshold and refining step count), and the
+    fastest point within one point of the plain morph's collision-free fraction."""
+    c3 = K.C3
+    arm, occ = world["arm"], world["occ"]
+    n = int(q.shape[1])
+    points = REFINE_POINTS if refine else tuple((th, c3.T) for th in AMORTISED_THRESHOLDS)
+    sweep = []
+    for th, steps in points:
+        o2, f2, n2 = P.amortised_morph(mlp, occ, arm, q, steps, c3.eta, th, refine=refine)
+        t = Timer(torch)
+        with t:
+            P.amortised_morph(mlp, occ, arm, q, steps, c3.eta, th, out=o2, flag=f2,
+                              n_fallback=n2, refine=refine)
+        ms2 = t.ms()
+        _, h2 = P.label_configs(arm, *world["boxes"], o2, count=True)
+        r = {"threshold": th, "ms": ms2, "speedup": pl_ms / ms2,
+             "fallback_fraction": int(n2.item()) / n, "collision_free": 1 - h2.item() / n}
+        if refine:
+            r["refine_steps"] = steps
+        sweep.append(r)
+    eq = [r for r in sweep if r["collision_free"] >= cf_plain - 0.01]
+    return sweep, (max(eq, key=lambda r: r["speedup"]) if eq else None)
+
+
 def amortised(args, P, I, K, torch, world):
     from paper_2108_11775_amd import amortise
     c3, c5 = K.C3, K.C5
@@ -824,12 +865,23 @@ def amortised(args, P, I, K, torch, world):
                                     I.philox_seed(c5.cfg_id), c3.q_lo, c3.q_hi)
     gen_ms = t.ms()
     log(f"training pairs: {n_batches} x {c5.batch} in {gen_ms / 1e3:.1f} s")
-    mlp = P.Mlp.from_layers(I.mlp_init(c5.cfg_id, c5.widths))
-    t = Timer(torch)
-    with t:
-        losses = amortise.train(mlp, pairs, epochs, c5.lr, c5.beta1, c5.beta2, c5.eps, log=log,
-                                schedule=c5.schedule)
-    train_ms = t.ms()
+
+    def trained(ep, schedule, hard_weight, hard_thresh):
+        mlp = P.Mlp.from_layers(I.mlp_init(c5.cfg_id, c5.widths))
+        t = Timer(torch)
+        with t:
+            losses = amortise.train(mlp, pairs, ep, c5.lr, c5.beta1, c5.beta2, c5.eps, log=log,
+                                    schedule=schedule, hard_weight=hard_weight, occ=occ,
+                                    arm=arm, hard_thresh=hard_thresh or 0.5)
+        return mlp, losses, t.ms()
+
+    mlp, losses, train_ms = trained(epochs, c5.schedule, None, None)
+    variant_nets = []
+    if args.amortised_variants:
+        for name, fac, sched, hw, hth in AMORTISED_VARIANTS:
+            log(f"amortised variant: {name}")
+            vm, vl, vms = trained(epochs * fac, sched or c5.schedule, hw, hth)
+            variant_nets.append((name, fac, sched or c5.schedule, hw, hth, vm, vl, vms))
     del pairs
     q = P.uniform_samples(I.philox_seed(c5.cfg_id, K.STREAM_EVAL), 0, [c3.q_lo] * 7,
                           [c3.q_hi] * 7, c5.eval_samples)
@@ -853,37 +905,41 @@ def amortised(args, P, I, K, torch, world):
     _, fz, nz = P.amortised_morph(zero, occ, arm, q, c3.T, c3.eta, c5.threshold)
     n = c5.eval_samples
     nf_v = int(nf.item())
-    sweep = []
-    for th in (0.5, 0.3, 0.2, 0.1, 0.05, 0.02):
-        o2, f2, n2 = P.amortised_morph(mlp, occ, arm, q, c3.T, c3.eta, th)
-        t = Timer(torch)
-        with t:
-            P.amortised_morph(mlp, occ, arm, q, c3.T, c3.eta, th, out=o2, flag=f2, n_fallback=n2)
-        ms2 = t.ms()
-        _, h2 = P.label_configs(arm, *world["boxes"], o2, count=True)
-        sweep.append({"threshold": th, "ms": ms2, "speedup": pl_ms / ms2,
-                      "fallback_fraction": int(n2.item()) / n,
-                      "collision_free": 1 - h2.item() / n})
     # operating point at an equal collision-free fraction (within 1 point of the plain
     # morph's): the fastest threshold of the sweep that reaches it
     cf_plain = 1 - hp.item() / n
-    eq = [r for r in sweep if r["collision_free"] >= cf_plain - 0.01]
-    equal_cf = max(eq, key=lambda r: r["speedup"]) if eq else None
-    return {"workload": "amortised morph: residual MLP 7-256-256-256-7 SiLU (BF16 MFMA, FP32 "
-                        "accumulate) trained on plain-morph pairs, plain T=30 fallback where "
-                        "max body-point occupancy > 0.5; 65,536 held-out configurations",
-            "train_pairs": n_batches * c5.batch, "epochs": epochs,
-            "pair_generation_s": gen_ms / 1e3, "train_s": train_ms / 1e3,
-            "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
-            "amortised_ms": am_ms, "amortised_samples_per_s": n / (am_ms * 1e-3),
-            "plain_ms": pl_ms, "plain_samples_per_s": n / (pl_ms * 1e-3),
-            "speedup": pl_ms / am_ms, "fallback_fraction": nf_v / n,
-            "fallback_fraction_without_network": int(nz.item()) / n,
-            "collision_free_prior": 1 - h0.item() / n,
-            "collision_free_amortised": 1 - ha.item() / n,
-            "collision_free_plain": cf_plain,
-            "at_equal_collision_free": equal_cf,
-            "threshold_sweep": sweep}
+    sweep, equal_cf = amortised_frontier(P, K, torch, world, mlp, q, pl_ms, cf_plain)
+    res = {"workload": "amortised morph: residual MLP 7-256-256-256-7 SiLU (BF16 MFMA, FP32 "
+                       "accumulate) trained on plain-morph pairs, plain T=30 fallback where "
+                       "max body-point occupancy > 0.5; 65,536 held-out configurations",
+           "train_pairs": n_batches * c5.batch, "epochs": epochs,
+           "pair_generation_s": gen_ms / 1e3, "train_s": train_ms / 1e3,
+           "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+           "amortised_ms": am_ms, "amortised_samples_per_s": n / (am_ms * 1e-3),
+           "plain_ms": pl_ms, "plain_samples_per_s": n / (pl_ms * 1e-3),
+           "speedup": pl_ms / am_ms, "fallback_fraction": nf_v / n,
+           "fallback_fraction_without_network": int(nz.item()) / n,
+           "collision_free_prior": 1 - h0.item() / n,
+           "collision_free_amortised": 1 - ha.item() / n,
+           "collision_free_plain": cf_plain,
+           "at_equal_collision_free": equal_cf,
+           "threshold_sweep": sweep}
+    # the refining variant: flagged configurations take a few plain steps from q_hat
+    rs, re_ = amortised_frontier(P, K, torch, world, mlp, q, pl_ms, cf_plain, refine=True)
+    res["refine_variant"] = {"fallback": "flagged configurations take refine_steps plain steps "
+                                         "from q + f(q) instead of T from q",
+                             "at_equal_collision_free": re_, "sweep": rs}
+    if variant_nets:
+        res["variants"] = []
+        for name, fac, sched, hw, hth, vm, vl, vms in variant_nets:
+            vs, ve = amortised_frontier(P, K, torch, world, vm, q, pl_ms, cf_plain)
+            rvs, rve = amortised_frontier(P, K, torch, world, vm, q, pl_ms, cf_plain, refine=True)
+            res["variants"].append({"variant": name, "epochs": epochs * fac, "schedule": sched,
+                                    "hard_weight": hw, "hard_threshold": hth,
+                                    "train_s": vms / 1e3, "loss_last": float(vl[-1]),
+                                    "at_equal_collision_free": ve, "threshold_sweep": vs,
+                                    "refine_at_equal_collision_free": rve, "refine_sweep": rvs})
+    return res
 
 
 def main():
@@ -985,6 +1041,10 @@ def main():
                     "at equal collision-free fraction "
                     + (f"{eq['speedup']:.2f}x (threshold {eq['threshold']})" if eq
                        else "not reached"))
+                rq = am["refine_variant"]["at_equal_collision_free"]
+                log("refining variant at equal collision-free fraction: "
+                    + (f"{rq['speedup']:.2f}x (threshold {rq['threshold']}, "
+                       f"{rq['refine_steps']} steps)" if rq else "not reached"))
         except Exception as e:  # report what ran; the headline stands on its own
             wl["error"] = f"{type(e).__name__}: {e}"
         out["workloads"] = wl

@@ -359,6 +359,15 @@ int32_t pdmp_mlp_forward(const pdmp_mlp *mlp, const float *q, int64_t B, float *
 int32_t pdmp_mlp_backward(const pdmp_mlp *mlp, const float *q_hat, const float *target,
                           int64_t B, void *acts, float *grad, float *loss, void *ws,
                           size_t ws_bytes, void *stream);
+/* The same with per-sample weights, for training that emphasises hard samples:
+ * loss (1/(n_in B)) sum_b u_b |q_hat_b - target_b|^2 and its gradient, u_b = hard_weight
+ * where hard[b] != 0 and 1 elsewhere (hard: device uint8 [B], nullable = all 1, e.g.
+ * the flag of pdmp_arm_max_occupancy at q_hat).  hard_weight must be finite and >= 0
+ * (else PDMP_EINVAL); the workspace is pdmp_mlp_backward's. */
+int32_t pdmp_mlp_backward_weighted(const pdmp_mlp *mlp, const float *q_hat, const float *target,
+                                   int64_t B, const uint8_t *hard, float hard_weight, void *acts,
+                                   float *grad, float *loss, void *ws, size_t ws_bytes,
+                                   void *stream);
 
 /* Largest body-point occupancy of each configuration, max_p c(psi_p(q)) (maxc,
  * nullable, [n]) and flag = (max > thresh) (nullable, [n]).  FP32 kinematics. */
@@ -377,6 +386,16 @@ int32_t pdmp_amortised_morph(const pdmp_mlp *mlp, const pdmp_occupancy *occ, con
                              const float *q, float *out, int64_t n, int32_t T, float eta,
                              float thresh, uint8_t *flag, uint32_t *n_fallback, void *ws,
                              size_t ws_bytes, void *stream);
+/* The refining variant: a configuration whose q_hat is flagged takes T_refine plain
+ * joint-space steps (Sec. 3.2, Eq. 1 and 3) from q_hat instead of the T steps from q,
+ * so the plain morph repairs the network's output rather than replacing it (the
+ * result then differs from the plain morph's for those configurations).  Arguments,
+ * workspace and errors as pdmp_amortised_morph; T_refine = 0 returns q_hat. */
+int32_t pdmp_amortised_morph_refine(const pdmp_mlp *mlp, const pdmp_occupancy *occ,
+                                    const pdmp_arm *arm, const float *q, float *out, int64_t n,
+                                    int32_t T_refine, float eta, float thresh, uint8_t *flag,
+                                    uint32_t *n_fallback, void *ws, size_t ws_bytes,
+                                    void *stream);
 
 /* ---- the paper's occupancy network (Sec. 3.1): a fully connected network with
  * tanh activations between hidden layers and a sigmoid output, c(x) = sigma(s(x)),

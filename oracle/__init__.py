@@ -88,6 +88,9 @@ def _load():
         "orc_amortised_morph": (None, [C.c_int, _ip, _dp, C.c_int, C.c_int, _dp, C.c_int, _dp,
                                        _dp, C.c_double, C.c_double, _dp, _i64, C.c_int,
                                        C.c_double, C.c_double, _dp, _u8p, _dp]),
+        "orc_amortised_morph_refine": (None, [C.c_int, _ip, _dp, C.c_int, C.c_int, _dp, C.c_int,
+                                              _dp, _dp, C.c_double, C.c_double, _dp, _i64,
+                                              C.c_int, C.c_double, C.c_double, _dp, _u8p, _dp]),
         "orc_tanh_nparams": (C.c_int64, [C.c_int, C.c_int, C.c_int]),
         "orc_tanh_eval": (None, [C.c_int, C.c_int, C.c_int, _dp, _dp, _i64, _dp, _dp, _dp]),
         "orc_tanh_grad": (None, [C.c_int, C.c_int, C.c_int, _dp, _dp, _i64, _dp, _dp, _dp, _dp,
@@ -521,8 +524,10 @@ def mlp_loss_grad_weighted(widths, P, q, target, hard, hard_weight):
     return L, g
 
 
-def amortised_morph(widths, P, arm: Arm, occ: Occupancy, q, T, eta, thresh=0.5):
-    """(q_out, flag, max body-point occupancy at q_hat) of the amortised morph."""
+def amortised_morph(widths, P, arm: Arm, occ: Occupancy, q, T, eta, thresh=0.5,
+                    refine: bool = False):
+    """(q_out, flag, max body-point occupancy at q_hat) of the amortised morph; with
+    refine, flagged configurations take the T plain steps from q_hat instead of q."""
     wd = _widths(widths)
     q = _d(q)
     n = q.shape[1]
@@ -530,9 +535,9 @@ def amortised_morph(widths, P, arm: Arm, occ: Occupancy, q, T, eta, thresh=0.5):
     flag = np.zeros(n, np.uint8)
     maxc = _zeros(n)
     _, M, h, w, beta, ell = occ.args()
-    _load().orc_amortised_morph(wd.size - 1, _P(wd, _ip), _P(_d(P)), arm.ndof, arm.ppl,
-                                _P(arm.dh()), M, h, w, beta, ell, _P(q), n, int(T),
-                                float(eta), float(thresh), _P(out), _P(flag, _u8p), _P(maxc))
+    fn = _load().orc_amortised_morph_refine if refine else _load().orc_amortised_morph
+    fn(wd.size - 1, _P(wd, _ip), _P(_d(P)), arm.ndof, arm.ppl, _P(arm.dh()), M, h, w, beta, ell,
+       _P(q), n, int(T), float(eta), float(thresh), _P(out), _P(flag, _u8p), _P(maxc))
     return out, flag, maxc
 
 

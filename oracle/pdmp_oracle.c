@@ -999,10 +999,13 @@ double orc_mlp_loss_grad_weighted(int L, const int *widths, const double *P, con
 /* occupancy at q_hat exceeds `thresh` takes the plain morph from q instead.  */
 /* ------------------------------------------------------------------------- */
 
-void orc_amortised_morph(int L, const int *widths, const double *P, int ndof, int ppl,
-                         const double *dh, int M, const double *h, const double *w, double beta,
-                         double ell, const double *q, int64_t n, int T, double eta,
-                         double thresh, double *qout, uint8_t *flag, double *maxc) {
+/* With from_qhat the fallback starts from q_hat instead of q (the refining variant:
+ * flagged configurations take T plain steps from the network's output). */
+static void amortised_morph(int L, const int *widths, const double *P, int ndof, int ppl,
+                            const double *dh, int M, const double *h, const double *w,
+                            double beta, double ell, const double *q, int64_t n, int T,
+                            double eta, double thresh, int from_qhat, double *qout,
+                            uint8_t *flag, double *maxc) {
     double *qh = (double *)malloc(sizeof(double) * (size_t)ndof * (size_t)(n > 0 ? n : 1));
     orc_mlp_forward(L, widths, P, q, n, 1, qh, NULL);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -1024,7 +1027,8 @@ void orc_amortised_morph(int L, const int *widths, const double *P, int ndof, in
         if (flag) flag[s] = (uint8_t)fb;
         if (fb) {
             double gq[ORC_MAX_DOF];
-            for (int j = 0; j < ndof; ++j) qs[j] = q[(int64_t)j * n + s];
+            if (!from_qhat)
+                for (int j = 0; j < ndof; ++j) qs[j] = q[(int64_t)j * n + s];
             for (int t = 0; t < T; ++t) {
                 arm_cost_grad1(ndof, ppl, dh, M, h, w, beta, ell, qs, 0, gq);
                 for (int j = 0; j < ndof; ++j) qs[j] = qs[j] - eta * gq[j];
@@ -1033,6 +1037,23 @@ void orc_amortised_morph(int L, const int *widths, const double *P, int ndof, in
         for (int j = 0; j < ndof; ++j) qout[(int64_t)j * n + s] = qs[j];
     }
     free(qh);
+}
+
+void orc_amortised_morph(int L, const int *widths, const double *P, int ndof, int ppl,
+                         const double *dh, int M, const double *h, const double *w, double beta,
+                         double ell, const double *q, int64_t n, int T, double eta,
+                         double thresh, double *qout, uint8_t *flag, double *maxc) {
+    amortised_morph(L, widths, P, ndof, ppl, dh, M, h, w, beta, ell, q, n, T, eta, thresh, 0, qout,
+                    flag, maxc);
+}
+
+void orc_amortised_morph_refine(int L, const int *widths, const double *P, int ndof, int ppl,
+                                const double *dh, int M, const double *h, const double *w,
+                                double beta, double ell, const double *q, int64_t n, int T,
+                                double eta, double thresh, double *qout, uint8_t *flag,
+                                double *maxc) {
+    amortised_morph(L, widths, P, ndof, ppl, dh, M, h, w, beta, ell, q, n, T, eta, thresh, 1, qout,
+                    flag, maxc);
 }
 
 /* ------------------------------------------------------------------------- */

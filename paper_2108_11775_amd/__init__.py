@@ -550,8 +550,10 @@ class Mlp:
         m = self.c_struct()
         return _workspace(lib.pdmp_mlp_acts_size(C.byref(m), int(B)), device)
 
-    def backward(self, q_hat, target, acts, grad=None, loss=None, ws=None):
-        """MSE loss and its parameter gradient (FP32 flat) from saved activations."""
+    def backward(self, q_hat, target, acts, grad=None, loss=None, ws=None, hard=None,
+                 hard_weight: float = 1.0):
+        """MSE loss and its parameter gradient (FP32 flat) from saved activations; with
+        hard (uint8 [B]) the samples it marks weigh hard_weight in the loss."""
         torch = _torch()
         lib = _lib.load()
         B = int(q_hat.shape[1])
@@ -562,10 +564,15 @@ class Mlp:
             loss = torch.empty(1, dtype=torch.float32, device=q_hat.device)
         if ws is None:
             ws = _workspace(lib.pdmp_mlp_workspace_size(C.byref(m), B), q_hat.device)
-        _lib.call("pdmp_mlp_backward", C.byref(m), _dev(q_hat, "q_hat", torch.float32),
-                  _dev(target, "target", torch.float32, tuple(q_hat.shape)), B, _dev(acts, "acts"),
-                  _dev(grad, "grad", torch.float32, (self.num_params,)), _dev(loss, "loss"),
-                  _dev(ws, "ws"), ws.numel(), _stream(q_hat.device))
+        args = (_dev(acts, "acts"), _dev(grad, "grad", torch.float32, (self.num_params,)),
+                _dev(loss, "loss"), _dev(ws, "ws"), ws.numel(), _stream(q_hat.device))
+        qh = _dev(q_hat, "q_hat", torch.float32)
+        tg = _dev(target, "target", torch.float32, tuple(q_hat.shape))
+        if hard is None:
+            _lib.call("pdmp_mlp_backward", C.byref(m), qh, tg, B, *args)
+        else:
+            _lib.call("pdmp_mlp_backward_weighted", C.byref(m), qh, tg, B,
+                      _dev(hard, "hard", torch.uint8, (B,)), float(hard_weight), *args)
         return loss, grad
 
 
@@ -583,8 +590,10 @@ def arm_max_occupancy(occ: Occupancy, arm: Arm, q, thresh: float = 0.5):
 
 
 def amortised_morph(mlp: Mlp, occ: Occupancy, arm: Arm, q, T: int, eta: float,
-                    thresh: float = 0.5, out=None, flag=None, n_fallback=None, ws=None):
-    """Amortised morph: q + f(q), plain-morph fallback where max occupancy > thresh.
+                    thresh: float = 0.5, out=None, flag=None, n_fallback=None, ws=None,
+                    refine: bool = False):
+    """Amortised morph: q + f(q), plain-morph fallback where max occupancy > thresh
+    (T steps from q; with refine, T steps from q + f(q)).
 
     Returns (out [n_dof][n], flag [n] uint8, n_fallback [1] int32 device).
     """
@@ -600,7 +609,8 @@ def amortised_morph(mlp: Mlp, occ: Occupancy, arm: Arm, q, T: int, eta: float,
         n_fallback = torch.zeros(1, dtype=torch.int32, device=q.device)
     if ws is None:
         ws = _workspace(lib.pdmp_amortised_workspace_size(C.byref(m), C.byref(a), n), q.device)
-    _lib.call("pdmp_amortised_morph", C.byref(m), C.byref(o), C.byref(a),
+    _lib.call("pdmp_amortised_morph_refine" if refine else "pdmp_amortised_morph", C.byref(m),
+              C.byref(o), C.byref(a),
               _dev(q, "q", torch.float32, (arm.n_dof, n)), _dev(out, "out", torch.float32, (arm.n_dof, n)),
               n, int(T), float(eta), float(thresh), _dev(flag, "flag", torch.uint8, (n,)),
               _dev(n_fallback, "n_fallback"), _dev(ws, "ws"), ws.numel(), _stream(q.device))

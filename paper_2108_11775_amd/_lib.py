@@ -154,11 +154,16 @@ SIGNATURES = {
     "pdmp_mlp_forward": (_i32, [_P(pdmp_mlp), _vp, _i64, _vp, _vp, _vp, C.c_size_t, _vp]),
     "pdmp_mlp_backward": (_i32, [_P(pdmp_mlp), _vp, _vp, _i64, _vp, _vp, _vp, _vp, C.c_size_t,
                                  _vp]),
+    "pdmp_mlp_backward_weighted": (_i32, [_P(pdmp_mlp), _vp, _vp, _i64, _vp, _f, _vp, _vp, _vp,
+                                          _vp, C.c_size_t, _vp]),
     "pdmp_arm_max_occupancy": (_i32, [_P(pdmp_occupancy), _P(pdmp_arm), _vp, _i64, _f, _vp, _vp,
                                       _vp]),
     "pdmp_amortised_workspace_size": (C.c_size_t, [_P(pdmp_mlp), _P(pdmp_arm), _i64]),
     "pdmp_amortised_morph": (_i32, [_P(pdmp_mlp), _P(pdmp_occupancy), _P(pdmp_arm), _vp, _vp, _i64,
                                     _i32, _f, _f, _vp, _vp, _vp, C.c_size_t, _vp]),
+    "pdmp_amortised_morph_refine": (_i32, [_P(pdmp_mlp), _P(pdmp_occupancy), _P(pdmp_arm), _vp,
+                                           _vp, _i64, _i32, _f, _f, _vp, _vp, _vp, C.c_size_t,
+                                           _vp]),
 }
 
 _lib = None

@@ -14,7 +14,7 @@ import time
 
 import torch
 
-from . import Arm, Mlp, Occupancy, adam_step, morph_samples, uniform_samples
+from . import Arm, Mlp, Occupancy, adam_step, arm_max_occupancy, morph_samples, uniform_samples
 
 
 def make_pairs(occ: Occupancy, arm: Arm, n_batches: int, batch: int, T: int, eta: float,
@@ -29,16 +29,25 @@ def make_pairs(occ: Occupancy, arm: Arm, n_batches: int, batch: int, T: int, eta
 
 
 def train(mlp: Mlp, pairs, epochs: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
-          log=None, schedule: str = "constant"):
+          log=None, schedule: str = "constant", hard_weight=None, occ: Occupancy = None,
+          arm: Arm = None, hard_thresh: float = 0.5, restarts: int = 4):
     """Adam on the MSE between q + f(q) and the plain-morph target.
 
-    schedule "cosine" anneals the step as lr * (1 + cos(pi t / steps)) / 2.
+    schedule "cosine" anneals the step as lr * (1 + cos(pi t / steps)) / 2;
+    "cosine_restarts" does so over each of `restarts` equal periods.  With hard_weight,
+    every step first checks the network's own outputs (pdmp_arm_max_occupancy on occ,
+    arm) and weighs the samples whose q + f(q) lands above hard_thresh by hard_weight.
     Returns the per-step loss as a device tensor [epochs * len(pairs)].
     """
     import math
+    if schedule not in ("constant", "cosine", "cosine_restarts"):
+        raise ValueError(f"unknown schedule {schedule!r}")
+    if hard_weight is not None and (occ is None or arm is None):
+        raise ValueError("hard_weight needs the occupancy and the arm")
     dev = mlp.params.device
     B = int(pairs[0][0].shape[1])
     steps = epochs * len(pairs)
+    period = max(1, steps // max(1, restarts))
     losses = torch.empty(steps, dtype=torch.float32, device=dev)
     m = torch.zeros_like(mlp.params)
     v = torch.zeros_like(mlp.params)
@@ -50,9 +59,18 @@ def train(mlp: Mlp, pairs, epochs: int, lr: float, beta1=0.9, beta2=0.999, eps=1
     for ep in range(epochs):
         for q, tgt in pairs:
             mlp.forward(q, acts=acts, out=qhat)
-            mlp.backward(qhat, tgt, acts, grad=grad, loss=losses[t:t + 1])
+            hard = None
+            if hard_weight is not None:
+                _, hard = arm_max_occupancy(occ, arm, qhat, hard_thresh)
+            mlp.backward(qhat, tgt, acts, grad=grad, loss=losses[t:t + 1], hard=hard,
+                         hard_weight=1.0 if hard_weight is None else hard_weight)
             t += 1
-            lr_t = lr if schedule == "constant" else 0.5 * lr * (1.0 + math.cos(math.pi * (t - 1) / steps))
+            if schedule == "constant":
+                lr_t = lr
+            elif schedule == "cosine":
+                lr_t = 0.5 * lr * (1.0 + math.cos(math.pi * (t - 1) / steps))
+            else:
+                lr_t = 0.5 * lr * (1.0 + math.cos(math.pi * ((t - 1) % period) / period))
             adam_step(mlp.params, grad, m, v, t, lr_t, beta1, beta2, eps)
             mlp.pack()
         if log is not None:

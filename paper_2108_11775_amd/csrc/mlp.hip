@@ -196,10 +196,12 @@ __global__ void k_f32_to_bf16(const float *__restrict__ x, int64_t n, uint16_t *
     if (t < n) y[t] = f32_to_bf16(x[t]);
 }
 
-// MSE: dF[b][k] = bf16(2 (q_hat - t) / (n_out B)), per-block sums of (q_hat - t)^2.
+// MSE: dF[b][k] = bf16(2 u_b (q_hat - t) / (n_out B)), per-block sums of
+// u_b (q_hat - t)^2, with sample weight u_b = hard_w where hard[b] != 0, else 1 (hard
+// NULL: the plain MSE).
 __global__ void __launch_bounds__(256)
 k_mse(const float *__restrict__ qhat, const float *__restrict__ tgt, int n_out, int64_t B,
-      float scale, uint16_t *dF, double *parts) {
+      float scale, const uint8_t *__restrict__ hard, float hard_w, uint16_t *dF, double *parts) {
     __shared__ double sh[256];
     const int64_t total = B * n_out;
     const int64_t per = (total + gridDim.x - 1) / gridDim.x;
@@ -212,8 +214,9 @@ k_mse(const float *__restrict__ qhat, const float *__restrict__ tgt, int n_out, 
         const int k = (int)(t - b * n_out);
         const int64_t o = (int64_t)k * B + b;
         const float e = qhat[o] - tgt[o];
-        acc += (double)e * (double)e;
-        dF[t] = f32_to_bf16(2.0f * scale * e);
+        const float u = (hard && hard[b]) ? hard_w : 1.0f;
+        acc += (double)u * ((double)e * (double)e);
+        dF[t] = f32_to_bf16(2.0f * scale * u * e);
     }
     sh[threadIdx.x] = acc;
     __syncthreads();
@@ -416,7 +419,8 @@ size_t mlp_bwd_ws_bytes(const pdmp_mlp &m, int64_t B) {
 // Backward of the MSE loss through the whole network from saved activations.
 // grad: FP32 [nparams] in the flat layout; loss (nullable): device [1].
 int32_t launch_mlp_backward(const pdmp_mlp &m, const float *qhat, const float *target, int64_t B,
-                            void *acts, float *grad, float *loss, void *ws, hipStream_t st) {
+                            void *acts, float *grad, float *loss, void *ws, hipStream_t st,
+                            const uint8_t *hard, float hard_w) {
     const MlpLayout ly = layout_of(m);
     ActPtrs ap = act_ptrs(ly, acts, B);
     const int S = wgrad_splits(B);
@@ -437,7 +441,7 @@ int32_t launch_mlp_backward(const pdmp_mlp &m, const float *qhat, const float *t
 
     const int nb = 1024;
     hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, qhat, target, ly.n_in, B,
-                       (float)(1.0 / ((double)ly.n_in * (double)B)), dz[0], rparts);
+                       (float)(1.0 / ((double)ly.n_in * (double)B)), hard, hard_w, dz[0], rparts);
     if (loss)
         hipLaunchKernelGGL(k_final_scaled, dim3(1), dim3(256), 0, st, rparts, nb,
                            1.0 / ((double)ly.n_in * (double)B), loss);

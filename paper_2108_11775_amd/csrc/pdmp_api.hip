@@ -643,6 +643,24 @@ int32_t pdmp_mlp_backward(const pdmp_mlp *mlp, const float *q_hat, const float *
     return launch_mlp_backward(*mlp, q_hat, target, B, acts, grad, loss, ws, (hipStream_t)stream);
 }
 
+int32_t pdmp_mlp_backward_weighted(const pdmp_mlp *mlp, const float *q_hat, const float *target,
+                                   int64_t B, const uint8_t *hard, float hard_weight, void *acts,
+                                   float *grad, float *loss, void *ws, size_t ws_bytes,
+                                   void *stream) {
+    int32_t st = check_mlp(mlp, true);
+    if (st) return st;
+    PDMP_REQUIRE(B >= 1 && B <= 0x7fffffff, "B out of range");
+    PDMP_REQUIRE(q_hat && target && acts && grad, "NULL argument");
+    PDMP_REQUIRE(hard_weight >= 0.0f && hard_weight < INFINITY, "hard_weight not finite and >= 0");
+    const size_t need = mlp_bwd_ws_bytes(*mlp, B);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+        return PDMP_ENOMEM;
+    }
+    return launch_mlp_backward(*mlp, q_hat, target, B, acts, grad, loss, ws, (hipStream_t)stream,
+                               hard, hard_weight);
+}
+
 int32_t pdmp_arm_max_occupancy(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *q,
                                int64_t n, float thresh, float *maxc, uint8_t *flag,
                                void *stream) {
@@ -677,10 +695,11 @@ size_t pdmp_amortised_workspace_size(const pdmp_mlp *mlp, const pdmp_arm *arm, i
            al256h((size_t)arm->n_dof * n * 4) /* compact batch */;
 }
 
-int32_t pdmp_amortised_morph(const pdmp_mlp *mlp, const pdmp_occupancy *occ, const pdmp_arm *arm,
-                             const float *q, float *out, int64_t n, int32_t T, float eta,
-                             float thresh, uint8_t *flag, uint32_t *n_fallback, void *ws,
-                             size_t ws_bytes, void *stream) {
+// from_qhat: the fallback gathers the flagged rows of q_hat (out) instead of q.
+static int32_t amortised_impl(const pdmp_mlp *mlp, const pdmp_occupancy *occ, const pdmp_arm *arm,
+                              const float *q, float *out, int64_t n, int32_t T, float eta,
+                              float thresh, uint8_t *flag, uint32_t *n_fallback, void *ws,
+                              size_t ws_bytes, void *stream, bool from_qhat) {
     int32_t st = check_mlp(mlp, true);
     if (st) return st;
     st = check_occ(occ);
@@ -728,7 +747,8 @@ int32_t pdmp_amortised_morph(const pdmp_mlp *mlp, const pdmp_occupancy *occ, con
         st = launch_arm_max_occ(*arm, occ->hinges, occ->weights, occ->n_hinges, kappa, out, n,
                                 thresh, nullptr, fl, s);
     if (st) return st;
-    if ((st = launch_compact(*arm, fl, q, n, counts, offs, total, idx, qc, s))) return st;
+    if ((st = launch_compact(*arm, fl, from_qhat ? out : q, n, counts, offs, total, idx, qc, s)))
+        return st;
     st = PDMP_EUNSUPPORTED;
     if (grid)
         st = launch_arm_grid3d(*arm, occ->hinges, occ->weights, occ->n_hinges, grid, kappa, gscale,
@@ -738,6 +758,23 @@ int32_t pdmp_amortised_morph(const pdmp_mlp *mlp, const pdmp_occupancy *occ, con
                               n, T, eta, total, s);
     if (st) return st;
     return launch_scatter(*arm, idx, total, qc, n, out, s);
+}
+
+int32_t pdmp_amortised_morph(const pdmp_mlp *mlp, const pdmp_occupancy *occ, const pdmp_arm *arm,
+                             const float *q, float *out, int64_t n, int32_t T, float eta,
+                             float thresh, uint8_t *flag, uint32_t *n_fallback, void *ws,
+                             size_t ws_bytes, void *stream) {
+    return amortised_impl(mlp, occ, arm, q, out, n, T, eta, thresh, flag, n_fallback, ws,
+                          ws_bytes, stream, false);
+}
+
+int32_t pdmp_amortised_morph_refine(const pdmp_mlp *mlp, const pdmp_occupancy *occ,
+                                    const pdmp_arm *arm, const float *q, float *out, int64_t n,
+                                    int32_t T_refine, float eta, float thresh, uint8_t *flag,
+                                    uint32_t *n_fallback, void *ws, size_t ws_bytes,
+                                    void *stream) {
+    return amortised_impl(mlp, occ, arm, q, out, n, T_refine, eta, thresh, flag, n_fallback, ws,
+                          ws_bytes, stream, true);
 }
 
 // ---- the tanh occupancy network ----

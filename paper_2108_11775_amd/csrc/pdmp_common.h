@@ -180,7 +180,8 @@ size_t mlp_bwd_ws_bytes(const pdmp_mlp &m, int64_t B);
 int32_t launch_mlp_forward(const pdmp_mlp &m, const float *q, int64_t B, float *qhat, void *acts,
                            void *ws, hipStream_t st);
 int32_t launch_mlp_backward(const pdmp_mlp &m, const float *qhat, const float *target, int64_t B,
-                            void *acts, float *grad, float *loss, void *ws, hipStream_t st);
+                            void *acts, float *grad, float *loss, void *ws, hipStream_t st,
+                            const uint8_t *hard = nullptr, float hard_w = 1.0f);
 int32_t launch_f32_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_t st);
 int32_t launch_fk_points(const pdmp_arm &arm, const float *q, int64_t n, float *pts,
                          hipStream_t st);

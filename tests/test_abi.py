@@ -54,6 +54,16 @@ def test_invalid_arguments_rejected_before_launch():
     assert lib.pdmp_morph_samples(C.byref(occ), C.byref(arm), None, None, 4, 3, 0.1, None) == E
     arm.n_dof = 9
     assert lib.pdmp_fk_body_points(C.byref(arm), None, 4, None, None) == E
+    # weighted MLP backward: the weight is checked on the host (the pointers below are
+    # never dereferenced: the call returns before any launch)
+    fake = C.c_void_p(256)
+    mlp = _lib.pdmp_mlp(7, 64, 2, fake, fake)
+    for bad in (-1.0, float("nan"), float("inf")):
+        assert lib.pdmp_mlp_backward_weighted(C.byref(mlp), fake, fake, 16, None, bad, fake,
+                                              fake, None, fake, 1 << 30, None) == E
+        assert b"hard_weight" in lib.pdmp_last_error()
+    assert lib.pdmp_mlp_backward_weighted(C.byref(mlp), fake, fake, 0, None, 2.0, fake, fake,
+                                          None, fake, 1 << 30, None) == E
     arm.n_dof, arm.pts_per_link = 7, 12
     occ3 = _lib.pdmp_occupancy(3, 8, 16, 16, 0.5)
     assert (lib.pdmp_morph_samples(C.byref(occ3), C.byref(arm), None, None, 4, 3, 0.1, None)

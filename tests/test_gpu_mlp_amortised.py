@@ -82,6 +82,38 @@ def test_mse_gradient_per_layer(widths, B):
             off += n_el
 
 
+def test_weighted_mse_gradient_matches_oracle():
+    """The sample-weighted MSE (hard samples weigh 4) against the oracle's, at the BF16
+    bar; no hard sample, or weight 1, gives the plain backward's bits."""
+    require_gpu()
+    widths, B = (7, 256, 256, 256, 7), 3000
+    layers = _net(widths, seed=7)
+    mlp = P.Mlp.from_layers(layers)
+    q = I.uniform_points(7, K.STREAM_EVAL, 7, B, -math.pi, math.pi)
+    t = q + 0.3 * I.rng(7, 13).normal(size=q.shape).astype(np.float32)
+    hard = (I.rng(7, 14).uniform(size=B) < 0.3).astype(np.uint8)
+    acts = mlp.acts_buffer(B)
+    qh = mlp.forward(dev(q), acts=acts)
+    loss, grad = mlp.backward(qh, dev(t), acts, hard=dev(hard), hard_weight=4.0)
+    grad = host(grad)
+    Pb = O.mlp_pack([(_bf16(W), b) for W, b in layers])
+    L, gref = O.mlp_loss_grad_weighted(widths, Pb, q, t, hard, 4.0)
+    assert abs(host(loss)[0] - L) <= 2e-2 * L
+    off = 0
+    for li in range(len(widths) - 1):
+        fi, fo = widths[li], widths[li + 1]
+        for n_el in (fi * fo, fo):
+            a, b = grad[off:off + n_el], gref[off:off + n_el]
+            assert np.linalg.norm(a - b) <= 2e-2 * np.linalg.norm(b) + 1e-12, (li, n_el)
+            off += n_el
+    l0, g0 = mlp.backward(qh, dev(t), acts)
+    l1, g1 = mlp.backward(qh, dev(t), acts, hard=dev(np.zeros(B, np.uint8)), hard_weight=4.0)
+    l2, g2 = mlp.backward(qh, dev(t), acts, hard=dev(hard), hard_weight=1.0)
+    g0, g1, g2 = host(g0), host(g1), host(g2)
+    assert np.array_equal(g0, g1) and np.array_equal(g0, g2)
+    assert host(l0)[0] == host(l1)[0] == host(l2)[0]
+
+
 def test_arm_max_occupancy_matches_oracle():
     require_gpu()
     sc = arm_scene()
@@ -248,3 +280,53 @@ def test_amortised_config5_grid_path_sampled():
     assert np.all(err <= 1e-5 * np.maximum(1, amp) * np.maximum(1, np.abs(ref[:, both]).max(axis=0)))
     keep = sure & (flag == 0)
     assert np.all(np.abs(out[:, keep] - ref[:, keep]) <= 2e-2 * (np.abs(ref[:, keep] - qs[:, keep]) + 0.05))
+
+
+def test_refining_variant_on_the_grid_path():
+    """The refining amortised morph (flagged configurations take T_refine plain steps
+    from q_hat) on the bench's path: 16^3 grid, 7-256-256-256-7 network, 65,536
+    configurations.  Unflagged outputs are q_hat's bits; flagged ones are the plain
+    grid morph of q_hat (same bits) and, sampled, the oracle's morph of the GPU's q_hat
+    within the arm tolerance; the flags agree with the oracle's occupancy at the GPU's
+    q_hat away from the threshold.  A zero network gives the plain-fallback amortised
+    morph's bits."""
+    require_gpu()
+    sc = arm_scene()
+    a, d, al, th = sc["dh"]
+    arm_o, arm_g = O.Arm(a, d, al, th, 8), P.Arm(a, d, al, th, 8)
+    widths = (7, 256, 256, 256, 7)
+    layers = _net(widths, seed=10)
+    layers[-1] = (layers[-1][0] * 0.05, layers[-1][1] * 0.05)
+    mlp = P.Mlp.from_layers(layers)
+    c3 = K.C3
+    n, Tr, thr = c3.n_samples, 8, 0.3
+    q = O.uniform_samples(I.philox_seed(c3.cfg_id), 12, [c3.q_lo] * 7, [c3.q_hi] * 7, n)
+    go = gpu_occ(sc["h"], sc["wb"], sc["ell"], (16, 16, 16))
+    q_d = dev(q)
+    out, flag, nf = P.amortised_morph(mlp, go, arm_g, q_d, Tr, c3.eta, thr, refine=True)
+    qh = mlp.forward(q_d)
+    polished = host(P.morph_samples(go, qh, Tr, c3.eta, arm=arm_g))
+    out, flag, qh = host(out), host(flag), host(qh)
+    P.sync()
+    fb = flag.astype(bool)
+    assert int(host(nf)[0]) == int(fb.sum()) and 0 < fb.sum() < n
+    assert np.array_equal(out[:, ~fb], qh[:, ~fb])
+    assert np.array_equal(out[:, fb], polished[:, fb])
+    idx = np.unique(np.r_[0, np.arange(1, n, 1600), n - 1])
+    oo = oracle_occ(sc["h"], sc["wb"], sc["ell"])
+    qhs = np.ascontiguousarray(qh[:, idx]).astype(np.float64)
+    pts = O.fk_points(arm_o, qhs)
+    maxc = np.array([O.occ_eval(oo, pts[:, :, s])[1].max() for s in range(idx.size)])
+    sure = np.abs(maxc - thr) > 1e-4
+    assert np.array_equal(flag[idx][sure], (maxc[sure] > thr).astype(np.uint8))
+    sel = idx[fb[idx]]
+    assert sel.size > 0
+    ref, amp, _ = O.morph_arm(arm_o, oo, np.ascontiguousarray(qh[:, sel]).astype(np.float64), Tr,
+                              c3.eta, diag=True)
+    err = np.abs(out[:, sel] - ref).max(axis=0)
+    assert np.all(err <= 1e-5 * np.maximum(1, amp) * np.maximum(1, np.abs(ref).max(axis=0)))
+    # a zero network: q_hat = q, so the refining variant is the plain-fallback one
+    zero = P.Mlp.from_layers(I.mlp_init(5, widths))
+    z1, f1, _ = P.amortised_morph(zero, go, arm_g, q_d, c3.T, c3.eta, 0.5)
+    z2, f2, _ = P.amortised_morph(zero, go, arm_g, q_d, c3.T, c3.eta, 0.5, refine=True)
+    assert np.array_equal(host(f1), host(f2)) and np.array_equal(host(z1), host(z2))

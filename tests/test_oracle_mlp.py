@@ -107,3 +107,32 @@ def test_weighted_mse_is_the_mse_over_duplicated_samples():
     L2, g2 = O.mlp_loss_grad_weighted(widths, P, q, t, hard, 1.0)
     assert L1 == L0 and L2 == L0
     assert np.array_equal(g1, g0) and np.array_equal(g2, g0)
+
+
+def test_refining_amortised_morph_pins():
+    """The refining variant (flagged configurations take the plain steps from q_hat):
+    with a zero network q_hat = q, so it is the plain-fallback amortised morph bit for
+    bit; with no steps it returns q_hat everywhere; and each flagged configuration's
+    result is the plain morph of its q_hat."""
+    rng = np.random.default_rng(12)
+    arm = O.Arm(rng.uniform(0.1, 0.4, 7), np.zeros(7), np.array(K.C3.alpha), np.zeros(7), 8)
+    h = rng.uniform(-1.2, 1.2, (3, 48))
+    occ = O.Occupancy(h, rng.normal(0, 3.0, 48), -0.5, 0.3)
+    widths = (7, 16, 16, 7)
+    q = rng.uniform(-math.pi, math.pi, (7, 24))
+    P0 = O.mlp_pack(I.mlp_init(5, widths))
+    a, fa, ma = O.amortised_morph(widths, P0, arm, occ, q, 5, 0.01, 0.5)
+    r, fr, mr = O.amortised_morph(widths, P0, arm, occ, q, 5, 0.01, 0.5, refine=True)
+    assert np.array_equal(a, r) and np.array_equal(fa, fr) and np.array_equal(ma, mr)
+    layers = I.mlp_init(6, widths, zero_last=False)
+    layers[-1] = (layers[-1][0] * 0.1, layers[-1][1] * 0.1)
+    P1 = O.mlp_pack(layers)
+    qh = O.mlp_forward(widths, P1, q)
+    r0, f0, _ = O.amortised_morph(widths, P1, arm, occ, q, 0, 0.01, 0.5, refine=True)
+    assert np.array_equal(r0, qh)
+    r5, f5, _ = O.amortised_morph(widths, P1, arm, occ, q, 5, 0.01, 0.5, refine=True)
+    assert np.array_equal(f5, f0) and 0 < f5.sum() < 24
+    fb = f5 == 1
+    np.testing.assert_array_equal(r5[:, ~fb], qh[:, ~fb])
+    ref = O.morph_arm(arm, occ, np.ascontiguousarray(qh[:, fb]), 5, 0.01)
+    np.testing.assert_allclose(r5[:, fb], ref, rtol=0, atol=1e-12)
