@@ -350,7 +350,11 @@ int32_t pdmp_mlp_pack(const pdmp_mlp *mlp, uint16_t *params_bf16, void *stream);
 size_t pdmp_mlp_acts_size(const pdmp_mlp *mlp, int64_t B);
 size_t pdmp_mlp_workspace_size(const pdmp_mlp *mlp, int64_t B);
 /* q_hat [n_in][B] = q + f(q) for q [n_in][B].  acts (nullable, device,
- * pdmp_mlp_acts_size bytes): keep the activations for pdmp_mlp_backward. */
+ * pdmp_mlp_acts_size bytes): keep the activations for pdmp_mlp_backward.  Without
+ * acts, a network of hidden width a multiple of 32 up to 256 and n_in <= 16 runs
+ * as one fused kernel (activations in registers, hidden weights staged in LDS; the
+ * workspace is then unused); other shapes, and training forwards, run layer by
+ * layer.  Both accumulate in FP32 from BF16 weights and activations. */
 int32_t pdmp_mlp_forward(const pdmp_mlp *mlp, const float *q, int64_t B, float *q_hat, void *acts,
                          void *ws, size_t ws_bytes, void *stream);
 /* MSE loss (1/(n_in B)) sum |q_hat - target|^2 (loss, nullable, device [1]) and its

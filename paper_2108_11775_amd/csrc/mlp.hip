@@ -287,6 +287,163 @@ k_colsum_partial(const uint16_t *__restrict__ x, int64_t B, int N, int64_t rows_
         part[(int64_t)blockIdx.y * N + col] = ((sh[0][cl] + sh[1][cl]) + sh[2][cl]) + sh[3][cl];
 }
 
+// ------------------------------------------------- fused inference forward ---
+//
+// The inference forward of the whole network in one kernel: a block of four waves
+// takes 128 samples through every layer, each wave its own 32, with the activations
+// in registers.  A layer is C = W H^T on v_mfma_f32_32x32x16_bf16 (A = W rows, B =
+// the samples' activations, k = input feature), so a wave's output tiles leave lane
+// l holding features o = 32t + 8(v/4) + 4(l/32) + v%4 of sample l%32.  The next
+// layer takes them as its B operand where they lie: its k-step s reads slot
+// (s, l/32, j) as feature pi(16s + 8(l/32) + j) = 16s + 8(j/4) + 4(l/32) + j%4, which
+// is accumulator value v = 8(s%2) + j of tile s/2, and its A operand reads W's
+// columns in the same permuted order -- a permutation of the contraction index, so
+// the sum is the same.  Every layer's BF16 weights are staged per block in LDS (rows
+// padded against bank conflicts; a hidden layer of more than 4 tiles in two passes of
+// output tiles, so that two blocks share a CU and one stages while the other
+// computes).  Numerics as the layered path: BF16 inputs
+// and activations, FP32 accumulation, bias, SiLU and residual in FP32.
+constexpr int kMlpFB = 256;  // 4 waves, 128 samples; two blocks per CU
+
+// Slot of column x (0..15) of a 16-column block in the A fragments: lane half h reads
+// slots 8h .. 8h + 7, which must hold columns pi(8h + j) = 8(j/4) + 4h + j%4, so the
+// block's quads (4 columns) sit in the order 0, 2, 1, 3.
+__device__ __forceinline__ int mlp_slot(int x) { return ((x >> 2) & 1) * 8 + (x >> 3) * 4 + (x & 3); }
+
+template <int TH>
+__global__ void __launch_bounds__(kMlpFB) __attribute__((amdgpu_waves_per_eu(2)))
+k_mlp_fused(const uint16_t *__restrict__ wbf, const float *__restrict__ par, int n_in, int L,
+            const float *__restrict__ q, int64_t B, float *__restrict__ qhat) {
+    constexpr int H = 32 * TH, KH = 2 * TH, LROW = H + 8;
+    // hidden layers in passes of TP output tiles, so that two blocks fit in a CU's LDS
+    constexpr int TP = TH > 4 ? (TH + 1) / 2 : TH;
+    constexpr int WROWS = 32 * TP > 16 ? 32 * TP : 16;
+    static_assert(WROWS * LROW >= 16 * H, "room for the first layer's weights");
+    __shared__ __attribute__((aligned(16))) uint16_t Ws[WROWS * LROW];
+    __shared__ __attribute__((aligned(16))) float bs[H];  // the layer's bias
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6, hh = lane >> 5, r = lane & 31;
+    const int64_t n = (int64_t)blockIdx.x * (kMlpFB / 2) + wv * 32 + r;
+    const bool live = n < B;
+    // layout offsets (as the host's): layer 0 [H][n_in] + H, hidden [H][H] + H, last
+    // [n_in][H] + n_in
+    const int64_t w1 = (int64_t)H * n_in + H;
+    auto woff = [&](int l) -> int64_t {
+        return l == 0 ? 0 : w1 + (int64_t)(l - 1) * ((int64_t)H * H + H);
+    };
+    auto boff = [&](int l) -> int64_t {
+        return woff(l) + (l == 0 ? (int64_t)H * n_in : (l == L - 1 ? (int64_t)n_in * H : (int64_t)H * H));
+    };
+    auto frag = [&](int row, int sk) {  // the A fragment of row, k-step sk, this lane's half
+        bf16x8_t a;
+        const uint4 w4 = *reinterpret_cast<const uint4 *>(&Ws[row * LROW + 16 * sk + 8 * hh]);
+        __builtin_memcpy(&a, &w4, 16);
+        return a;
+    };
+    // layer 0: W_0 [H][n_in] into rows of 16 (zero past n_in), k = column directly
+    for (int e = tid; e < H * 16; e += kMlpFB) {
+        const int row = e >> 4, c = e & 15;
+        Ws[row * 16 + c] = c < n_in ? wbf[(int64_t)row * n_in + c] : (uint16_t)0;
+    }
+    for (int e = tid; e < H; e += kMlpFB) bs[e] = par[boff(0) + e];
+    // its B operand: bf16(q[8hh + j][n]), zero past n_in
+    bf16x8_t b0;
+    {
+        uint16_t u[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int f = 8 * hh + j;
+            u[j] = (live && f < n_in) ? f32_to_bf16(q[(int64_t)f * B + n]) : (uint16_t)0;
+        }
+        __builtin_memcpy(&b0, u, 16);
+    }
+    __syncthreads();
+    floatx16_t acc[TH];
+#pragma unroll
+    for (int t = 0; t < TH; ++t) {
+        bf16x8_t a;
+        const uint4 w4 = *reinterpret_cast<const uint4 *>(&Ws[(32 * t + r) * 16 + 8 * hh]);
+        __builtin_memcpy(&a, &w4, 16);
+        floatx16_t z = {};
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, z, 0, 0, 0);
+    }
+    bf16x8_t hb[KH];
+    // bias (from bs) + SiLU, into the next layer's B operands (slot j of k-step
+    // 2t + v/8 = v%8); biases o .. o + 3 of a quad are one 16-byte LDS read
+    auto epilogue = [&]() {
+#pragma unroll
+        for (int t = 0; t < TH; ++t)
+#pragma unroll
+            for (int u8 = 0; u8 < 2; ++u8) {
+                uint16_t u[8];
+#pragma unroll
+                for (int g = 0; g < 2; ++g) {
+                    const int v0 = 8 * u8 + 4 * g;
+                    const float4 b4 =
+                        *reinterpret_cast<const float4 *>(&bs[32 * t + 8 * (v0 >> 2) + 4 * hh]);
+                    const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        u[4 * g + i] = f32_to_bf16(silu_f(acc[t][v0 + i] + bb[i]));
+                }
+                __builtin_memcpy(&hb[2 * t + u8], u, 16);
+            }
+    };
+    epilogue();
+    // stage rows [0, rows) of a row-major [rows][H] weight matrix with each 16-column
+    // block's quads in fragment order (8-byte moves)
+    auto stage = [&](const uint16_t *__restrict__ W, int rows, const float *__restrict__ bias) {
+        __syncthreads();  // every wave is done with the previous contents
+        if (bias)
+            for (int e = tid; e < H; e += kMlpFB) bs[e] = bias[e];
+        const int nq = rows * (H / 4);
+#pragma unroll 8
+        for (int e = tid; e < nq; e += kMlpFB) {
+            const int row = e / (H / 4), q4 = e - row * (H / 4);
+            const int col = 4 * q4;
+            const uint2 v = *reinterpret_cast<const uint2 *>(W + (int64_t)row * H + col);
+            *reinterpret_cast<uint2 *>(&Ws[row * LROW + (col & ~15) + mlp_slot(col & 15)]) = v;
+        }
+        __syncthreads();
+    };
+    for (int l = 1; l < L - 1; ++l) {
+#pragma unroll
+        for (int t = 0; t < TH; ++t)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[t][v] = 0.0f;
+#pragma unroll
+        for (int t0 = 0; t0 < TH; t0 += TP) {
+            const int nt = TH - t0 < TP ? TH - t0 : TP;
+            stage(wbf + woff(l) + (int64_t)32 * t0 * H, 32 * nt, t0 == 0 ? par + boff(l) : nullptr);
+#pragma unroll
+            for (int sk = 0; sk < KH; ++sk)
+#pragma unroll
+                for (int t = t0; t < t0 + TP && t < TH; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        frag(32 * (t - t0) + r, sk), hb[sk], acc[t], 0, 0, 0);
+        }
+        epilogue();
+    }
+    // last layer: W_L [n_in][H] (rows past n_in read as zero)
+    stage(wbf + woff(L - 1), n_in, nullptr);
+    floatx16_t out = {};
+    const bf16x8_t zero8 = {};
+#pragma unroll
+    for (int sk = 0; sk < KH; ++sk)
+        out = __builtin_amdgcn_mfma_f32_32x32x16_bf16(r < n_in ? frag(r, sk) : zero8, hb[sk], out,
+                                                      0, 0, 0);
+    if (!live) return;
+    const float *bL = par + boff(L - 1);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int f = 8 * (v >> 2) + 4 * hh + (v & 3);
+        if (f < n_in) {
+            const int64_t o = (int64_t)f * B + n;
+            qhat[o] = q[o] + (out[v] + bL[f]);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host ---
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -346,6 +503,22 @@ size_t mlp_fwd_ws_bytes(const pdmp_mlp &m, int64_t B) {
 int32_t launch_mlp_forward(const pdmp_mlp &m, const float *q, int64_t B, float *qhat, void *acts,
                            void *ws, hipStream_t st) {
     const MlpLayout ly = layout_of(m);
+    if (!acts && ly.H % 32 == 0 && ly.H <= 256 && ly.n_in <= 16 && ly.L >= 2 &&
+        ((uintptr_t)m.params_bf16 & 15) == 0) {
+        // inference only: the fused kernel (no workspace used)
+        const dim3 grid((unsigned)((B + kMlpFB / 2 - 1) / (kMlpFB / 2)));
+        switch (ly.H / 32) {
+#define PDMP_FUSED(TH)                                                                          \
+    case TH:                                                                                    \
+        hipLaunchKernelGGL(k_mlp_fused<TH>, grid, dim3(kMlpFB), 0, st, m.params_bf16, m.params, \
+                           ly.n_in, ly.L, q, B, qhat);                                          \
+        break;
+            PDMP_FUSED(1) PDMP_FUSED(2) PDMP_FUSED(3) PDMP_FUSED(4)
+            PDMP_FUSED(5) PDMP_FUSED(6) PDMP_FUSED(7) PDMP_FUSED(8)
+#undef PDMP_FUSED
+        }
+        return check_launch("k_mlp_fused");
+    }
     uint16_t *h0, *hb[2];
     float *zs[8] = {nullptr};
     uint16_t *hs[8] = {nullptr};
