@@ -134,6 +134,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--settle-s", type=float, default=0.5,
+                   help="seconds of untimed headline steps before the warm-up steps, so that "
+                        "the GPU clocks have left their idle state")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=1 << 17,
                    help="prior samples the FP64 oracle morphs for the CPU baseline")
@@ -351,10 +354,19 @@ def headline(args, P, I, K, torch, dev):
             s_.__exit__()
             sev.append(s_)
 
+    # clocks: the GPU leaves its idle state over some hundred milliseconds of work, so
+    # untimed steps run for args.settle_s before the warm-up steps (not counted as steps)
+    t_settle = time.perf_counter()
+    n_settle = 0
+    while time.perf_counter() - t_settle < args.settle_s:
+        step(2000 + n_settle % 16, False)
+        torch.cuda.synchronize()
+        n_settle += 1
     for i in range(args.warmup):
         step(1000 + i, False)
     torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps)")
+    log(f"clock settling: {n_settle} untimed steps in {args.settle_s:.2f} s; "
+        f"warmup done ({args.warmup} steps)")
     tt = Timer(torch)
     with tt:
         for i in range(args.steps):
@@ -981,6 +993,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "clock_settle_s": args.settle_s,
         "ms_per_step": hl["ms_step"],
         "ms_per_step_median": hl["step_median"],
         "higher_is_better": True,

@@ -323,29 +323,40 @@ k_grid2d_sorted(const float *__restrict__ hinges, const float *__restrict__ weig
         // bounds of each 8-row group past which its ey_b vanish (a group of padding
         // rows only is never needed: its weights are zero)
         // (wave-uniform, in scalar registers)
+        // (wave-uniform, in scalar registers): one coordinate per lane, reduced over its
+        // k-step's 16 lanes and its group's 8 lanes
         float klo[KS], khi[KS], ga[4 * TB], gb[4 * TB];
+        const bool xin = lane < g0, yin = lane < g1;  // g0 <= 16 KS, g1 <= 32 TB
+        const float gx = gxs[min(lane, 16 * KS - 1)], gy = gys[min(lane, 32 * TB - 1)];
+        float xlo = xin ? gx : INFINITY, xhi = xin ? gx : -INFINITY;
+        float ylo = yin ? gy : INFINITY, yhi = yin ? gy : -INFINITY;
+        float ymag = yin ? fabsf(gy) : 0.0f;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            if (off < 16) {
+                xlo = fminf(xlo, __shfl_xor(xlo, off, 64));
+                xhi = fmaxf(xhi, __shfl_xor(xhi, off, 64));
+            }
+            if (off < 8) {
+                ylo = fminf(ylo, __shfl_xor(ylo, off, 64));
+                yhi = fmaxf(yhi, __shfl_xor(yhi, off, 64));
+            }
+            ymag = fmaxf(ymag, __shfl_xor(ymag, off, 64));
+        }
+        auto lane_f = [](float v, int l) {
+            return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+        };
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            float lo = INFINITY, hi = -INFINITY;
-            for (int a = 16 * ks; a < 16 * ks + 16 && a < g0; ++a) {
-                lo = fminf(lo, gxs[a]);
-                hi = fmaxf(hi, gxs[a]);
-            }
-            klo[ks] = uniform_f(lo);
-            khi[ks] = uniform_f(hi);
+            klo[ks] = lane_f(xlo, 16 * ks);
+            khi[ks] = lane_f(xhi, 16 * ks);
         }
-        float gmag = 0.0f;
 #pragma unroll
         for (int g = 0; g < 4 * TB; ++g) {
-            float lo = INFINITY, hi = -INFINITY;
-            for (int b = 8 * g; b < 8 * g + 8 && b < g1; ++b) {
-                lo = fminf(lo, gys[b]);
-                hi = fmaxf(hi, gys[b]);
-                gmag = fmaxf(gmag, fabsf(gys[b]));
-            }
-            ga[g] = uniform_f(lo - kYReach);
-            gb[g] = uniform_f(hi + kYReach);
+            ga[g] = lane_f(ylo, 8 * g) - kYReach;
+            gb[g] = lane_f(yhi, 8 * g) + kYReach;
         }
+        const float gmag = lane_f(ymag, 0);
         const uint32_t all_groups = (1u << (4 * TB)) - 1u;
         const bool group_test = gmag < 0x1p20f;
         for (int st = 0; st < T; ++st) {
