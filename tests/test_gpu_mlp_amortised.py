@@ -330,3 +330,48 @@ def test_refining_variant_on_the_grid_path():
     z1, f1, _ = P.amortised_morph(zero, go, arm_g, q_d, c3.T, c3.eta, 0.5)
     z2, f2, _ = P.amortised_morph(zero, go, arm_g, q_d, c3.T, c3.eta, 0.5, refine=True)
     assert np.array_equal(host(f1), host(f2)) and np.array_equal(host(z1), host(z2))
+
+
+def test_amortised_trained_network_grid_path_sampled():
+    """A network trained by the library itself (plain-morph pairs on the 16^3 grid path,
+    Adam through the BF16 forward/backward kernels) in the amortised morph on the grid
+    path, 65,536 configurations, every 1,600th against the oracle's amortised morph
+    with the same (BF16-rounded) weights: the trained f(q) is far from zero, so the
+    BF16 bar on the network's output and the flags are tested where they matter."""
+    from paper_2108_11775_amd import amortise
+    require_gpu()
+    sc = arm_scene()
+    a, d, al, th = sc["dh"]
+    arm_o, arm_g = O.Arm(a, d, al, th, 8), P.Arm(a, d, al, th, 8)
+    c3, c5 = K.C3, K.C5
+    go = gpu_occ(sc["h"], sc["wb"], sc["ell"], (16, 16, 16))
+    pairs = amortise.make_pairs(go, arm_g, 4, 8192, c3.T, c3.eta, I.philox_seed(c5.cfg_id, 77),
+                                c3.q_lo, c3.q_hi)
+    mlp = P.Mlp.from_layers(I.mlp_init(c5.cfg_id, c5.widths))
+    losses = host(amortise.train(mlp, pairs, 40, 3e-3, schedule="cosine"))
+    assert losses[-1] < 0.9 * losses[0]  # from f = 0 (MSE 0.06) towards the targets
+    n = c3.n_samples
+    q = O.uniform_samples(I.philox_seed(c3.cfg_id), 13, [c3.q_lo] * 7, [c3.q_hi] * 7, n)
+    out, flag, nf = P.amortised_morph(mlp, go, arm_g, dev(q), c3.T, c3.eta)
+    out, flag = host(out), host(flag)
+    idx = np.unique(np.r_[0, np.arange(1, n, 1600), n - 1])
+    out, flag, qs = out[:, idx], flag[idx], np.ascontiguousarray(q[:, idx])
+    layers = O.mlp_unpack(host(mlp.params).astype(np.float64), c5.widths)
+    Pb = O.mlp_pack([(_bf16(W), b) for W, b in layers])
+    oo = oracle_occ(sc["h"], sc["wb"], sc["ell"])
+    ref, fref, maxc = O.amortised_morph(c5.widths, Pb, arm_o, oo, qs, c3.T, c3.eta)
+    fq, fs = O.mlp_forward(c5.widths, Pb, qs, residual=False, with_scale=True)
+    assert np.abs(fq).max() > 0.1  # a trained, non-trivial correction
+    sure = np.abs(maxc - 0.5) > 2e-2
+    assert sure.sum() >= 0.8 * idx.size
+    assert np.array_equal(flag[sure], fref[sure])
+    both = sure & (flag == 1)
+    assert both.any() and (sure & (flag == 0)).any()
+    _, amp, _ = O.morph_arm(arm_o, oo, qs[:, both], c3.T, c3.eta, diag=True)
+    err = np.abs(out[:, both] - ref[:, both]).max(axis=0)
+    assert np.all(err <= 1e-5 * np.maximum(1, amp) * np.maximum(1, np.abs(ref[:, both]).max(axis=0)))
+    # kept configurations: q + f(q), f at the BF16 bar of the forward tests (relative to
+    # |f| + F_abs, F_abs = sum |W_L| |h| + |b_L|), plus the rounding of q + f in FP32
+    keep = sure & (flag == 0)
+    bound = 2e-2 * (np.abs(fq[:, keep]) + fs[:, keep]) + 2.0 ** -22 * np.abs(qs[:, keep])
+    assert np.all(np.abs(out[:, keep] - ref[:, keep]) <= bound)
