@@ -385,30 +385,31 @@ k_grid2d_sorted(const float *__restrict__ hinges, const float *__restrict__ weig
             f32x16_t U[TB], V[TB];
             int ln = lane;  // opaque: keeps the fragment reads inside the step loop
             asm volatile("" : "+v"(ln));
-            f16x8_t e[2], de[2];
-            if (km) h3_operands(gxs, xs, (float)c, __builtin_ctz(km), half, e, de);
-            bool first = true;
+            // the kept k-steps in order, j-th kept one in operand buffer j % 2: its
+            // successor's operands are formed while its products run, and the first
+            // starts the accumulators from the zero constant
+            f16x8_t eb[2][2], db[2][2];
+            uint32_t rem = km;
+            int ksn = rem ? __builtin_ctz(rem) : 0;
+            if (rem) h3_operands(gxs, xs, (float)c, ksn, half, eb[0], db[0]);
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                if (!((km >> ks) & 1u)) continue;
-                f16x8_t ec[2] = {e[0], e[1]}, dc[2] = {de[0], de[1]};
-                const uint32_t rest = km & ~((2u << ks) - 1u);
-                if (rest) h3_operands(gxs, xs, (float)c, __builtin_ctz(rest), half, e, de);
+            for (int j = 0; j < KS; ++j) {
+                if (!rem) break;
+                const int ks = ksn;
+                rem &= rem - 1u;
+                if (rem) {
+                    ksn = __builtin_ctz(rem);
+                    h3_operands(gxs, xs, (float)c, ksn, half, eb[(j + 1) & 1], db[(j + 1) & 1]);
+                }
 #pragma unroll
                 for (int t = 0; t < TB; ++t) {
                     if (!((tm >> t) & 1u)) continue;
                     const f16x8_t a1 = frag[(0 * KS + ks) * TB * 64 + t * 64 + ln];
                     const f16x8_t a2 = frag[(1 * KS + ks) * TB * 64 + t * 64 + ln];
-                    if (first) {
-                        const f32x16_t zero = {};
-                        U[t] = mfma_h3(a1, a2, ec[0], ec[1], zero);
-                        V[t] = mfma_h3(a1, a2, dc[0], dc[1], zero);
-                    } else {
-                        U[t] = mfma_h3(a1, a2, ec[0], ec[1], U[t]);
-                        V[t] = mfma_h3(a1, a2, dc[0], dc[1], V[t]);
-                    }
+                    const f32x16_t zero = {};
+                    U[t] = mfma_h3(a1, a2, eb[j & 1][0], eb[j & 1][1], j == 0 ? zero : U[t]);
+                    V[t] = mfma_h3(a1, a2, db[j & 1][0], db[j & 1][1], j == 0 ? zero : V[t]);
                 }
-                first = false;
             }
             s = 0.0f;
             sx = 0.0f;
