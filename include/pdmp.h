@@ -158,14 +158,17 @@ int32_t pdmp_occupancy_grad(const pdmp_occupancy *occ, const float *x, int64_t n
 int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,
                            float *out, int64_t n, int32_t T, float eta, void *stream);
 
-/* The same morph with a caller workspace (pdmp_morph_workspace_size bytes; 0 means the
- * call needs none and ws is ignored).  A large batch (n >= 2^17, T >= 1) on a 2-D hinge
- * grid of at most 64 x 64 is first ordered by a counting sort into 32 x 32 cells over
- * the hinge range, so that the samples of a wave lie close together; each step then
- * skips, wave by wave, the parts of the factorised sums that are exact zeros for all
- * of the wave's samples (hinge blocks whose FP16 operands underflow to zero, row tiles
- * whose y features underflow in FP32).  Every sample gets the same bits as from
- * pdmp_morph_samples.  PDMP_ENOMEM if ws is short; in == out allowed. */
+/* The same morph with a caller workspace (pdmp_morph_workspace_size bytes: 32 KiB of
+ * cell counters and 4 bytes per sample; 0 means the call needs none and ws is
+ * ignored).  A large batch (2^17 <= n < 2^32, T >= 1) on a 2-D hinge grid of at most
+ * 64 x 64 is first ordered by a counting sort into 32 x 32 cells over the hinge range,
+ * each eighth of the batch on its own (it is then read and written from one XCD), so
+ * that the samples of a wave lie close together; each step then skips, wave by wave,
+ * the parts of the factorised sums that are exact zeros for all of the wave's samples
+ * (16-hinge blocks whose FP16 operands underflow to zero, 8-row groups whose y
+ * features underflow in FP32).  Every sample gets the same bits as from
+ * pdmp_morph_samples.  PDMP_ENOMEM if ws is short; in == out allowed; calls that share
+ * a workspace must not overlap. */
 size_t pdmp_morph_workspace_size(const pdmp_occupancy *occ, const pdmp_arm *arm, int64_t n,
                                  int32_t T);
 int32_t pdmp_morph_samples_ws(const pdmp_occupancy *occ, const pdmp_arm *arm, const float *in,
