@@ -310,40 +310,6 @@ k_grid3d_ws(const float *__restrict__ hinges, const float *__restrict__ weights,
                                         eta, c_out, s_out, g_out, x_out, tr);
 }
 
-// FP32 DH chain (same convention as the pairwise arm kernel); sa, ca: the sine and
-// cosine of the constant link twists, taken once per kernel.
-template <int NDOF>
-__device__ __forceinline__ void g3_chain(const pdmp_arm &arm, const float (&sa_)[NDOF],
-                                         const float (&ca_)[NDOF], const float (&q)[NDOF],
-                                         float (&o)[NDOF + 1][3], float (&z)[NDOF][3]) {
-    float R[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-    o[0][0] = o[0][1] = o[0][2] = 0.0f;
-#pragma unroll
-    for (int i = 0; i < NDOF; ++i) {
-        z[i][0] = R[0][2];
-        z[i][1] = R[1][2];
-        z[i][2] = R[2][2];
-        float st, ct;
-        sincosf(arm.theta0[i] + q[i], &st, &ct);
-        const float sa = sa_[i], ca = ca_[i];
-        const float a = arm.a[i], d = arm.d[i];
-        const float lx = a * ct, ly = a * st;
-#pragma unroll
-        for (int r = 0; r < 3; ++r) o[i + 1][r] = o[i][r] + R[r][0] * lx + R[r][1] * ly + R[r][2] * d;
-        float N[3][3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            N[r][0] = R[r][0] * ct + R[r][1] * st;
-            N[r][1] = -R[r][0] * st * ca + R[r][1] * ct * ca + R[r][2] * sa;
-            N[r][2] = R[r][0] * st * sa - R[r][1] * ct * sa + R[r][2] * ca;
-        }
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) R[r][c] = N[r][c];
-    }
-}
-
 // Sum over the 8 lanes of a group (lanes 8g..8g+7), the same value in each: two
 // quad exchanges and the half-row mirror, all DPP moves (the order of the pairwise
 // sums is that of xor-1, xor-2, xor-4 exchanges).
@@ -357,6 +323,71 @@ __device__ __forceinline__ float sum8(float v) {
     v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
     v += dpp_mov<0x141>(v);  // row_half_mirror
     return v;
+}
+
+// The DH chain of one configuration by its 8 lanes: lane k = lane % 8 < NDOF forms link
+// k's transform A_k (rotation Rz(theta0_k + q_k) Rx(alpha_k), translation (a_k cos,
+// a_k sin, d_k) in frame k), and an inclusive scan composes them, P_k = A_0 ... A_k, in
+// three rounds (lane k takes P from lane k - r by a DPP row shift and composes
+// P <- P_{k-r} o P when k >= r, r = 1, 2, 4; lanes k >= NDOF carry the identity).  Lane
+// k ends with frame k + 1: origin o_{k+1} = P_k's translation, axis z_{k+1} = the third
+// column of its rotation.  lk: per link a, d, theta0, sin alpha, cos alpha (LDS).
+template <int NDOF, int CTRL>
+__device__ __forceinline__ void chain_round(int k, float (&R)[3][3], float (&t)[3]) {
+    constexpr int r = CTRL & 15;
+    float Rl[3][3], tl[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        tl[a] = dpp_mov<CTRL>(t[a]);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Rl[a][b] = dpp_mov<CTRL>(R[a][b]);
+    }
+    if (k >= r) {
+        float Rn[3][3], tn[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            tn[a] = tl[a] + Rl[a][0] * t[0] + Rl[a][1] * t[1] + Rl[a][2] * t[2];
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                Rn[a][b] = Rl[a][0] * R[0][b] + Rl[a][1] * R[1][b] + Rl[a][2] * R[2][b];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            t[a] = tn[a];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) R[a][b] = Rn[a][b];
+        }
+    }
+}
+
+template <int NDOF>
+__device__ __forceinline__ void g3_chain_scan(const float *lk, const float (&q)[NDOF], int k,
+                                              float (&R)[3][3], float (&t)[3]) {
+    static_assert(NDOF <= 8, "one lane per link");
+    float qk = q[0];
+#pragma unroll
+    for (int j = 1; j < NDOF; ++j) qk = k == j ? q[j] : qk;
+    const bool act = k < NDOF;
+    const float *p = lk + 5 * (act ? k : 0);
+    const float a = p[0], d = p[1], sa = p[3], ca = p[4];
+    float st, ct;
+    sincosf(p[2] + qk, &st, &ct);
+    if (act) {
+        R[0][0] = ct, R[0][1] = -st * ca, R[0][2] = st * sa;
+        R[1][0] = st, R[1][1] = ct * ca, R[1][2] = -ct * sa;
+        R[2][0] = 0.0f, R[2][1] = sa, R[2][2] = ca;
+        t[0] = a * ct, t[1] = a * st, t[2] = d;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            t[i] = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) R[i][j] = i == j ? 1.0f : 0.0f;
+        }
+    }
+    chain_round<NDOF, 0x111>(k, R, t);  // row_shr:1
+    chain_round<NDOF, 0x112>(k, R, t);  // row_shr:2
+    chain_round<NDOF, 0x114>(k, R, t);  // row_shr:4
 }
 
 // The per-configuration records in LDS (chain, axes, joint gradient) are written and
@@ -373,7 +404,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 template <int NDOF, int G0, int G2, bool MORPH, bool F16>
 __device__ __forceinline__ void arm_body(const pdmp_arm &arm, const uint4 *fraw,
                                          const SplitScheme &sc, const float *ax, const float *ay,
-                                         const float *az, float *kin, float beta, float kappa,
+                                         const float *az, float *kin, const float *lk,
+                                         float beta, float kappa,
                                          float gscale, const float *q_in, float *q_out, int64_t n,
                                          int64_t n_eff, int T, float eta, float thresh,
                                          float *maxc_out, uint8_t *flag_out, const Traj &tr) {
@@ -388,12 +420,9 @@ __device__ __forceinline__ void arm_body(const pdmp_arm &arm, const uint4 *fraw,
     const int P = arm.pts_per_link;
     const bool own = k < P;
     const float frac = own ? (float)(k + 1) / (float)P : 0.0f;
-    float q[NDOF], sa[NDOF], ca[NDOF];
+    float q[NDOF];
 #pragma unroll
-    for (int j = 0; j < NDOF; ++j) {
-        q[j] = q_in[(size_t)j * n + cs];
-        sincosf(arm.alpha[j], &sa[j], &ca[j]);
-    }
+    for (int j = 0; j < NDOF; ++j) q[j] = q_in[(size_t)j * n + cs];
 
     const int steps = MORPH ? T : 1;
     float mc = -1.0f;
@@ -402,19 +431,27 @@ __device__ __forceinline__ void arm_body(const pdmp_arm &arm, const uint4 *fraw,
     for (int st = 0; st < steps; ++st) {
         if (rec) traj_put<NDOF>(tr, st, tc, q);
         {
-            // the chain of this configuration, parked in LDS so that the link loop
-            // below does not hold ~45 registers across the MFMA work
-            float o[NDOF + 1][3], zx[NDOF][3];
-            g3_chain<NDOF>(arm, sa, ca, q, o, zx);
-            if (writer) {
+            // the chain of this configuration (each lane of it one link, composed by a
+            // scan), parked in LDS so that the link loop below does not hold ~45
+            // registers across the MFMA work; the lower half-wave writes it
+            float R[3][3], t[3];
+            g3_chain_scan<NDOF>(lk, q, k, R, t);
+            if (lane < 32) {
+                if (k < NDOF) {
 #pragma unroll
-                for (int i = 0; i <= NDOF; ++i)
+                    for (int e = 0; e < 3; ++e) ko[3 * (k + 1) + e] = t[e];
+                }
+                if (k + 1 < NDOF) {
 #pragma unroll
-                    for (int e = 0; e < 3; ++e) ko[3 * i + e] = o[i][e];
+                    for (int e = 0; e < 3; ++e) kz[3 * (k + 1) + e] = R[e][2];
+                }
+                if (k == 0) {
 #pragma unroll
-                for (int i = 0; i < NDOF; ++i)
-#pragma unroll
-                    for (int e = 0; e < 3; ++e) kz[3 * i + e] = zx[i][e];
+                    for (int e = 0; e < 3; ++e) {
+                        ko[e] = 0.0f;
+                        kz[e] = e == 2 ? 1.0f : 0.0f;
+                    }
+                }
             }
         }
         wave_lds_sync();
@@ -485,9 +522,17 @@ k_arm_grid3d(pdmp_arm arm, const float *__restrict__ hinges, const float *__rest
     __shared__ uint4 fraw[C::FRAG];
     __shared__ float ax[G0], ay[kG3Y], az[G2];
     __shared__ float kin[16 * KIN];
+    __shared__ float lk[5 * NDOF];  // per link: a, d, theta0, sin alpha, cos alpha
     __shared__ SplitRange rg;
     const int64_t n_eff = n_active ? min((int64_t)*n_active, n) : n;
     if ((int64_t)blockIdx.x * 16 >= n_eff) return;  // whole block idle (uniform)
+    if (threadIdx.x < NDOF) {
+        const int j = threadIdx.x;
+        lk[5 * j] = arm.a[j];
+        lk[5 * j + 1] = arm.d[j];
+        lk[5 * j + 2] = arm.theta0[j];
+        sincosf(arm.alpha[j], &lk[5 * j + 3], &lk[5 * j + 4]);
+    }
     // the range check pays off over the T steps of a morph; the single check pass
     // keeps the BF16 scheme
     const SplitScheme sc = g3_stage<G0, G2>(fraw, ax, ay, az, rg, hinges, weights, kappa, MORPH);
@@ -495,11 +540,11 @@ k_arm_grid3d(pdmp_arm arm, const float *__restrict__ hinges, const float *__rest
     constexpr int M = G0 * kG3Y * G2;
     const float beta = weights[M];
     if (MORPH && sc.fp16)
-        arm_body<NDOF, G0, G2, MORPH, true>(arm, fraw, sc, ax, ay, az, kin, beta, kappa, gscale,
+        arm_body<NDOF, G0, G2, MORPH, true>(arm, fraw, sc, ax, ay, az, kin, lk, beta, kappa, gscale,
                                             q_in, q_out, n, n_eff, T, eta, thresh, maxc_out,
                                             flag_out, tr);
     else
-        arm_body<NDOF, G0, G2, MORPH, false>(arm, fraw, sc, ax, ay, az, kin, beta, kappa, gscale,
+        arm_body<NDOF, G0, G2, MORPH, false>(arm, fraw, sc, ax, ay, az, kin, lk, beta, kappa, gscale,
                                              q_in, q_out, n, n_eff, T, eta, thresh, maxc_out,
                                              flag_out, tr);
 }
