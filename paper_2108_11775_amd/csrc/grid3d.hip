@@ -33,8 +33,10 @@ constexpr int kG3Block = 256;
 
 // The x contraction runs on one of two split schemes (mfma_split.h): two-part FP16
 // splits with three products where the operands' range allows, three-part BF16
-// splits with six products otherwise; morphs only (a single evaluation skips the
-// check and keeps the BF16 scheme).
+// splits with six products otherwise.  The workspace morph and both arm kernels
+// (morph and body-point check, each block running 7 links per configuration) test
+// the range; a single workspace evaluation, whose blocks mostly stage W, skips the
+// test and keeps the BF16 scheme.
 static_assert(kG3Block == 64 * kSplitWaves, "the scheme test's block");
 
 template <int G0, int G2>
@@ -533,13 +535,11 @@ k_arm_grid3d(pdmp_arm arm, const float *__restrict__ hinges, const float *__rest
         lk[5 * j + 2] = arm.theta0[j];
         sincosf(arm.alpha[j], &lk[5 * j + 3], &lk[5 * j + 4]);
     }
-    // the range check pays off over the T steps of a morph; the single check pass
-    // keeps the BF16 scheme
-    const SplitScheme sc = g3_stage<G0, G2>(fraw, ax, ay, az, rg, hinges, weights, kappa, MORPH);
+    const SplitScheme sc = g3_stage<G0, G2>(fraw, ax, ay, az, rg, hinges, weights, kappa, true);
     __syncthreads();
     constexpr int M = G0 * kG3Y * G2;
     const float beta = weights[M];
-    if (MORPH && sc.fp16)
+    if (sc.fp16)
         arm_body<NDOF, G0, G2, MORPH, true>(arm, fraw, sc, ax, ay, az, kin, lk, beta, kappa, gscale,
                                             q_in, q_out, n, n_eff, T, eta, thresh, maxc_out,
                                             flag_out, tr);
