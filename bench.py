@@ -633,16 +633,31 @@ def density_workload(P, I, K, torch, hl):
     occ, x0, N = hl["sc"]["occ"], hl["x0"], hl["N"]
     G0 = G1 = cfg.grid
     out = torch.empty_like(x0)
+    iters = 10
+    # the unordered kernels, then the ordered calls (counting sort + exact-zero
+    # skipping, the sort timed with them) that must give the same bits
     P.morph_logdet(occ, x0, cfg.T, cfg.eta, out=out)
     t = Timer(torch)
     with t:
-        _, ld = P.morph_logdet(occ, x0, cfg.T, cfg.eta, out=out)
-    ld_ms = t.ms()
-    iters = 10
+        _, ld_u = P.morph_logdet(occ, x0, cfg.T, cfg.eta, out=out)
+    ld_u_ms = t.ms()
     t = Timer(torch)
     with t:
-        y, ld_inv, resid = P.morph_inverse(occ, out, cfg.T, cfg.eta, iters)
+        y_u, ld_inv_u, resid_u = P.morph_inverse(occ, out, cfg.T, cfg.eta, iters)
+    inv_u_ms = t.ms()
+    ws = P.morph_workspace(occ, N, cfg.T)
+    out_o = torch.empty_like(x0)
+    P.morph_logdet(occ, x0, cfg.T, cfg.eta, out=out_o, ordered=True, ws=ws)
+    t = Timer(torch)
+    with t:
+        _, ld = P.morph_logdet(occ, x0, cfg.T, cfg.eta, out=out_o, ordered=True, ws=ws)
+    ld_ms = t.ms()
+    t = Timer(torch)
+    with t:
+        y, ld_inv, resid = P.morph_inverse(occ, out, cfg.T, cfg.eta, iters, ordered=True, ws=ws)
     inv_ms = t.ms()
+    same_bits = bool(torch.equal(out_o, out) and torch.equal(ld, ld_u) and torch.equal(y, y_u)
+                     and torch.equal(ld_inv, ld_inv_u) and torch.equal(resid, resid_u))
     rt = (y - x0).abs().amax(dim=0)
     ldd = (ld_inv - ld).abs().max().item()
     seed = I.philox_seed(cfg.cfg_id)
@@ -665,8 +680,12 @@ def density_workload(P, I, K, torch, hl):
     return {"workload": "log-det, inverse (fixed point, 10 iterations per step) and epsilon "
                         "mixture (eps=0.1) of the 2-D large morph: 1,048,576 samples, 64x64 "
                         "hinges, T=50, eta=0.02",
+            "path": "ordered (pdmp_morph_logdet_ws, pdmp_morph_inverse_ws: counting sort, "
+                    "then exact-zero skipping; the sort included in the times)",
             "logdet_ms": ld_ms, "logdet_samples_per_s": N / (ld_ms * 1e-3),
             "inverse_ms": inv_ms, "inverse_samples_per_s": N / (inv_ms * 1e-3),
+            "unordered": {"logdet_ms": ld_u_ms, "inverse_ms": inv_u_ms,
+                          "same_bits_as_ordered": same_bits},
             "inverse_residual_max": resid.max().item(),
             "round_trip_err_max": rt.max().item(), "round_trip_err_median": rt.median().item(),
             "logdet_roundtrip_diff_max": ldd,
@@ -676,7 +695,8 @@ def density_workload(P, I, K, torch, hl):
             "roofline_logdet": {"bound": "mfma", "achieved": ach,
                                 "peak": peak / 1e12, "unit": "TFLOP/s",
                                 "frac": ach * 1e12 / peak,
-                                "kernel": "k_grid2d_inv<2,4,kLogdet>", "split_scheme": scheme,
+                                "kernel": "k_grid2d_inv_sorted<2,4,kLogdet> (sort included)",
+                                "split_scheme": scheme,
                                 "work": "6*G0*G1 FP32-accurate flops per sample-step (the three "
                                         f"contractions), on {sname} MFMA as {nprod} split "
                                         "products each",
@@ -685,7 +705,8 @@ def density_workload(P, I, K, torch, hl):
                                  "achieved": inv_flops / (inv_ms * 1e-3) / 1e12,
                                  "peak": peak / 1e12, "unit": "TFLOP/s",
                                  "frac": inv_flops / (inv_ms * 1e-3) / peak,
-                                 "kernel": "k_grid2d_inv<2,4,kInverse>", "split_scheme": scheme,
+                                 "kernel": "k_grid2d_inv_sorted<2,4,kInverse> (sort included)",
+                                 "split_scheme": scheme,
                                  "work": "(4*iters + 6)*G0*G1 FP32-accurate flops per "
                                          f"sample-step, on {sname} MFMA as {nprod} split "
                                          "products each",
@@ -1028,8 +1049,11 @@ def main():
                 log("small 2-D done")
             if "density" in sel and hl["sc"]["occ"].grid:
                 wl["density_ws2d"] = density_workload(P, I, K, torch, hl)
-                log(f"log-det / inverse: {wl['density_ws2d']['logdet_ms']:.1f} / "
-                    f"{wl['density_ws2d']['inverse_ms']:.1f} ms")
+                dw = wl["density_ws2d"]
+                log(f"log-det / inverse, ordered: {dw['logdet_ms']:.2f} / {dw['inverse_ms']:.2f} "
+                    f"ms (unordered {dw['unordered']['logdet_ms']:.2f} / "
+                    f"{dw['unordered']['inverse_ms']:.2f} ms, same bits: "
+                    f"{dw['unordered']['same_bits_as_ordered']})")
             if "culled" in sel:
                 wl["culled_ws2d"] = culled_workload(P, I, K, torch, hl)
                 log(f"culled morph: {wl['culled_ws2d']['morph_ms']:.2f} ms")

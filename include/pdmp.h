@@ -215,6 +215,22 @@ int32_t pdmp_morph_inverse(const pdmp_occupancy *occ, const float *z, float *y, 
                            int32_t T, float eta, int32_t iters, float *logdet, float *resid,
                            void *stream);
 
+/* The same two calls with a caller workspace (pdmp_morph_workspace_size(occ, NULL, n,
+ * T) bytes; 0 means the call needs none and ws is ignored): a large batch on a 2-D
+ * hinge grid (the cases pdmp_morph_samples_ws orders) is first ordered by its cell
+ * (in, resp. z), and every evaluation then skips, wave by wave, the exact zeros of the
+ * factorised sums, Hessian included (on the FP16 scheme the Hessian's evaluations
+ * keep the 16-hinge blocks up to 35 rather than 30 kappa units squared beyond c).
+ * out / y, logdet and resid receive the same bits as from the calls above.
+ * PDMP_ENOMEM if ws is short; in == out (z == y) allowed; calls that share a
+ * workspace must not overlap. */
+int32_t pdmp_morph_logdet_ws(const pdmp_occupancy *occ, const float *in, float *out, int64_t n,
+                             int32_t T, float eta, float *logdet, void *ws, size_t ws_bytes,
+                             void *stream);
+int32_t pdmp_morph_inverse_ws(const pdmp_occupancy *occ, const float *z, float *y, int64_t n,
+                              int32_t T, float eta, int32_t iters, float *logdet, float *resid,
+                              void *ws, size_t ws_bytes, void *stream);
+
 /* ---- epsilon mixture with the prior (Sec. 3.3: sampling with an epsilon bias toward
  * the base distribution keeps regions the morph stretches thin reachable).
  * Draws the prior batch x0 [dim][n] exactly as pdmp_uniform_samples(seed, stream_id,

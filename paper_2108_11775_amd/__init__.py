@@ -308,9 +308,16 @@ def morph_trajectory(occ: Occupancy, x, T: int, eta: float, stride: int = 1,
     return out, traj
 
 
-def morph_logdet(occ: Occupancy, x, T: int, eta: float, out=None):
+def _ws_args(ws):
+    return (_dev(ws, "ws") if ws is not None else None, ws.numel() if ws is not None else 0)
+
+
+def morph_logdet(occ: Occupancy, x, T: int, eta: float, out=None, ordered: bool = False,
+                 ws=None):
     """(x_T, logdet): the workspace morph of x [dim][n] and, per sample,
-    sum_k log|det(I - eta Hc(x_k))| (the log-Jacobian of the map, Sec. 3.2)."""
+    sum_k log|det(I - eta Hc(x_k))| (the log-Jacobian of the map, Sec. 3.2).  With
+    ordered, pdmp_morph_logdet_ws (a large 2-D grid batch in spatial order, exact zeros
+    skipped, the same bits; ws from morph_workspace, allocated here if None)."""
     torch = _torch()
     n = int(x.shape[1])
     _dev(x, "x", torch.float32, (occ.dim, n))
@@ -318,16 +325,23 @@ def morph_logdet(occ: Occupancy, x, T: int, eta: float, out=None):
         out = torch.empty_like(x)
     ld = torch.empty(n, dtype=torch.float32, device=x.device)
     o = occ.c_struct()
-    _lib.call("pdmp_morph_logdet", C.byref(o), C.c_void_p(x.data_ptr()),
-              _dev(out, "out", torch.float32, (occ.dim, n)), n, int(T), float(eta),
-              _dev(ld, "logdet"), _stream(x.device))
+    args = (C.byref(o), C.c_void_p(x.data_ptr()), _dev(out, "out", torch.float32, (occ.dim, n)),
+            n, int(T), float(eta), _dev(ld, "logdet"))
+    if ordered:
+        if ws is None:
+            ws = morph_workspace(occ, n, T)
+        _lib.call("pdmp_morph_logdet_ws", *args, *_ws_args(ws), _stream(x.device))
+    else:
+        _lib.call("pdmp_morph_logdet", *args, _stream(x.device))
     return out, ld
 
 
-def morph_inverse(occ: Occupancy, z, T: int, eta: float, iters: int = 30):
+def morph_inverse(occ: Occupancy, z, T: int, eta: float, iters: int = 30,
+                  ordered: bool = False, ws=None):
     """(y, logdet, resid): the inverse of the T-step morph at z [dim][n] by fixed point
     (iters iterations per step), the forward log-determinant along the reconstructed
-    path and the largest fixed-point residual per sample."""
+    path and the largest fixed-point residual per sample.  With ordered,
+    pdmp_morph_inverse_ws (as in morph_logdet)."""
     torch = _torch()
     n = int(z.shape[1])
     _dev(z, "z", torch.float32, (occ.dim, n))
@@ -335,9 +349,14 @@ def morph_inverse(occ: Occupancy, z, T: int, eta: float, iters: int = 30):
     ld = torch.empty(n, dtype=torch.float32, device=z.device)
     r = torch.empty(n, dtype=torch.float32, device=z.device)
     o = occ.c_struct()
-    _lib.call("pdmp_morph_inverse", C.byref(o), C.c_void_p(z.data_ptr()), _dev(y, "y"), n,
-              int(T), float(eta), int(iters), _dev(ld, "logdet"), _dev(r, "resid"),
-              _stream(z.device))
+    args = (C.byref(o), C.c_void_p(z.data_ptr()), _dev(y, "y"), n, int(T), float(eta),
+            int(iters), _dev(ld, "logdet"), _dev(r, "resid"))
+    if ordered:
+        if ws is None:
+            ws = morph_workspace(occ, n, T)
+        _lib.call("pdmp_morph_inverse_ws", *args, *_ws_args(ws), _stream(z.device))
+    else:
+        _lib.call("pdmp_morph_inverse", *args, _stream(z.device))
     return y, ld, r
 
 

@@ -137,6 +137,10 @@ SIGNATURES = {
     "pdmp_morph_logdet": (_i32, [_P(pdmp_occupancy), _vp, _vp, _i64, _i32, _f, _vp, _vp]),
     "pdmp_morph_inverse": (_i32, [_P(pdmp_occupancy), _vp, _vp, _i64, _i32, _f, _i32, _vp, _vp,
                                   _vp]),
+    "pdmp_morph_logdet_ws": (_i32, [_P(pdmp_occupancy), _vp, _vp, _i64, _i32, _f, _vp, _vp,
+                                    C.c_size_t, _vp]),
+    "pdmp_morph_inverse_ws": (_i32, [_P(pdmp_occupancy), _vp, _vp, _i64, _i32, _f, _i32, _vp,
+                                     _vp, _vp, C.c_size_t, _vp]),
     "pdmp_mixture_samples": (_i32, [_P(pdmp_occupancy), _u64, _u32, _P(_f), _P(_f), _i64, _f,
                                     _i32, _f, _vp, _vp, _vp, _vp]),
     "pdmp_tanh_num_params": (_i64, [_P(pdmp_tanh_net)]),

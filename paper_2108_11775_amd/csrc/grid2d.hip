@@ -259,11 +259,7 @@ k_grid2d_mfma(const float *__restrict__ hinges, const float *__restrict__ weight
 // read and written by one XCD, whose L2 then holds the part's lines while its waves
 // gather and scatter single coordinates through the permutation: HBM sees about one
 // read and one write of each line instead of one per coordinate.
-constexpr int kSortCells = 32;  // per axis
-constexpr int kSortParts = 8;
-constexpr float kYReach = 12.5f;
-
-__device__ __forceinline__ uint32_t wave_any(bool p) { return __ballot(p) != 0 ? 1u : 0u; }
+constexpr int kSortCells = 32;  // per axis (kSortParts, the parts: grid2d_stage.h)
 
 // A wave-uniform value kept in a scalar register.
 __device__ __forceinline__ float uniform_f(float v) {
@@ -319,69 +315,15 @@ k_grid2d_sorted(const float *__restrict__ hinges, const float *__restrict__ weig
 
     if (sc.fp16) {
         const f16x8_t *frag = reinterpret_cast<const f16x8_t *>(fraw);
-        // the x-range of each k-step's hinges (kappa units; padding excluded) and the
-        // bounds of each 8-row group past which its ey_b vanish (a group of padding
-        // rows only is never needed: its weights are zero)
-        // (wave-uniform, in scalar registers)
-        // (wave-uniform, in scalar registers): one coordinate per lane, reduced over its
-        // k-step's 16 lanes and its group's 8 lanes
-        float klo[KS], khi[KS], ga[4 * TB], gb[4 * TB];
-        const bool xin = lane < g0, yin = lane < g1;  // g0 <= 16 KS, g1 <= 32 TB
-        const float gx = gxs[min(lane, 16 * KS - 1)], gy = gys[min(lane, 32 * TB - 1)];
-        float xlo = xin ? gx : INFINITY, xhi = xin ? gx : -INFINITY;
-        float ylo = yin ? gy : INFINITY, yhi = yin ? gy : -INFINITY;
-        float ymag = yin ? fabsf(gy) : 0.0f;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            if (off < 16) {
-                xlo = fminf(xlo, __shfl_xor(xlo, off, 64));
-                xhi = fmaxf(xhi, __shfl_xor(xhi, off, 64));
-            }
-            if (off < 8) {
-                ylo = fminf(ylo, __shfl_xor(ylo, off, 64));
-                yhi = fmaxf(yhi, __shfl_xor(yhi, off, 64));
-            }
-            ymag = fmaxf(ymag, __shfl_xor(ymag, off, 64));
-        }
-        auto lane_f = [](float v, int l) {
-            return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-        };
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            klo[ks] = lane_f(xlo, 16 * ks);
-            khi[ks] = lane_f(xhi, 16 * ks);
-        }
-#pragma unroll
-        for (int g = 0; g < 4 * TB; ++g) {
-            ga[g] = lane_f(ylo, 8 * g) - kYReach;
-            gb[g] = lane_f(yhi, 8 * g) + kYReach;
-        }
-        const float gmag = lane_f(ymag, 0);
-        const uint32_t all_groups = (1u << (4 * TB)) - 1u;
-        const bool group_test = gmag < 0x1p20f;
+        SkipFrame<TB, KS> fr;
+        skip_frame<TB, KS>(gxs, gys, g0, g1, fr);
         for (int st = 0; st < T; ++st) {
             if (rec) traj_put<2>(tr, st, (int64_t)tc, {x, y});
             const float xs = kappa * x, ys = kappa * y;
             const int c = split_scale_exp(xs, sc.gmin, sc.gmax);
-            const float lim = (float)(c + 30);
-            uint32_t km = 0, gm = 0;
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const float d = fmaxf(fmaxf(klo[ks] - xs, xs - khi[ks]), 0.0f);
-                km |= wave_any(d * d < lim) << ks;
-            }
-#pragma unroll
-            for (int g = 0; g < 4 * TB; ++g)
-                gm |= ((__ballot(!(ys <= ga[g])) & __ballot(!(ys >= gb[g]))) != 0 ? 1u : 0u) << g;
-            if (!group_test || __ballot(!__builtin_isfinite(xs) || !__builtin_isfinite(ys)) != 0) {
-                km = (1u << KS) - 1u;
-                gm = all_groups;
-            }
-            km = __builtin_amdgcn_readfirstlane(km);
-            gm = __builtin_amdgcn_readfirstlane(gm);
-            uint32_t tm = 0;
-#pragma unroll
-            for (int t = 0; t < TB; ++t) tm |= (((gm >> (4 * t)) & 15u) != 0 ? 1u : 0u) << t;
+            uint32_t km, gm;
+            skip_masks<TB, KS>(fr, xs, ys, (float)(c + 30), km, gm);
+            const uint32_t tm = skip_tiles<TB>(gm);
             f32x16_t U[TB], V[TB];
             int ln = lane;  // opaque: keeps the fragment reads inside the step loop
             asm volatile("" : "+v"(ln));
@@ -933,22 +875,33 @@ size_t grid2d_sorted_ws_bytes(int g0, int g1, int64_t n, int T) {
            (size_t)n * sizeof(uint32_t);
 }
 
+// The spatial order of x [2][n] (a workspace of grid2d_sorted_ws_bytes): *perm, the
+// permutation (each part's places in cell order), and *part, the samples per part.
+int32_t launch_sort2d(const float *hinges, int g0, int g1, const float *x, int64_t n, void *ws,
+                      hipStream_t st, const uint32_t **perm_out, int64_t *part_out) {
+    uint32_t *cursor = (uint32_t *)ws;
+    uint32_t *perm =
+        (uint32_t *)((char *)ws + (((size_t)kSortKeys * sizeof(uint32_t) + 255) & ~(size_t)255));
+    const int64_t part = sort_part(n);
+    const unsigned nb = (unsigned)(kSortParts * sort_chunks_per_part(n));
+    hipLaunchKernelGGL(k_sort_zero, dim3(1), dim3(kSortBlock), 0, st, cursor);
+    hipLaunchKernelGGL(k_sort_count, dim3(nb), dim3(kSortBlock), 0, st, hinges, g0, g1, x, n, part,
+                       cursor);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, st, cursor);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kSortBlock), 0, st, hinges, g0, g1, x, n,
+                       part, cursor, perm);
+    *perm_out = perm;
+    *part_out = part;
+    return check_launch("k_sort");
+}
+
 // The morph of a large batch in spatial order (PDMP_EUNSUPPORTED: not this path).
 int32_t launch_grid2d_sorted(const RbfArgs &a, int g0, int g1, void *ws, hipStream_t st) {
     if (!grid2d_sorted_ws_bytes(g0, g1, a.n, a.T) || (int64_t)g0 * g1 != a.M)
         return PDMP_EUNSUPPORTED;
-    uint32_t *cursor = (uint32_t *)ws;
-    uint32_t *perm =
-        (uint32_t *)((char *)ws + (((size_t)kSortKeys * sizeof(uint32_t) + 255) & ~(size_t)255));
-    const int64_t part = sort_part(a.n);
-    const unsigned nb = (unsigned)(kSortParts * sort_chunks_per_part(a.n));
-    hipLaunchKernelGGL(k_sort_zero, dim3(1), dim3(kSortBlock), 0, st, cursor);
-    hipLaunchKernelGGL(k_sort_count, dim3(nb), dim3(kSortBlock), 0, st, a.hinges, g0, g1, a.x_in,
-                       a.n, part, cursor);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, st, cursor);
-    hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kSortBlock), 0, st, a.hinges, g0, g1, a.x_in,
-                       a.n, part, cursor, perm);
-    if (int32_t e = check_launch("k_sort")) return e;
+    const uint32_t *perm;
+    int64_t part;
+    if (int32_t e = launch_sort2d(a.hinges, g0, g1, a.x_in, a.n, ws, st, &perm, &part)) return e;
     // kSortParts interleaved runs of blocks, each covering one part
     const dim3 grid((unsigned)(kSortParts * ((part + 127) / 128))), blk(kG2Block);
 #define PDMP_G2O(TB, KS)                                                                         \

@@ -17,11 +17,19 @@
 // accuracy (the split schemes of mfma_split.h: two-part FP16 splits and three
 // products where the operands' range allows, three-way bf16 splits and six products
 // otherwise); the y sums run on the accumulator layout as in the plain morph (same
-// lane mapping, same xor-32 pair sum).  Pairwise path (any hinges, 2-D or 3-D): one point per thread, hinges staged
-// in LDS tiles.
+// lane mapping, same xor-32 pair sum).  A large batch with a workspace runs in the
+// spatial order of the ordered morph (grid2d.hip: counting sort, then every
+// evaluation skips, wave by wave, the k-steps and 8-row groups that are exact zeros
+// for all the wave's samples; grid2d_stage.h), with the same bits per sample.
+// Pairwise path (any hinges, 2-D or 3-D): one point per thread, hinges staged in LDS
+// tiles.
 #include "grid2d_stage.h"
 #include "mfma_split.h"
 #include "pdmp_common.h"
+
+// No FMA contraction beyond the written fmaf calls: the ordered and unordered grid
+// kernels then round every sample's arithmetic alike.
+#pragma clang fp contract(off)
 
 namespace pdmp {
 
@@ -182,59 +190,181 @@ __device__ __forceinline__ void g2i_eval(const uint4 *fraw, const SplitScheme &s
     }
 }
 
+// g2i_eval on the FP16 scheme with the wave's exact-zero skipping (grid2d_stage.h):
+// the kept k-steps in order, the j-th kept one's operands in buffer j % NB (with two
+// buffers its successor's are formed while its products run; the first starts the
+// accumulators from the zero constant), and the kept 8-row groups of the kept tiles.
+// Each sum gets the bits of g2i_eval<.., true>'s: every sum is a separate accumulator
+// over the same terms in the same order, the skipped ones being exact zeros.  gys
+// 16-byte aligned.
+template <int TB, int KS, bool HESS>
+__device__ __forceinline__ void g2i_eval_skip(const uint4 *fraw, const SplitScheme &sc,
+                                              const SkipFrame<TB, KS> &fr, const float *gxs,
+                                              const float *gys, float xs, float ys, float &s,
+                                              float &sx, float &sy, float &sxx, float &sxy,
+                                              float &syy) {
+    const int lane0 = threadIdx.x & 63, half = lane0 >> 5;
+    int lane = lane0;  // opaque: the fragment reads stay inside the callers' loops
+    asm volatile("" : "+v"(lane));
+    const f16x8_t *frag = reinterpret_cast<const f16x8_t *>(fraw);
+    int k = 0;
+    const int c = split_scale_exp(xs, sc.gmin, sc.gmax, k);
+    const float cf = (float)c, sk = ldexpf(1.0f, -k);
+    uint32_t km, gm;
+    skip_masks<TB, KS>(fr, xs, ys, (float)(c + (HESS ? 35 : 30)), km, gm);
+    const uint32_t tm = skip_tiles<TB>(gm);
+    f32x16_t U[TB], V[TB], Q[TB];
+    // with the Hessian's third operand set one buffer (the operands of each kept
+    // k-step formed just before its products): two would not fit beside U, V and Q
+    constexpr int NB = HESS ? 1 : 2;
+    f16x8_t e[NB][2], de[NB][2], dde[NB][2];
+    uint32_t rem = km;
+    int ksn = rem ? __builtin_ctz(rem) : 0;
+    if (rem && NB == 2) g2i_operands_h<HESS>(gxs, xs, cf, sk, ksn, half, e[0], de[0], dde[0]);
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+        if (!rem) break;
+        const int ks = ksn;
+        const int cur = j % NB;
+        rem &= rem - 1u;
+        if (NB == 1) {
+            g2i_operands_h<HESS>(gxs, xs, cf, sk, ks, half, e[0], de[0], dde[0]);
+            if (rem) ksn = __builtin_ctz(rem);
+        } else if (rem) {
+            ksn = __builtin_ctz(rem);
+            g2i_operands_h<HESS>(gxs, xs, cf, sk, ksn, half, e[(j + 1) % NB], de[(j + 1) % NB],
+                                 dde[(j + 1) % NB]);
+        }
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            if (!((tm >> t) & 1u)) continue;
+            const f16x8_t a1 = frag[(0 * KS + ks) * TB * 64 + t * 64 + lane];
+            const f16x8_t a2 = frag[(1 * KS + ks) * TB * 64 + t * 64 + lane];
+            const f32x16_t zero = {};
+            U[t] = mfma_h3(a1, a2, e[cur][0], e[cur][1], j == 0 ? zero : U[t]);
+            V[t] = mfma_h3(a1, a2, de[cur][0], de[cur][1], j == 0 ? zero : V[t]);
+            if (HESS) Q[t] = mfma_h3(a1, a2, dde[cur][0], dde[cur][1], j == 0 ? zero : Q[t]);
+        }
+    }
+    s = sx = sy = sxx = sxy = syy = 0.0f;
+    if (km) {
+        // this lane's rows b = 32t + 8g + 4 half + r, read before the group branches
+        f32x4_t gy[TB][4];
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                gy[t][g] = *reinterpret_cast<const f32x4_t *>(&gys[32 * t + 8 * g + 4 * half]);
+            asm volatile("" ::"v"(gy[t][0]), "v"(gy[t][1]), "v"(gy[t][2]), "v"(gy[t][3]));
+        }
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            if (!((tm >> t) & 1u)) continue;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                if (!((gm >> (4 * t + g)) & 1u)) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int v = 4 * g + r;
+                    const float d = ys - gy[t][g][r];
+                    const float ey = exp2_fast(-d * d);
+                    const float ed = ey * d;
+                    s = fmaf(ey, U[t][v], s);
+                    sx = fmaf(ey, V[t][v], sx);
+                    sy = fmaf(ed, U[t][v], sy);
+                    if (HESS) {
+                        sxx = fmaf(ey, Q[t][v], sxx);
+                        sxy = fmaf(ed, V[t][v], sxy);
+                        syy = fmaf(ed * d, U[t][v], syy);
+                    }
+                }
+            }
+        }
+    }
+    s += __shfl_xor(s, 32, 64);
+    sx += __shfl_xor(sx, 32, 64);
+    sy += __shfl_xor(sy, 32, 64);
+    if (HESS) {
+        sxx += __shfl_xor(sxx, 32, 64);
+        sxy += __shfl_xor(sxy, 32, 64);
+        syy += __shfl_xor(syy, 32, 64);
+    }
+    const int un = -(sc.sw + c);
+    s = ldexpf(s, un);
+    sx = ldexpf(sx, un);
+    sy = ldexpf(sy, un);
+    if (HESS) {
+        sxx = ldexpf(sxx, un + k);
+        sxy = ldexpf(sxy, un);
+        syy = ldexpf(syy, un);
+    }
+}
+
 // MODE kLogdet: forward morph with the log-determinant.  MODE kInverse: inverse by
-// fixed point (iters per step) with residual and log-determinant.
-template <int TB, int KS, int MODE, bool F16>
+// fixed point (iters per step) with residual and log-determinant.  The lane reads
+// sample ic and writes sample i (i >= n: a tail lane, writes nothing); with ORD (the
+// ordered kernel on the FP16 scheme) each evaluation skips the wave's exact zeros by
+// the frame fr.
+template <int TB, int KS, int MODE, bool F16, bool ORD>
 __device__ __forceinline__ void g2i_body(const uint4 *fraw, const SplitScheme &sc,
                                          const float *gxs, const float *gys, float beta,
                                          float kappa, float gscale, const float *x_in, int64_t n,
                                          int T, float eta, int iters, float *x_out,
-                                         float *logdet_out, float *resid_out) {
+                                         float *logdet_out, float *resid_out, int64_t i,
+                                         int64_t ic, const SkipFrame<TB, KS> &fr) {
     const int lane = threadIdx.x & 63, half = lane >> 5;
-    const int64_t wave = (int64_t)blockIdx.x * (kIvBlock / 64) + (threadIdx.x >> 6);
-    const int64_t i = wave * 32 + (lane & 31);
-    const int64_t ic = i < n ? i : n - 1;
     float x = x_in[ic], y = x_in[(size_t)n + ic];
     const float il2 = gscale * kappa;  // 1 / l^2
     const float g2 = gscale * gscale;
     float ld = 0.0f, rmax = 0.0f;
+    // one evaluation at (x, y): s' and the sums of the gradient (and with HESS the
+    // Hessian), on the block's scheme, skipping the wave's exact zeros with ORD
+    auto eval = [&](auto hess, float &s, float &sx, float &sy, float &sxx, float &sxy,
+                    float &syy) {
+        constexpr bool H = decltype(hess)::value;
+        if constexpr (F16 && ORD)
+            g2i_eval_skip<TB, KS, H>(fraw, sc, fr, gxs, gys, kappa * x, kappa * y, s, sx, sy, sxx,
+                                     sxy, syy);
+        else
+            g2i_eval<TB, KS, H, F16>(fraw, sc, gxs, gys, kappa * x, kappa * y, s, sx, sy, sxx,
+                                     sxy, syy);
+    };
     for (int st = 0; st < T; ++st) {
         const float zx = x, zy = y;
-        const int evals = MODE == kInverse ? iters + 1 : 1;
-        for (int j = 0; j < evals; ++j) {
-            const bool last = j == evals - 1;
-            float s, sx, sy, sxx = 0.0f, sxy = 0.0f, syy = 0.0f;
-            if (last)
-                g2i_eval<TB, KS, true, F16>(fraw, sc, gxs, gys, kappa * x, kappa * y, s, sx, sy,
-                                            sxx, sxy, syy);
-            else
-                g2i_eval<TB, KS, false, F16>(fraw, sc, gxs, gys, kappa * x, kappa * y, s, sx, sy,
-                                             sxx, sxy, syy);
-            float c, sp;
-            sigmoid_and_slope(s + beta, c, sp);
-            const float gx = -gscale * sx, gy = -gscale * sy;  // grad s
-            if (last) {
-                const float spp = sp * (1.0f - 2.0f * c);
-                float H[2][2];
-                H[0][0] = sp * fmaf(g2, sxx, -il2 * s) + spp * gx * gx;
-                H[0][1] = sp * g2 * sxy + spp * gx * gy;
-                H[1][0] = H[0][1];
-                H[1][1] = sp * fmaf(g2, syy, -il2 * s) + spp * gy * gy;
-                ld += step_logdet<2>(H, eta);
+        if (MODE == kInverse) {
+            // the fixed-point iterations: gradient only
+            for (int j = 0; j < iters; ++j) {
+                float s, sx, sy, sxx = 0.0f, sxy = 0.0f, syy = 0.0f;
+                eval(std::false_type{}, s, sx, sy, sxx, sxy, syy);
+                float c, sp;
+                sigmoid_and_slope(s + beta, c, sp);
+                const float gx = -gscale * sx, gy = -gscale * sy;  // grad s
+                const float cx = sp * gx, cy = sp * gy;            // grad c
+                x = fmaf(eta, cx, zx);
+                y = fmaf(eta, cy, zy);
             }
-            const float cx = sp * gx, cy = sp * gy;  // grad c
-            if (MODE == kInverse) {
-                if (!last) {
-                    x = fmaf(eta, cx, zx);
-                    y = fmaf(eta, cy, zy);
-                } else {
-                    const float rx = fabsf(x - fmaf(eta, cx, zx)), ry = fabsf(y - fmaf(eta, cy, zy));
-                    rmax = fmaxf(rmax, fmaxf(rx, ry));
-                }
-            } else {
-                x = fmaf(-eta, cx, x);
-                y = fmaf(-eta, cy, y);
-            }
+        }
+        // the evaluation with the Hessian: the step's log-determinant, then the residual
+        // (inverse) or the Euler step (forward)
+        float s, sx, sy, sxx = 0.0f, sxy = 0.0f, syy = 0.0f;
+        eval(std::true_type{}, s, sx, sy, sxx, sxy, syy);
+        float c, sp;
+        sigmoid_and_slope(s + beta, c, sp);
+        const float gx = -gscale * sx, gy = -gscale * sy;  // grad s
+        const float spp = sp * (1.0f - 2.0f * c);
+        float H[2][2];
+        H[0][0] = sp * fmaf(g2, sxx, -il2 * s) + spp * gx * gx;
+        H[0][1] = sp * g2 * sxy + spp * gx * gy;
+        H[1][0] = H[0][1];
+        H[1][1] = sp * fmaf(g2, syy, -il2 * s) + spp * gy * gy;
+        ld += step_logdet<2>(H, eta);
+        const float cx = sp * gx, cy = sp * gy;  // grad c
+        if (MODE == kInverse) {
+            const float rx = fabsf(x - fmaf(eta, cx, zx)), ry = fabsf(y - fmaf(eta, cy, zy));
+            rmax = fmaxf(rmax, fmaxf(rx, ry));
+        } else {
+            x = fmaf(-eta, cx, x);
+            y = fmaf(-eta, cy, y);
         }
     }
     if (half != 0 || i >= n) return;
@@ -259,12 +389,54 @@ k_grid2d_inv(const float *__restrict__ hinges, const float *__restrict__ weights
     const SplitScheme sc =
         g2_stage<TB, KS, true>(fraw, gxs, gys, rg, hinges, weights, g0, g1, kappa);
     const float beta = weights[M];
+    const int64_t wave = (int64_t)blockIdx.x * (kIvBlock / 64) + (threadIdx.x >> 6);
+    const int64_t i = wave * 32 + (threadIdx.x & 31);
+    const int64_t ic = i < n ? i : n - 1;
+    const SkipFrame<TB, KS> none = {};  // not read without ORD
     if (sc.fp16)
-        g2i_body<TB, KS, MODE, true>(fraw, sc, gxs, gys, beta, kappa, gscale, x_in, n, T, eta,
-                                     iters, x_out, logdet_out, resid_out);
+        g2i_body<TB, KS, MODE, true, false>(fraw, sc, gxs, gys, beta, kappa, gscale, x_in, n, T,
+                                            eta, iters, x_out, logdet_out, resid_out, i, ic, none);
     else
-        g2i_body<TB, KS, MODE, false>(fraw, sc, gxs, gys, beta, kappa, gscale, x_in, n, T, eta,
-                                      iters, x_out, logdet_out, resid_out);
+        g2i_body<TB, KS, MODE, false, false>(fraw, sc, gxs, gys, beta, kappa, gscale, x_in, n, T,
+                                             eta, iters, x_out, logdet_out, resid_out, i, ic, none);
+}
+
+// The same in spatial order (perm, part: launch_sort2d; block b takes its samples from
+// part b mod kSortParts, so that each part stays on one XCD).
+// (Two waves per SIMD: with three, the 168 registers hold the U, V and Q
+// accumulators and the skip tests' wave-uniform frame only with spills, even with the
+// Hessian's products in a separate pass; measured slower or no faster.)
+template <int TB, int KS, int MODE>
+__global__ void __launch_bounds__(kIvBlock) __attribute__((amdgpu_waves_per_eu(2)))
+k_grid2d_inv_sorted(const float *__restrict__ hinges, const float *__restrict__ weights, int g0,
+                    int g1, float kappa, float gscale, const float *x_in, int64_t n, int T,
+                    float eta, int iters, const uint32_t *__restrict__ perm, int64_t part,
+                    float *x_out, float *logdet_out, float *resid_out) {
+    __shared__ uint4 fraw[3 * KS * TB * 64];
+    __shared__ float gxs[16 * KS];
+    __shared__ __align__(16) float gys[32 * TB];
+    __shared__ SplitRange rg;
+    const int M = g0 * g1;
+    const SplitScheme sc =
+        g2_stage<TB, KS, true>(fraw, gxs, gys, rg, hinges, weights, g0, g1, kappa);
+    const float beta = weights[M];
+    const int64_t p = blockIdx.x % kSortParts;
+    const int64_t k =
+        ((int64_t)(blockIdx.x / kSortParts) * (kIvBlock / 64) + (threadIdx.x >> 6)) * 32 +
+        (threadIdx.x & 31);
+    const int64_t slot = p * part + k;
+    const bool live = k < part && slot < n;
+    const int64_t ic = perm[live ? slot : n - 1];
+    const int64_t i = live ? ic : n;  // n: a tail lane
+    SkipFrame<TB, KS> fr = {};
+    if (sc.fp16) {
+        skip_frame<TB, KS>(gxs, gys, g0, g1, fr);
+        g2i_body<TB, KS, MODE, true, true>(fraw, sc, gxs, gys, beta, kappa, gscale, x_in, n, T,
+                                           eta, iters, x_out, logdet_out, resid_out, i, ic, fr);
+    } else {
+        g2i_body<TB, KS, MODE, false, false>(fraw, sc, gxs, gys, beta, kappa, gscale, x_in, n, T,
+                                             eta, iters, x_out, logdet_out, resid_out, i, ic, fr);
+    }
 }
 
 // -------------------------------------------------------- pairwise path ---
@@ -382,16 +554,29 @@ k_rbf_inv(const float *__restrict__ hinges, const float *__restrict__ weights, i
 int32_t launch_morph_inverse(int dim, int mode, const float *hinges, const float *weights, int M,
                              const int *grid, float ell, const float *x_in, int64_t n, int T,
                              float eta, int iters, float *x_out, float *logdet, float *resid,
-                             hipStream_t st) {
+                             hipStream_t st, void *ws) {
     float kappa, gscale;
     derive_scales(ell, kappa, gscale);
     if (dim == 2 && grid && grid[0] >= 1 && grid[1] >= 1 && grid[0] <= 64 && grid[1] <= 64 &&
         grid[0] * grid[1] == M) {
         const int g0 = grid[0], g1 = grid[1];
-        const dim3 blocks((unsigned)((n + 127) / 128)), blk(kIvBlock);
-#define PDMP_G2I(TB, KS, MD)                                                               \
-    hipLaunchKernelGGL((k_grid2d_inv<TB, KS, MD>), blocks, blk, 0, st, hinges, weights, g0, g1, \
-                       kappa, gscale, x_in, n, T, eta, iters, x_out, logdet, resid)
+        const uint32_t *perm = nullptr;
+        int64_t part = 0;
+        const bool ord = ws && grid2d_sorted_ws_bytes(g0, g1, n, T) != 0;
+        if (ord) {
+            if (int32_t e = launch_sort2d(hinges, g0, g1, x_in, n, ws, st, &perm, &part)) return e;
+        }
+        // the ordered kernel: kSortParts interleaved runs of blocks, one per part
+        const dim3 blocks((unsigned)(ord ? kSortParts * ((part + 127) / 128) : (n + 127) / 128)),
+            blk(kIvBlock);
+#define PDMP_G2I(TB, KS, MD)                                                                     \
+    if (ord)                                                                                     \
+        hipLaunchKernelGGL((k_grid2d_inv_sorted<TB, KS, MD>), blocks, blk, 0, st, hinges, weights, \
+                           g0, g1, kappa, gscale, x_in, n, T, eta, iters, perm, part, x_out,     \
+                           logdet, resid);                                                       \
+    else                                                                                         \
+        hipLaunchKernelGGL((k_grid2d_inv<TB, KS, MD>), blocks, blk, 0, st, hinges, weights, g0,  \
+                           g1, kappa, gscale, x_in, n, T, eta, iters, x_out, logdet, resid)
 #define PDMP_G2I_KS(TB, MD)                      \
     switch ((g0 + 15) / 16) {                    \
         case 1: PDMP_G2I(TB, 1, MD); break;      \

@@ -328,8 +328,21 @@ int32_t pdmp_split_scheme(const pdmp_occupancy *occ, int32_t *scheme, void *stre
     return st;
 }
 
-int32_t pdmp_morph_logdet(const pdmp_occupancy *occ, const float *in, float *out, int64_t n,
-                          int32_t T, float eta, float *logdet, void *stream) {
+// The workspace a _ws call needs (0: none); PDMP_ENOMEM when ws is short.
+static int32_t check_morph_ws(const pdmp_occupancy *occ, int64_t n, int32_t T, void *ws,
+                              size_t ws_bytes, void **use) {
+    const size_t need = pdmp_morph_workspace_size(occ, nullptr, n, T);
+    if (need && (!ws || ws_bytes < need)) {
+        set_error("workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : (size_t)0);
+        return PDMP_ENOMEM;
+    }
+    *use = need ? ws : nullptr;
+    return PDMP_OK;
+}
+
+static int32_t logdet_impl(const pdmp_occupancy *occ, const float *in, float *out, int64_t n,
+                           int32_t T, float eta, float *logdet, void *stream, bool with_ws,
+                           void *ws, size_t ws_bytes) {
     int32_t st = check_occ(occ);
     if (st) return st;
     PDMP_REQUIRE(n >= 0, "n < 0");
@@ -337,15 +350,17 @@ int32_t pdmp_morph_logdet(const pdmp_occupancy *occ, const float *in, float *out
     PDMP_REQUIRE(std::isfinite(eta), "eta not finite");
     if (n == 0) return PDMP_OK;
     PDMP_REQUIRE(in && out, "in/out NULL");
+    void *use = nullptr;
+    if (with_ws && (st = check_morph_ws(occ, n, T, ws, ws_bytes, &use))) return st;
     if ((st = grid_check(occ, stream))) return st;
     return launch_morph_inverse(occ->dim, kLogdet, occ->hinges, occ->weights, occ->n_hinges,
                                 has_grid(occ) ? occ->grid : nullptr, occ->lengthscale, in, n, T,
-                                eta, 0, out, logdet, nullptr, (hipStream_t)stream);
+                                eta, 0, out, logdet, nullptr, (hipStream_t)stream, use);
 }
 
-int32_t pdmp_morph_inverse(const pdmp_occupancy *occ, const float *z, float *y, int64_t n,
-                           int32_t T, float eta, int32_t iters, float *logdet, float *resid,
-                           void *stream) {
+static int32_t inverse_impl(const pdmp_occupancy *occ, const float *z, float *y, int64_t n,
+                            int32_t T, float eta, int32_t iters, float *logdet, float *resid,
+                            void *stream, bool with_ws, void *ws, size_t ws_bytes) {
     int32_t st = check_occ(occ);
     if (st) return st;
     PDMP_REQUIRE(n >= 0, "n < 0");
@@ -354,10 +369,35 @@ int32_t pdmp_morph_inverse(const pdmp_occupancy *occ, const float *z, float *y, 
     PDMP_REQUIRE(std::isfinite(eta), "eta not finite");
     if (n == 0) return PDMP_OK;
     PDMP_REQUIRE(z && y, "z/y NULL");
+    void *use = nullptr;
+    if (with_ws && (st = check_morph_ws(occ, n, T, ws, ws_bytes, &use))) return st;
     if ((st = grid_check(occ, stream))) return st;
     return launch_morph_inverse(occ->dim, kInverse, occ->hinges, occ->weights, occ->n_hinges,
                                 has_grid(occ) ? occ->grid : nullptr, occ->lengthscale, z, n, T,
-                                eta, iters, y, logdet, resid, (hipStream_t)stream);
+                                eta, iters, y, logdet, resid, (hipStream_t)stream, use);
+}
+
+int32_t pdmp_morph_logdet(const pdmp_occupancy *occ, const float *in, float *out, int64_t n,
+                          int32_t T, float eta, float *logdet, void *stream) {
+    return logdet_impl(occ, in, out, n, T, eta, logdet, stream, false, nullptr, 0);
+}
+
+int32_t pdmp_morph_logdet_ws(const pdmp_occupancy *occ, const float *in, float *out, int64_t n,
+                             int32_t T, float eta, float *logdet, void *ws, size_t ws_bytes,
+                             void *stream) {
+    return logdet_impl(occ, in, out, n, T, eta, logdet, stream, true, ws, ws_bytes);
+}
+
+int32_t pdmp_morph_inverse(const pdmp_occupancy *occ, const float *z, float *y, int64_t n,
+                           int32_t T, float eta, int32_t iters, float *logdet, float *resid,
+                           void *stream) {
+    return inverse_impl(occ, z, y, n, T, eta, iters, logdet, resid, stream, false, nullptr, 0);
+}
+
+int32_t pdmp_morph_inverse_ws(const pdmp_occupancy *occ, const float *z, float *y, int64_t n,
+                              int32_t T, float eta, int32_t iters, float *logdet, float *resid,
+                              void *ws, size_t ws_bytes, void *stream) {
+    return inverse_impl(occ, z, y, n, T, eta, iters, logdet, resid, stream, true, ws, ws_bytes);
 }
 
 int32_t pdmp_mixture_samples(const pdmp_occupancy *occ, uint64_t seed, uint32_t stream_id,

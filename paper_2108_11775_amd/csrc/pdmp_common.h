@@ -131,6 +131,10 @@ int32_t launch_grid2d(int mode, const RbfArgs &a, int g0, int g1, hipStream_t st
 // path, whose workspace size is then 0.
 size_t grid2d_sorted_ws_bytes(int g0, int g1, int64_t n, int T);
 int32_t launch_grid2d_sorted(const RbfArgs &a, int g0, int g1, void *ws, hipStream_t st);
+// The counting sort alone (into a workspace of grid2d_sorted_ws_bytes): the
+// permutation in ws and the samples per part.
+int32_t launch_sort2d(const float *hinges, int g0, int g1, const float *x, int64_t n, void *ws,
+                      hipStream_t st, const uint32_t **perm, int64_t *part);
 int32_t launch_grid3d_ws(int mode, const RbfArgs &a, const int *grid, hipStream_t st);
 int32_t launch_arm_grid3d(const pdmp_arm &arm, const float *h, const float *w, int M,
                           const int *grid, float kappa, float gscale, const float *qi, float *qo,
@@ -198,11 +202,13 @@ int32_t launch_grid_wgrad(int dim, const float *hinges, int M, const int *grid, 
                           const float *x, int64_t n, const float *g, float *part, int *rows,
                           hipStream_t st);
 size_t wgrad_rows_max(int64_t n);
-// Forward morph with log-determinant (kLogdet) or its inverse by fixed point (kInverse).
+// Forward morph with log-determinant (kLogdet) or its inverse by fixed point (kInverse);
+// with ws (grid2d_sorted_ws_bytes of the batch, nonzero) a large 2-D grid batch runs
+// in spatial order, exact zeros skipped (the same bits).
 int32_t launch_morph_inverse(int dim, int mode, const float *hinges, const float *weights, int M,
                              const int *grid, float ell, const float *x_in, int64_t n, int T,
                              float eta, int iters, float *x_out, float *logdet, float *resid,
-                             hipStream_t st);
+                             hipStream_t st, void *ws = nullptr);
 // Epsilon mixture: keep[i] = (u_i < eps) from Philox, out[:, i] = x0[:, i] where kept.
 int32_t launch_mix_select(uint64_t seed, uint32_t sid, float eps, int dim, int64_t n,
                           const float *x0, float *out, uint8_t *keep, hipStream_t st);

@@ -1,9 +1,12 @@
-"""The spatially ordered morph (pdmp_morph_samples_ws): a large 2-D grid batch is
-sorted into cells and each wave skips the parts of the factorised sums that are exact
-zeros for all its samples.  Every sample must get the same bits as from the plain
-morph (whose parity against the oracle, also along its own paths, the other tests
-hold), on the headline workload at full size, ragged batches, other grid shapes, both
-split schemes, points outside the hinge range and in place."""
+"""The spatially ordered morph (pdmp_morph_samples_ws) and log-determinant / inverse
+(pdmp_morph_logdet_ws, pdmp_morph_inverse_ws): a large 2-D grid batch is sorted into
+cells and each wave skips the parts of the factorised sums (the Hessian's included)
+that are exact zeros for all its samples.  Every sample must get the same bits as from
+the unordered calls (whose parity against the oracle, also along their own paths, the
+other tests hold), on the headline workload at full size, ragged batches, other grid
+shapes, both split schemes, points outside the hinge range and in place."""
+import ctypes as C
+
 import numpy as np
 import pytest
 
@@ -138,3 +141,114 @@ def test_ordered_morph_grid_far_from_origin():
     x = np.stack([rng.uniform(ax[0] - 3, ax[-1] + 3, n),
                   rng.uniform(ay[0] - 3, ay[-1] + 3, n)]).astype(np.float32)
     _same(go, dev(x), 5, 0.05)
+
+
+def _same_logdet_inverse(go, x, T, eta, iters):
+    """Log-det of x and the inverse of its morph, ordered against unordered, bit for
+    bit (NaN where NaN)."""
+    n = int(x.shape[1])
+    ws = P.morph_workspace(go, n, T)
+    assert ws is not None
+    o1, l1 = P.morph_logdet(go, x, T, eta)
+    o2, l2 = P.morph_logdet(go, x, T, eta, ordered=True, ws=ws)
+    assert np.array_equal(host(o2), host(o1), equal_nan=True), int((host(o2) != host(o1)).sum())
+    assert np.array_equal(host(l2), host(l1), equal_nan=True), int((host(l2) != host(l1)).sum())
+    y1, m1, r1 = P.morph_inverse(go, o1, T, eta, iters)
+    y2, m2, r2 = P.morph_inverse(go, o1, T, eta, iters, ordered=True, ws=ws)
+    for a, b in ((y2, y1), (m2, m1), (r2, r1)):
+        assert np.array_equal(host(a), host(b), equal_nan=True), int((host(a) != host(b)).sum())
+    return host(o1), host(l1), host(y1)
+
+
+def test_ordered_logdet_inverse_config2_full_size_same_bits():
+    """The headline batch (2^20 samples, 64 x 64 hinges, T = 50) through the log-det and
+    the inverse with 10 fixed-point iterations per step, ordered against unordered."""
+    require_gpu()
+    cfg = K.C2
+    sc = ws_scene(cfg)
+    x0 = P.uniform_samples(I.philox_seed(cfg.cfg_id), 0, [cfg.lo] * 2, [cfg.hi] * 2,
+                           cfg.n_samples)
+    go = gpu_occ(sc["h"], sc["wb"], sc["ell"], (cfg.grid, cfg.grid))
+    assert P.split_scheme(go) == ("fp16", 3)
+    out, _, _ = _same_logdet_inverse(go, x0, cfg.T, cfg.eta, 10)
+    # in place
+    x1 = x0.clone()
+    P.morph_logdet(go, x1, cfg.T, cfg.eta, out=x1, ordered=True)
+    assert np.array_equal(host(x1), out)
+    P.sync()
+
+
+@pytest.mark.parametrize("g0,g1,scheme", [(64, 64, "fp16"), (45, 37, "fp16"), (17, 64, "fp16"),
+                                           (64, 20, "bf16")])
+def test_ordered_logdet_inverse_shapes_and_schemes(g0, g1, scheme):
+    """As test_ordered_morph_shapes_and_schemes, through the log-det and the inverse:
+    random axes, weights over several decades with random signs, a ragged batch with
+    points up to 4 lengthscales outside the grid (where the FP16 operands are scaled
+    up and the Hessian's ex dx^2 operand reaches further than ex and ex dx)."""
+    require_gpu()
+    rng = np.random.default_rng(g0 * 1000 + g1)
+    ell = 0.35
+    ax = np.sort(rng.uniform(-6, 6, g0)).astype(np.float32)
+    ay = np.sort(rng.uniform(-5, 5, g1)).astype(np.float32)
+    j = np.arange(g0 * g1)
+    h = np.stack([ax[j % g0], ay[j // g0]]).astype(np.float32)
+    wb = (rng.choice([-1.0, 1.0], g0 * g1 + 1) * 2.0 ** rng.uniform(-8, 1, g0 * g1 + 1))
+    wb = wb.astype(np.float32)
+    if scheme == "bf16":
+        wb[3] = np.float32(np.abs(wb[:-1]).max() * 2.0 ** -30)
+    go = gpu_occ(h, wb, ell, (g0, g1))
+    assert split_rule(ax, wb[:-1], ell)[0] == scheme == P.split_scheme(go)[0]
+    n = (1 << 17) + 333
+    x = np.stack([rng.uniform(-6 - 4 * ell, 6 + 4 * ell, n),
+                  rng.uniform(-5 - 4 * ell, 5 + 4 * ell, n)]).astype(np.float32)
+    _same_logdet_inverse(go, dev(x), 4, 0.05, 3)
+
+
+def test_ordered_logdet_inverse_clustered_and_far_points():
+    """Points bunched in one corner, far outside the grid, NaN coordinates and a far
+    cluster holding non-finite ones (as for the ordered morph)."""
+    require_gpu()
+    cfg = K.C2
+    sc = ws_scene(cfg)
+    go = gpu_occ(sc["h"], sc["wb"], sc["ell"], (cfg.grid, cfg.grid))
+    rng = np.random.default_rng(6)
+    n = 1 << 17
+    x = np.concatenate([rng.uniform(-10, -9, (2, n // 2)),
+                        rng.uniform(30, 40, (2, n // 4)),
+                        rng.uniform(-10, 10, (2, n - n // 2 - n // 4))], axis=1).astype(np.float32)
+    x[:, 7] = np.nan
+    x[1, 99] = np.nan
+    far = np.arange(1000, 1256)
+    x[0, far] = -40.0
+    x[1, far] = 35.0
+    x[0, far[3]] = np.nan
+    x[0, far[50]] = np.inf
+    x[1, far[100]] = np.inf
+    x[0, far[150]] = -np.inf
+    _same_logdet_inverse(go, dev(x), 6, cfg.eta, 3)
+
+
+def test_ordered_logdet_inverse_workspace_rules():
+    require_gpu()
+    cfg = K.C2
+    sc = ws_scene(cfg)
+    go = gpu_occ(sc["h"], sc["wb"], sc["ell"], (cfg.grid, cfg.grid))
+    n = 1 << 17
+    need = _lib.load().pdmp_morph_workspace_size(C.byref(go.c_struct()), None, n, 5)
+    x = P.uniform_samples(I.philox_seed(2), 3, [cfg.lo] * 2, [cfg.hi] * 2, n)
+    short = P._workspace(need - 1, x.device)
+    for call in (lambda: P.morph_logdet(go, x, 5, cfg.eta, ordered=True, ws=short),
+                 lambda: P.morph_inverse(go, x, 5, cfg.eta, 2, ordered=True, ws=short)):
+        with pytest.raises(P.PdmpError) as e:
+            call()
+        assert e.value.status == _lib.PDMP_ENOMEM
+    # a small batch, or no grid, takes the unordered kernels (no workspace needed)
+    small = P.uniform_samples(I.philox_seed(2), 4, [cfg.lo] * 2, [cfg.hi] * 2, 3000)
+    assert P.morph_workspace(go, 3000, 5) is None
+    a, la = P.morph_logdet(go, small, 5, cfg.eta, ordered=True)
+    b, lb = P.morph_logdet(go, small, 5, cfg.eta)
+    assert np.array_equal(host(a), host(b)) and np.array_equal(host(la), host(lb))
+    dense = gpu_occ(sc["h"], sc["wb"], sc["ell"])
+    ya, _, _ = P.morph_inverse(dense, small, 3, cfg.eta, 2, ordered=True)
+    yb, _, _ = P.morph_inverse(dense, small, 3, cfg.eta, 2)
+    assert np.array_equal(host(ya), host(yb))
