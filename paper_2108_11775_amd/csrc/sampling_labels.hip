@@ -114,49 +114,137 @@ __device__ __forceinline__ void count_hits_block(int c, uint64_t *n_hit) {
     if (threadIdx.x == 0 && blk) atomicAdd((unsigned long long *)n_hit, (unsigned long long)blk);
 }
 
-// Discs staged in LDS as FP64 (cx, cy, r^2) tiles: r^2 of an FP32 radius is exact in
-// FP64, so every decision is the one of the plain per-disc loop; each thread carries
-// kLabPts points (coalesced: point base + u * blockDim).
-constexpr int kLabBlock = 256;
+// Discs in tiles of kLabTile: each tile staged in LDS as FP64 (cx, cy, r^2) (r^2 of an
+// FP32 radius is exact in FP64) and culled by a 16 x 16 cell grid over the tile's
+// bounding box: cell (i, j) lists, as a bit mask, the discs whose box [c - R, c + R],
+// R = |r| (1 + 2^-20), meets it, widened by 1/64 of a cell on each side; the outer
+// cells reach to infinity (cell indices are clamped, for the discs' ranges and the
+// points alike).  A point's FP64 test  (px - cx)^2 + (py - cy)^2 <= r^2  can hold only
+// within R of the centre on each axis (the test's rounding is 2^-52 relative, the
+// index arithmetic's a few FP32 ulps, both far inside the margins), so each point
+// tests only its cell's discs and every decision is the one of the plain per-disc
+// loop.  A tile with a non-finite disc, or a degenerate box, puts every disc in every
+// cell.  Each thread carries kLabPts points (coalesced: point base + u * blockDim).
+constexpr int kLabBlock = 1024;    // 4096 points share a block's cell masks
 constexpr int kLabPts = 4;
-constexpr int kLabTile = 1024;
+constexpr int kLabTile = 128;      // discs per tile: 4 mask words per cell
+constexpr int kLabCells = 16;      // per axis
+constexpr int kLabWords = kLabTile / 32;
 
 __global__ void __launch_bounds__(kLabBlock)
 k_label_discs(const float *__restrict__ cen, const float *__restrict__ rad, int K,
               const float *__restrict__ x, int64_t n, uint8_t *out, uint64_t *n_hit) {
 #pragma clang fp contract(off)
     __shared__ double sd[3][kLabTile];
+    __shared__ uint32_t mask[kLabCells * kLabCells][kLabWords];
+    __shared__ float red[5][kLabBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t base = (int64_t)blockIdx.x * kLabBlock * kLabPts + threadIdx.x;
-    double px[kLabPts], py[kLabPts];
+    float fx[kLabPts], fy[kLabPts];
     bool hit[kLabPts];
 #pragma unroll
     for (int u = 0; u < kLabPts; ++u) {
         const int64_t i = base + (int64_t)u * kLabBlock;
         const int64_t ic = i < n ? i : n - 1;
-        px[u] = x[ic];
-        py[u] = x[(size_t)n + ic];
+        fx[u] = x[ic];
+        fy[u] = x[(size_t)n + ic];
         hit[u] = false;
     }
     for (int k0 = 0; k0 < K; k0 += kLabTile) {
         const int kn = min(kLabTile, K - k0);
-        __syncthreads();
-        for (int j = threadIdx.x; j < kn; j += kLabBlock) {
-            sd[0][j] = (double)cen[k0 + j];
-            sd[1][j] = (double)cen[K + k0 + j];
-            const double r = rad[k0 + j];
-            sd[2][j] = r * r;
+        __syncthreads();  // the previous tile's readers are done
+        // stage the tile, its bounding box and whether every disc is finite
+        float xlo = INFINITY, xhi = -INFINITY, ylo = INFINITY, yhi = -INFINITY, bad = 0.0f;
+        float cx = 0.0f, cy = 0.0f, R = 0.0f;
+        const int j = threadIdx.x;
+        if (j < kn) {
+            cx = cen[k0 + j];
+            cy = cen[K + k0 + j];
+            const float r = rad[k0 + j];
+            sd[0][j] = (double)cx;
+            sd[1][j] = (double)cy;
+            sd[2][j] = (double)r * (double)r;
+            R = fabsf(r) * (1.0f + 0x1p-20f);
+            if (!__builtin_isfinite(cx) || !__builtin_isfinite(cy) || !__builtin_isfinite(R))
+                bad = 1.0f;
+            else {
+                xlo = cx - R, xhi = cx + R, ylo = cy - R, yhi = cy + R;
+            }
+        }
+        for (int c = threadIdx.x; c < kLabCells * kLabCells * kLabWords; c += kLabBlock)
+            (&mask[0][0])[c] = 0u;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            xlo = fminf(xlo, __shfl_xor(xlo, off, 64));
+            xhi = fmaxf(xhi, __shfl_xor(xhi, off, 64));
+            ylo = fminf(ylo, __shfl_xor(ylo, off, 64));
+            yhi = fmaxf(yhi, __shfl_xor(yhi, off, 64));
+            bad = fmaxf(bad, __shfl_xor(bad, off, 64));
+        }
+        if (lane == 0) {
+            red[0][wv] = xlo, red[1][wv] = xhi, red[2][wv] = ylo, red[3][wv] = yhi;
+            red[4][wv] = bad;
         }
         __syncthreads();
-        for (int k = 0; k < kn; ++k) {
-            const double cx = sd[0][k], cy = sd[1][k], rr = sd[2][k];
 #pragma unroll
-            for (int u = 0; u < kLabPts; ++u) {
-                const double dx = px[u] - cx;
-                const double dy = py[u] - cy;
-                const double a = dx * dx;
-                const double b = dy * dy;
-                const double d2 = a + b;
-                hit[u] = hit[u] || d2 <= rr;
+        for (int w = 0; w < kLabBlock / 64; ++w) {
+            xlo = fminf(xlo, red[0][w]), xhi = fmaxf(xhi, red[1][w]);
+            ylo = fminf(ylo, red[2][w]), yhi = fmaxf(yhi, red[3][w]);
+            bad = fmaxf(bad, red[4][w]);
+        }
+        // cells per unit on each axis (0: no culling, every disc in every cell)
+        const bool cull = bad == 0.0f && xhi > xlo && yhi > ylo &&
+                          __builtin_isfinite(xhi - xlo) && __builtin_isfinite(yhi - ylo);
+        const float sx = cull ? (float)kLabCells / (xhi - xlo) : 0.0f;
+        const float sy = cull ? (float)kLabCells / (yhi - ylo) : 0.0f;
+        auto cell_of = [](float v) {  // clamped, NaN to cell 0
+            return (int)fminf(fmaxf(floorf(v), 0.0f), (float)(kLabCells - 1));
+        };
+        if (j < kn) {
+            int i0 = 0, i1 = kLabCells - 1, j0 = 0, j1 = kLabCells - 1;
+            if (cull) {
+                constexpr float m = 1.0f / 64.0f;
+                i0 = cell_of((cx - R - xlo) * sx - m), i1 = cell_of((cx + R - xlo) * sx + m);
+                j0 = cell_of((cy - R - ylo) * sy - m), j1 = cell_of((cy + R - ylo) * sy + m);
+            }
+            const uint32_t bit = 1u << (j & 31);
+            for (int cj = j0; cj <= j1; ++cj)
+                for (int ci = i0; ci <= i1; ++ci)
+                    atomicOr(&mask[cj * kLabCells + ci][j >> 5], bit);
+        }
+        __syncthreads();
+        const int words = (kn + 31) >> 5;
+        int cell[kLabPts];
+#pragma unroll
+        for (int u = 0; u < kLabPts; ++u)
+            cell[u] = cull ? cell_of((fy[u] - ylo) * sy) * kLabCells + cell_of((fx[u] - xlo) * sx)
+                           : 0;
+        for (int q = 0; q < words; ++q) {
+            // the lane's points walk their cells' discs side by side (independent tests
+            // in flight together); a point stops at its first hit
+            uint32_t mq[kLabPts];
+#pragma unroll
+            for (int u = 0; u < kLabPts; ++u) mq[u] = hit[u] ? 0u : mask[cell[u]][q];
+            while (true) {
+                uint32_t left = 0;
+#pragma unroll
+                for (int u = 0; u < kLabPts; ++u) left |= mq[u];
+                if (!left) break;
+#pragma unroll
+                for (int u = 0; u < kLabPts; ++u) {
+                    if (!mq[u]) continue;
+                    const int k = 32 * q + __builtin_ctz(mq[u]);
+                    mq[u] &= mq[u] - 1u;
+                    const double dx = (double)fx[u] - sd[0][k];
+                    const double dy = (double)fy[u] - sd[1][k];
+                    const double a = dx * dx;
+                    const double b = dy * dy;
+                    const double d2 = a + b;
+                    if (d2 <= sd[2][k]) {
+                        hit[u] = true;
+                        mq[u] = 0u;
+                    }
+                }
             }
         }
     }

@@ -49,6 +49,57 @@ def test_label_discs_bit_exact_and_count():
     assert int(host(hit)[0]) == int(ref.sum())
 
 
+def _disc_case(rng, dc, dr, x):
+    lab, hit = P.label_points_discs(dev(dc.astype(np.float32)), dev(dr.astype(np.float32)),
+                                    dev(x.astype(np.float32)), count=True)
+    ref = O.label_discs(dc.astype(np.float32), dr.astype(np.float32), x.astype(np.float32))
+    assert np.array_equal(host(lab), ref), int((host(lab) != ref).sum())
+    assert int(host(hit)[0]) == int(ref.sum())
+
+
+def test_label_discs_cell_culling_edges():
+    """The disc labels cull discs by a 16 x 16 cell grid per tile of 128 discs; every
+    decision must still be the per-disc FP64 test's: points exactly on circles (and
+    one FP32 step inside and outside), on the cell grid's lines, outside the discs' box
+    and non-finite; several tiles; tiles with a non-finite disc or a degenerate box
+    (no culling); radii of either sign and zero."""
+    require_gpu()
+    rng = np.random.default_rng(31)
+    # integer centres and radii: (cx + r, cy) lies exactly on the circle
+    K = 300
+    dc = np.stack([rng.integers(-20, 20, K), rng.integers(-20, 20, K)]).astype(np.float32)
+    dr = rng.integers(1, 4, K).astype(np.float32)
+    dr[::7] *= -1.0
+    dr[5] = 0.0
+    on = np.concatenate([np.stack([dc[0] + dr, dc[1]]), np.stack([dc[0], dc[1] - dr]),
+                         np.stack([dc[0] - np.abs(dr), dc[1]])], axis=1)
+    up = np.nextafter(on.astype(np.float32), np.float32(np.inf))
+    dn = np.nextafter(on.astype(np.float32), np.float32(-np.inf))
+    # the 16 x 16 grid of the first tile's box: points on its lines
+    lo = (dc[:, :128] - np.abs(dr[:128]) * (1 + 2.0 ** -20)).min(axis=1)
+    hi = (dc[:, :128] + np.abs(dr[:128]) * (1 + 2.0 ** -20)).max(axis=1)
+    gx = lo[0] + (hi[0] - lo[0]) * np.arange(17) / 16
+    gy = lo[1] + (hi[1] - lo[1]) * np.arange(17) / 16
+    lines = np.stack(np.meshgrid(gx, gy)).reshape(2, -1)
+    wide = rng.uniform(-60, 60, (2, 50000))
+    odd = np.array([[np.nan, 0.0, np.inf, -np.inf, 1e30, -1e30, 0.0],
+                    [0.0, np.nan, 0.0, 3.0, 1e30, 0.0, -np.inf]])
+    x = np.concatenate([on, up, dn, lines, wide, odd], axis=1)
+    _disc_case(rng, dc, dr, x)
+    # ragged batch of one tile, all discs at one point (degenerate box), a single disc
+    _disc_case(rng, np.zeros((2, 7)), np.full(7, 2.5), np.concatenate([on[:, :50], wide], axis=1))
+    _disc_case(rng, np.array([[1.5], [-2.25]]), np.array([0.75]), wide[:, :1001])
+    _disc_case(rng, np.array([[1.5], [-2.25]]), np.array([0.0]),
+               np.concatenate([np.array([[1.5], [-2.25]]), wide[:, :99]], axis=1))
+    # a non-finite disc in the second tile (that tile takes every disc in every cell)
+    dc2, dr2 = dc.copy(), dr.copy()
+    dc2[0, 130] = np.nan
+    dr2[140] = np.inf
+    dc2[1, 150] = np.inf
+    dr2[150] = np.inf
+    _disc_case(rng, dc2, dr2, x)
+
+
 def test_label_tiny_scenes_bit_exact():
     require_gpu()
     d = json.load(open(os.path.join(GOLDEN, "labels_tiny.json")))
