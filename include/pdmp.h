@@ -219,9 +219,10 @@ int32_t pdmp_morph_inverse(const pdmp_occupancy *occ, const float *z, float *y, 
  * T) bytes; 0 means the call needs none and ws is ignored): a large batch on a 2-D
  * hinge grid (the cases pdmp_morph_samples_ws orders) is first ordered by its cell
  * (in, resp. z), and every evaluation then skips, wave by wave, the exact zeros of the
- * factorised sums, Hessian included (on the FP16 scheme the Hessian's evaluations
- * keep the 16-hinge blocks up to 35 rather than 30 kappa units squared beyond c).
- * out / y, logdet and resid receive the same bits as from the calls above.
+ * factorised sums, Hessian included (its third operand, ex dx^2, reaches further than
+ * ex dx, so the Hessian's evaluations keep 16-hinge blocks out to dx^2 < c + 35
+ * kappa units squared instead of c + 30).  out / y, logdet and resid receive the same
+ * bits as from the calls above.
  * PDMP_ENOMEM if ws is short; in == out (z == y) allowed; calls that share a
  * workspace must not overlap. */
 int32_t pdmp_morph_logdet_ws(const pdmp_occupancy *occ, const float *in, float *out, int64_t n,
