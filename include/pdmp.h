@@ -25,6 +25,13 @@
  *   occupancy is defined on all of R^d, so out-of-domain samples are legal.
  * - Results are deterministic: the same call on the same inputs gives the same
  *   bits (fixed-order reductions, no floating-point atomics).
+ * - Batch sizes: one kernel dispatch covers at most 2^32 - 1 work-items, and each
+ *   kernel whose grid grows with the batch is checked against that before its
+ *   launch; a call that would exceed it returns PDMP_EINVAL instead of running a
+ *   truncated grid (work already enqueued by the call, such as a sort into the
+ *   workspace, may have run).  The 2-D and 3-D grid paths take up to 2^31 - 1024
+ *   points (two threads per point), the grid arm kernel up to 2^28 - 16
+ *   configurations (sixteen threads each).
  */
 #ifndef PDMP_H
 #define PDMP_H
@@ -160,7 +167,7 @@ int32_t pdmp_morph_samples(const pdmp_occupancy *occ, const pdmp_arm *arm, const
 
 /* The same morph with a caller workspace (pdmp_morph_workspace_size bytes: 32 KiB of
  * cell counters and 4 bytes per sample; 0 means the call needs none and ws is
- * ignored).  A large batch (2^17 <= n < 2^32, T >= 1) on a 2-D hinge grid of at most
+ * ignored).  A large batch (2^17 <= n <= 2^31 - 1024, T >= 1) on a 2-D hinge grid of at most
  * 64 x 64 is first ordered by a counting sort into 32 x 32 cells over the hinge range,
  * each eighth of the batch on its own (it is then read and written from one XCD), so
  * that the samples of a wave lie close together; each step then skips, wave by wave,

@@ -46,6 +46,8 @@ def _load():
         "orc_set_num_threads": (None, [C.c_int]),
         "orc_philox4x32_10": (None, [_u32p, _u32p, _u32p]),
         "orc_uniform_samples": (None, [C.c_uint64, C.c_uint32, _fp, _fp, C.c_int, _i64, _fp]),
+        "orc_uniform_at": (None, [C.c_uint64, C.c_uint32, _fp, _fp, C.c_int,
+                                  C.POINTER(C.c_int64), _i64, _fp]),
         "orc_label_discs": (None, [_dp, _dp, _dp, C.c_int, _dp, _i64, _u8p]),
         "orc_label_boxes": (None, [_dp, _dp, C.c_int, _dp, _i64, _u8p]),
         "orc_occ_eval": (None, [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_double, _dp, _i64,
@@ -186,6 +188,19 @@ def uniform_samples(seed: int, stream: int, lo, hi, n: int) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ labels ---
+
+def uniform_at(seed: int, stream: int, lo, hi, idx) -> np.ndarray:
+    """Samples idx (any int64 indices) of the prior batch uniform_samples(seed, stream,
+    lo, hi, n) for any n above them: [dim][len(idx)] float32."""
+    lo = np.ascontiguousarray(np.asarray(lo, dtype=np.float32).reshape(-1))
+    hi = np.ascontiguousarray(np.asarray(hi, dtype=np.float32).reshape(-1))
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).reshape(-1))
+    out = np.zeros((lo.size, idx.size), np.float32)
+    _load().orc_uniform_at(C.c_uint64(seed), C.c_uint32(stream), _P(lo, _fp), _P(hi, _fp),
+                           lo.size, idx.ctypes.data_as(C.POINTER(C.c_int64)), idx.size,
+                           _P(out, _fp))
+    return out
+
 
 def label_discs(centres, radii, x) -> np.ndarray:
     """1 where a 2-D point lies in any closed disc (the Table 1 feasibility test)."""

@@ -94,21 +94,33 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
  * Philox(counter = {i_lo, i_hi, k/4, stream}, key = {seed_lo, seed_hi});
  * u = (word >> 8) * 2^-24 in [0,1); x = lo + (hi - lo) * u in FP64, rounded
  * once to FP32. */
+static float uniform_coord(uint64_t seed, uint32_t stream, const float *lo, const float *hi,
+                           int k, int64_t i) {
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), (uint32_t)(k / 4), stream};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    double u = (double)(r[k % 4] >> 8) * (1.0 / 16777216.0);
+    double span = (double)hi[k] - (double)lo[k];
+    double t = span * u;
+    double x = (double)lo[k] + t;
+    return (float)x;
+}
+
 void orc_uniform_samples(uint64_t seed, uint32_t stream, const float *lo, const float *hi,
                          int dim, int64_t n, float *out) {
-    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-    for (int64_t i = 0; i < n; ++i) {
-        for (int k = 0; k < dim; ++k) {
-            uint32_t ctr[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), (uint32_t)(k / 4), stream};
-            uint32_t r[4];
-            orc_philox4x32_10(ctr, key, r);
-            double u = (double)(r[k % 4] >> 8) * (1.0 / 16777216.0);
-            double span = (double)hi[k] - (double)lo[k];
-            double t = span * u;
-            double x = (double)lo[k] + t;
-            out[(int64_t)k * n + i] = (float)x;
-        }
-    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < dim; ++k)
+            out[(int64_t)k * n + i] = uniform_coord(seed, stream, lo, hi, k, i);
+}
+
+/* The same batch at chosen sample indices (the counter holds the index, so a sample
+ * needs no other): out[k m + j] = coordinate k of sample idx[j]. */
+void orc_uniform_at(uint64_t seed, uint32_t stream, const float *lo, const float *hi, int dim,
+                    const int64_t *idx, int64_t m, float *out) {
+    for (int64_t j = 0; j < m; ++j)
+        for (int k = 0; k < dim; ++k)
+            out[(int64_t)k * m + j] = uniform_coord(seed, stream, lo, hi, k, idx[j]);
 }
 
 /* ------------------------------------------------------------------------- */

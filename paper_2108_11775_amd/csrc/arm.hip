@@ -398,6 +398,7 @@ static int32_t launch_morph_arm_n(const pdmp_arm &arm, const float *h, const flo
     const int nchunks = chunks_for(M);
     const size_t lds = (size_t)(nchunks < TILE ? nchunks : TILE) * ChunkLayout<3>::kBytes;
     const int64_t blocks = (n + BLOCK / kArmLanes - 1) / (BLOCK / kArmLanes);
+    if (int32_t e = grid_guard(blocks, BLOCK, "k_morph_arm")) return e;
     hipLaunchKernelGGL((k_morph_arm<NDOF, BLOCK>), dim3((unsigned)blocks), dim3(BLOCK), lds, st, arm,
                        h, w, M, kappa, gscale, qi, qo, n, T, eta, n_active, traj);
     return check_launch("k_morph_arm");
@@ -412,6 +413,7 @@ static int32_t launch_arm_max_occ_n(const pdmp_arm &arm, const float *h, const f
     const int nchunks = chunks_for(M);
     const size_t lds = (size_t)(nchunks < TILE ? nchunks : TILE) * ChunkLayout<3>::kBytes;
     const int64_t blocks = (n + BLOCK / kArmLanes - 1) / (BLOCK / kArmLanes);
+    if (int32_t e = grid_guard(blocks, BLOCK, "k_arm_max_occ")) return e;
     hipLaunchKernelGGL((k_arm_max_occ<NDOF, BLOCK>), dim3((unsigned)blocks), dim3(BLOCK), lds, st,
                        arm, h, w, M, kappa, q, n, thresh, maxc, flag);
     return check_launch("k_arm_max_occ");
@@ -436,6 +438,7 @@ int32_t launch_arm_max_occ(const pdmp_arm &arm, const float *h, const float *w, 
 int32_t launch_compact(const pdmp_arm &arm, const uint8_t *flag, const float *q, int64_t n,
                        uint32_t *counts, uint32_t *offs, uint32_t *total, uint32_t *idx, float *qc,
                        hipStream_t st) {
+    if (int32_t e = grid_guard((n + 255) / 256, 256, "compact")) return e;
     const unsigned nb = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(256), 0, st, flag, n, counts);
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, st, counts, (int)nb, offs, total);
@@ -454,6 +457,7 @@ int32_t launch_compact(const pdmp_arm &arm, const uint8_t *flag, const float *q,
 
 int32_t launch_scatter(const pdmp_arm &arm, const uint32_t *idx, const uint32_t *total,
                        const float *qc, int64_t n, float *out, hipStream_t st) {
+    if (int32_t e = grid_guard((n + 255) / 256, 256, "k_scatter")) return e;
     const unsigned nb = (unsigned)((n + 255) / 256);
     switch (arm.n_dof) {
 #define PDMP_CASE(N)                                                                           \
@@ -485,6 +489,7 @@ int32_t launch_morph_arm(const pdmp_arm &arm, const float *h, const float *w, in
 
 int32_t launch_fk_points(const pdmp_arm &arm, const float *q, int64_t n, float *pts,
                          hipStream_t st) {
+    if (int32_t e = grid_guard((n + 255) / 256, 256, "k_fk_points")) return e;
     const unsigned blocks = (unsigned)((n + 255) / 256);
     switch (arm.n_dof) {
 #define PDMP_CASE(N)                                                                    \

@@ -344,6 +344,8 @@ int32_t launch_morph_culled(const pdmp_occupancy &occ, const pdmp_cull_grid &cg,
     p += al256c((size_t)dim * n * 4);
     int *bcnt = (int *)p;  // [kCullSortBlocks][m] (LDS path)
     const bool lds_sort = m <= kCullLdsCells;
+    if (int32_t ge = grid_guard((n + kCullBlock - 1) / kCullBlock, kCullBlock, "k_cull_morph"))
+        return ge;
     const int nblk = (int)std::min<int64_t>(kCullSortBlocks, (n + 1023) / 1024);
     const int64_t chunk = (n + nblk - 1) / nblk;
 

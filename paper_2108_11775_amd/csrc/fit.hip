@@ -263,6 +263,7 @@ int32_t launch_logit_bwd(int dim, const float *hinges, const float *weights, int
 
     const float *gw = g;
     if (s_fwd) {
+        if (int32_t e = grid_guard((n + 255) / 256, 256, "k_chain_sigmoid")) return e;
         hipLaunchKernelGGL(k_chain_sigmoid, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g,
                            s_fwd, n, geff);
         if (int32_t e = check_launch("k_chain_sigmoid")) return e;
@@ -314,6 +315,7 @@ int32_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, int
                     int t, float lr, float b1, float b2, float eps, float l2, hipStream_t st) {
     const double bc1 = 1.0 / (1.0 - std::pow((double)b1, (double)t));
     const double bc2 = 1.0 / (1.0 - std::pow((double)b2, (double)t));
+    if (int32_t e = grid_guard((n + 255) / 256, 256, "k_adam")) return e;
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, g, m, v, n,
                        n_decay, lr, b1, b2, eps, (float)bc1, (float)bc2, l2);
     return check_launch("k_adam");

@@ -477,11 +477,6 @@ __device__ __forceinline__ int sort_cell(float x, float y, const float (&f)[4]) 
 constexpr int kSortBlock = 256, kSortChunk = 4096;
 constexpr int kSortKeys = kSortParts * kSortCells * kSortCells;
 
-// Samples per part: ceil(n / 8).
-__host__ __device__ __forceinline__ int64_t sort_part(int64_t n) {
-    return (n + kSortParts - 1) / kSortParts;
-}
-
 // Chunks of kSortChunk samples are cut within each part, as the morph's places are:
 // block b takes chunk b / 8 of part b mod 8, so a part's reads of x and writes of its
 // counters and permutation entries all come from one XCD.
@@ -810,6 +805,7 @@ constexpr int64_t kG2SmallBatch = (int64_t)1 << 17;
 
 static int32_t launch_grid2d_small(const RbfArgs &a, int g0, int g1, hipStream_t st) {
     const int64_t blocks = (a.n + 63) / 64;
+    if (int32_t e = grid_guard(blocks, kG2sBlock, "k_grid2d_small")) return e;
     const dim3 grid((unsigned)blocks), blk(kG2sBlock);
 #define PDMP_G2S(TB, KB)                                                                         \
     hipLaunchKernelGGL((k_grid2d_small<TB, KB, kMorph>), grid, blk, 0, st, a.hinges, a.weights, g0, \
@@ -841,6 +837,7 @@ int32_t launch_grid2d(int mode, const RbfArgs &a, int g0, int g1, hipStream_t st
     // multi-step morph takes the 16-sample waves
     if (a.n < kG2SmallBatch && mode == kMorph && a.T > 1) return launch_grid2d_small(a, g0, g1, st);
     const int64_t blocks = (a.n + 127) / 128;
+    if (int32_t e = grid_guard(blocks, kG2Block, "k_grid2d_mfma")) return e;
     const dim3 grid((unsigned)blocks), blk(kG2Block);
 #define PDMP_G2(TB, KS, MODE)                                                                  \
     hipLaunchKernelGGL((k_grid2d_mfma<TB, KS, MODE>), grid, blk, 0, st, a.hinges, a.weights, g0, \
@@ -899,6 +896,9 @@ int32_t launch_sort2d(const float *hinges, int g0, int g1, const float *x, int64
 int32_t launch_grid2d_sorted(const RbfArgs &a, int g0, int g1, void *ws, hipStream_t st) {
     if (!grid2d_sorted_ws_bytes(g0, g1, a.n, a.T) || (int64_t)g0 * g1 != a.M)
         return PDMP_EUNSUPPORTED;
+    if (int32_t e = grid_guard(kSortParts * ((sort_part(a.n) + 127) / 128), kG2Block,
+                               "k_grid2d_sorted"))
+        return e;
     const uint32_t *perm;
     int64_t part;
     if (int32_t e = launch_sort2d(a.hinges, g0, g1, a.x_in, a.n, ws, st, &perm, &part)) return e;

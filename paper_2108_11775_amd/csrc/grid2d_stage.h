@@ -90,6 +90,11 @@ __device__ __forceinline__ SplitScheme g2_stage(uint4 *fraw, float *gxs, float *
 constexpr int kSortParts = 8;  // parts of an ordered batch, one per XCD
 constexpr float kYReach = 12.5f;
 
+// Samples per part: ceil(n / 8).
+__host__ __device__ __forceinline__ int64_t sort_part(int64_t n) {
+    return (n + kSortParts - 1) / kSortParts;
+}
+
 // The wave-uniform frame of the tests: each k-step's hinge x-range and each 8-row
 // group's widened y-range (kappa units; padding excluded: a group of padding rows
 // only is never needed, its weights being zero), in scalar registers.

@@ -576,6 +576,7 @@ int32_t launch_grid3d_scheme(const float *hinges, const float *weights, const in
 int32_t launch_grid3d_ws(int mode, const RbfArgs &a, const int *grid, hipStream_t st) {
     if (!g3_supported(grid, a.M) || (mode != kEval && mode != kGrad && mode != kMorph))
         return PDMP_EUNSUPPORTED;
+    if (int32_t e = grid_guard((a.n + 127) / 128, kG3Block, "k_grid3d_ws")) return e;
     const dim3 g((unsigned)((a.n + 127) / 128)), b(kG3Block);
 #define PDMP_G3(MODE)                                                                         \
     hipLaunchKernelGGL((k_grid3d_ws<16, 16, MODE>), g, b, 0, st, a.hinges, a.weights, a.kappa, \
@@ -594,6 +595,7 @@ int32_t launch_arm_grid3d(const pdmp_arm &arm, const float *h, const float *w, i
                           float thresh, float *maxc, uint8_t *flag, hipStream_t st,
                           const Traj &traj) {
     if (!g3_supported(grid, M) || arm.pts_per_link > 8) return PDMP_EUNSUPPORTED;
+    if (int32_t e = grid_guard((n + 15) / 16, kG3Block, "k_arm_grid3d")) return e;
     const dim3 g((unsigned)((n + 15) / 16)), b(kG3Block);
     switch (arm.n_dof) {
 #define PDMP_CASE(N)                                                                            \

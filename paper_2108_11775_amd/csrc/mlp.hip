@@ -175,6 +175,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 
 template <int EPI>
 static int32_t launch_gemm(const GemmArgs &g, int splits, hipStream_t st) {
+    if (int32_t e = grid_guard(((int64_t)g.M + kGT - 1) / kGT, 256, "k_gemm")) return e;
     dim3 grid((g.M + kGT - 1) / kGT, (g.N + kGT - 1) / kGT, splits);
     hipLaunchKernelGGL(k_gemm<EPI>, grid, dim3(256), 0, st, g);
     return check_launch("k_gemm");
@@ -506,6 +507,8 @@ int32_t launch_mlp_forward(const pdmp_mlp &m, const float *q, int64_t B, float *
     if (!acts && ly.H % 32 == 0 && ly.H <= 256 && ly.n_in <= 16 && ly.L >= 2 &&
         ((uintptr_t)m.params_bf16 & 15) == 0) {
         // inference only: the fused kernel (no workspace used)
+        if (int32_t e = grid_guard((B + kMlpFB / 2 - 1) / (kMlpFB / 2), kMlpFB, "k_mlp_fused"))
+            return e;
         const dim3 grid((unsigned)((B + kMlpFB / 2 - 1) / (kMlpFB / 2)));
         switch (ly.H / 32) {
 #define PDMP_FUSED(TH)                                                                          \
@@ -538,6 +541,7 @@ int32_t launch_mlp_forward(const pdmp_mlp &m, const float *q, int64_t B, float *
         hb[1] = (uint16_t *)c;
         for (int l = 0; l < ly.L - 1; ++l) hs[l] = hb[l & 1];
     }
+    if (int32_t e = grid_guard((B * ly.n_in + 255) / 256, 256, "k_q_to_bf16")) return e;
     hipLaunchKernelGGL(k_q_to_bf16, dim3((unsigned)((B * ly.n_in + 255) / 256)), dim3(256), 0, st, q,
                        ly.n_in, B, h0);
     if (int32_t e = check_launch("k_q_to_bf16")) return e;
@@ -669,6 +673,7 @@ int32_t launch_mlp_backward(const pdmp_mlp &m, const float *qhat, const float *t
 }
 
 int32_t launch_f32_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_t st) {
+    if (int32_t e = grid_guard((n + 255) / 256, 256, "k_f32_to_bf16")) return e;
     hipLaunchKernelGGL(k_f32_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, y);
     return check_launch("k_f32_to_bf16");
 }

@@ -563,6 +563,10 @@ int32_t launch_morph_inverse(int dim, int mode, const float *hinges, const float
         const uint32_t *perm = nullptr;
         int64_t part = 0;
         const bool ord = ws && grid2d_sorted_ws_bytes(g0, g1, n, T) != 0;
+        if (int32_t e = grid_guard(ord ? kSortParts * ((sort_part(n) + 127) / 128)
+                                       : (n + 127) / 128,
+                                   kIvBlock, "k_grid2d_inv"))
+            return e;
         if (ord) {
             if (int32_t e = launch_sort2d(hinges, g0, g1, x_in, n, ws, st, &perm, &part)) return e;
         }
@@ -595,6 +599,7 @@ int32_t launch_morph_inverse(int dim, int mode, const float *hinges, const float
 #undef PDMP_G2I
         return check_launch("k_grid2d_inv");
     }
+    if (int32_t e = grid_guard((n + kIvBlock - 1) / kIvBlock, kIvBlock, "k_rbf_inv")) return e;
     const dim3 blocks((unsigned)((n + kIvBlock - 1) / kIvBlock)), blk(kIvBlock);
 #define PDMP_RI(D, MD)                                                                        \
     hipLaunchKernelGGL((k_rbf_inv<D, MD>), blocks, blk, 0, st, hinges, weights, M, ell, x_in, n, \

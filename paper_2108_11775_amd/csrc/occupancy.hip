@@ -216,10 +216,7 @@ static int32_t launch_rbf_v(const RbfArgs &a, hipStream_t st) {
     const size_t lds = (size_t)used * ChunkLayout<DIM>::kBytes;
     const int64_t per_block = (int64_t)(BLOCK / G) * SPL;
     const int64_t blocks = (a.n + per_block - 1) / per_block;
-    if (blocks > 0x7fffffff) {
-        set_error("batch too large (%lld samples)", (long long)a.n);
-        return PDMP_EUNSUPPORTED;
-    }
+    if (int32_t e = grid_guard(blocks, BLOCK, "k_rbf")) return e;
     hipLaunchKernelGGL((k_rbf<DIM, SPL, G, BLOCK, MODE>), dim3((unsigned)blocks, (unsigned)splits),
                        dim3(BLOCK), lds, st, a.hinges, a.weights, a.M, a.bias, a.kappa, a.gscale,
                        a.x_in, a.n, a.T, a.eta, a.c_out, a.s_out, a.g_out, a.x_out, a.g_in,

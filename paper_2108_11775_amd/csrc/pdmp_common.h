@@ -21,6 +21,18 @@ const char *last_error();
 // launch on this thread failed.
 int32_t check_launch(const char *what);
 
+// One dispatch covers at most 2^32 - 1 work-items per grid dimension (the dispatch
+// packet counts the grid in work-items, 32 bits): a larger grid would run truncated,
+// without an error.  Launchers whose grid grows with the batch check it first and
+// return PDMP_EINVAL (nothing launched for it).
+inline int32_t grid_guard(int64_t blocks, int64_t threads, const char *what) {
+    if (blocks >= 0 && threads >= 0 && blocks * threads <= 0xffffffffll) return 0;
+    set_error("%s: %lld blocks of %lld threads exceed one dispatch (2^32 - 1 work-items); "
+              "split the batch",
+              what, (long long)blocks, (long long)threads);
+    return PDMP_EINVAL;
+}
+
 // Argument check of an extern "C" entry point: on failure, record the message and
 // return PDMP_EINVAL.
 #define PDMP_REQUIRE(cond, ...)           \

@@ -64,6 +64,7 @@ int32_t launch_uniform(uint64_t seed, uint32_t sid, const float *lo, const float
     }
     const int64_t work = n * ((dim + 3) / 4);
     const int64_t blocks = (work + 255) / 256;
+    if (int32_t e = grid_guard(blocks, 256, "k_uniform")) return e;
     hipLaunchKernelGGL(k_uniform, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t)seed,
                        (uint32_t)(seed >> 32), sid, box, dim, n, out);
     return check_launch("k_uniform");
@@ -88,6 +89,7 @@ k_mix_select(uint32_t k0, uint32_t k1, uint32_t sid, double eps, int dim, int64_
 
 int32_t launch_mix_select(uint64_t seed, uint32_t sid, float eps, int dim, int64_t n,
                           const float *x0, float *out, uint8_t *keep, hipStream_t st) {
+    if (int32_t e = grid_guard((n + 255) / 256, 256, "k_mix_select")) return e;
     hipLaunchKernelGGL(k_mix_select, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                        (uint32_t)seed, (uint32_t)(seed >> 32), sid, (double)eps, dim, n, x0, out,
                        keep);
@@ -339,6 +341,7 @@ int32_t launch_label_discs(const pdmp_discs &sc, const float *x, int64_t n, uint
     }
     if (n == 0) return PDMP_OK;
     const int64_t per = (int64_t)kLabBlock * kLabPts;
+    if (int32_t e = grid_guard((n + per - 1) / per, kLabBlock, "k_label_discs")) return e;
     hipLaunchKernelGGL(k_label_discs, dim3((unsigned)((n + per - 1) / per)), dim3(kLabBlock), 0,
                        st, sc.centres, sc.radii, sc.n, x, n, out, n_hit);
     return check_launch("k_label_discs");
@@ -352,6 +355,7 @@ int32_t launch_label_boxes(const pdmp_boxes &sc, const float *x, int64_t n, uint
         if (int32_t e = check_launch("k_zero_u64")) return e;
     }
     if (n == 0) return PDMP_OK;
+    if (int32_t e = grid_guard((n + 255) / 256, 256, "k_label_boxes")) return e;
     hipLaunchKernelGGL(k_label_boxes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                        sc.centres, sc.half, sc.n, x, n, out, n_hit);
     return check_launch("k_label_boxes");
@@ -365,6 +369,7 @@ int32_t launch_label_configs(const pdmp_arm &arm, const pdmp_boxes &sc, const fl
         if (int32_t e = check_launch("k_zero_u64")) return e;
     }
     if (n == 0) return PDMP_OK;
+    if (int32_t e = grid_guard((n + 255) / 256, 256, "k_label_configs")) return e;
     hipLaunchKernelGGL(k_label_configs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, arm,
                        sc.centres, sc.half, sc.n, q, n, out, n_hit);
     return check_launch("k_label_configs");

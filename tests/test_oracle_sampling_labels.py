@@ -61,6 +61,22 @@ def test_uniform_samples_independent_of_batch_and_stream():
     assert a[4, 5] == np.float32((int(r[0]) >> 8) / 2.0 ** 24)
 
 
+def test_uniform_at_matches_the_batch_and_the_high_counter_word():
+    """The indexed form gives the batch's samples at any index, the counter's high word
+    included (indices at and past 2^32 from the raw Philox block)."""
+    lo, hi = [-10.0, -3.0, 0.5, 2.0, -1.0], [10.0, 3.0, 1.5, 9.0, 1.0]
+    a = O.uniform_samples(4242, 6, lo, hi, 3001)
+    idx = np.array([0, 1, 17, 1023, 3000, 2999, 5])
+    assert np.array_equal(O.uniform_at(4242, 6, lo, hi, idx), a[:, idx])
+    lo32, hi32 = np.float32(lo), np.float32(hi)
+    for i in ((1 << 31) + 7, (1 << 32) - 1, 1 << 32, (1 << 33) + 12345):
+        got = O.uniform_at(4242, 6, lo, hi, [i])[:, 0]
+        for k in range(5):
+            r = O.philox4x32_10([i & 0xFFFFFFFF, i >> 32, k // 4, 6], [4242, 0])
+            u = (int(r[k % 4]) >> 8) / 2.0 ** 24
+            assert got[k] == np.float32(float(lo32[k]) + (float(hi32[k]) - float(lo32[k])) * u)
+
+
 def test_uniform_samples_moments():
     x = O.uniform_samples(99, 0, [0.0], [1.0], 1 << 18)[0].astype(np.float64)
     n = x.size
