@@ -165,6 +165,18 @@ def parse():
     return p.parse_args()
 
 
+def median_ms(torch, f, reps=5):
+    """Median over reps calls of f, each between its own pair of HIP events."""
+    ts = []
+    for _ in range(reps):
+        t = Timer(torch)
+        with t:
+            f()
+        ts.append(t)
+    ms = sorted(t.ms() for t in ts)
+    return ms[len(ms) // 2]
+
+
 class Timer:
     """HIP events on torch's current stream (the stream every call is launched on)."""
 
@@ -857,7 +869,7 @@ AMORTISED_VARIANTS = (
 )
 AMORTISED_THRESHOLDS = (0.5, 0.3, 0.2, 0.1, 0.05, 0.02)
 # the refining variant: trigger thresholds x plain steps from q_hat
-REFINE_POINTS = tuple((th, tr) for th in (0.1, 0.05, 0.03) for tr in (6, 8, 10, 12))
+REFINE_POINTS = tuple((th, tr) for th in (0.1, 0.07, 0.05, 0.03) for tr in (6, 7, 8, 9, 10, 12))
 
 
 def amortised_frontier(P, K, torch, world, mlp, q, pl_ms, cf_plain, refine=False):
@@ -871,11 +883,9 @@ def amortised_frontier(P, K, torch, world, mlp, q, pl_ms, cf_plain, refine=False
     sweep = []
     for th, steps in points:
         o2, f2, n2 = P.amortised_morph(mlp, occ, arm, q, steps, c3.eta, th, refine=refine)
-        t = Timer(torch)
-        with t:
-            P.amortised_morph(mlp, occ, arm, q, steps, c3.eta, th, out=o2, flag=f2,
-                              n_fallback=n2, refine=refine)
-        ms2 = t.ms()
+        ms2 = median_ms(torch, lambda: P.amortised_morph(mlp, occ, arm, q, steps, c3.eta, th,
+                                                         out=o2, flag=f2, n_fallback=n2,
+                                                         refine=refine))
         _, h2 = P.label_configs(arm, *world["boxes"], o2, count=True)
         r = {"threshold": th, "ms": ms2, "speedup": pl_ms / ms2,
              "fallback_fraction": int(n2.item()) / n, "collision_free": 1 - h2.item() / n}
@@ -927,10 +937,8 @@ def amortised(args, P, I, K, torch, world):
                               n_fallback=nf)
     am_ms = t.ms() / reps
     plain_out = P.morph_samples(occ, q, c3.T, c3.eta, arm=arm)
-    t = Timer(torch)
-    with t:
-        P.morph_samples(occ, q, c3.T, c3.eta, arm=arm, out=plain_out)
-    pl_ms = t.ms()
+    pl_ms = median_ms(torch, lambda: P.morph_samples(occ, q, c3.T, c3.eta, arm=arm,
+                                                     out=plain_out))
     _, ha = P.label_configs(arm, *world["boxes"], out, count=True)
     _, hp = P.label_configs(arm, *world["boxes"], plain_out, count=True)
     _, h0 = P.label_configs(arm, *world["boxes"], q, count=True)
