@@ -456,6 +456,14 @@ int32_t pdmp_tanh_occupancy_grad(const pdmp_tanh_net *net, const float *x, int64
  * in == out allowed, other overlap not. */
 int32_t pdmp_tanh_morph_samples(const pdmp_tanh_net *net, const float *in, float *out, int64_t n,
                                 int32_t T, float eta, void *stream);
+/* The split scheme of the hidden-to-hidden products in the three calls above, as their
+ * kernels decide it on the device from the weights: *scheme = 2 when the forward
+ * products W_l a run on two FP16 parts of the power-of-two-scaled W_l and of 2^14 a
+ * (three products per FP32-accurate multiply-add; every hidden W_l finite with each
+ * nonzero |w| at least 2^-19 of its largest), 1 when they run on three-way BF16 splits
+ * (six products).  The backward products W_l^T e always take the BF16 splits.  scheme is
+ * a HOST pointer; the call waits for `stream`. */
+int32_t pdmp_tanh_split_scheme(const pdmp_tanh_net *net, int32_t *scheme, void *stream);
 
 /* Fit of the network (Sec. 3.1: binary cross-entropy minimised by a gradient-descent
  * optimiser), full batch over n >= 1 labelled points pts [dim][n], labels u8 [n]:

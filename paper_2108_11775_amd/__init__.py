@@ -26,7 +26,7 @@ __all__ = ["Occupancy", "Arm", "PdmpError", "abi_version", "uniform_samples",
            "fk_body_points", "sync",
            "occupancy_bwd", "occupancy_bwd_noalloc", "bce_logits", "adam_step", "fit_occupancy", "Mlp", "arm_max_occupancy",
            "amortised_morph", "TanhNet", "tanh_occupancy_eval", "tanh_occupancy_grad",
-           "tanh_morph_samples", "tanh_loss_grad", "tanh_fit", "morph_logdet", "morph_inverse",
+           "tanh_morph_samples", "tanh_split_scheme", "tanh_loss_grad", "tanh_fit", "morph_logdet", "morph_inverse",
            "mixture_samples", "Bucket", "Sampler", "rrt_run", "cull_grid", "morph_culled"]
 
 
@@ -680,6 +680,16 @@ def tanh_occupancy_grad(net: TanhNet, x):
     _lib.call("pdmp_tanh_occupancy_grad", C.byref(o), _dev(x, "x", torch.float32, (net.dim, n)),
               n, _dev(c, "c"), _dev(g, "grad"), _stream(x.device))
     return c, g
+
+
+def tanh_split_scheme(net: TanhNet):
+    """(name, products per FP32 multiply-add) of the forward hidden-to-hidden products
+    in the network's eval, gradient and morph kernels, as the library decides it from
+    the weights: ("fp16", 3) or ("bf16", 6).  The backward products take ("bf16", 6)."""
+    v = C.c_int32(-1)
+    o = net.c_struct()
+    _lib.call("pdmp_tanh_split_scheme", C.byref(o), C.byref(v), _stream(net.params.device))
+    return SPLIT_SCHEMES[int(v.value)]
 
 
 def tanh_morph_samples(net: TanhNet, x, T: int, eta: float, out=None):

@@ -102,6 +102,7 @@ SIGNATURES = {
     "pdmp_morph_samples_ws": (_i32, [_P(pdmp_occupancy), _P(pdmp_arm), _vp, _vp, _i64, _i32, _f,
                                      _vp, C.c_size_t, _vp]),
     "pdmp_split_scheme": (_i32, [_P(pdmp_occupancy), _P(_i32), _vp]),
+    "pdmp_tanh_split_scheme": (_i32, [_P(pdmp_tanh_net), _P(_i32), _vp]),
     "pdmp_issue_rates": (_i32, [_P(C.c_double), _i32]),
     "pdmp_morph_trajectory": (_i32, [_P(pdmp_occupancy), _P(pdmp_arm), _vp, _vp, _i64, _i32, _f,
                                      _vp, _i64, _vp]),

@@ -864,6 +864,33 @@ int32_t pdmp_tanh_occupancy_grad(const pdmp_tanh_net *net, const float *x, int64
                            (hipStream_t)stream);
 }
 
+int32_t pdmp_tanh_split_scheme(const pdmp_tanh_net *net, int32_t *scheme, void *stream) {
+    int32_t st = check_tanh(net);
+    if (st) return st;
+    PDMP_REQUIRE(scheme != nullptr, "scheme NULL");
+    *scheme = 0;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(int32_t));
+    if (e != hipSuccess) {
+        set_error("hipMalloc: %s", hipGetErrorString(e));
+        return PDMP_EDEVICE;
+    }
+    st = launch_tanh_scheme(*net, d, s);
+    int32_t v = 0;
+    if (st == PDMP_OK) {
+        e = hipMemcpyAsync(&v, d, sizeof(v), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            set_error("tanh split scheme query: %s", hipGetErrorString(e));
+            st = PDMP_EDEVICE;
+        }
+    }
+    (void)hipFree(d);
+    if (st == PDMP_OK) *scheme = v;
+    return st;
+}
+
 int32_t pdmp_tanh_morph_samples(const pdmp_tanh_net *net, const float *in, float *out, int64_t n,
                                 int32_t T, float eta, void *stream) {
     int32_t st = check_tanh(net);

@@ -240,6 +240,9 @@ int32_t launch_tanh_loss_grad(const pdmp_tanh_net &net, const float *x, const ui
 int32_t launch_tanh_fit(const pdmp_tanh_net &net, const float *x, const uint8_t *y, int64_t n,
                         int steps, float lr, float l2, float b1, float b2, float eps, float *m,
                         float *v, int t0, float *loss_out, void *ws, hipStream_t st);
+// The tanh network's forward split scheme, as its kernels choose it: *out (device) = 2
+// (FP16 parts) or 1 (BF16 parts).
+int32_t launch_tanh_scheme(const pdmp_tanh_net &net, int32_t *out, hipStream_t st);
 // The tanh occupancy network: kEval, kGrad or kMorph over n >= 1 points.
 int32_t launch_tanh_net(const pdmp_tanh_net &net, int mode, const float *x, int64_t n, int T,
                         float eta, float *c_out, float *s_out, float *g_out, float *x_out,

@@ -103,6 +103,93 @@ __device__ __forceinline__ float tn_sum4(float p) {
 
 // ---- BF16-MFMA form (morph, value, gradient) ----
 
+// The forward hidden products' scheme (the block's choice from the weights, every
+// block alike): FP16 parts when each hidden-to-hidden W_l is finite with every nonzero
+// |w| at least 2^-19 of its largest -- then 2^fsw W_l, largest in [2^14, 2^15), has
+// two FP16 parts of 11 bits each and three products carry a multiply-add at FP32
+// accuracy (mfma_split.h) -- and the layer's scale 2^(fsw + kTnAct) lies in [1, 2^100]
+// with the scaled bias at most 2^120 (the accumulator starts from it: nothing is lost
+// or overflows in scaling); three-way BF16 splits and six products otherwise.  The
+// backward products stay on BF16 parts: their vectors e_l have no bound to scale by.
+struct TnFwd {
+    int fwh;          // 1: FP16 forward products
+    int fsw[4];       // per hidden-to-hidden layer l (index l - 1): the scale exponent
+    uint32_t wmx[4], wmn[4], bmx[4];  // largest, smallest nonzero |w|; largest |b| (bits)
+};
+
+// Activations enter the FP16 forward products as 2^kTnAct a (|a| <= 1): FP16 keeps 11
+// bits of every |a| >= 2^-28 and the products stay below 2^29 in the FP32 accumulator.
+constexpr int kTnAct = 14;
+
+// Every thread of the block calls it; it synchronises the block.
+template <int L>
+__device__ void tn_forward_scheme(TnFwd &F, const float *__restrict__ P, int dim, int H) {
+    if (threadIdx.x < 4) {
+        F.wmx[threadIdx.x] = 0u;
+        F.wmn[threadIdx.x] = 0xffffffffu;
+        F.bmx[threadIdx.x] = 0u;
+    }
+    __syncthreads();
+    for (int l = 1; l < L; ++l) {
+        const float *W = P + tn_w_off(l, dim, H);  // W_l (H x H), then b_l (H)
+        uint32_t mx = 0u, mn = 0xffffffffu, bm = 0u;
+        for (int e = threadIdx.x; e < H * H; e += blockDim.x) {
+            const uint32_t u = __float_as_uint(W[e]) & 0x7fffffffu;
+            mx = max(mx, u);
+            if (u != 0u) mn = min(mn, u);
+        }
+        for (int e = threadIdx.x; e < H; e += blockDim.x)
+            bm = max(bm, __float_as_uint(W[(int64_t)H * H + e]) & 0x7fffffffu);
+        atomicMax(&F.wmx[l - 1], mx);
+        atomicMin(&F.wmn[l - 1], mn);
+        atomicMax(&F.bmx[l - 1], bm);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = L > 1;
+        for (int l = 0; l < L - 1; ++l) {
+            const uint32_t mx = F.wmx[l], mn = F.wmn[l], bm = F.bmx[l];
+            int e = 0;
+            if (mx >= 0x7f800000u || bm >= 0x7f800000u) {
+                ok = 0;  // Inf or NaN
+            } else if (mx != 0u) {
+                frexpf(__uint_as_float(mx), &e);  // largest = m 2^e, m in [0.5, 1)
+                if (__uint_as_float(mn) < ldexpf(__uint_as_float(mx), -19)) ok = 0;
+            }
+            const int fsw = mx != 0u ? 15 - e : 0;
+            if (fsw + kTnAct < 0 || fsw + kTnAct > 100 ||
+                ldexpf(__uint_as_float(bm), fsw + kTnAct) > 0x1p120f)
+                ok = 0;
+            F.fsw[l] = fsw;
+        }
+        F.fwh = ok;
+    }
+    __syncthreads();
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) k_tanh_scheme(const float *__restrict__ P, int dim, int H,
+                                                     int32_t *out) {
+    __shared__ TnFwd F;
+    tn_forward_scheme<L>(F, P, dim, H);
+    if (threadIdx.x == 0) *out = F.fwh ? 2 : 1;
+}
+
+// The forward scheme the morph, value and gradient kernel takes: 2 (FP16 parts) or 1.
+int32_t launch_tanh_scheme(const pdmp_tanh_net &net, int32_t *out, hipStream_t st) {
+#define PDMP_TS(L)                                                                         \
+    hipLaunchKernelGGL(k_tanh_scheme<L>, dim3(1), dim3(256), 0, st, net.params, net.dim, \
+                       net.hidden, out)
+    switch (net.n_hidden) {
+        case 1: PDMP_TS(1); break;
+        case 2: PDMP_TS(2); break;
+        case 3: PDMP_TS(3); break;
+        default: PDMP_TS(4); break;
+    }
+#undef PDMP_TS
+    return check_launch("k_tanh_scheme");
+}
+
 template <int DIM, int NT, int L>
 struct TnLdsX6 {
     static constexpr int HP = 16 * NT;
@@ -117,11 +204,14 @@ struct TnLdsX6 {
     float bias[L][HP];
     float vo[HP];
     float bo;
+    TnFwd F;  // the forward products' scheme
 };
 
 template <int DIM, int NT, int L>
 __device__ void tn_stage_x6(TnLdsX6<DIM, NT, L> &S, const float *__restrict__ P, int H) {
     using LD = TnLdsX6<DIM, NT, L>;
+    tn_forward_scheme<L>(S.F, P, DIM, H);
+    const bool fh = S.F.fwh != 0;
     for (int idx = threadIdx.x; idx < LD::NF / 3; idx += blockDim.x) {
         const int ln = idx & 63, q = idx >> 6;  // q = ((l-1) NT + first) KB + kb
         const int kb = q % LD::KB, first = (q / LD::KB) % NT, l = 1 + q / (LD::KB * NT);
@@ -137,12 +227,21 @@ __device__ void tn_stage_x6(TnLdsX6<DIM, NT, L> &S, const float *__restrict__ P,
             vb[j] = ok ? W[(int64_t)unit * H + other] : 0.0f;  // backward: W^T
         }
         bf16x8_t f1, f2, f3, b1, b2, b3;
-        split3(vf, f1, f2, f3);
-        split3(vb, b1, b2, b3);
         const int base = q * 3 * 64 + ln;
-        S.fw[base] = f1;
-        S.fw[base + 64] = f2;
-        S.fw[base + 128] = f3;
+        if (fh) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) vf[j] = ldexpf(vf[j], S.F.fsw[l - 1]);
+            f16x8_t h1, h2;
+            split2h(vf, h1, h2);
+            reinterpret_cast<f16x8_t *>(S.fw)[base] = h1;
+            reinterpret_cast<f16x8_t *>(S.fw)[base + 64] = h2;
+        } else {
+            split3(vf, f1, f2, f3);
+            S.fw[base] = f1;
+            S.fw[base + 64] = f2;
+            S.fw[base + 128] = f3;
+        }
+        split3(vb, b1, b2, b3);
         S.bw[base] = b1;
         S.bw[base + 64] = b2;
         S.bw[base + 128] = b3;
@@ -175,8 +274,9 @@ __device__ __forceinline__ void tn_kblock(const f32x4_tn (&v)[NT], int kb, bf16x
     split3(b, p1, p2, p3);
 }
 
-// s (all four lanes of the point) and, with GRAD, grad_x s at the point x.
-template <int DIM, int NT, int L, bool GRAD>
+// s (all four lanes of the point) and, with GRAD, grad_x s at the point x; with FH
+// the forward hidden products on the FP16 parts (the block's scheme, S.fwh).
+template <int DIM, int NT, int L, bool GRAD, bool FH>
 __device__ __forceinline__ void tn_point_x6(const TnLdsX6<DIM, NT, L> &S, const float (&x)[DIM],
                                             float &s, float (&g)[DIM]) {
     using LD = TnLdsX6<DIM, NT, L>;
@@ -214,22 +314,41 @@ __device__ __forceinline__ void tn_point_x6(const TnLdsX6<DIM, NT, L> &S, const 
 #pragma unroll
     for (int l = 1; l < L; ++l) {
         f32x4_tn z[NT];
+        // FP16 products accumulate 2^(fsw + kTnAct) (W a + b), unscaled below (exact)
+        const int zs = FH ? S.F.fsw[l - 1] + kTnAct : 0;
 #pragma unroll
         for (int to = 0; to < NT; ++to) {
             const float4 bb = tn_ld4(&S.bias[l][16 * to + u4]);
-            z[to][0] = bb.x;
-            z[to][1] = bb.y;
-            z[to][2] = bb.z;
-            z[to][3] = bb.w;
+            z[to][0] = FH ? ldexpf(bb.x, zs) : bb.x;
+            z[to][1] = FH ? ldexpf(bb.y, zs) : bb.y;
+            z[to][2] = FH ? ldexpf(bb.z, zs) : bb.z;
+            z[to][3] = FH ? ldexpf(bb.w, zs) : bb.w;
         }
 #pragma unroll
         for (int kb = 0; kb < LD::KB; ++kb) {
-            bf16x8_t b1, b2, b3;
-            tn_kblock<NT>(a, kb, b1, b2, b3);
+            if (FH) {
+                float bv[8];
 #pragma unroll
-            for (int to = 0; to < NT; ++to) {
-                const bf16x8_t *f = S.fw + (((l - 1) * NT + to) * LD::KB + kb) * 3 * 64 + lane;
-                z[to] = mfma16_x6(f[0], f[64], f[128], b1, b2, b3, z[to]);
+                for (int j = 0; j < 8; ++j) {
+                    const int t = 2 * kb + j / 4;
+                    bv[j] = t < NT ? a[t < NT ? t : 0][j & 3] * (float)(1 << kTnAct) : 0.0f;
+                }
+                f16x8_t h1, h2;
+                split2h(bv, h1, h2);
+#pragma unroll
+                for (int to = 0; to < NT; ++to) {
+                    const f16x8_t *f = reinterpret_cast<const f16x8_t *>(S.fw) +
+                                       (((l - 1) * NT + to) * LD::KB + kb) * 3 * 64 + lane;
+                    z[to] = mfma16_h3(f[0], f[64], h1, h2, z[to]);
+                }
+            } else {
+                bf16x8_t b1, b2, b3;
+                tn_kblock<NT>(a, kb, b1, b2, b3);
+#pragma unroll
+                for (int to = 0; to < NT; ++to) {
+                    const bf16x8_t *f = S.fw + (((l - 1) * NT + to) * LD::KB + kb) * 3 * 64 + lane;
+                    z[to] = mfma16_x6(f[0], f[64], f[128], b1, b2, b3, z[to]);
+                }
             }
         }
 #pragma unroll
@@ -237,7 +356,7 @@ __device__ __forceinline__ void tn_point_x6(const TnLdsX6<DIM, NT, L> &S, const 
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 float av, dv;
-                tanh_slope(z[to][v], av, dv);
+                tanh_slope(FH ? ldexpf(z[to][v], -zs) : z[to][v], av, dv);
                 a[to][v] = av;
                 d[l][to][v] = dv;
             }
@@ -317,7 +436,10 @@ k_tanh_net(const float *__restrict__ P, int H, const float *x_in, int64_t n, int
         for (int k = 0; k < DIM; ++k) x[k] = x_in[(size_t)k * n + ic];
         const int steps = MODE == kMorph ? T : 1;
         for (int st = 0; st < steps; ++st) {
-            tn_point_x6<DIM, NT, L, MODE != kEval>(S, x, s, g);
+            if (S.F.fwh)
+                tn_point_x6<DIM, NT, L, MODE != kEval, true>(S, x, s, g);
+            else
+                tn_point_x6<DIM, NT, L, MODE != kEval, false>(S, x, s, g);
             if (MODE == kMorph) {
                 float c, sp;
                 sigmoid_and_slope(s, c, sp);

@@ -74,6 +74,87 @@ def test_eval_grad_shapes(dim, H, L):
     _check_eval_grad(gnet, onet, x)
 
 
+def _tanh_rule(params, dim, H, L):
+    """The documented rule for the forward hidden products' scheme, stated here
+    independently of the library: FP16 parts (three products) when every hidden-to-
+    hidden W_l and b_l is finite, every nonzero |w| of W_l is at least 2^-19 of its
+    largest, and with m 2^e its largest (m in [0.5, 1)) the layer's scale exponent
+    z = 29 - e lies in [0, 100] with 2^z max|b_l| <= 2^120; BF16 parts otherwise."""
+    p = np.asarray(params, dtype=np.float32)
+    ok = L > 1
+    off = H * dim + H
+    for _ in range(1, L):
+        w = np.abs(p[off:off + H * H])
+        b = np.abs(p[off + H * H:off + H * H + H])
+        off += H * H + H
+        if not (np.all(np.isfinite(w)) and np.all(np.isfinite(b))):
+            ok = False
+            continue
+        e = 0
+        if w.max() > 0:
+            e = int(np.frexp(w.max())[1])
+            ok &= float(w[w > 0].min()) >= float(w.max()) * 2.0 ** -19
+        z = (15 - e if w.max() > 0 else 0) + 14
+        ok &= 0 <= z <= 100 and float(b.max()) * 2.0 ** z <= 2.0 ** 120
+    return ("fp16", 3) if ok else ("bf16", 6)
+
+
+FWD_CASES = ["fp16-edge", "fp16-small-layer", "bf16-tiny-weight", "bf16-huge-weight",
+             "bf16-tiny-layer", "bf16-large-layer", "bf16-large-bias"]
+
+
+@pytest.mark.parametrize("case", FWD_CASES)
+def test_eval_grad_forward_schemes(case):
+    """The forward hidden products run on FP16 parts of 2^fsw W_l when every nonzero
+    hidden weight is within 2^-19 of its layer's largest and the layer's scale keeps
+    its bias finite, on BF16 parts otherwise (the backward always on BF16 parts).  Both
+    schemes at their edges: weights spread over 2^-18.9 of the largest with random
+    signs, or a whole layer scaled by 2^-60 (FP16); one weight at 2^-20 of the largest,
+    one weight of 1e30 (the units it feeds saturate), a layer scaled by 2^-110 or 2^40,
+    a bias of 1e30 (BF16): the library reports the scheme the rule gives and matches
+    the oracle either way."""
+    require_gpu()
+    rng = np.random.default_rng(1 + FWD_CASES.index(case))
+    dim, H, L = 2, 64, 3
+    n_p = O.tanh_nparams(dim, H, L)
+    params = rng.normal(0, 1.0 / np.sqrt(H), n_p) * 1.5
+    w1 = H * dim + H  # W_1 starts after W_0, b_0
+    blk = params[w1:w1 + H * H]
+    if case == "fp16-edge":
+        blk[:] = np.sign(blk) * 0.4 * 2.0 ** rng.uniform(-18.9, 0, H * H)
+    elif case == "fp16-small-layer":
+        blk *= 2.0 ** -60
+    elif case == "bf16-tiny-weight":
+        blk[17] = np.abs(blk).max() * 2.0 ** -20
+    elif case == "bf16-huge-weight":
+        blk[5] = 1e30
+    elif case == "bf16-tiny-layer":
+        blk *= 2.0 ** -110
+    elif case == "bf16-large-layer":
+        blk *= 2.0 ** 40
+    else:
+        params[w1 + H * H + 3] = 1e30
+    params[w1:w1 + H * H] = blk
+    gnet, onet = _pair(dim, H, L, params)
+    want = {"fp16": ("fp16", 3), "bf16": ("bf16", 6)}[case[:4]]
+    assert _tanh_rule(params, dim, H, L) == want == P.tanh_split_scheme(gnet)
+    x = rng.uniform(-3, 3, (dim, 2049)).astype(np.float32)
+    _check_eval_grad(gnet, onet, x)
+
+
+def test_forward_scheme_of_the_trained_shapes():
+    """The networks the morph tests and the bench fit (Xavier-style weights, small
+    biases) take the FP16 forward products, one hidden layer none (no hidden-to-hidden
+    product: reported as BF16)."""
+    require_gpu()
+    rng = np.random.default_rng(11)
+    for dim, H, L in [(2, 64, 3), (3, 64, 2), (3, 32, 4), (2, 16, 1)]:
+        params = rng.normal(0, 1.0 / np.sqrt(H), O.tanh_nparams(dim, H, L))
+        gnet, _ = _pair(dim, H, L, params)
+        assert P.tanh_split_scheme(gnet) == _tanh_rule(params, dim, H, L), (dim, H, L)
+        assert P.tanh_split_scheme(gnet)[0] == ("fp16" if L > 1 else "bf16")
+
+
 def _morph_check(onet, x0, T, eta, out, idx=None):
     if idx is not None:
         x0, out = x0[:, idx], out[:, idx]
