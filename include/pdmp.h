@@ -68,7 +68,12 @@ typedef enum {
  *           splits when every nonzero |w| is at least 2^-19 of the largest and no
  *           two consecutive X0 coordinates are more than 6 sqrt(2 ln 2) l apart
  *           (morphs only), three-part BF16 splits otherwise.
- *           Hinges that are not that grid give undefined results.
+ *           Every call that takes the factorised path first checks the statement
+ *           on the device (each hinge equal, by value, to its axis coordinates; a
+ *           NaN coordinate fails).  Hinges that are not that grid give undefined
+ *           results of that call, which still runs to completion, and the next
+ *           pdmp_sync() returns PDMP_EINVAL (the flag is per device and cleared by
+ *           that report).
  * dim must be 2 or 3, M >= 1, lengthscale > 0 and finite. */
 typedef struct {
     int32_t dim;
