@@ -17,7 +17,9 @@
 // operands' range needs FP32's exponent range); each 32-row tile holds two z-planes
 // (c = 2t, 2t+1), so in the accumulator layout lane l owns the fixed y indices
 // b = (8(v/4) + 4(l/32) + v%4) mod 16 and the y/z contractions need only per-lane
-// tables of ey and ez.
+// tables of ey and ez.  The U terms are summed over z first (per y slot, the plane sums
+// with ez and with ez (z - Z_c), then one y contraction after the tiles: 2 instead of 3
+// multiply-adds per accumulator value and none per plane), the V term over y first.
 // The two lanes of a point are summed by one xor-32 exchange (bit-identical).
 //
 // Arm mapping: a wave carries 4 configurations x 8 body points of one link at a
@@ -163,15 +165,18 @@ __device__ __forceinline__ void g3_point(const uint4 *fraw, const SplitScheme &s
             if (GRAD) split3(de, d1, d2, d3);
         }
     }
-    float ey[8], dey[8];  // the lane's 8 distinct y indices
+    // ey of the lane's 8 distinct y indices; the U terms z first (per y slot u the
+    // plane sums q_u = sum_c ez_c U_(u,c) and qz_u with dez_c, contracted with ey and
+    // ey dy after the tiles), the V term y first per plane
+    float ey[8], q[8], qz[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const int b = 8 * (u >> 2) + 4 * h + (u & 3);
         const float d = ys - ay[b];
         ey[u] = exp2_fast(-d * d);
-        dey[u] = ey[u] * d;
+        q[u] = qz[u] = 0.0f;
     }
-    s = sx = sy = sz = 0.0f;
+    sx = 0.0f;
 #pragma unroll
     for (int t = 0; t < C::TB; ++t) {
         // the two z-planes of this tile
@@ -199,26 +204,31 @@ __device__ __forceinline__ void g3_point(const uint4 *fraw, const SplitScheme &s
             U = mfma_x6(a1, a2, a3, e1, e2, e3, zero);
             if (GRAD) V = mfma_x6(a1, a2, a3, d1, d2, d3, zero);
         }
-        // row i = 8(v/4) + 4h + v%4 of tile t: b = i mod 16 (table slot v%8), c = 2t + v/8;
-        // the y sums of each z-plane first, then one ez (dez) factor per plane
+        // row i = 8(v/4) + 4h + v%4 of tile t: b = i mod 16 (y slot v%8), c = 2t + v/8,
+        // so U[u] and U[u + 8] share slot u on the tile's two planes
 #pragma unroll
-        for (int cz = 0; cz < 2; ++cz) {
-            float py = 0.0f, pyx = 0.0f, pdy = 0.0f;
+        for (int u = 0; u < 8; ++u) {
+            q[u] = fmaf(ez[1], U[u + 8], fmaf(ez[0], U[u], q[u]));
+            if (GRAD) qz[u] = fmaf(dez[1], U[u + 8], fmaf(dez[0], U[u], qz[u]));
+        }
+        if (GRAD) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int v = 8 * cz + u;
-                py = fmaf(ey[u], U[v], py);
-                if (GRAD) {
-                    pyx = fmaf(ey[u], V[v], pyx);
-                    pdy = fmaf(dey[u], U[v], pdy);
-                }
-            }
-            s = fmaf(ez[cz], py, s);
-            if (GRAD) {
+            for (int cz = 0; cz < 2; ++cz) {
+                float pyx = 0.0f;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) pyx = fmaf(ey[u], V[8 * cz + u], pyx);
                 sx = fmaf(ez[cz], pyx, sx);
-                sy = fmaf(ez[cz], pdy, sy);
-                sz = fmaf(dez[cz], py, sz);
             }
+        }
+    }
+    s = sy = sz = 0.0f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        s = fmaf(ey[u], q[u], s);
+        if (GRAD) {
+            const int b = 8 * (u >> 2) + 4 * h + (u & 3);
+            sy = fmaf(ey[u] * (ys - ay[b]), q[u], sy);
+            sz = fmaf(ey[u], qz[u], sz);
         }
     }
     s += __shfl_xor(s, 32, 64);
@@ -290,6 +300,7 @@ __device__ __forceinline__ void g3_ws_body(const uint4 *fraw, const SplitScheme 
 
 template <int G0, int G2, int MODE>
 __global__ void __launch_bounds__(kG3Block)
+__attribute__((amdgpu_waves_per_eu(MODE == kMorph ? 3 : 1)))
 k_grid3d_ws(const float *__restrict__ hinges, const float *__restrict__ weights, float kappa,
             float gscale, const float *x_in, int64_t n, int T, float eta, float *c_out,
             float *s_out, float *g_out, float *x_out, Traj tr) {
