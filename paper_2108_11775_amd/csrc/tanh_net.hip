@@ -41,6 +41,16 @@ __device__ __forceinline__ void tanh_slope(float z, float &a, float &d) {
     d = 4.0f * e * (r * r);
 }
 
+// The same from a pre-activation held scaled by 2^zs, k = -2 log2(e) 2^-zs, returning
+// as tanh (as a power of two): both scalings are exact, so a / as and d are the bits
+// tanh_slope gives for z 2^-zs.
+__device__ __forceinline__ void tanh_slope_sc(float z, float k, float as, float &a, float &d) {
+    const float e = exp2_fast(k * fabsf(z));
+    const float r = __builtin_amdgcn_rcpf(1.0f + e);
+    a = copysignf((1.0f - e) * (r * as), z);
+    d = 4.0f * e * (r * r);
+}
+
 template <int DIM, int NT, int L>
 struct TnLds {
     static constexpr int HP = 16 * NT;
@@ -253,7 +263,9 @@ __device__ void tn_stage_x6(TnLdsX6<DIM, NT, L> &S, const float *__restrict__ P,
 #pragma unroll
         for (int l = 0; l < L; ++l) {
             const int64_t bo = tn_w_off(l, DIM, H) + (int64_t)H * (l == 0 ? DIM : H);
-            S.bias[l][idx] = ok ? P[bo + idx] : 0.0f;
+            // FP16 forward: the hidden biases enter the accumulator as 2^(fsw + kTnAct) b
+            const float b = ok ? P[bo + idx] : 0.0f;
+            S.bias[l][idx] = fh && l > 0 ? ldexpf(b, S.F.fsw[l - 1] + kTnAct) : b;
         }
         S.vo[idx] = ok ? P[tn_w_off(L, DIM, H) + idx] : 0.0f;
     }
@@ -305,7 +317,8 @@ __device__ __forceinline__ void tn_point_x6(const TnLdsX6<DIM, NT, L> &S, const 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             float av, dv;
-            tanh_slope(z[v], av, dv);
+            // FP16 forward: the activations feeding a hidden product are held as 2^kTnAct a
+            tanh_slope_sc(z[v], -2.0f * kLog2e, FH ? (float)(1 << kTnAct) : 1.0f, av, dv);
             a[t][v] = av;
             d[0][t][v] = dv;
         }
@@ -314,15 +327,16 @@ __device__ __forceinline__ void tn_point_x6(const TnLdsX6<DIM, NT, L> &S, const 
 #pragma unroll
     for (int l = 1; l < L; ++l) {
         f32x4_tn z[NT];
-        // FP16 products accumulate 2^(fsw + kTnAct) (W a + b), unscaled below (exact)
-        const int zs = FH ? S.F.fsw[l - 1] + kTnAct : 0;
+        // FP16 products accumulate 2^(fsw + kTnAct) (W a + b) from the bias staged at
+        // that scale; the tanh below takes the unscaling in its exponent (exact)
+        const float kz = FH ? ldexpf(-2.0f * kLog2e, -(S.F.fsw[l - 1] + kTnAct)) : -2.0f * kLog2e;
 #pragma unroll
         for (int to = 0; to < NT; ++to) {
             const float4 bb = tn_ld4(&S.bias[l][16 * to + u4]);
-            z[to][0] = FH ? ldexpf(bb.x, zs) : bb.x;
-            z[to][1] = FH ? ldexpf(bb.y, zs) : bb.y;
-            z[to][2] = FH ? ldexpf(bb.z, zs) : bb.z;
-            z[to][3] = FH ? ldexpf(bb.w, zs) : bb.w;
+            z[to][0] = bb.x;
+            z[to][1] = bb.y;
+            z[to][2] = bb.z;
+            z[to][3] = bb.w;
         }
 #pragma unroll
         for (int kb = 0; kb < LD::KB; ++kb) {
@@ -331,7 +345,7 @@ __device__ __forceinline__ void tn_point_x6(const TnLdsX6<DIM, NT, L> &S, const 
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const int t = 2 * kb + j / 4;
-                    bv[j] = t < NT ? a[t < NT ? t : 0][j & 3] * (float)(1 << kTnAct) : 0.0f;
+                    bv[j] = t < NT ? a[t < NT ? t : 0][j & 3] : 0.0f;  // 2^kTnAct a
                 }
                 f16x8_t h1, h2;
                 split2h(bv, h1, h2);
@@ -356,7 +370,9 @@ __device__ __forceinline__ void tn_point_x6(const TnLdsX6<DIM, NT, L> &S, const 
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 float av, dv;
-                tanh_slope(FH ? ldexpf(z[to][v], -zs) : z[to][v], av, dv);
+                // scaled by 2^kTnAct again where the next hidden product takes it
+                tanh_slope_sc(z[to][v], kz, FH && l + 1 < L ? (float)(1 << kTnAct) : 1.0f, av,
+                              dv);
                 a[to][v] = av;
                 d[l][to][v] = dv;
             }
