@@ -106,6 +106,12 @@ def test_tanh_network_shapes_checked_on_the_host():
     assert lib.pdmp_tanh_morph_samples(C.byref(fake), None, None, 1, -1, 0.1, None) == \
         _lib.PDMP_EINVAL
     assert lib.pdmp_tanh_morph_samples(C.byref(fake), None, None, 0, 3, 0.1, None) == 0
+    # the forward scheme query: the network and the out-pointer are checked first
+    v = C.c_int32(-1)
+    assert lib.pdmp_tanh_split_scheme(None, C.byref(v), None) == _lib.PDMP_EINVAL
+    assert lib.pdmp_tanh_split_scheme(C.byref(net), C.byref(v), None) == _lib.PDMP_EINVAL
+    assert lib.pdmp_tanh_split_scheme(C.byref(fake), None, None) == _lib.PDMP_EINVAL
+    assert b"scheme" in lib.pdmp_last_error()
     import paper_2108_11775_amd as P
     with pytest.raises(ValueError):
         P.TanhNet(2, 100, 2, None)
