@@ -541,8 +541,9 @@ int32_t launch_tanh_net(const pdmp_tanh_net &net, int mode, const float *x, int6
 //   k_tanh_wgrad   dW_l = sum_i e_{l+1,i} [a_{l,i}; 1]^T (the bias as a column of ones;
 //                  layer L: r against [a_L; 1]) as 16 x 16 tiles on FP32 MFMA with the
 //                  points as contraction index, in fixed point ranges -> partial rows;
+//                  the first split's row carries + l2 w on the weight entries (not the
+//                  biases) and, when the loss is asked for, each tile's sum of w^2;
 //   k_sum_rows     fixed-order sum of the partial rows (fit.hip);
-//   k_tanh_decay   + l2 w on the weight entries (not the biases);
 //   Adam           (fit.hip).
 
 template <int DIM, int NT, int L>
@@ -697,12 +698,16 @@ struct TnGradTiles {
 
 // Partial rows of the loss gradient: block (tile, split).  Layer l < L: rows o of
 // E_{l+1} (H), columns i of [a_l; 1] (n_l + 1, a_0 = x); layer L: the single row r
-// against [a_L; 1].  Points of split s: [s kps, min(n, (s+1) kps)).
+// against [a_L; 1].  Points of split s: [s kps, min(n, (s+1) kps)).  The blocks of
+// split 0 add the decay l2 w to the weight entries of their tile and, with wsq_part,
+// write the tile's sum of w^2 (FP64, fixed order) to wsq_part[tile].
 __global__ void __launch_bounds__(256)
 k_tanh_wgrad(int dim, int H, int L, const float *__restrict__ x, const float *__restrict__ A,
              const float *__restrict__ E, const float *__restrict__ r, int64_t n, int64_t kps,
-             TnGradTiles tt, int64_t np, float *__restrict__ part) {
+             TnGradTiles tt, int64_t np, const float *__restrict__ P, float l2,
+             float *__restrict__ part, double *__restrict__ wsq_part) {
     __shared__ float red[256];
+    __shared__ double rw[256];
     const int tile = blockIdx.x;
     int l = 0;
     while (l < L && tile >= tt.start[l + 1]) ++l;
@@ -742,68 +747,26 @@ k_tanh_wgrad(int dim, int H, int L, const float *__restrict__ x, const float *__
         __syncthreads();
     }
     const int o = 16 * ro + (threadIdx.x >> 4), i = 16 * co + (threadIdx.x & 15);
-    if (o >= rows || i > nl) return;
+    const bool in = o < rows && i <= nl;
     const int64_t off = (int64_t)(l == 0 ? 0 : (int64_t)H * dim + H + (int64_t)(l - 1) * (H * H + H));
-    int64_t j;
+    int64_t j = 0;
     if (l < L) j = i < nl ? off + (int64_t)o * nl + i : off + (int64_t)H * nl + o;
     else j = off + i;  // v entries, then b_o at i == H
-    part[(size_t)blockIdx.y * np + j] = red[threadIdx.x];
-}
-
-// grad += l2 w on the weight entries (W_l and v), not on the biases.
-__global__ void __launch_bounds__(256)
-k_tanh_decay(float *grad, const float *__restrict__ P, int dim, int H, int L, int64_t np,
-             float l2) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= np) return;
-    int64_t off = 0;
-    bool w = false;
-    for (int l = 0; l <= L; ++l) {
-        const int64_t nw = l < L ? (int64_t)H * (l == 0 ? dim : H) : H;
-        const int64_t nb = l < L ? H : 1;
-        if (j < off + nw) {
-            w = true;
-            break;
-        }
-        if (j < off + nw + nb) break;
-        off += nw + nb;
+    const bool wt = in && i < nl;  // a weight entry (i == nl is the bias column)
+    if (blockIdx.y != 0) {
+        if (in) part[(size_t)blockIdx.y * np + j] = red[threadIdx.x];
+        return;
     }
-    if (w) grad[j] = fmaf(l2, P[j], grad[j]);
-}
-
-// out[0] = sum of squares of the weight entries, one block, fixed order.  1024 threads
-// with four independent loads in flight each: the few thousand weights take a handful
-// of memory round trips instead of one per entry of a 256-thread loop.
-constexpr int kTnWsqBlock = 1024;
-__global__ void __launch_bounds__(kTnWsqBlock)
-k_tanh_wsq(const float *__restrict__ P, int dim, int H, int L, double *out) {
-    __shared__ double sh[kTnWsqBlock];
-    double acc = 0.0;
-    int64_t off = 0;
-    for (int l = 0; l <= L; ++l) {
-        const int64_t nw = l < L ? (int64_t)H * (l == 0 ? dim : H) : H;
-        int64_t j = threadIdx.x;
-        for (; j + 3 * kTnWsqBlock < nw; j += 4 * kTnWsqBlock) {
-            const double w0 = P[off + j], w1 = P[off + j + kTnWsqBlock];
-            const double w2 = P[off + j + 2 * kTnWsqBlock], w3 = P[off + j + 3 * kTnWsqBlock];
-            acc += w0 * w0;
-            acc += w1 * w1;
-            acc += w2 * w2;
-            acc += w3 * w3;
-        }
-        for (; j < nw; j += kTnWsqBlock) {
-            const double w = P[off + j];
-            acc += w * w;
-        }
-        off += nw + (l < L ? H : 1);
-    }
-    sh[threadIdx.x] = acc;
+    const float w = wt ? P[j] : 0.0f;
+    if (in) part[j] = wt ? fmaf(l2, w, red[threadIdx.x]) : red[threadIdx.x];
+    if (!wsq_part) return;  // uniform over the block
+    rw[threadIdx.x] = (double)w * (double)w;
     __syncthreads();
-    for (unsigned s2 = kTnWsqBlock / 2; s2 >= 1; s2 >>= 1) {
-        if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
+    for (unsigned s2 = 128; s2 >= 1; s2 >>= 1) {
+        if (threadIdx.x < s2) rw[threadIdx.x] += rw[threadIdx.x + s2];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = sh[0];
+    if (threadIdx.x == 0) wsq_part[tile] = rw[0];
 }
 
 static void tn_grad_tiles(int dim, int H, int L, TnGradTiles &tt) {
@@ -836,7 +799,8 @@ size_t tanh_fit_ws_bytes(const pdmp_tanh_net &net, int64_t n) {
     int64_t kps;
     const int S = tn_splits(n, tt.start[L + 1], kps);
     return 2 * al256t((size_t)(L * H * n) * 4) + 2 * al256t((size_t)n * 4) +
-           al256t((size_t)S * np * 4) + al256t((size_t)np * 4) + al256t(1024 * 8) + al256t(8);
+           al256t((size_t)S * np * 4) + al256t((size_t)np * 4) + al256t(1024 * 8) +
+           al256t((size_t)tt.start[L + 1] * 8);
 }
 
 template <int DIM, int NT, int L>
@@ -885,7 +849,7 @@ int32_t launch_tanh_loss_grad(const pdmp_tanh_net &net, const float *x, const ui
     p += al256t((size_t)np * 4);  // spare (keeps the layout of the fit workspace)
     double *rparts = (double *)p;
     p += al256t(1024 * 8);
-    double *wsq = (double *)p;
+    double *wsq = (double *)p;  // per tile: the sum of w^2 of its weight entries
 
 #define PDMP_TNFB(D)                                                                 \
     if (H <= 16) tn_fb_depth<D, 1>(net, x, y, n, A, E, r, bce, st);                  \
@@ -899,18 +863,13 @@ int32_t launch_tanh_loss_grad(const pdmp_tanh_net &net, const float *x, const ui
 #undef PDMP_TNFB
     if (int32_t e = check_launch("k_tanh_fb")) return e;
     hipLaunchKernelGGL(k_tanh_wgrad, dim3((unsigned)tt.start[L + 1], (unsigned)S), dim3(256), 0, st,
-                       dim, H, L, x, A, E, r, n, kps, tt, np, part);
+                       dim, H, L, x, A, E, r, n, kps, tt, np, net.params, l2, part,
+                       loss ? wsq : nullptr);
     if (int32_t e = check_launch("k_tanh_wgrad")) return e;
     if (int32_t e = launch_sum_rows(part, S, np, 1.0, nullptr, 0.0f, grad, st)) return e;
-    hipLaunchKernelGGL(k_tanh_decay, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, grad,
-                       net.params, dim, H, L, np, l2);
-    if (int32_t e = check_launch("k_tanh_decay")) return e;
     if (loss) {
-        hipLaunchKernelGGL(k_tanh_wsq, dim3(1), dim3(kTnWsqBlock), 0, st, net.params, dim, H, L,
-                           wsq);
-        if (int32_t e = check_launch("k_tanh_wsq")) return e;
-        if (int32_t e = launch_sum_with(bce, n, 1.0 / (double)n, wsq, 1, 0.5 * (double)l2, loss,
-                                        rparts, st))
+        if (int32_t e = launch_sum_with(bce, n, 1.0 / (double)n, wsq, tt.start[L + 1],
+                                        0.5 * (double)l2, loss, rparts, st))
             return e;
     }
     return PDMP_OK;
