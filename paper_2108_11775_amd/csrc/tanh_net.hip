@@ -535,7 +535,7 @@ int32_t launch_tanh_net(const pdmp_tanh_net &net, int mode, const float *x, int6
 // ------------------------------------------------------------------ fit ---
 //
 // BCE fit of the network (Sec. 3.1), full batch over n labelled points.  One step:
-//   k_tanh_fb      per point: forward, r = (sigma(s) - y)/n, the per-point BCE, and
+//   k_tanh_fb      per point: forward, r = (sigma(s) - y)/n, the BCE (summed per block), and
 //                  the reverse pass e_L = r v (1 - a_L^2), e_l = (1 - a_l^2) W_l^T e_{l+1};
 //                  stores a_l and e_l ([layer][unit][point], coalesced per unit);
 //   k_tanh_wgrad   dW_l = sum_i e_{l+1,i} [a_{l,i}; 1]^T (the bias as a column of ones;
@@ -544,17 +544,20 @@ int32_t launch_tanh_net(const pdmp_tanh_net &net, int mode, const float *x, int6
 //                  the first split's row carries + l2 w on the weight entries (not the
 //                  biases) and, when the loss is asked for, each tile's sum of w^2;
 //   k_sum_rows     fixed-order sum of the partial rows (fit.hip);
+//   k_tanh_loss    the loss from the two kernels' partial sums (when asked for);
 //   Adam           (fit.hip).
 
 template <int DIM, int NT, int L>
 __global__ void __launch_bounds__(kTnBlock)
 k_tanh_fb(const float *__restrict__ P, int H, const float *__restrict__ x,
           const uint8_t *__restrict__ y, int64_t n, float inv_n, float *__restrict__ A,
-          float *__restrict__ E, float *__restrict__ r_out, float *__restrict__ bce_out) {
+          float *__restrict__ E, float *__restrict__ r_out, double *__restrict__ bce_part) {
     __shared__ __attribute__((aligned(16))) TnLds<DIM, NT, L> S;
+    __shared__ double rb[kTnBlock];
     tn_stage<DIM, NT, L>(S, P, H);
     __syncthreads();
     const int lane = threadIdx.x & 63, quad = lane >> 4, u4 = 4 * quad;
+    double bacc = 0.0;  // this lane's points' BCE (quad 0 lanes), in tile order
     const int64_t tiles = (n + kTnPts - 1) / kTnPts;
     const int64_t wstride = (int64_t)gridDim.x * (kTnBlock / 64);
     for (int64_t tile = (int64_t)blockIdx.x * (kTnBlock / 64) + (threadIdx.x >> 6); tile < tiles;
@@ -647,7 +650,7 @@ k_tanh_fb(const float *__restrict__ P, int H, const float *__restrict__ x,
         const float r = ok ? (yes ? -sig_neg : sig_pos) * inv_n : 0.0f;
         if (ok && quad == 0) {
             r_out[i] = r;
-            bce_out[i] = fmaxf(s, 0.0f) - yv * s + log1pf(e1);
+            bacc += (double)(fmaxf(s, 0.0f) - yv * s + log1pf(e1));
         }
         f32x4_tn e[NT];
 #pragma unroll
@@ -687,6 +690,37 @@ k_tanh_fb(const float *__restrict__ P, int H, const float *__restrict__ x,
                 }
         }
     }
+    if (!bce_part) return;  // uniform over the block
+    // the block's BCE sum, fixed order
+    rb[threadIdx.x] = bacc;
+    __syncthreads();
+    for (unsigned s2 = kTnBlock / 2; s2 >= 1; s2 >>= 1) {
+        if (threadIdx.x < s2) rb[threadIdx.x] += rb[threadIdx.x + s2];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bce_part[blockIdx.x] = rb[0];
+}
+
+// out = sa sum_{i < na} a[i] + sb sum_{i < nb} b[i], one block, fixed order (the loss
+// from the BCE partials of k_tanh_fb and the w^2 partials of k_tanh_wgrad).
+__global__ void __launch_bounds__(256)
+k_tanh_loss(const double *__restrict__ a, int na, double sa, const double *__restrict__ b, int nb,
+            double sb, float *out) {
+    __shared__ double sh[2][256];
+    double ta = 0.0, tb = 0.0;
+    for (int i = threadIdx.x; i < na; i += 256) ta += a[i];
+    for (int i = threadIdx.x; i < nb; i += 256) tb += b[i];
+    sh[0][threadIdx.x] = ta;
+    sh[1][threadIdx.x] = tb;
+    __syncthreads();
+    for (unsigned s2 = 128; s2 >= 1; s2 >>= 1) {
+        if (threadIdx.x < s2) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + s2];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + s2];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = (float)(sa * sh[0][0] + sb * sh[1][0]);
 }
 
 // Tiles of the weight-gradient products, layer by layer (at most kTnMaxLayers + 1).
@@ -798,24 +832,29 @@ size_t tanh_fit_ws_bytes(const pdmp_tanh_net &net, int64_t n) {
     tn_grad_tiles(net.dim, net.hidden, net.n_hidden, tt);
     int64_t kps;
     const int S = tn_splits(n, tt.start[L + 1], kps);
-    return 2 * al256t((size_t)(L * H * n) * 4) + 2 * al256t((size_t)n * 4) +
+    return 2 * al256t((size_t)(L * H * n) * 4) + al256t((size_t)n * 4) +
            al256t((size_t)S * np * 4) + al256t((size_t)np * 4) + al256t(1024 * 8) +
            al256t((size_t)tt.start[L + 1] * 8);
 }
 
+// Blocks of k_tanh_fb for n points: a wave per tile of 16 points, at most 1024 blocks.
+static int tn_fb_blocks(int64_t n) {
+    const int64_t tiles = (n + kTnPts - 1) / kTnPts;
+    const int64_t blocks = (tiles + 3) / 4;
+    return (int)(blocks < 1024 ? blocks : 1024);
+}
+
 template <int DIM, int NT, int L>
 static void tn_fb_launch(const pdmp_tanh_net &net, const float *x, const uint8_t *y, int64_t n,
-                         float *A, float *E, float *r, float *bce, hipStream_t st) {
-    const int64_t tiles = (n + kTnPts - 1) / kTnPts;
-    int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 1024) blocks = 1024;
+                         float *A, float *E, float *r, double *bce, hipStream_t st) {
+    const int blocks = tn_fb_blocks(n);
     hipLaunchKernelGGL((k_tanh_fb<DIM, NT, L>), dim3((unsigned)blocks), dim3(kTnBlock), 0, st,
                        net.params, net.hidden, x, y, n, (float)(1.0 / (double)n), A, E, r, bce);
 }
 
 template <int DIM, int NT>
 static void tn_fb_depth(const pdmp_tanh_net &net, const float *x, const uint8_t *y, int64_t n,
-                        float *A, float *E, float *r, float *bce, hipStream_t st) {
+                        float *A, float *E, float *r, double *bce, hipStream_t st) {
     switch (net.n_hidden) {
         case 1: tn_fb_launch<DIM, NT, 1>(net, x, y, n, A, E, r, bce, st); break;
         case 2: tn_fb_launch<DIM, NT, 2>(net, x, y, n, A, E, r, bce, st); break;
@@ -842,14 +881,13 @@ int32_t launch_tanh_loss_grad(const pdmp_tanh_net &net, const float *x, const ui
     p += al256t((size_t)L * H * n * 4);
     float *r = (float *)p;
     p += al256t((size_t)n * 4);
-    float *bce = (float *)p;
-    p += al256t((size_t)n * 4);
     float *part = (float *)p;
     p += al256t((size_t)S * np * 4);
     p += al256t((size_t)np * 4);  // spare (keeps the layout of the fit workspace)
-    double *rparts = (double *)p;
+    double *rparts = (double *)p;  // per k_tanh_fb block: the sum of its points' BCE
     p += al256t(1024 * 8);
     double *wsq = (double *)p;  // per tile: the sum of w^2 of its weight entries
+    double *bce = loss ? rparts : nullptr;
 
 #define PDMP_TNFB(D)                                                                 \
     if (H <= 16) tn_fb_depth<D, 1>(net, x, y, n, A, E, r, bce, st);                  \
@@ -868,9 +906,9 @@ int32_t launch_tanh_loss_grad(const pdmp_tanh_net &net, const float *x, const ui
     if (int32_t e = check_launch("k_tanh_wgrad")) return e;
     if (int32_t e = launch_sum_rows(part, S, np, 1.0, nullptr, 0.0f, grad, st)) return e;
     if (loss) {
-        if (int32_t e = launch_sum_with(bce, n, 1.0 / (double)n, wsq, tt.start[L + 1],
-                                        0.5 * (double)l2, loss, rparts, st))
-            return e;
+        hipLaunchKernelGGL(k_tanh_loss, dim3(1), dim3(256), 0, st, rparts, tn_fb_blocks(n),
+                           1.0 / (double)n, wsq, tt.start[L + 1], 0.5 * (double)l2, loss);
+        if (int32_t e = check_launch("k_tanh_loss")) return e;
     }
     return PDMP_OK;
 }
@@ -887,7 +925,7 @@ int32_t launch_tanh_fit(const pdmp_tanh_net &net, const float *x, const uint8_t 
     int64_t kps;
     const int S = tn_splits(n, tt.start[L + 1], kps);
     char *p = (char *)ws;
-    p += 2 * al256t((size_t)L * H * n * 4) + 2 * al256t((size_t)n * 4) + al256t((size_t)S * np * 4);
+    p += 2 * al256t((size_t)L * H * n * 4) + al256t((size_t)n * 4) + al256t((size_t)S * np * 4);
     float *grad = (float *)p;
     for (int t = 0; t < steps; ++t) {
         if (int32_t e = launch_tanh_loss_grad(net, x, y, n, l2, loss_out ? loss_out + t : nullptr,
