@@ -863,11 +863,56 @@ static void tn_fb_depth(const pdmp_tanh_net &net, const float *x, const uint8_t 
     }
 }
 
+// One Adam step's state and coefficients (bc1 = 1/(1 - beta1^t), bc2 = 1/(1 - beta2^t)).
+struct TnAdam {
+    float *m, *v;
+    float lr, b1, b2, eps, bc1, bc2;
+};
+
+// grad[j] = sum_{r < rows} part[r np + j] in the order of k_sum_rows (sixteen phases
+// summing the rows r = ph mod 16 in increasing order, four loads at a time, the phases
+// added in order), then the Adam step of parameter j on it (the update of k_adam).
+constexpr int kTnSumPh = 16;
+__global__ void __launch_bounds__(64 * kTnSumPh)
+k_tanh_sum_adam(const float *__restrict__ part, int rows, int64_t np, float *__restrict__ grad,
+                float *__restrict__ P, TnAdam ad) {
+    __shared__ double sh[kTnSumPh][64];
+    const int cl = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 64 + cl;
+    double acc = 0.0;
+    if (j < np) {
+        int r = ph;
+        for (; r + 3 * kTnSumPh < rows; r += 4 * kTnSumPh) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = part[(size_t)(r + u * kTnSumPh) * np + j];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc += v[u];
+        }
+        for (; r < rows; r += kTnSumPh) acc += part[(size_t)r * np + j];
+    }
+    sh[ph][cl] = acc;
+    __syncthreads();
+    if (ph != 0 || j >= np) return;
+    double t = sh[0][cl];
+#pragma unroll
+    for (int q = 1; q < kTnSumPh; ++q) t += sh[q][cl];
+    const float gk = (float)t;
+    grad[j] = gk;
+    const float mk = ad.b1 * ad.m[j] + (1.0f - ad.b1) * gk;
+    const float vk = ad.b2 * ad.v[j] + (1.0f - ad.b2) * gk * gk;
+    ad.m[j] = mk;
+    ad.v[j] = vk;
+    const float mh = mk * ad.bc1, vh = vk * ad.bc2;
+    P[j] = P[j] - ad.lr * mh / (sqrtf(vh) + ad.eps);
+}
+
 // Loss (nullable, device [1]) and gradient (device [np]) of the fit objective at the
-// current parameters.  `ws` holds tanh_fit_ws_bytes(net, n) bytes.
-int32_t launch_tanh_loss_grad(const pdmp_tanh_net &net, const float *x, const uint8_t *y,
-                              int64_t n, float l2, float *loss, float *grad, void *ws,
-                              hipStream_t st) {
+// current parameters, and with `ad` the Adam step on that gradient in the same pass
+// over it.  `ws` holds tanh_fit_ws_bytes(net, n) bytes.
+static int32_t tanh_loss_grad_step(const pdmp_tanh_net &net, const float *x, const uint8_t *y,
+                                   int64_t n, float l2, float *loss, float *grad, void *ws,
+                                   const TnAdam *ad, hipStream_t st) {
     const int dim = net.dim, H = net.hidden, L = net.n_hidden;
     const int64_t np = (int64_t)H * dim + H + (int64_t)(L - 1) * (H * H + H) + H + 1;
     TnGradTiles tt;
@@ -904,13 +949,25 @@ int32_t launch_tanh_loss_grad(const pdmp_tanh_net &net, const float *x, const ui
                        dim, H, L, x, A, E, r, n, kps, tt, np, net.params, l2, part,
                        loss ? wsq : nullptr);
     if (int32_t e = check_launch("k_tanh_wgrad")) return e;
-    if (int32_t e = launch_sum_rows(part, S, np, 1.0, nullptr, 0.0f, grad, st)) return e;
+    if (ad) {
+        hipLaunchKernelGGL(k_tanh_sum_adam, dim3((unsigned)((np + 63) / 64)), dim3(64 * kTnSumPh),
+                           0, st, part, S, np, grad, (float *)net.params, *ad);
+        if (int32_t e = check_launch("k_tanh_sum_adam")) return e;
+    } else if (int32_t e = launch_sum_rows(part, S, np, 1.0, nullptr, 0.0f, grad, st)) {
+        return e;
+    }
     if (loss) {
         hipLaunchKernelGGL(k_tanh_loss, dim3(1), dim3(256), 0, st, rparts, tn_fb_blocks(n),
                            1.0 / (double)n, wsq, tt.start[L + 1], 0.5 * (double)l2, loss);
         if (int32_t e = check_launch("k_tanh_loss")) return e;
     }
     return PDMP_OK;
+}
+
+int32_t launch_tanh_loss_grad(const pdmp_tanh_net &net, const float *x, const uint8_t *y,
+                              int64_t n, float l2, float *loss, float *grad, void *ws,
+                              hipStream_t st) {
+    return tanh_loss_grad_step(net, x, y, n, l2, loss, grad, ws, nullptr, st);
 }
 
 // `steps` full-batch Adam steps on the fit objective; the parameters (net.params)
@@ -928,11 +985,18 @@ int32_t launch_tanh_fit(const pdmp_tanh_net &net, const float *x, const uint8_t 
     p += 2 * al256t((size_t)L * H * n * 4) + al256t((size_t)n * 4) + al256t((size_t)S * np * 4);
     float *grad = (float *)p;
     for (int t = 0; t < steps; ++t) {
-        if (int32_t e = launch_tanh_loss_grad(net, x, y, n, l2, loss_out ? loss_out + t : nullptr,
-                                              grad, ws, st))
-            return e;
-        if (int32_t e = launch_adam((float *)net.params, grad, m, v, np, 0, t0 + t + 1, lr, b1, b2,
-                                    eps, 0.0f, st))
+        const int tt1 = t0 + t + 1;
+        TnAdam ad;
+        ad.m = m;
+        ad.v = v;
+        ad.lr = lr;
+        ad.b1 = b1;
+        ad.b2 = b2;
+        ad.eps = eps;
+        ad.bc1 = (float)(1.0 / (1.0 - std::pow((double)b1, (double)tt1)));
+        ad.bc2 = (float)(1.0 / (1.0 - std::pow((double)b2, (double)tt1)));
+        if (int32_t e = tanh_loss_grad_step(net, x, y, n, l2, loss_out ? loss_out + t : nullptr,
+                                            grad, ws, &ad, st))
             return e;
     }
     return PDMP_OK;
