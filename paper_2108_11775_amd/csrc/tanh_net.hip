@@ -539,13 +539,14 @@ int32_t launch_tanh_net(const pdmp_tanh_net &net, int mode, const float *x, int6
 //                  the reverse pass e_L = r v (1 - a_L^2), e_l = (1 - a_l^2) W_l^T e_{l+1};
 //                  stores a_l and e_l ([layer][unit][point], coalesced per unit);
 //   k_tanh_wgrad   dW_l = sum_i e_{l+1,i} [a_{l,i}; 1]^T (the bias as a column of ones;
-//                  layer L: r against [a_L; 1]) as 16 x 16 tiles on FP32 MFMA with the
-//                  points as contraction index, in fixed point ranges -> partial rows;
-//                  the first split's row carries + l2 w on the weight entries (not the
-//                  biases) and, when the loss is asked for, each tile's sum of w^2;
-//   k_sum_rows     fixed-order sum of the partial rows (fit.hip);
-//   k_tanh_loss    the loss from the two kernels' partial sums (when asked for);
-//   Adam           (fit.hip).
+//                  layer L: r against [a_L; 1]) on FP32 MFMA with the points as
+//                  contraction index, one block per layer and range of points ->
+//                  partial rows; the first range's row carries + l2 w on the weight
+//                  entries (not the biases) and, when the loss is asked for, each
+//                  layer's sum of w^2;
+//   k_tanh_sum_adam fixed-order sum of the partial rows and the Adam step (fit), or
+//   k_sum_rows     the sum alone (fit.hip; the loss and gradient query);
+//   k_tanh_loss    the loss from the two kernels' partial sums (when asked for).
 
 template <int DIM, int NT, int L>
 __global__ void __launch_bounds__(kTnBlock)
@@ -723,103 +724,126 @@ k_tanh_loss(const double *__restrict__ a, int na, double sa, const double *__res
     if (threadIdx.x == 0) *out = (float)(sa * sh[0][0] + sb * sh[1][0]);
 }
 
-// Tiles of the weight-gradient products, layer by layer (at most kTnMaxLayers + 1).
-constexpr int kTnMaxLayers = 4;
-struct TnGradTiles {
-    int start[kTnMaxLayers + 2];  // first global tile of layer l; start[L+1] = total
-    int ct[kTnMaxLayers + 1];     // column tiles of layer l
-};
+// Weight-gradient products, one block per (layer, split of the points).
+constexpr int kTnWgChunk = 64;   // points staged per round
+constexpr int kTnWgRS = kTnWgChunk + 1;  // LDS row stride: lanes of one MFMA hit 64 banks
+constexpr int kTnWgRows = 64;    // rows of E (H <= 64)
+constexpr int kTnWgCols = 80;    // columns [a; 1] padded to 16 (H + 1 <= 65)
 
-// Partial rows of the loss gradient: block (tile, split).  Layer l < L: rows o of
-// E_{l+1} (H), columns i of [a_l; 1] (n_l + 1, a_0 = x); layer L: the single row r
-// against [a_L; 1].  Points of split s: [s kps, min(n, (s+1) kps)).  The blocks of
-// split 0 add the decay l2 w to the weight entries of their tile and, with wsq_part,
-// write the tile's sum of w^2 (FP64, fixed order) to wsq_part[tile].
+// Partial rows of the loss gradient.  Block (l, split): layer l < L: dW_l = E_{l+1}
+// [a_l; 1]^T (rows o of E (H), columns i of [a_l; 1], n_l + 1 of them, a_0 = x); layer
+// L: the single row r against [a_L; 1]; over the points [split kps, min(n, (split +
+// 1) kps)).  Each round stages 64 points of the rows and columns in LDS (coalesced row
+// reads, issued a round ahead), then every 16 x 16 output tile of the layer, owned by
+// one wave, takes 16 FP32 MFMAs (lane group q takes the points 16q + m, m < 16); each
+// output sums its points in a fixed order.  The blocks of split 0 add the decay l2 w
+// to the weight entries of their layer and, with wsq_part, write the layer's sum of
+// w^2 (FP64, fixed order) to wsq_part[l].
 __global__ void __launch_bounds__(256)
 k_tanh_wgrad(int dim, int H, int L, const float *__restrict__ x, const float *__restrict__ A,
              const float *__restrict__ E, const float *__restrict__ r, int64_t n, int64_t kps,
-             TnGradTiles tt, int64_t np, const float *__restrict__ P, float l2,
-             float *__restrict__ part, double *__restrict__ wsq_part) {
-    __shared__ float red[256];
+             int64_t np, const float *__restrict__ P, float l2, float *__restrict__ part,
+             double *__restrict__ wsq_part) {
+    __shared__ float Xs[kTnWgRows * kTnWgRS];
+    __shared__ float Ys[kTnWgCols * kTnWgRS];
     __shared__ double rw[256];
-    const int tile = blockIdx.x;
-    int l = 0;
-    while (l < L && tile >= tt.start[l + 1]) ++l;
-    const int lt = tile - tt.start[l];
-    const int ro = lt / tt.ct[l], co = lt % tt.ct[l];
+    const int l = blockIdx.x;
     const int rows = l < L ? H : 1;
     const int nl = l == 0 ? dim : H;  // columns before the ones column
+    const int RT = (rows + 15) / 16, CT = (nl + 1 + 15) / 16, NTl = RT * CT;
     const float *X = l < L ? E + (size_t)l * H * n : r;
     const float *Y = l == 0 ? x : A + (size_t)(l - 1) * H * n;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int orow = 16 * ro + (lane & 15), icol = 16 * co + (lane & 15);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane >> 4, c16 = lane & 15;
     const int64_t ks = (int64_t)blockIdx.y * kps;
     const int64_t ke = ks + kps < n ? ks + kps : n;
-    f32x4_tn acc;
-    acc[0] = acc[1] = acc[2] = acc[3] = 0.0f;
-    for (int64_t k0 = ks + 16 * wv; k0 < ke; k0 += 64) {
+    f32x4_tn acc[5];  // this wave's tiles t = wv + 4 u (at most 20 per layer)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t k = k0 + 4 * (lane >> 4) + j;
-            const bool kin = k < ke;
-            float av = 0.0f, bv = 0.0f;
-            if (kin && orow < rows) av = X[(size_t)orow * n + k];
-            if (kin && icol < nl) bv = Y[(size_t)icol * n + k];
-            else if (kin && icol == nl) bv = 1.0f;
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+    for (int u = 0; u < 5; ++u) acc[u][0] = acc[u][1] = acc[u][2] = acc[u][3] = 0.0f;
+    // this thread's staging values for one round: rows wv + 4u of X and of [Y; 1] at
+    // point k0 + lane, loaded a round ahead so that their latency overlaps the MFMAs
+    constexpr int XU = kTnWgRows / 4, YU = kTnWgCols / 4;
+    float xv[XU], yv[YU];
+    auto load_round = [&](int64_t k0) {
+        const int64_t k = k0 + lane;
+        const bool kin = k < ke;
+#pragma unroll
+        for (int u = 0; u < XU; ++u) {
+            const int rr = wv + 4 * u;
+            xv[u] = kin && rr < rows ? X[(size_t)rr * n + k] : 0.0f;
         }
-    }
-    // wave sums in a fixed order: ((w0 + w1) + w2) + w3; entry v of lane l is
-    // (row 4(l/16) + v, column l%16) of the tile
-    for (int w = 0; w < 4; ++w) {
-        if (wv == w)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                float &dst = red[(4 * (lane >> 4) + v) * 16 + (lane & 15)];
-                dst = w == 0 ? acc[v] : dst + acc[v];
-            }
+        for (int u = 0; u < YU; ++u) {
+            const int cc = wv + 4 * u;
+            float v = 0.0f;
+            if (cc < nl) v = kin ? Y[(size_t)cc * n + k] : 0.0f;
+            else if (cc == nl) v = 1.0f;  // the bias column
+            yv[u] = v;
+        }
+    };
+    if (ks < ke) load_round(ks);
+    for (int64_t k0 = ks; k0 < ke; k0 += kTnWgChunk) {
+#pragma unroll
+        for (int u = 0; u < XU; ++u)
+            if (wv + 4 * u < 16 * RT) Xs[(wv + 4 * u) * kTnWgRS + lane] = xv[u];
+#pragma unroll
+        for (int u = 0; u < YU; ++u)
+            if (wv + 4 * u < 16 * CT) Ys[(wv + 4 * u) * kTnWgRS + lane] = yv[u];
+        __syncthreads();
+        if (k0 + kTnWgChunk < ke) load_round(k0 + kTnWgChunk);
+#pragma unroll
+        for (int u = 0; u < 5; ++u) {
+            const int t = wv + 4 * u;
+            if (t >= NTl) break;  // uniform over the wave
+            const int ro = t / CT, co = t % CT;
+            const float *xa = Xs + (16 * ro + c16) * kTnWgRS + 16 * q;
+            const float *yb = Ys + (16 * co + c16) * kTnWgRS + 16 * q;
+#pragma unroll
+            for (int m = 0; m < 16; ++m)
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[m], yb[m], acc[u], 0, 0, 0);
+        }
         __syncthreads();
     }
-    const int o = 16 * ro + (threadIdx.x >> 4), i = 16 * co + (threadIdx.x & 15);
-    const bool in = o < rows && i <= nl;
+    // entry v of lane (c16, q) in a tile is (row 4q + v, column c16)
     const int64_t off = (int64_t)(l == 0 ? 0 : (int64_t)H * dim + H + (int64_t)(l - 1) * (H * H + H));
-    int64_t j = 0;
-    if (l < L) j = i < nl ? off + (int64_t)o * nl + i : off + (int64_t)H * nl + o;
-    else j = off + i;  // v entries, then b_o at i == H
-    const bool wt = in && i < nl;  // a weight entry (i == nl is the bias column)
-    if (blockIdx.y != 0) {
-        if (in) part[(size_t)blockIdx.y * np + j] = red[threadIdx.x];
-        return;
+    double wq = 0.0;  // this lane's w^2 over its weight entries (split 0)
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+        const int t = wv + 4 * u;
+        if (t >= NTl) break;
+        const int ro = t / CT, co = t % CT;
+        const int i = 16 * co + c16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int o = 16 * ro + 4 * q + v;
+            if (o >= rows || i > nl) continue;
+            int64_t j;
+            if (l < L) j = i < nl ? off + (int64_t)o * nl + i : off + (int64_t)H * nl + o;
+            else j = off + i;  // v entries, then b_o at i == H
+            float val = acc[u][v];
+            if (blockIdx.y == 0 && i < nl) {  // a weight entry (i == nl: the bias)
+                const float w = P[j];
+                val = fmaf(l2, w, val);
+                wq += (double)w * (double)w;
+            }
+            part[(size_t)blockIdx.y * np + j] = val;
+        }
     }
-    const float w = wt ? P[j] : 0.0f;
-    if (in) part[j] = wt ? fmaf(l2, w, red[threadIdx.x]) : red[threadIdx.x];
-    if (!wsq_part) return;  // uniform over the block
-    rw[threadIdx.x] = (double)w * (double)w;
+    if (blockIdx.y != 0 || !wsq_part) return;  // uniform over the block
+    rw[threadIdx.x] = wq;
     __syncthreads();
     for (unsigned s2 = 128; s2 >= 1; s2 >>= 1) {
         if (threadIdx.x < s2) rw[threadIdx.x] += rw[threadIdx.x + s2];
         __syncthreads();
     }
-    if (threadIdx.x == 0) wsq_part[tile] = rw[0];
+    if (threadIdx.x == 0) wsq_part[l] = rw[0];
 }
 
-static void tn_grad_tiles(int dim, int H, int L, TnGradTiles &tt) {
-    int acc = 0;
-    for (int l = 0; l <= L; ++l) {
-        const int rows = l < L ? H : 1, cols = (l == 0 ? dim : H) + 1;
-        tt.start[l] = acc;
-        tt.ct[l] = (cols + 15) / 16;
-        acc += ((rows + 15) / 16) * tt.ct[l];
-    }
-    tt.start[L + 1] = acc;
-}
-
-static int tn_splits(int64_t n, int tiles, int64_t &kps) {
-    int64_t s = (1024 + tiles - 1) / tiles;
-    const int64_t smax = (n + 63) / 64;
-    if (s > smax) s = smax;
-    if (s < 1) s = 1;
-    kps = ((n + s - 1) / s + 63) / 64 * 64;
+// Points per split of the weight-gradient products: whole rounds of 64, about 128
+// splits (at most as many as there are rounds).
+static int tn_splits(int64_t n, int64_t &kps) {
+    const int64_t rounds = (n + kTnWgChunk - 1) / kTnWgChunk;
+    const int64_t per = (rounds + 127) / 128;
+    kps = (per < 1 ? 1 : per) * kTnWgChunk;
     return (int)((n + kps - 1) / kps);
 }
 
@@ -828,13 +852,11 @@ static size_t al256t(size_t b) { return (b + 255) & ~(size_t)255; }
 size_t tanh_fit_ws_bytes(const pdmp_tanh_net &net, int64_t n) {
     const int64_t H = net.hidden, L = net.n_hidden;
     const int64_t np = H * net.dim + H + (L - 1) * (H * H + H) + H + 1;
-    TnGradTiles tt;
-    tn_grad_tiles(net.dim, net.hidden, net.n_hidden, tt);
     int64_t kps;
-    const int S = tn_splits(n, tt.start[L + 1], kps);
+    const int S = tn_splits(n, kps);
     return 2 * al256t((size_t)(L * H * n) * 4) + al256t((size_t)n * 4) +
            al256t((size_t)S * np * 4) + al256t((size_t)np * 4) + al256t(1024 * 8) +
-           al256t((size_t)tt.start[L + 1] * 8);
+           al256t((size_t)(L + 1) * 8);
 }
 
 // Blocks of k_tanh_fb for n points: a wave per tile of 16 points, at most 1024 blocks.
@@ -915,10 +937,8 @@ static int32_t tanh_loss_grad_step(const pdmp_tanh_net &net, const float *x, con
                                    const TnAdam *ad, hipStream_t st) {
     const int dim = net.dim, H = net.hidden, L = net.n_hidden;
     const int64_t np = (int64_t)H * dim + H + (int64_t)(L - 1) * (H * H + H) + H + 1;
-    TnGradTiles tt;
-    tn_grad_tiles(dim, H, L, tt);
     int64_t kps;
-    const int S = tn_splits(n, tt.start[L + 1], kps);
+    const int S = tn_splits(n, kps);
     char *p = (char *)ws;
     float *A = (float *)p;
     p += al256t((size_t)L * H * n * 4);
@@ -931,7 +951,7 @@ static int32_t tanh_loss_grad_step(const pdmp_tanh_net &net, const float *x, con
     p += al256t((size_t)np * 4);  // spare (keeps the layout of the fit workspace)
     double *rparts = (double *)p;  // per k_tanh_fb block: the sum of its points' BCE
     p += al256t(1024 * 8);
-    double *wsq = (double *)p;  // per tile: the sum of w^2 of its weight entries
+    double *wsq = (double *)p;  // per layer: the sum of w^2 of its weight entries
     double *bce = loss ? rparts : nullptr;
 
 #define PDMP_TNFB(D)                                                                 \
@@ -945,9 +965,8 @@ static int32_t tanh_loss_grad_step(const pdmp_tanh_net &net, const float *x, con
     }
 #undef PDMP_TNFB
     if (int32_t e = check_launch("k_tanh_fb")) return e;
-    hipLaunchKernelGGL(k_tanh_wgrad, dim3((unsigned)tt.start[L + 1], (unsigned)S), dim3(256), 0, st,
-                       dim, H, L, x, A, E, r, n, kps, tt, np, net.params, l2, part,
-                       loss ? wsq : nullptr);
+    hipLaunchKernelGGL(k_tanh_wgrad, dim3((unsigned)(L + 1), (unsigned)S), dim3(256), 0, st, dim, H,
+                       L, x, A, E, r, n, kps, np, net.params, l2, part, loss ? wsq : nullptr);
     if (int32_t e = check_launch("k_tanh_wgrad")) return e;
     if (ad) {
         hipLaunchKernelGGL(k_tanh_sum_adam, dim3((unsigned)((np + 63) / 64)), dim3(64 * kTnSumPh),
@@ -958,7 +977,7 @@ static int32_t tanh_loss_grad_step(const pdmp_tanh_net &net, const float *x, con
     }
     if (loss) {
         hipLaunchKernelGGL(k_tanh_loss, dim3(1), dim3(256), 0, st, rparts, tn_fb_blocks(n),
-                           1.0 / (double)n, wsq, tt.start[L + 1], 0.5 * (double)l2, loss);
+                           1.0 / (double)n, wsq, L + 1, 0.5 * (double)l2, loss);
         if (int32_t e = check_launch("k_tanh_loss")) return e;
     }
     return PDMP_OK;
@@ -977,10 +996,8 @@ int32_t launch_tanh_fit(const pdmp_tanh_net &net, const float *x, const uint8_t 
                         float *v, int t0, float *loss_out, void *ws, hipStream_t st) {
     const int dim = net.dim, H = net.hidden, L = net.n_hidden;
     const int64_t np = (int64_t)H * dim + H + (int64_t)(L - 1) * (H * H + H) + H + 1;
-    TnGradTiles tt;
-    tn_grad_tiles(dim, H, L, tt);
     int64_t kps;
-    const int S = tn_splits(n, tt.start[L + 1], kps);
+    const int S = tn_splits(n, kps);
     char *p = (char *)ws;
     p += 2 * al256t((size_t)L * H * n * 4) + al256t((size_t)n * 4) + al256t((size_t)S * np * 4);
     float *grad = (float *)p;
