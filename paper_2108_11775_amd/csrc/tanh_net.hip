@@ -70,21 +70,41 @@ __device__ __forceinline__ int64_t tn_w_off(int l, int dim, int H) {
     return l == 0 ? 0 : (int64_t)H * dim + H + (int64_t)(l - 1) * (H * H + H);
 }
 
+// Called by blocks of kTnBlock threads.  The fragments are loaded in batches of
+// eight per thread, every load unconditional (a padded entry reads W[0] and is
+// replaced by zero), so that a batch's loads are in flight together before their LDS
+// stores; a load per entry behind its own branch left their latency serialised.
 template <int DIM, int NT, int L>
 __device__ void tn_stage(TnLds<DIM, NT, L> &S, const float *__restrict__ P, int H) {
     using LD = TnLds<DIM, NT, L>;
-    for (int idx = threadIdx.x; idx < LD::NF; idx += blockDim.x) {
-        const int ln = idx & 63, v = (idx >> 6) & 3;
-        const int q = idx >> 8;  // ((l-1) NT + first) NT + second
-        const int second = q % NT, first = (q / NT) % NT, l = 1 + q / (NT * NT);
-        const float *W = P + tn_w_off(l, DIM, H);
-        {  // forward: first = to (row tile), second = ti (contraction tile)
-            const int row = 16 * first + (ln & 15), col = 16 * second + 4 * (ln >> 4) + v;
-            S.fw[idx] = (row < H && col < H) ? W[(int64_t)row * H + col] : 0.0f;
+    constexpr int NB = 8;
+    for (int base = 0; base < LD::NF; base += kTnBlock * NB) {
+        float fv[NB], bv[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int idx = base + u * kTnBlock + threadIdx.x;
+            const int ln = idx & 63, v = (idx >> 6) & 3;
+            const int q = idx >> 8;  // ((l-1) NT + first) NT + second
+            const int second = q % NT, first = (q / NT) % NT, l = 1 + q / (NT * NT);
+            const bool in = idx < LD::NF;  // then l < L (NF > 0 means L >= 2)
+            const float *W = P + tn_w_off(in ? l : L - 1, DIM, H);
+            // forward: first = to (row tile), second = ti (contraction tile)
+            const int fr = 16 * first + (ln & 15), fc = 16 * second + 4 * (ln >> 4) + v;
+            // backward: first = ti (row tile of W^T), second = to (contraction tile)
+            const int br = 16 * second + 4 * (ln >> 4) + v, bc = 16 * first + (ln & 15);
+            const bool fok = in && fr < H && fc < H, bok = in && br < H && bc < H;
+            const float f = W[fok ? (int64_t)fr * H + fc : 0];
+            const float b = W[bok ? (int64_t)br * H + bc : 0];
+            fv[u] = fok ? f : 0.0f;
+            bv[u] = bok ? b : 0.0f;
         }
-        {  // backward: first = ti (row tile of W^T), second = to (contraction tile)
-            const int row = 16 * second + 4 * (ln >> 4) + v, col = 16 * first + (ln & 15);
-            S.bw[idx] = (row < H && col < H) ? W[(int64_t)row * H + col] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int idx = base + u * kTnBlock + threadIdx.x;
+            if (idx < LD::NF) {
+                S.fw[idx] = fv[u];
+                S.bw[idx] = bv[u];
+            }
         }
     }
     for (int idx = threadIdx.x; idx < LD::HP; idx += blockDim.x) {
